@@ -1,0 +1,199 @@
+/*
+ * csketch.h - C ABI of the MI355X (gfx950) convolution Count sketch library.
+ *
+ * Method: Heddes, Nunes, Givargis & Nicolau, "Convolution and Cross-Correlation of
+ * Count Sketches Enables Fast Cardinality Estimation of Multi-Join Queries"
+ * (SIGMOD 2024).  One Count sketch per relation of a join query, d independent
+ * repetitions of m int64 counters each.  A tuple adds its frequency change, times the
+ * product of the sign hashes of the joins its attributes take part in, to the counter
+ * at the sum (mod m) of its attributes' bin hashes (Sec. 3.2, Eq. 2-4, Alg. 2).  The
+ * estimate of the join size combines the sketches along the join graph by circular
+ * cross-correlation and Hadamard products (Eq. 5, Alg. 3) and takes the median of the
+ * d repetitions (Sec. 3.3).
+ *
+ * Conventions (the paper leaves them open; this library fixes them):
+ *   - hash field p = 2^61 - 1; keys are uint32, so distinct keys stay distinct mod p;
+ *   - coefficients come from SplitMix64 seeded with `seed`: each draw is next() >> 3,
+ *     redrawn if it equals p; draw order: for each repetition t, for each join e (in
+ *     the caller's edge order) a0, a1, a2, a3; then for each graph component q
+ *     (numbered by smallest attribute id) b0, b1;
+ *   - sign s_e(x) = +1 if (a0 + a1 x + a2 x^2 + a3 x^3 mod p) is even, else -1
+ *     (4-wise independent family); bin h_q(x) = (b0 + b1 x mod p) mod m (2-wise);
+ *   - counters are int64 and wrap modulo 2^64;
+ *   - the median of an even number of repetitions is the lower middle value.
+ *
+ * Memory: every pointer documented as "device" must be device memory of the device
+ * that was current when the handle was created (e.g. a torch CUDA/HIP tensor's
+ * data_ptr()).  Streams are hipStream_t values passed as void* (NULL = null stream).
+ * The library allocates and owns the counters and its work buffers; callers own
+ * every buffer they pass in and keep it alive until the stream has passed the call.
+ *
+ * Errors: every call returns a cs_status; on failure cs_last_error() returns a
+ * thread-local message.  No exception crosses this boundary.  Handles are not
+ * thread-safe: one thread at a time per handle.
+ */
+#ifndef CSKETCH_H
+#define CSKETCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum cs_status {
+    CS_OK = 0,
+    CS_EINVAL = 1,   /* bad argument (null pointer, size out of range, bad relation id) */
+    CS_EGRAPH = 2,   /* the join graph is not an acyclic connected equi-join query */
+    CS_ENOMEM = 3,   /* device or host allocation failed */
+    CS_EDEVICE = 4,  /* a HIP runtime call failed */
+    CS_EBUSY = 5,    /* admission refused: memory budget or queue full */
+    CS_ERANGE = 6    /* a value is beyond what the library represents */
+} cs_status;
+
+/* A join query (Sec. 2.6, Fig. 3).  Attributes 0..n_attr-1 are globally numbered
+ * vertices; attr_rel[u] is the relation owning attribute u; edges[2e], edges[2e+1]
+ * are the attributes joined by join e.  Valid queries: every relation owns at least
+ * one attribute, every attribute takes part in at least one join, a join links two
+ * different relations, and the relations with the joins form a tree (n_edge =
+ * n_rel - 1, connected).  Self-joins are written with a copy of the relation.
+ * Limits: n_rel <= 16, n_attr <= 32, at most 8 attributes per relation, at most 8
+ * joins per attribute.  All arrays are host memory, read during the call only. */
+typedef struct cs_graph {
+    int32_t n_rel;
+    int32_t n_attr;
+    const int32_t *attr_rel;   /* [n_attr] */
+    int32_t n_edge;
+    const int32_t *edges;      /* [n_edge][2] */
+} cs_graph;
+
+typedef struct cs_sketch cs_sketch;   /* opaque: the sketches of one query */
+
+/* Result of an estimate.  `value` is the median over the d repetitions as fp64: the
+ * correctly rounded value of the exact integer median when exact != 0.  value_i64
+ * holds the exact median when exact != 0 and it fits in int64 (fits_i64 != 0). */
+typedef struct cs_estimate_t {
+    double value;
+    int64_t value_i64;
+    int32_t exact;
+    int32_t fits_i64;
+    int32_t d;
+    int32_t n_modular;   /* repetitions whose exact value needed the modular path */
+} cs_estimate_t;
+
+/* Per-repetition detail, for tests and diagnostics (host arrays of length d). */
+typedef struct cs_reps_t {
+    double *value;       /* X_t as fp64 (correctly rounded when exact) */
+    int64_t *lo;         /* low 64 bits of the exact X_t (two's complement int128) */
+    int64_t *hi;         /* high 64 bits of the exact X_t */
+    int32_t *exact;      /* 1: lo/hi hold X_t exactly */
+    double *bound;       /* certified bound on |fp64 FFT estimate - X_t| (0 if no FFT) */
+} cs_reps_t;
+
+/* Update strategies (all give bit-identical counters). */
+typedef enum cs_update_strategy {
+    CS_UPDATE_AUTO = 0,
+    CS_UPDATE_GLOBAL_ATOMIC = 1,  /* one device-scope int64 atomic per tuple and repetition */
+    CS_UPDATE_LDS_PRIVATE = 2,    /* the d x m counters cut into LDS-sized segments;
+                                     each workgroup accumulates one segment for one chunk
+                                     of tuples in LDS, stores partial sums to the
+                                     handle's scratch buffer, and a reduce kernel adds
+                                     them into the counters */
+    CS_UPDATE_WAVE_AGGREGATE = 3  /* equal buckets of one wavefront merged before the atomic */
+} cs_update_strategy;
+
+/* Estimate plans chosen at cs_create from the join graph. */
+typedef enum cs_plan_kind {
+    CS_PLAN_DOT = 1,       /* two relations: X_t = <c_0, c_1> in exact 128-bit integers */
+    CS_PLAN_SPECTRAL = 2,  /* every graph component joins exactly two attributes (chains,
+                              stars, any tree of binary joins): X_t = (1/m) sum_f of the
+                              product of the relations' spectra, conjugated on alternate
+                              levels; fp64 FFT + modular residue for exactness */
+    CS_PLAN_GENERAL = 3    /* some component joins three or more attributes: Alg. 3's
+                              Hadamard / cross-correlation sequence in modular arithmetic
+                              (number-theoretic transforms), exact */
+} cs_plan_kind;
+
+typedef struct cs_info_t {
+    int32_t n_rel, n_attr, n_edge, n_comp;
+    uint32_t m, d;
+    int32_t plan;              /* cs_plan_kind */
+    int32_t device;
+    uint64_t counter_bytes;    /* r * d * m * 8 */
+    uint64_t workspace_bytes;  /* estimate work buffers currently held */
+} cs_info_t;
+
+/* ------------------------------------------------------------------ lifecycle */
+
+/* Validate the query, draw the hash coefficients (Alg. 1: SampleSignHashes and
+ * SampleBinHashes; Sec. 3.2 initialization), allocate r*d*m int64 counters on the
+ * current device and zero them.  m must be a power of two in [2, 2^20]; 1 <= d <= 64.
+ * Errors: CS_EINVAL, CS_EGRAPH, CS_ENOMEM, CS_EDEVICE. */
+cs_status cs_create(const cs_graph *graph, uint32_t m, uint32_t d, uint64_t seed,
+                    cs_sketch **out);
+
+/* Free the handle and its device memory (synchronises the device first). */
+cs_status cs_destroy(cs_sketch *h);
+
+/* Bytes of counters cs_create would allocate (for admission control); 0 if invalid. */
+uint64_t cs_sketch_bytes(const cs_graph *graph, uint32_t m, uint32_t d);
+
+cs_status cs_get_info(const cs_sketch *h, cs_info_t *out);
+
+/* Thread-local message of the last failure on this thread ("" if none). */
+const char *cs_last_error(void);
+
+/* ------------------------------------------------------------------ update (Alg. 2) */
+
+/* Stream n tuples of relation `rel` into its sketch (Alg. 2 for each repetition).
+ * Calls on one handle must be ordered (one stream, or event dependencies): the
+ * segmented strategy uses the handle's scratch buffer.
+ *   keys:    device, uint32 [n][a_rel] tuple-major; column c is the c-th attribute of
+ *            `rel` in ascending attribute id.
+ *   weights: device, int64 [n] frequency changes Delta (turnstile model, Sec. 2.1),
+ *            or NULL for Delta = +1.
+ * Asynchronous and ordered on `stream`; allocates nothing.  n = 0 is a no-op.
+ * Errors: CS_EINVAL (bad handle, rel out of range, keys NULL with n > 0). */
+cs_status cs_update(cs_sketch *h, int32_t rel, const uint32_t *keys, const int64_t *weights,
+                    uint64_t n, void *stream);
+
+/* Same with an explicit strategy and launch width (0 = automatic); for tests and
+ * tuning.  CS_EINVAL if the strategy does not support this handle's m and d. */
+cs_status cs_update_ex(cs_sketch *h, int32_t rel, const uint32_t *keys, const int64_t *weights,
+                       uint64_t n, void *stream, int32_t strategy, int32_t grid_blocks);
+
+/* ------------------------------------------------------------------ estimate (Eq. 5, Alg. 3) */
+
+/* Estimate the join size: per repetition X_t (Eq. 5, evaluated as in Alg. 3), then
+ * the median.  Runs on `stream` and blocks until the result is on the host.
+ * `reps` may be NULL.  Errors: CS_EINVAL, CS_EDEVICE, CS_ENOMEM. */
+cs_status cs_estimate(cs_sketch *h, void *stream, cs_estimate_t *out, const cs_reps_t *reps);
+
+/* ------------------------------------------------------------------ state */
+
+/* Zero every counter (stream-ordered). */
+cs_status cs_reset(cs_sketch *h, void *stream);
+
+/* dst += src counter-wise (sketch linearity, Sec. 2.2).  Both handles must have the
+ * same graph, m, d and seed.  Stream-ordered. */
+cs_status cs_merge(cs_sketch *dst, const cs_sketch *src, void *stream);
+
+/* Copy relation rel's counters, int64 [d][m], to host memory (synchronous). */
+cs_status cs_read_sketch(cs_sketch *h, int32_t rel, int64_t *host_out);
+
+/* Device address of relation rel's counters, int64 [d][m] (owned by the handle). */
+cs_status cs_sketch_device_ptr(cs_sketch *h, int32_t rel, int64_t **out);
+
+/* Copy the drawn coefficients to host memory: sign [d][n_edge][4] (a0..a3), bin
+ * [d][n_comp][2] (b0, b1). */
+cs_status cs_read_coeffs(const cs_sketch *h, uint64_t *sign_out, uint64_t *bin_out);
+
+/* Graph component of each attribute, int32 [n_attr] (host). */
+cs_status cs_read_components(const cs_sketch *h, int32_t *psi_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSKETCH_H */

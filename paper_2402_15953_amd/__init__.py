@@ -1,0 +1,217 @@
+"""Python binding of libcsketch (MI355X convolution Count sketches).
+
+Argument marshalling only: every step of the update and the estimate runs in the HIP
+library.  Device buffers are torch tensors on the current HIP device; streams are
+torch streams.  There is no CPU fallback: without the built library or a GPU, the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcsketch.so")
+
+CS_OK, CS_EINVAL, CS_EGRAPH, CS_ENOMEM, CS_EDEVICE, CS_EBUSY, CS_ERANGE = range(7)
+UPDATE_AUTO, UPDATE_GLOBAL_ATOMIC, UPDATE_LDS_PRIVATE, UPDATE_WAVE_AGGREGATE = range(4)
+PLAN_DOT, PLAN_SPECTRAL, PLAN_GENERAL = 1, 2, 3
+
+EXPORTED = [
+    "cs_create", "cs_destroy", "cs_sketch_bytes", "cs_get_info", "cs_last_error",
+    "cs_update", "cs_update_ex", "cs_estimate", "cs_reset", "cs_merge", "cs_read_sketch",
+    "cs_sketch_device_ptr", "cs_read_coeffs", "cs_read_components",
+]
+
+
+class CsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"csketch status {status}: {msg}")
+        self.status = status
+
+
+class _Graph(ctypes.Structure):
+    _fields_ = [("n_rel", ctypes.c_int32), ("n_attr", ctypes.c_int32),
+                ("attr_rel", ctypes.POINTER(ctypes.c_int32)), ("n_edge", ctypes.c_int32),
+                ("edges", ctypes.POINTER(ctypes.c_int32))]
+
+
+class _Estimate(ctypes.Structure):
+    _fields_ = [("value", ctypes.c_double), ("value_i64", ctypes.c_int64), ("exact", ctypes.c_int32),
+                ("fits_i64", ctypes.c_int32), ("d", ctypes.c_int32), ("n_modular", ctypes.c_int32)]
+
+
+class _Reps(ctypes.Structure):
+    _fields_ = [("value", ctypes.c_void_p), ("lo", ctypes.c_void_p), ("hi", ctypes.c_void_p),
+                ("exact", ctypes.c_void_p), ("bound", ctypes.c_void_p)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n_rel", ctypes.c_int32), ("n_attr", ctypes.c_int32), ("n_edge", ctypes.c_int32),
+                ("n_comp", ctypes.c_int32), ("m", ctypes.c_uint32), ("d", ctypes.c_uint32),
+                ("plan", ctypes.c_int32), ("device", ctypes.c_int32), ("counter_bytes", ctypes.c_uint64),
+                ("workspace_bytes", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libcsketch.so (building it first only if it has never been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, u32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64
+        L.cs_create.argtypes = [ctypes.POINTER(_Graph), u32, u32, u64, ctypes.POINTER(vp)]
+        L.cs_destroy.argtypes = [vp]
+        L.cs_sketch_bytes.argtypes = [ctypes.POINTER(_Graph), u32, u32]
+        L.cs_sketch_bytes.restype = u64
+        L.cs_get_info.argtypes = [vp, ctypes.POINTER(_Info)]
+        L.cs_last_error.restype = ctypes.c_char_p
+        L.cs_update.argtypes = [vp, i32, vp, vp, u64, vp]
+        L.cs_update_ex.argtypes = [vp, i32, vp, vp, u64, vp, i32, i32]
+        L.cs_estimate.argtypes = [vp, vp, ctypes.POINTER(_Estimate), ctypes.POINTER(_Reps)]
+        L.cs_reset.argtypes = [vp, vp]
+        L.cs_merge.argtypes = [vp, vp, vp]
+        L.cs_read_sketch.argtypes = [vp, i32, vp]
+        L.cs_sketch_device_ptr.argtypes = [vp, i32, ctypes.POINTER(vp)]
+        L.cs_read_coeffs.argtypes = [vp, vp, vp]
+        L.cs_read_components.argtypes = [vp, vp]
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != CS_OK:
+        raise CsError(status, lib().cs_last_error().decode())
+
+
+def _graph_struct(graph):
+    attr = (ctypes.c_int32 * len(graph.attr_rel))(*graph.attr_rel)
+    flat = [x for e in graph.edges for x in e]
+    edges = (ctypes.c_int32 * max(1, len(flat)))(*flat)
+    g = _Graph(int(graph.n_rel), len(graph.attr_rel), attr, len(graph.edges), edges)
+    g._keep = (attr, edges)
+    return g
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def sketch_bytes(graph, m: int, d: int) -> int:
+    return int(lib().cs_sketch_bytes(ctypes.byref(_graph_struct(graph)), m, d))
+
+
+class Sketch:
+    """The d x m int64 sketches of every relation of one join query."""
+
+    def __init__(self, graph, m: int, d: int, seed: int):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("csketch needs a HIP GPU; there is no CPU fallback")
+        self.graph = graph
+        self.m, self.d, self.seed = int(m), int(d), int(seed)
+        h = ctypes.c_void_p()
+        _check(lib().cs_create(ctypes.byref(_graph_struct(graph)), self.m, self.d, self.seed, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        i = _Info()
+        _check(lib().cs_get_info(self._h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in _Info._fields_}
+
+    def update(self, rel: int, keys, weights=None, stream=None, strategy: int = UPDATE_AUTO, grid: int = 0):
+        """keys: device int32/uint32 tensor [n, a_rel] (or [n] for one column), contiguous;
+        weights: device int64 tensor [n] or None."""
+        import torch
+        if keys.dtype not in (torch.int32, torch.uint32) or not keys.is_cuda or not keys.is_contiguous():
+            raise TypeError("keys must be a contiguous int32/uint32 device tensor")
+        n = keys.shape[0]
+        wp = None
+        if weights is not None:
+            if weights.dtype != torch.int64 or not weights.is_cuda or not weights.is_contiguous() \
+                    or weights.shape[0] != n:
+                raise TypeError("weights must be a contiguous int64 device tensor of length n")
+            wp = ctypes.c_void_p(weights.data_ptr())
+        _check(lib().cs_update_ex(self._h, int(rel), ctypes.c_void_p(keys.data_ptr()), wp, int(n),
+                                  _stream_ptr(stream), int(strategy), int(grid)))
+
+    def estimate(self, stream=None, reps: bool = False) -> dict:
+        e = _Estimate()
+        rp = None
+        arrs = None
+        if reps:
+            arrs = dict(value=np.zeros(self.d, np.float64), lo=np.zeros(self.d, np.int64),
+                        hi=np.zeros(self.d, np.int64), exact=np.zeros(self.d, np.int32),
+                        bound=np.zeros(self.d, np.float64))
+            rp = _Reps(*(a.ctypes.data for a in (arrs["value"], arrs["lo"], arrs["hi"], arrs["exact"],
+                                                    arrs["bound"])))
+        _check(lib().cs_estimate(self._h, _stream_ptr(stream), ctypes.byref(e),
+                                 ctypes.byref(rp) if rp is not None else None))
+        out = dict(value=e.value, value_i64=e.value_i64 if e.fits_i64 else None, exact=bool(e.exact),
+                   d=e.d, n_modular=e.n_modular)
+        if arrs is not None:
+            ints = []
+            for t in range(self.d):
+                if arrs["exact"][t]:
+                    x = (int(arrs["hi"][t]) << 64) | (int(arrs["lo"][t]) & ((1 << 64) - 1))
+                    ints.append(x)
+                else:
+                    ints.append(None)
+            out.update(rep_values=arrs["value"].tolist(), rep_ints=ints, rep_bounds=arrs["bound"].tolist())
+        return out
+
+    def reset(self, stream=None):
+        _check(lib().cs_reset(self._h, _stream_ptr(stream)))
+
+    def merge_from(self, other: "Sketch", stream=None):
+        _check(lib().cs_merge(self._h, other._h, _stream_ptr(stream)))
+
+    def read_sketch(self, rel: int) -> np.ndarray:
+        out = np.zeros((self.d, self.m), dtype=np.int64)
+        _check(lib().cs_read_sketch(self._h, int(rel), out.ctypes.data))
+        return out
+
+    def device_ptr(self, rel: int) -> int:
+        p = ctypes.c_void_p()
+        _check(lib().cs_sketch_device_ptr(self._h, int(rel), ctypes.byref(p)))
+        return p.value
+
+    def coefficients(self):
+        E, Q = len(self.graph.edges), self.info()["n_comp"]
+        s = np.zeros((self.d, E, 4), dtype=np.uint64)
+        b = np.zeros((self.d, Q, 2), dtype=np.uint64)
+        _check(lib().cs_read_coeffs(self._h, s.ctypes.data, b.ctypes.data))
+        return s, b
+
+    def components(self) -> list:
+        out = np.zeros(len(self.graph.attr_rel), dtype=np.int32)
+        _check(lib().cs_read_components(self._h, out.ctypes.data))
+        return out.tolist()

@@ -1,0 +1,60 @@
+// The sketch handle: graph plan, coefficients, counters and estimate work buffers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "csk_internal.h"
+#include "csk_transform.h"
+
+namespace csk {
+
+// Host-side analysis of a join query (Sec. 2.6, Table 1).
+struct GraphPlan {
+    int32_t n_rel = 0, n_attr = 0, n_edge = 0, n_comp = 0;
+    std::vector<int32_t> attr_rel;                 // [n_attr]
+    std::vector<int32_t> edges;                    // [n_edge][2]
+    std::vector<int32_t> psi;                      // component of each attribute
+    std::vector<std::vector<int32_t>> omega;       // attributes of each relation, ascending
+    std::vector<std::vector<int32_t>> gamma;       // attributes joined with u, ascending
+    std::vector<std::vector<int32_t>> gamma_edge;  // join index of (u, gamma[u][i])
+    std::vector<int32_t> comp_size;                // attributes per component
+    int32_t plan = 0;                              // cs_plan_kind
+    uint32_t conj_mask = 0;                        // spectral plan: relations taken conjugated
+    std::vector<Op> ops;                           // general plan: Alg. 3 as register ops
+    int32_t n_regs = 0;
+    int32_t result_reg = -1;
+    std::vector<RelPlan> rel;                      // update plans
+};
+
+cs_status analyze_graph(const cs_graph *g, GraphPlan *out);
+
+// Estimate work buffers, grown on demand and kept by the handle.
+struct EstimateWork {
+    void *buf = nullptr;        // one device allocation carved into the pieces below
+    size_t bytes = 0;
+};
+
+struct Handle {
+    int device = 0;
+    uint32_t m = 0;
+    int32_t log2m = 0;
+    uint32_t d = 0;
+    uint64_t seed = 0;
+    GraphPlan g;
+    std::vector<uint64_t> sign_coef;   // [d][E][4]
+    std::vector<uint64_t> bin_coef;    // [d][Q][2]
+    int64_t *counters = nullptr;       // [r][d][m]
+    uint64_t *coef_dev = nullptr;      // per relation: [d][coef_per_rep], concatenated
+    std::vector<size_t> coef_off;      // offset of relation k's table in coef_dev
+    EstimateWork work;
+    void *scratch = nullptr;           // partial sums of the LDS-segmented update
+    size_t scratch_bytes = 0;
+    void *result_host = nullptr;       // pinned host staging for results
+};
+
+cs_status estimate_run(Handle &h, hipStream_t s, cs_estimate_t *out, const cs_reps_t *reps);
+
+}  // namespace csk

@@ -1,0 +1,49 @@
+// Device-side polynomial hashing over the Mersenne prime field p = 2^61 - 1.
+//
+// The sign hashes are degree-3 polynomials (a 4-wise independent family) and the bin
+// hashes degree-1 polynomials (2-wise independent), as the initialization paragraph
+// of Sec. 3.2 requires; Sec. 4 evaluates them over a Mersenne prime field.  Keys are
+// 32-bit, so one Horner step v*x + a multiplies a 61-bit value by a 32-bit key: two
+// 32x32->64 multiplies, then the Mersenne fold 2^61 = 1 (mod p).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace csk {
+
+constexpr uint64_t kHashP = (1ull << 61) - 1;
+
+// One Horner step: returns r = v * x + a (mod p) in lazy form, r < 2^61 + 4.
+// Requires v < 2^62 and a < 2^61.
+__device__ __forceinline__ uint64_t hstep(uint64_t v, uint32_t x, uint64_t a)
+{
+    const uint64_t lo = (uint64_t)(uint32_t)v * (uint64_t)x;          // < 2^64
+    const uint64_t hi = (uint64_t)(uint32_t)(v >> 32) * (uint64_t)x;  // < 2^62
+    // v * x = t * 2^32 + (lo mod 2^32) with t = hi + (lo >> 32) < 2^62 + 2^32
+    const uint64_t t = hi + (lo >> 32);
+    // low 61 bits of v*x, and v*x >> 61
+    const uint64_t low61 = ((t & 0x1FFFFFFFull) << 32) | (lo & 0xFFFFFFFFull);
+    const uint64_t r = low61 + (t >> 29) + a;                          // < 2^62 + 2^34
+    return (r & kHashP) + (r >> 61);
+}
+
+__device__ __forceinline__ uint64_t hcanon(uint64_t r)
+{
+    return r >= kHashP ? r - kHashP : r;
+}
+
+// b0 + b1 x mod p (canonical)
+__device__ __forceinline__ uint64_t hash_deg1(const uint64_t *b, uint32_t x)
+{
+    return hcanon(hstep(b[1], x, b[0]));
+}
+
+// a0 + a1 x + a2 x^2 + a3 x^3 mod p (canonical)
+__device__ __forceinline__ uint64_t hash_deg3(const uint64_t *a, uint32_t x)
+{
+    return hcanon(hstep(hstep(hstep(a[3], x, a[2]), x, a[1]), x, a[0]));
+}
+
+}  // namespace csk

@@ -1,0 +1,103 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/csketch.h"
+
+namespace csk {
+
+constexpr int kMaxRel = 16;
+constexpr int kMaxAttr = 32;
+constexpr int kMaxCols = 8;          // attributes per relation
+constexpr int kMaxEdgesPerAttr = 8;  // joins per attribute
+constexpr int kMaxD = 64;
+constexpr int kMaxLog2M = 20;
+constexpr int kMaxPrimes = 12;       // modular path: up to ~370-bit results
+constexpr uint64_t kP61 = (1ull << 61) - 1;
+
+// ------------------------------------------------------------------ errors
+
+void set_error(const std::string &msg);
+cs_status fail(cs_status st, const std::string &msg);
+#define CSK_HIP(call)                                                                  \
+    do {                                                                               \
+        hipError_t _e = (call);                                                        \
+        if (_e != hipSuccess)                                                          \
+            return ::csk::fail(CS_EDEVICE, std::string(#call) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+// ------------------------------------------------------------------ plans
+
+// Per-relation hashing plan: key column c carries attribute omega[c]; its bin hash is
+// the component's, and its sign is the product over the joins at that attribute.
+// The coefficients of one repetition are laid out for the update kernel as, for each
+// column in order: b0, b1, then a0..a3 of each join at the column.
+struct RelPlan {
+    int32_t n_cols;
+    int32_t coef_per_rep;             // u64 coefficients per repetition
+    int32_t n_edges[kMaxCols];        // joins per column
+};
+
+// Modular op list (Alg. 3 in modular arithmetic) for general queries.
+enum OpCode : int32_t { OP_LOAD = 0, OP_ONES = 1, OP_HAD = 2, OP_CORR = 3 };
+struct Op {
+    int32_t code;
+    int32_t dst;   // register
+    int32_t src;   // register (HAD: dst *= src; CORR: dst = src star dst) or relation (LOAD)
+};
+
+struct Handle;  // defined in csk_api.cpp
+
+// ------------------------------------------------------------------ modular primes
+
+struct PrimeInfo {
+    uint32_t p;
+    uint32_t pinv_neg;   // -p^{-1} mod 2^32
+    uint32_t r2;         // 2^64 mod p   (R^2, R = 2^32)
+    uint32_t r3;         // 2^96 mod p   (R^3)
+    uint32_t neg2_64;    // (-2^64 * R) mod p: Montgomery form of -2^64
+    uint32_t g;          // generator of the multiplicative group
+};
+// NTT primes p < 2^31 with 2^kMaxLog2M | p - 1, largest first (host table).
+const std::vector<PrimeInfo> &ntt_primes();
+
+// ------------------------------------------------------------------ device tables
+
+// Twiddles exp(-2 pi i k / 2^L) for k < 2^L, fp64 complex interleaved, cached per
+// device and L.  Computed on the host in long double.
+const double *twiddles_f64(int device, int log2m, hipStream_t s, cs_status *st);
+// Montgomery-form powers of a primitive 2^L-th root of unity mod prime i (forward and
+// inverse tables, each 2^L entries), cached per device, L and prime.
+const uint32_t *roots_mod(int device, int log2m, int prime, bool inverse, hipStream_t s,
+                          cs_status *st);
+
+// ------------------------------------------------------------------ launchers
+
+struct UpdateArgs {
+    const uint32_t *keys;
+    const int64_t *weights;
+    uint64_t n;
+    const uint64_t *coef;   // [d][coef_per_rep]
+    uint64_t *sketch;       // [d][m]
+    uint32_t m;
+    int32_t d;
+    RelPlan plan;
+    void *scratch;          // partial-sum buffer of the LDS-segmented strategy (may be null)
+    size_t scratch_bytes;
+};
+struct SegGeom {
+    uint32_t R;        // counter cells per segment
+    int32_t segments;  // segments covering [d][m]
+    int32_t chunks;    // tuple chunks (partial buffers)
+};
+SegGeom seg_geometry(uint32_t m, int32_t d, bool narrow, size_t scratch_bytes);
+size_t seg_scratch_bytes(uint32_t m, int32_t d);
+cs_status launch_update(const UpdateArgs &a, int strategy, int grid_blocks, hipStream_t s);
+int auto_update_strategy(uint32_t m, int32_t d, uint64_t n, bool narrow, bool has_scratch);
+
+}  // namespace csk

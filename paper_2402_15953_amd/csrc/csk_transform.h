@@ -1,0 +1,63 @@
+// Transform launchers (fp64 FFT and NTT) and the per-prime constants they use.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "csk_internal.h"
+
+namespace csk {
+
+// Geometry of one transform pass: each block transforms 2^log2C interleaved transforms
+// of length 2^log2L whose element n of column c sits at
+// block_base + c * col_stride + n * elem_stride, block_base = blockIdx.x * block_stride.
+struct PassGeom {
+    int32_t log2m;
+    int32_t log2L;
+    int32_t log2C;
+    int32_t blocks;
+    int64_t elem_stride;
+    int64_t col_stride;
+    int64_t block_stride;
+    int32_t twiddle;   // multiply output n of column c by w_m^(n * (blockIdx.x * C + c))
+    int32_t scale;     // multiply by m^-1 (inverse NTT, last pass)
+};
+
+// Constants of one NTT prime, as the device reads them.
+struct PrimeDev {
+    uint32_t p;
+    uint32_t pinv_neg;   // -p^-1 mod 2^32
+    uint32_t r2;         // 2^64 mod p
+    uint32_t r3;         // 2^96 mod p
+    uint32_t neg2_64;    // Montgomery form of -2^64 mod p
+    uint32_t one;        // Montgomery form of 1 (2^32 mod p)
+    uint32_t minv[kMaxLog2M + 1];  // Montgomery form of 2^-L mod p
+};
+
+// Position of frequency f in the output of the forward transform of length 2^log2m.
+__host__ __device__ inline uint32_t freq_pos(uint32_t f, int log2m)
+{
+    if (log2m <= 12) return f;
+    const uint32_t n1 = 1u << (log2m - 12);
+    return ((f & (n1 - 1)) << 12) | (f >> (log2m - 12));
+}
+// Frequency held at position pos of the forward transform's output.
+__host__ __device__ inline uint32_t pos_freq(uint32_t pos, int log2m)
+{
+    if (log2m <= 12) return pos;
+    const int l1 = log2m - 12;
+    return (pos >> 12) | ((pos & 4095u) << l1);
+}
+
+cs_status fft_f64_forward(const int64_t *sk, const int32_t *pack_re, const int32_t *pack_im, int n_vec,
+                          double2 *buf, int log2m, const double2 *tw, int log2T, hipStream_t s);
+
+// sk != null: vector (prime i, j) is loaded from sketch sk_index[j] (first pass).
+cs_status ntt_forward(const int64_t *sk, const int32_t *sk_index, int vec_per_prime, int n_primes,
+                      uint32_t *buf, int log2m, const PrimeDev *primes, const uint32_t *roots, int log2T,
+                      hipStream_t s);
+cs_status ntt_inverse(int vec_per_prime, int n_primes, uint32_t *buf, int log2m, const PrimeDev *primes,
+                      const uint32_t *roots, int log2T, hipStream_t s);
+
+}  // namespace csk

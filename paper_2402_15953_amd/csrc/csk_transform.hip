@@ -1,0 +1,282 @@
+// Power-of-two transforms over the sketches: the fp64 complex FFT used by the estimate
+// (Alg. 3 evaluates cross-correlations through FFT / IFFT) and the number-theoretic
+// transform (same structure, Montgomery arithmetic modulo a 31-bit prime) used for the
+// exact modular evaluation.
+//
+// Lengths up to 4096 are done in one pass inside LDS.  Longer lengths m = N1 * 4096 use
+// the four-step decomposition (Bailey): element n = 4096 n1 + n2.
+//   forward: pass 1 transforms each column n2 over n1 (stride 4096) and multiplies
+//            output f1 by w_m^(f1 n2); pass 2 transforms each row over n2.  Position
+//            4096 f1 + f2 then holds frequency f = f1 + N1 f2 (no final transpose).
+//   inverse: takes that permuted order back to natural order: row pass over f2 with
+//            w_m^(-n2 f1) applied to output n2, then the column pass over f1.
+// Inside LDS each tile is loaded in bit-reversed order and finished by radix-2
+// decimation-in-time stages; twiddles come from host-computed tables.
+#include <hip/hip_runtime.h>
+
+#include "csk_internal.h"
+#include "csk_rings.h"
+#include "csk_transform.h"
+
+namespace csk {
+
+namespace {
+
+constexpr int kTile = 4096;
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ uint32_t bitrev(uint32_t x, int bits)
+{
+    return bits ? (__brev(x) >> (32 - bits)) : 0u;
+}
+
+// Radix-2 DIT stages on C interleaved transforms of length 2^log2L held in LDS as
+// s[n * C + c] (bit-reversed input, natural output).  tw[k] = w_T^k, T = 2^log2T.
+template <class Ring>
+__device__ __forceinline__ void lds_stages(typename Ring::T *s, int log2L, int log2C, const Ring &R,
+                                           const typename Ring::T *__restrict__ tw, int log2T)
+{
+    const int C = 1 << log2C;
+    const int nbf = (1 << (log2L - 1)) << log2C;
+    for (int lh = 0; lh < log2L; ++lh) {
+        const int half = 1 << lh;
+        for (int b = threadIdx.x; b < nbf; b += kThreads) {
+            const int c = b & (C - 1);
+            const int bb = b >> log2C;
+            const int k = bb & (half - 1);
+            const int i0 = ((bb >> lh) << (lh + 1)) + k;
+            const int i1 = i0 + half;
+            const typename Ring::T u = s[i0 * C + c];
+            const typename Ring::T v = R.mul(s[i1 * C + c], tw[(size_t)k << (log2T - lh - 1)]);
+            s[i0 * C + c] = R.add(u, v);
+            s[i1 * C + c] = R.sub(u, v);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- fp64 complex FFT pass
+
+// Source of a pass: either the complex work buffer, or (first pass) the int64 sketches
+// of the (relation, repetition) pair packed into one complex vector: re + i * im.
+struct F64Src {
+    const int64_t *sk;        // sketches, [n_sk][m]
+    const int32_t *pack_re;   // [n_vec] sketch index for the real part
+    const int32_t *pack_im;   // [n_vec] sketch index for the imaginary part, -1 = none
+};
+
+__global__ __launch_bounds__(kThreads) void k_fft_f64(F64Src src, double2 *buf, PassGeom g,
+                                                      const double2 *__restrict__ tw, int log2T)
+{
+    __shared__ double2 s[kTile];
+    const int v = blockIdx.y;
+    const int blk = blockIdx.x;
+    const int C = 1 << g.log2C;
+    const int L = 1 << g.log2L;
+    const int64_t m = (int64_t)1 << g.log2m;
+    const int64_t base = (int64_t)blk * g.block_stride;
+    double2 *vec = buf + (size_t)v * m;
+    const int total = L << g.log2C;
+    if (src.sk) {
+        const int64_t *re = src.sk + (size_t)src.pack_re[v] * m;
+        const int im_idx = src.pack_im[v];
+        const int64_t *im = im_idx >= 0 ? src.sk + (size_t)im_idx * m : nullptr;
+        for (int idx = threadIdx.x; idx < total; idx += kThreads) {
+            const int n = idx >> g.log2C, c = idx & (C - 1);
+            const int64_t pos = base + (int64_t)c * g.col_stride + (int64_t)n * g.elem_stride;
+            s[(bitrev(n, g.log2L) << g.log2C) + c] =
+                make_double2((double)re[pos], im ? (double)im[pos] : 0.0);
+        }
+    } else {
+        for (int idx = threadIdx.x; idx < total; idx += kThreads) {
+            const int n = idx >> g.log2C, c = idx & (C - 1);
+            const int64_t pos = base + (int64_t)c * g.col_stride + (int64_t)n * g.elem_stride;
+            s[(bitrev(n, g.log2L) << g.log2C) + c] = vec[pos];
+        }
+    }
+    __syncthreads();
+    RingC R;
+    lds_stages<RingC>(s, g.log2L, g.log2C, R, tw, log2T);
+    for (int idx = threadIdx.x; idx < total; idx += kThreads) {
+        const int n = idx >> g.log2C, c = idx & (C - 1);
+        const int64_t pos = base + (int64_t)c * g.col_stride + (int64_t)n * g.elem_stride;
+        double2 val = s[(n << g.log2C) + c];
+        if (g.twiddle) {
+            const int64_t colid = (int64_t)blk * C + c;
+            const int64_t e = ((int64_t)n * colid) & (m - 1);
+            val = R.mul(val, tw[(size_t)e << (log2T - g.log2m)]);
+        }
+        vec[pos] = val;
+    }
+}
+
+// ---------------------------------------------------------------- NTT pass
+
+struct ModSrc {
+    const int64_t *sk;        // sketches [n_sk][m] (first pass only; else null)
+    const int32_t *sk_index;  // [vec_per_prime] sketch index of vector v % vec_per_prime
+};
+
+__global__ __launch_bounds__(kThreads) void k_ntt(ModSrc src, uint32_t *buf, PassGeom g, int vec_per_prime,
+                                                  const PrimeDev *__restrict__ primes,
+                                                  const uint32_t *__restrict__ roots, int log2T, int inverse)
+{
+    __shared__ uint32_t s[kTile];
+    const int v = blockIdx.y;
+    const int pi = v / vec_per_prime;
+    const PrimeDev P = primes[pi];
+    const RingM R{P.p, P.pinv_neg};
+    const uint32_t *tw = roots + ((size_t)(2 * pi + inverse) << log2T);
+    const int blk = blockIdx.x;
+    const int C = 1 << g.log2C;
+    const int L = 1 << g.log2L;
+    const int64_t m = (int64_t)1 << g.log2m;
+    const int64_t base = (int64_t)blk * g.block_stride;
+    uint32_t *vec = buf + (size_t)v * m;
+    const int total = L << g.log2C;
+    if (src.sk) {
+        const int64_t *in = src.sk + (size_t)src.sk_index[v % vec_per_prime] * m;
+        for (int idx = threadIdx.x; idx < total; idx += kThreads) {
+            const int n = idx >> g.log2C, c = idx & (C - 1);
+            const int64_t pos = base + (int64_t)c * g.col_stride + (int64_t)n * g.elem_stride;
+            s[(bitrev(n, g.log2L) << g.log2C) + c] = mont_from_i64(R, in[pos], P.r2, P.r3, P.neg2_64);
+        }
+    } else {
+        for (int idx = threadIdx.x; idx < total; idx += kThreads) {
+            const int n = idx >> g.log2C, c = idx & (C - 1);
+            const int64_t pos = base + (int64_t)c * g.col_stride + (int64_t)n * g.elem_stride;
+            s[(bitrev(n, g.log2L) << g.log2C) + c] = vec[pos];
+        }
+    }
+    __syncthreads();
+    lds_stages<RingM>(s, g.log2L, g.log2C, R, tw, log2T);
+    for (int idx = threadIdx.x; idx < total; idx += kThreads) {
+        const int n = idx >> g.log2C, c = idx & (C - 1);
+        const int64_t pos = base + (int64_t)c * g.col_stride + (int64_t)n * g.elem_stride;
+        uint32_t val = s[(n << g.log2C) + c];
+        if (g.twiddle) {
+            const int64_t colid = (int64_t)blk * C + c;
+            const int64_t e = ((int64_t)n * colid) & (m - 1);
+            val = R.mul(val, tw[(size_t)e << (log2T - g.log2m)]);
+        }
+        if (g.scale) val = R.mul(val, P.minv[g.log2m]);
+        vec[pos] = val;
+    }
+}
+
+PassGeom column_pass(int log2m, bool twiddle)
+{
+    PassGeom g{};
+    g.log2m = log2m;
+    g.log2L = log2m - 12;
+    g.log2C = 12 - g.log2L;
+    g.elem_stride = kTile;
+    g.col_stride = 1;
+    g.block_stride = (int64_t)1 << g.log2C;
+    g.blocks = kTile >> g.log2C;
+    g.twiddle = twiddle;
+    return g;
+}
+
+PassGeom row_pass(int log2m, bool twiddle)
+{
+    PassGeom g{};
+    g.log2m = log2m;
+    g.log2L = 12;
+    g.log2C = 0;
+    g.elem_stride = 1;
+    g.col_stride = 0;
+    g.block_stride = kTile;
+    g.blocks = 1 << (log2m - 12);
+    g.twiddle = twiddle;
+    return g;
+}
+
+PassGeom single_pass(int log2m)
+{
+    PassGeom g{};
+    g.log2m = log2m;
+    g.log2L = log2m;
+    g.log2C = 0;
+    g.elem_stride = 1;
+    g.block_stride = 0;
+    g.blocks = 1;
+    return g;
+}
+
+}  // namespace
+
+cs_status fft_f64_forward(const int64_t *sk, const int32_t *pack_re, const int32_t *pack_im, int n_vec,
+                          double2 *buf, int log2m, const double2 *tw, int log2T, hipStream_t s)
+{
+    if (n_vec == 0) return CS_OK;
+    F64Src first{sk, pack_re, pack_im};
+    F64Src self{nullptr, nullptr, nullptr};
+    if (log2m <= 12) {
+        PassGeom g = single_pass(log2m);
+        hipLaunchKernelGGL(k_fft_f64, dim3(g.blocks, n_vec), dim3(kThreads), 0, s, first, buf, g, tw, log2T);
+        CSK_HIP(hipGetLastError());
+        return CS_OK;
+    }
+    PassGeom g1 = column_pass(log2m, true);
+    hipLaunchKernelGGL(k_fft_f64, dim3(g1.blocks, n_vec), dim3(kThreads), 0, s, first, buf, g1, tw, log2T);
+    CSK_HIP(hipGetLastError());
+    PassGeom g2 = row_pass(log2m, false);
+    hipLaunchKernelGGL(k_fft_f64, dim3(g2.blocks, n_vec), dim3(kThreads), 0, s, self, buf, g2, tw, log2T);
+    CSK_HIP(hipGetLastError());
+    return CS_OK;
+}
+
+cs_status ntt_forward(const int64_t *sk, const int32_t *sk_index, int vec_per_prime, int n_primes,
+                      uint32_t *buf, int log2m, const PrimeDev *primes, const uint32_t *roots, int log2T,
+                      hipStream_t s)
+{
+    const int n_vec = vec_per_prime * n_primes;
+    if (n_vec == 0) return CS_OK;
+    ModSrc first{sk, sk_index};
+    ModSrc self{nullptr, nullptr};
+    if (log2m <= 12) {
+        PassGeom g = single_pass(log2m);
+        hipLaunchKernelGGL(k_ntt, dim3(g.blocks, n_vec), dim3(kThreads), 0, s, sk ? first : self, buf, g,
+                           vec_per_prime, primes, roots, log2T, 0);
+        CSK_HIP(hipGetLastError());
+        return CS_OK;
+    }
+    PassGeom g1 = column_pass(log2m, true);
+    hipLaunchKernelGGL(k_ntt, dim3(g1.blocks, n_vec), dim3(kThreads), 0, s, sk ? first : self, buf, g1,
+                       vec_per_prime, primes, roots, log2T, 0);
+    CSK_HIP(hipGetLastError());
+    PassGeom g2 = row_pass(log2m, false);
+    hipLaunchKernelGGL(k_ntt, dim3(g2.blocks, n_vec), dim3(kThreads), 0, s, self, buf, g2, vec_per_prime,
+                       primes, roots, log2T, 0);
+    CSK_HIP(hipGetLastError());
+    return CS_OK;
+}
+
+cs_status ntt_inverse(int vec_per_prime, int n_primes, uint32_t *buf, int log2m, const PrimeDev *primes,
+                      const uint32_t *roots, int log2T, hipStream_t s)
+{
+    const int n_vec = vec_per_prime * n_primes;
+    if (n_vec == 0) return CS_OK;
+    ModSrc self{nullptr, nullptr};
+    if (log2m <= 12) {
+        PassGeom g = single_pass(log2m);
+        g.scale = 1;
+        hipLaunchKernelGGL(k_ntt, dim3(g.blocks, n_vec), dim3(kThreads), 0, s, self, buf, g, vec_per_prime,
+                           primes, roots, log2T, 1);
+        CSK_HIP(hipGetLastError());
+        return CS_OK;
+    }
+    PassGeom g1 = row_pass(log2m, true);
+    hipLaunchKernelGGL(k_ntt, dim3(g1.blocks, n_vec), dim3(kThreads), 0, s, self, buf, g1, vec_per_prime,
+                       primes, roots, log2T, 1);
+    CSK_HIP(hipGetLastError());
+    PassGeom g2 = column_pass(log2m, false);
+    g2.scale = 1;
+    hipLaunchKernelGGL(k_ntt, dim3(g2.blocks, n_vec), dim3(kThreads), 0, s, self, buf, g2, vec_per_prime,
+                       primes, roots, log2T, 1);
+    CSK_HIP(hipGetLastError());
+    return CS_OK;
+}
+
+}  // namespace csk

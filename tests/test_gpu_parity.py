@@ -1,0 +1,256 @@
+"""GPU path versus the CPU oracle, through the C ABI.
+
+Sketches must be bit-identical; estimates must equal the oracle's exact integers for
+every repetition (the library resolves every repetition exactly unless flagged).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from tests.helpers import keys_u32, oracle_sketches, to_device_keys
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    import paper_2402_15953_amd as csk
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _run_gpu(graph, rels, weights, m, d, seed, strategy=0, grid=0):
+    sk = csk.Sketch(graph, m, d, seed)
+    for k, keys in enumerate(rels):
+        kd = to_device_keys(keys)
+        wd = None if weights is None else torch.from_numpy(weights[k]).cuda()
+        sk.update(k, kd, wd, strategy=strategy, grid=grid)
+    torch.cuda.synchronize()
+    return sk
+
+
+def _rels(graph, n, dist, D, config, s=1.1):
+    return [keys_u32(W.relation_keys(graph, k, n, dist, config=config, s=s, D=D)) for k in range(graph.n_rel)]
+
+
+# --------------------------------------------------------------------------- setup checks
+
+@pytest.mark.parametrize("graph", [W.single_join(), W.chain(3), W.chain(5), W.star(4), W.fig3_query(),
+                                   W.multiway_star(3)])
+def test_coefficients_and_components_match(graph):
+    _say("coeffs", graph.name)
+    info = oracle.analyze(graph)
+    for seed in (0, 7, 2 ** 63 + 5):
+        sk = csk.Sketch(graph, 1024, 5, seed)
+        s, b = sk.coefficients()
+        co = oracle.draw_coefficients(seed, 5, len(info.edges), info.n_comp)
+        assert np.array_equal(s, co.sign_array())
+        assert np.array_equal(b, co.bin_array())
+        assert sk.components() == info.psi
+        sk.close()
+
+
+def test_invalid_arguments_rejected():
+    with pytest.raises(csk.CsError) as e:
+        csk.Sketch(W.chain(3), 1000, 5, 1)   # m not a power of two
+    assert e.value.status == csk.CS_EINVAL
+    with pytest.raises(csk.CsError) as e:
+        csk.Sketch(W.JoinGraph(3, (0, 1, 2), ((0, 1), (1, 2), (0, 2))), 1024, 5, 1)
+    assert e.value.status == csk.CS_EGRAPH
+    with pytest.raises(csk.CsError) as e:
+        csk.Sketch(W.chain(3), 1024, 65, 1)
+    assert e.value.status == csk.CS_EINVAL
+    sk = csk.Sketch(W.chain(3), 1024, 5, 1)
+    keys = torch.zeros(10, 1, dtype=torch.int32, device="cuda")
+    with pytest.raises(csk.CsError):
+        sk.update(3, keys)
+    sk.update(0, keys[:0])  # n = 0 is a no-op
+    assert not sk.read_sketch(0).any()
+
+
+# --------------------------------------------------------------------------- sketch parity (Alg. 2)
+
+SKETCH_CASES = [
+    # graph, n, m, d, dist, D, weights
+    (W.single_join(), 100_000, 1024, 5, "uniform", 10_000, None),
+    (W.chain(3), 65, 2, 1, "uniform", 50, "pm1"),
+    (W.chain(3), 1, 16, 3, "uniform", 50, None),
+    (W.chain(3), 64, 1 << 16, 9, "zipf", 10 ** 6, None),
+    (W.chain(3), 20_011, 1 << 16, 9, "zipf", 10 ** 6, "big"),
+    (W.chain(5), 30_000, 1 << 13, 15, "zipf", 10 ** 7, "pm1"),
+    (W.star(5), 12_345, 4096, 5, "zipf", 1000, None),
+    (W.fig3_query(), 7_777, 512, 7, "uniform", 200, "big"),
+    (W.multiway_star(4), 5_000, 256, 4, "zipf", 100, None),
+    (W.chain(3), 50_000, 1 << 18, 3, "zipf", 10 ** 7, None),
+]
+
+
+def _weights(kind, graph, n):
+    if kind is None:
+        return None
+    if kind == "pm1":
+        return [W.turnstile_weights(n, 0.1, seed=k).numpy() for k in range(graph.n_rel)]
+    return [W.random_weights(n, -2 ** 62, 2 ** 62, seed=50 + k).numpy() for k in range(graph.n_rel)]
+
+
+@pytest.mark.parametrize("case", range(len(SKETCH_CASES)))
+@pytest.mark.parametrize("strategy", [1, 2, 3])
+def test_sketch_bit_exact(case, strategy):
+    graph, n, m, d, dist, D, wk = SKETCH_CASES[case]
+    _say("sketch", case, graph.name, n, m, d, dist, wk, "strategy", strategy)
+    rels = _rels(graph, n, dist, D, config=90 + case)
+    weights = _weights(wk, graph, n)
+    seed = 1000 + case
+    info, co, ref = oracle_sketches(graph, rels, weights, m, d, seed)
+    sk = _run_gpu(graph, rels, weights, m, d, seed, strategy=strategy)
+    for k in range(graph.n_rel):
+        got = sk.read_sketch(k)
+        assert np.array_equal(got, ref[k]), (k, np.argwhere(got != ref[k])[:5])
+    sk.close()
+
+
+def test_sketch_batches_and_misaligned_keys():
+    """Streaming in uneven batches, including a two-column key buffer that is only
+    4-byte aligned, gives the same counters as one batch (linearity, Sec. 2.2)."""
+    graph = W.chain(3)
+    n, m, d, seed = 10_001, 4096, 5, 3
+    rels = _rels(graph, n, "zipf", 10 ** 5, config=77)
+    info, co, ref = oracle_sketches(graph, rels, None, m, d, seed)
+    sk = csk.Sketch(graph, m, d, seed)
+    for k, keys in enumerate(rels):
+        a = keys.shape[1]
+        buf = np.zeros(n * a + 1, dtype=np.uint32)
+        buf[1:] = keys.reshape(-1)
+        dev = torch.from_numpy(buf.view(np.int32)).cuda()
+        flat = dev[1:]  # 4-byte aligned only
+        cuts = [0, 1, 64, 1000, 5000, n]
+        for lo, hi in zip(cuts[:-1], cuts[1:]):
+            part = flat[lo * a:hi * a].view(hi - lo, a)
+            sk.update(k, part)
+    torch.cuda.synchronize()
+    for k in range(graph.n_rel):
+        assert np.array_equal(sk.read_sketch(k), ref[k])
+
+
+def test_turnstile_insert_delete_and_reset():
+    graph = W.chain(3)
+    n, m, d = 5000, 1024, 5
+    rels = _rels(graph, n, "zipf", 1000, config=78)
+    sk = csk.Sketch(graph, m, d, 11)
+    for k, keys in enumerate(rels):
+        kd = to_device_keys(keys)
+        w = torch.randint(-1000, 1000, (n,), dtype=torch.int64, device="cuda")
+        sk.update(k, kd, w)
+        sk.update(k, kd, -w)
+    assert all(not sk.read_sketch(k).any() for k in range(3))
+    sk.update(0, to_device_keys(rels[0]))
+    assert sk.read_sketch(0).any()
+    sk.reset()
+    assert not sk.read_sketch(0).any()
+
+
+def test_merge_is_sum():
+    graph = W.star(3)
+    n, m, d, seed = 3000, 2048, 5, 9
+    rels = _rels(graph, n, "uniform", 500, config=79)
+    a = _run_gpu(graph, [r[: n // 2] for r in rels], None, m, d, seed)
+    b = _run_gpu(graph, [r[n // 2:] for r in rels], None, m, d, seed)
+    a.merge_from(b)
+    torch.cuda.synchronize()
+    info, co, ref = oracle_sketches(graph, rels, None, m, d, seed)
+    for k in range(3):
+        assert np.array_equal(a.read_sketch(k), ref[k])
+
+
+# --------------------------------------------------------------------------- estimate parity (Eq. 5 / Alg. 3)
+
+INT128_EXACT = 2 ** 125   # the library represents exact results below this magnitude
+
+
+def _check_estimate(graph, sk, ref_sketches, m, d, info):
+    """Every repetition below 2^125 must equal the oracle's exact integer; beyond it the
+    fp64 value must be within 1e-12 relative; the median must match the oracle's."""
+    est = sk.estimate(reps=True)
+    reps = []
+    for t in range(d):
+        exact = oracle.estimate_alg3(info, [ref_sketches[k][t] for k in range(graph.n_rel)], m, method="ntt")
+        reps.append(exact)
+        if abs(exact) < INT128_EXACT:
+            assert est["rep_ints"][t] is not None, (t, est)
+            assert est["rep_ints"][t] == exact, (t, est["rep_ints"][t], exact, est["rep_bounds"][t])
+            assert est["rep_values"][t] == float(exact)
+        else:
+            assert abs(est["rep_values"][t] - exact) <= 1e-12 * abs(exact), (t, est["rep_values"][t], exact)
+    med = oracle.median_lower(reps)
+    if abs(med) < INT128_EXACT:
+        assert est["exact"]
+        assert est["value"] == float(med)
+    else:
+        assert abs(est["value"] - med) <= 1e-12 * abs(med)
+    if -2 ** 63 <= med < 2 ** 63:
+        assert est["value_i64"] == med
+    return est
+
+
+EST_CASES = [
+    # graph, n, m, d, dist, D, s, weights
+    (W.single_join(), 100_000, 1024, 5, "uniform", 10_000, 1.0, None),
+    (W.chain(3), 2_000, 64, 5, "zipf", 100, 1.1, None),
+    (W.chain(3), 200_000, 1 << 16, 9, "zipf", 10 ** 6, 1.1, None),
+    (W.chain(4), 50_000, 8192, 5, "zipf", 10 ** 4, 1.2, "pm1"),
+    (W.chain(5), 100_000, 1 << 14, 7, "zipf", 10 ** 5, 1.5, None),
+    (W.star(4), 30_000, 4096, 5, "zipf", 1000, 1.2, None),
+    (W.star(6), 10_000, 1024, 9, "zipf", 1000, 1.2, None),
+    (W.chain(3), 3_000, 1 << 12, 5, "zipf", 10 ** 4, 1.1, "big"),
+    (W.chain(4), 3_000, 1 << 10, 5, "zipf", 10 ** 4, 1.1, "huge"),
+    (W.fig3_query(), 3_000, 256, 5, "zipf", 500, 1.1, None),
+    (W.multiway_star(3), 2_000, 128, 3, "uniform", 50, 1.0, None),
+    (W.chain(3), 100_000, 1 << 18, 3, "zipf", 10 ** 7, 1.0, None),
+    (W.chain(6), 5_000, 2, 4, "uniform", 30, 1.0, None),
+]
+
+
+@pytest.mark.parametrize("case", range(len(EST_CASES)))
+def test_estimate_exact(case):
+    graph, n, m, d, dist, D, s, wk = EST_CASES[case]
+    _say("estimate", case, graph.name, n, m, d, dist, s, wk)
+    rels = _rels(graph, n, dist, D, config=60 + case, s=s)
+    weights = None
+    if wk == "pm1":
+        weights = [W.turnstile_weights(n, 0.1, seed=k).numpy() for k in range(graph.n_rel)]
+    elif wk == "big":
+        weights = [W.random_weights(n, -2 ** 30, 2 ** 30, seed=60 + k).numpy() for k in range(graph.n_rel)]
+    elif wk == "huge":
+        weights = [W.random_weights(n, -2 ** 45, 2 ** 45, seed=60 + k).numpy() for k in range(graph.n_rel)]
+    seed = 7 + case
+    info, co, ref = oracle_sketches(graph, rels, weights, m, d, seed)
+    sk = _run_gpu(graph, rels, weights, m, d, seed)
+    for k in range(graph.n_rel):
+        assert np.array_equal(sk.read_sketch(k), ref[k])
+    est = _check_estimate(graph, sk, ref, m, d, info)
+    _say("  value", est["value"], "modular reps", est["n_modular"])
+    sk.close()
+
+
+def test_empty_sketches_estimate_zero():
+    for graph in (W.single_join(), W.chain(4), W.fig3_query()):
+        sk = csk.Sketch(graph, 1024, 3, 1)
+        est = sk.estimate(reps=True)
+        assert est["exact"] and est["value"] == 0.0 and est["value_i64"] == 0
+        assert est["rep_ints"] == [0, 0, 0]
+        sk.close()
+
+
+def test_estimate_is_deterministic():
+    graph = W.chain(4)
+    n, m, d = 50_000, 1 << 15, 5
+    rels = _rels(graph, n, "zipf", 10 ** 5, config=81)
+    sk = _run_gpu(graph, rels, None, m, d, 5)
+    a = sk.estimate(reps=True)
+    b = sk.estimate(reps=True)
+    assert a == b
