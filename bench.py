@@ -28,11 +28,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "tuple updates/s into d×m count sketches + estimates/s; batched vs plain; p99 ms"
 HBM_PEAK_GBS = 8000.0
-# Horner-step peak (mod 2^61-1 multiply-add by a 32-bit key): 256 CUs x 64 lanes x
-# 2.4 GHz / 80 lane-cycles... derived from the compiled instruction mix of one step:
-# 12 full-rate VALU instructions (4 cycles per wave64) + 2 v_mad_u64_u32 (16 cycles)
-# = 80 SIMD cycles per wave64 step, 4 SIMDs per CU.
-ALU_STEP_PEAK = 256 * 4 * 64 * 2.4e9 / 80.0
+# Horner-step peak (one v <- v * x + a mod 2^61 - 1 with a 32-bit key x): the chip
+# issues 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 VALU lane-instructions/s,
+# and the compiled step is 13 VALU instructions (2 v_mad_u64_u32, 64-bit adds and
+# shifts, the Mersenne fold), so 3.02e12 steps/s.
+ALU_STEP_PEAK = 256 * 4 * 16 * 2.4e9 / 13.0
 
 
 def parse():

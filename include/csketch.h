@@ -100,8 +100,16 @@ typedef enum cs_update_strategy {
                                      of tuples in LDS, stores partial sums to the
                                      handle's scratch buffer, and a reduce kernel adds
                                      them into the counters */
-    CS_UPDATE_WAVE_AGGREGATE = 3  /* equal buckets of one wavefront merged before the atomic */
+    CS_UPDATE_WAVE_AGGREGATE = 3, /* equal buckets of one wavefront merged before the atomic */
+    CS_UPDATE_PARTITION = 4       /* sort by bucket: each tuple hashed once per repetition
+                                     into 16-bit records partitioned by (repetition, bucket
+                                     range) through LDS, then one workgroup per partition
+                                     sums its records in LDS (segmented reduce); needs
+                                     weights NULL or CS_UPDATE_UNIT_WEIGHTS */
 } cs_update_strategy;
+
+/* cs_update_ex flags */
+#define CS_UPDATE_UNIT_WEIGHTS 1  /* the caller guarantees every weight is +1 or -1 */
 
 /* Estimate plans chosen at cs_create from the join graph. */
 typedef enum cs_plan_kind {
@@ -161,7 +169,8 @@ cs_status cs_update(cs_sketch *h, int32_t rel, const uint32_t *keys, const int64
 /* Same with an explicit strategy and launch width (0 = automatic); for tests and
  * tuning.  CS_EINVAL if the strategy does not support this handle's m and d. */
 cs_status cs_update_ex(cs_sketch *h, int32_t rel, const uint32_t *keys, const int64_t *weights,
-                       uint64_t n, void *stream, int32_t strategy, int32_t grid_blocks);
+                       uint64_t n, void *stream, int32_t strategy, int32_t grid_blocks,
+                       int32_t flags);
 
 /* ------------------------------------------------------------------ estimate (Eq. 5, Alg. 3) */
 

@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcsketch.so")
 
 CS_OK, CS_EINVAL, CS_EGRAPH, CS_ENOMEM, CS_EDEVICE, CS_EBUSY, CS_ERANGE = range(7)
-UPDATE_AUTO, UPDATE_GLOBAL_ATOMIC, UPDATE_LDS_PRIVATE, UPDATE_WAVE_AGGREGATE = range(4)
+UPDATE_AUTO, UPDATE_GLOBAL_ATOMIC, UPDATE_LDS_PRIVATE, UPDATE_WAVE_AGGREGATE, UPDATE_PARTITION = range(5)
+UPDATE_UNIT_WEIGHTS = 1
 PLAN_DOT, PLAN_SPECTRAL, PLAN_GENERAL = 1, 2, 3
 
 EXPORTED = [
@@ -75,7 +76,7 @@ def lib() -> ctypes.CDLL:
         L.cs_get_info.argtypes = [vp, ctypes.POINTER(_Info)]
         L.cs_last_error.restype = ctypes.c_char_p
         L.cs_update.argtypes = [vp, i32, vp, vp, u64, vp]
-        L.cs_update_ex.argtypes = [vp, i32, vp, vp, u64, vp, i32, i32]
+        L.cs_update_ex.argtypes = [vp, i32, vp, vp, u64, vp, i32, i32, i32]
         L.cs_estimate.argtypes = [vp, vp, ctypes.POINTER(_Estimate), ctypes.POINTER(_Reps)]
         L.cs_reset.argtypes = [vp, vp]
         L.cs_merge.argtypes = [vp, vp, vp]
@@ -147,9 +148,10 @@ class Sketch:
         _check(lib().cs_get_info(self._h, ctypes.byref(i)))
         return {f: getattr(i, f) for f, _ in _Info._fields_}
 
-    def update(self, rel: int, keys, weights=None, stream=None, strategy: int = UPDATE_AUTO, grid: int = 0):
+    def update(self, rel: int, keys, weights=None, stream=None, strategy: int = UPDATE_AUTO, grid: int = 0,
+               unit_weights: bool = False):
         """keys: device int32/uint32 tensor [n, a_rel] (or [n] for one column), contiguous;
-        weights: device int64 tensor [n] or None."""
+        weights: device int64 tensor [n] or None; unit_weights: every weight is +-1."""
         import torch
         if keys.dtype not in (torch.int32, torch.uint32) or not keys.is_cuda or not keys.is_contiguous():
             raise TypeError("keys must be a contiguous int32/uint32 device tensor")
@@ -161,7 +163,8 @@ class Sketch:
                 raise TypeError("weights must be a contiguous int64 device tensor of length n")
             wp = ctypes.c_void_p(weights.data_ptr())
         _check(lib().cs_update_ex(self._h, int(rel), ctypes.c_void_p(keys.data_ptr()), wp, int(n),
-                                  _stream_ptr(stream), int(strategy), int(grid)))
+                                  _stream_ptr(stream), int(strategy), int(grid),
+                                  UPDATE_UNIT_WEIGHTS if unit_weights else 0))
 
     def estimate(self, stream=None, reps: bool = False) -> dict:
         e = _Estimate()

@@ -350,14 +350,14 @@ cs_status cs_get_info(const cs_sketch *hs, cs_info_t *out)
 }
 
 cs_status cs_update_ex(cs_sketch *hs, int32_t rel, const uint32_t *keys, const int64_t *weights, uint64_t n,
-                       void *stream, int32_t strategy, int32_t grid_blocks)
+                       void *stream, int32_t strategy, int32_t grid_blocks, int32_t flags)
 {
     if (!hs) return fail(CS_EINVAL, "null handle");
     Handle &h = hs->h;
     if (rel < 0 || rel >= h.g.n_rel) return fail(CS_EINVAL, "relation out of range");
     if (n == 0) return CS_OK;
     if (!keys) return fail(CS_EINVAL, "null keys");
-    if (strategy < CS_UPDATE_AUTO || strategy > CS_UPDATE_WAVE_AGGREGATE) return fail(CS_EINVAL, "bad strategy");
+    if (strategy < CS_UPDATE_AUTO || strategy > CS_UPDATE_PARTITION) return fail(CS_EINVAL, "bad strategy");
     UpdateArgs a;
     a.keys = keys;
     a.weights = weights;
@@ -369,13 +369,14 @@ cs_status cs_update_ex(cs_sketch *hs, int32_t rel, const uint32_t *keys, const i
     a.plan = h.g.rel[rel];
     a.scratch = h.scratch;
     a.scratch_bytes = h.scratch_bytes;
+    a.unit_weights = (flags & CS_UPDATE_UNIT_WEIGHTS) != 0;
     return launch_update(a, strategy, grid_blocks, static_cast<hipStream_t>(stream));
 }
 
 cs_status cs_update(cs_sketch *hs, int32_t rel, const uint32_t *keys, const int64_t *weights, uint64_t n,
                     void *stream)
 {
-    return cs_update_ex(hs, rel, keys, weights, n, stream, CS_UPDATE_AUTO, 0);
+    return cs_update_ex(hs, rel, keys, weights, n, stream, CS_UPDATE_AUTO, 0, 0);
 }
 
 cs_status cs_estimate(cs_sketch *hs, void *stream, cs_estimate_t *out, const cs_reps_t *reps)

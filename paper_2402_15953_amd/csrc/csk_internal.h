@@ -89,6 +89,7 @@ struct UpdateArgs {
     RelPlan plan;
     void *scratch;          // partial-sum buffer of the LDS-segmented strategy (may be null)
     size_t scratch_bytes;
+    bool unit_weights;      // caller guarantees every weight is +1 or -1
 };
 struct SegGeom {
     uint32_t R;        // counter cells per segment
@@ -96,8 +97,17 @@ struct SegGeom {
     int32_t chunks;    // tuple chunks (partial buffers)
 };
 SegGeom seg_geometry(uint32_t m, int32_t d, bool narrow, size_t scratch_bytes);
+constexpr int kMaxPartRanges = 512;
+constexpr uint64_t kPartMaxChunk = 1ull << 21;
+struct PartGeom {
+    int32_t log2R;      // bucket range = 2^log2R buckets
+    int32_t ranges;     // ranges per repetition
+    uint64_t chunk;     // tuples per pass pair
+    size_t tab_offset;  // range table after the records in the scratch buffer
+};
+PartGeom part_geometry(uint32_t m, int32_t d, size_t scratch_bytes);
 size_t seg_scratch_bytes(uint32_t m, int32_t d);
 cs_status launch_update(const UpdateArgs &a, int strategy, int grid_blocks, hipStream_t s);
-int auto_update_strategy(uint32_t m, int32_t d, uint64_t n, bool narrow, bool has_scratch);
+int auto_update_strategy(uint32_t m, int32_t d, uint64_t n, int n_cols, bool unit, bool has_scratch);
 
 }  // namespace csk

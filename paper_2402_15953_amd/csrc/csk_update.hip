@@ -214,7 +214,8 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg(const uint32_t *__rest
             const uint64_t flat = ((uint64_t)t << log2m) + j;
             const uint32_t loc = (uint32_t)(flat - cell0);
             if constexpr (sizeof(CT) == 4) {
-                atomicAdd(reinterpret_cast<unsigned int *>(&s_c[loc]), neg ? 0xFFFFFFFFu : 1u);
+                const int32_t v32 = (int32_t)delta;  // +1, or +-1 with unit weights
+                atomicAdd(&s_c[loc], neg ? -v32 : v32);
             } else {
                 const uint64_t val = neg ? (uint64_t)0 - (uint64_t)delta : (uint64_t)delta;
                 atomicAdd(reinterpret_cast<unsigned long long *>(&s_c[loc]), (unsigned long long)val);
@@ -235,6 +236,202 @@ __global__ void k_seg_reduce(const CT *__restrict__ partial, int32_t C, uint64_t
         uint64_t s = 0;
         for (int c = 0; c < C; ++c) s += (uint64_t)(int64_t)partial[(size_t)c * cells + e];
         sketch[e] += s;
+    }
+}
+
+// ---------------------------------------------------------------- sort by bucket
+//
+// Partition strategy for large m: the tuples are processed in chunks of at most
+// kPartMaxChunk.  Pass 1 (k_part_hash) merges the identical tuples of a tile of
+// kPartTile tuples, hashes every distinct tuple once per repetition, and writes one
+// 32-bit record per (distinct tuple, repetition) -- the bucket's offset inside its
+// bucket range and the signed Delta sum -- sorted by bucket range through an LDS
+// counting sort, plus the start of each range's run.  Pass 2
+// (k_part_accum) gives each (repetition, bucket range) to one workgroup, which sums
+// its records from every tile in LDS and adds the sums into the sketch.  Each tuple is
+// hashed once; global memory sees only coalesced record traffic.  Deltas must be +1
+// (weights NULL) or +-1 (flag CS_UPDATE_UNIT_WEIGHTS).
+
+constexpr int kPartTile = 2048;
+constexpr int kPartPerThread = kPartTile / kBlock;  // 8
+constexpr int kDedupSlots = 2 * kPartTile;          // open-addressing table, load <= 1/2
+static_assert(kDedupSlots < 0xFFFF, "slot codes are 16-bit, 0xFFFF marks the reserved slot");
+constexpr uint64_t kEmptyKey = ~0ull;
+
+template <int NC>
+__device__ __forceinline__ uint64_t pack_key(const uint32_t (&x)[NC])
+{
+    if constexpr (NC == 1) return (uint64_t)x[0];
+    else return (uint64_t)x[0] | ((uint64_t)x[1] << 32);
+}
+
+template <int NC>
+__device__ __forceinline__ void unpack_key(uint64_t k, uint32_t (&x)[NC])
+{
+    x[0] = (uint32_t)k;
+    if constexpr (NC == 2) x[1] = (uint32_t)(k >> 32);
+}
+
+// Pass 1.  A tile's identical tuples are first merged in an LDS hash table (their
+// Deltas summed: the sketch is linear, Sec. 2.2), so a hot key costs one hash and one
+// record per tile.  Each distinct tuple is then hashed per repetition into a 32-bit
+// record: bucket offset inside its range (13 bits) and signed sum of Deltas times the
+// sign (19 bits; |sum| <= kPartTile).
+template <int NC>
+__global__ __launch_bounds__(kBlock) void k_part_hash(const uint32_t *__restrict__ keys,
+                                                      const int64_t *__restrict__ weights, uint64_t n,
+                                                      const uint64_t *__restrict__ coef, int32_t cpr,
+                                                      DevPlan plan, uint32_t m, int32_t d, int32_t log2R,
+                                                      int32_t ranges, bool vec2, uint32_t *rec_out,
+                                                      int32_t *tab)
+{
+    __shared__ uint64_t s_key[kDedupSlots + 1];  // slot kDedupSlots: the tuple whose packed key is kEmptyKey
+    __shared__ int32_t s_w[kDedupSlots + 1];
+    __shared__ uint16_t s_list[kPartTile];
+    __shared__ int32_t s_cnt[kMaxPartRanges + 1];
+    __shared__ int32_t s_nlist;
+    uint32_t *s_rec = reinterpret_cast<uint32_t *>(s_key);  // reused once the list is in registers
+
+    const uint64_t i0 = (uint64_t)blockIdx.x * kPartTile;
+    const int nv = (int)(n - i0 < (uint64_t)kPartTile ? n - i0 : (uint64_t)kPartTile);
+    for (int e = threadIdx.x; e <= kDedupSlots; e += kBlock) {
+        s_key[e] = kEmptyKey;
+        s_w[e] = 0;
+    }
+    if (threadIdx.x == 0) s_nlist = 0;
+    __syncthreads();
+    // ---- merge identical tuples
+#pragma unroll
+    for (int k = 0; k < kPartPerThread; ++k) {
+        const int e = threadIdx.x + k * kBlock;
+        if (e < nv) {
+            uint32_t xx[NC];
+            load_keys<NC>(keys, i0 + e, vec2, xx);
+            const int32_t w = weights ? (weights[i0 + e] < 0 ? -1 : 1) : 1;
+            const uint64_t key = pack_key<NC>(xx);
+            if (key == kEmptyKey) {
+                atomicAdd(&s_w[kDedupSlots], w);
+            } else {
+                uint32_t slot = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 52) & (kDedupSlots - 1);
+                for (;;) {
+                    const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long *>(&s_key[slot]),
+                                                             (unsigned long long)kEmptyKey, (unsigned long long)key);
+                    if (old == kEmptyKey || old == key) {
+                        atomicAdd(&s_w[slot], w);
+                        break;
+                    }
+                    slot = (slot + 1) & (kDedupSlots - 1);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e <= kDedupSlots; e += kBlock) {
+        const bool used = e == kDedupSlots ? true : s_key[e] != kEmptyKey;
+        if (used && s_w[e] != 0) s_list[atomicAdd(&s_nlist, 1)] = (uint16_t)(e < kDedupSlots ? e : 0xFFFF);
+    }
+    __syncthreads();
+    const int u = s_nlist;
+    uint32_t x[kPartPerThread][NC];
+    int32_t wv[kPartPerThread];
+#pragma unroll
+    for (int k = 0; k < kPartPerThread; ++k) {
+        const int l = threadIdx.x + k * kBlock;
+        wv[k] = 0;
+        if (l < u) {
+            const uint32_t code = s_list[l];
+            const int slot = code == 0xFFFFu ? kDedupSlots : (int)code;
+            uint32_t xx[NC];
+            unpack_key<NC>(s_key[slot], xx);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) x[k][c] = xx[c];
+            wv[k] = s_w[slot];
+        } else {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) x[k][c] = 0;
+        }
+    }
+    __syncthreads();
+    // ---- per repetition: hash, counting sort by bucket range, coalesced store
+    const uint32_t rmask = (1u << log2R) - 1;
+    for (int t = 0; t < d; ++t) {
+        for (int r = threadIdx.x; r <= ranges; r += kBlock) s_cnt[r] = 0;
+        __syncthreads();
+        const uint64_t *cf = coef + (size_t)t * cpr;
+        uint32_t rec[kPartPerThread];
+        uint16_t rng[kPartPerThread];
+        uint16_t pos[kPartPerThread];
+#pragma unroll
+        for (int k = 0; k < kPartPerThread; ++k) {
+            const int l = threadIdx.x + k * kBlock;
+            if (l < u) {
+                uint32_t j, neg;
+                hash_rep<NC>(cf, plan, x[k], j, neg);
+                j &= m - 1;
+                const int32_t val = neg ? -wv[k] : wv[k];
+                rec[k] = (j & rmask) | ((uint32_t)val << 13);
+                rng[k] = (uint16_t)(j >> log2R);
+                pos[k] = (uint16_t)atomicAdd(&s_cnt[rng[k]], 1);
+            }
+        }
+        __syncthreads();
+        // exclusive scan of the range counts (ranges <= kMaxPartRanges), one wave
+        if (threadIdx.x < 64) {
+            int carry = 0;
+            for (int base = 0; base < ranges; base += 64) {
+                const int r = base + (int)threadIdx.x;
+                const int v = r < ranges ? s_cnt[r] : 0;
+                int incl = v;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int y = __shfl_up(incl, o, 64);
+                    if ((int)threadIdx.x >= o) incl += y;
+                }
+                if (r < ranges) s_cnt[r] = carry + incl - v;
+                carry += __shfl(incl, 63, 64);
+            }
+            if (threadIdx.x == 0) s_cnt[ranges] = carry;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPartPerThread; ++k) {
+            const int l = threadIdx.x + k * kBlock;
+            if (l < u) s_rec[s_cnt[rng[k]] + pos[k]] = rec[k];
+        }
+        int32_t *tb = tab + ((size_t)blockIdx.x * d + t) * (ranges + 1);
+        for (int r = threadIdx.x; r <= ranges; r += kBlock) tb[r] = s_cnt[r];
+        __syncthreads();
+        uint32_t *o = rec_out + ((size_t)blockIdx.x * d + t) * kPartTile;
+        for (int e = threadIdx.x; e < u; e += kBlock) o[e] = s_rec[e];
+        __syncthreads();
+    }
+}
+
+// Block (range r, repetition t): sum the records of every tile, add into the sketch.
+__global__ __launch_bounds__(kBlock) void k_part_accum(const uint32_t *__restrict__ rec,
+                                                       const int32_t *__restrict__ tab, int32_t tiles,
+                                                       int32_t d, int32_t ranges, int32_t log2R, uint32_t m,
+                                                       uint64_t *sketch)
+{
+    extern __shared__ int32_t s_acc[];
+    const int r = blockIdx.x, t = blockIdx.y;
+    const int R = 1 << log2R;
+    for (int e = threadIdx.x; e < R; e += kBlock) s_acc[e] = 0;
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int tile = wave; tile < tiles; tile += kBlock / 64) {
+        const int32_t *tb = tab + ((size_t)tile * d + t) * (ranges + 1);
+        const int beg = tb[r], end = tb[r + 1];
+        const uint32_t *base = rec + ((size_t)tile * d + t) * kPartTile;
+        for (int e = beg + lane; e < end; e += 64) {
+            const uint32_t v = base[e];
+            atomicAdd(&s_acc[v & 0x1FFFu], (int32_t)v >> 13);
+        }
+    }
+    __syncthreads();
+    uint64_t *out = sketch + (size_t)t * m + ((size_t)r << log2R);
+    for (int e = threadIdx.x; e < R; e += kBlock) {
+        const int32_t v = s_acc[e];
+        if (v) out[e] += (uint64_t)(int64_t)v;
     }
 }
 
@@ -264,8 +461,8 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
     }
     if (strategy == CS_UPDATE_LDS_PRIVATE) {
         if (!a.scratch) return fail(CS_EINVAL, "LDS-segmented update needs the handle's scratch buffer");
-        // every Delta = +1 and fewer than 2^31 tuples: int32 partial counters cannot overflow
-        const bool narrow = a.weights == nullptr && a.n < (1ull << 31);
+        // every Delta = +-1 and fewer than 2^31 tuples: int32 partial counters cannot overflow
+        const bool narrow = (a.weights == nullptr || a.unit_weights) && a.n < (1ull << 31);
         const SegGeom sg = seg_geometry(a.m, a.d, narrow, a.scratch_bytes);
         const uint64_t chunk = (a.n + sg.chunks - 1) / sg.chunks;
         const uint64_t cells = (uint64_t)a.d * a.m;
@@ -297,6 +494,31 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
         CSK_HIP(hipGetLastError());
         return CS_OK;
     }
+    if (strategy == CS_UPDATE_PARTITION) {
+        if constexpr (NC > 2) return fail(CS_EINVAL, "the partition strategy handles at most 2 key columns");
+        if (a.weights && !a.unit_weights)
+            return fail(CS_EINVAL, "the partition strategy needs weights NULL or flagged as +-1");
+        if (!a.scratch) return fail(CS_EINVAL, "the partition strategy needs the handle's scratch buffer");
+        const PartGeom pg = part_geometry(a.m, a.d, a.scratch_bytes);
+        if (pg.chunk == 0) return fail(CS_EINVAL, "scratch buffer too small for the partition strategy");
+        uint32_t *rec = reinterpret_cast<uint32_t *>(a.scratch);
+        int32_t *tab = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(a.scratch) + pg.tab_offset);
+        const size_t lds = ((size_t)1 << pg.log2R) * sizeof(int32_t);
+        for (uint64_t base = 0; base < a.n; base += pg.chunk) {
+            const uint64_t cn = a.n - base < pg.chunk ? a.n - base : pg.chunk;
+            const int tiles = (int)((cn + kPartTile - 1) / kPartTile);
+            const uint32_t *kb = a.keys + base * a.plan.n_cols;
+            const bool v2 = NC == 2 && ((uintptr_t)kb % 8) == 0;
+            hipLaunchKernelGGL(k_part_hash<NC>, dim3(tiles), dim3(kBlock), 0, s, kb,
+                               a.weights ? a.weights + base : nullptr, cn, a.coef, a.plan.coef_per_rep, plan, a.m,
+                               a.d, pg.log2R, pg.ranges, v2, rec, tab);
+            CSK_HIP(hipGetLastError());
+            hipLaunchKernelGGL(k_part_accum, dim3(pg.ranges, a.d), dim3(kBlock), lds, s, rec, tab, tiles, a.d,
+                               pg.ranges, pg.log2R, a.m, a.sketch);
+            CSK_HIP(hipGetLastError());
+        }
+        return CS_OK;
+    }
     return fail(CS_EINVAL, "unknown update strategy");
 }
 
@@ -310,14 +532,42 @@ SegGeom seg_geometry(uint32_t m, int32_t d, bool narrow, size_t scratch_bytes)
     const uint64_t cells = (uint64_t)d * m;
     if (m <= g.R) g.R = (g.R / m) * m;  // whole repetitions per segment
     g.segments = (int32_t)((cells + g.R - 1) / g.R);
-    // enough blocks to fill the GPU twice, bounded by the scratch buffer
-    int32_t C = (512 + g.segments - 1) / g.segments;
+    // one 128 KB workgroup per CU: a whole number of rounds over the 256 CUs (two
+    // rounds when there are few segments), bounded by the scratch buffer
+    int32_t C = 512 / g.segments;
+    if (C < 1) C = 1;
     const uint64_t per_chunk = cells * (narrow ? 4 : 8);
     const int32_t cap = (int32_t)std::max<uint64_t>(1, scratch_bytes / per_chunk);
     if (C > cap) C = cap;
     if (C > 64) C = 64;
     if (C < 1) C = 1;
     g.chunks = C;
+    return g;
+}
+
+PartGeom part_geometry(uint32_t m, int32_t d, size_t scratch_bytes)
+{
+    PartGeom g{};
+    // about 256+ (repetition, range) workgroups in pass 2; ranges a power of two
+    int ranges = 1;
+    while (ranges * d < 256 && ranges < kMaxPartRanges) ranges <<= 1;
+    int log2m = 0;
+    while ((1u << log2m) < m) ++log2m;
+    int log2R = log2m;
+    while ((1 << (log2m - log2R)) < ranges && log2R > 0) --log2R;
+    if (log2R > 13) log2R = 13;       // pass-2 LDS: 2^13 int32 = 32 KB
+    g.log2R = log2R;
+    g.ranges = 1 << (log2m - log2R);
+    if (g.ranges > kMaxPartRanges) {  // m beyond 2^13 * kMaxPartRanges
+        g.chunk = 0;
+        return g;
+    }
+    // chunk: records (4 bytes per distinct tuple and repetition) + range table per tile
+    const uint64_t per_tile = (uint64_t)kPartTile * d * 4 + (uint64_t)d * (g.ranges + 1) * 4;
+    uint64_t tiles = scratch_bytes / per_tile;
+    if (tiles > (kPartMaxChunk / kPartTile)) tiles = kPartMaxChunk / kPartTile;
+    g.chunk = tiles * kPartTile;
+    g.tab_offset = (size_t)tiles * kPartTile * d * 4;
     return g;
 }
 
@@ -329,18 +579,22 @@ size_t seg_scratch_bytes(uint32_t m, int32_t d)
         SegGeom g = seg_geometry(m, d, narrow != 0, (size_t)-1);
         best = std::max<size_t>(best, (size_t)g.chunks * cells * (narrow ? 4 : 8));
     }
+    // the partition strategy's chunk of kPartMaxChunk tuples
+    const PartGeom pg = part_geometry(m, d, (size_t)-1);
+    const uint64_t tiles = kPartMaxChunk / kPartTile;
+    best = std::max<size_t>(best, (size_t)(tiles * kPartTile * d * 4 + tiles * d * (pg.ranges + 1) * 4));
     return best;
 }
 
-int auto_update_strategy(uint32_t m, int32_t d, uint64_t n, bool narrow, bool has_scratch)
+int auto_update_strategy(uint32_t m, int32_t d, uint64_t n, int n_cols, bool unit, bool has_scratch)
 {
-    // The segmented LDS path replaces n*d global atomics (about 2.4e10/s on the whole
-    // chip) by LDS atomics plus chunks*d*m partial stores; it pays once the tuples
-    // outnumber the partial cells it writes.
-    if (has_scratch) {
-        const SegGeom g = seg_geometry(m, d, narrow, (size_t)-1);
-        if (n >= (uint64_t)g.chunks * m * 2) return CS_UPDATE_LDS_PRIVATE;
-    }
+    // Global atomics run at about 2.4e10/s on the whole chip, the hash at about
+    // 3e12 Horner steps/s: beyond small inputs the update must aggregate in LDS.
+    if (!has_scratch) return CS_UPDATE_GLOBAL_ATOMIC;
+    const SegGeom g = seg_geometry(m, d, unit, (size_t)-1);
+    const bool big = n >= (uint64_t)g.chunks * m * 2;
+    (void)n_cols;
+    if (big) return CS_UPDATE_LDS_PRIVATE;
     return CS_UPDATE_GLOBAL_ATOMIC;
 }
 
@@ -348,7 +602,8 @@ cs_status launch_update(const UpdateArgs &a, int strategy, int grid_blocks, hipS
 {
     if (a.n == 0) return CS_OK;
     if (strategy == CS_UPDATE_AUTO)
-        strategy = auto_update_strategy(a.m, a.d, a.n, a.weights == nullptr, a.scratch != nullptr);
+        strategy = auto_update_strategy(a.m, a.d, a.n, a.plan.n_cols, a.weights == nullptr || a.unit_weights,
+                                        a.scratch != nullptr);
     switch (a.plan.n_cols) {
         case 1: return launch_nc<1>(a, strategy, grid_blocks, s);
         case 2: return launch_nc<2>(a, strategy, grid_blocks, s);

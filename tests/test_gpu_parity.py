@@ -24,12 +24,12 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _run_gpu(graph, rels, weights, m, d, seed, strategy=0, grid=0):
+def _run_gpu(graph, rels, weights, m, d, seed, strategy=0, grid=0, unit=False):
     sk = csk.Sketch(graph, m, d, seed)
     for k, keys in enumerate(rels):
         kd = to_device_keys(keys)
         wd = None if weights is None else torch.from_numpy(weights[k]).cuda()
-        sk.update(k, kd, wd, strategy=strategy, grid=grid)
+        sk.update(k, kd, wd, strategy=strategy, grid=grid, unit_weights=unit)
     torch.cuda.synchronize()
     return sk
 
@@ -53,6 +53,18 @@ def test_coefficients_and_components_match(graph):
         assert np.array_equal(b, co.bin_array())
         assert sk.components() == info.psi
         sk.close()
+
+
+def test_partition_strategy_refuses_general_weights():
+    sk = csk.Sketch(W.chain(3), 1 << 16, 3, 1)
+    keys = torch.zeros(100, 1, dtype=torch.int32, device="cuda")
+    w = torch.full((100,), 3, dtype=torch.int64, device="cuda")
+    with pytest.raises(csk.CsError) as e:
+        sk.update(0, keys, w, strategy=csk.UPDATE_PARTITION)
+    assert e.value.status == csk.CS_EINVAL
+    sk.update(0, keys, w)  # auto picks a strategy that handles any weights
+    torch.cuda.synchronize()
+    sk.close()
 
 
 def test_invalid_arguments_rejected():
@@ -87,6 +99,8 @@ SKETCH_CASES = [
     (W.fig3_query(), 7_777, 512, 7, "uniform", 200, "big"),
     (W.multiway_star(4), 5_000, 256, 4, "zipf", 100, None),
     (W.chain(3), 50_000, 1 << 18, 3, "zipf", 10 ** 7, None),
+    (W.chain(3), (1 << 21) + 12_345, 1 << 16, 2, "zipf", 10 ** 6, "pm1"),
+    (W.star(4), 70_000, 1 << 20, 2, "uniform", 10 ** 9, None),
 ]
 
 
@@ -99,15 +113,19 @@ def _weights(kind, graph, n):
 
 
 @pytest.mark.parametrize("case", range(len(SKETCH_CASES)))
-@pytest.mark.parametrize("strategy", [1, 2, 3])
+@pytest.mark.parametrize("strategy", [0, 1, 2, 3, 4])
 def test_sketch_bit_exact(case, strategy):
     graph, n, m, d, dist, D, wk = SKETCH_CASES[case]
+    if strategy == 4 and (wk == "big" or max(len(graph.columns(k)) for k in range(graph.n_rel)) > 2):
+        pytest.skip("partition strategy: +-1 weights and at most two key columns")
+    if strategy in (1, 3) and n > 1_000_000:
+        pytest.skip("global-atomic strategies: kept to the small cases")
     _say("sketch", case, graph.name, n, m, d, dist, wk, "strategy", strategy)
     rels = _rels(graph, n, dist, D, config=90 + case)
     weights = _weights(wk, graph, n)
     seed = 1000 + case
     info, co, ref = oracle_sketches(graph, rels, weights, m, d, seed)
-    sk = _run_gpu(graph, rels, weights, m, d, seed, strategy=strategy)
+    sk = _run_gpu(graph, rels, weights, m, d, seed, strategy=strategy, unit=(wk == "pm1"))
     for k in range(graph.n_rel):
         got = sk.read_sketch(k)
         assert np.array_equal(got, ref[k]), (k, np.argwhere(got != ref[k])[:5])
@@ -135,6 +153,23 @@ def test_sketch_batches_and_misaligned_keys():
     torch.cuda.synchronize()
     for k in range(graph.n_rel):
         assert np.array_equal(sk.read_sketch(k), ref[k])
+
+
+@pytest.mark.parametrize("strategy", [0, 1, 2, 3, 4])
+def test_adversarial_keys(strategy):
+    """All tuples on one key, the all-ones key pair, and keys at the uint32 limits."""
+    graph = W.chain(3)
+    n, m, d, seed = 50_000, 1 << 16, 3, 21
+    rng = np.random.default_rng(5)
+    rels = [np.full((n, 1), 7, dtype=np.uint32),
+            np.where(rng.random((n, 2)) < 0.5, 0xFFFFFFFF, 0).astype(np.uint32),
+            rng.choice(np.array([0, 1, 0xFFFFFFFE, 0xFFFFFFFF], dtype=np.uint32), size=(n, 1))]
+    weights = [W.turnstile_weights(n, 0.3, seed=k).numpy() for k in range(3)]
+    info, co, ref = oracle_sketches(graph, rels, weights, m, d, seed)
+    sk = _run_gpu(graph, rels, weights, m, d, seed, strategy=strategy, unit=True)
+    for k in range(3):
+        assert np.array_equal(sk.read_sketch(k), ref[k]), k
+    sk.close()
 
 
 def test_turnstile_insert_delete_and_reset():
