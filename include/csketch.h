@@ -179,6 +179,48 @@ cs_status cs_update_ex(cs_sketch *h, int32_t rel, const uint32_t *keys, const in
  * `reps` may be NULL.  Errors: CS_EINVAL, CS_EDEVICE, CS_ENOMEM. */
 cs_status cs_estimate(cs_sketch *h, void *stream, cs_estimate_t *out, const cs_reps_t *reps);
 
+/* ------------------------------------------------------------------ batched mode */
+
+/* One relation's tuple stream within a batch (same meaning as cs_update's arguments). */
+typedef struct cs_update_item {
+    cs_sketch *sketch;
+    int32_t rel;
+    int32_t flags;             /* CS_UPDATE_UNIT_WEIGHTS or 0 */
+    const uint32_t *keys;      /* device, [n][a_rel] */
+    const int64_t *weights;    /* device, [n], or NULL for +1 */
+    uint64_t n;
+} cs_update_item;
+
+typedef struct cs_batch cs_batch;   /* work-list tables, estimate workspace, captured graph */
+
+cs_status cs_batch_create(cs_batch **out);
+cs_status cs_batch_destroy(cs_batch *b);
+
+/* Alg. 2 for many queries' relations in ONE persistent kernel launch: the items are
+ * cut into tasks (tuple ranges; for relations with many tuples per counter, one LDS
+ * segment of the counters each), ordered largest first and pulled by one 1024-thread
+ * workgroup per CU.  Counters end bit-identical to cs_update of every item.  Items
+ * may belong to different handles (different graphs, m, d) on one device; two items
+ * must not target one relation of one handle twice unless ordered by the caller's
+ * stream.  Plans the work list on the host, uploads it, launches, returns without
+ * waiting.  Errors: CS_EINVAL (bad item), CS_ENOMEM, CS_EDEVICE. */
+cs_status cs_batch_update(cs_batch *b, const cs_update_item *items, int32_t n_items, void *stream);
+
+/* Plan the items once and capture the launch (counter reset + persistent kernel) in a
+ * HIP graph; cs_batch_replay launches it again on `stream` with the same buffers. */
+cs_status cs_batch_capture(cs_batch *b, const cs_update_item *items, int32_t n_items, void *stream);
+cs_status cs_batch_replay(cs_batch *b, void *stream);
+
+/* Estimates of n queries at once (Eq. 5 / Alg. 3 + median per query): one norm launch,
+ * one FFT and one product-reduce launch per sketch length, one finalize launch, plus
+ * the modular exactness pass for the repetitions that need it.  Results are identical
+ * to cs_estimate of each query.  outs[n]; reps NULL or n entries.  Blocking. */
+cs_status cs_batch_estimate(cs_batch *b, cs_sketch *const *sketches, int32_t n, void *stream,
+                            cs_estimate_t *outs, const cs_reps_t *reps);
+
+/* Task counts of the last planned batch update. */
+cs_status cs_batch_stats(const cs_batch *b, uint64_t *tasks_atomic, uint64_t *tasks_segment);
+
 /* ------------------------------------------------------------------ state */
 
 /* Zero every counter (stream-ordered). */

@@ -25,6 +25,8 @@ EXPORTED = [
     "cs_create", "cs_destroy", "cs_sketch_bytes", "cs_get_info", "cs_last_error",
     "cs_update", "cs_update_ex", "cs_estimate", "cs_reset", "cs_merge", "cs_read_sketch",
     "cs_sketch_device_ptr", "cs_read_coeffs", "cs_read_components",
+    "cs_batch_create", "cs_batch_destroy", "cs_batch_update", "cs_batch_capture", "cs_batch_replay",
+    "cs_batch_estimate", "cs_batch_stats",
 ]
 
 
@@ -48,6 +50,11 @@ class _Estimate(ctypes.Structure):
 class _Reps(ctypes.Structure):
     _fields_ = [("value", ctypes.c_void_p), ("lo", ctypes.c_void_p), ("hi", ctypes.c_void_p),
                 ("exact", ctypes.c_void_p), ("bound", ctypes.c_void_p)]
+
+
+class _Item(ctypes.Structure):
+    _fields_ = [("sketch", ctypes.c_void_p), ("rel", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("keys", ctypes.c_void_p), ("weights", ctypes.c_void_p), ("n", ctypes.c_uint64)]
 
 
 class _Info(ctypes.Structure):
@@ -84,6 +91,14 @@ def lib() -> ctypes.CDLL:
         L.cs_sketch_device_ptr.argtypes = [vp, i32, ctypes.POINTER(vp)]
         L.cs_read_coeffs.argtypes = [vp, vp, vp]
         L.cs_read_components.argtypes = [vp, vp]
+        L.cs_batch_create.argtypes = [ctypes.POINTER(vp)]
+        L.cs_batch_destroy.argtypes = [vp]
+        L.cs_batch_update.argtypes = [vp, ctypes.POINTER(_Item), i32, vp]
+        L.cs_batch_capture.argtypes = [vp, ctypes.POINTER(_Item), i32, vp]
+        L.cs_batch_replay.argtypes = [vp, vp]
+        L.cs_batch_estimate.argtypes = [vp, ctypes.POINTER(vp), i32, vp, ctypes.POINTER(_Estimate),
+                                        ctypes.POINTER(_Reps)]
+        L.cs_batch_stats.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64)]
         _lib = L
     return _lib
 
@@ -109,6 +124,27 @@ def _stream_ptr(stream):
     if isinstance(stream, int):
         return ctypes.c_void_p(stream)
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _reps_struct(d):
+    arrs = dict(value=np.zeros(d, np.float64), lo=np.zeros(d, np.int64), hi=np.zeros(d, np.int64),
+                exact=np.zeros(d, np.int32), bound=np.zeros(d, np.float64))
+    rp = _Reps(*(a.ctypes.data for a in (arrs["value"], arrs["lo"], arrs["hi"], arrs["exact"], arrs["bound"])))
+    return rp, arrs
+
+
+def _estimate_dict(e, arrs):
+    out = dict(value=e.value, value_i64=e.value_i64 if e.fits_i64 else None, exact=bool(e.exact),
+               d=e.d, n_modular=e.n_modular)
+    if arrs is not None:
+        ints = []
+        for t in range(len(arrs["value"])):
+            if arrs["exact"][t]:
+                ints.append((int(arrs["hi"][t]) << 64) | (int(arrs["lo"][t]) & ((1 << 64) - 1)))
+            else:
+                ints.append(None)
+        out.update(rep_values=arrs["value"].tolist(), rep_ints=ints, rep_bounds=arrs["bound"].tolist())
+    return out
 
 
 def sketch_bytes(graph, m: int, d: int) -> int:
@@ -168,28 +204,10 @@ class Sketch:
 
     def estimate(self, stream=None, reps: bool = False) -> dict:
         e = _Estimate()
-        rp = None
-        arrs = None
-        if reps:
-            arrs = dict(value=np.zeros(self.d, np.float64), lo=np.zeros(self.d, np.int64),
-                        hi=np.zeros(self.d, np.int64), exact=np.zeros(self.d, np.int32),
-                        bound=np.zeros(self.d, np.float64))
-            rp = _Reps(*(a.ctypes.data for a in (arrs["value"], arrs["lo"], arrs["hi"], arrs["exact"],
-                                                    arrs["bound"])))
+        rp, arrs = _reps_struct(self.d) if reps else (None, None)
         _check(lib().cs_estimate(self._h, _stream_ptr(stream), ctypes.byref(e),
                                  ctypes.byref(rp) if rp is not None else None))
-        out = dict(value=e.value, value_i64=e.value_i64 if e.fits_i64 else None, exact=bool(e.exact),
-                   d=e.d, n_modular=e.n_modular)
-        if arrs is not None:
-            ints = []
-            for t in range(self.d):
-                if arrs["exact"][t]:
-                    x = (int(arrs["hi"][t]) << 64) | (int(arrs["lo"][t]) & ((1 << 64) - 1))
-                    ints.append(x)
-                else:
-                    ints.append(None)
-            out.update(rep_values=arrs["value"].tolist(), rep_ints=ints, rep_bounds=arrs["bound"].tolist())
-        return out
+        return _estimate_dict(e, arrs)
 
     def reset(self, stream=None):
         _check(lib().cs_reset(self._h, _stream_ptr(stream)))
@@ -218,3 +236,66 @@ class Sketch:
         out = np.zeros(len(self.graph.attr_rel), dtype=np.int32)
         _check(lib().cs_read_components(self._h, out.ctypes.data))
         return out.tolist()
+
+
+class Batch:
+    """Batched updates (one persistent launch) and estimates over many Sketch handles."""
+
+    def __init__(self):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("csketch needs a HIP GPU; there is no CPU fallback")
+        b = ctypes.c_void_p()
+        _check(lib().cs_batch_create(ctypes.byref(b)))
+        self._b = b
+        self._keep = None
+
+    def close(self):
+        if getattr(self, "_b", None):
+            lib().cs_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _items(items):
+        """items: iterable of (sketch, rel, keys, weights_or_None, unit_weights)."""
+        items = list(items)
+        arr = (_Item * max(1, len(items)))()
+        for i, (sk, rel, keys, w, unit) in enumerate(items):
+            arr[i] = _Item(sk.handle.value, int(rel), UPDATE_UNIT_WEIGHTS if unit else 0,
+                           keys.data_ptr(), None if w is None else w.data_ptr(), int(keys.shape[0]))
+        return arr, len(items)
+
+    def update(self, items, stream=None):
+        arr, n = self._items(items)
+        _check(lib().cs_batch_update(self._b, arr, n, _stream_ptr(stream)))
+
+    def capture(self, items, stream=None):
+        arr, n = self._items(items)
+        _check(lib().cs_batch_capture(self._b, arr, n, _stream_ptr(stream)))
+
+    def replay(self, stream=None):
+        _check(lib().cs_batch_replay(self._b, _stream_ptr(stream)))
+
+    def stats(self):
+        a, b = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().cs_batch_stats(self._b, ctypes.byref(a), ctypes.byref(b)))
+        return {"tasks_atomic": a.value, "tasks_segment": b.value}
+
+    def estimate(self, sketches, stream=None, reps: bool = False):
+        sketches = list(sketches)
+        n = len(sketches)
+        hs = (ctypes.c_void_p * max(1, n))(*[s.handle.value for s in sketches])
+        outs = (_Estimate * max(1, n))()
+        rps, arrs = None, None
+        if reps:
+            pairs = [_reps_struct(s.d) for s in sketches]
+            rps = (_Reps * n)(*[p[0] for p in pairs])
+            arrs = [p[1] for p in pairs]
+        _check(lib().cs_batch_estimate(self._b, hs, n, _stream_ptr(stream), outs, rps))
+        return [_estimate_dict(outs[i], arrs[i] if arrs else None) for i in range(n)]

@@ -222,9 +222,6 @@ cs_status analyze_graph(const cs_graph *g, GraphPlan *out)
 
 using namespace csk;
 
-struct cs_sketch {
-    Handle h;
-};
 
 extern "C" {
 

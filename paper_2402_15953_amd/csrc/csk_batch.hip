@@ -1,0 +1,419 @@
+// Batched mode: thousands of uneven queries' updates in one persistent launch, and
+// their estimates in one batched pass (estimate_batch).
+//
+// The update work list is cut into tasks: a tuple range of one relation of one query,
+// and, for relations with many tuples per counter, one LDS segment of its [d][m]
+// counters.  A persistent grid (one 1024-thread workgroup per CU, 128 KB LDS) pulls
+// tasks from an atomic counter, largest first:
+//   segment task - LDS counters of the segment (int32 when every Delta is +-1), the
+//                  range's tuples hashed (bins first; signs only for in-segment buckets
+//                  when the segment is a bucket range), then the non-zero counters are
+//                  added into the sketch with one global atomic each;
+//   atomic task  - few tuples per counter: one global atomic per tuple and repetition.
+// Counters are int64 and all adds commute, so the result is bit-identical to the plain
+// per-query path whatever the task order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "csk_handle.h"
+#include "csk_hash.h"
+#include "csk_internal.h"
+
+namespace csk {
+
+namespace {
+
+constexpr int kBBlock = 1024;
+constexpr size_t kBLds = 128 * 1024;
+
+struct BItem {
+    const uint32_t *keys;
+    const int64_t *weights;
+    const uint64_t *coef;
+    uint64_t *sketch;
+    uint64_t n;
+    int32_t cpr;
+    int32_t n_cols;
+    uint32_t m;
+    int32_t log2m;
+    int32_t d;
+    uint32_t R;        // cells per segment (segment tasks)
+    int32_t narrow;    // int32 LDS counters (Deltas +-1)
+    int32_t vec2;      // two-column keys 8-byte aligned
+    DevPlan plan;
+};
+
+struct BTask {
+    int32_t item;
+    int32_t kind;      // 0: atomic, 1: LDS segment
+    uint32_t seg;
+    uint32_t pad;
+    uint64_t begin, end;
+};
+
+__global__ void k_zero_u32(unsigned int *p) { *p = 0u; }
+
+template <int NC>
+__device__ void run_atomic(const BItem &I, uint64_t begin, uint64_t end)
+{
+    for (uint64_t i = begin + threadIdx.x; i < end; i += kBBlock) {
+        uint32_t x[NC];
+        load_keys<NC>(I.keys, i, I.vec2 != 0, x);
+        const int64_t delta = I.weights ? I.weights[i] : 1;
+        const uint64_t *cf = I.coef;
+        for (int t = 0; t < I.d; ++t, cf += I.cpr) {
+            uint32_t j, neg;
+            hash_rep<NC>(cf, I.plan, x, j, neg);
+            j &= I.m - 1;
+            const uint64_t val = neg ? (uint64_t)0 - (uint64_t)delta : (uint64_t)delta;
+            atomicAdd(reinterpret_cast<unsigned long long *>(I.sketch) + (size_t)t * I.m + j,
+                      (unsigned long long)val);
+        }
+    }
+}
+
+template <int NC, typename CT>
+__device__ void run_segment(const BItem &I, uint32_t seg, uint64_t begin, uint64_t end, CT *s_c)
+{
+    const uint64_t cells = (uint64_t)I.d << I.log2m;
+    const uint64_t cell0 = (uint64_t)seg * I.R;
+    const uint64_t cell1 = cell0 + I.R < cells ? cell0 + I.R : cells;
+    const uint32_t span = (uint32_t)(cell1 - cell0);
+    const int t0 = (int)(cell0 >> I.log2m);
+    const int t1 = (int)((cell1 - 1) >> I.log2m);
+    const bool whole = I.R >= I.m;
+    for (uint32_t e = threadIdx.x; e < span; e += kBBlock) s_c[e] = 0;
+    __syncthreads();
+    for (uint64_t i = begin + threadIdx.x; i < end; i += kBBlock) {
+        uint32_t x[NC];
+        load_keys<NC>(I.keys, i, I.vec2 != 0, x);
+        const int64_t delta = I.weights ? I.weights[i] : 1;
+        for (int t = t0; t <= t1; ++t) {
+            const uint64_t *cf = I.coef + (size_t)t * I.cpr;
+            uint32_t j, neg;
+            if (whole) {
+                hash_rep<NC>(cf, I.plan, x, j, neg);
+                j &= I.m - 1;
+            } else {
+                j = 0;
+                const uint64_t *cb = cf;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    j += (uint32_t)hash_deg1(cb, x[c]);
+                    cb += 2 + 4 * I.plan.n_edges[c];
+                }
+                j &= I.m - 1;
+                const uint64_t flat = ((uint64_t)t << I.log2m) + j;
+                if (flat < cell0 || flat >= cell1) continue;
+                neg = 0;
+                const uint64_t *cs = cf;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    cs += 2;
+                    for (int e = 0; e < I.plan.n_edges[c]; ++e) {
+                        neg ^= (uint32_t)hash_deg3(cs, x[c]) & 1u;
+                        cs += 4;
+                    }
+                }
+            }
+            const uint32_t loc = (uint32_t)((((uint64_t)t << I.log2m) + j) - cell0);
+            if constexpr (sizeof(CT) == 4) {
+                const int32_t v32 = (int32_t)delta;
+                atomicAdd(&s_c[loc], neg ? -v32 : v32);
+            } else {
+                const uint64_t val = neg ? (uint64_t)0 - (uint64_t)delta : (uint64_t)delta;
+                atomicAdd(reinterpret_cast<unsigned long long *>(&s_c[loc]), (unsigned long long)val);
+            }
+        }
+    }
+    __syncthreads();
+    unsigned long long *out = reinterpret_cast<unsigned long long *>(I.sketch) + cell0;
+    for (uint32_t e = threadIdx.x; e < span; e += kBBlock) {
+        const int64_t v = (int64_t)s_c[e];
+        if (v) atomicAdd(out + e, (unsigned long long)v);
+    }
+    __syncthreads();
+}
+
+template <int NC>
+__device__ void run_task(const BItem &I, const BTask &T, unsigned char *lds)
+{
+    if (T.kind == 0) {
+        run_atomic<NC>(I, T.begin, T.end);
+    } else if (I.narrow) {
+        run_segment<NC, int32_t>(I, T.seg, T.begin, T.end, reinterpret_cast<int32_t *>(lds));
+    } else {
+        run_segment<NC, int64_t>(I, T.seg, T.begin, T.end, reinterpret_cast<int64_t *>(lds));
+    }
+}
+
+// Persistent workgroups pull tasks until the list is exhausted; every workgroup exits
+// once the shared counter passes n_tasks.
+__global__ __launch_bounds__(kBBlock) void k_batch_update(const BItem *__restrict__ items,
+                                                          const BTask *__restrict__ tasks, int32_t n_tasks,
+                                                          unsigned int *counter)
+{
+    extern __shared__ __align__(16) unsigned char s_lds[];
+    __shared__ int s_task;
+    for (;;) {
+        if (threadIdx.x == 0) s_task = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int task = s_task;
+        __syncthreads();
+        if (task >= n_tasks) break;
+        const BTask T = tasks[task];
+        const BItem I = items[T.item];
+        switch (I.n_cols) {
+            case 1: run_task<1>(I, T, s_lds); break;
+            case 2: run_task<2>(I, T, s_lds); break;
+            case 3: run_task<3>(I, T, s_lds); break;
+            case 4: run_task<4>(I, T, s_lds); break;
+            case 5: run_task<5>(I, T, s_lds); break;
+            case 6: run_task<6>(I, T, s_lds); break;
+            case 7: run_task<7>(I, T, s_lds); break;
+            default: run_task<8>(I, T, s_lds); break;
+        }
+    }
+}
+
+}  // namespace
+
+// Host side of a batch: work-list planning, device tables, optional graph.
+struct BatchState {
+    int device = -1;
+    void *tables = nullptr;    // items, tasks, counter
+    size_t table_bytes = 0;
+    int32_t n_tasks = 0;
+    size_t o_items = 0, o_tasks = 0, o_counter = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t capture_stream = nullptr;
+    EstimateWork est;
+    std::vector<Handle *> est_handles;
+    uint64_t tasks_atomic = 0, tasks_segment = 0;
+};
+
+namespace {
+
+cs_status plan_batch(BatchState &B, const cs_update_item *items, int32_t n_items, hipStream_t s)
+{
+    std::vector<BItem> bi;
+    std::vector<BTask> bt;
+    std::vector<double> cost;
+    B.tasks_atomic = B.tasks_segment = 0;
+    for (int32_t i = 0; i < n_items; ++i) {
+        const cs_update_item &it = items[i];
+        if (!it.sketch) return fail(CS_EINVAL, "batch item without handle");
+        const Handle &h = it.sketch->h;
+        if (it.rel < 0 || it.rel >= h.g.n_rel) return fail(CS_EINVAL, "batch item relation out of range");
+        if (it.n == 0) continue;
+        if (!it.keys) return fail(CS_EINVAL, "batch item without keys");
+        if (B.device < 0) B.device = h.device;
+        if (h.device != B.device) return fail(CS_EINVAL, "batch items on different devices");
+        const RelPlan &rp = h.g.rel[it.rel];
+        BItem I{};
+        I.keys = it.keys;
+        I.weights = it.weights;
+        I.coef = h.coef_dev + h.coef_off[it.rel];
+        I.sketch = reinterpret_cast<uint64_t *>(h.counters + (size_t)it.rel * h.d * h.m);
+        I.n = it.n;
+        I.cpr = rp.coef_per_rep;
+        I.n_cols = rp.n_cols;
+        I.m = h.m;
+        I.log2m = h.log2m;
+        I.d = (int32_t)h.d;
+        const bool unit = it.weights == nullptr || (it.flags & CS_UPDATE_UNIT_WEIGHTS);
+        I.narrow = unit && it.n < (1ull << 31);
+        I.vec2 = rp.n_cols == 2 && ((uintptr_t)it.keys % 8) == 0;
+        for (int c = 0; c < kMaxCols; ++c) I.plan.n_edges[c] = c < rp.n_cols ? rp.n_edges[c] : 0;
+        uint32_t R = I.narrow ? (1u << 15) : (1u << 14);
+        if (h.m <= R) R = (R / h.m) * h.m;
+        I.R = R;
+        const int idx = (int)bi.size();
+        bi.push_back(I);
+        int steps = 0;
+        for (int c = 0; c < rp.n_cols; ++c) steps += 1 + 3 * rp.n_edges[c];
+        const uint64_t cells = (uint64_t)h.d * h.m;
+        const uint64_t tuple_reps = it.n * h.d;
+        if (tuple_reps < 16 * cells || it.n < 4096) {
+            // few tuples per counter: global atomics
+            const uint64_t chunk = 1u << 16;
+            for (uint64_t b = 0; b < it.n; b += chunk) {
+                BTask T{idx, 0, 0, 0, b, std::min<uint64_t>(it.n, b + chunk)};
+                bt.push_back(T);
+                cost.push_back((double)(T.end - T.begin) * h.d * (steps + 40));
+                ++B.tasks_atomic;
+            }
+        } else {
+            const uint32_t segs = (uint32_t)((cells + R - 1) / R);
+            const uint64_t C = (it.n + (1u << 18) - 1) >> 18;
+            const uint64_t chunk = (it.n + C - 1) / C;
+            const int reps_per_seg = R >= h.m ? (int)(R / h.m) : 1;
+            const int ranges = R >= h.m ? 1 : (int)(h.m / R);
+            for (uint32_t sg = 0; sg < segs; ++sg)
+                for (uint64_t b = 0; b < it.n; b += chunk) {
+                    BTask T{idx, 1, sg, 0, b, std::min<uint64_t>(it.n, b + chunk)};
+                    bt.push_back(T);
+                    cost.push_back((double)(T.end - T.begin) * reps_per_seg * (steps + ranges) + R);
+                    ++B.tasks_segment;
+                }
+        }
+    }
+    // largest first
+    std::vector<int> order(bt.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<BTask> sorted(bt.size());
+    for (size_t i = 0; i < order.size(); ++i) sorted[i] = bt[order[i]];
+    const size_t o_items = 0;
+    const size_t o_tasks = (bi.size() * sizeof(BItem) + 255) & ~(size_t)255;
+    const size_t o_counter = o_tasks + ((sorted.size() * sizeof(BTask) + 255) & ~(size_t)255);
+    const size_t bytes = o_counter + 256;
+    if (B.table_bytes < bytes) {
+        if (B.tables) {
+            CSK_HIP(hipStreamSynchronize(s));
+            hipFree(B.tables);
+        }
+        B.tables = nullptr;
+        B.table_bytes = 0;
+        if (hipMalloc(&B.tables, bytes) != hipSuccess) return fail(CS_ENOMEM, "batch tables");
+        B.table_bytes = bytes;
+    }
+    std::vector<char> img(o_counter, 0);
+    if (!bi.empty()) std::memcpy(img.data() + o_items, bi.data(), bi.size() * sizeof(BItem));
+    if (!sorted.empty()) std::memcpy(img.data() + o_tasks, sorted.data(), sorted.size() * sizeof(BTask));
+    CSK_HIP(hipMemcpyAsync(B.tables, img.data(), img.size(), hipMemcpyHostToDevice, s));
+    CSK_HIP(hipStreamSynchronize(s));
+    B.n_tasks = (int32_t)sorted.size();
+    B.o_items = o_items;
+    B.o_tasks = o_tasks;
+    B.o_counter = o_counter;
+    return CS_OK;
+}
+
+cs_status launch_batch(BatchState &B, hipStream_t s)
+{
+    if (B.n_tasks == 0) return CS_OK;
+    char *t = static_cast<char *>(B.tables);
+    unsigned int *counter = reinterpret_cast<unsigned int *>(t + B.o_counter);
+    int n_cu = 256;
+    CSK_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, B.device));
+    const int grid = std::min(n_cu, B.n_tasks);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, counter);
+    CSK_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_batch_update, dim3(grid), dim3(kBBlock), kBLds, s,
+                       reinterpret_cast<const BItem *>(t + B.o_items), reinterpret_cast<const BTask *>(t + B.o_tasks),
+                       B.n_tasks, counter);
+    CSK_HIP(hipGetLastError());
+    return CS_OK;
+}
+
+void drop_graph(BatchState &B)
+{
+    if (B.exec) hipGraphExecDestroy(B.exec);
+    if (B.graph) hipGraphDestroy(B.graph);
+    B.exec = nullptr;
+    B.graph = nullptr;
+}
+
+}  // namespace
+
+}  // namespace csk
+
+using namespace csk;
+
+struct cs_batch {
+    BatchState b;
+};
+
+extern "C" {
+
+cs_status cs_batch_create(cs_batch **out)
+{
+    if (!out) return fail(CS_EINVAL, "null output");
+    cs_batch *b = new (std::nothrow) cs_batch();
+    if (!b) return fail(CS_ENOMEM, "host allocation failed");
+    CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch_update),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBLds));
+    *out = b;
+    return CS_OK;
+}
+
+cs_status cs_batch_destroy(cs_batch *b)
+{
+    if (!b) return CS_OK;
+    hipDeviceSynchronize();
+    drop_graph(b->b);
+    if (b->b.capture_stream) hipStreamDestroy(b->b.capture_stream);
+    if (b->b.tables) hipFree(b->b.tables);
+    if (b->b.est.buf) hipFree(b->b.est.buf);
+    delete b;
+    return CS_OK;
+}
+
+cs_status cs_batch_update(cs_batch *b, const cs_update_item *items, int32_t n_items, void *stream)
+{
+    if (!b || (n_items > 0 && !items)) return fail(CS_EINVAL, "null argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    cs_status st = plan_batch(b->b, items, n_items, s);
+    if (st != CS_OK) return st;
+    return launch_batch(b->b, s);
+}
+
+cs_status cs_batch_capture(cs_batch *b, const cs_update_item *items, int32_t n_items, void *stream)
+{
+    if (!b || (n_items > 0 && !items)) return fail(CS_EINVAL, "null argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    drop_graph(b->b);
+    cs_status st = plan_batch(b->b, items, n_items, s);
+    if (st != CS_OK) return st;
+    // capture on a private stream (the null stream cannot be captured); the graph is
+    // launched later on the caller's stream
+    if (!b->b.capture_stream) CSK_HIP(hipStreamCreateWithFlags(&b->b.capture_stream, hipStreamNonBlocking));
+    hipStream_t cs = b->b.capture_stream;
+    CSK_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    st = launch_batch(b->b, cs);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &g);
+    if (st != CS_OK) {
+        if (g) hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(CS_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    b->b.graph = g;
+    CSK_HIP(hipGraphInstantiate(&b->b.exec, g, nullptr, nullptr, 0));
+    return CS_OK;
+}
+
+cs_status cs_batch_replay(cs_batch *b, void *stream)
+{
+    if (!b || !b->b.exec) return fail(CS_EINVAL, "no captured batch");
+    CSK_HIP(hipGraphLaunch(b->b.exec, static_cast<hipStream_t>(stream)));
+    return CS_OK;
+}
+
+cs_status cs_batch_estimate(cs_batch *b, cs_sketch *const *sketches, int32_t n, void *stream, cs_estimate_t *outs,
+                            const cs_reps_t *reps)
+{
+    if (!b || (n > 0 && (!sketches || !outs))) return fail(CS_EINVAL, "null argument");
+    std::vector<Handle *> hs(n);
+    for (int i = 0; i < n; ++i) {
+        if (!sketches[i]) return fail(CS_EINVAL, "null handle in batch");
+        hs[i] = &sketches[i]->h;
+    }
+    return estimate_batch(hs.data(), n, static_cast<hipStream_t>(stream), outs, reps, b->b.est);
+}
+
+cs_status cs_batch_stats(const cs_batch *b, uint64_t *tasks_atomic, uint64_t *tasks_segment)
+{
+    if (!b) return fail(CS_EINVAL, "null batch");
+    if (tasks_atomic) *tasks_atomic = b->b.tasks_atomic;
+    if (tasks_segment) *tasks_segment = b->b.tasks_segment;
+    return CS_OK;
+}
+
+}  // extern "C"

@@ -195,42 +195,72 @@ __device__ bool digits_to_i128(const uint32_t *dig, int K, const CrtTables &T, _
     return true;
 }
 
+// ---------------------------------------------------------------- descriptors
+
+// One sketch vector c_k[t] (norm partials at off * 2 doubles).
+struct SkDesc {
+    const int64_t *p;
+    int32_t log2m;
+    int32_t nb;
+    int64_t off;
+};
+
+// One repetition t of query q.
+struct RepDesc {
+    const int64_t *c0;     // DOT plan: relation 0 and 1 at repetition t
+    const int64_t *c1;
+    int32_t q, t, log2m, r, d;
+    uint32_t conj;         // SPECTRAL: relations taken conjugated
+    int32_t vec_base;      // SPECTRAL: first packed vector of query q in its group's buffer
+    int32_t nb;            // blocks of this repetition's reductions
+    int32_t sk_base;       // first sketch (k * d + t order) of query q in the SkDesc table
+    int32_t mod_vec_base;  // modular pass: first vector of query q in its group's buffer
+    int64_t spec_off;      // fp64 spectral partials, (2 + r) doubles per block
+    int64_t dot_off;       // DOT partials, 2 u64 per block
+    int64_t mod_off;       // modular partials (per prime plane)
+};
+
+struct QDesc {
+    int32_t plan, r, d, log2m, rep_base, nb;
+};
+
 // ---------------------------------------------------------------- kernels
 
-// Sum of squares and sum of absolute values of each sketch vector (fp64), per block.
-__global__ __launch_bounds__(kThreads) void k_norms(const int64_t *__restrict__ sk, int log2m, int nb,
-                                                    double *partials)
+// Sum of squares and of absolute values of each sketch vector (fp64), per block.
+__global__ __launch_bounds__(kThreads) void k_norms(const SkDesc *__restrict__ sks, double *partials)
 {
     __shared__ double sh[kThreads / 64];
-    const int64_t m = (int64_t)1 << log2m;
-    const int64_t *c = sk + (size_t)blockIdx.y * m;
+    const SkDesc S = sks[blockIdx.x];
+    const int blk = blockIdx.y;
+    if (blk >= S.nb) return;
+    const int64_t m = (int64_t)1 << S.log2m;
     double s2 = 0.0, s1 = 0.0;
-    for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < m; j += (int64_t)nb * kThreads) {
-        const double v = (double)c[j];
+    for (int64_t j = (int64_t)blk * kThreads + threadIdx.x; j < m; j += (int64_t)S.nb * kThreads) {
+        const double v = (double)S.p[j];
         s2 += v * v;
         s1 += fabs(v);
     }
     const double a = block_sum(s2, sh);
     const double b = block_sum(s1, sh);
     if (threadIdx.x == 0) {
-        double *o = partials + ((size_t)blockIdx.y * nb + blockIdx.x) * 2;
+        double *o = partials + (S.off + blk) * 2;
         o[0] = a;
         o[1] = b;
     }
 }
 
 // 128-bit inner product of c_0[t] and c_1[t], per block.
-__global__ __launch_bounds__(kThreads) void k_dot(const int64_t *__restrict__ c0, const int64_t *__restrict__ c1,
-                                                  int log2m, int nb, unsigned long long *partials)
+__global__ __launch_bounds__(kThreads) void k_dot(const RepDesc *__restrict__ reps, const int32_t *__restrict__ idx,
+                                                  unsigned long long *partials)
 {
     __shared__ unsigned __int128 sh[kThreads];
-    const int64_t m = (int64_t)1 << log2m;
-    const int t = blockIdx.y;
-    const int64_t *a = c0 + (size_t)t * m;
-    const int64_t *b = c1 + (size_t)t * m;
+    const RepDesc D = reps[idx[blockIdx.x]];
+    const int blk = blockIdx.y;
+    if (blk >= D.nb) return;
+    const int64_t m = (int64_t)1 << D.log2m;
     __int128 acc = 0;
-    for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < m; j += (int64_t)nb * kThreads)
-        acc += (__int128)a[j] * (__int128)b[j];
+    for (int64_t j = (int64_t)blk * kThreads + threadIdx.x; j < m; j += (int64_t)D.nb * kThreads)
+        acc += (__int128)D.c0[j] * (__int128)D.c1[j];
     sh[threadIdx.x] = (unsigned __int128)acc;
     __syncthreads();
     for (int s = kThreads / 2; s > 0; s >>= 1) {
@@ -238,45 +268,49 @@ __global__ __launch_bounds__(kThreads) void k_dot(const int64_t *__restrict__ c0
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        unsigned long long *o = partials + ((size_t)t * nb + blockIdx.x) * 2;
+        unsigned long long *o = partials + (D.dot_off + blk) * 2;
         o[0] = (unsigned long long)(uint64_t)sh[0];
         o[1] = (unsigned long long)(uint64_t)(sh[0] >> 64);
     }
 }
 
-// fp64 spectral product-reduce.  vec_of / part_of [d][r]: packed vector and half
-// (0: real input, 1: imaginary input) holding relation k's repetition t.
-// partials [d][nb][2 + r]: sum Re(term), sum |Re|+|Im| of terms, max |C_k| per relation.
-__global__ __launch_bounds__(kThreads) void k_spec_f64(const double2 *__restrict__ Z, int log2m, int r,
-                                                       const int32_t *__restrict__ vec_of,
-                                                       const int32_t *__restrict__ part_of, uint32_t conj_mask,
-                                                       int nb, double *partials)
+// fp64 spectral product-reduce for repetitions idx[blockIdx.y] of one m-group.
+// Sketch s = k * d + t of a query is half (s & 1) of packed vector vec_base + s / 2.
+// partials: sum Re(term), sum |Re|+|Im| of terms, max |C_k| per relation.
+__global__ __launch_bounds__(kThreads) void k_spec_f64(const double2 *__restrict__ Z,
+                                                       const RepDesc *__restrict__ reps,
+                                                       const int32_t *__restrict__ idx, double *partials)
 {
     __shared__ double sh[kThreads / 64];
+    const RepDesc D = reps[idx[blockIdx.x]];
+    const int blk = blockIdx.y;
+    if (blk >= D.nb) return;
+    const int log2m = D.log2m;
     const uint32_t m = 1u << log2m;
-    const int t = blockIdx.y;
+    const int r = D.r;
     double acc = 0.0, acc_abs = 0.0;
     double mx[kMaxRel];
 #pragma unroll
     for (int k = 0; k < kMaxRel; ++k) mx[k] = 0.0;
-    for (uint32_t pos = blockIdx.x * kThreads + threadIdx.x; pos < m; pos += (uint32_t)nb * kThreads) {
+    for (uint32_t pos = blk * kThreads + threadIdx.x; pos < m; pos += (uint32_t)D.nb * kThreads) {
         const uint32_t f = pos_freq(pos, log2m);
         const uint32_t npos = freq_pos((m - f) & (m - 1), log2m);
         double pr = 1.0, pi = 0.0;
 #pragma unroll
         for (int k = 0; k < kMaxRel; ++k) {
             if (k < r) {
-                const double2 *zv = Z + (size_t)vec_of[t * r + k] * m;
+                const int sidx = k * D.d + D.t;
+                const double2 *zv = Z + (size_t)(D.vec_base + (sidx >> 1)) * m;
                 const double2 a = zv[pos], b = zv[npos];
                 double cr, ci;
-                if (part_of[t * r + k] == 0) {
+                if ((sidx & 1) == 0) {
                     cr = 0.5 * (a.x + b.x);
                     ci = 0.5 * (a.y - b.y);
                 } else {
                     cr = 0.5 * (a.y + b.y);
                     ci = 0.5 * (b.x - a.x);
                 }
-                if ((conj_mask >> k) & 1u) ci = -ci;
+                if ((D.conj >> k) & 1u) ci = -ci;
                 mx[k] = fmax(mx[k], fabs(cr) + fabs(ci));
                 const double nr = pr * cr - pi * ci;
                 const double ni = pr * ci + pi * cr;
@@ -287,7 +321,7 @@ __global__ __launch_bounds__(kThreads) void k_spec_f64(const double2 *__restrict
         acc += pr;
         acc_abs += fabs(pr) + fabs(pi);
     }
-    double *o = partials + ((size_t)t * nb + blockIdx.x) * (2 + r);
+    double *o = partials + (D.spec_off + (int64_t)blk * (2 + r));
     const double s0 = block_sum(acc, sh);
     if (threadIdx.x == 0) o[0] = s0;
     const double s1 = block_sum(acc_abs, sh);
@@ -298,26 +332,32 @@ __global__ __launch_bounds__(kThreads) void k_spec_f64(const double2 *__restrict
     }
 }
 
-// Modular spectral product-reduce over buffers [K][r*d][m] (vector (i, k, t) at
-// i * r * d + k * d + t).  partials [K][d][nb] (uint32 residues, Montgomery form).
-__global__ __launch_bounds__(kThreads) void k_spec_mod(const uint32_t *__restrict__ N, int log2m, int r, int d,
-                                                       uint32_t conj_mask, const PrimeDev *__restrict__ primes,
-                                                       int nb, uint32_t *partials)
+// Modular spectral product-reduce.  Buffer [K][vpp][m]; query q's sketch k * d + t is
+// vector mod_vec_base + k * d + t.  partials [K][plane] at mod_off.
+__global__ __launch_bounds__(kThreads) void k_spec_mod(const uint32_t *__restrict__ N, int vpp,
+                                                       const RepDesc *__restrict__ reps,
+                                                       const int32_t *__restrict__ idx,
+                                                       const PrimeDev *__restrict__ primes, int64_t plane,
+                                                       uint32_t *partials)
 {
     __shared__ uint32_t sh[kThreads];
-    const uint32_t m = 1u << log2m;
-    const int t = blockIdx.y, pi = blockIdx.z;
+    const RepDesc D = reps[idx[blockIdx.x]];
+    const int blk = blockIdx.y;
+    if (blk >= D.nb) return;
+    const int pi = blockIdx.z;
     const PrimeDev P = primes[pi];
     const RingM R{P.p, P.pinv_neg};
-    const uint32_t *base = N + (size_t)pi * r * d * m;
+    const int log2m = D.log2m;
+    const uint32_t m = 1u << log2m;
+    const uint32_t *base = N + (size_t)pi * vpp * m;
     uint32_t acc = 0;
-    for (uint32_t pos = blockIdx.x * kThreads + threadIdx.x; pos < m; pos += (uint32_t)nb * kThreads) {
+    for (uint32_t pos = blk * kThreads + threadIdx.x; pos < m; pos += (uint32_t)D.nb * kThreads) {
         const uint32_t f = pos_freq(pos, log2m);
         const uint32_t npos = freq_pos((m - f) & (m - 1), log2m);
         uint32_t prod = P.one;
-        for (int k = 0; k < r; ++k) {
-            const uint32_t *v = base + ((size_t)k * d + t) * m;
-            prod = R.mul(prod, ((conj_mask >> k) & 1u) ? v[npos] : v[pos]);
+        for (int k = 0; k < D.r; ++k) {
+            const uint32_t *v = base + (size_t)(D.mod_vec_base + k * D.d + D.t) * m;
+            prod = R.mul(prod, ((D.conj >> k) & 1u) ? v[npos] : v[pos]);
         }
         acc = R.add(acc, prod);
     }
@@ -327,7 +367,7 @@ __global__ __launch_bounds__(kThreads) void k_spec_mod(const uint32_t *__restric
         if ((int)threadIdx.x < s) sh[threadIdx.x] = R.add(sh[threadIdx.x], sh[threadIdx.x + s]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) partials[((size_t)pi * d + t) * nb + blockIdx.x] = sh[0];
+    if (threadIdx.x == 0) partials[(size_t)pi * plane + D.mod_off + blk] = sh[0];
 }
 
 // ---- general plan register operations, buffers [K][d][m] per register
@@ -373,14 +413,17 @@ __global__ void k_mod_mul(uint32_t *dst, const uint32_t *__restrict__ src, int l
     }
 }
 
+// Sum of register vector (prime i, repetition t) -> partials[i * plane + mod_off(rep) + b].
 __global__ __launch_bounds__(kThreads) void k_mod_sum(const uint32_t *__restrict__ reg, int log2m, int d,
                                                       const PrimeDev *__restrict__ primes, int nb,
-                                                      uint32_t *partials)
+                                                      const RepDesc *__restrict__ reps, int rep_base,
+                                                      int64_t plane, uint32_t *partials)
 {
     __shared__ uint32_t sh[kThreads];
     const uint32_t m = 1u << log2m;
     const int v = blockIdx.y;  // i * d + t
-    const PrimeDev P = primes[v / d];
+    const int pi = v / d, t = v % d;
+    const PrimeDev P = primes[pi];
     const RingM R{P.p, P.pinv_neg};
     const uint32_t *a = reg + (size_t)v * m;
     uint32_t acc = 0;
@@ -391,48 +434,48 @@ __global__ __launch_bounds__(kThreads) void k_mod_sum(const uint32_t *__restrict
         if ((int)threadIdx.x < s) sh[threadIdx.x] = R.add(sh[threadIdx.x], sh[threadIdx.x + s]);
         __syncthreads();
     }
-    // partials [K][d][nb]
-    if (threadIdx.x == 0) partials[(size_t)v * nb + blockIdx.x] = sh[0];
+    if (threadIdx.x == 0) partials[(size_t)pi * plane + reps[rep_base + t].mod_off + blockIdx.x] = sh[0];
 }
 
-// ---- finalize
+// ---- finalize: one workgroup per query, one thread per repetition
 
 struct FinalizeArgs {
-    int32_t plan;
     int32_t stage;        // 1: after the fp64 / dot / norms pass; 2: after the modular pass
-    int32_t r, d, log2m;
-    int32_t nb_norm, nb_spec, nb_mod, nb_dot;
-    int32_t n_primes;     // primes used by the modular pass (stage 2)
-    int32_t mod_scale_m;  // modular partial sums carry the 1/m factor of the spectral sum
-    const double *norms;  // [r*d][nb_norm][2]
-    const double *spec;   // [d][nb_spec][2+r]
-    const unsigned long long *dot;  // [d][nb_dot][2]
-    const uint32_t *modp; // [K][d][nb_mod]
-    const int32_t *partner;  // [r*d] sketch index packed with sketch s, -1 none
+    const QDesc *qs;
+    const RepDesc *reps;
+    const SkDesc *sks;
+    const double *norms;
+    const double *spec;
+    const unsigned long long *dot;
+    const uint32_t *modp;
+    int64_t mod_plane;
     const PrimeDev *primes;
     CrtTables crt;
-    RepDev *reps;
-    OutDev *out;
-    double n_eff_spec;    // sequential additions in the spectral sum (rounding bound)
-    double n_eff_norm;
+    RepDev *rs;
+    OutDev *outs;
 };
 
 __global__ void k_finalize(FinalizeArgs a)
 {
+    const QDesc Q = a.qs[blockIdx.x];
     const int t = threadIdx.x;
     const double u = 0x1p-53;
-    const double m = (double)(1u << a.log2m);
-    if (t < a.d) {
-        RepDev &rp = a.reps[t];
+    const double m = (double)(1u << Q.log2m);
+    const int plan = Q.plan;
+    if (t < Q.d) {
+        const RepDesc D = a.reps[Q.rep_base + t];
+        RepDev &rp = a.rs[Q.rep_base + t];
+        const double per_thread = ceil(m / ((double)D.nb * kThreads));
+        const double n_eff = per_thread + 8.0 + D.nb;
         if (a.stage == 1) {
             rp.kprimes = 0;
             rp.status = 0;
             rp.window = 0;
             rp.bound = 0.0;
-            if (a.plan == CS_PLAN_DOT) {
+            if (plan == CS_PLAN_DOT) {
                 unsigned __int128 s = 0;
-                for (int b = 0; b < a.nb_dot; ++b) {
-                    const unsigned long long *p = a.dot + ((size_t)t * a.nb_dot + b) * 2;
+                for (int b = 0; b < D.nb; ++b) {
+                    const unsigned long long *p = a.dot + (D.dot_off + b) * 2;
                     s += ((unsigned __int128)p[1] << 64) | p[0];
                 }
                 const __int128 x = (__int128)s;
@@ -444,61 +487,63 @@ __global__ void k_finalize(FinalizeArgs a)
             } else {
                 // norms of each relation's sketch at this repetition (upper bounds)
                 double s2[kMaxRel], s1[kMaxRel];
-                const double up = 1.0 + (a.n_eff_norm + 4.0) * u * 1.01;
-                for (int k = 0; k < a.r; ++k) {
-                    const int s = k * a.d + t;
-                    double q = 0.0, l = 0.0;
-                    for (int b = 0; b < a.nb_norm; ++b) {
-                        q += a.norms[((size_t)s * a.nb_norm + b) * 2];
-                        l += a.norms[((size_t)s * a.nb_norm + b) * 2 + 1];
+                const double up = 1.0 + (n_eff + 4.0) * u * 1.01;
+                for (int k = 0; k < Q.r; ++k) {
+                    const SkDesc S = a.sks[D.sk_base + k * Q.d + t];
+                    double qq = 0.0, l = 0.0;
+                    for (int b = 0; b < S.nb; ++b) {
+                        qq += a.norms[(S.off + b) * 2];
+                        l += a.norms[(S.off + b) * 2 + 1];
                     }
-                    s2[k] = q * up;
+                    s2[k] = qq * up;
                     s1[k] = l * up;
                 }
-                if (a.plan == CS_PLAN_SPECTRAL) {
+                if (plan == CS_PLAN_SPECTRAL) {
                     double sum = 0.0, sabs = 0.0, mx[kMaxRel];
-                    for (int k = 0; k < a.r; ++k) mx[k] = 0.0;
-                    for (int b = 0; b < a.nb_spec; ++b) {
-                        const double *p = a.spec + ((size_t)t * a.nb_spec + b) * (2 + a.r);
+                    for (int k = 0; k < Q.r; ++k) mx[k] = 0.0;
+                    for (int b = 0; b < D.nb; ++b) {
+                        const double *p = a.spec + D.spec_off + (int64_t)b * (2 + Q.r);
                         sum += p[0];
                         sabs += p[1];
-                        for (int k = 0; k < a.r; ++k) mx[k] = fmax(mx[k], p[2 + k]);
+                        for (int k = 0; k < Q.r; ++k) mx[k] = fmax(mx[k], p[2 + k]);
                     }
                     const double xf = sum / m;
                     // fp64 FFT error (radix-2 Cooley-Tukey, twiddles within 2u):
                     // ||fl(FFT z) - FFT z||_2 <= kappa sqrt(m) ||z||_2.
                     const double g4 = 4.0 * u / (1.0 - 4.0 * u);
                     const double eta = 2.0 * u + g4 * (1.41421356237309515 + 2.0 * u);
-                    const double kappa = 2.0 * (a.log2m + 3) * eta;
+                    const double kappa = 2.0 * (Q.log2m + 3) * eta;
                     const double sm = sqrt(m) * (1.0 + 4.0 * u);
                     double e[kMaxRel], N[kMaxRel], M[kMaxRel];
-                    for (int k = 0; k < a.r; ++k) {
-                        const int s = k * a.d + t;
-                        const int ps = a.partner[s];
+                    const int n_sk = Q.r * Q.d;
+                    for (int k = 0; k < Q.r; ++k) {
+                        // packed partner: sketch index s ^ 1 within the query
+                        const int sidx = k * Q.d + t;
                         double z2 = s2[k];
-                        if (ps >= 0) {
-                            // partner's squared norm, recomputed from the norm partials
-                            double q = 0.0;
-                            for (int b = 0; b < a.nb_norm; ++b) q += a.norms[((size_t)ps * a.nb_norm + b) * 2];
-                            z2 += q * up;
+                        const int ps = sidx ^ 1;
+                        if (ps < n_sk) {
+                            const SkDesc S = a.sks[D.sk_base + ps];
+                            double qq = 0.0;
+                            for (int b = 0; b < S.nb; ++b) qq += a.norms[(S.off + b) * 2];
+                            z2 += qq * up;
                         }
                         e[k] = kappa * sm * sqrt(z2) * (1.0 + 4.0 * u);
                         N[k] = sm * sqrt(s2[k]) * (1.0 + 4.0 * u) + e[k];
                         M[k] = mx[k] * (1.0 + 4.0 * u) + e[k];
                     }
                     double dT = 0.0;
-                    for (int k = 0; k < a.r; ++k) {
+                    for (int k = 0; k < Q.r; ++k) {
                         double best = INFINITY;
-                        for (int j = 0; j < a.r; ++j) {
+                        for (int j = 0; j < Q.r; ++j) {
                             if (j == k) continue;
                             double v = N[j];
-                            for (int i = 0; i < a.r; ++i)
+                            for (int i = 0; i < Q.r; ++i)
                                 if (i != j && i != k) v *= M[i];
                             best = fmin(best, v);
                         }
                         dT += e[k] * best;
                     }
-                    const double rho = ((a.r - 1) * 3.0 + a.n_eff_spec + 4.0) * u * 1.01;
+                    const double rho = ((Q.r - 1) * 3.0 + n_eff + 4.0) * u * 1.01;
                     const double bound = 2.0 * (dT + rho * sabs) / m * (1.0 + 1e-10);
                     rp.xf = xf;
                     rp.bound = bound;
@@ -513,7 +558,7 @@ __global__ void k_finalize(FinalizeArgs a)
                         rp.value = xf;
                         rp.lo = rp.hi = 0;
                         if (isfinite(bound) && isfinite(xf)) {
-                            // window around xf when xf fits in int128, else full centered range
+                            // window around xf when xf fits in int128, else full centred range
                             rp.window = fabs(xf) < 0x1p120 ? 1 : 0;
                             const double need = rp.window ? log2(2.0 * bound + 4.0) + 1.0
                                                           : log2(2.0 * (fabs(xf) + bound) + 4.0) + 1.0;
@@ -529,7 +574,7 @@ __global__ void k_finalize(FinalizeArgs a)
                 } else {  // GENERAL: primes to cover 2 * prod_k ||c_k||_1 + 2
                     double lb = 0.0;
                     bool zero = false;
-                    for (int k = 0; k < a.r; ++k) {
+                    for (int k = 0; k < Q.r; ++k) {
                         if (s1[k] == 0.0) zero = true;
                         lb += log2(s1[k]);
                     }
@@ -539,7 +584,6 @@ __global__ void k_finalize(FinalizeArgs a)
                     if (zero) {
                         rp.exact = 1;
                         rp.lo = rp.hi = 0;
-                        rp.value = 0.0;
                     } else {
                         const double need = lb + 3.0;
                         double have = 0.0;
@@ -557,11 +601,11 @@ __global__ void k_finalize(FinalizeArgs a)
                 const PrimeDev &P = a.primes[i];
                 const RingM R{P.p, P.pinv_neg};
                 uint32_t s = 0;
-                for (int b = 0; b < a.nb_mod; ++b) s = R.add(s, a.modp[((size_t)i * a.d + t) * a.nb_mod + b]);
-                if (a.mod_scale_m) s = R.mul(s, P.minv[a.log2m]);
+                for (int b = 0; b < D.nb; ++b) s = R.add(s, a.modp[(size_t)i * a.mod_plane + D.mod_off + b]);
+                if (plan == CS_PLAN_SPECTRAL) s = R.mul(s, P.minv[Q.log2m]);
                 res[i] = R.mul(s, 1u);  // out of Montgomery form
             }
-            if (a.plan == CS_PLAN_SPECTRAL && rp.window) {
+            if (plan == CS_PLAN_SPECTRAL && rp.window) {
                 const __int128 x0 = double_to_i128(rint(rp.xf));
                 for (int i = 0; i < K; ++i) {
                     const uint32_t p = a.crt.p[i];
@@ -600,18 +644,19 @@ __global__ void k_finalize(FinalizeArgs a)
     __syncthreads();
     if (t == 0) {
         // median: order by fp64 value, ties between exact values by the integers
+        const RepDev *R0 = a.rs + Q.rep_base;
         int idx[kMaxD];
         int n_mod = 0;
-        for (int i = 0; i < a.d; ++i) {
+        for (int i = 0; i < Q.d; ++i) {
             idx[i] = i;
-            if (a.reps[i].kprimes > 0) ++n_mod;
+            if (R0[i].kprimes > 0) ++n_mod;
         }
-        for (int i = 1; i < a.d; ++i) {
+        for (int i = 1; i < Q.d; ++i) {
             const int cur = idx[i];
             int j = i - 1;
             while (j >= 0) {
-                const RepDev &A = a.reps[idx[j]];
-                const RepDev &B = a.reps[cur];
+                const RepDev &A = R0[idx[j]];
+                const RepDev &B = R0[cur];
                 bool greater;
                 if (A.value != B.value) {
                     greater = A.value > B.value;
@@ -628,16 +673,17 @@ __global__ void k_finalize(FinalizeArgs a)
             }
             idx[j + 1] = cur;
         }
-        const int med = idx[(a.d - 1) / 2];
-        const RepDev &R = a.reps[med];
-        a.out->value = R.value;
-        a.out->lo = R.lo;
-        a.out->hi = R.hi;
-        a.out->exact = R.exact;
+        const int med = idx[(Q.d - 1) / 2];
+        const RepDev &R = R0[med];
+        OutDev &o = a.outs[blockIdx.x];
+        o.value = R.value;
+        o.lo = R.lo;
+        o.hi = R.hi;
+        o.exact = R.exact;
         const __int128 x = (__int128)(((unsigned __int128)(uint64_t)R.hi << 64) | (uint64_t)R.lo);
-        a.out->fits = R.exact && x >= (__int128)INT64_MIN && x <= (__int128)INT64_MAX;
-        a.out->n_modular = n_mod;
-        a.out->median_rep = med;
+        o.fits = R.exact && x >= (__int128)INT64_MIN && x <= (__int128)INT64_MAX;
+        o.n_modular = n_mod;
+        o.median_rep = med;
     }
 }
 
@@ -799,22 +845,6 @@ cs_status device_primes(int device, hipStream_t s, PrimeDev **out)
     return CS_OK;
 }
 
-// ---------------------------------------------------------------- work buffers
-
-struct Work {
-    double *norms = nullptr;
-    double *spec = nullptr;
-    unsigned long long *dot = nullptr;
-    uint32_t *modp = nullptr;
-    double2 *Z = nullptr;
-    uint32_t *modbuf = nullptr;
-    int32_t *tables = nullptr;   // pack_re, pack_im, vec_of, part_of, partner, sk_index
-    RepDev *reps = nullptr;
-    OutDev *out = nullptr;
-};
-
-size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
-
 }  // namespace
 
 const std::vector<PrimeInfo> &ntt_primes()
@@ -896,160 +926,317 @@ const uint32_t *roots_mod(int device, int log2m, int /*prime*/, bool /*inverse*/
     return dp;
 }
 
-cs_status estimate_run(Handle &h, hipStream_t s, cs_estimate_t *out, const cs_reps_t *reps)
+// ---------------------------------------------------------------- host: batched estimate engine
+
+namespace {
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int nblocks_for(int log2m)
 {
-    const GraphPlan &g = h.g;
-    const int r = g.n_rel, d = (int)h.d, L = h.log2m;
-    const size_t m = h.m;
-    const int plan = g.plan;
-    PrimeDev *primes = nullptr;
-    cs_status st = device_primes(h.device, s, &primes);
-    if (st != CS_OK) return st;
+    size_t nb = ((size_t)1 << log2m) / (kThreads * 8);
+    if (nb < 1) nb = 1;
+    if (nb > 64) nb = 64;
+    return (int)nb;
+}
 
-    // block counts: each thread of a reduction handles >= 8 elements
-    auto nblocks = [&](size_t len) {
-        size_t nb = len / (kThreads * 8);
-        if (nb < 1) nb = 1;
-        if (nb > 64) nb = 64;
-        return (int)nb;
-    };
-    const int nb = nblocks(m);
-    const int n_sk = r * d;
-    const int n_vec = (n_sk + 1) / 2;
-    int n_regs = g.n_regs > 0 ? g.n_regs : 1;
-
-    // ---- sizes of the work buffers (kMaxPrimes primes reserved for modular buffers)
+struct Carve {
     size_t off = 0;
-    auto take = [&](size_t bytes) {
+    size_t take(size_t bytes)
+    {
         const size_t o = off;
         off += align_up(bytes);
         return o;
+    }
+};
+
+}  // namespace
+
+cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t *outs, const cs_reps_t *reps_out,
+                         EstimateWork &ws)
+{
+    if (nq <= 0) return CS_OK;
+    const int device = hs[0]->device;
+    for (int q = 0; q < nq; ++q)
+        if (hs[q]->device != device) return fail(CS_EINVAL, "batched estimate: handles on different devices");
+    PrimeDev *primes = nullptr;
+    cs_status st = device_primes(device, s, &primes);
+    if (st != CS_OK) return st;
+
+    // ---- host tables
+    std::vector<QDesc> qd(nq);
+    std::vector<RepDesc> rd;
+    std::vector<SkDesc> sd;
+    std::vector<int32_t> dot_idx;
+    struct Group {
+        int log2m;
+        std::vector<int> queries;
+        std::vector<int32_t> rep_idx;
+        std::vector<const int64_t *> re, im;
+        size_t z_off = 0;
     };
-    const size_t o_norms = take((size_t)n_sk * nb * 2 * sizeof(double));
-    const size_t o_spec = take((size_t)d * nb * (2 + r) * sizeof(double));
-    const size_t o_dot = take((size_t)d * nb * 2 * sizeof(unsigned long long));
-    const size_t o_modp = take((size_t)kMaxPrimes * d * nb * sizeof(uint32_t));
-    const size_t o_Z = take(plan == CS_PLAN_SPECTRAL ? (size_t)n_vec * m * sizeof(double2) : 0);
-    size_t mod_elems = 0;
-    const size_t o_tables = take((size_t)(2 * n_vec + 3 * n_sk + n_sk) * sizeof(int32_t));
-    const size_t o_reps = take((size_t)d * sizeof(RepDev));
-    const size_t o_out = take(sizeof(OutDev));
-    const size_t base_bytes = off;
-    (void)mod_elems;
-    (void)n_regs;
-    if (h.work.bytes < base_bytes) {
-        if (h.work.buf) hipFree(h.work.buf);
-        h.work.buf = nullptr;
-        h.work.bytes = 0;
-        if (hipMalloc(&h.work.buf, base_bytes) != hipSuccess) return fail(CS_ENOMEM, "estimate workspace");
-        h.work.bytes = base_bytes;
-    }
-    char *wb = static_cast<char *>(h.work.buf);
-    Work w;
-    w.norms = reinterpret_cast<double *>(wb + o_norms);
-    w.spec = reinterpret_cast<double *>(wb + o_spec);
-    w.dot = reinterpret_cast<unsigned long long *>(wb + o_dot);
-    w.modp = reinterpret_cast<uint32_t *>(wb + o_modp);
-    w.Z = reinterpret_cast<double2 *>(wb + o_Z);
-    w.tables = reinterpret_cast<int32_t *>(wb + o_tables);
-    w.reps = reinterpret_cast<RepDev *>(wb + o_reps);
-    w.out = reinterpret_cast<OutDev *>(wb + o_out);
-
-    // ---- host tables: packing of (relation, repetition) sketches into complex vectors
-    std::vector<int32_t> tab(2 * n_vec + 3 * n_sk + n_sk, -1);
-    int32_t *pack_re = tab.data(), *pack_im = pack_re + n_vec, *vec_of = pack_im + n_vec;
-    int32_t *part_of = vec_of + n_sk, *partner = part_of + n_sk, *sk_index = partner + n_sk;
-    for (int v = 0; v < n_vec; ++v) {
-        pack_re[v] = 2 * v;
-        pack_im[v] = 2 * v + 1 < n_sk ? 2 * v + 1 : -1;
-    }
-    for (int k = 0; k < r; ++k)
-        for (int t = 0; t < d; ++t) {
-            const int sidx = k * d + t;
-            vec_of[t * r + k] = sidx / 2;
-            part_of[t * r + k] = sidx % 2;
-            const int other = sidx ^ 1;
-            partner[sidx] = other < n_sk ? other : -1;
-            sk_index[sidx] = sidx;
+    std::map<int, Group> groups;
+    std::vector<int> general_q;
+    int64_t norm_off = 0, spec_off = 0, dot_off = 0, mod_off = 0;
+    for (int q = 0; q < nq; ++q) {
+        const Handle &h = *hs[q];
+        const int r = h.g.n_rel, d = (int)h.d, L = h.log2m;
+        const int nb = nblocks_for(L);
+        QDesc &Q = qd[q];
+        Q.plan = h.g.plan;
+        Q.r = r;
+        Q.d = d;
+        Q.log2m = L;
+        Q.rep_base = (int32_t)rd.size();
+        Q.nb = nb;
+        const int sk_base = (int)sd.size();
+        const size_t m = h.m;
+        if (Q.plan != CS_PLAN_DOT) {
+            for (int k = 0; k < r; ++k)
+                for (int t = 0; t < d; ++t) {
+                    SkDesc S;
+                    S.p = h.counters + ((size_t)k * d + t) * m;
+                    S.log2m = L;
+                    S.nb = nb;
+                    S.off = norm_off;
+                    norm_off += nb;
+                    sd.push_back(S);
+                }
         }
-    int32_t *dtab = w.tables;
-    CSK_HIP(hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    const int32_t *d_pack_re = dtab, *d_pack_im = dtab + n_vec, *d_vec_of = d_pack_im + n_vec;
-    const int32_t *d_part_of = d_vec_of + n_sk, *d_partner = d_part_of + n_sk, *d_sk_index = d_partner + n_sk;
+        int vec_base = 0;
+        Group *G = nullptr;
+        if (Q.plan == CS_PLAN_SPECTRAL) {
+            G = &groups[L];
+            G->log2m = L;
+            G->queries.push_back(q);
+            vec_base = (int)G->re.size();
+            const int n_sk = r * d;
+            for (int v = 0; v < (n_sk + 1) / 2; ++v) {
+                const int s0 = 2 * v, s1 = 2 * v + 1;
+                G->re.push_back(sd[sk_base + s0].p);
+                G->im.push_back(s1 < n_sk ? sd[sk_base + s1].p : nullptr);
+            }
+        }
+        if (Q.plan == CS_PLAN_GENERAL) general_q.push_back(q);
+        for (int t = 0; t < d; ++t) {
+            RepDesc D{};
+            D.c0 = h.counters + (size_t)t * m;
+            D.c1 = h.counters + ((size_t)d + t) * m;
+            D.q = q;
+            D.t = t;
+            D.log2m = L;
+            D.r = r;
+            D.d = d;
+            D.conj = h.g.conj_mask;
+            D.vec_base = vec_base;
+            D.nb = nb;
+            D.sk_base = sk_base;
+            D.mod_vec_base = 0;
+            D.spec_off = spec_off;
+            D.dot_off = dot_off;
+            D.mod_off = mod_off;
+            mod_off += nb;
+            if (Q.plan == CS_PLAN_SPECTRAL) {
+                spec_off += (int64_t)nb * (2 + r);
+                G->rep_idx.push_back((int32_t)rd.size());
+            }
+            if (Q.plan == CS_PLAN_DOT) {
+                dot_off += nb;
+                dot_idx.push_back((int32_t)rd.size());
+            }
+            rd.push_back(D);
+        }
+    }
+    const int n_rep = (int)rd.size();
+    const int64_t mod_plane = mod_off;
 
-    FinalizeArgs fa{};
-    fa.plan = plan;
-    fa.r = r;
-    fa.d = d;
-    fa.log2m = L;
-    fa.nb_norm = nb;
-    fa.nb_spec = nb;
-    fa.nb_mod = nb;
-    fa.nb_dot = nb;
-    fa.norms = w.norms;
-    fa.spec = w.spec;
-    fa.dot = w.dot;
-    fa.modp = w.modp;
-    fa.partner = d_partner;
-    fa.primes = primes;
-    fa.crt = g_crt;
-    fa.reps = w.reps;
-    fa.out = w.out;
-    const double per_thread = std::ceil((double)m / ((double)nb * kThreads));
-    fa.n_eff_spec = per_thread + 8.0 + nb;
-    fa.n_eff_norm = per_thread + 8.0 + nb;
+    // ---- workspace layout
+    Carve c;
+    const size_t o_q = c.take(qd.size() * sizeof(QDesc));
+    const size_t o_rep = c.take(rd.size() * sizeof(RepDesc));
+    const size_t o_sk = c.take(std::max<size_t>(1, sd.size()) * sizeof(SkDesc));
+    const size_t o_dotidx = c.take(std::max<size_t>(1, dot_idx.size()) * sizeof(int32_t));
+    std::vector<size_t> o_gidx, o_gre, o_gim;
+    size_t z_total = 0;
+    for (auto &kv : groups) {
+        Group &G = kv.second;
+        o_gidx.push_back(c.take(G.rep_idx.size() * sizeof(int32_t)));
+        o_gre.push_back(c.take(G.re.size() * sizeof(void *)));
+        o_gim.push_back(c.take(G.im.size() * sizeof(void *)));
+        G.z_off = z_total;
+        z_total += align_up(G.re.size() * ((size_t)1 << G.log2m) * sizeof(double2));
+    }
+    const size_t host_tables = c.off;
+    const size_t o_norms = c.take(std::max<int64_t>(1, norm_off) * 2 * sizeof(double));
+    const size_t o_spec = c.take(std::max<int64_t>(1, spec_off) * sizeof(double));
+    const size_t o_dot = c.take(std::max<int64_t>(1, dot_off) * 2 * sizeof(unsigned long long));
+    const size_t o_modp = c.take((size_t)kMaxPrimes * std::max<int64_t>(1, mod_plane) * sizeof(uint32_t));
+    const size_t o_rs = c.take((size_t)n_rep * sizeof(RepDev));
+    const size_t o_outs = c.take((size_t)nq * sizeof(OutDev));
+    const size_t o_Z = c.take(z_total);
+    if (ws.bytes < c.off) {
+        if (ws.buf) {
+            CSK_HIP(hipStreamSynchronize(s));
+            hipFree(ws.buf);
+        }
+        ws.buf = nullptr;
+        ws.bytes = 0;
+        if (hipMalloc(&ws.buf, c.off) != hipSuccess) return fail(CS_ENOMEM, "estimate workspace");
+        ws.bytes = c.off;
+    }
+    char *wb = static_cast<char *>(ws.buf);
+    // host image of the tables, one upload
+    std::vector<char> img(host_tables, 0);
+    std::memcpy(img.data() + o_q, qd.data(), qd.size() * sizeof(QDesc));
+    std::memcpy(img.data() + o_rep, rd.data(), rd.size() * sizeof(RepDesc));
+    if (!sd.empty()) std::memcpy(img.data() + o_sk, sd.data(), sd.size() * sizeof(SkDesc));
+    if (!dot_idx.empty()) std::memcpy(img.data() + o_dotidx, dot_idx.data(), dot_idx.size() * sizeof(int32_t));
+    {
+        int gi = 0;
+        for (auto &kv : groups) {
+            Group &G = kv.second;
+            std::memcpy(img.data() + o_gidx[gi], G.rep_idx.data(), G.rep_idx.size() * sizeof(int32_t));
+            std::memcpy(img.data() + o_gre[gi], G.re.data(), G.re.size() * sizeof(void *));
+            std::memcpy(img.data() + o_gim[gi], G.im.data(), G.im.size() * sizeof(void *));
+            ++gi;
+        }
+    }
+    CSK_HIP(hipMemcpyAsync(wb, img.data(), img.size(), hipMemcpyHostToDevice, s));
+    const QDesc *d_q = reinterpret_cast<const QDesc *>(wb + o_q);
+    RepDesc *d_rep = reinterpret_cast<RepDesc *>(wb + o_rep);
+    const SkDesc *d_sk = reinterpret_cast<const SkDesc *>(wb + o_sk);
+    double *d_norms = reinterpret_cast<double *>(wb + o_norms);
+    double *d_spec = reinterpret_cast<double *>(wb + o_spec);
+    unsigned long long *d_dot = reinterpret_cast<unsigned long long *>(wb + o_dot);
+    uint32_t *d_modp = reinterpret_cast<uint32_t *>(wb + o_modp);
+    RepDev *d_rs = reinterpret_cast<RepDev *>(wb + o_rs);
+    OutDev *d_outs = reinterpret_cast<OutDev *>(wb + o_outs);
 
     // ---- stage 1
-    if (plan == CS_PLAN_DOT) {
-        const int64_t *c0 = h.counters;
-        const int64_t *c1 = h.counters + (size_t)d * m;
-        hipLaunchKernelGGL(k_dot, dim3(nb, d), dim3(kThreads), 0, s, c0, c1, L, nb, w.dot);
+    if (!sd.empty()) {
+        hipLaunchKernelGGL(k_norms, dim3((unsigned)sd.size(), 64), dim3(kThreads), 0, s, d_sk, d_norms);
         CSK_HIP(hipGetLastError());
-    } else {
-        hipLaunchKernelGGL(k_norms, dim3(nb, n_sk), dim3(kThreads), 0, s, h.counters, L, nb, w.norms);
+    }
+    if (!dot_idx.empty()) {
+        hipLaunchKernelGGL(k_dot, dim3((unsigned)dot_idx.size(), 64), dim3(kThreads), 0, s, d_rep,
+                           reinterpret_cast<const int32_t *>(wb + o_dotidx), d_dot);
         CSK_HIP(hipGetLastError());
-        if (plan == CS_PLAN_SPECTRAL) {
-            const double *tw = twiddles_f64(h.device, L, s, &st);
+    }
+    {
+        int gi = 0;
+        for (auto &kv : groups) {
+            Group &G = kv.second;
+            const double *tw = twiddles_f64(device, G.log2m, s, &st);
             if (!tw) return st;
-            st = fft_f64_forward(h.counters, d_pack_re, d_pack_im, n_vec, w.Z, L,
-                                 reinterpret_cast<const double2 *>(tw), L, s);
+            double2 *Z = reinterpret_cast<double2 *>(wb + o_Z + G.z_off);
+            st = fft_f64_forward(reinterpret_cast<const int64_t *const *>(wb + o_gre[gi]),
+                                 reinterpret_cast<const int64_t *const *>(wb + o_gim[gi]), (int)G.re.size(), Z,
+                                 G.log2m, reinterpret_cast<const double2 *>(tw), G.log2m, s);
             if (st != CS_OK) return st;
-            hipLaunchKernelGGL(k_spec_f64, dim3(nb, d), dim3(kThreads), 0, s, w.Z, L, r, d_vec_of, d_part_of,
-                               g.conj_mask, nb, w.spec);
+            hipLaunchKernelGGL(k_spec_f64, dim3((unsigned)G.rep_idx.size(), 64), dim3(kThreads), 0, s, Z, d_rep,
+                               reinterpret_cast<const int32_t *>(wb + o_gidx[gi]), d_spec);
             CSK_HIP(hipGetLastError());
+            ++gi;
         }
     }
+    FinalizeArgs fa{};
+    fa.qs = d_q;
+    fa.reps = d_rep;
+    fa.sks = d_sk;
+    fa.norms = d_norms;
+    fa.spec = d_spec;
+    fa.dot = d_dot;
+    fa.modp = d_modp;
+    fa.mod_plane = mod_plane;
+    fa.primes = primes;
+    fa.crt = g_crt;
+    fa.rs = d_rs;
+    fa.outs = d_outs;
     fa.stage = 1;
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kMaxD), 0, s, fa);
+    hipLaunchKernelGGL(k_finalize, dim3(nq), dim3(kMaxD), 0, s, fa);
     CSK_HIP(hipGetLastError());
 
-    std::vector<RepDev> hr(d);
-    CSK_HIP(hipMemcpyAsync(hr.data(), w.reps, d * sizeof(RepDev), hipMemcpyDeviceToHost, s));
+    std::vector<RepDev> hr(n_rep);
+    CSK_HIP(hipMemcpyAsync(hr.data(), d_rs, n_rep * sizeof(RepDev), hipMemcpyDeviceToHost, s));
     CSK_HIP(hipStreamSynchronize(s));
-    int K = 0;
-    for (int t = 0; t < d; ++t) K = std::max(K, hr[t].kprimes);
 
-    // ---- stage 2: modular residues
-    if (K > 0) {
-        const uint32_t *roots = roots_mod(h.device, L, 0, false, s, &st);
-        if (!roots) return st;
-        size_t mod_bytes;
-        if (plan == CS_PLAN_SPECTRAL) mod_bytes = (size_t)K * n_sk * m * sizeof(uint32_t);
-        else mod_bytes = (size_t)g.n_regs * K * d * m * sizeof(uint32_t);
-        void *mb = nullptr;
-        if (hipMallocAsync(&mb, mod_bytes, s) != hipSuccess) return fail(CS_ENOMEM, "modular workspace");
-        uint32_t *M = static_cast<uint32_t *>(mb);
-        if (plan == CS_PLAN_SPECTRAL) {
-            st = ntt_forward(h.counters, d_sk_index, n_sk, K, M, L, primes, roots, L, s);
+    // ---- stage 2: modular residues for the repetitions that need them
+    bool any = false;
+    for (int i = 0; i < n_rep; ++i) any = any || hr[i].kprimes > 0;
+    std::vector<void *> mod_bufs;
+    if (any) {
+        // spectral groups: every repetition of a query that needs one is recomputed
+        for (auto &kv : groups) {
+            Group &G = kv.second;
+            int K = 0;
+            std::vector<int> needq;
+            for (int q : G.queries) {
+                int kq = 0;
+                for (int t = 0; t < qd[q].d; ++t) kq = std::max(kq, hr[qd[q].rep_base + t].kprimes);
+                if (kq > 0) {
+                    needq.push_back(q);
+                    K = std::max(K, kq);
+                }
+            }
+            if (needq.empty()) continue;
+            const uint32_t *roots = roots_mod(device, G.log2m, 0, false, s, &st);
+            if (!roots) return st;
+            std::vector<const int64_t *> ptrs;
+            std::vector<int32_t> idx;
+            for (int q : needq) {
+                const int base = (int)ptrs.size();
+                for (int k = 0; k < qd[q].r; ++k)
+                    for (int t = 0; t < qd[q].d; ++t) ptrs.push_back(hs[q]->counters + ((size_t)k * qd[q].d + t) * hs[q]->m);
+                for (int t = 0; t < qd[q].d; ++t) {
+                    rd[qd[q].rep_base + t].mod_vec_base = base;
+                    idx.push_back(qd[q].rep_base + t);
+                }
+            }
+            const int vpp = (int)ptrs.size();
+            const size_t m = (size_t)1 << G.log2m;
+            const size_t tab_bytes = align_up(ptrs.size() * sizeof(void *)) + align_up(idx.size() * sizeof(int32_t));
+            void *mb = nullptr;
+            if (hipMallocAsync(&mb, tab_bytes + (size_t)K * vpp * m * sizeof(uint32_t), s) != hipSuccess)
+                return fail(CS_ENOMEM, "modular workspace");
+            mod_bufs.push_back(mb);
+            char *mbc = static_cast<char *>(mb);
+            std::vector<char> mimg(tab_bytes, 0);
+            std::memcpy(mimg.data(), ptrs.data(), ptrs.size() * sizeof(void *));
+            std::memcpy(mimg.data() + align_up(ptrs.size() * sizeof(void *)), idx.data(), idx.size() * sizeof(int32_t));
+            CSK_HIP(hipMemcpyAsync(mbc, mimg.data(), tab_bytes, hipMemcpyHostToDevice, s));
+            // updated mod_vec_base of these repetitions
+            for (int q : needq)
+                CSK_HIP(hipMemcpyAsync(d_rep + qd[q].rep_base, rd.data() + qd[q].rep_base, qd[q].d * sizeof(RepDesc),
+                                       hipMemcpyHostToDevice, s));
+            uint32_t *N = reinterpret_cast<uint32_t *>(mbc + tab_bytes);
+            st = ntt_forward(reinterpret_cast<const int64_t *const *>(mbc), vpp, K, N, G.log2m, primes, roots,
+                             G.log2m, s);
             if (st != CS_OK) return st;
-            hipLaunchKernelGGL(k_spec_mod, dim3(nb, d, K), dim3(kThreads), 0, s, M, L, r, d, g.conj_mask, primes,
-                               nb, w.modp);
+            hipLaunchKernelGGL(k_spec_mod, dim3((unsigned)idx.size(), 64, K), dim3(kThreads), 0, s, N, vpp, d_rep,
+                               reinterpret_cast<const int32_t *>(mbc + align_up(ptrs.size() * sizeof(void *))), primes,
+                               mod_plane, d_modp);
             CSK_HIP(hipGetLastError());
-            fa.mod_scale_m = 1;
-        } else {
+            // keep mimg alive until the copy is consumed
+            CSK_HIP(hipStreamSynchronize(s));
+        }
+        // general plans: Alg. 3's register program per query
+        for (int q : general_q) {
+            int K = 0;
+            for (int t = 0; t < qd[q].d; ++t) K = std::max(K, hr[qd[q].rep_base + t].kprimes);
+            if (K == 0) continue;
+            const Handle &h = *hs[q];
+            const int d = (int)h.d, L = h.log2m;
+            const size_t m = h.m;
+            const uint32_t *roots = roots_mod(device, L, 0, false, s, &st);
+            if (!roots) return st;
             const size_t reg_elems = (size_t)K * d * m;
+            void *mb = nullptr;
+            if (hipMallocAsync(&mb, (size_t)h.g.n_regs * reg_elems * sizeof(uint32_t), s) != hipSuccess)
+                return fail(CS_ENOMEM, "modular workspace");
+            mod_bufs.push_back(mb);
+            uint32_t *M = static_cast<uint32_t *>(mb);
             const int gx = (int)std::min<size_t>(64, (m + 255) / 256);
-            for (const Op &op : g.ops) {
+            for (const Op &op : h.g.ops) {
                 uint32_t *dst = M + (size_t)op.dst * reg_elems;
                 switch (op.code) {
                     case OP_LOAD:
@@ -1065,9 +1252,9 @@ cs_status estimate_run(Handle &h, hipStream_t s, cs_estimate_t *out, const cs_re
                         break;
                     case OP_CORR: {
                         uint32_t *src = M + (size_t)op.src * reg_elems;
-                        st = ntt_forward(nullptr, nullptr, d, K, src, L, primes, roots, L, s);
+                        st = ntt_forward(nullptr, d, K, src, L, primes, roots, L, s);
                         if (st != CS_OK) return st;
-                        st = ntt_forward(nullptr, nullptr, d, K, dst, L, primes, roots, L, s);
+                        st = ntt_forward(nullptr, d, K, dst, L, primes, roots, L, s);
                         if (st != CS_OK) return st;
                         hipLaunchKernelGGL(k_mod_mul, dim3(gx, K * d), dim3(256), 0, s, dst, src, L, d, primes, 1);
                         CSK_HIP(hipGetLastError());
@@ -1080,38 +1267,48 @@ cs_status estimate_run(Handle &h, hipStream_t s, cs_estimate_t *out, const cs_re
                 }
                 CSK_HIP(hipGetLastError());
             }
-            hipLaunchKernelGGL(k_mod_sum, dim3(nb, K * d), dim3(kThreads), 0, s,
-                               M + (size_t)g.result_reg * reg_elems, L, d, primes, nb, w.modp);
+            hipLaunchKernelGGL(k_mod_sum, dim3(qd[q].nb, K * d), dim3(kThreads), 0, s,
+                               M + (size_t)h.g.result_reg * reg_elems, L, d, primes, qd[q].nb, d_rep, qd[q].rep_base,
+                               mod_plane, d_modp);
             CSK_HIP(hipGetLastError());
-            fa.mod_scale_m = 0;
         }
         fa.stage = 2;
-        fa.n_primes = K;
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kMaxD), 0, s, fa);
+        hipLaunchKernelGGL(k_finalize, dim3(nq), dim3(kMaxD), 0, s, fa);
         CSK_HIP(hipGetLastError());
-        CSK_HIP(hipFreeAsync(mb, s));
+        for (void *mb : mod_bufs) CSK_HIP(hipFreeAsync(mb, s));
     }
 
-    OutDev ho;
-    CSK_HIP(hipMemcpyAsync(&ho, w.out, sizeof(OutDev), hipMemcpyDeviceToHost, s));
-    CSK_HIP(hipMemcpyAsync(hr.data(), w.reps, d * sizeof(RepDev), hipMemcpyDeviceToHost, s));
+    std::vector<OutDev> ho(nq);
+    CSK_HIP(hipMemcpyAsync(ho.data(), d_outs, nq * sizeof(OutDev), hipMemcpyDeviceToHost, s));
+    if (reps_out) CSK_HIP(hipMemcpyAsync(hr.data(), d_rs, n_rep * sizeof(RepDev), hipMemcpyDeviceToHost, s));
     CSK_HIP(hipStreamSynchronize(s));
-    out->value = ho.value;
-    out->exact = ho.exact;
-    out->fits_i64 = ho.fits;
-    out->value_i64 = ho.fits ? ho.lo : 0;
-    out->d = d;
-    out->n_modular = ho.n_modular;
-    if (reps) {
-        for (int t = 0; t < d; ++t) {
-            if (reps->value) reps->value[t] = hr[t].value;
-            if (reps->lo) reps->lo[t] = hr[t].lo;
-            if (reps->hi) reps->hi[t] = hr[t].hi;
-            if (reps->exact) reps->exact[t] = hr[t].exact;
-            if (reps->bound) reps->bound[t] = hr[t].bound;
+    for (int q = 0; q < nq; ++q) {
+        cs_estimate_t &o = outs[q];
+        o.value = ho[q].value;
+        o.exact = ho[q].exact;
+        o.fits_i64 = ho[q].fits;
+        o.value_i64 = ho[q].fits ? ho[q].lo : 0;
+        o.d = qd[q].d;
+        o.n_modular = ho[q].n_modular;
+        if (reps_out) {
+            const cs_reps_t &R = reps_out[q];
+            for (int t = 0; t < qd[q].d; ++t) {
+                const RepDev &x = hr[qd[q].rep_base + t];
+                if (R.value) R.value[t] = x.value;
+                if (R.lo) R.lo[t] = x.lo;
+                if (R.hi) R.hi[t] = x.hi;
+                if (R.exact) R.exact[t] = x.exact;
+                if (R.bound) R.bound[t] = x.bound;
+            }
         }
     }
     return CS_OK;
+}
+
+cs_status estimate_run(Handle &h, hipStream_t s, cs_estimate_t *out, const cs_reps_t *reps)
+{
+    Handle *hp = &h;
+    return estimate_batch(&hp, 1, s, out, reps, h.work);
 }
 
 }  // namespace csk

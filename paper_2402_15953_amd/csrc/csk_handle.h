@@ -56,5 +56,14 @@ struct Handle {
 };
 
 cs_status estimate_run(Handle &h, hipStream_t s, cs_estimate_t *out, const cs_reps_t *reps);
+// Estimates of nq queries at once (one FFT launch per sketch length, one product-reduce
+// launch per length, one finalize launch); reps_out may be null or hold nq entries.
+cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t *outs, const cs_reps_t *reps_out,
+                         EstimateWork &ws);
 
 }  // namespace csk
+
+// The opaque handle of the C ABI.
+struct cs_sketch {
+    csk::Handle h;
+};

@@ -11,6 +11,8 @@
 
 #include <cstdint>
 
+#include "csk_internal.h"
+
 namespace csk {
 
 constexpr uint64_t kHashP = (1ull << 61) - 1;
@@ -44,6 +46,48 @@ __device__ __forceinline__ uint64_t hash_deg1(const uint64_t *b, uint32_t x)
 __device__ __forceinline__ uint64_t hash_deg3(const uint64_t *a, uint32_t x)
 {
     return hcanon(hstep(hstep(hstep(a[3], x, a[2]), x, a[1]), x, a[0]));
+}
+
+// Per-relation hashing plan as the kernels read it: joins at each key column.
+struct DevPlan {
+    int32_t n_edges[kMaxCols];
+};
+
+template <int NC>
+__device__ __forceinline__ void load_keys(const uint32_t *__restrict__ keys, uint64_t i, bool vec2,
+                                          uint32_t (&x)[NC])
+{
+    if constexpr (NC == 2) {
+        if (vec2) {
+            const uint2 v = reinterpret_cast<const uint2 *>(keys)[i];
+            x[0] = v.x;
+            x[1] = v.y;
+            return;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) x[c] = keys[i * NC + c];
+}
+
+// Hash one tuple for one repetition; `cf` points at that repetition's coefficients
+// (per column: b0, b1, then a0..a3 per join).  Returns the bin (mod 2^32; caller masks)
+// and the sign bit (1 = negative).
+template <int NC>
+__device__ __forceinline__ void hash_rep(const uint64_t *__restrict__ cf, const DevPlan &plan,
+                                         const uint32_t (&x)[NC], uint32_t &j, uint32_t &neg)
+{
+    j = 0;
+    neg = 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        j += (uint32_t)hash_deg1(cf, x[c]);
+        cf += 2;
+        const int ne = plan.n_edges[c];
+        for (int e = 0; e < ne; ++e) {
+            neg ^= (uint32_t)hash_deg3(cf, x[c]) & 1u;
+            cf += 4;
+        }
+    }
 }
 
 }  // namespace csk

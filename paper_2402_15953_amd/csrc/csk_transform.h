@@ -50,13 +50,15 @@ __host__ __device__ inline uint32_t pos_freq(uint32_t pos, int log2m)
     return (pos >> 12) | ((pos & 4095u) << l1);
 }
 
-cs_status fft_f64_forward(const int64_t *sk, const int32_t *pack_re, const int32_t *pack_im, int n_vec,
-                          double2 *buf, int log2m, const double2 *tw, int log2T, hipStream_t s);
+// Forward fp64 FFTs of n_vec complex vectors re[v] + i im[v] (device pointer tables of
+// int64 sketches; im[v] may be null) into buf [n_vec][m].
+cs_status fft_f64_forward(const int64_t *const *re, const int64_t *const *im, int n_vec, double2 *buf, int log2m,
+                          const double2 *tw, int log2T, hipStream_t s);
 
-// sk != null: vector (prime i, j) is loaded from sketch sk_index[j] (first pass).
-cs_status ntt_forward(const int64_t *sk, const int32_t *sk_index, int vec_per_prime, int n_primes,
-                      uint32_t *buf, int log2m, const PrimeDev *primes, const uint32_t *roots, int log2T,
-                      hipStream_t s);
+// ptrs != null: vector (prime i, j) is loaded from sketch ptrs[j] (device pointer table);
+// ptrs == null: transform buf in place.
+cs_status ntt_forward(const int64_t *const *ptrs, int vec_per_prime, int n_primes, uint32_t *buf, int log2m,
+                      const PrimeDev *primes, const uint32_t *roots, int log2T, hipStream_t s);
 cs_status ntt_inverse(int vec_per_prime, int n_primes, uint32_t *buf, int log2m, const PrimeDev *primes,
                       const uint32_t *roots, int log2T, hipStream_t s);
 

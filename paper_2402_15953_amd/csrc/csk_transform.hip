@@ -60,27 +60,25 @@ __device__ __forceinline__ void lds_stages(typename Ring::T *s, int log2L, int l
 // Source of a pass: either the complex work buffer, or (first pass) the int64 sketches
 // of the (relation, repetition) pair packed into one complex vector: re + i * im.
 struct F64Src {
-    const int64_t *sk;        // sketches, [n_sk][m]
-    const int32_t *pack_re;   // [n_vec] sketch index for the real part
-    const int32_t *pack_im;   // [n_vec] sketch index for the imaginary part, -1 = none
+    const int64_t *const *re;  // [n_vec] sketch loaded as the real part (null: in place)
+    const int64_t *const *im;  // [n_vec] sketch loaded as the imaginary part (entry null: 0)
 };
 
 __global__ __launch_bounds__(kThreads) void k_fft_f64(F64Src src, double2 *buf, PassGeom g,
                                                       const double2 *__restrict__ tw, int log2T)
 {
     __shared__ double2 s[kTile];
-    const int v = blockIdx.y;
-    const int blk = blockIdx.x;
+    const int v = blockIdx.x;
+    const int blk = blockIdx.y;
     const int C = 1 << g.log2C;
     const int L = 1 << g.log2L;
     const int64_t m = (int64_t)1 << g.log2m;
     const int64_t base = (int64_t)blk * g.block_stride;
     double2 *vec = buf + (size_t)v * m;
     const int total = L << g.log2C;
-    if (src.sk) {
-        const int64_t *re = src.sk + (size_t)src.pack_re[v] * m;
-        const int im_idx = src.pack_im[v];
-        const int64_t *im = im_idx >= 0 ? src.sk + (size_t)im_idx * m : nullptr;
+    if (src.re) {
+        const int64_t *re = src.re[v];
+        const int64_t *im = src.im[v];
         for (int idx = threadIdx.x; idx < total; idx += kThreads) {
             const int n = idx >> g.log2C, c = idx & (C - 1);
             const int64_t pos = base + (int64_t)c * g.col_stride + (int64_t)n * g.elem_stride;
@@ -113,8 +111,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_f64(F64Src src, double2 *buf, 
 // ---------------------------------------------------------------- NTT pass
 
 struct ModSrc {
-    const int64_t *sk;        // sketches [n_sk][m] (first pass only; else null)
-    const int32_t *sk_index;  // [vec_per_prime] sketch index of vector v % vec_per_prime
+    const int64_t *const *ptr;  // [vec_per_prime] sketch of vector v % vec_per_prime (null: in place)
 };
 
 __global__ __launch_bounds__(kThreads) void k_ntt(ModSrc src, uint32_t *buf, PassGeom g, int vec_per_prime,
@@ -122,20 +119,20 @@ __global__ __launch_bounds__(kThreads) void k_ntt(ModSrc src, uint32_t *buf, Pas
                                                   const uint32_t *__restrict__ roots, int log2T, int inverse)
 {
     __shared__ uint32_t s[kTile];
-    const int v = blockIdx.y;
+    const int v = blockIdx.x;
     const int pi = v / vec_per_prime;
     const PrimeDev P = primes[pi];
     const RingM R{P.p, P.pinv_neg};
     const uint32_t *tw = roots + ((size_t)(2 * pi + inverse) << log2T);
-    const int blk = blockIdx.x;
+    const int blk = blockIdx.y;
     const int C = 1 << g.log2C;
     const int L = 1 << g.log2L;
     const int64_t m = (int64_t)1 << g.log2m;
     const int64_t base = (int64_t)blk * g.block_stride;
     uint32_t *vec = buf + (size_t)v * m;
     const int total = L << g.log2C;
-    if (src.sk) {
-        const int64_t *in = src.sk + (size_t)src.sk_index[v % vec_per_prime] * m;
+    if (src.ptr) {
+        const int64_t *in = src.ptr[v % vec_per_prime];
         for (int idx = threadIdx.x; idx < total; idx += kThreads) {
             const int n = idx >> g.log2C, c = idx & (C - 1);
             const int64_t pos = base + (int64_t)c * g.col_stride + (int64_t)n * g.elem_stride;
@@ -206,48 +203,47 @@ PassGeom single_pass(int log2m)
 
 }  // namespace
 
-cs_status fft_f64_forward(const int64_t *sk, const int32_t *pack_re, const int32_t *pack_im, int n_vec,
-                          double2 *buf, int log2m, const double2 *tw, int log2T, hipStream_t s)
+cs_status fft_f64_forward(const int64_t *const *re, const int64_t *const *im, int n_vec, double2 *buf, int log2m,
+                          const double2 *tw, int log2T, hipStream_t s)
 {
     if (n_vec == 0) return CS_OK;
-    F64Src first{sk, pack_re, pack_im};
-    F64Src self{nullptr, nullptr, nullptr};
+    F64Src first{re, im};
+    F64Src self{nullptr, nullptr};
     if (log2m <= 12) {
         PassGeom g = single_pass(log2m);
-        hipLaunchKernelGGL(k_fft_f64, dim3(g.blocks, n_vec), dim3(kThreads), 0, s, first, buf, g, tw, log2T);
+        hipLaunchKernelGGL(k_fft_f64, dim3(n_vec, g.blocks), dim3(kThreads), 0, s, first, buf, g, tw, log2T);
         CSK_HIP(hipGetLastError());
         return CS_OK;
     }
     PassGeom g1 = column_pass(log2m, true);
-    hipLaunchKernelGGL(k_fft_f64, dim3(g1.blocks, n_vec), dim3(kThreads), 0, s, first, buf, g1, tw, log2T);
+    hipLaunchKernelGGL(k_fft_f64, dim3(n_vec, g1.blocks), dim3(kThreads), 0, s, first, buf, g1, tw, log2T);
     CSK_HIP(hipGetLastError());
     PassGeom g2 = row_pass(log2m, false);
-    hipLaunchKernelGGL(k_fft_f64, dim3(g2.blocks, n_vec), dim3(kThreads), 0, s, self, buf, g2, tw, log2T);
+    hipLaunchKernelGGL(k_fft_f64, dim3(n_vec, g2.blocks), dim3(kThreads), 0, s, self, buf, g2, tw, log2T);
     CSK_HIP(hipGetLastError());
     return CS_OK;
 }
 
-cs_status ntt_forward(const int64_t *sk, const int32_t *sk_index, int vec_per_prime, int n_primes,
-                      uint32_t *buf, int log2m, const PrimeDev *primes, const uint32_t *roots, int log2T,
-                      hipStream_t s)
+cs_status ntt_forward(const int64_t *const *ptrs, int vec_per_prime, int n_primes, uint32_t *buf, int log2m,
+                      const PrimeDev *primes, const uint32_t *roots, int log2T, hipStream_t s)
 {
     const int n_vec = vec_per_prime * n_primes;
     if (n_vec == 0) return CS_OK;
-    ModSrc first{sk, sk_index};
-    ModSrc self{nullptr, nullptr};
+    ModSrc first{ptrs};
+    ModSrc self{nullptr};
     if (log2m <= 12) {
         PassGeom g = single_pass(log2m);
-        hipLaunchKernelGGL(k_ntt, dim3(g.blocks, n_vec), dim3(kThreads), 0, s, sk ? first : self, buf, g,
+        hipLaunchKernelGGL(k_ntt, dim3(n_vec, g.blocks), dim3(kThreads), 0, s, ptrs ? first : self, buf, g,
                            vec_per_prime, primes, roots, log2T, 0);
         CSK_HIP(hipGetLastError());
         return CS_OK;
     }
     PassGeom g1 = column_pass(log2m, true);
-    hipLaunchKernelGGL(k_ntt, dim3(g1.blocks, n_vec), dim3(kThreads), 0, s, sk ? first : self, buf, g1,
+    hipLaunchKernelGGL(k_ntt, dim3(n_vec, g1.blocks), dim3(kThreads), 0, s, ptrs ? first : self, buf, g1,
                        vec_per_prime, primes, roots, log2T, 0);
     CSK_HIP(hipGetLastError());
     PassGeom g2 = row_pass(log2m, false);
-    hipLaunchKernelGGL(k_ntt, dim3(g2.blocks, n_vec), dim3(kThreads), 0, s, self, buf, g2, vec_per_prime,
+    hipLaunchKernelGGL(k_ntt, dim3(n_vec, g2.blocks), dim3(kThreads), 0, s, self, buf, g2, vec_per_prime,
                        primes, roots, log2T, 0);
     CSK_HIP(hipGetLastError());
     return CS_OK;
@@ -258,22 +254,22 @@ cs_status ntt_inverse(int vec_per_prime, int n_primes, uint32_t *buf, int log2m,
 {
     const int n_vec = vec_per_prime * n_primes;
     if (n_vec == 0) return CS_OK;
-    ModSrc self{nullptr, nullptr};
+    ModSrc self{nullptr};
     if (log2m <= 12) {
         PassGeom g = single_pass(log2m);
         g.scale = 1;
-        hipLaunchKernelGGL(k_ntt, dim3(g.blocks, n_vec), dim3(kThreads), 0, s, self, buf, g, vec_per_prime,
+        hipLaunchKernelGGL(k_ntt, dim3(n_vec, g.blocks), dim3(kThreads), 0, s, self, buf, g, vec_per_prime,
                            primes, roots, log2T, 1);
         CSK_HIP(hipGetLastError());
         return CS_OK;
     }
     PassGeom g1 = row_pass(log2m, true);
-    hipLaunchKernelGGL(k_ntt, dim3(g1.blocks, n_vec), dim3(kThreads), 0, s, self, buf, g1, vec_per_prime,
+    hipLaunchKernelGGL(k_ntt, dim3(n_vec, g1.blocks), dim3(kThreads), 0, s, self, buf, g1, vec_per_prime,
                        primes, roots, log2T, 1);
     CSK_HIP(hipGetLastError());
     PassGeom g2 = column_pass(log2m, false);
     g2.scale = 1;
-    hipLaunchKernelGGL(k_ntt, dim3(g2.blocks, n_vec), dim3(kThreads), 0, s, self, buf, g2, vec_per_prime,
+    hipLaunchKernelGGL(k_ntt, dim3(n_vec, g2.blocks), dim3(kThreads), 0, s, self, buf, g2, vec_per_prime,
                        primes, roots, log2T, 1);
     CSK_HIP(hipGetLastError());
     return CS_OK;

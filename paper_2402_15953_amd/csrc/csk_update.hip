@@ -30,47 +30,6 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kSegBlock = 1024;
 
-struct DevPlan {
-    int32_t n_edges[kMaxCols];
-};
-
-template <int NC>
-__device__ __forceinline__ void load_keys(const uint32_t *__restrict__ keys, uint64_t i, bool vec2,
-                                          uint32_t (&x)[NC])
-{
-    if constexpr (NC == 2) {
-        if (vec2) {
-            const uint2 v = reinterpret_cast<const uint2 *>(keys)[i];
-            x[0] = v.x;
-            x[1] = v.y;
-            return;
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < NC; ++c) x[c] = keys[i * NC + c];
-}
-
-// Hash one tuple for one repetition; `cf` points at that repetition's coefficients
-// (per column: b0, b1, then a0..a3 per join).  Returns the bin (mod 2^32; caller masks)
-// and the sign bit (1 = negative).
-template <int NC>
-__device__ __forceinline__ void hash_rep(const uint64_t *__restrict__ cf, const DevPlan &plan,
-                                         const uint32_t (&x)[NC], uint32_t &j, uint32_t &neg)
-{
-    j = 0;
-    neg = 0;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        j += (uint32_t)hash_deg1(cf, x[c]);
-        cf += 2;
-        const int ne = plan.n_edges[c];
-        for (int e = 0; e < ne; ++e) {
-            neg ^= (uint32_t)hash_deg3(cf, x[c]) & 1u;
-            cf += 4;
-        }
-    }
-}
-
 template <int NC>
 __global__ __launch_bounds__(kBlock) void k_update_global(const uint32_t *__restrict__ keys,
                                                           const int64_t *__restrict__ weights,
