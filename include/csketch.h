@@ -221,6 +221,63 @@ cs_status cs_batch_estimate(cs_batch *b, cs_sketch *const *sketches, int32_t n, 
 /* Task counts of the last planned batch update. */
 cs_status cs_batch_stats(const cs_batch *b, uint64_t *tasks_atomic, uint64_t *tasks_segment);
 
+/* ------------------------------------------------------------------ serving */
+
+typedef struct cs_server_config {
+    uint64_t memory_budget;    /* bytes of counters admitted over all live queries (0: none) */
+    int32_t n_streams;         /* update streams (default 2) */
+    int32_t max_batch_items;   /* update items per launch (default 4096) */
+    int32_t max_pending;       /* submitted-but-unfinished requests before CS_EBUSY (0: none) */
+    int32_t reserved;
+} cs_server_config;
+
+typedef struct cs_completion {
+    uint64_t ticket;
+    int32_t qid;
+    int32_t kind;              /* 0 update, 1 estimate */
+    int32_t status;            /* cs_status of the request */
+    int32_t reserved;
+    double submit_us, start_us, done_us;   /* host steady-clock microseconds */
+    cs_estimate_t estimate;    /* kind 1 */
+} cs_completion;
+
+typedef struct cs_server_stats_t {
+    uint64_t submitted, completed, used_bytes;
+    uint64_t update_launches, estimate_batches, epochs;
+    int32_t live_queries;
+    int32_t reserved;
+} cs_server_stats_t;
+
+typedef struct cs_server cs_server;
+
+/* A server keeps live sketches resident on the current device and executes update
+ * batches and estimate requests as they arrive: updates of each arrival epoch go into
+ * one batched persistent launch (round robin over n_streams), estimates into one
+ * batched estimate on their own stream, overlapping with later updates.  An estimate
+ * of a query reflects exactly the updates of that query submitted before it.  Two
+ * native threads (scheduler, estimator). */
+cs_status cs_server_create(const cs_server_config *cfg, cs_server **out);
+/* Waits for all submitted requests, stops the threads, frees every live query. */
+cs_status cs_server_destroy(cs_server *s);
+/* Admission: CS_EBUSY when the query's counters do not fit the memory budget. */
+cs_status cs_server_add_query(cs_server *s, const cs_graph *graph, uint32_t m, uint32_t d, uint64_t seed,
+                              int32_t *qid);
+/* Waits for all submitted requests, then frees the query's memory. */
+cs_status cs_server_remove_query(cs_server *s, int32_t qid);
+/* The handle of a live query (for reading its sketches; do not update it directly). */
+cs_status cs_server_sketch(cs_server *s, int32_t qid, cs_sketch **out);
+/* Enqueue a turnstile update batch (device keys / weights owned by the caller, alive
+ * until its completion is polled) or an estimate request; returns a ticket.
+ * CS_EBUSY when max_pending requests are outstanding. */
+cs_status cs_server_submit_update(cs_server *s, int32_t qid, int32_t rel, const uint32_t *keys,
+                                  const int64_t *weights, uint64_t n, int32_t flags, uint64_t *ticket);
+cs_status cs_server_submit_estimate(cs_server *s, int32_t qid, uint64_t *ticket);
+/* Non-blocking: move up to max finished requests into out. */
+cs_status cs_server_poll(cs_server *s, cs_completion *out, int32_t max, int32_t *n_out);
+/* Block until every submitted request has finished. */
+cs_status cs_server_drain(cs_server *s);
+cs_status cs_server_stats(cs_server *s, cs_server_stats_t *out);
+
 /* ------------------------------------------------------------------ state */
 
 /* Zero every counter (stream-ordered). */

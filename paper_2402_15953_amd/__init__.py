@@ -27,6 +27,9 @@ EXPORTED = [
     "cs_sketch_device_ptr", "cs_read_coeffs", "cs_read_components",
     "cs_batch_create", "cs_batch_destroy", "cs_batch_update", "cs_batch_capture", "cs_batch_replay",
     "cs_batch_estimate", "cs_batch_stats",
+    "cs_server_create", "cs_server_destroy", "cs_server_add_query", "cs_server_remove_query",
+    "cs_server_sketch", "cs_server_submit_update", "cs_server_submit_estimate", "cs_server_poll",
+    "cs_server_drain", "cs_server_stats",
 ]
 
 
@@ -55,6 +58,23 @@ class _Reps(ctypes.Structure):
 class _Item(ctypes.Structure):
     _fields_ = [("sketch", ctypes.c_void_p), ("rel", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("keys", ctypes.c_void_p), ("weights", ctypes.c_void_p), ("n", ctypes.c_uint64)]
+
+
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("memory_budget", ctypes.c_uint64), ("n_streams", ctypes.c_int32),
+                ("max_batch_items", ctypes.c_int32), ("max_pending", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class _Completion(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("qid", ctypes.c_int32), ("kind", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32), ("submit_us", ctypes.c_double),
+                ("start_us", ctypes.c_double), ("done_us", ctypes.c_double), ("estimate", _Estimate)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("used_bytes", ctypes.c_uint64),
+                ("update_launches", ctypes.c_uint64), ("estimate_batches", ctypes.c_uint64),
+                ("epochs", ctypes.c_uint64), ("live_queries", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -99,6 +119,16 @@ def lib() -> ctypes.CDLL:
         L.cs_batch_estimate.argtypes = [vp, ctypes.POINTER(vp), i32, vp, ctypes.POINTER(_Estimate),
                                         ctypes.POINTER(_Reps)]
         L.cs_batch_stats.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64)]
+        L.cs_server_create.argtypes = [ctypes.POINTER(_ServerConfig), ctypes.POINTER(vp)]
+        L.cs_server_destroy.argtypes = [vp]
+        L.cs_server_add_query.argtypes = [vp, ctypes.POINTER(_Graph), u32, u32, u64, ctypes.POINTER(i32)]
+        L.cs_server_remove_query.argtypes = [vp, i32]
+        L.cs_server_sketch.argtypes = [vp, i32, ctypes.POINTER(vp)]
+        L.cs_server_submit_update.argtypes = [vp, i32, i32, vp, vp, u64, i32, ctypes.POINTER(u64)]
+        L.cs_server_submit_estimate.argtypes = [vp, i32, ctypes.POINTER(u64)]
+        L.cs_server_poll.argtypes = [vp, ctypes.POINTER(_Completion), i32, ctypes.POINTER(i32)]
+        L.cs_server_drain.argtypes = [vp]
+        L.cs_server_stats.argtypes = [vp, ctypes.POINTER(_ServerStats)]
         _lib = L
     return _lib
 
@@ -299,3 +329,91 @@ class Batch:
             arrs = [p[1] for p in pairs]
         _check(lib().cs_batch_estimate(self._b, hs, n, _stream_ptr(stream), outs, rps))
         return [_estimate_dict(outs[i], arrs[i] if arrs else None) for i in range(n)]
+
+
+class _Borrowed(Sketch):
+    """A live query's handle owned by a Server (read-only use)."""
+
+    def __init__(self, h, graph, m, d, seed):  # noqa: D401 - no cs_create
+        self._h = h
+        self.graph, self.m, self.d, self.seed = graph, m, d, seed
+
+    def close(self):
+        self._h = None
+
+
+class Server:
+    """Serving loop: live sketches in HBM, update batches and estimates as they arrive."""
+
+    def __init__(self, memory_budget: int = 0, n_streams: int = 2, max_batch_items: int = 4096,
+                 max_pending: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("csketch needs a HIP GPU; there is no CPU fallback")
+        cfg = _ServerConfig(int(memory_budget), int(n_streams), int(max_batch_items), int(max_pending), 0)
+        s = ctypes.c_void_p()
+        _check(lib().cs_server_create(ctypes.byref(cfg), ctypes.byref(s)))
+        self._s = s
+        self._queries = {}
+
+    def close(self):
+        if getattr(self, "_s", None):
+            lib().cs_server_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_query(self, graph, m: int, d: int, seed: int) -> int:
+        q = ctypes.c_int32()
+        _check(lib().cs_server_add_query(self._s, ctypes.byref(_graph_struct(graph)), int(m), int(d), int(seed),
+                                         ctypes.byref(q)))
+        self._queries[q.value] = (graph, int(m), int(d), int(seed))
+        return q.value
+
+    def remove_query(self, qid: int):
+        _check(lib().cs_server_remove_query(self._s, int(qid)))
+        self._queries.pop(qid, None)
+
+    def sketch(self, qid: int) -> Sketch:
+        h = ctypes.c_void_p()
+        _check(lib().cs_server_sketch(self._s, int(qid), ctypes.byref(h)))
+        return _Borrowed(h, *self._queries[qid])
+
+    def submit_update(self, qid: int, rel: int, keys, weights=None, unit_weights: bool = False) -> int:
+        t = ctypes.c_uint64()
+        _check(lib().cs_server_submit_update(self._s, int(qid), int(rel), ctypes.c_void_p(keys.data_ptr()),
+                                             None if weights is None else ctypes.c_void_p(weights.data_ptr()),
+                                             int(keys.shape[0]), UPDATE_UNIT_WEIGHTS if unit_weights else 0,
+                                             ctypes.byref(t)))
+        return t.value
+
+    def submit_estimate(self, qid: int) -> int:
+        t = ctypes.c_uint64()
+        _check(lib().cs_server_submit_estimate(self._s, int(qid), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, max_n: int = 4096):
+        buf = (_Completion * max_n)()
+        n = ctypes.c_int32()
+        _check(lib().cs_server_poll(self._s, buf, max_n, ctypes.byref(n)))
+        out = []
+        for i in range(n.value):
+            c = buf[i]
+            d = dict(ticket=c.ticket, qid=c.qid, kind=c.kind, status=c.status, submit_us=c.submit_us,
+                     start_us=c.start_us, done_us=c.done_us)
+            if c.kind == 1:
+                d["estimate"] = _estimate_dict(c.estimate, None)
+            out.append(d)
+        return out
+
+    def drain(self):
+        _check(lib().cs_server_drain(self._s))
+
+    def stats(self) -> dict:
+        st = _ServerStats()
+        _check(lib().cs_server_stats(self._s, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in _ServerStats._fields_ if f != "reserved"}

@@ -235,6 +235,18 @@ uint64_t cs_sketch_bytes(const cs_graph *graph, uint32_t m, uint32_t d)
 
 cs_status cs_create(const cs_graph *graph, uint32_t m, uint32_t d, uint64_t seed, cs_sketch **out)
 {
+    return create_handle(graph, m, d, seed, true, out);
+}
+
+}  // extern "C"
+
+namespace csk {
+
+// Handle creation; without scratch the handle serves batched and served updates only
+// (cs_update then uses the global-atomic strategy).
+cs_status create_handle(const cs_graph *graph, uint32_t m, uint32_t d, uint64_t seed, bool with_scratch,
+                        cs_sketch **out)
+{
     if (!out) return fail(CS_EINVAL, "null output handle");
     *out = nullptr;
     if (m < 2 || m > (1u << kMaxLog2M) || (m & (m - 1))) return fail(CS_EINVAL, "m must be a power of two in [2, 2^20]");
@@ -292,8 +304,8 @@ cs_status cs_create(const cs_graph *graph, uint32_t m, uint32_t d, uint64_t seed
         delete hs;
         return fail(CS_ENOMEM, "coefficient allocation failed");
     }
-    h.scratch_bytes = seg_scratch_bytes(m, (int32_t)d);
-    if (hipMalloc(&h.scratch, h.scratch_bytes) != hipSuccess) {
+    h.scratch_bytes = with_scratch ? seg_scratch_bytes(m, (int32_t)d) : 0;
+    if (with_scratch && hipMalloc(&h.scratch, h.scratch_bytes) != hipSuccess) {
         hipFree(h.counters);
         hipFree(h.coef_dev);
         delete hs;
@@ -311,6 +323,10 @@ cs_status cs_create(const cs_graph *graph, uint32_t m, uint32_t d, uint64_t seed
     *out = hs;
     return CS_OK;
 }
+
+}  // namespace csk
+
+extern "C" {
 
 cs_status cs_destroy(cs_sketch *hs)
 {

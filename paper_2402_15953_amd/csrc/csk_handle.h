@@ -56,6 +56,12 @@ struct Handle {
 };
 
 cs_status estimate_run(Handle &h, hipStream_t s, cs_estimate_t *out, const cs_reps_t *reps);
+}  // namespace csk
+struct cs_sketch;
+namespace csk {
+// Handle creation; without scratch the handle serves batched and served updates only.
+cs_status create_handle(const cs_graph *graph, uint32_t m, uint32_t d, uint64_t seed, bool with_scratch,
+                        cs_sketch **out);
 // Estimates of nq queries at once (one FFT launch per sketch length, one product-reduce
 // launch per length, one finalize launch); reps_out may be null or hold nq entries.
 cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t *outs, const cs_reps_t *reps_out,

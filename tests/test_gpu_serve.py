@@ -1,0 +1,146 @@
+"""Serving loop through the C ABI: every estimate served in a mixed, concurrent trace
+equals the estimate of the same query computed alone from exactly the updates that were
+submitted before it; admission control by sketch memory."""
+import random
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from tests.helpers import keys_u32, to_device_keys
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    import paper_2402_15953_amd as csk
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _pools(specs, pool_n):
+    pools = []
+    for qi, sp in enumerate(specs):
+        rels = []
+        for k in range(sp.graph.n_rel):
+            keys = keys_u32(W.relation_keys(sp.graph, k, pool_n, "zipf", config=700 + qi, s=1.1, D=10 ** 5))
+            rels.append(to_device_keys(keys))
+        pools.append(rels)
+    return pools
+
+
+def _trace(specs, pool_n, n_req, seed, est_frac=0.2, del_frac=0.1, max_len=20_000):
+    """(kind, qid, rel, off, len, sign) requests; deletes re-send a slice inserted earlier."""
+    rng = random.Random(seed)
+    inserted = {}
+    out = []
+    for _ in range(n_req):
+        q = rng.randrange(len(specs))
+        if rng.random() < est_frac:
+            out.append(("E", q, 0, 0, 0, 0))
+            continue
+        k = rng.randrange(specs[q].graph.n_rel)
+        prev = inserted.get((q, k), [])
+        if prev and rng.random() < del_frac:
+            off, ln = prev.pop(rng.randrange(len(prev)))
+            out.append(("U", q, k, off, ln, -1))
+        else:
+            ln = rng.randint(1, max_len)
+            off = rng.randrange(0, pool_n - ln + 1)
+            inserted.setdefault((q, k), []).append((off, ln))
+            out.append(("U", q, k, off, ln, +1))
+    return out
+
+
+def test_served_estimates_equal_alone():
+    specs = W.batched_queries(10, seed=31, m_log2=(10, 14), d_choices=(5, 9), n_range=(10, 100))
+    pool_n = 60_000
+    pools = _pools(specs, pool_n)
+    ones = torch.ones(pool_n, dtype=torch.int64, device="cuda")
+    minus = -ones
+    srv = csk.Server(n_streams=3, max_batch_items=64)
+    qids = [srv.add_query(sp.graph, sp.m, sp.d, sp.sketch_seed) for sp in specs]
+    trace = _trace(specs, pool_n, 400, seed=1)
+    tickets = {}
+    history = {q: [] for q in range(len(specs))}
+    est_history = {}
+    for i, (kind, q, k, off, ln, sign) in enumerate(trace):
+        if kind == "U":
+            keys = pools[q][k][off:off + ln]
+            w = (ones if sign > 0 else minus)[off:off + ln]
+            t = srv.submit_update(qids[q], k, keys, w, unit_weights=True)
+            history[q].append((k, off, ln, sign))
+        else:
+            t = srv.submit_estimate(qids[q])
+            est_history[t] = (q, list(history[q]))
+        tickets[t] = (kind, q)
+        if i % 97 == 0:
+            srv.drain()
+    srv.drain()
+    comps = srv.poll(10_000)
+    assert len(comps) == len(trace)
+    assert all(c["status"] == 0 for c in comps)
+    st = srv.stats()
+    _say("server stats", st)
+    assert st["update_launches"] < sum(1 for r in trace if r[0] == "U")   # updates were batched
+    n_checked = 0
+    for c in comps:
+        if c["kind"] != 1:
+            continue
+        q, hist = est_history[c["ticket"]]
+        sp = specs[q]
+        alone = csk.Sketch(sp.graph, sp.m, sp.d, sp.sketch_seed)
+        for (k, off, ln, sign) in hist:
+            alone.update(k, pools[q][k][off:off + ln], (ones if sign > 0 else minus)[off:off + ln],
+                         unit_weights=True)
+        ref = alone.estimate()
+        assert c["estimate"] == ref, (c["ticket"], q, c["estimate"], ref)
+        alone.close()
+        n_checked += 1
+    _say("estimates checked", n_checked)
+    assert n_checked > 40
+    lat = sorted(c["done_us"] - c["submit_us"] for c in comps)
+    assert lat[0] >= 0
+    srv.close()
+
+
+def test_admission_by_memory():
+    g = W.chain(3)
+    per = csk.sketch_bytes(g, 1 << 14, 9)
+    srv = csk.Server(memory_budget=2 * per + 10)
+    a = srv.add_query(g, 1 << 14, 9, 1)
+    b = srv.add_query(g, 1 << 14, 9, 2)
+    with pytest.raises(csk.CsError) as e:
+        srv.add_query(g, 1 << 14, 9, 3)
+    assert e.value.status == csk.CS_EBUSY
+    srv.remove_query(a)
+    c = srv.add_query(g, 1 << 14, 9, 4)   # fits again
+    assert srv.stats()["live_queries"] == 2
+    srv.close()
+    del b, c
+
+
+def test_queue_limit():
+    g = W.single_join()
+    srv = csk.Server(max_pending=4)
+    q = srv.add_query(g, 1024, 5, 1)
+    keys = torch.zeros(1 << 20, 1, dtype=torch.int32, device="cuda")
+    n_ok, busy = 0, 0
+    for _ in range(64):
+        try:
+            srv.submit_update(q, 0, keys)
+            n_ok += 1
+        except csk.CsError as e:
+            assert e.status == csk.CS_EBUSY
+            busy += 1
+    srv.drain()
+    assert n_ok >= 4
+    comps = srv.poll()
+    assert len(comps) == n_ok
+    sk = srv.sketch(q)
+    assert int(np.abs(sk.read_sketch(0)).sum(axis=1)[0]) == n_ok * (1 << 20)
+    srv.close()
