@@ -44,6 +44,12 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-tuples", type=int, default=1 << 22, help="oracle sample per relation")
     ap.add_argument("--strategy", type=int, default=0)
+    ap.add_argument("--batch-queries", type=int, default=4096,
+                    help="batched section: chain/star queries (0 skips the section)")
+    ap.add_argument("--serve-queries", type=int, default=256, help="serving section: live queries (0 skips)")
+    ap.add_argument("--serve-seconds", type=float, default=3.0, help="serving section: seconds per load level")
+    ap.add_argument("--serve-rates", type=str, default="250,1000,4000,16000",
+                    help="serving section: offered update-batch arrival rates (batches/s)")
     return ap.parse_args()
 
 
@@ -167,11 +173,184 @@ def main():
         "estimate": {"value": res["value"], "exact": res["exact"], "n_modular": res["n_modular"]},
     }
 
+    sk.close()
+    del keys
+    torch.cuda.empty_cache()
+    if args.batch_queries > 0:
+        out["batched"] = bench_batched(args.batch_queries, dev, stream)
+        torch.cuda.empty_cache()
+    if args.serve_queries > 0:
+        out["serving"] = bench_serving(args.serve_queries, dev, args.serve_seconds,
+                                       [float(x) for x in args.serve_rates.split(",") if x])
+        torch.cuda.empty_cache()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(graph, keys, m, d, seed, args.cpu_tuples)
+        keys_cpu = [W.relation_keys(graph, k, args.cpu_tuples, "zipf", config=config, s=s, D=D).to(torch.int32)
+                    for k in range(graph.n_rel)]
+        out["cpu_baseline"] = cpu_baseline(graph, keys_cpu, m, d, seed, args.cpu_tuples)
 
     print(json.dumps(out), flush=True)
-    sk.close()
+
+
+def bench_batched(n_queries, dev, stream):
+    """Uneven chain/star queries (2-6 relations, n log-uniform in [1e3, 1e6], m = 2^10..2^16,
+    d in {5, 9}, Zipf(1.2) keys over 1e6): plain per-query calls vs one batched update
+    (graph replay) and one batched estimate, on the same inputs."""
+    import torch
+
+    import paper_2402_15953_amd as csk
+    import workloads as W
+
+    specs = W.batched_queries(n_queries, seed=4)
+    keys = []
+    for qi, sp in enumerate(specs):
+        keys.append([W.relation_keys(sp.graph, k, sp.n_per_rel[k], "zipf", config=4000 + qi, s=1.2, D=10 ** 6,
+                                     device=dev).to(torch.int32).contiguous() for k in range(sp.graph.n_rel)])
+    torch.cuda.synchronize()
+    tuples = sum(sum(sp.n_per_rel) for sp in specs)
+    sks = [csk.Sketch(sp.graph, sp.m, sp.d, sp.sketch_seed) for sp in specs]
+
+    def plain_pass():
+        t0 = time.perf_counter()
+        for sk_, ks in zip(sks, keys):
+            for k, kk in enumerate(ks):
+                sk_.update(k, kk, stream=stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ests = [sk_.estimate(stream=stream) for sk_ in sks]
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1, ests
+
+    def reset_all():
+        for sk_ in sks:
+            sk_.reset(stream=stream)
+        torch.cuda.synchronize()
+
+    plain_pass()                      # warm-up (kernel loading, scratch, workspaces)
+    reset_all()
+    t_up_plain, t_est_plain, est_plain = plain_pass()
+    reset_all()
+    b = csk.Batch()
+    items = [(sk_, k, kk, None, False) for sk_, ks in zip(sks, keys) for k, kk in enumerate(ks)]
+    t0 = time.perf_counter()
+    b.capture(items, stream=stream)   # plans the work list (host) and captures the launch
+    t_plan = time.perf_counter() - t0
+    b.replay(stream=stream)
+    torch.cuda.synchronize()
+    b.estimate(sks, stream=stream)    # warm-up of the batched estimate workspace
+    reset_all()
+    t0 = time.perf_counter()
+    b.replay(stream=stream)
+    torch.cuda.synchronize()
+    t_up_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    est_batch = b.estimate(sks, stream=stream)
+    t_est_batch = time.perf_counter() - t0
+    stats = b.stats()
+    b.close()
+    identical = est_batch == est_plain
+    for sk_ in sks:
+        sk_.close()
+    return {"workload": f"{n_queries} chain/star queries, 2-6 relations, n log-uniform [1e3,1e6], "
+                        "m=2^10..2^16, d in {5,9}, Zipf(1.2) over 1e6, weights +1",
+            "tuples": tuples,
+            "plain_update_tuples_per_s": tuples / t_up_plain, "batched_update_tuples_per_s": tuples / t_up_batch,
+            "plain_estimates_per_s": n_queries / t_est_plain, "batched_estimates_per_s": n_queries / t_est_batch,
+            "update_speedup": t_up_plain / t_up_batch, "estimate_speedup": t_est_plain / t_est_batch,
+            "batched_plan_s": t_plan, "tasks": stats, "identical_estimates": identical}
+
+
+def bench_serving(n_queries, dev, seconds, rates):
+    """Live chain/star queries (m = 2^14..2^18, d = 9), Poisson arrivals of turnstile update
+    batches (2^U[10,18] tuples, 10% deletes of earlier batches, weights +-1) and estimate
+    requests at 1 estimate per 4 update batches; latency per request = completion - arrival."""
+    import random
+
+    import numpy as np
+    import torch
+
+    import paper_2402_15953_amd as csk
+    import workloads as W
+
+    specs = W.batched_queries(n_queries, seed=5, m_log2=(14, 18), d_choices=(9,), n_range=(1, 2))
+    pool = 1 << 18
+    pools = [[W.relation_keys(sp.graph, k, pool, "zipf", config=5000 + qi, s=1.1, D=10 ** 6,
+                              device=dev).to(torch.int32).contiguous() for k in range(sp.graph.n_rel)]
+             for qi, sp in enumerate(specs)]
+    ones = torch.ones(pool, dtype=torch.int64, device=dev)
+    minus = -ones
+    torch.cuda.synchronize()
+    srv = csk.Server(n_streams=3, max_batch_items=1024)
+    qids = [srv.add_query(sp.graph, sp.m, sp.d, sp.sketch_seed) for sp in specs]
+    # warm-up: one small update and one estimate per query (kernel loading, twiddle
+    # tables, estimate workspace), then reset to empty sketches
+    for qi, sp in enumerate(specs):
+        srv.submit_update(qids[qi], 0, pools[qi][0][:1024], ones[:1024], unit_weights=True)
+        srv.submit_estimate(qids[qi])
+        srv.submit_update(qids[qi], 0, pools[qi][0][:1024], minus[:1024], unit_weights=True)
+    srv.drain()
+    srv.poll(1 << 20)
+    levels = []
+    rng = random.Random(9)
+    inserted = {}
+    for rate in rates:
+        # warm-up burst, then the timed window
+        plan = []
+        t = 0.0
+        total_rate = rate * 1.25          # update batches + estimates (1:4)
+        while t < seconds:
+            t += rng.expovariate(total_rate)
+            q = rng.randrange(n_queries)
+            if rng.random() < 0.2:
+                plan.append((t, "E", q, 0, 0, 0, 0))
+                continue
+            k = rng.randrange(specs[q].graph.n_rel)
+            prev = inserted.get((q, k), [])
+            if prev and rng.random() < 0.1:
+                off, ln = prev.pop(rng.randrange(len(prev)))
+                plan.append((t, "U", q, k, off, ln, -1))
+            else:
+                ln = 1 << rng.randint(10, 18)
+                off = rng.randrange(0, pool - ln + 1)
+                inserted.setdefault((q, k), []).append((off, ln))
+                plan.append((t, "U", q, k, off, ln, 1))
+        srv.drain()
+        srv.poll(1 << 20)
+        t0 = time.perf_counter()
+        tuples = 0
+        busy = 0
+        for (ta, kind, q, k, off, ln, sign) in plan:
+            while time.perf_counter() - t0 < ta:
+                pass
+            try:
+                if kind == "U":
+                    srv.submit_update(qids[q], k, pools[q][k][off:off + ln],
+                                      (ones if sign > 0 else minus)[off:off + ln], unit_weights=True)
+                    tuples += ln
+                else:
+                    srv.submit_estimate(qids[q])
+            except csk.CsError:
+                busy += 1
+        srv.drain()
+        wall = time.perf_counter() - t0
+        comps = srv.poll(1 << 20)
+        lat_u = np.array([c["done_us"] - c["submit_us"] for c in comps if c["kind"] == 0]) / 1e3
+        lat_e = np.array([c["done_us"] - c["submit_us"] for c in comps if c["kind"] == 1]) / 1e3
+        n_e = int(len(lat_e))
+
+        def pct(a, p):
+            return float(np.percentile(a, p)) if len(a) else None
+
+        levels.append({"offered_update_batches_per_s": rate, "offered_estimates_per_s": rate / 4,
+                       "seconds": wall, "tuples_per_s": tuples / wall, "estimates_per_s": n_e / wall,
+                       "update_p50_ms": pct(lat_u, 50), "update_p99_ms": pct(lat_u, 99),
+                       "estimate_p50_ms": pct(lat_e, 50), "estimate_p99_ms": pct(lat_e, 99),
+                       "requests": len(comps), "refused": busy})
+    st = srv.stats()
+    srv.close()
+    return {"workload": f"{n_queries} live chain/star queries, m=2^14..2^18, d=9, Zipf(1.1) over 1e6, "
+                        "update batches 2^U[10,18] tuples, 10% deletes, estimate:update = 1:4, Poisson arrivals",
+            "resident_counter_bytes": int(st["used_bytes"]), "levels": levels,
+            "update_launches": int(st["update_launches"]), "estimate_batches": int(st["estimate_batches"])}
 
 
 def cpu_baseline(graph, keys, m, d, seed, n_sample):
@@ -183,7 +362,7 @@ def cpu_baseline(graph, keys, m, d, seed, n_sample):
 
     info = oracle.analyze(graph)
     co = oracle.draw_coefficients(seed, d, len(info.edges), info.n_comp)
-    host = [k[:n_sample].cpu().numpy().view(np.uint32) for k in keys]
+    host = [k[:n_sample].cpu().numpy().view(np.uint32).reshape(n_sample, -1) for k in keys]
     t0 = time.perf_counter()
     sks = [oracle.create_sketch(info, k, host[k], None, m, co) for k in range(graph.n_rel)]
     t1 = time.perf_counter()

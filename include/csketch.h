@@ -98,14 +98,15 @@ typedef enum cs_update_strategy {
     CS_UPDATE_LDS_PRIVATE = 2,    /* the d x m counters cut into LDS-sized segments;
                                      each workgroup accumulates one segment for one chunk
                                      of tuples in LDS, stores partial sums to the
-                                     handle's scratch buffer, and a reduce kernel adds
+                                     device's scratch pool, and a reduce kernel adds
                                      them into the counters */
     CS_UPDATE_WAVE_AGGREGATE = 3, /* equal buckets of one wavefront merged before the atomic */
-    CS_UPDATE_PARTITION = 4       /* sort by bucket: each tuple hashed once per repetition
-                                     into 16-bit records partitioned by (repetition, bucket
+    CS_UPDATE_PARTITION = 4       /* sort by bucket: identical tuples of a tile merged in
+                                     LDS, each distinct tuple hashed once per repetition
+                                     into 32-bit records partitioned by (repetition, bucket
                                      range) through LDS, then one workgroup per partition
                                      sums its records in LDS (segmented reduce); needs
-                                     weights NULL or CS_UPDATE_UNIT_WEIGHTS */
+                                     weights NULL or CS_UPDATE_UNIT_WEIGHTS, <= 2 columns */
 } cs_update_strategy;
 
 /* cs_update_ex flags */
@@ -155,13 +156,15 @@ const char *cs_last_error(void);
 /* ------------------------------------------------------------------ update (Alg. 2) */
 
 /* Stream n tuples of relation `rel` into its sketch (Alg. 2 for each repetition).
- * Calls on one handle must be ordered (one stream, or event dependencies): the
- * segmented strategy uses the handle's scratch buffer.
+ * Calls on one handle must be ordered (one stream, or event dependencies).  The
+ * segmented and partition strategies use one scratch buffer per device shared by all
+ * handles (reuse ordered by an event); it grows, once, to the largest (m, d) seen:
+ * the only allocation on this path.
  *   keys:    device, uint32 [n][a_rel] tuple-major; column c is the c-th attribute of
  *            `rel` in ascending attribute id.
  *   weights: device, int64 [n] frequency changes Delta (turnstile model, Sec. 2.1),
  *            or NULL for Delta = +1.
- * Asynchronous and ordered on `stream`; allocates nothing.  n = 0 is a no-op.
+ * Asynchronous and ordered on `stream`.  n = 0 is a no-op.
  * Errors: CS_EINVAL (bad handle, rel out of range, keys NULL with n > 0). */
 cs_status cs_update(cs_sketch *h, int32_t rel, const uint32_t *keys, const int64_t *weights,
                     uint64_t n, void *stream);

@@ -304,13 +304,7 @@ cs_status create_handle(const cs_graph *graph, uint32_t m, uint32_t d, uint64_t 
         delete hs;
         return fail(CS_ENOMEM, "coefficient allocation failed");
     }
-    h.scratch_bytes = with_scratch ? seg_scratch_bytes(m, (int32_t)d) : 0;
-    if (with_scratch && hipMalloc(&h.scratch, h.scratch_bytes) != hipSuccess) {
-        hipFree(h.counters);
-        hipFree(h.coef_dev);
-        delete hs;
-        return fail(CS_ENOMEM, "update scratch allocation failed");
-    }
+    (void)with_scratch;  // update scratch is a per-device pool shared by all handles
     if (hipMemcpy(h.coef_dev, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(h.counters, 0, n_ctr * sizeof(int64_t)) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
@@ -380,8 +374,8 @@ cs_status cs_update_ex(cs_sketch *hs, int32_t rel, const uint32_t *keys, const i
     a.m = h.m;
     a.d = (int32_t)h.d;
     a.plan = h.g.rel[rel];
-    a.scratch = h.scratch;
-    a.scratch_bytes = h.scratch_bytes;
+    a.scratch = nullptr;
+    a.scratch_bytes = 0;
     a.unit_weights = (flags & CS_UPDATE_UNIT_WEIGHTS) != 0;
     return launch_update(a, strategy, grid_blocks, static_cast<hipStream_t>(stream));
 }

@@ -226,13 +226,26 @@ struct QDesc {
 
 // ---------------------------------------------------------------- kernels
 
+// Flattened launches: block b belongs to item i with prefix[i] <= b < prefix[i + 1].
+__device__ __forceinline__ int find_item(const int64_t *__restrict__ prefix, int n, int64_t b)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // Sum of squares and of absolute values of each sketch vector (fp64), per block.
-__global__ __launch_bounds__(kThreads) void k_norms(const SkDesc *__restrict__ sks, double *partials)
+__global__ __launch_bounds__(kThreads) void k_norms(const SkDesc *__restrict__ sks, const int64_t *__restrict__ prefix,
+                                                    int n_items, double *partials)
 {
     __shared__ double sh[kThreads / 64];
-    const SkDesc S = sks[blockIdx.x];
-    const int blk = blockIdx.y;
-    if (blk >= S.nb) return;
+    const int item = find_item(prefix, n_items, blockIdx.x);
+    const SkDesc S = sks[item];
+    const int blk = (int)(blockIdx.x - prefix[item]);
     const int64_t m = (int64_t)1 << S.log2m;
     double s2 = 0.0, s1 = 0.0;
     for (int64_t j = (int64_t)blk * kThreads + threadIdx.x; j < m; j += (int64_t)S.nb * kThreads) {
@@ -251,12 +264,13 @@ __global__ __launch_bounds__(kThreads) void k_norms(const SkDesc *__restrict__ s
 
 // 128-bit inner product of c_0[t] and c_1[t], per block.
 __global__ __launch_bounds__(kThreads) void k_dot(const RepDesc *__restrict__ reps, const int32_t *__restrict__ idx,
+                                                  const int64_t *__restrict__ prefix, int n_items,
                                                   unsigned long long *partials)
 {
     __shared__ unsigned __int128 sh[kThreads];
-    const RepDesc D = reps[idx[blockIdx.x]];
-    const int blk = blockIdx.y;
-    if (blk >= D.nb) return;
+    const int item = find_item(prefix, n_items, blockIdx.x);
+    const RepDesc D = reps[idx[item]];
+    const int blk = (int)(blockIdx.x - prefix[item]);
     const int64_t m = (int64_t)1 << D.log2m;
     __int128 acc = 0;
     for (int64_t j = (int64_t)blk * kThreads + threadIdx.x; j < m; j += (int64_t)D.nb * kThreads)
@@ -279,12 +293,14 @@ __global__ __launch_bounds__(kThreads) void k_dot(const RepDesc *__restrict__ re
 // partials: sum Re(term), sum |Re|+|Im| of terms, max |C_k| per relation.
 __global__ __launch_bounds__(kThreads) void k_spec_f64(const double2 *__restrict__ Z,
                                                        const RepDesc *__restrict__ reps,
-                                                       const int32_t *__restrict__ idx, double *partials)
+                                                       const int32_t *__restrict__ idx,
+                                                       const int64_t *__restrict__ prefix, int n_items,
+                                                       double *partials)
 {
     __shared__ double sh[kThreads / 64];
-    const RepDesc D = reps[idx[blockIdx.x]];
-    const int blk = blockIdx.y;
-    if (blk >= D.nb) return;
+    const int item = find_item(prefix, n_items, blockIdx.x);
+    const RepDesc D = reps[idx[item]];
+    const int blk = (int)(blockIdx.x - prefix[item]);
     const int log2m = D.log2m;
     const uint32_t m = 1u << log2m;
     const int r = D.r;
@@ -337,14 +353,15 @@ __global__ __launch_bounds__(kThreads) void k_spec_f64(const double2 *__restrict
 __global__ __launch_bounds__(kThreads) void k_spec_mod(const uint32_t *__restrict__ N, int vpp,
                                                        const RepDesc *__restrict__ reps,
                                                        const int32_t *__restrict__ idx,
+                                                       const int64_t *__restrict__ prefix, int n_items,
                                                        const PrimeDev *__restrict__ primes, int64_t plane,
                                                        uint32_t *partials)
 {
     __shared__ uint32_t sh[kThreads];
-    const RepDesc D = reps[idx[blockIdx.x]];
-    const int blk = blockIdx.y;
-    if (blk >= D.nb) return;
-    const int pi = blockIdx.z;
+    const int item = find_item(prefix, n_items, blockIdx.x);
+    const RepDesc D = reps[idx[item]];
+    const int blk = (int)(blockIdx.x - prefix[item]);
+    const int pi = blockIdx.y;
     const PrimeDev P = primes[pi];
     const RingM R{P.p, P.pinv_neg};
     const int log2m = D.log2m;
@@ -1056,11 +1073,22 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
     const size_t o_rep = c.take(rd.size() * sizeof(RepDesc));
     const size_t o_sk = c.take(std::max<size_t>(1, sd.size()) * sizeof(SkDesc));
     const size_t o_dotidx = c.take(std::max<size_t>(1, dot_idx.size()) * sizeof(int32_t));
-    std::vector<size_t> o_gidx, o_gre, o_gim;
+    // block prefixes of the flattened launches
+    std::vector<int64_t> sk_pre(sd.size() + 1, 0), dot_pre(dot_idx.size() + 1, 0);
+    for (size_t i = 0; i < sd.size(); ++i) sk_pre[i + 1] = sk_pre[i] + sd[i].nb;
+    for (size_t i = 0; i < dot_idx.size(); ++i) dot_pre[i + 1] = dot_pre[i] + rd[dot_idx[i]].nb;
+    const size_t o_skpre = c.take(sk_pre.size() * sizeof(int64_t));
+    const size_t o_dotpre = c.take(dot_pre.size() * sizeof(int64_t));
+    std::vector<size_t> o_gidx, o_gre, o_gim, o_gpre;
+    std::vector<std::vector<int64_t>> g_pre;
     size_t z_total = 0;
     for (auto &kv : groups) {
         Group &G = kv.second;
         o_gidx.push_back(c.take(G.rep_idx.size() * sizeof(int32_t)));
+        std::vector<int64_t> pre(G.rep_idx.size() + 1, 0);
+        for (size_t i = 0; i < G.rep_idx.size(); ++i) pre[i + 1] = pre[i] + rd[G.rep_idx[i]].nb;
+        o_gpre.push_back(c.take(pre.size() * sizeof(int64_t)));
+        g_pre.push_back(std::move(pre));
         o_gre.push_back(c.take(G.re.size() * sizeof(void *)));
         o_gim.push_back(c.take(G.im.size() * sizeof(void *)));
         G.z_off = z_total;
@@ -1091,11 +1119,14 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
     std::memcpy(img.data() + o_rep, rd.data(), rd.size() * sizeof(RepDesc));
     if (!sd.empty()) std::memcpy(img.data() + o_sk, sd.data(), sd.size() * sizeof(SkDesc));
     if (!dot_idx.empty()) std::memcpy(img.data() + o_dotidx, dot_idx.data(), dot_idx.size() * sizeof(int32_t));
+    std::memcpy(img.data() + o_skpre, sk_pre.data(), sk_pre.size() * sizeof(int64_t));
+    std::memcpy(img.data() + o_dotpre, dot_pre.data(), dot_pre.size() * sizeof(int64_t));
     {
         int gi = 0;
         for (auto &kv : groups) {
             Group &G = kv.second;
             std::memcpy(img.data() + o_gidx[gi], G.rep_idx.data(), G.rep_idx.size() * sizeof(int32_t));
+            std::memcpy(img.data() + o_gpre[gi], g_pre[gi].data(), g_pre[gi].size() * sizeof(int64_t));
             std::memcpy(img.data() + o_gre[gi], G.re.data(), G.re.size() * sizeof(void *));
             std::memcpy(img.data() + o_gim[gi], G.im.data(), G.im.size() * sizeof(void *));
             ++gi;
@@ -1114,12 +1145,14 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
 
     // ---- stage 1
     if (!sd.empty()) {
-        hipLaunchKernelGGL(k_norms, dim3((unsigned)sd.size(), 64), dim3(kThreads), 0, s, d_sk, d_norms);
+        hipLaunchKernelGGL(k_norms, dim3((unsigned)sk_pre.back()), dim3(kThreads), 0, s, d_sk,
+                           reinterpret_cast<const int64_t *>(wb + o_skpre), (int)sd.size(), d_norms);
         CSK_HIP(hipGetLastError());
     }
     if (!dot_idx.empty()) {
-        hipLaunchKernelGGL(k_dot, dim3((unsigned)dot_idx.size(), 64), dim3(kThreads), 0, s, d_rep,
-                           reinterpret_cast<const int32_t *>(wb + o_dotidx), d_dot);
+        hipLaunchKernelGGL(k_dot, dim3((unsigned)dot_pre.back()), dim3(kThreads), 0, s, d_rep,
+                           reinterpret_cast<const int32_t *>(wb + o_dotidx),
+                           reinterpret_cast<const int64_t *>(wb + o_dotpre), (int)dot_idx.size(), d_dot);
         CSK_HIP(hipGetLastError());
     }
     {
@@ -1133,8 +1166,9 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
                                  reinterpret_cast<const int64_t *const *>(wb + o_gim[gi]), (int)G.re.size(), Z,
                                  G.log2m, reinterpret_cast<const double2 *>(tw), G.log2m, s);
             if (st != CS_OK) return st;
-            hipLaunchKernelGGL(k_spec_f64, dim3((unsigned)G.rep_idx.size(), 64), dim3(kThreads), 0, s, Z, d_rep,
-                               reinterpret_cast<const int32_t *>(wb + o_gidx[gi]), d_spec);
+            hipLaunchKernelGGL(k_spec_f64, dim3((unsigned)g_pre[gi].back()), dim3(kThreads), 0, s, Z, d_rep,
+                               reinterpret_cast<const int32_t *>(wb + o_gidx[gi]),
+                               reinterpret_cast<const int64_t *>(wb + o_gpre[gi]), (int)G.rep_idx.size(), d_spec);
             CSK_HIP(hipGetLastError());
             ++gi;
         }
@@ -1194,7 +1228,10 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
             }
             const int vpp = (int)ptrs.size();
             const size_t m = (size_t)1 << G.log2m;
-            const size_t tab_bytes = align_up(ptrs.size() * sizeof(void *)) + align_up(idx.size() * sizeof(int32_t));
+            std::vector<int64_t> mpre(idx.size() + 1, 0);
+            for (size_t i = 0; i < idx.size(); ++i) mpre[i + 1] = mpre[i] + rd[idx[i]].nb;
+            const size_t o_mpre = align_up(ptrs.size() * sizeof(void *)) + align_up(idx.size() * sizeof(int32_t));
+            const size_t tab_bytes = o_mpre + align_up(mpre.size() * sizeof(int64_t));
             void *mb = nullptr;
             if (hipMallocAsync(&mb, tab_bytes + (size_t)K * vpp * m * sizeof(uint32_t), s) != hipSuccess)
                 return fail(CS_ENOMEM, "modular workspace");
@@ -1203,6 +1240,7 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
             std::vector<char> mimg(tab_bytes, 0);
             std::memcpy(mimg.data(), ptrs.data(), ptrs.size() * sizeof(void *));
             std::memcpy(mimg.data() + align_up(ptrs.size() * sizeof(void *)), idx.data(), idx.size() * sizeof(int32_t));
+            std::memcpy(mimg.data() + o_mpre, mpre.data(), mpre.size() * sizeof(int64_t));
             CSK_HIP(hipMemcpyAsync(mbc, mimg.data(), tab_bytes, hipMemcpyHostToDevice, s));
             // updated mod_vec_base of these repetitions
             for (int q : needq)
@@ -1212,8 +1250,9 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
             st = ntt_forward(reinterpret_cast<const int64_t *const *>(mbc), vpp, K, N, G.log2m, primes, roots,
                              G.log2m, s);
             if (st != CS_OK) return st;
-            hipLaunchKernelGGL(k_spec_mod, dim3((unsigned)idx.size(), 64, K), dim3(kThreads), 0, s, N, vpp, d_rep,
-                               reinterpret_cast<const int32_t *>(mbc + align_up(ptrs.size() * sizeof(void *))), primes,
+            hipLaunchKernelGGL(k_spec_mod, dim3((unsigned)mpre.back(), K), dim3(kThreads), 0, s, N, vpp, d_rep,
+                               reinterpret_cast<const int32_t *>(mbc + align_up(ptrs.size() * sizeof(void *))),
+                               reinterpret_cast<const int64_t *>(mbc + o_mpre), (int)idx.size(), primes,
                                mod_plane, d_modp);
             CSK_HIP(hipGetLastError());
             // keep mimg alive until the copy is consumed

@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "csk_hash.h"
 #include "csk_internal.h"
@@ -419,7 +421,7 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
         return CS_OK;
     }
     if (strategy == CS_UPDATE_LDS_PRIVATE) {
-        if (!a.scratch) return fail(CS_EINVAL, "LDS-segmented update needs the handle's scratch buffer");
+        if (!a.scratch) return fail(CS_EINVAL, "LDS-segmented update needs a scratch buffer");
         // every Delta = +-1 and fewer than 2^31 tuples: int32 partial counters cannot overflow
         const bool narrow = (a.weights == nullptr || a.unit_weights) && a.n < (1ull << 31);
         const SegGeom sg = seg_geometry(a.m, a.d, narrow, a.scratch_bytes);
@@ -457,7 +459,7 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
         if constexpr (NC > 2) return fail(CS_EINVAL, "the partition strategy handles at most 2 key columns");
         if (a.weights && !a.unit_weights)
             return fail(CS_EINVAL, "the partition strategy needs weights NULL or flagged as +-1");
-        if (!a.scratch) return fail(CS_EINVAL, "the partition strategy needs the handle's scratch buffer");
+        if (!a.scratch) return fail(CS_EINVAL, "the partition strategy needs a scratch buffer");
         const PartGeom pg = part_geometry(a.m, a.d, a.scratch_bytes);
         if (pg.chunk == 0) return fail(CS_EINVAL, "scratch buffer too small for the partition strategy");
         uint32_t *rec = reinterpret_cast<uint32_t *>(a.scratch);
@@ -557,12 +559,30 @@ int auto_update_strategy(uint32_t m, int32_t d, uint64_t n, int n_cols, bool uni
     return CS_UPDATE_GLOBAL_ATOMIC;
 }
 
-cs_status launch_update(const UpdateArgs &a, int strategy, int grid_blocks, hipStream_t s)
+namespace {
+
+// One scratch buffer per device, shared by every handle's segmented / partition
+// updates.  Reuse is stream-ordered: each user waits for the previous user's event.
+struct ScratchPool {
+    std::mutex mu;
+    void *buf = nullptr;
+    size_t bytes = 0;
+    hipEvent_t last = nullptr;
+    bool used = false;
+};
+std::mutex g_pool_mu;
+std::map<int, ScratchPool *> g_pools;
+
+ScratchPool &pool_of(int device)
 {
-    if (a.n == 0) return CS_OK;
-    if (strategy == CS_UPDATE_AUTO)
-        strategy = auto_update_strategy(a.m, a.d, a.n, a.plan.n_cols, a.weights == nullptr || a.unit_weights,
-                                        a.scratch != nullptr);
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    ScratchPool *&p = g_pools[device];
+    if (!p) p = new ScratchPool();
+    return *p;
+}
+
+cs_status dispatch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStream_t s)
+{
     switch (a.plan.n_cols) {
         case 1: return launch_nc<1>(a, strategy, grid_blocks, s);
         case 2: return launch_nc<2>(a, strategy, grid_blocks, s);
@@ -574,6 +594,40 @@ cs_status launch_update(const UpdateArgs &a, int strategy, int grid_blocks, hipS
         case 8: return launch_nc<8>(a, strategy, grid_blocks, s);
         default: return fail(CS_EINVAL, "relation has an unsupported number of key columns");
     }
+}
+
+}  // namespace
+
+cs_status launch_update(const UpdateArgs &a_in, int strategy, int grid_blocks, hipStream_t s)
+{
+    if (a_in.n == 0) return CS_OK;
+    UpdateArgs a = a_in;
+    const bool unit = a.weights == nullptr || a.unit_weights;
+    if (strategy == CS_UPDATE_AUTO) strategy = auto_update_strategy(a.m, a.d, a.n, a.plan.n_cols, unit, true);
+    if (strategy != CS_UPDATE_LDS_PRIVATE && strategy != CS_UPDATE_PARTITION) return dispatch_nc(a, strategy, grid_blocks, s);
+    int dev = 0;
+    CSK_HIP(hipGetDevice(&dev));
+    ScratchPool &P = pool_of(dev);
+    std::lock_guard<std::mutex> lk(P.mu);
+    const size_t need = seg_scratch_bytes(a.m, a.d);
+    if (P.bytes < need) {
+        // grows to the largest (m, d) seen; the only allocation on the update path
+        CSK_HIP(hipDeviceSynchronize());
+        if (P.buf) hipFree(P.buf);
+        P.buf = nullptr;
+        P.bytes = 0;
+        if (hipMalloc(&P.buf, need) != hipSuccess) return fail(CS_ENOMEM, "update scratch allocation failed");
+        P.bytes = need;
+        P.used = false;
+    }
+    if (!P.last) CSK_HIP(hipEventCreateWithFlags(&P.last, hipEventDisableTiming));
+    if (P.used) CSK_HIP(hipStreamWaitEvent(s, P.last, 0));
+    a.scratch = P.buf;
+    a.scratch_bytes = P.bytes;
+    const cs_status st = dispatch_nc(a, strategy, grid_blocks, s);
+    CSK_HIP(hipEventRecord(P.last, s));
+    P.used = true;
+    return st;
 }
 
 }  // namespace csk
