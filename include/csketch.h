@@ -111,6 +111,10 @@ typedef enum cs_update_strategy {
 
 /* cs_update_ex flags */
 #define CS_UPDATE_UNIT_WEIGHTS 1  /* the caller guarantees every weight is +1 or -1 */
+#define CS_UPDATE_NO_COMPACT 2    /* segmented strategy: do not use the compacting kernel for
+                                     bucket-range segments (testing and tuning) */
+#define CS_UPDATE_NO_COUNTERS16 4 /* segmented strategy: do not use 16-bit LDS counters
+                                     (testing and tuning) */
 
 /* Estimate plans chosen at cs_create from the join graph. */
 typedef enum cs_plan_kind {
@@ -170,7 +174,9 @@ cs_status cs_update(cs_sketch *h, int32_t rel, const uint32_t *keys, const int64
                     uint64_t n, void *stream);
 
 /* Same with an explicit strategy and launch width (0 = automatic); for tests and
- * tuning.  CS_EINVAL if the strategy does not support this handle's m and d. */
+ * tuning.  grid_blocks is the number of workgroups for the atomic strategies and the
+ * number of tuple chunks for the segmented one (bounded by its scratch buffer).
+ * CS_EINVAL if the strategy does not support this handle's m and d. */
 cs_status cs_update_ex(cs_sketch *h, int32_t rel, const uint32_t *keys, const int64_t *weights,
                        uint64_t n, void *stream, int32_t strategy, int32_t grid_blocks,
                        int32_t flags);

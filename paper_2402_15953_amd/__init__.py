@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(HERE, "libcsketch.so")
 CS_OK, CS_EINVAL, CS_EGRAPH, CS_ENOMEM, CS_EDEVICE, CS_EBUSY, CS_ERANGE = range(7)
 UPDATE_AUTO, UPDATE_GLOBAL_ATOMIC, UPDATE_LDS_PRIVATE, UPDATE_WAVE_AGGREGATE, UPDATE_PARTITION = range(5)
 UPDATE_UNIT_WEIGHTS = 1
+UPDATE_NO_COMPACT = 2
+UPDATE_NO_COUNTERS16 = 4
 PLAN_DOT, PLAN_SPECTRAL, PLAN_GENERAL = 1, 2, 3
 
 EXPORTED = [
@@ -215,7 +217,7 @@ class Sketch:
         return {f: getattr(i, f) for f, _ in _Info._fields_}
 
     def update(self, rel: int, keys, weights=None, stream=None, strategy: int = UPDATE_AUTO, grid: int = 0,
-               unit_weights: bool = False):
+               unit_weights: bool = False, compact: bool = True, counters16: bool = True):
         """keys: device int32/uint32 tensor [n, a_rel] (or [n] for one column), contiguous;
         weights: device int64 tensor [n] or None; unit_weights: every weight is +-1."""
         import torch
@@ -230,7 +232,9 @@ class Sketch:
             wp = ctypes.c_void_p(weights.data_ptr())
         _check(lib().cs_update_ex(self._h, int(rel), ctypes.c_void_p(keys.data_ptr()), wp, int(n),
                                   _stream_ptr(stream), int(strategy), int(grid),
-                                  UPDATE_UNIT_WEIGHTS if unit_weights else 0))
+                                  (UPDATE_UNIT_WEIGHTS if unit_weights else 0)
+                                  | (0 if compact else UPDATE_NO_COMPACT)
+                                  | (0 if counters16 else UPDATE_NO_COUNTERS16)))
 
     def estimate(self, stream=None, reps: bool = False) -> dict:
         e = _Estimate()

@@ -377,6 +377,8 @@ cs_status cs_update_ex(cs_sketch *hs, int32_t rel, const uint32_t *keys, const i
     a.scratch = nullptr;
     a.scratch_bytes = 0;
     a.unit_weights = (flags & CS_UPDATE_UNIT_WEIGHTS) != 0;
+    a.compact = (flags & CS_UPDATE_NO_COMPACT) == 0;
+    a.counters16 = (flags & CS_UPDATE_NO_COUNTERS16) == 0;
     return launch_update(a, strategy, grid_blocks, static_cast<hipStream_t>(stream));
 }
 

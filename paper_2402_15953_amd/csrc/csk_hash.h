@@ -17,22 +17,24 @@ namespace csk {
 
 constexpr uint64_t kHashP = (1ull << 61) - 1;
 
-// One Horner step: returns r = v * x + a (mod p) in lazy form, r < 2^61 + 4.
-// Requires v < 2^62 and a < 2^61.
+// One Horner step: returns r = v * x + a (mod p) in redundant form.
+// Invariant: v < 2^63 and a < 2^61 give r < 2^61 + 2^34 + 8 + 2^61 < 2^63, so steps
+// chain without an intermediate fold; hcanon() reduces the final value.
 __device__ __forceinline__ uint64_t hstep(uint64_t v, uint32_t x, uint64_t a)
 {
     const uint64_t lo = (uint64_t)(uint32_t)v * (uint64_t)x;          // < 2^64
-    const uint64_t hi = (uint64_t)(uint32_t)(v >> 32) * (uint64_t)x;  // < 2^62
-    // v * x = t * 2^32 + (lo mod 2^32) with t = hi + (lo >> 32) < 2^62 + 2^32
+    const uint64_t hi = (uint64_t)(uint32_t)(v >> 32) * (uint64_t)x;  // < 2^63
+    // v * x = t * 2^32 + (lo mod 2^32) with t = hi + (lo >> 32) < 2^63 + 2^32
     const uint64_t t = hi + (lo >> 32);
-    // low 61 bits of v*x, and v*x >> 61
+    // (v * x mod 2^61) + (v * x >> 61) + a, using 2^61 = 1 (mod p)
     const uint64_t low61 = ((t & 0x1FFFFFFFull) << 32) | (lo & 0xFFFFFFFFull);
-    const uint64_t r = low61 + (t >> 29) + a;                          // < 2^62 + 2^34
-    return (r & kHashP) + (r >> 61);
+    return low61 + (t >> 29) + a;
 }
 
+// Canonical residue in [0, p) of a redundant value r < 2^63.
 __device__ __forceinline__ uint64_t hcanon(uint64_t r)
 {
+    r = (r & kHashP) + (r >> 61);  // < 2^61 + 4
     return r >= kHashP ? r - kHashP : r;
 }
 
@@ -89,5 +91,37 @@ __device__ __forceinline__ void hash_rep(const uint64_t *__restrict__ cf, const 
         }
     }
 }
+
+// Coefficients of one repetition for relations whose every key column takes part in
+// exactly one join (chains, stars): b0, b1, a0..a3 per column, held in registers.
+template <int NC>
+struct CoefE1 {
+    uint64_t b0[NC], b1[NC], a[NC][4];
+    __device__ __forceinline__ void load(const uint64_t *__restrict__ cf)
+    {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            b0[c] = cf[6 * c];
+            b1[c] = cf[6 * c + 1];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) a[c][k] = cf[6 * c + 2 + k];
+        }
+    }
+    __device__ __forceinline__ uint32_t bin(const uint32_t (&x)[NC]) const
+    {
+        uint32_t j = 0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) j += (uint32_t)hcanon(hstep(b1[c], x[c], b0[c]));
+        return j;
+    }
+    __device__ __forceinline__ uint32_t neg(const uint32_t (&x)[NC]) const
+    {
+        uint32_t s = 0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            s ^= (uint32_t)hcanon(hstep(hstep(hstep(a[c][3], x[c], a[c][2]), x[c], a[c][1]), x[c], a[c][0])) & 1u;
+        return s;
+    }
+};
 
 }  // namespace csk

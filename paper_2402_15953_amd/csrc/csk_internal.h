@@ -90,6 +90,8 @@ struct UpdateArgs {
     void *scratch;          // partial-sum buffer of the LDS-segmented strategy (may be null)
     size_t scratch_bytes;
     bool unit_weights;      // caller guarantees every weight is +1 or -1
+    bool compact = true;    // segmented strategy: compacting kernel for bucket-range segments
+    bool counters16 = true; // segmented strategy: 16-bit LDS counters when they hold a repetition
 };
 struct SegGeom {
     uint32_t R;        // counter cells per segment
@@ -97,6 +99,7 @@ struct SegGeom {
     int32_t chunks;    // tuple chunks (partial buffers)
 };
 SegGeom seg_geometry(uint32_t m, int32_t d, bool narrow, size_t scratch_bytes);
+SegGeom seg16_geometry(uint32_t m, int32_t d, size_t scratch_bytes);
 constexpr int kMaxPartRanges = 512;
 constexpr uint64_t kPartMaxChunk = 1ull << 21;
 struct PartGeom {

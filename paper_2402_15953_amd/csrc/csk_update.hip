@@ -119,7 +119,7 @@ __global__ __launch_bounds__(kBlock) void k_update_waveagg(const uint32_t *__res
 // chunk's partial sums; k_seg_reduce adds the partials of all chunks into the sketch.
 // A segment holds whole repetitions when m <= R, else a bucket range of one
 // repetition (its tuples' signs are then only needed for in-range buckets).
-template <int NC, typename CT>
+template <int NC, typename CT, bool E1>
 __global__ __launch_bounds__(kSegBlock) void k_update_seg(const uint32_t *__restrict__ keys,
                                                           const int64_t *__restrict__ weights, uint64_t n,
                                                           const uint64_t *__restrict__ coef, int32_t cpr,
@@ -139,14 +139,22 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg(const uint32_t *__rest
     __syncthreads();
     const uint64_t begin = (uint64_t)blockIdx.x * chunk;
     const uint64_t end = begin + chunk < n ? begin + chunk : n;
-    for (uint64_t i = begin + threadIdx.x; i < end; i += kSegBlock) {
-        uint32_t x[NC];
-        load_keys<NC>(keys, i, vec2, x);
-        const int64_t delta = weights ? weights[i] : 1;
-        for (int t = t0; t <= t1; ++t) {
-            const uint64_t *cf = coef + (size_t)t * cpr;
+    // repetition outermost: its coefficients stay in scalar registers over the tuples
+    for (int t = t0; t <= t1; ++t) {
+        const uint64_t *cf = coef + (size_t)t * cpr;
+        CoefE1<NC> K;
+        if constexpr (E1) K.load(cf);
+        const uint32_t row = (uint32_t)(((uint64_t)t << log2m) - cell0);  // may wrap; used mod 2^32
+        for (uint64_t i = begin + threadIdx.x; i < end; i += kSegBlock) {
+            uint32_t x[NC];
+            load_keys<NC>(keys, i, vec2, x);
             uint32_t j, neg;
-            if (whole) {
+            if constexpr (E1) {
+                j = K.bin(x) & (m - 1);
+                const uint32_t loc = row + j;
+                if (!whole && loc >= span) continue;  // bucket outside this segment
+                neg = K.neg(x);
+            } else if (whole) {
                 hash_rep<NC>(cf, plan, x, j, neg);
                 j &= m - 1;
             } else {
@@ -159,8 +167,7 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg(const uint32_t *__rest
                     cb += 2 + 4 * plan.n_edges[c];
                 }
                 j &= m - 1;
-                const uint64_t flat = ((uint64_t)t << log2m) + j;
-                if (flat < cell0 || flat >= cell1) continue;
+                if (row + j >= span) continue;
                 neg = 0;
                 const uint64_t *cs = cf;
 #pragma unroll
@@ -172,8 +179,8 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg(const uint32_t *__rest
                     }
                 }
             }
-            const uint64_t flat = ((uint64_t)t << log2m) + j;
-            const uint32_t loc = (uint32_t)(flat - cell0);
+            const uint32_t loc = row + j;
+            const int64_t delta = weights ? weights[i] : 1;
             if constexpr (sizeof(CT) == 4) {
                 const int32_t v32 = (int32_t)delta;  // +1, or +-1 with unit weights
                 atomicAdd(&s_c[loc], neg ? -v32 : v32);
@@ -186,6 +193,169 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg(const uint32_t *__rest
     __syncthreads();
     CT *out = partial + (size_t)blockIdx.x * cells + cell0;
     for (uint32_t e = threadIdx.x; e < span; e += kSegBlock) out[e] = s_c[e];
+}
+
+// Compacting variant for segments that hold a bucket range of one repetition (m > R),
+// one join per key column, Deltas +-1 (int32 counters).  Each wavefront hashes the bins
+// of 64 tuples, appends the in-range ones (keys, counter offset, sign of Delta) to its
+// LDS queue, and computes the sign hashes only when 64 are queued, so sign work is done
+// at full SIMD width instead of once per range.
+constexpr int kQCap = 128;  // queue entries per wavefront (< 64 pending + 64 pushed)
+
+template <int NC>
+__global__ __launch_bounds__(kSegBlock) void k_update_seg_compact(const uint32_t *__restrict__ keys,
+                                                                  const int64_t *__restrict__ weights,
+                                                                  uint64_t n, const uint64_t *__restrict__ coef,
+                                                                  int32_t cpr, uint32_t m, int32_t log2m,
+                                                                  int32_t d, uint32_t R, uint64_t chunk, bool vec2,
+                                                                  int32_t *partial)
+{
+    extern __shared__ __align__(16) unsigned char s_raw[];
+    int32_t *s_c = reinterpret_cast<int32_t *>(s_raw);                                // [R]
+    uint32_t *q_x = reinterpret_cast<uint32_t *>(s_raw + (size_t)R * sizeof(int32_t));  // [waves][NC][kQCap]
+    uint32_t *q_l = q_x + (kSegBlock / 64) * NC * kQCap;                              // [waves][kQCap]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t *qx = q_x + wave * NC * kQCap;
+    uint32_t *ql = q_l + wave * kQCap;
+    const uint64_t cells = (uint64_t)d << log2m;
+    const uint64_t cell0 = (uint64_t)blockIdx.y * R;
+    const int t = (int)(cell0 >> log2m);
+    const uint32_t off = (uint32_t)(cell0 - ((uint64_t)t << log2m));  // first bucket of the range
+    for (uint32_t e = threadIdx.x; e < R; e += kSegBlock) s_c[e] = 0;
+    __syncthreads();
+    CoefE1<NC> K;
+    K.load(coef + (size_t)t * cpr);
+    const uint64_t begin = (uint64_t)blockIdx.x * chunk;
+    const uint64_t end = begin + chunk < n ? begin + chunk : n;
+    uint32_t head = 0, count = 0;  // wave-uniform queue state
+    auto drain = [&](uint32_t k) {  // lanes < k take one queued entry each
+        if ((uint32_t)lane < k) {
+            const uint32_t slot = (head + lane) & (kQCap - 1);
+            uint32_t x[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) x[c] = qx[c * kQCap + slot];
+            const uint32_t l = ql[slot];
+            const int32_t v = (K.neg(x) ^ (l >> 31)) ? -1 : 1;
+            atomicAdd(&s_c[l & 0x7FFFFFFFu], v);
+        }
+        head = (head + k) & (kQCap - 1);
+        count -= k;
+    };
+    for (uint64_t base = begin + (uint64_t)wave * 64; base < end; base += kSegBlock) {
+        const uint64_t i = base + lane;
+        bool in = false;
+        uint32_t x[NC], loc = 0;
+        if (i < end) {
+            load_keys<NC>(keys, i, vec2, x);
+            const uint32_t j = (K.bin(x) & (m - 1)) - off;
+            if (j < R) {
+                in = true;
+                loc = j | ((weights && weights[i] < 0) ? 0x80000000u : 0u);
+            }
+        }
+        const uint64_t mask = __ballot(in);
+        if (in) {
+            const uint32_t pos = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+            const uint32_t slot = (head + count + pos) & (kQCap - 1);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) qx[c * kQCap + slot] = x[c];
+            ql[slot] = loc;
+        }
+        count += (uint32_t)__popcll(mask);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (count >= 64) drain(64);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (count > 0) drain(count);
+    __syncthreads();
+    int32_t *out = partial + (size_t)blockIdx.x * cells + cell0;
+    for (uint32_t e = threadIdx.x; e < R; e += kSegBlock) out[e] = s_c[e];
+}
+
+// 16-bit variant for Deltas +-1: two counters per 32-bit LDS word, each stored as
+// value + 2^15, so a whole repetition of m <= 2^16 buckets fits 128 KB of LDS.  A
+// counter that reaches 2^15 +- 2^14 hands 2^14 to the int64 sketch (global atomic) and
+// takes it off its 16-bit half by compare-and-swap, only while it is still beyond the
+// threshold; a half therefore stays within 2^15 +- (2^14 + in-flight adds) and never
+// carries into its neighbour, and value + spilled stays exact.
+constexpr uint32_t kBias16 = 0x8000u, kHi16 = 0xC000u, kLo16 = 0x4000u, kSpill16 = 0x4000u;
+
+__device__ __forceinline__ void spill16(uint32_t *w, uint32_t shift, unsigned long long *g)
+{
+    for (;;) {
+        const uint32_t old = *reinterpret_cast<volatile uint32_t *>(w);
+        const uint32_t h = (old >> shift) & 0xFFFFu;
+        uint32_t nw;
+        unsigned long long amt;
+        if (h >= kHi16) {
+            nw = old - (kSpill16 << shift);
+            amt = (unsigned long long)kSpill16;
+        } else if (h <= kLo16) {
+            nw = old + (kSpill16 << shift);
+            amt = (unsigned long long)0 - (unsigned long long)kSpill16;
+        } else {
+            return;
+        }
+        if (atomicCAS(w, old, nw) == old) atomicAdd(g, amt);
+    }
+}
+
+template <int NC, bool E1>
+__global__ __launch_bounds__(kSegBlock) void k_update_seg16(const uint32_t *__restrict__ keys,
+                                                            const int64_t *__restrict__ weights, uint64_t n,
+                                                            const uint64_t *__restrict__ coef, int32_t cpr,
+                                                            DevPlan plan, uint32_t m, int32_t log2m, int32_t d,
+                                                            uint32_t R, uint64_t chunk, bool vec2,
+                                                            int32_t *partial, unsigned long long *sketch)
+{
+    extern __shared__ __align__(16) unsigned char s_raw[];
+    uint32_t *s_w = reinterpret_cast<uint32_t *>(s_raw);  // [R / 2] words, two counters each
+    const uint64_t cells = (uint64_t)d << log2m;
+    const uint64_t cell0 = (uint64_t)blockIdx.y * R;
+    const uint64_t cell1 = cell0 + R < cells ? cell0 + R : cells;
+    const uint32_t span = (uint32_t)(cell1 - cell0);  // even: R and m are even
+    const int t0 = (int)(cell0 >> log2m);
+    const int t1 = (int)((cell1 - 1) >> log2m);
+    for (uint32_t e = threadIdx.x; e < span / 2; e += kSegBlock) s_w[e] = (kBias16 << 16) | kBias16;
+    __syncthreads();
+    const uint64_t begin = (uint64_t)blockIdx.x * chunk;
+    const uint64_t end = begin + chunk < n ? begin + chunk : n;
+    for (int t = t0; t <= t1; ++t) {
+        const uint64_t *cf = coef + (size_t)t * cpr;
+        CoefE1<NC> K;
+        if constexpr (E1) K.load(cf);
+        const uint32_t row = (uint32_t)(((uint64_t)t << log2m) - cell0);
+        for (uint64_t i = begin + threadIdx.x; i < end; i += kSegBlock) {
+            uint32_t x[NC];
+            load_keys<NC>(keys, i, vec2, x);
+            uint32_t j, neg;
+            if constexpr (E1) {
+                j = K.bin(x) & (m - 1);
+                neg = K.neg(x);
+            } else {
+                hash_rep<NC>(cf, plan, x, j, neg);
+                j &= m - 1;
+            }
+            if (weights && weights[i] < 0) neg ^= 1u;
+            const uint32_t loc = row + j;
+            const uint32_t shift = (loc & 1u) << 4;
+            uint32_t *w = &s_w[loc >> 1];
+            const uint32_t old = atomicAdd(w, neg ? (0xFFFFFFFFu << shift) : (1u << shift));
+            const uint32_t h = ((old >> shift) & 0xFFFFu) + (neg ? 0xFFFFFFFFu : 1u);
+            if (h >= kHi16 || h <= kLo16)
+                spill16(w, shift, sketch + ((uint64_t)t << log2m) + j);
+        }
+    }
+    __syncthreads();
+    int32_t *out = partial + (size_t)blockIdx.x * cells + cell0;
+    for (uint32_t e = threadIdx.x; e < span; e += kSegBlock) {
+        const uint32_t h = (s_w[e >> 1] >> ((e & 1u) << 4)) & 0xFFFFu;
+        out[e] = (int32_t)h - (int32_t)kBias16;
+    }
 }
 
 // sketch[cell] += sum over chunks of partial[chunk][cell] (int64, wrapping)
@@ -214,7 +384,9 @@ __global__ void k_seg_reduce(const CT *__restrict__ partial, int32_t C, uint64_t
 // (weights NULL) or +-1 (flag CS_UPDATE_UNIT_WEIGHTS).
 
 constexpr int kPartTile = 2048;
-constexpr int kPartPerThread = kPartTile / kBlock;  // 8
+constexpr int kPB = 512;                            // pass-1 workgroup
+constexpr int kPartPerThread = kPartTile / kPB;     // 4
+constexpr int kPAB = 1024;                          // pass-2 workgroup
 constexpr int kDedupSlots = 2 * kPartTile;          // open-addressing table, load <= 1/2
 static_assert(kDedupSlots < 0xFFFF, "slot codes are 16-bit, 0xFFFF marks the reserved slot");
 constexpr uint64_t kEmptyKey = ~0ull;
@@ -239,7 +411,7 @@ __device__ __forceinline__ void unpack_key(uint64_t k, uint32_t (&x)[NC])
 // record: bucket offset inside its range (13 bits) and signed sum of Deltas times the
 // sign (19 bits; |sum| <= kPartTile).
 template <int NC>
-__global__ __launch_bounds__(kBlock) void k_part_hash(const uint32_t *__restrict__ keys,
+__global__ __launch_bounds__(kPB) void k_part_hash(const uint32_t *__restrict__ keys,
                                                       const int64_t *__restrict__ weights, uint64_t n,
                                                       const uint64_t *__restrict__ coef, int32_t cpr,
                                                       DevPlan plan, uint32_t m, int32_t d, int32_t log2R,
@@ -255,7 +427,7 @@ __global__ __launch_bounds__(kBlock) void k_part_hash(const uint32_t *__restrict
 
     const uint64_t i0 = (uint64_t)blockIdx.x * kPartTile;
     const int nv = (int)(n - i0 < (uint64_t)kPartTile ? n - i0 : (uint64_t)kPartTile);
-    for (int e = threadIdx.x; e <= kDedupSlots; e += kBlock) {
+    for (int e = threadIdx.x; e <= kDedupSlots; e += kPB) {
         s_key[e] = kEmptyKey;
         s_w[e] = 0;
     }
@@ -264,7 +436,7 @@ __global__ __launch_bounds__(kBlock) void k_part_hash(const uint32_t *__restrict
     // ---- merge identical tuples
 #pragma unroll
     for (int k = 0; k < kPartPerThread; ++k) {
-        const int e = threadIdx.x + k * kBlock;
+        const int e = threadIdx.x + k * kPB;
         if (e < nv) {
             uint32_t xx[NC];
             load_keys<NC>(keys, i0 + e, vec2, xx);
@@ -287,7 +459,7 @@ __global__ __launch_bounds__(kBlock) void k_part_hash(const uint32_t *__restrict
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e <= kDedupSlots; e += kBlock) {
+    for (int e = threadIdx.x; e <= kDedupSlots; e += kPB) {
         const bool used = e == kDedupSlots ? true : s_key[e] != kEmptyKey;
         if (used && s_w[e] != 0) s_list[atomicAdd(&s_nlist, 1)] = (uint16_t)(e < kDedupSlots ? e : 0xFFFF);
     }
@@ -297,7 +469,7 @@ __global__ __launch_bounds__(kBlock) void k_part_hash(const uint32_t *__restrict
     int32_t wv[kPartPerThread];
 #pragma unroll
     for (int k = 0; k < kPartPerThread; ++k) {
-        const int l = threadIdx.x + k * kBlock;
+        const int l = threadIdx.x + k * kPB;
         wv[k] = 0;
         if (l < u) {
             const uint32_t code = s_list[l];
@@ -316,7 +488,7 @@ __global__ __launch_bounds__(kBlock) void k_part_hash(const uint32_t *__restrict
     // ---- per repetition: hash, counting sort by bucket range, coalesced store
     const uint32_t rmask = (1u << log2R) - 1;
     for (int t = 0; t < d; ++t) {
-        for (int r = threadIdx.x; r <= ranges; r += kBlock) s_cnt[r] = 0;
+        for (int r = threadIdx.x; r <= ranges; r += kPB) s_cnt[r] = 0;
         __syncthreads();
         const uint64_t *cf = coef + (size_t)t * cpr;
         uint32_t rec[kPartPerThread];
@@ -324,7 +496,7 @@ __global__ __launch_bounds__(kBlock) void k_part_hash(const uint32_t *__restrict
         uint16_t pos[kPartPerThread];
 #pragma unroll
         for (int k = 0; k < kPartPerThread; ++k) {
-            const int l = threadIdx.x + k * kBlock;
+            const int l = threadIdx.x + k * kPB;
             if (l < u) {
                 uint32_t j, neg;
                 hash_rep<NC>(cf, plan, x[k], j, neg);
@@ -355,42 +527,82 @@ __global__ __launch_bounds__(kBlock) void k_part_hash(const uint32_t *__restrict
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kPartPerThread; ++k) {
-            const int l = threadIdx.x + k * kBlock;
+            const int l = threadIdx.x + k * kPB;
             if (l < u) s_rec[s_cnt[rng[k]] + pos[k]] = rec[k];
         }
         int32_t *tb = tab + ((size_t)blockIdx.x * d + t) * (ranges + 1);
-        for (int r = threadIdx.x; r <= ranges; r += kBlock) tb[r] = s_cnt[r];
+        for (int r = threadIdx.x; r <= ranges; r += kPB) tb[r] = s_cnt[r];
         __syncthreads();
         uint32_t *o = rec_out + ((size_t)blockIdx.x * d + t) * kPartTile;
-        for (int e = threadIdx.x; e < u; e += kBlock) o[e] = s_rec[e];
+        for (int e = threadIdx.x; e < u; e += kPB) o[e] = s_rec[e];
         __syncthreads();
     }
 }
 
 // Block (range r, repetition t): sum the records of every tile, add into the sketch.
-__global__ __launch_bounds__(kBlock) void k_part_accum(const uint32_t *__restrict__ rec,
-                                                       const int32_t *__restrict__ tab, int32_t tiles,
-                                                       int32_t d, int32_t ranges, int32_t log2R, uint32_t m,
-                                                       uint64_t *sketch)
+// The tiles' run bounds are loaded in parallel first; the records of all tiles are then
+// walked as one flattened index space, four independent loads per thread in flight.
+__global__ __launch_bounds__(kPAB) void k_part_accum(const uint32_t *__restrict__ rec,
+                                                     const int32_t *__restrict__ tab, int32_t tiles,
+                                                     int32_t d, int32_t ranges, int32_t log2R, uint32_t m,
+                                                     uint64_t *sketch)
 {
-    extern __shared__ int32_t s_acc[];
+    extern __shared__ int32_t s_dyn[];
+    int32_t *s_acc = s_dyn;                    // [R]
+    int32_t *s_pre = s_dyn + (1 << log2R);     // [tiles + 1] prefix of run lengths
+    int32_t *s_beg = s_pre + tiles + 1;        // [tiles]
     const int r = blockIdx.x, t = blockIdx.y;
     const int R = 1 << log2R;
-    for (int e = threadIdx.x; e < R; e += kBlock) s_acc[e] = 0;
-    __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int tile = wave; tile < tiles; tile += kBlock / 64) {
+    for (int e = threadIdx.x; e < R; e += kPAB) s_acc[e] = 0;
+    for (int tile = threadIdx.x; tile < tiles; tile += kPAB) {
         const int32_t *tb = tab + ((size_t)tile * d + t) * (ranges + 1);
         const int beg = tb[r], end = tb[r + 1];
-        const uint32_t *base = rec + ((size_t)tile * d + t) * kPartTile;
-        for (int e = beg + lane; e < end; e += 64) {
-            const uint32_t v = base[e];
-            atomicAdd(&s_acc[v & 0x1FFFu], (int32_t)v >> 13);
+        s_beg[tile] = beg;
+        s_pre[tile + 1] = end - beg;
+    }
+    if (threadIdx.x == 0) s_pre[0] = 0;
+    __syncthreads();
+    // inclusive scan of run lengths (tiles <= kPartMaxChunk / kPartTile), one wave
+    if (threadIdx.x < 64) {
+        int carry = 0;
+        for (int base = 1; base <= tiles; base += 64) {
+            const int i = base + (int)threadIdx.x;
+            int v = i <= tiles ? s_pre[i] : 0;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(v, o, 64);
+                if ((int)threadIdx.x >= o) v += y;
+            }
+            if (i <= tiles) s_pre[i] = carry + v;
+            carry += __shfl(v, 63, 64);
         }
     }
     __syncthreads();
+    const int total = s_pre[tiles];
+    for (int g0 = threadIdx.x; g0 < total; g0 += 4 * kPAB) {
+        uint32_t v[4];
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int g = g0 + u * kPAB;
+            ok[u] = g < total;
+            v[u] = 0;
+            if (ok[u]) {
+                int lo = 0, hi = tiles - 1;  // tile with s_pre[tile] <= g < s_pre[tile + 1]
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_pre[mid] <= g) lo = mid;
+                    else hi = mid - 1;
+                }
+                v[u] = rec[((size_t)lo * d + t) * kPartTile + s_beg[lo] + (g - s_pre[lo])];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (ok[u]) atomicAdd(&s_acc[v[u] & 0x1FFFu], (int32_t)v[u] >> 13);
+    }
+    __syncthreads();
     uint64_t *out = sketch + (size_t)t * m + ((size_t)r << log2R);
-    for (int e = threadIdx.x; e < R; e += kBlock) {
+    for (int e = threadIdx.x; e < R; e += kPAB) {
         const int32_t v = s_acc[e];
         if (v) out[e] += (uint64_t)(int64_t)v;
     }
@@ -424,30 +636,72 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
         if (!a.scratch) return fail(CS_EINVAL, "LDS-segmented update needs a scratch buffer");
         // every Delta = +-1 and fewer than 2^31 tuples: int32 partial counters cannot overflow
         const bool narrow = (a.weights == nullptr || a.unit_weights) && a.n < (1ull << 31);
-        const SegGeom sg = seg_geometry(a.m, a.d, narrow, a.scratch_bytes);
-        const uint64_t chunk = (a.n + sg.chunks - 1) / sg.chunks;
         const uint64_t cells = (uint64_t)a.d * a.m;
+        // grid_blocks > 0 fixes the number of tuple chunks (bounded by the scratch buffer)
+        auto chunks_for = [&](int32_t c, size_t elem) -> int32_t {
+            if (grid_blocks <= 0) return c;
+            const uint64_t cap = std::max<uint64_t>(1, a.scratch_bytes / (cells * elem));
+            return (int32_t)std::min<uint64_t>((uint64_t)grid_blocks, std::min<uint64_t>(cap, 4096));
+        };
+        SegGeom sg = seg_geometry(a.m, a.d, narrow, a.scratch_bytes);
+        sg.chunks = chunks_for(sg.chunks, narrow ? 4 : 8);
+        const uint64_t chunk = (a.n + sg.chunks - 1) / sg.chunks;
         dim3 grid((unsigned)sg.chunks, (unsigned)sg.segments);
         const size_t lds = (size_t)sg.R * (narrow ? 4 : 8);
         int log2m = 0;
         while ((1u << log2m) < a.m) ++log2m;
-        if (narrow) {
-            CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_update_seg<NC, int32_t>),
+        bool e1 = true;
+        for (int c = 0; c < a.plan.n_cols; ++c) e1 = e1 && a.plan.n_edges[c] == 1;
+        auto launch = [&](auto kern, auto *part) -> cs_status {
+            CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-            hipLaunchKernelGGL((k_update_seg<NC, int32_t>), grid, dim3(kSegBlock), lds, s, a.keys, a.weights, a.n,
-                               a.coef, a.plan.coef_per_rep, plan, a.m, log2m, a.d, sg.R, chunk, vec2,
-                               reinterpret_cast<int32_t *>(a.scratch));
+            hipLaunchKernelGGL(kern, grid, dim3(kSegBlock), lds, s, a.keys, a.weights, a.n, a.coef,
+                               a.plan.coef_per_rep, plan, a.m, log2m, a.d, sg.R, chunk, vec2, part);
+            CSK_HIP(hipGetLastError());
+            return CS_OK;
+        };
+        cs_status st;
+        if (narrow && a.m <= (1u << 16) && a.m > (1u << 15) && a.counters16) {
+            // 16-bit LDS counters: a whole repetition per workgroup
+            SegGeom g16 = seg16_geometry(a.m, a.d, a.scratch_bytes);
+            g16.chunks = chunks_for(g16.chunks, 4);
+            const uint64_t chunk16 = (a.n + g16.chunks - 1) / g16.chunks;
+            dim3 grid16((unsigned)g16.chunks, (unsigned)g16.segments);
+            const size_t lds16 = (size_t)g16.R * 2;
+            int32_t *part = reinterpret_cast<int32_t *>(a.scratch);
+            auto kern = e1 ? &k_update_seg16<NC, true> : &k_update_seg16<NC, false>;
+            CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds16));
+            hipLaunchKernelGGL(kern, grid16, dim3(kSegBlock), lds16, s, a.keys, a.weights, a.n, a.coef,
+                               a.plan.coef_per_rep, plan, a.m, log2m, a.d, g16.R, chunk16, vec2, part,
+                               reinterpret_cast<unsigned long long *>(a.sketch));
+            CSK_HIP(hipGetLastError());
+            hipLaunchKernelGGL(k_seg_reduce<int32_t>, dim3((unsigned)std::min<uint64_t>((cells + 255) / 256, 8192)),
+                               dim3(256), 0, s, reinterpret_cast<const int32_t *>(a.scratch), g16.chunks, cells,
+                               a.sketch);
+        } else if (narrow && e1 && sg.R < a.m && NC <= 2 && a.compact) {
+            // bucket-range segments: compacting kernel (queue after the counters in LDS)
+            int32_t *part = reinterpret_cast<int32_t *>(a.scratch);
+            const size_t lds_c = (size_t)sg.R * 4 + (size_t)(kSegBlock / 64) * (NC + 1) * kQCap * 4;
+            CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_update_seg_compact<NC>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_c));
+            hipLaunchKernelGGL(k_update_seg_compact<NC>, grid, dim3(kSegBlock), lds_c, s, a.keys, a.weights, a.n,
+                               a.coef, a.plan.coef_per_rep, a.m, log2m, a.d, sg.R, chunk, vec2, part);
             CSK_HIP(hipGetLastError());
             hipLaunchKernelGGL(k_seg_reduce<int32_t>, dim3((unsigned)std::min<uint64_t>((cells + 255) / 256, 8192)),
                                dim3(256), 0, s, reinterpret_cast<const int32_t *>(a.scratch), sg.chunks, cells,
                                a.sketch);
+        } else if (narrow) {
+            int32_t *part = reinterpret_cast<int32_t *>(a.scratch);
+            st = e1 ? launch(&k_update_seg<NC, int32_t, true>, part) : launch(&k_update_seg<NC, int32_t, false>, part);
+            if (st != CS_OK) return st;
+            hipLaunchKernelGGL(k_seg_reduce<int32_t>, dim3((unsigned)std::min<uint64_t>((cells + 255) / 256, 8192)),
+                               dim3(256), 0, s, reinterpret_cast<const int32_t *>(a.scratch), sg.chunks, cells,
+                               a.sketch);
         } else {
-            CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_update_seg<NC, int64_t>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-            hipLaunchKernelGGL((k_update_seg<NC, int64_t>), grid, dim3(kSegBlock), lds, s, a.keys, a.weights, a.n,
-                               a.coef, a.plan.coef_per_rep, plan, a.m, log2m, a.d, sg.R, chunk, vec2,
-                               reinterpret_cast<int64_t *>(a.scratch));
-            CSK_HIP(hipGetLastError());
+            int64_t *part = reinterpret_cast<int64_t *>(a.scratch);
+            st = e1 ? launch(&k_update_seg<NC, int64_t, true>, part) : launch(&k_update_seg<NC, int64_t, false>, part);
+            if (st != CS_OK) return st;
             hipLaunchKernelGGL(k_seg_reduce<int64_t>, dim3((unsigned)std::min<uint64_t>((cells + 255) / 256, 8192)),
                                dim3(256), 0, s, reinterpret_cast<const int64_t *>(a.scratch), sg.chunks, cells,
                                a.sketch);
@@ -464,17 +718,18 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
         if (pg.chunk == 0) return fail(CS_EINVAL, "scratch buffer too small for the partition strategy");
         uint32_t *rec = reinterpret_cast<uint32_t *>(a.scratch);
         int32_t *tab = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(a.scratch) + pg.tab_offset);
-        const size_t lds = ((size_t)1 << pg.log2R) * sizeof(int32_t);
+        const size_t max_tiles = pg.chunk / kPartTile;
+        const size_t lds = (((size_t)1 << pg.log2R) + 2 * max_tiles + 1) * sizeof(int32_t);
         for (uint64_t base = 0; base < a.n; base += pg.chunk) {
             const uint64_t cn = a.n - base < pg.chunk ? a.n - base : pg.chunk;
             const int tiles = (int)((cn + kPartTile - 1) / kPartTile);
             const uint32_t *kb = a.keys + base * a.plan.n_cols;
             const bool v2 = NC == 2 && ((uintptr_t)kb % 8) == 0;
-            hipLaunchKernelGGL(k_part_hash<NC>, dim3(tiles), dim3(kBlock), 0, s, kb,
+            hipLaunchKernelGGL(k_part_hash<NC>, dim3(tiles), dim3(kPB), 0, s, kb,
                                a.weights ? a.weights + base : nullptr, cn, a.coef, a.plan.coef_per_rep, plan, a.m,
                                a.d, pg.log2R, pg.ranges, v2, rec, tab);
             CSK_HIP(hipGetLastError());
-            hipLaunchKernelGGL(k_part_accum, dim3(pg.ranges, a.d), dim3(kBlock), lds, s, rec, tab, tiles, a.d,
+            hipLaunchKernelGGL(k_part_accum, dim3(pg.ranges, a.d), dim3(kPAB), lds, s, rec, tab, tiles, a.d,
                                pg.ranges, pg.log2R, a.m, a.sketch);
             CSK_HIP(hipGetLastError());
         }
@@ -497,11 +752,25 @@ SegGeom seg_geometry(uint32_t m, int32_t d, bool narrow, size_t scratch_bytes)
     // rounds when there are few segments), bounded by the scratch buffer
     int32_t C = 512 / g.segments;
     if (C < 1) C = 1;
-    const uint64_t per_chunk = cells * (narrow ? 4 : 8);
-    const int32_t cap = (int32_t)std::max<uint64_t>(1, scratch_bytes / per_chunk);
-    if (C > cap) C = cap;
+    const uint64_t cap = std::max<uint64_t>(1, scratch_bytes / (cells * (narrow ? 4 : 8)));
+    if ((uint64_t)C > cap) C = (int32_t)cap;
     if (C > 64) C = 64;
+    g.chunks = C;
+    return g;
+}
+
+SegGeom seg16_geometry(uint32_t m, int32_t d, size_t scratch_bytes)
+{
+    SegGeom g{};
+    g.R = 1u << 16;  // 16-bit counters in 128 KB of LDS
+    const uint64_t cells = (uint64_t)d * m;
+    if (m <= g.R) g.R = (g.R / m) * m;
+    g.segments = (int32_t)((cells + g.R - 1) / g.R);
+    int32_t C = 512 / g.segments;
     if (C < 1) C = 1;
+    const uint64_t cap = std::max<uint64_t>(1, scratch_bytes / (cells * 4));
+    if ((uint64_t)C > cap) C = (int32_t)cap;
+    if (C > 64) C = 64;
     g.chunks = C;
     return g;
 }
@@ -539,6 +808,10 @@ size_t seg_scratch_bytes(uint32_t m, int32_t d)
     for (int narrow = 0; narrow < 2; ++narrow) {
         SegGeom g = seg_geometry(m, d, narrow != 0, (size_t)-1);
         best = std::max<size_t>(best, (size_t)g.chunks * cells * (narrow ? 4 : 8));
+    }
+    {
+        const SegGeom g16 = seg16_geometry(m, d, (size_t)-1);
+        best = std::max<size_t>(best, (size_t)g16.chunks * cells * 4);
     }
     // the partition strategy's chunk of kPartMaxChunk tuples
     const PartGeom pg = part_geometry(m, d, (size_t)-1);

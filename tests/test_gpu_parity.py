@@ -24,12 +24,13 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _run_gpu(graph, rels, weights, m, d, seed, strategy=0, grid=0, unit=False):
+def _run_gpu(graph, rels, weights, m, d, seed, strategy=0, grid=0, unit=False, compact=True, counters16=True):
     sk = csk.Sketch(graph, m, d, seed)
     for k, keys in enumerate(rels):
         kd = to_device_keys(keys)
         wd = None if weights is None else torch.from_numpy(weights[k]).cuda()
-        sk.update(k, kd, wd, strategy=strategy, grid=grid, unit_weights=unit)
+        sk.update(k, kd, wd, strategy=strategy, grid=grid, unit_weights=unit, compact=compact,
+                  counters16=counters16)
     torch.cuda.synchronize()
     return sk
 
@@ -110,6 +111,56 @@ def _weights(kind, graph, n):
     if kind == "pm1":
         return [W.turnstile_weights(n, 0.1, seed=k).numpy() for k in range(graph.n_rel)]
     return [W.random_weights(n, -2 ** 62, 2 ** 62, seed=50 + k).numpy() for k in range(graph.n_rel)]
+
+
+@pytest.mark.parametrize("case", range(len(SKETCH_CASES)))
+@pytest.mark.parametrize("compact", [False, True])
+def test_sketch_segmented_kernel_variants(case, compact):
+    """The segmented strategy with 16-bit counters off, with and without the compacting
+    kernel for bucket-range segments: every kernel variant must give the same counters."""
+    graph, n, m, d, dist, D, wk = SKETCH_CASES[case]
+    _say("sketch variant", case, graph.name, n, m, d, "compact", compact)
+    rels = _rels(graph, n, dist, D, config=90 + case)
+    weights = _weights(wk, graph, n)
+    info, co, ref = oracle_sketches(graph, rels, weights, m, d, 1000 + case)
+    sk = _run_gpu(graph, rels, weights, m, d, 1000 + case, strategy=2, unit=(wk == "pm1"), compact=compact,
+                  counters16=False)
+    for k in range(graph.n_rel):
+        assert np.array_equal(sk.read_sketch(k), ref[k]), k
+    sk.close()
+
+
+@pytest.mark.parametrize("kind", ["all_plus", "all_minus", "alternating", "two_hot"])
+def test_counters16_spill(kind):
+    """16-bit LDS counters hand multiples of 2^14 to the int64 sketch; counters driven far
+    past +-2^15 in either direction, or swinging across the spill thresholds, stay exact."""
+    graph = W.single_join()
+    n, m, d, seed = 400_000, 1 << 16, 5, 77
+    rng = np.random.default_rng(9)
+    if kind == "two_hot":
+        k0 = rng.choice(np.array([3, 11], dtype=np.uint32), size=(n, 1))
+    else:
+        k0 = np.full((n, 1), 12345, dtype=np.uint32)
+    k1 = rng.integers(0, 1000, size=(n, 1), dtype=np.uint32)
+    if kind == "all_plus":
+        w0 = np.ones(n, dtype=np.int64)
+    elif kind == "all_minus":
+        w0 = -np.ones(n, dtype=np.int64)
+    elif kind == "alternating":
+        # runs of 30 000 of one sign, then the other: the counter swings across both thresholds
+        w0 = np.where((np.arange(n) // 30_000) % 2 == 0, 1, -1).astype(np.int64)
+    else:
+        w0 = np.where(rng.random(n) < 0.8, 1, -1).astype(np.int64)
+    w1 = -np.ones(n, dtype=np.int64)
+    rels, weights = [k0, k1], [w0, w1]
+    _say("counters16", kind, n, m, d)
+    info, co, ref = oracle_sketches(graph, rels, weights, m, d, seed)
+    # grid=1: one chunk, so one workgroup per repetition sees every tuple
+    for c16, grid in ((True, 1), (True, 3), (True, 0), (False, 1)):
+        sk = _run_gpu(graph, rels, weights, m, d, seed, strategy=2, grid=grid, unit=True, counters16=c16)
+        for k in range(2):
+            assert np.array_equal(sk.read_sketch(k), ref[k]), (c16, grid, k)
+        sk.close()
 
 
 @pytest.mark.parametrize("case", range(len(SKETCH_CASES)))
