@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-tuples", type=int, default=1 << 22, help="oracle sample per relation")
     ap.add_argument("--strategy", type=int, default=0)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a device copy of this many bytes (counter calibration) and exit")
     ap.add_argument("--batch-queries", type=int, default=4096,
                     help="batched section: chain/star queries (0 skips the section)")
     ap.add_argument("--serve-queries", type=int, default=256, help="serving section: live queries (0 skips)")
@@ -51,6 +53,53 @@ def parse():
     ap.add_argument("--serve-rates", type=str, default="250,1000,4000,16000",
                     help="serving section: offered update-batch arrival rates (batches/s)")
     return ap.parse_args()
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "update_seg16_chain3_1e7_m65536_d9_traffic.md")
+KERNEL_SOURCES = ["csk_update.hip", "csk_hash.h", "csk_internal.h"]
+
+
+def kernel_source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2402_15953_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(strategy: int):
+    """HBM bytes per launch of the dominant kernel from the committed FETCH_SIZE and
+    WRITE_SIZE counter summary (scaled by a copy kernel of known size), or None when the
+    summary is missing, was taken for another strategy, or the kernel sources changed
+    since the counters were taken."""
+    if strategy != 0 or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    fields = {}
+    with open(TRAFFIC_PROFILE) as fh:
+        for line in fh:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(nbytes: int):
+    """A plain device copy of known size (the scale for the FETCH_SIZE / WRITE_SIZE
+    counters): five launches of dst.copy_(src) on nbytes."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": src.numel() * 4, "launches": 5}), flush=True)
 
 
 def horner_steps_per_tuple(graph, k, d):
@@ -68,6 +117,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus %d is not supported" % args.gpus}))
         print("bench.py runs on exactly one GPU (no multi-GPU path in this build)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe > 0:
+        copy_probe(args.copy_probe)
+        return
 
     import numpy as np
     import torch
@@ -95,6 +147,7 @@ def main():
 
     n_rel = graph.n_rel
     ev = {k: [] for k in range(n_rel)}
+    kev = {k: [] for k in range(n_rel)}   # around the hashing kernel alone (cs_update_timed)
     est_ev = []
 
     def step(record):
@@ -103,11 +156,15 @@ def main():
             if record:
                 a = torch.cuda.Event(enable_timing=True)
                 b = torch.cuda.Event(enable_timing=True)
+                ka = torch.cuda.Event(enable_timing=True)
+                kb = torch.cuda.Event(enable_timing=True)
                 a.record(stream)
-            sk.update(k, keys[k], None, stream=stream, strategy=args.strategy)
-            if record:
+                sk.update(k, keys[k], None, stream=stream, strategy=args.strategy, timing=(ka, kb))
                 b.record(stream)
                 ev[k].append((a, b))
+                kev[k].append((ka, kb))
+            else:
+                sk.update(k, keys[k], None, stream=stream, strategy=args.strategy)
         if record:
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
@@ -135,14 +192,17 @@ def main():
     est_ms = sum(a.elapsed_time(b) for a, b in est_ev) / len(est_ev)
     upd_total_ms = sum(upd_ms.values())
 
-    # dominant kernel: the slowest relation's update launch
-    kdom = max(upd_ms, key=upd_ms.get)
+    kern_ms = {k: sum(a.elapsed_time(b) for a, b in kev[k]) / len(kev[k]) for k in range(n_rel)}
+
+    # dominant kernel: the slowest hashing kernel (one launch per relation and step)
+    kdom = max(kern_ms, key=kern_ms.get)
     a_dom = len(graph.columns(kdom))
     bytes_dom = n * 4 * a_dom                       # uint32 keys, weights NULL
     steps_dom = n * horner_steps_per_tuple(graph, kdom, d)
-    dur_s = upd_ms[kdom] / 1e3
+    dur_s = kern_ms[kdom] / 1e3
     alu_achieved = steps_dom / dur_s
     hbm_achieved = bytes_dom / dur_s / 1e9
+    traffic = measured_traffic(args.strategy)
 
     out = {
         "metric": METRIC,
@@ -162,10 +222,12 @@ def main():
                    "relations": n_rel, "tuples_per_relation": n, "m": m, "d": d, "zipf_s": s, "domain": D,
                    "sketch_seed": seed, "data_seed_base": W.DATA_SEED_BASE},
         "roofline": {"bound": "alu", "achieved": alu_achieved / 1e12, "peak": ALU_STEP_PEAK / 1e12,
-                     "unit": "T Horner-steps/s", "frac": alu_achieved / ALU_STEP_PEAK, "traffic": None,
-                     "kernel": f"update relation {kdom} ({a_dom} key columns)",
+                     "unit": "T Horner-steps/s", "frac": alu_achieved / ALU_STEP_PEAK, "traffic": traffic,
+                     "kernel": f"hashing kernel of relation {kdom}'s update ({a_dom} key columns)",
+                     "kernel_ms": kern_ms[kdom], "algorithmic_bytes": bytes_dom,
                      "hbm_GBps": hbm_achieved, "hbm_frac": hbm_achieved / HBM_PEAK_GBS},
         "update_ms_per_relation": {str(k): v for k, v in upd_ms.items()},
+        "hash_kernel_ms_per_relation": {str(k): v for k, v in kern_ms.items()},
         "update_tuples_per_s": tuples_per_step / (upd_total_ms / 1e3),
         "estimate_ms": est_ms,
         "estimates_per_s": 1e3 / est_ms,

@@ -181,6 +181,16 @@ cs_status cs_update_ex(cs_sketch *h, int32_t rel, const uint32_t *keys, const in
                        uint64_t n, void *stream, int32_t strategy, int32_t grid_blocks,
                        int32_t flags);
 
+/* cs_update_ex that also records two caller-created hipEvent_t on `stream`: ev_start just
+ * before the update's hashing kernel and ev_stop just after it (the segmented strategy's
+ * reduction of partial sums falls outside; for the partition strategy both passes over
+ * every chunk fall inside).  Either event may be NULL.  Per-kernel timing for monitoring
+ * and tuning; the counters are the same as cs_update's.  Errors as cs_update_ex, and
+ * CS_EDEVICE if an event cannot be recorded. */
+cs_status cs_update_timed(cs_sketch *h, int32_t rel, const uint32_t *keys, const int64_t *weights,
+                          uint64_t n, void *stream, int32_t strategy, int32_t grid_blocks,
+                          int32_t flags, void *ev_start, void *ev_stop);
+
 /* ------------------------------------------------------------------ estimate (Eq. 5, Alg. 3) */
 
 /* Estimate the join size: per repetition X_t (Eq. 5, evaluated as in Alg. 3), then

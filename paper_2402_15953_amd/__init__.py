@@ -25,7 +25,7 @@ PLAN_DOT, PLAN_SPECTRAL, PLAN_GENERAL = 1, 2, 3
 
 EXPORTED = [
     "cs_create", "cs_destroy", "cs_sketch_bytes", "cs_get_info", "cs_last_error",
-    "cs_update", "cs_update_ex", "cs_estimate", "cs_reset", "cs_merge", "cs_read_sketch",
+    "cs_update", "cs_update_ex", "cs_update_timed", "cs_estimate", "cs_reset", "cs_merge", "cs_read_sketch",
     "cs_sketch_device_ptr", "cs_read_coeffs", "cs_read_components",
     "cs_batch_create", "cs_batch_destroy", "cs_batch_update", "cs_batch_capture", "cs_batch_replay",
     "cs_batch_estimate", "cs_batch_stats",
@@ -106,6 +106,7 @@ def lib() -> ctypes.CDLL:
         L.cs_last_error.restype = ctypes.c_char_p
         L.cs_update.argtypes = [vp, i32, vp, vp, u64, vp]
         L.cs_update_ex.argtypes = [vp, i32, vp, vp, u64, vp, i32, i32, i32]
+        L.cs_update_timed.argtypes = [vp, i32, vp, vp, u64, vp, i32, i32, i32, vp, vp]
         L.cs_estimate.argtypes = [vp, vp, ctypes.POINTER(_Estimate), ctypes.POINTER(_Reps)]
         L.cs_reset.argtypes = [vp, vp]
         L.cs_merge.argtypes = [vp, vp, vp]
@@ -156,6 +157,15 @@ def _stream_ptr(stream):
     if isinstance(stream, int):
         return ctypes.c_void_p(stream)
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _event_ptr(ev):
+    """Raw hipEvent_t of a torch.cuda.Event (created on first use), or None."""
+    if ev is None:
+        return None
+    if not ev.cuda_event:
+        ev.record()   # torch creates the event lazily, on its first record
+    return ctypes.c_void_p(ev.cuda_event)
 
 
 def _reps_struct(d):
@@ -217,9 +227,11 @@ class Sketch:
         return {f: getattr(i, f) for f, _ in _Info._fields_}
 
     def update(self, rel: int, keys, weights=None, stream=None, strategy: int = UPDATE_AUTO, grid: int = 0,
-               unit_weights: bool = False, compact: bool = True, counters16: bool = True):
+               unit_weights: bool = False, compact: bool = True, counters16: bool = True, timing=None):
         """keys: device int32/uint32 tensor [n, a_rel] (or [n] for one column), contiguous;
-        weights: device int64 tensor [n] or None; unit_weights: every weight is +-1."""
+        weights: device int64 tensor [n] or None; unit_weights: every weight is +-1;
+        timing: optional (start, stop) torch.cuda.Event pair recorded around the hashing
+        kernel (cs_update_timed)."""
         import torch
         if keys.dtype not in (torch.int32, torch.uint32) or not keys.is_cuda or not keys.is_contiguous():
             raise TypeError("keys must be a contiguous int32/uint32 device tensor")
@@ -230,11 +242,15 @@ class Sketch:
                     or weights.shape[0] != n:
                 raise TypeError("weights must be a contiguous int64 device tensor of length n")
             wp = ctypes.c_void_p(weights.data_ptr())
-        _check(lib().cs_update_ex(self._h, int(rel), ctypes.c_void_p(keys.data_ptr()), wp, int(n),
-                                  _stream_ptr(stream), int(strategy), int(grid),
-                                  (UPDATE_UNIT_WEIGHTS if unit_weights else 0)
-                                  | (0 if compact else UPDATE_NO_COMPACT)
-                                  | (0 if counters16 else UPDATE_NO_COUNTERS16)))
+        flags = ((UPDATE_UNIT_WEIGHTS if unit_weights else 0) | (0 if compact else UPDATE_NO_COMPACT)
+                 | (0 if counters16 else UPDATE_NO_COUNTERS16))
+        if timing is None:
+            _check(lib().cs_update_ex(self._h, int(rel), ctypes.c_void_p(keys.data_ptr()), wp, int(n),
+                                      _stream_ptr(stream), int(strategy), int(grid), flags))
+        else:
+            e0, e1 = _event_ptr(timing[0]), _event_ptr(timing[1])
+            _check(lib().cs_update_timed(self._h, int(rel), ctypes.c_void_p(keys.data_ptr()), wp, int(n),
+                                         _stream_ptr(stream), int(strategy), int(grid), flags, e0, e1))
 
     def estimate(self, stream=None, reps: bool = False) -> dict:
         e = _Estimate()

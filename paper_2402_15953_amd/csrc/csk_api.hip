@@ -359,6 +359,13 @@ cs_status cs_get_info(const cs_sketch *hs, cs_info_t *out)
 cs_status cs_update_ex(cs_sketch *hs, int32_t rel, const uint32_t *keys, const int64_t *weights, uint64_t n,
                        void *stream, int32_t strategy, int32_t grid_blocks, int32_t flags)
 {
+    return cs_update_timed(hs, rel, keys, weights, n, stream, strategy, grid_blocks, flags, nullptr, nullptr);
+}
+
+cs_status cs_update_timed(cs_sketch *hs, int32_t rel, const uint32_t *keys, const int64_t *weights, uint64_t n,
+                          void *stream, int32_t strategy, int32_t grid_blocks, int32_t flags, void *ev_start,
+                          void *ev_stop)
+{
     if (!hs) return fail(CS_EINVAL, "null handle");
     Handle &h = hs->h;
     if (rel < 0 || rel >= h.g.n_rel) return fail(CS_EINVAL, "relation out of range");
@@ -379,6 +386,8 @@ cs_status cs_update_ex(cs_sketch *hs, int32_t rel, const uint32_t *keys, const i
     a.unit_weights = (flags & CS_UPDATE_UNIT_WEIGHTS) != 0;
     a.compact = (flags & CS_UPDATE_NO_COMPACT) == 0;
     a.counters16 = (flags & CS_UPDATE_NO_COUNTERS16) == 0;
+    a.ev_start = static_cast<hipEvent_t>(ev_start);
+    a.ev_stop = static_cast<hipEvent_t>(ev_stop);
     return launch_update(a, strategy, grid_blocks, static_cast<hipStream_t>(stream));
 }
 

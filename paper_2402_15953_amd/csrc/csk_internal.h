@@ -31,6 +31,12 @@ cs_status fail(cs_status st, const std::string &msg);
             return ::csk::fail(CS_EDEVICE, std::string(#call) + ": " + hipGetErrorString(_e)); \
     } while (0)
 
+// Record an optional timing event on stream s (inside functions returning cs_status).
+#define CSK_MARK(ev, s)                                \
+    do {                                               \
+        if (ev) CSK_HIP(hipEventRecord((ev), (s)));    \
+    } while (0)
+
 // ------------------------------------------------------------------ plans
 
 // Per-relation hashing plan: key column c carries attribute omega[c]; its bin hash is
@@ -92,6 +98,8 @@ struct UpdateArgs {
     bool unit_weights;      // caller guarantees every weight is +1 or -1
     bool compact = true;    // segmented strategy: compacting kernel for bucket-range segments
     bool counters16 = true; // segmented strategy: 16-bit LDS counters when they hold a repetition
+    hipEvent_t ev_start = nullptr;  // recorded just before / after the hashing kernel(s)
+    hipEvent_t ev_stop = nullptr;
 };
 struct SegGeom {
     uint32_t R;        // counter cells per segment

@@ -310,7 +310,7 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16(const uint32_t *__re
                                                             const uint64_t *__restrict__ coef, int32_t cpr,
                                                             DevPlan plan, uint32_t m, int32_t log2m, int32_t d,
                                                             uint32_t R, uint64_t chunk, bool vec2,
-                                                            int32_t *partial, unsigned long long *sketch)
+                                                            uint32_t *partial, unsigned long long *sketch)
 {
     extern __shared__ __align__(16) unsigned char s_raw[];
     uint32_t *s_w = reinterpret_cast<uint32_t *>(s_raw);  // [R / 2] words, two counters each
@@ -351,10 +351,27 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16(const uint32_t *__re
         }
     }
     __syncthreads();
-    int32_t *out = partial + (size_t)blockIdx.x * cells + cell0;
-    for (uint32_t e = threadIdx.x; e < span; e += kSegBlock) {
-        const uint32_t h = (s_w[e >> 1] >> ((e & 1u) << 4)) & 0xFFFFu;
-        out[e] = (int32_t)h - (int32_t)kBias16;
+    // partial sums leave as the biased 16-bit pairs: [chunk][cells / 2] words
+    uint32_t *out = partial + (size_t)blockIdx.x * (cells >> 1) + (cell0 >> 1);
+    for (uint32_t e = threadIdx.x; e < span / 2; e += kSegBlock) out[e] = s_w[e];
+}
+
+// sketch[2w + h] += sum over chunks of (half h of partial[chunk][w]) - 2^15
+__global__ void k_seg_reduce16(const uint32_t *__restrict__ partial, int32_t C, uint64_t words,
+                               unsigned long long *sketch)
+{
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words;
+         w += (uint64_t)gridDim.x * blockDim.x) {
+        int64_t lo = 0, hi = 0;
+        for (int c = 0; c < C; ++c) {
+            const uint32_t v = partial[(size_t)c * words + w];
+            lo += (int64_t)(v & 0xFFFFu);
+            hi += (int64_t)(v >> 16);
+        }
+        lo -= (int64_t)C * kBias16;
+        hi -= (int64_t)C * kBias16;
+        sketch[2 * w] += (unsigned long long)lo;
+        sketch[2 * w + 1] += (unsigned long long)hi;
     }
 }
 
@@ -623,6 +640,7 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
     if (strategy == CS_UPDATE_GLOBAL_ATOMIC || strategy == CS_UPDATE_WAVE_AGGREGATE) {
         uint64_t blocks = grid_blocks > 0 ? (uint64_t)grid_blocks : (uint64_t)n_cu * 16;
         if (blocks > need) blocks = need;
+        CSK_MARK(a.ev_start, s);
         if (strategy == CS_UPDATE_GLOBAL_ATOMIC)
             hipLaunchKernelGGL(k_update_global<NC>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a.keys,
                                a.weights, a.n, a.coef, a.plan.coef_per_rep, sk, a.m, a.d, plan, vec2);
@@ -630,6 +648,7 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
             hipLaunchKernelGGL(k_update_waveagg<NC>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a.keys,
                                a.weights, a.n, a.coef, a.plan.coef_per_rep, sk, a.m, a.d, plan, vec2);
         CSK_HIP(hipGetLastError());
+        CSK_MARK(a.ev_stop, s);
         return CS_OK;
     }
     if (strategy == CS_UPDATE_LDS_PRIVATE) {
@@ -655,39 +674,46 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
         auto launch = [&](auto kern, auto *part) -> cs_status {
             CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            CSK_MARK(a.ev_start, s);
             hipLaunchKernelGGL(kern, grid, dim3(kSegBlock), lds, s, a.keys, a.weights, a.n, a.coef,
                                a.plan.coef_per_rep, plan, a.m, log2m, a.d, sg.R, chunk, vec2, part);
             CSK_HIP(hipGetLastError());
+            CSK_MARK(a.ev_stop, s);
             return CS_OK;
         };
         cs_status st;
         if (narrow && a.m <= (1u << 16) && a.m > (1u << 15) && a.counters16) {
             // 16-bit LDS counters: a whole repetition per workgroup
             SegGeom g16 = seg16_geometry(a.m, a.d, a.scratch_bytes);
-            g16.chunks = chunks_for(g16.chunks, 4);
+            g16.chunks = chunks_for(g16.chunks, 2);
             const uint64_t chunk16 = (a.n + g16.chunks - 1) / g16.chunks;
             dim3 grid16((unsigned)g16.chunks, (unsigned)g16.segments);
             const size_t lds16 = (size_t)g16.R * 2;
-            int32_t *part = reinterpret_cast<int32_t *>(a.scratch);
+            uint32_t *part = reinterpret_cast<uint32_t *>(a.scratch);
             auto kern = e1 ? &k_update_seg16<NC, true> : &k_update_seg16<NC, false>;
             CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds16));
+            CSK_MARK(a.ev_start, s);
             hipLaunchKernelGGL(kern, grid16, dim3(kSegBlock), lds16, s, a.keys, a.weights, a.n, a.coef,
                                a.plan.coef_per_rep, plan, a.m, log2m, a.d, g16.R, chunk16, vec2, part,
                                reinterpret_cast<unsigned long long *>(a.sketch));
             CSK_HIP(hipGetLastError());
-            hipLaunchKernelGGL(k_seg_reduce<int32_t>, dim3((unsigned)std::min<uint64_t>((cells + 255) / 256, 8192)),
-                               dim3(256), 0, s, reinterpret_cast<const int32_t *>(a.scratch), g16.chunks, cells,
-                               a.sketch);
+            CSK_MARK(a.ev_stop, s);
+            const uint64_t words = cells / 2;
+            hipLaunchKernelGGL(k_seg_reduce16, dim3((unsigned)std::min<uint64_t>((words + 255) / 256, 8192)),
+                               dim3(256), 0, s, part, g16.chunks, words,
+                               reinterpret_cast<unsigned long long *>(a.sketch));
         } else if (narrow && e1 && sg.R < a.m && NC <= 2 && a.compact) {
             // bucket-range segments: compacting kernel (queue after the counters in LDS)
             int32_t *part = reinterpret_cast<int32_t *>(a.scratch);
             const size_t lds_c = (size_t)sg.R * 4 + (size_t)(kSegBlock / 64) * (NC + 1) * kQCap * 4;
             CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_update_seg_compact<NC>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_c));
+            CSK_MARK(a.ev_start, s);
             hipLaunchKernelGGL(k_update_seg_compact<NC>, grid, dim3(kSegBlock), lds_c, s, a.keys, a.weights, a.n,
                                a.coef, a.plan.coef_per_rep, a.m, log2m, a.d, sg.R, chunk, vec2, part);
             CSK_HIP(hipGetLastError());
+            CSK_MARK(a.ev_stop, s);
             hipLaunchKernelGGL(k_seg_reduce<int32_t>, dim3((unsigned)std::min<uint64_t>((cells + 255) / 256, 8192)),
                                dim3(256), 0, s, reinterpret_cast<const int32_t *>(a.scratch), sg.chunks, cells,
                                a.sketch);
@@ -720,6 +746,7 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
         int32_t *tab = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(a.scratch) + pg.tab_offset);
         const size_t max_tiles = pg.chunk / kPartTile;
         const size_t lds = (((size_t)1 << pg.log2R) + 2 * max_tiles + 1) * sizeof(int32_t);
+        CSK_MARK(a.ev_start, s);  // both passes over every chunk
         for (uint64_t base = 0; base < a.n; base += pg.chunk) {
             const uint64_t cn = a.n - base < pg.chunk ? a.n - base : pg.chunk;
             const int tiles = (int)((cn + kPartTile - 1) / kPartTile);
@@ -733,6 +760,7 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
                                pg.ranges, pg.log2R, a.m, a.sketch);
             CSK_HIP(hipGetLastError());
         }
+        CSK_MARK(a.ev_stop, s);
         return CS_OK;
     }
     return fail(CS_EINVAL, "unknown update strategy");
@@ -768,7 +796,7 @@ SegGeom seg16_geometry(uint32_t m, int32_t d, size_t scratch_bytes)
     g.segments = (int32_t)((cells + g.R - 1) / g.R);
     int32_t C = 512 / g.segments;
     if (C < 1) C = 1;
-    const uint64_t cap = std::max<uint64_t>(1, scratch_bytes / (cells * 4));
+    const uint64_t cap = std::max<uint64_t>(1, scratch_bytes / (cells * 2));
     if ((uint64_t)C > cap) C = (int32_t)cap;
     if (C > 64) C = 64;
     g.chunks = C;
@@ -811,7 +839,7 @@ size_t seg_scratch_bytes(uint32_t m, int32_t d)
     }
     {
         const SegGeom g16 = seg16_geometry(m, d, (size_t)-1);
-        best = std::max<size_t>(best, (size_t)g16.chunks * cells * 4);
+        best = std::max<size_t>(best, (size_t)g16.chunks * cells * 2);
     }
     // the partition strategy's chunk of kPartMaxChunk tuples
     const PartGeom pg = part_geometry(m, d, (size_t)-1);
