@@ -332,7 +332,7 @@ cs_status cs_destroy(cs_sketch *hs)
     hipDeviceSynchronize();
     if (h.counters) hipFree(h.counters);
     if (h.coef_dev) hipFree(h.coef_dev);
-    if (h.work.buf) hipFree(h.work.buf);
+    release_work(h.work);
     if (h.scratch) hipFree(h.scratch);
     hipSetDevice(cur);
     delete hs;

@@ -350,7 +350,7 @@ cs_status cs_batch_destroy(cs_batch *b)
     drop_graph(b->b);
     if (b->b.capture_stream) hipStreamDestroy(b->b.capture_stream);
     if (b->b.tables) hipFree(b->b.tables);
-    if (b->b.est.buf) hipFree(b->b.est.buf);
+    release_work(b->b.est);
     delete b;
     return CS_OK;
 }

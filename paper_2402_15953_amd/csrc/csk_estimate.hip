@@ -70,6 +70,18 @@ __device__ __forceinline__ double warp_sum(double v)
     return v;
 }
 
+// Butterfly reductions: every lane ends with the same value (fixed order).
+__device__ __forceinline__ double wave_allsum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_allmax(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
 // Block-wide sum with a fixed reduction order.
 __device__ double block_sum(double v, double *sh)
 {
@@ -355,10 +367,11 @@ __global__ __launch_bounds__(kThreads) void k_spec_mod(const uint32_t *__restric
                                                        const int32_t *__restrict__ idx,
                                                        const int64_t *__restrict__ prefix, int n_items,
                                                        const PrimeDev *__restrict__ primes, int64_t plane,
-                                                       uint32_t *partials)
+                                                       uint32_t *partials, const int32_t *__restrict__ kp)
 {
     __shared__ uint32_t sh[kThreads];
     const int item = find_item(prefix, n_items, blockIdx.x);
+    if (kp && (int)blockIdx.y >= kp[idx[item]]) return;  // prime not needed by this repetition
     const RepDesc D = reps[idx[item]];
     const int blk = (int)(blockIdx.x - prefix[item]);
     const int pi = blockIdx.y;
@@ -470,18 +483,81 @@ struct FinalizeArgs {
     CrtTables crt;
     RepDev *rs;
     OutDev *outs;
+    int32_t *kp;    // stage 1 also stores each repetition's prime count here
+    int32_t kcap;   // stage 2 finishes repetitions needing at most kcap primes
 };
 
-__global__ void k_finalize(FinalizeArgs a)
+constexpr int kFinThreads = 256;
+constexpr int kSpecPrimes = 5;                       // speculative modular step: primes (155 bits)
+constexpr size_t kSpecBudget = (size_t)1 << 30;      // and its largest workspace
+
+__global__ __launch_bounds__(kFinThreads) void k_finalize(FinalizeArgs a)
 {
+    __shared__ double s_val[kMaxD];
+    __shared__ int64_t s_lo[kMaxD], s_hi[kMaxD];
+    __shared__ int32_t s_ex[kMaxD], s_kp[kMaxD];
+    // stage 1: per-block partials of this query reduced once, one wavefront per
+    // sketch (norms) or repetition (spectral sums), in a fixed order
+    __shared__ double s_q2[kMaxRel * kMaxD], s_l1[kMaxRel * kMaxD];
+    __shared__ double s_sum[kMaxD], s_sabs[kMaxD], s_mx[kMaxD * kMaxRel];
     const QDesc Q = a.qs[blockIdx.x];
     const int t = threadIdx.x;
     const double u = 0x1p-53;
     const double m = (double)(1u << Q.log2m);
     const int plan = Q.plan;
+    if (a.stage == 1 && plan != CS_PLAN_DOT) {
+        const int lane = t & 63, wave = t >> 6, n_waves = kFinThreads / 64;
+        const RepDesc D0 = a.reps[Q.rep_base];
+        const int nb = Q.nb;
+        const int64_t norm0 = a.sks[D0.sk_base].off;  // a query's sketches are contiguous
+        for (int j = wave; j < Q.r * Q.d; j += n_waves) {
+            const double *p = a.norms + (norm0 + (int64_t)j * nb) * 2;
+            double q2 = 0.0, l1 = 0.0;
+            for (int b = lane; b < nb; b += 64) {
+                q2 += p[2 * b];
+                l1 += p[2 * b + 1];
+            }
+            q2 = wave_allsum(q2);
+            l1 = wave_allsum(l1);
+            if (lane == 0) {
+                s_q2[j] = q2;
+                s_l1[j] = l1;
+            }
+        }
+        if (plan == CS_PLAN_SPECTRAL) {
+            const int w = 2 + Q.r;
+            for (int tt = wave; tt < Q.d; tt += n_waves) {
+                const double *p = a.spec + D0.spec_off + (int64_t)tt * nb * w;
+                double sm = 0.0, sa = 0.0, mx[kMaxRel];
+#pragma unroll
+                for (int k = 0; k < kMaxRel; ++k) mx[k] = 0.0;
+                for (int b = lane; b < nb; b += 64) {
+                    sm += p[(int64_t)b * w];
+                    sa += p[(int64_t)b * w + 1];
+#pragma unroll
+                    for (int k = 0; k < kMaxRel; ++k)
+                        if (k < Q.r) mx[k] = fmax(mx[k], p[(int64_t)b * w + 2 + k]);
+                }
+                sm = wave_allsum(sm);
+                sa = wave_allsum(sa);
+#pragma unroll
+                for (int k = 0; k < kMaxRel; ++k)
+                    if (k < Q.r) mx[k] = wave_allmax(mx[k]);
+                if (lane == 0) {
+                    s_sum[tt] = sm;
+                    s_sabs[tt] = sa;
+#pragma unroll
+                    for (int k = 0; k < kMaxRel; ++k)
+                        if (k < Q.r) s_mx[tt * kMaxRel + k] = mx[k];
+                }
+            }
+        }
+    }
+    __syncthreads();
     if (t < Q.d) {
         const RepDesc D = a.reps[Q.rep_base + t];
-        RepDev &rp = a.rs[Q.rep_base + t];
+        // this repetition's record lives in registers; written back once at the end
+        RepDev rp = a.rs[Q.rep_base + t];
         const double per_thread = ceil(m / ((double)D.nb * kThreads));
         const double n_eff = per_thread + 8.0 + D.nb;
         if (a.stage == 1) {
@@ -506,24 +582,13 @@ __global__ void k_finalize(FinalizeArgs a)
                 double s2[kMaxRel], s1[kMaxRel];
                 const double up = 1.0 + (n_eff + 4.0) * u * 1.01;
                 for (int k = 0; k < Q.r; ++k) {
-                    const SkDesc S = a.sks[D.sk_base + k * Q.d + t];
-                    double qq = 0.0, l = 0.0;
-                    for (int b = 0; b < S.nb; ++b) {
-                        qq += a.norms[(S.off + b) * 2];
-                        l += a.norms[(S.off + b) * 2 + 1];
-                    }
-                    s2[k] = qq * up;
-                    s1[k] = l * up;
+                    s2[k] = s_q2[k * Q.d + t] * up;
+                    s1[k] = s_l1[k * Q.d + t] * up;
                 }
                 if (plan == CS_PLAN_SPECTRAL) {
-                    double sum = 0.0, sabs = 0.0, mx[kMaxRel];
-                    for (int k = 0; k < Q.r; ++k) mx[k] = 0.0;
-                    for (int b = 0; b < D.nb; ++b) {
-                        const double *p = a.spec + D.spec_off + (int64_t)b * (2 + Q.r);
-                        sum += p[0];
-                        sabs += p[1];
-                        for (int k = 0; k < Q.r; ++k) mx[k] = fmax(mx[k], p[2 + k]);
-                    }
+                    const double sum = s_sum[t], sabs = s_sabs[t];
+                    double mx[kMaxRel];
+                    for (int k = 0; k < Q.r; ++k) mx[k] = s_mx[t * kMaxRel + k];
                     const double xf = sum / m;
                     // fp64 FFT error (radix-2 Cooley-Tukey, twiddles within 2u):
                     // ||fl(FFT z) - FFT z||_2 <= kappa sqrt(m) ||z||_2.
@@ -538,12 +603,7 @@ __global__ void k_finalize(FinalizeArgs a)
                         const int sidx = k * Q.d + t;
                         double z2 = s2[k];
                         const int ps = sidx ^ 1;
-                        if (ps < n_sk) {
-                            const SkDesc S = a.sks[D.sk_base + ps];
-                            double qq = 0.0;
-                            for (int b = 0; b < S.nb; ++b) qq += a.norms[(S.off + b) * 2];
-                            z2 += qq * up;
-                        }
+                        if (ps < n_sk) z2 += s_q2[ps] * up;
                         e[k] = kappa * sm * sqrt(z2) * (1.0 + 4.0 * u);
                         N[k] = sm * sqrt(s2[k]) * (1.0 + 4.0 * u) + e[k];
                         M[k] = mx[k] * (1.0 + 4.0 * u) + e[k];
@@ -611,7 +671,7 @@ __global__ void k_finalize(FinalizeArgs a)
                     }
                 }
             }
-        } else if (rp.kprimes > 0) {  // stage 2: residues -> exact value
+        } else if (rp.kprimes > 0 && rp.kprimes <= a.kcap) {  // stage 2: residues -> exact value
             const int K = rp.kprimes;
             uint32_t res[kMaxPrimes], dig[kMaxPrimes];
             for (int i = 0; i < K; ++i) {
@@ -657,50 +717,48 @@ __global__ void k_finalize(FinalizeArgs a)
                 }
             }
         }
+        a.rs[Q.rep_base + t] = rp;
+        if (a.stage == 1) a.kp[Q.rep_base + t] = rp.kprimes;
+        s_val[t] = rp.value;
+        s_ex[t] = rp.exact;
+        s_lo[t] = rp.lo;
+        s_hi[t] = rp.hi;
+        s_kp[t] = rp.kprimes;
     }
     __syncthreads();
-    if (t == 0) {
-        // median: order by fp64 value, ties between exact values by the integers
-        const RepDev *R0 = a.rs + Q.rep_base;
-        int idx[kMaxD];
-        int n_mod = 0;
+    if (t < Q.d) {
+        // median (lower middle) by rank: total order on (fp64 value, exact flag, exact
+        // integer when present, repetition index); for exact repetitions this is the
+        // order of the integers, fp64 rounding being monotone
+        const double v = s_val[t];
+        const int ex = s_ex[t];
+        const __int128 x = ex ? (__int128)(((unsigned __int128)(uint64_t)s_hi[t] << 64) | (uint64_t)s_lo[t]) : 0;
+        int rank = 0, n_mod = 0;
         for (int i = 0; i < Q.d; ++i) {
-            idx[i] = i;
-            if (R0[i].kprimes > 0) ++n_mod;
-        }
-        for (int i = 1; i < Q.d; ++i) {
-            const int cur = idx[i];
-            int j = i - 1;
-            while (j >= 0) {
-                const RepDev &A = R0[idx[j]];
-                const RepDev &B = R0[cur];
-                bool greater;
-                if (A.value != B.value) {
-                    greater = A.value > B.value;
-                } else if (A.exact && B.exact) {
-                    const __int128 xa = (__int128)(((unsigned __int128)(uint64_t)A.hi << 64) | (uint64_t)A.lo);
-                    const __int128 xb = (__int128)(((unsigned __int128)(uint64_t)B.hi << 64) | (uint64_t)B.lo);
-                    greater = xa > xb;
-                } else {
-                    greater = false;
-                }
-                if (!greater) break;
-                idx[j + 1] = idx[j];
-                --j;
+            n_mod += s_kp[i] > 0;
+            const double vi = s_val[i];
+            bool less;
+            if (vi != v) {
+                less = vi < v;
+            } else if (s_ex[i] != ex) {
+                less = s_ex[i] < ex;
+            } else {
+                const __int128 xi =
+                    s_ex[i] ? (__int128)(((unsigned __int128)(uint64_t)s_hi[i] << 64) | (uint64_t)s_lo[i]) : 0;
+                less = xi != x ? xi < x : i < t;
             }
-            idx[j + 1] = cur;
+            rank += less;
         }
-        const int med = idx[(Q.d - 1) / 2];
-        const RepDev &R = R0[med];
-        OutDev &o = a.outs[blockIdx.x];
-        o.value = R.value;
-        o.lo = R.lo;
-        o.hi = R.hi;
-        o.exact = R.exact;
-        const __int128 x = (__int128)(((unsigned __int128)(uint64_t)R.hi << 64) | (uint64_t)R.lo);
-        o.fits = R.exact && x >= (__int128)INT64_MIN && x <= (__int128)INT64_MAX;
-        o.n_modular = n_mod;
-        o.median_rep = med;
+        if (rank == (Q.d - 1) / 2) {
+            OutDev &o = a.outs[blockIdx.x];
+            o.value = v;
+            o.lo = s_lo[t];
+            o.hi = s_hi[t];
+            o.exact = ex;
+            o.fits = ex && x >= (__int128)INT64_MIN && x <= (__int128)INT64_MAX;
+            o.n_modular = n_mod;
+            o.median_rep = t;
+        }
     }
 }
 
@@ -990,6 +1048,8 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
         std::vector<int> queries;
         std::vector<int32_t> rep_idx;
         std::vector<const int64_t *> re, im;
+        std::vector<const int64_t *> mod_ptrs;  // every sketch, (query, relation, repetition) order
+        std::vector<int32_t> rep_of;            // repetition of each of those sketches
         size_t z_off = 0;
     };
     std::map<int, Group> groups;
@@ -1020,7 +1080,7 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
                     sd.push_back(S);
                 }
         }
-        int vec_base = 0;
+        int vec_base = 0, mod_base = 0;
         Group *G = nullptr;
         if (Q.plan == CS_PLAN_SPECTRAL) {
             G = &groups[L];
@@ -1032,6 +1092,11 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
                 const int s0 = 2 * v, s1 = 2 * v + 1;
                 G->re.push_back(sd[sk_base + s0].p);
                 G->im.push_back(s1 < n_sk ? sd[sk_base + s1].p : nullptr);
+            }
+            mod_base = (int)G->mod_ptrs.size();
+            for (int j = 0; j < n_sk; ++j) {
+                G->mod_ptrs.push_back(sd[sk_base + j].p);
+                G->rep_of.push_back(Q.rep_base + j % d);
             }
         }
         if (Q.plan == CS_PLAN_GENERAL) general_q.push_back(q);
@@ -1048,7 +1113,7 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
             D.vec_base = vec_base;
             D.nb = nb;
             D.sk_base = sk_base;
-            D.mod_vec_base = 0;
+            D.mod_vec_base = mod_base;
             D.spec_off = spec_off;
             D.dot_off = dot_off;
             D.mod_off = mod_off;
@@ -1079,7 +1144,7 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
     for (size_t i = 0; i < dot_idx.size(); ++i) dot_pre[i + 1] = dot_pre[i] + rd[dot_idx[i]].nb;
     const size_t o_skpre = c.take(sk_pre.size() * sizeof(int64_t));
     const size_t o_dotpre = c.take(dot_pre.size() * sizeof(int64_t));
-    std::vector<size_t> o_gidx, o_gre, o_gim, o_gpre;
+    std::vector<size_t> o_gidx, o_gre, o_gim, o_gpre, o_gptr, o_grepof;
     std::vector<std::vector<int64_t>> g_pre;
     size_t z_total = 0;
     for (auto &kv : groups) {
@@ -1091,6 +1156,8 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
         g_pre.push_back(std::move(pre));
         o_gre.push_back(c.take(G.re.size() * sizeof(void *)));
         o_gim.push_back(c.take(G.im.size() * sizeof(void *)));
+        o_gptr.push_back(c.take(G.mod_ptrs.size() * sizeof(void *)));
+        o_grepof.push_back(c.take(G.rep_of.size() * sizeof(int32_t)));
         G.z_off = z_total;
         z_total += align_up(G.re.size() * ((size_t)1 << G.log2m) * sizeof(double2));
     }
@@ -1100,6 +1167,7 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
     const size_t o_dot = c.take(std::max<int64_t>(1, dot_off) * 2 * sizeof(unsigned long long));
     const size_t o_modp = c.take((size_t)kMaxPrimes * std::max<int64_t>(1, mod_plane) * sizeof(uint32_t));
     const size_t o_rs = c.take((size_t)n_rep * sizeof(RepDev));
+    const size_t o_kp = c.take((size_t)n_rep * sizeof(int32_t));
     const size_t o_outs = c.take((size_t)nq * sizeof(OutDev));
     const size_t o_Z = c.take(z_total);
     if (ws.bytes < c.off) {
@@ -1113,8 +1181,33 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
         ws.bytes = c.off;
     }
     char *wb = static_cast<char *>(ws.buf);
+    // pinned host staging: [tables | repetition records | outputs | modular-step tables]
+    Carve hc;
+    const size_t h_img = hc.take(host_tables);
+    const size_t h_rs = hc.take((size_t)n_rep * sizeof(RepDev));
+    const size_t h_outs = hc.take((size_t)nq * sizeof(OutDev));
+    const size_t h_mod = hc.take(align_up(sd.size() * sizeof(void *)) + align_up((size_t)n_rep * sizeof(int32_t)) +
+                                 (size_t)(n_rep + 1 + (int)groups.size()) * sizeof(int64_t) +
+                                 3 * 256 * (groups.size() + 1));
+    if (ws.host_bytes < hc.off) {
+        if (ws.host) hipHostFree(ws.host);
+        ws.host = nullptr;
+        ws.host_bytes = 0;
+        if (hipHostMalloc(&ws.host, hc.off, hipHostMallocDefault) != hipSuccess)
+            return fail(CS_ENOMEM, "estimate host staging");
+        ws.host_bytes = hc.off;
+    }
+    char *hb = static_cast<char *>(ws.host);
+    RepDev *hr = reinterpret_cast<RepDev *>(hb + h_rs);
+    OutDev *ho = reinterpret_cast<OutDev *>(hb + h_outs);
     // host image of the tables, one upload
-    std::vector<char> img(host_tables, 0);
+    struct HostImg {
+        char *p;
+        size_t n;
+        char *data() { return p; }
+        size_t size() const { return n; }
+    } img{hb + h_img, host_tables};
+    std::memset(img.data(), 0, img.size());
     std::memcpy(img.data() + o_q, qd.data(), qd.size() * sizeof(QDesc));
     std::memcpy(img.data() + o_rep, rd.data(), rd.size() * sizeof(RepDesc));
     if (!sd.empty()) std::memcpy(img.data() + o_sk, sd.data(), sd.size() * sizeof(SkDesc));
@@ -1129,6 +1222,8 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
             std::memcpy(img.data() + o_gpre[gi], g_pre[gi].data(), g_pre[gi].size() * sizeof(int64_t));
             std::memcpy(img.data() + o_gre[gi], G.re.data(), G.re.size() * sizeof(void *));
             std::memcpy(img.data() + o_gim[gi], G.im.data(), G.im.size() * sizeof(void *));
+            std::memcpy(img.data() + o_gptr[gi], G.mod_ptrs.data(), G.mod_ptrs.size() * sizeof(void *));
+            std::memcpy(img.data() + o_grepof[gi], G.rep_of.data(), G.rep_of.size() * sizeof(int32_t));
             ++gi;
         }
     }
@@ -1141,6 +1236,7 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
     unsigned long long *d_dot = reinterpret_cast<unsigned long long *>(wb + o_dot);
     uint32_t *d_modp = reinterpret_cast<uint32_t *>(wb + o_modp);
     RepDev *d_rs = reinterpret_cast<RepDev *>(wb + o_rs);
+    int32_t *d_kp = reinterpret_cast<int32_t *>(wb + o_kp);
     OutDev *d_outs = reinterpret_cast<OutDev *>(wb + o_outs);
 
     // ---- stage 1
@@ -1186,19 +1282,99 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
     fa.crt = g_crt;
     fa.rs = d_rs;
     fa.outs = d_outs;
+    fa.kp = d_kp;
+    fa.kcap = kMaxPrimes;
     fa.stage = 1;
-    hipLaunchKernelGGL(k_finalize, dim3(nq), dim3(kMaxD), 0, s, fa);
+    hipLaunchKernelGGL(k_finalize, dim3(nq), dim3(kFinThreads), 0, s, fa);
     CSK_HIP(hipGetLastError());
 
-    std::vector<RepDev> hr(n_rep);
-    CSK_HIP(hipMemcpyAsync(hr.data(), d_rs, n_rep * sizeof(RepDev), hipMemcpyDeviceToHost, s));
+    // ---- speculative modular step: when no query has a general plan and the workspace
+    // is modest, the residues of the first kSpecPrimes primes are computed right behind
+    // stage 1, without a round trip to the host; each repetition's blocks beyond the
+    // primes it needs (decided on the device by stage 1) return at once
+    int kdone = 0;
+    {
+        size_t spec_bytes = 0;
+        for (auto &kv : groups)
+            spec_bytes += align_up((size_t)kSpecPrimes * kv.second.mod_ptrs.size() * ((size_t)1 << kv.second.log2m) *
+                                   sizeof(uint32_t));
+        if (general_q.empty() && !groups.empty() && spec_bytes <= kSpecBudget) {
+            if (ws.mod_bytes < spec_bytes) {
+                if (ws.mod) hipFree(ws.mod);
+                ws.mod = nullptr;
+                ws.mod_bytes = 0;
+                if (hipMalloc(&ws.mod, spec_bytes) != hipSuccess) return fail(CS_ENOMEM, "modular workspace");
+                ws.mod_bytes = spec_bytes;
+            }
+            char *mod_cur = static_cast<char *>(ws.mod);
+            int gi = 0;
+            for (auto &kv : groups) {
+                Group &G = kv.second;
+                const uint32_t *roots = roots_mod(device, G.log2m, 0, false, s, &st);
+                if (!roots) return st;
+                const int vpp = (int)G.mod_ptrs.size();
+                uint32_t *N = reinterpret_cast<uint32_t *>(mod_cur);
+                mod_cur += align_up((size_t)kSpecPrimes * vpp * ((size_t)1 << G.log2m) * sizeof(uint32_t));
+                st = ntt_forward(reinterpret_cast<const int64_t *const *>(wb + o_gptr[gi]), vpp, kSpecPrimes, N,
+                                 G.log2m, primes, roots, G.log2m, s,
+                                 reinterpret_cast<const int32_t *>(wb + o_grepof[gi]), d_kp);
+                if (st != CS_OK) return st;
+                hipLaunchKernelGGL(k_spec_mod, dim3((unsigned)g_pre[gi].back(), kSpecPrimes), dim3(kThreads), 0, s,
+                                   N, vpp, d_rep, reinterpret_cast<const int32_t *>(wb + o_gidx[gi]),
+                                   reinterpret_cast<const int64_t *>(wb + o_gpre[gi]), (int)G.rep_idx.size(),
+                                   primes, mod_plane, d_modp, d_kp);
+                CSK_HIP(hipGetLastError());
+                ++gi;
+            }
+            fa.stage = 2;
+            fa.kcap = kSpecPrimes;
+            hipLaunchKernelGGL(k_finalize, dim3(nq), dim3(kFinThreads), 0, s, fa);
+            CSK_HIP(hipGetLastError());
+            kdone = kSpecPrimes;
+        }
+    }
+    CSK_HIP(hipMemcpyAsync(hr, d_rs, n_rep * sizeof(RepDev), hipMemcpyDeviceToHost, s));
+    CSK_HIP(hipMemcpyAsync(ho, d_outs, nq * sizeof(OutDev), hipMemcpyDeviceToHost, s));
     CSK_HIP(hipStreamSynchronize(s));
 
-    // ---- stage 2: modular residues for the repetitions that need them
+    // ---- stage 2: modular residues for the repetitions still waiting for them
     bool any = false;
-    for (int i = 0; i < n_rep; ++i) any = any || hr[i].kprimes > 0;
-    std::vector<void *> mod_bufs;
+    for (int i = 0; i < n_rep; ++i) any = any || hr[i].kprimes > kdone;
     if (any) {
+        // device workspace of the whole step, sized first (grows, never shrinks)
+        size_t mod_need = 0;
+        for (auto &kv : groups) {
+            const Group &G = kv.second;
+            int K = 0, vpp = 0, nidx = 0;
+            for (int q : G.queries) {
+                int kq = 0;
+                for (int t = 0; t < qd[q].d; ++t) kq = std::max(kq, hr[qd[q].rep_base + t].kprimes);
+                if (kq > kdone) {
+                    K = std::max(K, kq);
+                    vpp += qd[q].r * qd[q].d;
+                    nidx += qd[q].d;
+                }
+            }
+            if (K == 0) continue;
+            const size_t tabs = align_up((size_t)vpp * sizeof(void *)) + align_up((size_t)nidx * sizeof(int32_t)) +
+                                align_up((size_t)(nidx + 1) * sizeof(int64_t));
+            mod_need += tabs + align_up((size_t)K * vpp * ((size_t)1 << G.log2m) * sizeof(uint32_t));
+        }
+        for (int q : general_q) {
+            int K = 0;
+            for (int t = 0; t < qd[q].d; ++t) K = std::max(K, hr[qd[q].rep_base + t].kprimes);
+            if (K <= kdone) continue;
+            mod_need += align_up((size_t)hs[q]->g.n_regs * K * qd[q].d * hs[q]->m * sizeof(uint32_t));
+        }
+        if (ws.mod_bytes < mod_need) {
+            if (ws.mod) hipFree(ws.mod);
+            ws.mod = nullptr;
+            ws.mod_bytes = 0;
+            if (hipMalloc(&ws.mod, mod_need) != hipSuccess) return fail(CS_ENOMEM, "modular workspace");
+            ws.mod_bytes = mod_need;
+        }
+        char *mod_cur = static_cast<char *>(ws.mod);
+        char *mod_host = hb + h_mod;
         // spectral groups: every repetition of a query that needs one is recomputed
         for (auto &kv : groups) {
             Group &G = kv.second;
@@ -1207,7 +1383,7 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
             for (int q : G.queries) {
                 int kq = 0;
                 for (int t = 0; t < qd[q].d; ++t) kq = std::max(kq, hr[qd[q].rep_base + t].kprimes);
-                if (kq > 0) {
+                if (kq > kdone) {
                     needq.push_back(q);
                     K = std::max(K, kq);
                 }
@@ -1232,16 +1408,14 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
             for (size_t i = 0; i < idx.size(); ++i) mpre[i + 1] = mpre[i] + rd[idx[i]].nb;
             const size_t o_mpre = align_up(ptrs.size() * sizeof(void *)) + align_up(idx.size() * sizeof(int32_t));
             const size_t tab_bytes = o_mpre + align_up(mpre.size() * sizeof(int64_t));
-            void *mb = nullptr;
-            if (hipMallocAsync(&mb, tab_bytes + (size_t)K * vpp * m * sizeof(uint32_t), s) != hipSuccess)
-                return fail(CS_ENOMEM, "modular workspace");
-            mod_bufs.push_back(mb);
-            char *mbc = static_cast<char *>(mb);
-            std::vector<char> mimg(tab_bytes, 0);
-            std::memcpy(mimg.data(), ptrs.data(), ptrs.size() * sizeof(void *));
-            std::memcpy(mimg.data() + align_up(ptrs.size() * sizeof(void *)), idx.data(), idx.size() * sizeof(int32_t));
-            std::memcpy(mimg.data() + o_mpre, mpre.data(), mpre.size() * sizeof(int64_t));
-            CSK_HIP(hipMemcpyAsync(mbc, mimg.data(), tab_bytes, hipMemcpyHostToDevice, s));
+            char *mbc = mod_cur;
+            mod_cur += tab_bytes + align_up((size_t)K * vpp * m * sizeof(uint32_t));
+            char *mimg = mod_host;  // pinned; stays untouched until the call returns
+            mod_host += tab_bytes;
+            std::memcpy(mimg, ptrs.data(), ptrs.size() * sizeof(void *));
+            std::memcpy(mimg + align_up(ptrs.size() * sizeof(void *)), idx.data(), idx.size() * sizeof(int32_t));
+            std::memcpy(mimg + o_mpre, mpre.data(), mpre.size() * sizeof(int64_t));
+            CSK_HIP(hipMemcpyAsync(mbc, mimg, tab_bytes, hipMemcpyHostToDevice, s));
             // updated mod_vec_base of these repetitions
             for (int q : needq)
                 CSK_HIP(hipMemcpyAsync(d_rep + qd[q].rep_base, rd.data() + qd[q].rep_base, qd[q].d * sizeof(RepDesc),
@@ -1253,27 +1427,22 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
             hipLaunchKernelGGL(k_spec_mod, dim3((unsigned)mpre.back(), K), dim3(kThreads), 0, s, N, vpp, d_rep,
                                reinterpret_cast<const int32_t *>(mbc + align_up(ptrs.size() * sizeof(void *))),
                                reinterpret_cast<const int64_t *>(mbc + o_mpre), (int)idx.size(), primes,
-                               mod_plane, d_modp);
+                               mod_plane, d_modp, nullptr);
             CSK_HIP(hipGetLastError());
-            // keep mimg alive until the copy is consumed
-            CSK_HIP(hipStreamSynchronize(s));
         }
         // general plans: Alg. 3's register program per query
         for (int q : general_q) {
             int K = 0;
             for (int t = 0; t < qd[q].d; ++t) K = std::max(K, hr[qd[q].rep_base + t].kprimes);
-            if (K == 0) continue;
+            if (K <= kdone) continue;
             const Handle &h = *hs[q];
             const int d = (int)h.d, L = h.log2m;
             const size_t m = h.m;
             const uint32_t *roots = roots_mod(device, L, 0, false, s, &st);
             if (!roots) return st;
             const size_t reg_elems = (size_t)K * d * m;
-            void *mb = nullptr;
-            if (hipMallocAsync(&mb, (size_t)h.g.n_regs * reg_elems * sizeof(uint32_t), s) != hipSuccess)
-                return fail(CS_ENOMEM, "modular workspace");
-            mod_bufs.push_back(mb);
-            uint32_t *M = static_cast<uint32_t *>(mb);
+            uint32_t *M = reinterpret_cast<uint32_t *>(mod_cur);
+            mod_cur += align_up((size_t)h.g.n_regs * reg_elems * sizeof(uint32_t));
             const int gx = (int)std::min<size_t>(64, (m + 255) / 256);
             for (const Op &op : h.g.ops) {
                 uint32_t *dst = M + (size_t)op.dst * reg_elems;
@@ -1312,15 +1481,13 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
             CSK_HIP(hipGetLastError());
         }
         fa.stage = 2;
-        hipLaunchKernelGGL(k_finalize, dim3(nq), dim3(kMaxD), 0, s, fa);
+        fa.kcap = kMaxPrimes;
+        hipLaunchKernelGGL(k_finalize, dim3(nq), dim3(kFinThreads), 0, s, fa);
         CSK_HIP(hipGetLastError());
-        for (void *mb : mod_bufs) CSK_HIP(hipFreeAsync(mb, s));
+        CSK_HIP(hipMemcpyAsync(ho, d_outs, nq * sizeof(OutDev), hipMemcpyDeviceToHost, s));
+        if (reps_out) CSK_HIP(hipMemcpyAsync(hr, d_rs, n_rep * sizeof(RepDev), hipMemcpyDeviceToHost, s));
+        CSK_HIP(hipStreamSynchronize(s));
     }
-
-    std::vector<OutDev> ho(nq);
-    CSK_HIP(hipMemcpyAsync(ho.data(), d_outs, nq * sizeof(OutDev), hipMemcpyDeviceToHost, s));
-    if (reps_out) CSK_HIP(hipMemcpyAsync(hr.data(), d_rs, n_rep * sizeof(RepDev), hipMemcpyDeviceToHost, s));
-    CSK_HIP(hipStreamSynchronize(s));
     for (int q = 0; q < nq; ++q) {
         cs_estimate_t &o = outs[q];
         o.value = ho[q].value;
@@ -1342,6 +1509,14 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
         }
     }
     return CS_OK;
+}
+
+void release_work(EstimateWork &w)
+{
+    if (w.buf) hipFree(w.buf);
+    if (w.mod) hipFree(w.mod);
+    if (w.host) hipHostFree(w.host);
+    w = EstimateWork{};
 }
 
 cs_status estimate_run(Handle &h, hipStream_t s, cs_estimate_t *out, const cs_reps_t *reps)

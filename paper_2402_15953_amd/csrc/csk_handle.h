@@ -35,7 +35,13 @@ cs_status analyze_graph(const cs_graph *g, GraphPlan *out);
 struct EstimateWork {
     void *buf = nullptr;        // one device allocation carved into the pieces below
     size_t bytes = 0;
+    void *mod = nullptr;        // device workspace of the modular (exact) step
+    size_t mod_bytes = 0;
+    void *host = nullptr;       // pinned host staging: tables up, results down
+    size_t host_bytes = 0;
 };
+// Frees every buffer of a workspace (the device must be idle for it).
+void release_work(EstimateWork &w);
 
 struct Handle {
     int device = 0;

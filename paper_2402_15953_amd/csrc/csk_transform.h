@@ -56,9 +56,12 @@ cs_status fft_f64_forward(const int64_t *const *re, const int64_t *const *im, in
                           const double2 *tw, int log2T, hipStream_t s);
 
 // ptrs != null: vector (prime i, j) is loaded from sketch ptrs[j] (device pointer table);
-// ptrs == null: transform buf in place.
+// ptrs == null: transform buf in place.  rep_of / kp (both device, may be null): vector j
+// serves repetition rep_of[j], which needs kp[rep_of[j]] primes; the blocks of primes
+// beyond that return without touching buf.
 cs_status ntt_forward(const int64_t *const *ptrs, int vec_per_prime, int n_primes, uint32_t *buf, int log2m,
-                      const PrimeDev *primes, const uint32_t *roots, int log2T, hipStream_t s);
+                      const PrimeDev *primes, const uint32_t *roots, int log2T, hipStream_t s,
+                      const int32_t *rep_of = nullptr, const int32_t *kp = nullptr);
 cs_status ntt_inverse(int vec_per_prime, int n_primes, uint32_t *buf, int log2m, const PrimeDev *primes,
                       const uint32_t *roots, int log2T, hipStream_t s);
 

@@ -116,11 +116,13 @@ struct ModSrc {
 
 __global__ __launch_bounds__(kThreads) void k_ntt(ModSrc src, uint32_t *buf, PassGeom g, int vec_per_prime,
                                                   const PrimeDev *__restrict__ primes,
-                                                  const uint32_t *__restrict__ roots, int log2T, int inverse)
+                                                  const uint32_t *__restrict__ roots, int log2T, int inverse,
+                                                  const int32_t *__restrict__ rep_of, const int32_t *__restrict__ kp)
 {
     __shared__ uint32_t s[kTile];
     const int v = blockIdx.x;
     const int pi = v / vec_per_prime;
+    if (kp && pi >= kp[rep_of[v % vec_per_prime]]) return;  // prime not needed
     const PrimeDev P = primes[pi];
     const RingM R{P.p, P.pinv_neg};
     const uint32_t *tw = roots + ((size_t)(2 * pi + inverse) << log2T);
@@ -225,7 +227,8 @@ cs_status fft_f64_forward(const int64_t *const *re, const int64_t *const *im, in
 }
 
 cs_status ntt_forward(const int64_t *const *ptrs, int vec_per_prime, int n_primes, uint32_t *buf, int log2m,
-                      const PrimeDev *primes, const uint32_t *roots, int log2T, hipStream_t s)
+                      const PrimeDev *primes, const uint32_t *roots, int log2T, hipStream_t s,
+                      const int32_t *rep_of, const int32_t *kp)
 {
     const int n_vec = vec_per_prime * n_primes;
     if (n_vec == 0) return CS_OK;
@@ -234,17 +237,17 @@ cs_status ntt_forward(const int64_t *const *ptrs, int vec_per_prime, int n_prime
     if (log2m <= 12) {
         PassGeom g = single_pass(log2m);
         hipLaunchKernelGGL(k_ntt, dim3(n_vec, g.blocks), dim3(kThreads), 0, s, ptrs ? first : self, buf, g,
-                           vec_per_prime, primes, roots, log2T, 0);
+                           vec_per_prime, primes, roots, log2T, 0, rep_of, kp);
         CSK_HIP(hipGetLastError());
         return CS_OK;
     }
     PassGeom g1 = column_pass(log2m, true);
     hipLaunchKernelGGL(k_ntt, dim3(n_vec, g1.blocks), dim3(kThreads), 0, s, ptrs ? first : self, buf, g1,
-                       vec_per_prime, primes, roots, log2T, 0);
+                       vec_per_prime, primes, roots, log2T, 0, rep_of, kp);
     CSK_HIP(hipGetLastError());
     PassGeom g2 = row_pass(log2m, false);
     hipLaunchKernelGGL(k_ntt, dim3(n_vec, g2.blocks), dim3(kThreads), 0, s, self, buf, g2, vec_per_prime,
-                       primes, roots, log2T, 0);
+                       primes, roots, log2T, 0, rep_of, kp);
     CSK_HIP(hipGetLastError());
     return CS_OK;
 }
@@ -259,18 +262,18 @@ cs_status ntt_inverse(int vec_per_prime, int n_primes, uint32_t *buf, int log2m,
         PassGeom g = single_pass(log2m);
         g.scale = 1;
         hipLaunchKernelGGL(k_ntt, dim3(n_vec, g.blocks), dim3(kThreads), 0, s, self, buf, g, vec_per_prime,
-                           primes, roots, log2T, 1);
+                           primes, roots, log2T, 1, nullptr, nullptr);
         CSK_HIP(hipGetLastError());
         return CS_OK;
     }
     PassGeom g1 = row_pass(log2m, true);
     hipLaunchKernelGGL(k_ntt, dim3(n_vec, g1.blocks), dim3(kThreads), 0, s, self, buf, g1, vec_per_prime,
-                       primes, roots, log2T, 1);
+                       primes, roots, log2T, 1, nullptr, nullptr);
     CSK_HIP(hipGetLastError());
     PassGeom g2 = column_pass(log2m, false);
     g2.scale = 1;
     hipLaunchKernelGGL(k_ntt, dim3(n_vec, g2.blocks), dim3(kThreads), 0, s, self, buf, g2, vec_per_prime,
-                       primes, roots, log2T, 1);
+                       primes, roots, log2T, 1, nullptr, nullptr);
     CSK_HIP(hipGetLastError());
     return CS_OK;
 }
