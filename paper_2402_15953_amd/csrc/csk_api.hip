@@ -17,10 +17,14 @@ namespace csk {
 namespace {
 thread_local std::string g_err;
 
+// Zeroes n int64 (the counter block is 256-byte aligned): 16-byte stores, then the tail.
 __global__ void k_fill_zero(int64_t *p, size_t n)
 {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        p[i] = 0;
+    const size_t n2 = n / 2;
+    longlong2 *q = reinterpret_cast<longlong2 *>(p);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (size_t)gridDim.x * blockDim.x)
+        q[i] = make_longlong2(0, 0);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && (n & 1)) p[n - 1] = 0;
 }
 
 __global__ void k_add_i64(int64_t *dst, const int64_t *src, size_t n)

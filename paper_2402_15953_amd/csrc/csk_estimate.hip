@@ -488,6 +488,7 @@ struct FinalizeArgs {
 };
 
 constexpr int kFinThreads = 256;
+constexpr int kStage = 4096;  // doubles staged through LDS per chunk
 constexpr int kSpecPrimes = 5;                       // speculative modular step: primes (155 bits)
 constexpr size_t kSpecBudget = (size_t)1 << 30;      // and its largest workspace
 
@@ -500,55 +501,65 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinalizeArgs a)
     // sketch (norms) or repetition (spectral sums), in a fixed order
     __shared__ double s_q2[kMaxRel * kMaxD], s_l1[kMaxRel * kMaxD];
     __shared__ double s_sum[kMaxD], s_sabs[kMaxD], s_mx[kMaxD * kMaxRel];
+    __shared__ double s_stage[kStage];
+    __shared__ uint32_t s_res[kMaxD * kMaxPrimes], s_dig[kMaxD * kMaxPrimes];
+    static_assert(kStage >= kMaxD * 3 * kMaxRel, "bound terms reuse the staging area");
     const QDesc Q = a.qs[blockIdx.x];
     const int t = threadIdx.x;
     const double u = 0x1p-53;
     const double m = (double)(1u << Q.log2m);
     const int plan = Q.plan;
     if (a.stage == 1 && plan != CS_PLAN_DOT) {
-        const int lane = t & 63, wave = t >> 6, n_waves = kFinThreads / 64;
+        // The partials of a query are contiguous: staged through LDS in chunks (every
+        // thread's loads of a chunk are in flight together), then each owner (sketch or
+        // repetition) adds its own records in index order.
         const RepDesc D0 = a.reps[Q.rep_base];
         const int nb = Q.nb;
-        const int64_t norm0 = a.sks[D0.sk_base].off;  // a query's sketches are contiguous
-        for (int j = wave; j < Q.r * Q.d; j += n_waves) {
-            const double *p = a.norms + (norm0 + (int64_t)j * nb) * 2;
-            double q2 = 0.0, l1 = 0.0;
-            for (int b = lane; b < nb; b += 64) {
-                q2 += p[2 * b];
-                l1 += p[2 * b + 1];
-            }
-            q2 = wave_allsum(q2);
-            l1 = wave_allsum(l1);
-            if (lane == 0) {
-                s_q2[j] = q2;
-                s_l1[j] = l1;
-            }
+        const int n_sk = Q.r * Q.d;
+        const int w = 2 + Q.r;
+        for (int j = t; j < n_sk; j += kFinThreads) s_q2[j] = s_l1[j] = 0.0;
+        for (int tt = t; tt < Q.d; tt += kFinThreads) {
+            s_sum[tt] = s_sabs[tt] = 0.0;
+            for (int k = 0; k < kMaxRel; ++k) s_mx[tt * kMaxRel + k] = 0.0;
         }
-        if (plan == CS_PLAN_SPECTRAL) {
-            const int w = 2 + Q.r;
-            for (int tt = wave; tt < Q.d; tt += n_waves) {
-                const double *p = a.spec + D0.spec_off + (int64_t)tt * nb * w;
-                double sm = 0.0, sa = 0.0, mx[kMaxRel];
-#pragma unroll
-                for (int k = 0; k < kMaxRel; ++k) mx[k] = 0.0;
-                for (int b = lane; b < nb; b += 64) {
-                    sm += p[(int64_t)b * w];
-                    sa += p[(int64_t)b * w + 1];
-#pragma unroll
-                    for (int k = 0; k < kMaxRel; ++k)
-                        if (k < Q.r) mx[k] = fmax(mx[k], p[(int64_t)b * w + 2 + k]);
-                }
-                sm = wave_allsum(sm);
-                sa = wave_allsum(sa);
-#pragma unroll
-                for (int k = 0; k < kMaxRel; ++k)
-                    if (k < Q.r) mx[k] = wave_allmax(mx[k]);
-                if (lane == 0) {
-                    s_sum[tt] = sm;
-                    s_sabs[tt] = sa;
-#pragma unroll
-                    for (int k = 0; k < kMaxRel; ++k)
-                        if (k < Q.r) s_mx[tt * kMaxRel + k] = mx[k];
+        for (int pass = 0; pass < (plan == CS_PLAN_SPECTRAL ? 2 : 1); ++pass) {
+            // pass 0: norms, records of 2 doubles (sum of squares, sum of |c|), nb per sketch
+            // pass 1: spectral sums, records of w doubles, nb per repetition
+            const int rec = pass == 0 ? 2 : w;
+            const int n_own = pass == 0 ? n_sk : Q.d;
+            const double *src = pass == 0 ? a.norms + a.sks[D0.sk_base].off * 2 : a.spec + D0.spec_off;
+            const int64_t len = (int64_t)n_own * nb * rec;
+            const int64_t seg = (int64_t)nb * rec;
+            const int64_t chunk = (int64_t)(kStage / rec) * rec;  // whole records per chunk
+            for (int64_t c0 = 0; c0 < len; c0 += chunk) {
+                const int cl = (int)(len - c0 < chunk ? len - c0 : chunk);
+                __syncthreads();
+#pragma unroll 4
+                for (int i = t; i < cl; i += kFinThreads) s_stage[i] = src[c0 + i];
+                __syncthreads();
+                for (int o = t; o < n_own; o += kFinThreads) {
+                    const int64_t lo = std::max<int64_t>(c0, (int64_t)o * seg);
+                    const int64_t hi = std::min<int64_t>(c0 + cl, (int64_t)(o + 1) * seg);
+                    if (lo >= hi) continue;
+                    if (pass == 0) {
+                        double q2 = s_q2[o], l1 = s_l1[o];
+                        for (int64_t e = lo; e < hi; e += 2) {
+                            q2 += s_stage[e - c0];
+                            l1 += s_stage[e - c0 + 1];
+                        }
+                        s_q2[o] = q2;
+                        s_l1[o] = l1;
+                    } else {
+                        double sm = s_sum[o], sa = s_sabs[o];
+                        for (int64_t e = lo; e < hi; e += w) {
+                            sm += s_stage[e - c0];
+                            sa += s_stage[e - c0 + 1];
+                            for (int k = 0; k < Q.r; ++k)
+                                s_mx[o * kMaxRel + k] = fmax(s_mx[o * kMaxRel + k], s_stage[e - c0 + 2 + k]);
+                        }
+                        s_sum[o] = sm;
+                        s_sabs[o] = sa;
+                    }
                 }
             }
         }
@@ -579,16 +590,14 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinalizeArgs a)
                 rp.xf = rp.value;
             } else {
                 // norms of each relation's sketch at this repetition (upper bounds)
-                double s2[kMaxRel], s1[kMaxRel];
+                // per-relation values live in LDS (indexed loops over r would
+                // otherwise put per-thread arrays in scratch memory)
                 const double up = 1.0 + (n_eff + 4.0) * u * 1.01;
-                for (int k = 0; k < Q.r; ++k) {
-                    s2[k] = s_q2[k * Q.d + t] * up;
-                    s1[k] = s_l1[k * Q.d + t] * up;
-                }
+                auto s2 = [&](int k) { return s_q2[k * Q.d + t] * up; };
+                auto s1 = [&](int k) { return s_l1[k * Q.d + t] * up; };
                 if (plan == CS_PLAN_SPECTRAL) {
                     const double sum = s_sum[t], sabs = s_sabs[t];
-                    double mx[kMaxRel];
-                    for (int k = 0; k < Q.r; ++k) mx[k] = s_mx[t * kMaxRel + k];
+                    const double *mx = s_mx + t * kMaxRel;
                     const double xf = sum / m;
                     // fp64 FFT error (radix-2 Cooley-Tukey, twiddles within 2u):
                     // ||fl(FFT z) - FFT z||_2 <= kappa sqrt(m) ||z||_2.
@@ -596,16 +605,18 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinalizeArgs a)
                     const double eta = 2.0 * u + g4 * (1.41421356237309515 + 2.0 * u);
                     const double kappa = 2.0 * (Q.log2m + 3) * eta;
                     const double sm = sqrt(m) * (1.0 + 4.0 * u);
-                    double e[kMaxRel], N[kMaxRel], M[kMaxRel];
+                    double *e = s_stage + t * 3 * kMaxRel;  // the staging area is free now
+                    double *N = e + kMaxRel;
+                    double *M = N + kMaxRel;
                     const int n_sk = Q.r * Q.d;
                     for (int k = 0; k < Q.r; ++k) {
                         // packed partner: sketch index s ^ 1 within the query
                         const int sidx = k * Q.d + t;
-                        double z2 = s2[k];
+                        double z2 = s2(k);
                         const int ps = sidx ^ 1;
                         if (ps < n_sk) z2 += s_q2[ps] * up;
                         e[k] = kappa * sm * sqrt(z2) * (1.0 + 4.0 * u);
-                        N[k] = sm * sqrt(s2[k]) * (1.0 + 4.0 * u) + e[k];
+                        N[k] = sm * sqrt(s2(k)) * (1.0 + 4.0 * u) + e[k];
                         M[k] = mx[k] * (1.0 + 4.0 * u) + e[k];
                     }
                     double dT = 0.0;
@@ -652,8 +663,8 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinalizeArgs a)
                     double lb = 0.0;
                     bool zero = false;
                     for (int k = 0; k < Q.r; ++k) {
-                        if (s1[k] == 0.0) zero = true;
-                        lb += log2(s1[k]);
+                        if (s1(k) == 0.0) zero = true;
+                        lb += log2(s1(k));
                     }
                     rp.exact = 0;
                     rp.value = 0.0;
@@ -673,7 +684,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinalizeArgs a)
             }
         } else if (rp.kprimes > 0 && rp.kprimes <= a.kcap) {  // stage 2: residues -> exact value
             const int K = rp.kprimes;
-            uint32_t res[kMaxPrimes], dig[kMaxPrimes];
+            uint32_t *res = s_res + t * kMaxPrimes, *dig = s_dig + t * kMaxPrimes;
             for (int i = 0; i < K; ++i) {
                 const PrimeDev &P = a.primes[i];
                 const RingM R{P.p, P.pinv_neg};

@@ -23,22 +23,63 @@ namespace csk {
 namespace {
 
 constexpr int kTile = 4096;
-constexpr int kThreads = 256;
+constexpr int kThreads = 1024;  // 16 wavefronts per tile: two butterflies per thread per stage
 
 __device__ __forceinline__ uint32_t bitrev(uint32_t x, int bits)
 {
     return bits ? (__brev(x) >> (32 - bits)) : 0u;
 }
 
+// Copies w_L^j (j < L / 2, L = 2^log2L) from the table tw[k] = w_T^k, T = 2^log2T, into
+// LDS; every stage of a length-L transform takes its twiddles from there.
+template <class T>
+__device__ __forceinline__ void load_stage_twiddles(T *stw, int log2L, const T *__restrict__ tw, int log2T)
+{
+    for (int j = threadIdx.x; j < (1 << (log2L - 1)); j += kThreads) stw[j] = tw[(size_t)j << (log2T - log2L)];
+}
+
 // Radix-2 DIT stages on C interleaved transforms of length 2^log2L held in LDS as
-// s[n * C + c] (bit-reversed input, natural output).  tw[k] = w_T^k, T = 2^log2T.
+// s[n * C + c] (bit-reversed input, natural output); stw from load_stage_twiddles.
+// Stages go in pairs: a thread takes the four elements two consecutive stages combine,
+// applies both stages' radix-2 butterflies in registers (the same operations as two
+// separate stages, so the same rounding), and writes them back once.
 template <class Ring>
 __device__ __forceinline__ void lds_stages(typename Ring::T *s, int log2L, int log2C, const Ring &R,
-                                           const typename Ring::T *__restrict__ tw, int log2T)
+                                           const typename Ring::T *stw)
 {
+    using T = typename Ring::T;
     const int C = 1 << log2C;
+    int lh = 0;
+    for (; lh + 1 < log2L; lh += 2) {
+        const int half = 1 << lh;
+        const int ngr = (1 << (log2L - 2)) << log2C;
+        for (int b = threadIdx.x; b < ngr; b += kThreads) {
+            const int c = b & (C - 1);
+            const int bb = b >> log2C;
+            const int k = bb & (half - 1);
+            const int i0 = ((bb >> lh) << (lh + 2)) + k;
+            const int i1 = i0 + half, i2 = i0 + 2 * half, i3 = i0 + 3 * half;
+            const T x0 = s[i0 * C + c], x1 = s[i1 * C + c], x2 = s[i2 * C + c], x3 = s[i3 * C + c];
+            // stage lh: pairs (i0, i1) and (i2, i3), twiddle w_{2 half}^k
+            const T w1 = stw[k << (log2L - lh - 1)];
+            T v = R.mul(x1, w1);
+            const T y0 = R.add(x0, v), y1 = R.sub(x0, v);
+            v = R.mul(x3, w1);
+            const T y2 = R.add(x2, v), y3 = R.sub(x2, v);
+            // stage lh + 1: pairs (i0, i2) with w_{4 half}^k and (i1, i3) with w_{4 half}^(k + half)
+            const T w2 = stw[k << (log2L - lh - 2)];
+            const T w3 = stw[(k + half) << (log2L - lh - 2)];
+            v = R.mul(y2, w2);
+            s[i0 * C + c] = R.add(y0, v);
+            s[i2 * C + c] = R.sub(y0, v);
+            v = R.mul(y3, w3);
+            s[i1 * C + c] = R.add(y1, v);
+            s[i3 * C + c] = R.sub(y1, v);
+        }
+        __syncthreads();
+    }
     const int nbf = (1 << (log2L - 1)) << log2C;
-    for (int lh = 0; lh < log2L; ++lh) {
+    for (; lh < log2L; ++lh) {  // the last stage when their number is odd
         const int half = 1 << lh;
         for (int b = threadIdx.x; b < nbf; b += kThreads) {
             const int c = b & (C - 1);
@@ -47,7 +88,7 @@ __device__ __forceinline__ void lds_stages(typename Ring::T *s, int log2L, int l
             const int i0 = ((bb >> lh) << (lh + 1)) + k;
             const int i1 = i0 + half;
             const typename Ring::T u = s[i0 * C + c];
-            const typename Ring::T v = R.mul(s[i1 * C + c], tw[(size_t)k << (log2T - lh - 1)]);
+            const typename Ring::T v = R.mul(s[i1 * C + c], stw[k << (log2L - lh - 1)]);
             s[i0 * C + c] = R.add(u, v);
             s[i1 * C + c] = R.sub(u, v);
         }
@@ -68,6 +109,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_f64(F64Src src, double2 *buf, 
                                                       const double2 *__restrict__ tw, int log2T)
 {
     __shared__ double2 s[kTile];
+    __shared__ double2 stw[kTile / 2];
     const int v = blockIdx.x;
     const int blk = blockIdx.y;
     const int C = 1 << g.log2C;
@@ -92,9 +134,10 @@ __global__ __launch_bounds__(kThreads) void k_fft_f64(F64Src src, double2 *buf, 
             s[(bitrev(n, g.log2L) << g.log2C) + c] = vec[pos];
         }
     }
+    load_stage_twiddles(stw, g.log2L, tw, log2T);
     __syncthreads();
     RingC R;
-    lds_stages<RingC>(s, g.log2L, g.log2C, R, tw, log2T);
+    lds_stages<RingC>(s, g.log2L, g.log2C, R, stw);
     for (int idx = threadIdx.x; idx < total; idx += kThreads) {
         const int n = idx >> g.log2C, c = idx & (C - 1);
         const int64_t pos = base + (int64_t)c * g.col_stride + (int64_t)n * g.elem_stride;
@@ -120,10 +163,11 @@ __global__ __launch_bounds__(kThreads) void k_ntt(ModSrc src, uint32_t *buf, Pas
                                                   const int32_t *__restrict__ rep_of, const int32_t *__restrict__ kp)
 {
     __shared__ uint32_t s[kTile];
+    __shared__ uint32_t stw[kTile / 2];
     const int v = blockIdx.x;
     const int pi = v / vec_per_prime;
     if (kp && pi >= kp[rep_of[v % vec_per_prime]]) return;  // prime not needed
-    const PrimeDev P = primes[pi];
+    const PrimeDev &P = primes[pi];  // by reference: a copy with minv[] indexed would live in scratch
     const RingM R{P.p, P.pinv_neg};
     const uint32_t *tw = roots + ((size_t)(2 * pi + inverse) << log2T);
     const int blk = blockIdx.y;
@@ -147,8 +191,9 @@ __global__ __launch_bounds__(kThreads) void k_ntt(ModSrc src, uint32_t *buf, Pas
             s[(bitrev(n, g.log2L) << g.log2C) + c] = vec[pos];
         }
     }
+    load_stage_twiddles(stw, g.log2L, tw, log2T);
     __syncthreads();
-    lds_stages<RingM>(s, g.log2L, g.log2C, R, tw, log2T);
+    lds_stages<RingM>(s, g.log2L, g.log2C, R, stw);
     for (int idx = threadIdx.x; idx < total; idx += kThreads) {
         const int n = idx >> g.log2C, c = idx & (C - 1);
         const int64_t pos = base + (int64_t)c * g.col_stride + (int64_t)n * g.elem_stride;

@@ -329,9 +329,30 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16(const uint32_t *__re
         CoefE1<NC> K;
         if constexpr (E1) K.load(cf);
         const uint32_t row = (uint32_t)(((uint64_t)t << log2m) - cell0);
-        for (uint64_t i = begin + threadIdx.x; i < end; i += kSegBlock) {
+        unsigned long long *srow = sketch + ((uint64_t)t << log2m);
+        // Software pipeline: the next tuple's keys (and weight) are loaded while this one
+        // is hashed, and the value an LDS add returns is checked one tuple later, so
+        // neither latency stalls the wavefront.  Deferring the check lets a thread have
+        // two adds outstanding: a half still stays within 2^15 +- (2^14 + 2 * 1024).
+        uint64_t i = begin + threadIdx.x;
+        uint32_t xn[NC];
+        int64_t wn = 0;
+        if (i < end) {
+            load_keys<NC>(keys, i, vec2, xn);
+            if (weights) wn = weights[i];
+        }
+        bool pend = false;
+        uint32_t p_old = 0, p_shift = 0, p_neg = 0, p_j = 0;
+        uint32_t *p_w = s_w;
+        for (; i < end; i += kSegBlock) {
             uint32_t x[NC];
-            load_keys<NC>(keys, i, vec2, x);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) x[c] = xn[c];
+            const int64_t wt = wn;
+            if (i + kSegBlock < end) {
+                load_keys<NC>(keys, i + kSegBlock, vec2, xn);
+                if (weights) wn = weights[i + kSegBlock];
+            }
             uint32_t j, neg;
             if constexpr (E1) {
                 j = K.bin(x) & (m - 1);
@@ -340,14 +361,25 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16(const uint32_t *__re
                 hash_rep<NC>(cf, plan, x, j, neg);
                 j &= m - 1;
             }
-            if (weights && weights[i] < 0) neg ^= 1u;
+            if (wt < 0) neg ^= 1u;
             const uint32_t loc = row + j;
             const uint32_t shift = (loc & 1u) << 4;
             uint32_t *w = &s_w[loc >> 1];
             const uint32_t old = atomicAdd(w, neg ? (0xFFFFFFFFu << shift) : (1u << shift));
-            const uint32_t h = ((old >> shift) & 0xFFFFu) + (neg ? 0xFFFFFFFFu : 1u);
-            if (h >= kHi16 || h <= kLo16)
-                spill16(w, shift, sketch + ((uint64_t)t << log2m) + j);
+            if (pend) {
+                const uint32_t h = ((p_old >> p_shift) & 0xFFFFu) + (p_neg ? 0xFFFFFFFFu : 1u);
+                if (h >= kHi16 || h <= kLo16) spill16(p_w, p_shift, srow + p_j);
+            }
+            pend = true;
+            p_old = old;
+            p_shift = shift;
+            p_neg = neg;
+            p_j = j;
+            p_w = w;
+        }
+        if (pend) {
+            const uint32_t h = ((p_old >> p_shift) & 0xFFFFu) + (p_neg ? 0xFFFFFFFFu : 1u);
+            if (h >= kHi16 || h <= kLo16) spill16(p_w, p_shift, srow + p_j);
         }
     }
     __syncthreads();
@@ -363,6 +395,7 @@ __global__ void k_seg_reduce16(const uint32_t *__restrict__ partial, int32_t C, 
     for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words;
          w += (uint64_t)gridDim.x * blockDim.x) {
         int64_t lo = 0, hi = 0;
+#pragma unroll 8
         for (int c = 0; c < C; ++c) {
             const uint32_t v = partial[(size_t)c * words + w];
             lo += (int64_t)(v & 0xFFFFu);
@@ -794,7 +827,8 @@ SegGeom seg16_geometry(uint32_t m, int32_t d, size_t scratch_bytes)
     const uint64_t cells = (uint64_t)d * m;
     if (m <= g.R) g.R = (g.R / m) * m;
     g.segments = (int32_t)((cells + g.R - 1) / g.R);
-    int32_t C = 512 / g.segments;
+    // one round of 128 KB workgroups over the 256 CUs: fewer partial sums to reduce
+    int32_t C = 256 / g.segments;
     if (C < 1) C = 1;
     const uint64_t cap = std::max<uint64_t>(1, scratch_bytes / (cells * 2));
     if ((uint64_t)C > cap) C = (int32_t)cap;
