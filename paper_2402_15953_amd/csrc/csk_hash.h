@@ -22,13 +22,18 @@ constexpr uint64_t kHashP = (1ull << 61) - 1;
 // chain without an intermediate fold; hcanon() reduces the final value.
 __device__ __forceinline__ uint64_t hstep(uint64_t v, uint32_t x, uint64_t a)
 {
-    const uint64_t lo = (uint64_t)(uint32_t)v * (uint64_t)x;          // < 2^64
-    const uint64_t hi = (uint64_t)(uint32_t)(v >> 32) * (uint64_t)x;  // < 2^63
-    // v * x = t * 2^32 + (lo mod 2^32) with t = hi + (lo >> 32) < 2^63 + 2^32
-    const uint64_t t = hi + (lo >> 32);
-    // (v * x mod 2^61) + (v * x >> 61) + a, using 2^61 = 1 (mod p)
-    const uint64_t low61 = ((t & 0x1FFFFFFFull) << 32) | (lo & 0xFFFFFFFFull);
-    return low61 + (t >> 29) + a;
+    const uint64_t lo = (uint64_t)(uint32_t)v * (uint64_t)x;  // < 2^64
+    // v * x = t * 2^32 + (lo mod 2^32) with t = (v >> 32) * x + (lo >> 32) < 2^63 + 2^32
+    const uint64_t t = (uint64_t)(uint32_t)(v >> 32) * (uint64_t)x + (lo >> 32);
+    // (v * x mod 2^61) + (v * x >> 61) + a, using 2^61 = 1 (mod p).  The low 61 bits
+    // are the pair (lo mod 2^32, t mod 2^29); adding s = (v * x >> 61) + a to that pair
+    // word by word with a carry keeps the compiler from materialising it (one
+    // instruction less per step than a 64-bit or-then-add).
+    const uint64_t s = (t >> 29) + a;
+    unsigned int carry;
+    const uint32_t rl = __builtin_addc((uint32_t)lo, (uint32_t)s, 0u, &carry);
+    const uint32_t rh = __builtin_addc((uint32_t)t & 0x1FFFFFFFu, (uint32_t)(s >> 32), carry, &carry);
+    return ((uint64_t)rh << 32) | rl;
 }
 
 // Canonical residue in [0, p) of a redundant value r < 2^63.
