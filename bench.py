@@ -10,9 +10,12 @@ relation's tuples into its d x m sketches (one update launch per relation), then
 estimate (fp64 FFT spectral product-reduce, exactness step, median over d).
 
 Printed: one JSON line.  `value` is tuple updates per second over whole steps.
-`roofline` describes the dominant kernel (the update of the two-column relation),
-timed with HIP events on the stream it runs on.  `cpu_baseline` is the CPU oracle on a
-bounded prefix of the same input, on this host.
+`roofline` describes the dominant kernel (the hashing kernel of the two-column
+relation), timed inside the timed steps with HIP events the library records around it
+on the stream it runs on (events without the system-scope fence, so recording them
+flushes no caches).  The per-relation update and estimate times come from a few
+diagnostic steps after the timed ones.  `cpu_baseline` is the CPU oracle on a bounded
+prefix of the same input, on this host.
 """
 from __future__ import annotations
 
@@ -150,49 +153,60 @@ def main():
     kev = {k: [] for k in range(n_rel)}   # around the hashing kernel alone (cs_update_timed)
     est_ev = []
 
-    def step(record):
+    # timing events, made before the timed region (recording one costs no cache flush)
+    n_diag = 3
+    timers = iter([csk.Timer() for _ in range(args.steps * 2 * n_rel + n_diag * (n_rel + 2))])
+
+    def step(mode):
+        """mode 0: untimed; 1: timed step, the library records a pair around each hashing
+        kernel; 2: diagnostic step (after the timed region), marks where each relation's
+        update starts and around the estimate."""
         sk.reset(stream=stream)
+        marks = []
         for k in range(n_rel):
-            if record:
-                a = torch.cuda.Event(enable_timing=True)
-                b = torch.cuda.Event(enable_timing=True)
-                ka = torch.cuda.Event(enable_timing=True)
-                kb = torch.cuda.Event(enable_timing=True)
-                a.record(stream)
+            if mode == 1:
+                ka, kb = next(timers), next(timers)
                 sk.update(k, keys[k], None, stream=stream, strategy=args.strategy, timing=(ka, kb))
-                b.record(stream)
-                ev[k].append((a, b))
                 kev[k].append((ka, kb))
-            else:
-                sk.update(k, keys[k], None, stream=stream, strategy=args.strategy)
-        if record:
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
+                continue
+            if mode == 2:
+                a = next(timers)
+                a.record(stream)
+                marks.append(a)
+            sk.update(k, keys[k], None, stream=stream, strategy=args.strategy)
+        if mode == 2:
+            a, b = next(timers), next(timers)
             a.record(stream)
+            marks.append(a)
+            for k in range(n_rel):
+                ev[k].append((marks[k], marks[k + 1]))
         res = sk.estimate(stream=stream)
-        if record:
+        if mode == 2:
             b.record(stream)
             est_ev.append((a, b))
         return res
 
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
-            step(False)
+            step(0)
         torch.cuda.synchronize()
         t_start = time.perf_counter()
         for _ in range(args.steps):
-            res = step(True)
+            res = step(1)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
+        for _ in range(n_diag):
+            step(2)
+        torch.cuda.synchronize()
 
     ms_per_step = elapsed * 1e3 / args.steps
     tuples_per_step = n * n_rel
     value = tuples_per_step * args.steps / elapsed
-    upd_ms = {k: sum(a.elapsed_time(b) for a, b in ev[k]) / len(ev[k]) for k in range(n_rel)}
-    est_ms = sum(a.elapsed_time(b) for a, b in est_ev) / len(est_ev)
+    upd_ms = {k: sum(a.elapsed_ms(b) for a, b in ev[k]) / len(ev[k]) for k in range(n_rel)}
+    est_ms = sum(a.elapsed_ms(b) for a, b in est_ev) / len(est_ev)
     upd_total_ms = sum(upd_ms.values())
 
-    kern_ms = {k: sum(a.elapsed_time(b) for a, b in kev[k]) / len(kev[k]) for k in range(n_rel)}
+    kern_ms = {k: sum(a.elapsed_ms(b) for a, b in kev[k]) / len(kev[k]) for k in range(n_rel)}
 
     # dominant kernel: the slowest hashing kernel (one launch per relation and step)
     kdom = max(kern_ms, key=kern_ms.get)

@@ -162,8 +162,9 @@ const char *cs_last_error(void);
 /* Stream n tuples of relation `rel` into its sketch (Alg. 2 for each repetition).
  * Calls on one handle must be ordered (one stream, or event dependencies).  The
  * segmented and partition strategies use one scratch buffer per device shared by all
- * handles (reuse ordered by an event); it grows, once, to the largest (m, d) seen:
- * the only allocation on this path.
+ * handles; it grows, once, to the largest (m, d) seen: the only allocation on this
+ * path.  Its reuse is ordered by the stream while consecutive users share one; a call on
+ * another stream than the previous user's first waits for the device to be idle.
  *   keys:    device, uint32 [n][a_rel] tuple-major; column c is the c-th attribute of
  *            `rel` in ascending attribute id.
  *   weights: device, int64 [n] frequency changes Delta (turnstile model, Sec. 2.1),
@@ -318,6 +319,21 @@ cs_status cs_read_coeffs(const cs_sketch *h, uint64_t *sign_out, uint64_t *bin_o
 
 /* Graph component of each attribute, int32 [n_attr] (host). */
 cs_status cs_read_components(const cs_sketch *h, int32_t *psi_out);
+
+/* ------------------------------------------------------------------ timing */
+
+/* Timing events (hipEvent_t) for cs_update_timed and for marks between calls, created
+ * without the system-scope fence an ordinary event performs when it completes, so that
+ * recording one does not write back and invalidate caches in the middle of the timed
+ * work.  Not for synchronising with host reads of device memory.
+ *   cs_timer_create:  *ev receives a new event (CS_EDEVICE on failure).
+ *   cs_timer_record:  records ev on `stream` (stream-ordered).
+ *   cs_timer_elapsed: waits for `stop`, then *ms = time from start to stop.
+ *   cs_timer_destroy: releases ev. */
+cs_status cs_timer_create(void **ev);
+cs_status cs_timer_record(void *ev, void *stream);
+cs_status cs_timer_elapsed(void *start, void *stop, float *ms);
+cs_status cs_timer_destroy(void *ev);
 
 #ifdef __cplusplus
 }

@@ -27,6 +27,7 @@ EXPORTED = [
     "cs_create", "cs_destroy", "cs_sketch_bytes", "cs_get_info", "cs_last_error",
     "cs_update", "cs_update_ex", "cs_update_timed", "cs_estimate", "cs_reset", "cs_merge", "cs_read_sketch",
     "cs_sketch_device_ptr", "cs_read_coeffs", "cs_read_components",
+    "cs_timer_create", "cs_timer_record", "cs_timer_elapsed", "cs_timer_destroy",
     "cs_batch_create", "cs_batch_destroy", "cs_batch_update", "cs_batch_capture", "cs_batch_replay",
     "cs_batch_estimate", "cs_batch_stats",
     "cs_server_create", "cs_server_destroy", "cs_server_add_query", "cs_server_remove_query",
@@ -114,6 +115,10 @@ def lib() -> ctypes.CDLL:
         L.cs_sketch_device_ptr.argtypes = [vp, i32, ctypes.POINTER(vp)]
         L.cs_read_coeffs.argtypes = [vp, vp, vp]
         L.cs_read_components.argtypes = [vp, vp]
+        L.cs_timer_create.argtypes = [ctypes.POINTER(vp)]
+        L.cs_timer_record.argtypes = [vp, vp]
+        L.cs_timer_elapsed.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_float)]
+        L.cs_timer_destroy.argtypes = [vp]
         L.cs_batch_create.argtypes = [ctypes.POINTER(vp)]
         L.cs_batch_destroy.argtypes = [vp]
         L.cs_batch_update.argtypes = [vp, ctypes.POINTER(_Item), i32, vp]
@@ -160,12 +165,43 @@ def _stream_ptr(stream):
 
 
 def _event_ptr(ev):
-    """Raw hipEvent_t of a torch.cuda.Event (created on first use), or None."""
+    """Raw hipEvent_t of a Timer or a torch.cuda.Event (created on first use), or None."""
     if ev is None:
         return None
+    if isinstance(ev, Timer):
+        return ev.handle
     if not ev.cuda_event:
         ev.record()   # torch creates the event lazily, on its first record
     return ctypes.c_void_p(ev.cuda_event)
+
+
+class Timer:
+    """A timing event without the system-scope fence (cs_timer_*): recording it does not
+    write back caches in the middle of the timed work."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        _check(lib().cs_timer_create(ctypes.byref(h)))
+        self.handle = h
+
+    def record(self, stream=None):
+        _check(lib().cs_timer_record(self.handle, _stream_ptr(stream)))
+
+    def elapsed_ms(self, stop: "Timer") -> float:
+        ms = ctypes.c_float()
+        _check(lib().cs_timer_elapsed(self.handle, stop.handle, ctypes.byref(ms)))
+        return float(ms.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().cs_timer_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _reps_struct(d):

@@ -442,6 +442,37 @@ cs_status cs_read_sketch(cs_sketch *hs, int32_t rel, int64_t *host_out)
     return CS_OK;
 }
 
+cs_status cs_timer_create(void **ev)
+{
+    if (!ev) return fail(CS_EINVAL, "null argument");
+    hipEvent_t e = nullptr;
+    CSK_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+    *ev = e;
+    return CS_OK;
+}
+
+cs_status cs_timer_record(void *ev, void *stream)
+{
+    if (!ev) return fail(CS_EINVAL, "null event");
+    CSK_HIP(hipEventRecord(static_cast<hipEvent_t>(ev), static_cast<hipStream_t>(stream)));
+    return CS_OK;
+}
+
+cs_status cs_timer_elapsed(void *start, void *stop, float *ms)
+{
+    if (!start || !stop || !ms) return fail(CS_EINVAL, "null argument");
+    CSK_HIP(hipEventSynchronize(static_cast<hipEvent_t>(stop)));
+    CSK_HIP(hipEventElapsedTime(ms, static_cast<hipEvent_t>(start), static_cast<hipEvent_t>(stop)));
+    return CS_OK;
+}
+
+cs_status cs_timer_destroy(void *ev)
+{
+    if (!ev) return CS_OK;
+    CSK_HIP(hipEventDestroy(static_cast<hipEvent_t>(ev)));
+    return CS_OK;
+}
+
 cs_status cs_sketch_device_ptr(cs_sketch *hs, int32_t rel, int64_t **out)
 {
     if (!hs || !out) return fail(CS_EINVAL, "null argument");

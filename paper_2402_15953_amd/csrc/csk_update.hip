@@ -902,7 +902,7 @@ struct ScratchPool {
     std::mutex mu;
     void *buf = nullptr;
     size_t bytes = 0;
-    hipEvent_t last = nullptr;
+    hipStream_t last_stream = nullptr;  // stream of the last user
     bool used = false;
 };
 std::mutex g_pool_mu;
@@ -955,13 +955,15 @@ cs_status launch_update(const UpdateArgs &a_in, int strategy, int grid_blocks, h
         P.bytes = need;
         P.used = false;
     }
-    if (!P.last) CSK_HIP(hipEventCreateWithFlags(&P.last, hipEventDisableTiming));
-    if (P.used) CSK_HIP(hipStreamWaitEvent(s, P.last, 0));
+    // Consecutive users on one stream are ordered by it: no event or marker per call.
+    // On a change of stream the device is drained first (the previous stream may since
+    // have been destroyed, so nothing is recorded on it).
+    if (P.used && s != P.last_stream) CSK_HIP(hipDeviceSynchronize());
     a.scratch = P.buf;
     a.scratch_bytes = P.bytes;
     const cs_status st = dispatch_nc(a, strategy, grid_blocks, s);
-    CSK_HIP(hipEventRecord(P.last, s));
     P.used = true;
+    P.last_stream = s;
     return st;
 }
 
