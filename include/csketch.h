@@ -192,6 +192,45 @@ cs_status cs_update_timed(cs_sketch *h, int32_t rel, const uint32_t *keys, const
                           uint64_t n, void *stream, int32_t strategy, int32_t grid_blocks,
                           int32_t flags, void *ev_start, void *ev_stop);
 
+/* ------------------------------------------------------------------ autotuner */
+
+#define CS_TUNE_MAX_CANDIDATES 16
+
+typedef struct cs_tune_candidate {
+    int32_t strategy;          /* cs_update_strategy */
+    int32_t grid_blocks;       /* as in cs_update_ex (0 = automatic) */
+    int32_t flags;             /* CS_UPDATE_NO_COMPACT / CS_UPDATE_NO_COUNTERS16 */
+    int32_t valid;             /* 1: ran, counters equal the reference's; 0: not
+                                  applicable to this handle; -1: counters differed */
+    float ms;                  /* median of three timed runs, -1 if not valid */
+} cs_tune_candidate;
+
+typedef struct cs_tune_report {
+    int32_t n;                 /* candidates tried */
+    int32_t best;              /* index of the chosen one */
+    cs_tune_candidate cand[CS_TUNE_MAX_CANDIDATES];
+} cs_tune_report;
+
+/* Times every applicable update variant (strategy, launch width, kernel flags) on these
+ * tuples of relation `rel` (same arguments as cs_update; `flags` may carry
+ * CS_UPDATE_UNIT_WEIGHTS), each into private counters so the handle's sketch is left
+ * untouched, checks each variant's counters against the global-atomic kernel's
+ * (a variant that differs is never chosen), and records the fastest for this class:
+ * (device architecture, m, d, key columns, one-join columns or not, weight kind,
+ * floor(log2 n)).  cs_update / cs_update_ex with CS_UPDATE_AUTO then use it for every
+ * handle of that class.  Synchronous; allocates two d x m int64 buffers for its run.
+ * Errors: CS_EINVAL (arguments), CS_ENOMEM, CS_EDEVICE. */
+cs_status cs_tune_update(cs_sketch *h, int32_t rel, const uint32_t *keys, const int64_t *weights,
+                         uint64_t n, void *stream, int32_t flags, cs_tune_report *out);
+/* Forget every tuned choice. */
+cs_status cs_tune_clear(void);
+/* Write the tuned choices to a text file / merge those of a file written by
+ * cs_tune_save (CS_EINVAL if unreadable or malformed; nothing is merged then). */
+cs_status cs_tune_save(const char *path);
+cs_status cs_tune_load(const char *path);
+/* Number of tuned classes held. */
+cs_status cs_tune_count(int32_t *n_out);
+
 /* ------------------------------------------------------------------ estimate (Eq. 5, Alg. 3) */
 
 /* Estimate the join size: per repetition X_t (Eq. 5, evaluated as in Alg. 3), then

@@ -28,6 +28,7 @@ EXPORTED = [
     "cs_update", "cs_update_ex", "cs_update_timed", "cs_estimate", "cs_reset", "cs_merge", "cs_read_sketch",
     "cs_sketch_device_ptr", "cs_read_coeffs", "cs_read_components",
     "cs_timer_create", "cs_timer_record", "cs_timer_elapsed", "cs_timer_destroy",
+    "cs_tune_update", "cs_tune_clear", "cs_tune_save", "cs_tune_load", "cs_tune_count",
     "cs_batch_create", "cs_batch_destroy", "cs_batch_update", "cs_batch_capture", "cs_batch_replay",
     "cs_batch_estimate", "cs_batch_stats",
     "cs_server_create", "cs_server_destroy", "cs_server_add_query", "cs_server_remove_query",
@@ -56,6 +57,18 @@ class _Estimate(ctypes.Structure):
 class _Reps(ctypes.Structure):
     _fields_ = [("value", ctypes.c_void_p), ("lo", ctypes.c_void_p), ("hi", ctypes.c_void_p),
                 ("exact", ctypes.c_void_p), ("bound", ctypes.c_void_p)]
+
+
+class _TuneCand(ctypes.Structure):
+    _fields_ = [("strategy", ctypes.c_int32), ("grid_blocks", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("valid", ctypes.c_int32), ("ms", ctypes.c_float)]
+
+
+TUNE_MAX_CANDIDATES = 16
+
+
+class _TuneReport(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("best", ctypes.c_int32), ("cand", _TuneCand * TUNE_MAX_CANDIDATES)]
 
 
 class _Item(ctypes.Structure):
@@ -119,6 +132,11 @@ def lib() -> ctypes.CDLL:
         L.cs_timer_record.argtypes = [vp, vp]
         L.cs_timer_elapsed.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_float)]
         L.cs_timer_destroy.argtypes = [vp]
+        L.cs_tune_update.argtypes = [vp, i32, vp, vp, u64, vp, i32, ctypes.POINTER(_TuneReport)]
+        L.cs_tune_clear.argtypes = []
+        L.cs_tune_save.argtypes = [ctypes.c_char_p]
+        L.cs_tune_load.argtypes = [ctypes.c_char_p]
+        L.cs_tune_count.argtypes = [ctypes.POINTER(ctypes.c_int32)]
         L.cs_batch_create.argtypes = [ctypes.POINTER(vp)]
         L.cs_batch_destroy.argtypes = [vp]
         L.cs_batch_update.argtypes = [vp, ctypes.POINTER(_Item), i32, vp]
@@ -223,6 +241,41 @@ def _estimate_dict(e, arrs):
                 ints.append(None)
         out.update(rep_values=arrs["value"].tolist(), rep_ints=ints, rep_bounds=arrs["bound"].tolist())
     return out
+
+
+STRATEGY_NAMES = {UPDATE_GLOBAL_ATOMIC: "global_atomic", UPDATE_LDS_PRIVATE: "lds_segmented",
+                  UPDATE_WAVE_AGGREGATE: "wave_aggregate", UPDATE_PARTITION: "partition"}
+
+
+def tune_update(sketch: "Sketch", rel: int, keys, weights=None, unit_weights: bool = False, stream=None) -> dict:
+    """Autotune the update for this handle's class on these tuples (cs_tune_update);
+    returns the candidates with their median times and the chosen one."""
+    n = keys.shape[0]
+    rep = _TuneReport()
+    wp = None if weights is None else ctypes.c_void_p(weights.data_ptr())
+    _check(lib().cs_tune_update(sketch.handle, int(rel), ctypes.c_void_p(keys.data_ptr()), wp, int(n),
+                                _stream_ptr(stream), UPDATE_UNIT_WEIGHTS if unit_weights else 0, ctypes.byref(rep)))
+    cands = [dict(strategy=STRATEGY_NAMES.get(c.strategy, c.strategy), grid=c.grid_blocks, flags=c.flags,
+                  valid=int(c.valid), ms=float(c.ms)) for c in rep.cand[:rep.n]]
+    return {"candidates": cands, "best": cands[rep.best], "best_index": rep.best}
+
+
+def tune_clear():
+    _check(lib().cs_tune_clear())
+
+
+def tune_save(path: str):
+    _check(lib().cs_tune_save(str(path).encode()))
+
+
+def tune_load(path: str):
+    _check(lib().cs_tune_load(str(path).encode()))
+
+
+def tune_count() -> int:
+    n = ctypes.c_int32()
+    _check(lib().cs_tune_count(ctypes.byref(n)))
+    return n.value
 
 
 def sketch_bytes(graph, m: int, d: int) -> int:

@@ -17,6 +17,7 @@ SOURCES = [
     "csk_update.hip",
     "csk_transform.hip",
     "csk_estimate.hip",
+    "csk_tune.hip",
     "csk_batch.hip",
     "csk_serve.hip",
 ]

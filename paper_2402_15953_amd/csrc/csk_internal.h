@@ -106,8 +106,9 @@ struct SegGeom {
     int32_t segments;  // segments covering [d][m]
     int32_t chunks;    // tuple chunks (partial buffers)
 };
-SegGeom seg_geometry(uint32_t m, int32_t d, bool narrow, size_t scratch_bytes);
-SegGeom seg16_geometry(uint32_t m, int32_t d, size_t scratch_bytes);
+// n: tuples of the update (chunks shrink for small inputs); the default sizes buffers.
+SegGeom seg_geometry(uint32_t m, int32_t d, bool narrow, size_t scratch_bytes, uint64_t n = ~0ull);
+SegGeom seg16_geometry(uint32_t m, int32_t d, size_t scratch_bytes, uint64_t n = ~0ull);
 constexpr int kMaxPartRanges = 512;
 constexpr uint64_t kPartMaxChunk = 1ull << 21;
 struct PartGeom {
@@ -119,6 +120,8 @@ struct PartGeom {
 PartGeom part_geometry(uint32_t m, int32_t d, size_t scratch_bytes);
 size_t seg_scratch_bytes(uint32_t m, int32_t d);
 cs_status launch_update(const UpdateArgs &a, int strategy, int grid_blocks, hipStream_t s);
+// Tuned (strategy, grid, flags) for this update's class on `device`, if one was tuned.
+bool tune_lookup(const UpdateArgs &a, int device, int *strategy, int *grid, int *flags);
 int auto_update_strategy(uint32_t m, int32_t d, uint64_t n, int n_cols, bool unit, bool has_scratch);
 
 }  // namespace csk

@@ -695,7 +695,7 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
             const uint64_t cap = std::max<uint64_t>(1, a.scratch_bytes / (cells * elem));
             return (int32_t)std::min<uint64_t>((uint64_t)grid_blocks, std::min<uint64_t>(cap, 4096));
         };
-        SegGeom sg = seg_geometry(a.m, a.d, narrow, a.scratch_bytes);
+        SegGeom sg = seg_geometry(a.m, a.d, narrow, a.scratch_bytes, a.n);
         sg.chunks = chunks_for(sg.chunks, narrow ? 4 : 8);
         const uint64_t chunk = (a.n + sg.chunks - 1) / sg.chunks;
         dim3 grid((unsigned)sg.chunks, (unsigned)sg.segments);
@@ -717,7 +717,7 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
         cs_status st;
         if (narrow && a.m <= (1u << 16) && a.m > (1u << 15) && a.counters16) {
             // 16-bit LDS counters: a whole repetition per workgroup
-            SegGeom g16 = seg16_geometry(a.m, a.d, a.scratch_bytes);
+            SegGeom g16 = seg16_geometry(a.m, a.d, a.scratch_bytes, a.n);
             g16.chunks = chunks_for(g16.chunks, 2);
             const uint64_t chunk16 = (a.n + g16.chunks - 1) / g16.chunks;
             dim3 grid16((unsigned)g16.chunks, (unsigned)g16.segments);
@@ -801,7 +801,17 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
 
 }  // namespace
 
-SegGeom seg_geometry(uint32_t m, int32_t d, bool narrow, size_t scratch_bytes)
+// At least this many tuples per chunk: a small update runs on fewer workgroups rather
+// than paying each one's counter initialisation and partial-sum traffic.
+constexpr uint64_t kSegTuplesPerChunk = 32768;
+
+int32_t chunks_for_n(int32_t C, uint64_t n)
+{
+    const uint64_t by_n = (n + kSegTuplesPerChunk - 1) / kSegTuplesPerChunk;
+    return (int32_t)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)C, by_n));
+}
+
+SegGeom seg_geometry(uint32_t m, int32_t d, bool narrow, size_t scratch_bytes, uint64_t n)
 {
     SegGeom g{};
     // LDS per block: 128 KB of counters (one 1024-thread block per CU)
@@ -816,11 +826,11 @@ SegGeom seg_geometry(uint32_t m, int32_t d, bool narrow, size_t scratch_bytes)
     const uint64_t cap = std::max<uint64_t>(1, scratch_bytes / (cells * (narrow ? 4 : 8)));
     if ((uint64_t)C > cap) C = (int32_t)cap;
     if (C > 64) C = 64;
-    g.chunks = C;
+    g.chunks = chunks_for_n(C, n);
     return g;
 }
 
-SegGeom seg16_geometry(uint32_t m, int32_t d, size_t scratch_bytes)
+SegGeom seg16_geometry(uint32_t m, int32_t d, size_t scratch_bytes, uint64_t n)
 {
     SegGeom g{};
     g.R = 1u << 16;  // 16-bit counters in 128 KB of LDS
@@ -833,7 +843,7 @@ SegGeom seg16_geometry(uint32_t m, int32_t d, size_t scratch_bytes)
     const uint64_t cap = std::max<uint64_t>(1, scratch_bytes / (cells * 2));
     if ((uint64_t)C > cap) C = (int32_t)cap;
     if (C > 64) C = 64;
-    g.chunks = C;
+    g.chunks = chunks_for_n(C, n);
     return g;
 }
 
@@ -884,14 +894,15 @@ size_t seg_scratch_bytes(uint32_t m, int32_t d)
 
 int auto_update_strategy(uint32_t m, int32_t d, uint64_t n, int n_cols, bool unit, bool has_scratch)
 {
-    // Global atomics run at about 2.4e10/s on the whole chip, the hash at about
-    // 3e12 Horner steps/s: beyond small inputs the update must aggregate in LDS.
-    if (!has_scratch) return CS_UPDATE_GLOBAL_ATOMIC;
-    const SegGeom g = seg_geometry(m, d, unit, (size_t)-1);
-    const bool big = n >= (uint64_t)g.chunks * m * 2;
+    // Global atomics run at about 2.4e10/s on the whole chip (and far slower on the hot
+    // buckets of skewed keys), the hash at about 5e12 Horner steps/s: beyond a few
+    // microseconds of atomics the update aggregates in LDS, on as many chunks as the
+    // input fills (seg_geometry).
+    (void)m;
     (void)n_cols;
-    if (big) return CS_UPDATE_LDS_PRIVATE;
-    return CS_UPDATE_GLOBAL_ATOMIC;
+    (void)unit;
+    if (!has_scratch) return CS_UPDATE_GLOBAL_ATOMIC;
+    return n * (uint64_t)d >= 65536 ? CS_UPDATE_LDS_PRIVATE : CS_UPDATE_GLOBAL_ATOMIC;
 }
 
 namespace {
@@ -938,10 +949,20 @@ cs_status launch_update(const UpdateArgs &a_in, int strategy, int grid_blocks, h
     if (a_in.n == 0) return CS_OK;
     UpdateArgs a = a_in;
     const bool unit = a.weights == nullptr || a.unit_weights;
-    if (strategy == CS_UPDATE_AUTO) strategy = auto_update_strategy(a.m, a.d, a.n, a.plan.n_cols, unit, true);
-    if (strategy != CS_UPDATE_LDS_PRIVATE && strategy != CS_UPDATE_PARTITION) return dispatch_nc(a, strategy, grid_blocks, s);
     int dev = 0;
     CSK_HIP(hipGetDevice(&dev));
+    if (strategy == CS_UPDATE_AUTO) {
+        int ts = 0, tg = 0, tf = 0;
+        if (tune_lookup(a, dev, &ts, &tg, &tf)) {  // the autotuner's choice for this class
+            strategy = ts;
+            grid_blocks = tg;
+            a.compact = a.compact && (tf & CS_UPDATE_NO_COMPACT) == 0;
+            a.counters16 = a.counters16 && (tf & CS_UPDATE_NO_COUNTERS16) == 0;
+        } else {
+            strategy = auto_update_strategy(a.m, a.d, a.n, a.plan.n_cols, unit, true);
+        }
+    }
+    if (strategy != CS_UPDATE_LDS_PRIVATE && strategy != CS_UPDATE_PARTITION) return dispatch_nc(a, strategy, grid_blocks, s);
     ScratchPool &P = pool_of(dev);
     std::lock_guard<std::mutex> lk(P.mu);
     const size_t need = seg_scratch_bytes(a.m, a.d);

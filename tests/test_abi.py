@@ -47,3 +47,32 @@ def test_binding_refuses_without_gpu():
         pytest.skip("GPU present")
     with pytest.raises(RuntimeError):
         csk.Sketch(W.chain(3), 1024, 5, 7)
+
+
+def test_tune_table_file_roundtrip(tmp_path):
+    """The autotuner's table file: load, save, reload; a malformed file merges nothing."""
+    import paper_2402_15953_amd as csk
+    csk.tune_clear()
+    assert csk.tune_count() == 0
+    good = tmp_path / "tune.txt"
+    good.write_text("csketch-tune 1\n"
+                    "gfx950-256cu 65536 9 2 1 1 23 2 28 0 0.290000\n"
+                    "gfx950-256cu 4096 5 1 1 0 16 1 0 0 0.010000\n")
+    csk.tune_load(str(good))
+    assert csk.tune_count() == 2
+    out = tmp_path / "again.txt"
+    csk.tune_save(str(out))
+    lines = out.read_text().splitlines()
+    assert lines[0] == "csketch-tune 1"
+    assert sorted(lines[1:]) == sorted(good.read_text().splitlines()[1:])
+    bad = tmp_path / "bad.txt"
+    bad.write_text("csketch-tune 1\ngfx950-256cu 65536 9 2 1 1 23 7 28 0 0.29\n")   # strategy 7 does not exist
+    with pytest.raises(csk.CsError) as e:
+        csk.tune_load(str(bad))
+    assert e.value.status == csk.CS_EINVAL
+    assert csk.tune_count() == 2
+    (tmp_path / "nohdr.txt").write_text("gfx950-256cu 65536 9 2 1 1 23 2 28 0 0.29\n")
+    with pytest.raises(csk.CsError):
+        csk.tune_load(str(tmp_path / "nohdr.txt"))
+    csk.tune_clear()
+    assert csk.tune_count() == 0
