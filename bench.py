@@ -61,7 +61,7 @@ def parse():
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "update_seg16_chain3_1e7_m65536_d9_traffic.md")
-KERNEL_SOURCES = ["csk_update.hip", "csk_hash.h", "csk_internal.h"]
+KERNEL_SOURCES = ["csk_update.hip", "csk_hash.h", "csk_counters16.h", "csk_internal.h"]
 
 
 def kernel_source_digest() -> str:

@@ -19,6 +19,7 @@
 #include <new>
 #include <vector>
 
+#include "csk_counters16.h"
 #include "csk_handle.h"
 #include "csk_hash.h"
 #include "csk_internal.h"
@@ -139,13 +140,112 @@ __device__ void run_segment(const BItem &I, uint32_t seg, uint64_t begin, uint64
     __syncthreads();
 }
 
+// Segment task with exact 16-bit counters (every Delta +-1): R = 2^16 counters in
+// 128 KB, whole repetitions when m <= 2^16.  Keys of the next tuple are loaded while
+// this one is hashed, and each LDS add's returned value is checked one add later.
+// At the end, each non-zero counter is added into the sketch with one global atomic.
+template <int NC>
+__device__ void run_segment16(const BItem &I, uint32_t seg, uint64_t begin, uint64_t end, uint32_t *s_w)
+{
+    const uint64_t cells = (uint64_t)I.d << I.log2m;
+    const uint64_t cell0 = (uint64_t)seg * I.R;
+    const uint64_t cell1 = cell0 + I.R < cells ? cell0 + I.R : cells;
+    const uint32_t span = (uint32_t)(cell1 - cell0);  // even: R and m are even
+    const int t0 = (int)(cell0 >> I.log2m);
+    const int t1 = (int)((cell1 - 1) >> I.log2m);
+    const bool whole = I.R >= I.m;
+    unsigned long long *sk = reinterpret_cast<unsigned long long *>(I.sketch);
+    for (uint32_t e = threadIdx.x; e < span / 2; e += kBBlock) s_w[e] = (kBias16 << 16) | kBias16;
+    __syncthreads();
+    uint64_t i = begin + threadIdx.x;
+    uint32_t xn[NC];
+    int64_t wn = 0;
+    if (i < end) {
+        load_keys<NC>(I.keys, i, I.vec2 != 0, xn);
+        if (I.weights) wn = I.weights[i];
+    }
+    bool pend = false;
+    uint32_t p_old = 0, p_shift = 0, p_neg = 0;
+    uint64_t p_g = 0;
+    uint32_t *p_w = s_w;
+    for (; i < end; i += kBBlock) {
+        uint32_t x[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) x[c] = xn[c];
+        const int64_t wt = wn;
+        if (i + kBBlock < end) {
+            load_keys<NC>(I.keys, i + kBBlock, I.vec2 != 0, xn);
+            if (I.weights) wn = I.weights[i + kBBlock];
+        }
+        for (int t = t0; t <= t1; ++t) {
+            const uint64_t *cf = I.coef + (size_t)t * I.cpr;
+            uint32_t j, neg;
+            if (whole) {
+                hash_rep<NC>(cf, I.plan, x, j, neg);
+                j &= I.m - 1;
+            } else {
+                j = 0;
+                const uint64_t *cb = cf;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    j += (uint32_t)hash_deg1(cb, x[c]);
+                    cb += 2 + 4 * I.plan.n_edges[c];
+                }
+                j &= I.m - 1;
+                const uint64_t flat = ((uint64_t)t << I.log2m) + j;
+                if (flat < cell0 || flat >= cell1) continue;
+                neg = 0;
+                const uint64_t *cs = cf;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    cs += 2;
+                    for (int e = 0; e < I.plan.n_edges[c]; ++e) {
+                        neg ^= (uint32_t)hash_deg3(cs, x[c]) & 1u;
+                        cs += 4;
+                    }
+                }
+            }
+            if (wt < 0) neg ^= 1u;
+            const uint64_t g = ((uint64_t)t << I.log2m) + j;
+            const uint32_t loc = (uint32_t)(g - cell0);
+            const uint32_t shift = (loc & 1u) << 4;
+            uint32_t *w = &s_w[loc >> 1];
+            const uint32_t old = atomicAdd(w, neg ? (0xFFFFFFFFu << shift) : (1u << shift));
+            if (pend) {
+                const uint32_t h = ((p_old >> p_shift) & 0xFFFFu) + (p_neg ? 0xFFFFFFFFu : 1u);
+                if (h >= kHi16 || h <= kLo16) spill16(p_w, p_shift, sk + p_g);
+            }
+            pend = true;
+            p_old = old;
+            p_shift = shift;
+            p_neg = neg;
+            p_g = g;
+            p_w = w;
+        }
+    }
+    if (pend) {
+        const uint32_t h = ((p_old >> p_shift) & 0xFFFFu) + (p_neg ? 0xFFFFFFFFu : 1u);
+        if (h >= kHi16 || h <= kLo16) spill16(p_w, p_shift, sk + p_g);
+    }
+    __syncthreads();
+    unsigned long long *out = sk + cell0;
+    for (uint32_t e = threadIdx.x; e < span / 2; e += kBBlock) {
+        const uint32_t w = s_w[e];
+        const int64_t lo = (int64_t)(w & 0xFFFFu) - (int64_t)kBias16;
+        const int64_t hi = (int64_t)(w >> 16) - (int64_t)kBias16;
+        if (lo) atomicAdd(out + 2 * e, (unsigned long long)lo);
+        if (hi) atomicAdd(out + 2 * e + 1, (unsigned long long)hi);
+    }
+    __syncthreads();
+}
+
 template <int NC>
 __device__ void run_task(const BItem &I, const BTask &T, unsigned char *lds)
 {
     if (T.kind == 0) {
         run_atomic<NC>(I, T.begin, T.end);
     } else if (I.narrow) {
-        run_segment<NC, int32_t>(I, T.seg, T.begin, T.end, reinterpret_cast<int32_t *>(lds));
+        run_segment16<NC>(I, T.seg, T.begin, T.end, reinterpret_cast<uint32_t *>(lds));
     } else {
         run_segment<NC, int64_t>(I, T.seg, T.begin, T.end, reinterpret_cast<int64_t *>(lds));
     }
@@ -230,7 +330,8 @@ cs_status plan_batch(BatchState &B, const cs_update_item *items, int32_t n_items
         I.narrow = unit && it.n < (1ull << 31);
         I.vec2 = rp.n_cols == 2 && ((uintptr_t)it.keys % 8) == 0;
         for (int c = 0; c < kMaxCols; ++c) I.plan.n_edges[c] = c < rp.n_cols ? rp.n_edges[c] : 0;
-        uint32_t R = I.narrow ? (1u << 15) : (1u << 14);
+        // LDS segment: 2^16 16-bit counters (Deltas +-1) or 2^14 int64 counters
+        uint32_t R = I.narrow ? (1u << 16) : (1u << 14);
         if (h.m <= R) R = (R / h.m) * h.m;
         I.R = R;
         const int idx = (int)bi.size();
@@ -239,7 +340,9 @@ cs_status plan_batch(BatchState &B, const cs_update_item *items, int32_t n_items
         for (int c = 0; c < rp.n_cols; ++c) steps += 1 + 3 * rp.n_edges[c];
         const uint64_t cells = (uint64_t)h.d * h.m;
         const uint64_t tuple_reps = it.n * h.d;
-        if (tuple_reps < 16 * cells || it.n < 4096) {
+        // atomics only where aggregation cannot pay: a few microseconds of them at most
+        // (the segment task's fixed cost is zeroing and flushing its LDS counters)
+        if (tuple_reps < 65536 || tuple_reps < cells / 4) {
             // few tuples per counter: global atomics
             const uint64_t chunk = 1u << 16;
             for (uint64_t b = 0; b < it.n; b += chunk) {
