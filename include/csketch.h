@@ -115,6 +115,10 @@ typedef enum cs_update_strategy {
                                      bucket-range segments (testing and tuning) */
 #define CS_UPDATE_NO_COUNTERS16 4 /* segmented strategy: do not use 16-bit LDS counters
                                      (testing and tuning) */
+#define CS_UPDATE_TEST_FULL_REDUCTION 8 /* testing: most tuples take the full mod-p
+                                     reduction of their hashes, which otherwise only
+                                     hashes within 3 of a multiple of 2^61 - 1 need
+                                     (the counters are the same) */
 
 /* Estimate plans chosen at cs_create from the join graph. */
 typedef enum cs_plan_kind {

@@ -21,6 +21,7 @@ UPDATE_AUTO, UPDATE_GLOBAL_ATOMIC, UPDATE_LDS_PRIVATE, UPDATE_WAVE_AGGREGATE, UP
 UPDATE_UNIT_WEIGHTS = 1
 UPDATE_NO_COMPACT = 2
 UPDATE_NO_COUNTERS16 = 4
+UPDATE_TEST_FULL_REDUCTION = 8
 PLAN_DOT, PLAN_SPECTRAL, PLAN_GENERAL = 1, 2, 3
 
 EXPORTED = [
@@ -316,7 +317,8 @@ class Sketch:
         return {f: getattr(i, f) for f, _ in _Info._fields_}
 
     def update(self, rel: int, keys, weights=None, stream=None, strategy: int = UPDATE_AUTO, grid: int = 0,
-               unit_weights: bool = False, compact: bool = True, counters16: bool = True, timing=None):
+               unit_weights: bool = False, compact: bool = True, counters16: bool = True, timing=None,
+               extra_flags: int = 0):
         """keys: device int32/uint32 tensor [n, a_rel] (or [n] for one column), contiguous;
         weights: device int64 tensor [n] or None; unit_weights: every weight is +-1;
         timing: optional (start, stop) torch.cuda.Event pair recorded around the hashing
@@ -332,7 +334,7 @@ class Sketch:
                 raise TypeError("weights must be a contiguous int64 device tensor of length n")
             wp = ctypes.c_void_p(weights.data_ptr())
         flags = ((UPDATE_UNIT_WEIGHTS if unit_weights else 0) | (0 if compact else UPDATE_NO_COMPACT)
-                 | (0 if counters16 else UPDATE_NO_COUNTERS16))
+                 | (0 if counters16 else UPDATE_NO_COUNTERS16) | int(extra_flags))
         if timing is None:
             _check(lib().cs_update_ex(self._h, int(rel), ctypes.c_void_p(keys.data_ptr()), wp, int(n),
                                       _stream_ptr(stream), int(strategy), int(grid), flags))

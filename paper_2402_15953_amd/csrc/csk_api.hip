@@ -390,6 +390,7 @@ cs_status cs_update_timed(cs_sketch *hs, int32_t rel, const uint32_t *keys, cons
     a.unit_weights = (flags & CS_UPDATE_UNIT_WEIGHTS) != 0;
     a.compact = (flags & CS_UPDATE_NO_COMPACT) == 0;
     a.counters16 = (flags & CS_UPDATE_NO_COUNTERS16) == 0;
+    if (flags & CS_UPDATE_TEST_FULL_REDUCTION) a.canon_thresh = 0xF0000000u;
     a.ev_start = static_cast<hipEvent_t>(ev_start);
     a.ev_stop = static_cast<hipEvent_t>(ev_stop);
     return launch_update(a, strategy, grid_blocks, static_cast<hipStream_t>(stream));

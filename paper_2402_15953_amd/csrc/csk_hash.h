@@ -36,6 +36,24 @@ __device__ __forceinline__ uint64_t hstep(uint64_t v, uint32_t x, uint64_t a)
     return ((uint64_t)rh << 32) | rl;
 }
 
+// hstep on a value held as two 32-bit words (the form the kernels keep between steps:
+// joining and splitting 64-bit values costs the compiler extra moves).
+struct HPair {
+    uint32_t lo, hi;
+};
+__device__ __forceinline__ HPair hstep_p(HPair v, uint32_t x, uint64_t a)
+{
+    const uint64_t lo = (uint64_t)v.lo * (uint64_t)x;
+    const uint64_t t = (uint64_t)v.hi * (uint64_t)x + (lo >> 32);
+    const uint64_t s = (t >> 29) + a;
+    unsigned int carry;
+    HPair r;
+    r.lo = __builtin_addc((uint32_t)lo, (uint32_t)s, 0u, &carry);
+    r.hi = __builtin_addc((uint32_t)t & 0x1FFFFFFFu, (uint32_t)(s >> 32), carry, &carry);
+    return r;
+}
+__device__ __forceinline__ HPair hpair(uint64_t v) { return HPair{(uint32_t)v, (uint32_t)(v >> 32)}; }
+
 // Canonical residue in [0, p) of a redundant value r < 2^63.
 __device__ __forceinline__ uint64_t hcanon(uint64_t r)
 {
@@ -126,6 +144,30 @@ struct CoefE1 {
         for (int c = 0; c < NC; ++c)
             s ^= (uint32_t)hcanon(hstep(hstep(hstep(a[c][3], x[c], a[c][2]), x[c], a[c][1]), x[c], a[c][0])) & 1u;
         return s;
+    }
+    // bin() and neg() without the canonical reduction, for the common case.  A Horner
+    // result r < 2^63 is r = q 2^61 + u (q = r >> 61, u < 2^61), and r mod p = q + u -
+    // p [q + u >= p].  The bins need r mod p only modulo 2^32 and the signs only its
+    // parity; p = -1 (mod 2^32) and p is odd, so r mod p = r_lo + q + c (mod 2^32) and
+    // its parity is (r_lo ^ q ^ c) & 1, with c = [q + u >= p].  c can be 1 only when the
+    // top 29 bits of u are all ones (u >= p - 3); `flag` is the largest (r_hi | 0xE0000000)
+    // over the tuple's hashes, and a caller that finds flag >= 0xFFFFFFFF takes bin() and
+    // neg() instead (about once in 2^29 hashes).
+    __device__ __forceinline__ void bin_neg_fast(const uint32_t (&x)[NC], uint32_t &j, uint32_t &neg,
+                                                 uint32_t &flag) const
+    {
+        j = 0;
+        neg = 0;
+        flag = 0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const HPair rb = hstep_p(hpair(b1[c]), x[c], b0[c]);
+            j += rb.lo + (rb.hi >> 29);
+            const HPair rs = hstep_p(hstep_p(hstep_p(hpair(a[c][3]), x[c], a[c][2]), x[c], a[c][1]), x[c], a[c][0]);
+            neg ^= rs.lo ^ (rs.hi >> 29);
+            flag = max(flag, max(rb.hi | 0xE0000000u, rs.hi | 0xE0000000u));
+        }
+        neg &= 1u;
     }
 };
 

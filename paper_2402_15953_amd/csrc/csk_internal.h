@@ -98,6 +98,9 @@ struct UpdateArgs {
     bool unit_weights;      // caller guarantees every weight is +1 or -1
     bool compact = true;    // segmented strategy: compacting kernel for bucket-range segments
     bool counters16 = true; // segmented strategy: 16-bit LDS counters when they hold a repetition
+    // hashes whose flag (CoefE1::bin_neg_fast) reaches this take the full reduction; the
+    // exact bound is 0xFFFFFFFF, a test lowers it to send half of them that way
+    uint32_t canon_thresh = 0xFFFFFFFFu;
     hipEvent_t ev_start = nullptr;  // recorded just before / after the hashing kernel(s)
     hipEvent_t ev_stop = nullptr;
 };

@@ -283,7 +283,8 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16(const uint32_t *__re
                                                             const uint64_t *__restrict__ coef, int32_t cpr,
                                                             DevPlan plan, uint32_t m, int32_t log2m, int32_t d,
                                                             uint32_t R, uint64_t chunk, bool vec2,
-                                                            uint32_t *partial, unsigned long long *sketch)
+                                                            uint32_t *partial, unsigned long long *sketch,
+                                                            uint32_t canon_thresh)
 {
     extern __shared__ __align__(16) unsigned char s_raw[];
     uint32_t *s_w = reinterpret_cast<uint32_t *>(s_raw);  // [R / 2] words, two counters each
@@ -328,8 +329,13 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16(const uint32_t *__re
             }
             uint32_t j, neg;
             if constexpr (E1) {
-                j = K.bin(x) & (m - 1);
-                neg = K.neg(x);
+                uint32_t flag;
+                K.bin_neg_fast(x, j, neg, flag);
+                if (flag >= canon_thresh) {  // a hash may need the full reduction
+                    j = K.bin(x);
+                    neg = K.neg(x);
+                }
+                j &= m - 1;
             } else {
                 hash_rep<NC>(cf, plan, x, j, neg);
                 j &= m - 1;
@@ -702,7 +708,7 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
             CSK_MARK(a.ev_start, s);
             hipLaunchKernelGGL(kern, grid16, dim3(kSegBlock), lds16, s, a.keys, a.weights, a.n, a.coef,
                                a.plan.coef_per_rep, plan, a.m, log2m, a.d, g16.R, chunk16, vec2, part,
-                               reinterpret_cast<unsigned long long *>(a.sketch));
+                               reinterpret_cast<unsigned long long *>(a.sketch), a.canon_thresh);
             CSK_HIP(hipGetLastError());
             CSK_MARK(a.ev_stop, s);
             const uint64_t words = cells / 2;

@@ -24,13 +24,14 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _run_gpu(graph, rels, weights, m, d, seed, strategy=0, grid=0, unit=False, compact=True, counters16=True):
+def _run_gpu(graph, rels, weights, m, d, seed, strategy=0, grid=0, unit=False, compact=True, counters16=True,
+             extra_flags=0):
     sk = csk.Sketch(graph, m, d, seed)
     for k, keys in enumerate(rels):
         kd = to_device_keys(keys)
         wd = None if weights is None else torch.from_numpy(weights[k]).cuda()
         sk.update(k, kd, wd, strategy=strategy, grid=grid, unit_weights=unit, compact=compact,
-                  counters16=counters16)
+                  counters16=counters16, extra_flags=extra_flags)
     torch.cuda.synchronize()
     return sk
 
@@ -125,6 +126,23 @@ def test_sketch_segmented_kernel_variants(case, compact):
     info, co, ref = oracle_sketches(graph, rels, weights, m, d, 1000 + case)
     sk = _run_gpu(graph, rels, weights, m, d, 1000 + case, strategy=2, unit=(wk == "pm1"), compact=compact,
                   counters16=False)
+    for k in range(graph.n_rel):
+        assert np.array_equal(sk.read_sketch(k), ref[k]), k
+    sk.close()
+
+
+@pytest.mark.parametrize("case", range(len(SKETCH_CASES)))
+@pytest.mark.parametrize("strategy", [0, 2])
+def test_sketch_full_reduction_path(case, strategy):
+    """Hashes normally skip the full mod-p reduction (it changes a result only within 3 of
+    a multiple of p); with the test flag most tuples take it: the counters must not change."""
+    graph, n, m, d, dist, D, wk = SKETCH_CASES[case]
+    _say("sketch full-reduction path", case, graph.name, n, m, d, "strategy", strategy)
+    rels = _rels(graph, n, dist, D, config=90 + case)
+    weights = _weights(wk, graph, n)
+    info, co, ref = oracle_sketches(graph, rels, weights, m, d, 1000 + case)
+    sk = _run_gpu(graph, rels, weights, m, d, 1000 + case, strategy=strategy, unit=(wk == "pm1"),
+                  extra_flags=csk.UPDATE_TEST_FULL_REDUCTION)
     for k in range(graph.n_rel):
         assert np.array_equal(sk.read_sketch(k), ref[k]), k
     sk.close()
