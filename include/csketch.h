@@ -196,6 +196,35 @@ cs_status cs_update_timed(cs_sketch *h, int32_t rel, const uint32_t *keys, const
                           uint64_t n, void *stream, int32_t strategy, int32_t grid_blocks,
                           int32_t flags, void *ev_start, void *ev_stop);
 
+/* ------------------------------------------------------------------ filtered ingestion */
+
+#define CS_MAX_PREDICATES 8
+
+/* One range predicate on a non-join attribute column: lo <= value <= hi (uint32).  An
+ * equality is lo == hi; a one-sided bound uses 0 or 0xFFFFFFFF. */
+typedef struct cs_predicate {
+    int32_t column;            /* column of the attrs buffer */
+    uint32_t lo, hi;
+} cs_predicate;
+
+/* cs_update restricted to the tuples that satisfy every predicate (a conjunction): the
+ * query's filters applied while its relation streams in, so tuples that fail them never
+ * reach the sketch (the experimental setup of Sec. 4.1).
+ *   attrs: device, uint32 [n][n_attrs] tuple-major, the tuples' filtered columns
+ *          (1 <= n_attrs <= CS_MAX_PREDICATES); may be NULL when n_preds = 0.
+ *   preds: host array of n_preds (0..CS_MAX_PREDICATES) predicates.
+ *   flags: as cs_update_ex (CS_UPDATE_UNIT_WEIGHTS ...).
+ *   n_kept: optional, receives the number of tuples that passed.
+ * The qualifying tuples are first copied (keys, and weights when given; their order is
+ * not kept, which the counters do not depend on) into a per-device buffer that grows
+ * to the largest n seen; the call waits on `stream` for that pass to read the count
+ * back, then updates asynchronously like cs_update.
+ * Errors: CS_EINVAL (arguments), CS_ENOMEM, CS_EDEVICE. */
+cs_status cs_update_filtered(cs_sketch *h, int32_t rel, const uint32_t *keys, const int64_t *weights,
+                             uint64_t n, const uint32_t *attrs, int32_t n_attrs,
+                             const cs_predicate *preds, int32_t n_preds, int32_t flags, void *stream,
+                             uint64_t *n_kept);
+
 /* ------------------------------------------------------------------ autotuner */
 
 #define CS_TUNE_MAX_CANDIDATES 16

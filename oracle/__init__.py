@@ -284,6 +284,19 @@ def create_sketch(info: QueryInfo, k: int, keys, weights, m: int, coeffs: Coeffi
     return out
 
 
+def filter_rows(keys, weights, attrs, predicates):
+    """The tuples a query's filters keep (Sec. 4.1: filter predicates are applied while
+    the relation streams in, so failing tuples never reach the sketch): rows i with
+    lo <= attrs[i][col] <= hi for every (col, lo, hi).  Returns (keys, weights) of the
+    kept rows in input order (weights None stays None)."""
+    keys = np.asarray(keys)
+    attrs = np.asarray(attrs).astype(np.uint64).reshape(keys.shape[0], -1)
+    keep = np.ones(keys.shape[0], dtype=bool)
+    for col, lo, hi in predicates:
+        keep &= (attrs[:, col] >= lo) & (attrs[:, col] <= hi)
+    return keys[keep], (None if weights is None else np.asarray(weights)[keep])
+
+
 def create_sketch_py(info: QueryInfo, k: int, keys, weights, m: int, t: int,
                      sign_fn: Optional[Callable[[int, int], int]] = None,
                      bin_fn: Optional[Callable[[int, int], int]] = None,

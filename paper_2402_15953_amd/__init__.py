@@ -26,7 +26,7 @@ PLAN_DOT, PLAN_SPECTRAL, PLAN_GENERAL = 1, 2, 3
 
 EXPORTED = [
     "cs_create", "cs_destroy", "cs_sketch_bytes", "cs_get_info", "cs_last_error",
-    "cs_update", "cs_update_ex", "cs_update_timed", "cs_estimate", "cs_reset", "cs_merge", "cs_read_sketch",
+    "cs_update", "cs_update_ex", "cs_update_timed", "cs_update_filtered", "cs_estimate", "cs_reset", "cs_merge", "cs_read_sketch",
     "cs_sketch_device_ptr", "cs_read_coeffs", "cs_read_components",
     "cs_timer_create", "cs_timer_record", "cs_timer_elapsed", "cs_timer_destroy",
     "cs_tune_update", "cs_tune_clear", "cs_tune_save", "cs_tune_load", "cs_tune_count",
@@ -58,6 +58,13 @@ class _Estimate(ctypes.Structure):
 class _Reps(ctypes.Structure):
     _fields_ = [("value", ctypes.c_void_p), ("lo", ctypes.c_void_p), ("hi", ctypes.c_void_p),
                 ("exact", ctypes.c_void_p), ("bound", ctypes.c_void_p)]
+
+
+MAX_PREDICATES = 8
+
+
+class _Predicate(ctypes.Structure):
+    _fields_ = [("column", ctypes.c_int32), ("lo", ctypes.c_uint32), ("hi", ctypes.c_uint32)]
 
 
 class _TuneCand(ctypes.Structure):
@@ -122,6 +129,8 @@ def lib() -> ctypes.CDLL:
         L.cs_update.argtypes = [vp, i32, vp, vp, u64, vp]
         L.cs_update_ex.argtypes = [vp, i32, vp, vp, u64, vp, i32, i32, i32]
         L.cs_update_timed.argtypes = [vp, i32, vp, vp, u64, vp, i32, i32, i32, vp, vp]
+        L.cs_update_filtered.argtypes = [vp, i32, vp, vp, u64, vp, i32, ctypes.POINTER(_Predicate), i32, i32, vp,
+                                         ctypes.POINTER(u64)]
         L.cs_estimate.argtypes = [vp, vp, ctypes.POINTER(_Estimate), ctypes.POINTER(_Reps)]
         L.cs_reset.argtypes = [vp, vp]
         L.cs_merge.argtypes = [vp, vp, vp]
@@ -342,6 +351,31 @@ class Sketch:
             e0, e1 = _event_ptr(timing[0]), _event_ptr(timing[1])
             _check(lib().cs_update_timed(self._h, int(rel), ctypes.c_void_p(keys.data_ptr()), wp, int(n),
                                          _stream_ptr(stream), int(strategy), int(grid), flags, e0, e1))
+
+    def update_filtered(self, rel: int, keys, attrs, predicates, weights=None, stream=None,
+                        unit_weights: bool = False) -> int:
+        """Stream only the tuples whose attrs satisfy every (column, lo, hi) predicate
+        (lo <= attrs[i][column] <= hi); attrs: device int32/uint32 tensor [n, n_attrs].
+        Returns the number of tuples kept."""
+        import torch
+        if keys.dtype not in (torch.int32, torch.uint32) or not keys.is_cuda or not keys.is_contiguous():
+            raise TypeError("keys must be a contiguous int32/uint32 device tensor")
+        n = keys.shape[0]
+        preds = list(predicates)
+        arr = (_Predicate * max(1, len(preds)))(*[_Predicate(int(c), int(lo), int(hi)) for c, lo, hi in preds])
+        ap, n_attrs = None, 0
+        if attrs is not None:
+            if attrs.dtype not in (torch.int32, torch.uint32) or not attrs.is_cuda or not attrs.is_contiguous() \
+                    or attrs.shape[0] != n:
+                raise TypeError("attrs must be a contiguous int32/uint32 device tensor [n, n_attrs]")
+            ap = ctypes.c_void_p(attrs.data_ptr())
+            n_attrs = 1 if attrs.dim() == 1 else int(attrs.shape[1])
+        wp = None if weights is None else ctypes.c_void_p(weights.data_ptr())
+        kept = ctypes.c_uint64()
+        _check(lib().cs_update_filtered(self._h, int(rel), ctypes.c_void_p(keys.data_ptr()), wp, int(n), ap, n_attrs,
+                                        arr, len(preds), UPDATE_UNIT_WEIGHTS if unit_weights else 0,
+                                        _stream_ptr(stream), ctypes.byref(kept)))
+        return kept.value
 
     def estimate(self, stream=None, reps: bool = False) -> dict:
         e = _Estimate()

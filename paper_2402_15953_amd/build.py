@@ -18,6 +18,7 @@ SOURCES = [
     "csk_transform.hip",
     "csk_estimate.hip",
     "csk_tune.hip",
+    "csk_filter.hip",
     "csk_batch.hip",
     "csk_serve.hip",
 ]

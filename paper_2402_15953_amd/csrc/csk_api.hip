@@ -396,6 +396,43 @@ cs_status cs_update_timed(cs_sketch *hs, int32_t rel, const uint32_t *keys, cons
     return launch_update(a, strategy, grid_blocks, static_cast<hipStream_t>(stream));
 }
 
+cs_status cs_update_filtered(cs_sketch *hs, int32_t rel, const uint32_t *keys, const int64_t *weights, uint64_t n,
+                             const uint32_t *attrs, int32_t n_attrs, const cs_predicate *preds, int32_t n_preds,
+                             int32_t flags, void *stream, uint64_t *n_kept)
+{
+    if (!hs) return fail(CS_EINVAL, "null handle");
+    Handle &h = hs->h;
+    if (rel < 0 || rel >= h.g.n_rel) return fail(CS_EINVAL, "relation out of range");
+    if (n_kept) *n_kept = 0;
+    if (n == 0) return CS_OK;
+    if (!keys) return fail(CS_EINVAL, "null keys");
+    if (n_preds < 0 || n_preds > CS_MAX_PREDICATES) return fail(CS_EINVAL, "too many predicates");
+    if (n_preds > 0 && (!preds || !attrs || n_attrs <= 0 || n_attrs > CS_MAX_PREDICATES))
+        return fail(CS_EINVAL, "predicates need attribute columns");
+    FilterSpec f{};
+    f.n = n_preds;
+    for (int i = 0; i < n_preds; ++i) {
+        if (preds[i].column < 0 || preds[i].column >= n_attrs) return fail(CS_EINVAL, "predicate column out of range");
+        f.col[i] = preds[i].column;
+        f.lo[i] = preds[i].lo;
+        f.hi[i] = preds[i].hi;
+    }
+    if (n_preds == 0) {  // nothing to filter
+        if (n_kept) *n_kept = n;
+        return cs_update_ex(hs, rel, keys, weights, n, stream, CS_UPDATE_AUTO, 0, flags);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const uint32_t *fkeys = nullptr;
+    const int64_t *fw = nullptr;
+    uint64_t kept = 0;
+    cs_status st = filter_tuples(h.device, keys, h.g.rel[rel].n_cols, weights, n, attrs, n_attrs, f, s, &fkeys, &fw,
+                                 &kept);
+    if (st != CS_OK) return st;
+    if (n_kept) *n_kept = kept;
+    if (kept == 0) return CS_OK;
+    return cs_update_ex(hs, rel, fkeys, fw, kept, stream, CS_UPDATE_AUTO, 0, flags);
+}
+
 cs_status cs_update(cs_sketch *hs, int32_t rel, const uint32_t *keys, const int64_t *weights, uint64_t n,
                     void *stream)
 {

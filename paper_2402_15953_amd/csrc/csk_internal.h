@@ -123,6 +123,17 @@ struct PartGeom {
 PartGeom part_geometry(uint32_t m, int32_t d, size_t scratch_bytes);
 size_t seg_scratch_bytes(uint32_t m, int32_t d);
 cs_status launch_update(const UpdateArgs &a, int strategy, int grid_blocks, hipStream_t s);
+// Conjunction of range predicates lo <= attrs[i][col] <= hi (ingestion filters).
+struct FilterSpec {
+    int32_t n;
+    int32_t col[CS_MAX_PREDICATES];
+    uint32_t lo[CS_MAX_PREDICATES], hi[CS_MAX_PREDICATES];
+};
+// Copies the tuples (keys, and weights when given) that satisfy f into a per-device
+// buffer and returns it with their count (synchronous on s: the count is read back).
+cs_status filter_tuples(int device, const uint32_t *keys, int n_cols, const int64_t *weights, uint64_t n,
+                        const uint32_t *attrs, int n_attrs, const FilterSpec &f, hipStream_t s,
+                        const uint32_t **keys_out, const int64_t **weights_out, uint64_t *kept);
 // Tuned (strategy, grid, flags) for this update's class on `device`, if one was tuned.
 bool tune_lookup(const UpdateArgs &a, int device, int *strategy, int *grid, int *flags);
 int auto_update_strategy(uint32_t m, int32_t d, uint64_t n, int n_cols, bool unit, bool has_scratch);

@@ -194,6 +194,36 @@ def test_linearity_and_turnstile():
     assert not both.any()
 
 
+def test_filter_rows_pins():
+    """Filtered ingestion: the kept rows are exactly those a per-row check of every
+    predicate accepts (brute force), and their sketch equals the sketch of all rows with
+    the failing rows' Delta set to 0 (linearity: a zero change adds nothing)."""
+    graph = W.chain(3)
+    info = oracle.analyze(graph)
+    m = 64
+    coeffs = oracle.draw_coefficients(11, 3, len(info.edges), info.n_comp)
+    n = 3000
+    keys = W.relation_keys(graph, 1, n, "zipf", config=12, s=1.1, D=500).numpy()
+    w = W.random_weights(n, -50, 50, seed=4).numpy()
+    rng = np.random.default_rng(2)
+    attrs = rng.integers(0, 2 ** 32, size=(n, 3), dtype=np.uint64).astype(np.uint32)
+    attrs[:, 1] = rng.integers(0, 10, size=n)
+    preds = [(1, 2, 6), (0, 0, 0xC0000000), (2, 0x10000000, 0xFFFFFFFF)]
+    fk, fw = oracle.filter_rows(keys, w, attrs, preds)
+    brute = [i for i in range(n) if all(lo <= int(attrs[i, c]) <= hi for c, lo, hi in preds)]
+    assert 0 < len(brute) < n
+    assert np.array_equal(fk, keys[brute]) and np.array_equal(fw, w[brute])
+    zeroed = w.copy()
+    mask = np.zeros(n, dtype=bool)
+    mask[brute] = True
+    zeroed[~mask] = 0
+    assert np.array_equal(oracle.create_sketch(info, 1, fk, fw, m, coeffs),
+                          oracle.create_sketch(info, 1, keys, zeroed, m, coeffs))
+    # no predicate keeps everything; an empty range keeps nothing
+    assert len(oracle.filter_rows(keys, None, attrs, [])[0]) == n
+    assert len(oracle.filter_rows(keys, None, attrs, [(1, 5, 4)])[0]) == 0
+
+
 def test_counters_wrap_mod_2_64():
     info = oracle.analyze(W.single_join())
     coeffs = oracle.draw_coefficients(1, 1, 1, 1)
