@@ -253,9 +253,9 @@ def main():
         "estimate": {"value": res["value"], "exact": res["exact"], "n_modular": res["n_modular"]},
     }
 
-    sk.close()
     if args.filtered:
         out["filtered"] = bench_filtered(sk, keys, graph, dev, stream, args.steps)
+    sk.close()
     del keys
     torch.cuda.empty_cache()
     if args.batch_queries > 0:
