@@ -1,7 +1,7 @@
 // Ingestion filters (Sec. 4.1 processes each query's filter predicates while tuples
 // stream in): the tuples that satisfy a conjunction of range predicates on non-join
-// columns are copied into a per-device buffer, wavefront by wavefront (ballot, one
-// atomic reservation per wavefront), and only they are sketched.  The copy's order
+// columns are copied into a per-device buffer, tile by tile (one atomic reservation per
+// tile of 4096 tuples), and only they are sketched.  The copy's order
 // differs from the input's; the counters, integer sums, do not depend on it.
 #include <hip/hip_runtime.h>
 
@@ -19,34 +19,55 @@ constexpr int kFilterBlock = 256;
 
 __global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
 
+// A workgroup takes a tile of kFilterBlock x kFilterPer tuples (a thread's tuples are
+// kFilterBlock apart, so every load is coalesced), counts the tuples each thread keeps,
+// scans the counts in LDS, reserves the tile's slots with one atomic, and writes.
+constexpr int kFilterPer = 16;
+
 __global__ __launch_bounds__(kFilterBlock) void k_filter(const uint32_t *__restrict__ keys, int n_cols,
                                                          const int64_t *__restrict__ weights, uint64_t n,
                                                          const uint32_t *__restrict__ attrs, int n_attrs,
                                                          FilterSpec f, uint32_t *okeys, int64_t *ow,
                                                          unsigned long long *count)
 {
-    const int lane = threadIdx.x & 63;
-    // grid-stride over whole blocks, so every lane of a wavefront reaches the ballot
-    for (uint64_t base = (uint64_t)blockIdx.x * kFilterBlock; base < n;
-         base += (uint64_t)gridDim.x * kFilterBlock) {
-        const uint64_t i = base + threadIdx.x;
-        bool keep = i < n;
-        if (keep) {
-            for (int p = 0; p < f.n; ++p) {
-                const uint32_t v = attrs[i * (uint64_t)n_attrs + f.col[p]];
-                keep = keep && v >= f.lo[p] && v <= f.hi[p];
-            }
+    __shared__ uint32_t s_cnt[kFilterBlock];
+    __shared__ unsigned long long s_base;
+    const uint64_t tile = (uint64_t)kFilterBlock * kFilterPer;
+    for (uint64_t t0 = (uint64_t)blockIdx.x * tile; t0 < n; t0 += (uint64_t)gridDim.x * tile) {
+        uint32_t keep = 0;  // bit u: tuple t0 + u * kFilterBlock + threadIdx.x passes
+#pragma unroll
+        for (int u = 0; u < kFilterPer; ++u) {
+            const uint64_t i = t0 + (uint64_t)u * kFilterBlock + threadIdx.x;
+            bool k = i < n;
+            if (k)
+                for (int p = 0; p < f.n; ++p) {
+                    const uint32_t v = attrs[i * (uint64_t)n_attrs + f.col[p]];
+                    k = k && v >= f.lo[p] && v <= f.hi[p];
+                }
+            keep |= (uint32_t)k << u;
         }
-        const unsigned long long mask = __ballot(keep);
-        const int cnt = __popcll(mask);
-        unsigned long long at = 0;
-        if (lane == 0 && cnt) at = atomicAdd(count, (unsigned long long)cnt);
-        at = __shfl(at, 0, 64);
-        if (keep) {
-            const uint64_t o = at + (uint64_t)__popcll(mask & ((1ull << lane) - 1ull));
+        const uint32_t mine = __popc(keep);
+        s_cnt[threadIdx.x] = mine;
+        __syncthreads();
+        // inclusive scan of the per-thread counts (Hillis-Steele in LDS)
+        for (int off = 1; off < kFilterBlock; off <<= 1) {
+            const uint32_t add = threadIdx.x >= (unsigned)off ? s_cnt[threadIdx.x - off] : 0u;
+            __syncthreads();
+            s_cnt[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (threadIdx.x == kFilterBlock - 1)
+            s_base = s_cnt[threadIdx.x] ? atomicAdd(count, (unsigned long long)s_cnt[threadIdx.x]) : 0ull;
+        __syncthreads();
+        uint64_t o = s_base + s_cnt[threadIdx.x] - mine;
+        for (int u = 0; u < kFilterPer; ++u) {
+            if (!((keep >> u) & 1u)) continue;
+            const uint64_t i = t0 + (uint64_t)u * kFilterBlock + threadIdx.x;
             for (int c = 0; c < n_cols; ++c) okeys[o * n_cols + c] = keys[i * n_cols + c];
             if (weights) ow[o] = weights[i];
+            ++o;
         }
+        __syncthreads();  // s_cnt and s_base are rewritten by the next tile
     }
 }
 
@@ -101,7 +122,8 @@ cs_status filter_tuples(int device, const uint32_t *keys, int n_cols, const int6
     int64_t *ow = weights ? reinterpret_cast<int64_t *>(base + o_w) : nullptr;
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, count);
     CSK_HIP(hipGetLastError());
-    const uint64_t blocks = std::min<uint64_t>((n + kFilterBlock - 1) / kFilterBlock, 65536);
+    const uint64_t tile = (uint64_t)kFilterBlock * kFilterPer;
+    const uint64_t blocks = std::min<uint64_t>((n + tile - 1) / tile, 8192);
     hipLaunchKernelGGL(k_filter, dim3((unsigned)blocks), dim3(kFilterBlock), 0, s, keys, n_cols, weights, n, attrs,
                        n_attrs, f, okeys, ow, count);
     CSK_HIP(hipGetLastError());
