@@ -145,7 +145,10 @@ typedef struct cs_info_t {
 
 /* Validate the query, draw the hash coefficients (Alg. 1: SampleSignHashes and
  * SampleBinHashes; Sec. 3.2 initialization), allocate r*d*m int64 counters on the
- * current device and zero them.  m must be a power of two in [2, 2^20]; 1 <= d <= 64.
+ * current device and zero them.  2 <= m <= 2^20 (any m: buckets are h(x) mod m; a
+ * power of two unlocks the spectral plan, the partition strategy and the one-join
+ * kernels, an even m the 16-bit counters); 1 <= d <= 64.  With m not a power of two a
+ * graph of binary joins (r > 2) is estimated by the general plan.
  * Errors: CS_EINVAL, CS_EGRAPH, CS_ENOMEM, CS_EDEVICE. */
 cs_status cs_create(const cs_graph *graph, uint32_t m, uint32_t d, uint64_t seed,
                     cs_sketch **out);

@@ -16,7 +16,8 @@ What it computes, each function citing the passage it follows:
   estimate_eq5       the estimate X of Eq. 5 by direct enumeration of J
   estimate_alg3      Alg. 3 (GetQueryEstimate / CombineSketches) in exact integers;
                      the cross-correlation of Def. 3.1 is evaluated directly (small m)
-                     or modulo NTT primes with Chinese remaindering (any m)
+                     or modulo primes with Chinese remaindering (through the NTT when
+                     m is a power of two, term by term otherwise)
   median_lower       median of the d repetitions (Sec. 3.3; Sec. 4.1 uses l = 5)
   join_size          the exact cardinality E[X] of Thm. 3.1
   variance_bound     3^(r-1)/m * prod ||F_k||_2^2 of Thm. 3.1
@@ -380,8 +381,9 @@ class _ExactRing:
 
 
 class _ModRing:
-    """Vectors modulo an NTT prime p (< 2^31); cross-correlation through the
-    number-theoretic transform (a textbook radix-2 NTT), exact modulo p."""
+    """Vectors modulo a prime p (< 2^31) with m | p - 1; cross-correlation through the
+    number-theoretic transform (a textbook radix-2 NTT) when m is a power of two, by
+    its definition otherwise; exact modulo p."""
 
     def __init__(self, m, p, g):
         self.m, self.p, self.g = m, p, g
@@ -398,8 +400,18 @@ class _ModRing:
         return (a * b) % np.uint64(self.p)
 
     def correlate(self, a, x):
-        # a star x = (reverse a) * x, reverse(a)_i = a_{(-i) mod m} (circular convolution)
         m, p = self.m, self.p
+        if m & (m - 1):
+            # m not a power of two: Def. 3.1 term by term modulo p,
+            # (a star x)_j = sum_i a_i x_{(j+i) mod m}, rows j in blocks
+            out = np.empty(m, dtype=np.uint64)
+            i = np.arange(m)
+            for j0 in range(0, m, 256):
+                j = np.arange(j0, min(m, j0 + 256))
+                prod = (a[None, :] * x[(j[:, None] + i[None, :]) % m]) % np.uint64(p)
+                out[j0:j0 + len(j)] = np.sum(prod, axis=1, dtype=np.uint64) % np.uint64(p)
+            return out
+        # a star x = (reverse a) * x, reverse(a)_i = a_{(-i) mod m} (circular convolution)
         ar = a[(-np.arange(m)) % m]
         fa = ntt(ar, p, self.g)
         fx = ntt(x, p, self.g)
@@ -434,9 +446,10 @@ def estimate_alg3(info: QueryInfo, sketches: Sequence[Sequence[int]], m: int,
     """GetQueryEstimate of Alg. 3 for one repetition, exact.
 
     method 'direct': integer vectors, correlation by Def. 3.1 (O(m^2));
-    method 'ntt':    the same sequence of ring operations modulo enough NTT primes,
-                     then the Chinese remainder theorem; |X| <= prod_k ||c_k||_1 fixes
-                     how many primes are needed (requires m a power of two)."""
+    method 'ntt':    the same sequence of ring operations modulo enough primes, then
+                     the Chinese remainder theorem; |X| <= prod_k ||c_k||_1 fixes how
+                     many primes are needed.  Correlations go through the NTT when m is
+                     a power of two and term by term (Def. 3.1, O(m^2)) otherwise."""
     if method == "auto":
         method = "direct" if m <= 64 else "ntt"
     if method == "direct":

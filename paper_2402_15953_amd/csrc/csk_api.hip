@@ -177,7 +177,10 @@ cs_status analyze_graph(const cs_graph *g, GraphPlan *out)
             if (depth[k] & 1) P.conj_mask |= 1u << k;
     } else {
         P.plan = CS_PLAN_GENERAL;
-        // Alg. 3 (CombineSketches from root attribute 0) compiled to register ops.
+    }
+    if (r > 2) {
+        // Alg. 3 (CombineSketches from root attribute 0) compiled to register ops: the
+        // general plan's program, and the spectral plan's when m is not a power of two.
         std::vector<int> free_regs;
         int n_regs = 0;
         auto alloc = [&]() {
@@ -253,7 +256,7 @@ cs_status create_handle(const cs_graph *graph, uint32_t m, uint32_t d, uint64_t 
 {
     if (!out) return fail(CS_EINVAL, "null output handle");
     *out = nullptr;
-    if (m < 2 || m > (1u << kMaxLog2M) || (m & (m - 1))) return fail(CS_EINVAL, "m must be a power of two in [2, 2^20]");
+    if (m < 2 || m > (1u << kMaxLog2M)) return fail(CS_EINVAL, "m must be in [2, 2^20]");
     if (d < 1 || d > (uint32_t)kMaxD) return fail(CS_EINVAL, "d must be in [1, 64]");
     cs_sketch *hs = new (std::nothrow) cs_sketch();
     if (!hs) return fail(CS_ENOMEM, "host allocation failed");
@@ -264,7 +267,11 @@ cs_status create_handle(const cs_graph *graph, uint32_t m, uint32_t d, uint64_t 
         return st;
     }
     h.m = m;
-    h.log2m = 31 - __builtin_clz(m);
+    h.log2m = 31 - __builtin_clz(m);  // exact only when m is a power of two
+    h.pow2 = (m & (m - 1)) == 0;
+    // the frequency-domain plan needs power-of-two transforms; otherwise Alg. 3 runs as
+    // its register program (time-domain correlations through zero-padded transforms)
+    if (!h.pow2 && h.g.plan == CS_PLAN_SPECTRAL) h.g.plan = CS_PLAN_GENERAL;
     h.d = d;
     h.seed = seed;
     if (hipGetDevice(&h.device) != hipSuccess) {

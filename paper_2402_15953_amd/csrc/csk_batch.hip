@@ -69,7 +69,6 @@ __device__ void run_atomic(const BItem &I, uint64_t begin, uint64_t end)
         for (int t = 0; t < I.d; ++t, cf += I.cpr) {
             uint32_t j, neg;
             hash_rep<NC>(cf, I.plan, x, j, neg);
-            j &= I.m - 1;
             const uint64_t val = neg ? (uint64_t)0 - (uint64_t)delta : (uint64_t)delta;
             atomicAdd(reinterpret_cast<unsigned long long *>(I.sketch) + (size_t)t * I.m + j,
                       (unsigned long long)val);
@@ -80,12 +79,12 @@ __device__ void run_atomic(const BItem &I, uint64_t begin, uint64_t end)
 template <int NC, typename CT>
 __device__ void run_segment(const BItem &I, uint32_t seg, uint64_t begin, uint64_t end, CT *s_c)
 {
-    const uint64_t cells = (uint64_t)I.d << I.log2m;
+    const uint64_t cells = (uint64_t)I.d * I.m;
     const uint64_t cell0 = (uint64_t)seg * I.R;
     const uint64_t cell1 = cell0 + I.R < cells ? cell0 + I.R : cells;
     const uint32_t span = (uint32_t)(cell1 - cell0);
-    const int t0 = (int)(cell0 >> I.log2m);
-    const int t1 = (int)((cell1 - 1) >> I.log2m);
+    const int t0 = (int)(cell0 / I.m);
+    const int t1 = (int)((cell1 - 1) / I.m);
     const bool whole = I.R >= I.m;
     for (uint32_t e = threadIdx.x; e < span; e += kBBlock) s_c[e] = 0;
     __syncthreads();
@@ -98,30 +97,13 @@ __device__ void run_segment(const BItem &I, uint32_t seg, uint64_t begin, uint64
             uint32_t j, neg;
             if (whole) {
                 hash_rep<NC>(cf, I.plan, x, j, neg);
-                j &= I.m - 1;
             } else {
-                j = 0;
-                const uint64_t *cb = cf;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    j += (uint32_t)hash_deg1(cb, x[c]);
-                    cb += 2 + 4 * I.plan.n_edges[c];
-                }
-                j &= I.m - 1;
-                const uint64_t flat = ((uint64_t)t << I.log2m) + j;
+                j = hash_bin<NC>(cf, I.plan, x);
+                const uint64_t flat = (uint64_t)t * I.m + j;
                 if (flat < cell0 || flat >= cell1) continue;
-                neg = 0;
-                const uint64_t *cs = cf;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    cs += 2;
-                    for (int e = 0; e < I.plan.n_edges[c]; ++e) {
-                        neg ^= (uint32_t)hash_deg3(cs, x[c]) & 1u;
-                        cs += 4;
-                    }
-                }
+                neg = hash_neg<NC>(cf, I.plan, x);
             }
-            const uint32_t loc = (uint32_t)((((uint64_t)t << I.log2m) + j) - cell0);
+            const uint32_t loc = (uint32_t)(((uint64_t)t * I.m + j) - cell0);
             if constexpr (sizeof(CT) == 4) {
                 const int32_t v32 = (int32_t)delta;
                 atomicAdd(&s_c[loc], neg ? -v32 : v32);
@@ -147,12 +129,12 @@ __device__ void run_segment(const BItem &I, uint32_t seg, uint64_t begin, uint64
 template <int NC>
 __device__ void run_segment16(const BItem &I, uint32_t seg, uint64_t begin, uint64_t end, uint32_t *s_w)
 {
-    const uint64_t cells = (uint64_t)I.d << I.log2m;
+    const uint64_t cells = (uint64_t)I.d * I.m;
     const uint64_t cell0 = (uint64_t)seg * I.R;
     const uint64_t cell1 = cell0 + I.R < cells ? cell0 + I.R : cells;
     const uint32_t span = (uint32_t)(cell1 - cell0);  // even: R and m are even
-    const int t0 = (int)(cell0 >> I.log2m);
-    const int t1 = (int)((cell1 - 1) >> I.log2m);
+    const int t0 = (int)(cell0 / I.m);
+    const int t1 = (int)((cell1 - 1) / I.m);
     const bool whole = I.R >= I.m;
     unsigned long long *sk = reinterpret_cast<unsigned long long *>(I.sketch);
     for (uint32_t e = threadIdx.x; e < span / 2; e += kBBlock) s_w[e] = (kBias16 << 16) | kBias16;
@@ -182,31 +164,14 @@ __device__ void run_segment16(const BItem &I, uint32_t seg, uint64_t begin, uint
             uint32_t j, neg;
             if (whole) {
                 hash_rep<NC>(cf, I.plan, x, j, neg);
-                j &= I.m - 1;
             } else {
-                j = 0;
-                const uint64_t *cb = cf;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    j += (uint32_t)hash_deg1(cb, x[c]);
-                    cb += 2 + 4 * I.plan.n_edges[c];
-                }
-                j &= I.m - 1;
-                const uint64_t flat = ((uint64_t)t << I.log2m) + j;
+                j = hash_bin<NC>(cf, I.plan, x);
+                const uint64_t flat = (uint64_t)t * I.m + j;
                 if (flat < cell0 || flat >= cell1) continue;
-                neg = 0;
-                const uint64_t *cs = cf;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    cs += 2;
-                    for (int e = 0; e < I.plan.n_edges[c]; ++e) {
-                        neg ^= (uint32_t)hash_deg3(cs, x[c]) & 1u;
-                        cs += 4;
-                    }
-                }
+                neg = hash_neg<NC>(cf, I.plan, x);
             }
             if (wt < 0) neg ^= 1u;
-            const uint64_t g = ((uint64_t)t << I.log2m) + j;
+            const uint64_t g = (uint64_t)t * I.m + j;
             const uint32_t loc = (uint32_t)(g - cell0);
             const uint32_t shift = (loc & 1u) << 4;
             uint32_t *w = &s_w[loc >> 1];
@@ -327,9 +292,10 @@ cs_status plan_batch(BatchState &B, const cs_update_item *items, int32_t n_items
         I.log2m = h.log2m;
         I.d = (int32_t)h.d;
         const bool unit = it.weights == nullptr || (it.flags & CS_UPDATE_UNIT_WEIGHTS);
-        I.narrow = unit && it.n < (1ull << 31);
+        I.narrow = unit && it.n < (1ull << 31) && (h.m % 2) == 0;  // 16-bit pairs need even segments
         I.vec2 = rp.n_cols == 2 && ((uintptr_t)it.keys % 8) == 0;
         for (int c = 0; c < kMaxCols; ++c) I.plan.n_edges[c] = c < rp.n_cols ? rp.n_edges[c] : 0;
+        I.plan.bm = make_binmod(h.m);
         // LDS segment: 2^16 16-bit counters (Deltas +-1) or 2^14 int64 counters
         uint32_t R = I.narrow ? (1u << 16) : (1u << 14);
         if (h.m <= R) R = (R / h.m) * h.m;

@@ -215,6 +215,8 @@ struct SkDesc {
     int32_t log2m;
     int32_t nb;
     int64_t off;
+    uint32_t m;
+    uint32_t pad;
 };
 
 // One repetition t of query q.
@@ -222,6 +224,7 @@ struct RepDesc {
     const int64_t *c0;     // DOT plan: relation 0 and 1 at repetition t
     const int64_t *c1;
     int32_t q, t, log2m, r, d;
+    uint32_t m;            // buckets (log2m is exact only for powers of two)
     uint32_t conj;         // SPECTRAL: relations taken conjugated
     int32_t vec_base;      // SPECTRAL: first packed vector of query q in its group's buffer
     int32_t nb;            // blocks of this repetition's reductions
@@ -234,6 +237,7 @@ struct RepDesc {
 
 struct QDesc {
     int32_t plan, r, d, log2m, rep_base, nb;
+    uint32_t m;
 };
 
 // ---------------------------------------------------------------- kernels
@@ -258,7 +262,7 @@ __global__ __launch_bounds__(kThreads) void k_norms(const SkDesc *__restrict__ s
     const int item = find_item(prefix, n_items, blockIdx.x);
     const SkDesc S = sks[item];
     const int blk = (int)(blockIdx.x - prefix[item]);
-    const int64_t m = (int64_t)1 << S.log2m;
+    const int64_t m = S.m;
     double s2 = 0.0, s1 = 0.0;
     for (int64_t j = (int64_t)blk * kThreads + threadIdx.x; j < m; j += (int64_t)S.nb * kThreads) {
         const double v = (double)S.p[j];
@@ -283,7 +287,7 @@ __global__ __launch_bounds__(kThreads) void k_dot(const RepDesc *__restrict__ re
     const int item = find_item(prefix, n_items, blockIdx.x);
     const RepDesc D = reps[idx[item]];
     const int blk = (int)(blockIdx.x - prefix[item]);
-    const int64_t m = (int64_t)1 << D.log2m;
+    const int64_t m = D.m;
     __int128 acc = 0;
     for (int64_t j = (int64_t)blk * kThreads + threadIdx.x; j < m; j += (int64_t)D.nb * kThreads)
         acc += (__int128)D.c0[j] * (__int128)D.c1[j];
@@ -402,10 +406,9 @@ __global__ __launch_bounds__(kThreads) void k_spec_mod(const uint32_t *__restric
 
 // ---- general plan register operations, buffers [K][d][m] per register
 
-__global__ void k_mod_load(uint32_t *reg, const int64_t *__restrict__ sk, int log2m, int d,
+__global__ void k_mod_load(uint32_t *reg, const int64_t *__restrict__ sk, uint32_t m, int d,
                            const PrimeDev *__restrict__ primes)
 {
-    const int64_t m = (int64_t)1 << log2m;
     const int v = blockIdx.y;  // i * d + t
     const PrimeDev P = primes[v / d];
     const RingM R{P.p, P.pinv_neg};
@@ -415,9 +418,8 @@ __global__ void k_mod_load(uint32_t *reg, const int64_t *__restrict__ sk, int lo
         o[j] = mont_from_i64(R, c[j], P.r2, P.r3, P.neg2_64);
 }
 
-__global__ void k_mod_ones(uint32_t *reg, int log2m, int d, const PrimeDev *__restrict__ primes)
+__global__ void k_mod_ones(uint32_t *reg, uint32_t m, int d, const PrimeDev *__restrict__ primes)
 {
-    const int64_t m = (int64_t)1 << log2m;
     const int v = blockIdx.y;
     const uint32_t one = primes[v / d].one;
     uint32_t *o = reg + (size_t)v * m;
@@ -427,10 +429,9 @@ __global__ void k_mod_ones(uint32_t *reg, int log2m, int d, const PrimeDev *__re
 
 // dst = dst o src (time domain) or dst[pos] = src[-f] * dst[f] (frequency domain, the
 // pointwise step of the cross-correlation src star dst).
-__global__ void k_mod_mul(uint32_t *dst, const uint32_t *__restrict__ src, int log2m, int d,
+__global__ void k_mod_mul(uint32_t *dst, const uint32_t *__restrict__ src, uint32_t m, int log2m, int d,
                           const PrimeDev *__restrict__ primes, int negate_src)
 {
-    const uint32_t m = 1u << log2m;
     const int v = blockIdx.y;
     const PrimeDev P = primes[v / d];
     const RingM R{P.p, P.pinv_neg};
@@ -444,13 +445,12 @@ __global__ void k_mod_mul(uint32_t *dst, const uint32_t *__restrict__ src, int l
 }
 
 // Sum of register vector (prime i, repetition t) -> partials[i * plane + mod_off(rep) + b].
-__global__ __launch_bounds__(kThreads) void k_mod_sum(const uint32_t *__restrict__ reg, int log2m, int d,
+__global__ __launch_bounds__(kThreads) void k_mod_sum(const uint32_t *__restrict__ reg, uint32_t m, int d,
                                                       const PrimeDev *__restrict__ primes, int nb,
                                                       const RepDesc *__restrict__ reps, int rep_base,
                                                       int64_t plane, uint32_t *partials)
 {
     __shared__ uint32_t sh[kThreads];
-    const uint32_t m = 1u << log2m;
     const int v = blockIdx.y;  // i * d + t
     const int pi = v / d, t = v % d;
     const PrimeDev P = primes[pi];
@@ -465,6 +465,34 @@ __global__ __launch_bounds__(kThreads) void k_mod_sum(const uint32_t *__restrict
         __syncthreads();
     }
     if (threadIdx.x == 0) partials[(size_t)pi * plane + reps[rep_base + t].mod_off + blockIdx.x] = sh[0];
+}
+
+// Zero-padded copy of length-m register vectors into length-M buffers (M >= 2m - 1, a
+// power of two), reversed (i -> (m - i) mod m) when `reverse`: the operands of a linear
+// convolution whose wrap-around sum is the cross-correlation of Def. 3.1 for any m.
+__global__ void k_mod_pad(uint32_t *out, const uint32_t *__restrict__ in, uint32_t m, uint32_t M, int reverse)
+{
+    const int v = blockIdx.y;
+    const uint32_t *a = in + (size_t)v * m;
+    uint32_t *o = out + (size_t)v * M;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < M; i += gridDim.x * blockDim.x) {
+        uint32_t val = 0;
+        if (i < m) val = a[reverse ? (i == 0 ? 0 : m - i) : i];
+        o[i] = val;
+    }
+}
+
+// dst[j] = lin[j] + lin[j + m]: the circular (length m) result of a linear one.
+__global__ void k_mod_fold(uint32_t *dst, const uint32_t *__restrict__ lin, uint32_t m, uint32_t M, int d,
+                           const PrimeDev *__restrict__ primes)
+{
+    const int v = blockIdx.y;
+    const PrimeDev &P = primes[v / d];
+    const RingM R{P.p, P.pinv_neg};
+    const uint32_t *l = lin + (size_t)v * M;
+    uint32_t *o = dst + (size_t)v * m;
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x)
+        o[j] = j + m < M ? R.add(l[j], l[j + m]) : l[j];
 }
 
 // ---- finalize: one workgroup per query, one thread per repetition
@@ -507,7 +535,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinalizeArgs a)
     const QDesc Q = a.qs[blockIdx.x];
     const int t = threadIdx.x;
     const double u = 0x1p-53;
-    const double m = (double)(1u << Q.log2m);
+    const double m = (double)Q.m;
     const int plan = Q.plan;
     if (a.stage == 1 && plan != CS_PLAN_DOT) {
         // The partials of a query are contiguous: staged through LDS in chunks (every
@@ -825,7 +853,7 @@ bool is_prime_u32(uint64_t n)
 std::vector<PrimeInfo> build_primes()
 {
     std::vector<PrimeInfo> out;
-    const uint64_t step = 1ull << kMaxLog2M;
+    const uint64_t step = 1ull << kMaxLog2N;
     for (uint64_t c = ((1ull << 31) - 1) / step; c > 0 && (int)out.size() < kMaxPrimes; --c) {
         const uint64_t p = c * step + 1;
         if (p >= (1ull << 31) || !is_prime_u32(p)) continue;
@@ -839,7 +867,7 @@ std::vector<PrimeInfo> build_primes()
         const uint64_t m64 = P.r2;  // 2^64 mod p
         const uint64_t neg = (p - m64) % p;
         P.neg2_64 = (uint32_t)((unsigned __int128)neg * ((1ull << 32) % p) % p);
-        // generator: p - 1 = c * 2^20
+        // generator: p - 1 = c * 2^21
         std::vector<uint64_t> fs{2};
         uint64_t cc = c;
         for (uint64_t q = 2; q * q <= cc; ++q)
@@ -914,7 +942,7 @@ cs_status device_primes(int device, hipStream_t s, PrimeDev **out)
             D.r3 = P[i].r3;
             D.neg2_64 = P[i].neg2_64;
             D.one = (uint32_t)((1ull << 32) % P[i].p);
-            for (int L = 0; L <= kMaxLog2M; ++L) {
+            for (int L = 0; L <= kMaxLog2N; ++L) {
                 const uint64_t inv_m = powmod(powmod(2, L, P[i].p), P[i].p - 2, P[i].p);
                 D.minv[L] = (uint32_t)((unsigned __int128)inv_m * ((1ull << 32) % P[i].p) % P[i].p);
             }
@@ -1018,9 +1046,16 @@ namespace {
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int nblocks_for(int log2m)
+int ceil_log2(uint32_t x)
 {
-    size_t nb = ((size_t)1 << log2m) / (kThreads * 8);
+    int L = 0;
+    while ((1ull << L) < x) ++L;
+    return L;
+}
+
+int nblocks_for(uint32_t m)
+{
+    size_t nb = (size_t)m / (kThreads * 8);
     if (nb < 1) nb = 1;
     if (nb > 64) nb = 64;
     return (int)nb;
@@ -1069,12 +1104,13 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
     for (int q = 0; q < nq; ++q) {
         const Handle &h = *hs[q];
         const int r = h.g.n_rel, d = (int)h.d, L = h.log2m;
-        const int nb = nblocks_for(L);
+        const int nb = nblocks_for(h.m);
         QDesc &Q = qd[q];
         Q.plan = h.g.plan;
         Q.r = r;
         Q.d = d;
         Q.log2m = L;
+        Q.m = h.m;
         Q.rep_base = (int32_t)rd.size();
         Q.nb = nb;
         const int sk_base = (int)sd.size();
@@ -1085,6 +1121,7 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
                     SkDesc S;
                     S.p = h.counters + ((size_t)k * d + t) * m;
                     S.log2m = L;
+                    S.m = h.m;
                     S.nb = nb;
                     S.off = norm_off;
                     norm_off += nb;
@@ -1118,6 +1155,7 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
             D.q = q;
             D.t = t;
             D.log2m = L;
+            D.m = h.m;
             D.r = r;
             D.d = d;
             D.conj = h.g.conj_mask;
@@ -1376,6 +1414,9 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
             for (int t = 0; t < qd[q].d; ++t) K = std::max(K, hr[qd[q].rep_base + t].kprimes);
             if (K <= kdone) continue;
             mod_need += align_up((size_t)hs[q]->g.n_regs * K * qd[q].d * hs[q]->m * sizeof(uint32_t));
+            if (!hs[q]->pow2)
+                mod_need += 2 * align_up((size_t)K * qd[q].d * ((size_t)1 << ceil_log2(2 * hs[q]->m - 1)) *
+                                         sizeof(uint32_t));
         }
         if (ws.mod_bytes < mod_need) {
             if (ws.mod) hipFree(ws.mod);
@@ -1447,38 +1488,69 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
             for (int t = 0; t < qd[q].d; ++t) K = std::max(K, hr[qd[q].rep_base + t].kprimes);
             if (K <= kdone) continue;
             const Handle &h = *hs[q];
-            const int d = (int)h.d, L = h.log2m;
-            const size_t m = h.m;
+            const int d = (int)h.d;
+            const uint32_t m = h.m;
+            // transform length: m itself, or (m not a power of two) the power of two
+            // LM >= 2m - 1 of a zero-padded linear convolution
+            const int L = h.pow2 ? h.log2m : ceil_log2(2 * m - 1);
+            const uint32_t Mlen = 1u << L;
             const uint32_t *roots = roots_mod(device, L, 0, false, s, &st);
             if (!roots) return st;
             const size_t reg_elems = (size_t)K * d * m;
             uint32_t *M = reinterpret_cast<uint32_t *>(mod_cur);
             mod_cur += align_up((size_t)h.g.n_regs * reg_elems * sizeof(uint32_t));
-            const int gx = (int)std::min<size_t>(64, (m + 255) / 256);
+            uint32_t *padA = nullptr, *padB = nullptr;
+            if (!h.pow2) {
+                padA = reinterpret_cast<uint32_t *>(mod_cur);
+                mod_cur += align_up((size_t)K * d * Mlen * sizeof(uint32_t));
+                padB = reinterpret_cast<uint32_t *>(mod_cur);
+                mod_cur += align_up((size_t)K * d * Mlen * sizeof(uint32_t));
+            }
+            const int gx = (int)std::min<size_t>(64, ((size_t)m + 255) / 256);
+            const int gxM = (int)std::min<size_t>(256, ((size_t)Mlen + 255) / 256);
             for (const Op &op : h.g.ops) {
                 uint32_t *dst = M + (size_t)op.dst * reg_elems;
                 switch (op.code) {
                     case OP_LOAD:
                         hipLaunchKernelGGL(k_mod_load, dim3(gx, K * d), dim3(256), 0, s, dst,
-                                           h.counters + (size_t)op.src * d * m, L, d, primes);
+                                           h.counters + (size_t)op.src * d * m, m, d, primes);
                         break;
                     case OP_ONES:
-                        hipLaunchKernelGGL(k_mod_ones, dim3(gx, K * d), dim3(256), 0, s, dst, L, d, primes);
+                        hipLaunchKernelGGL(k_mod_ones, dim3(gx, K * d), dim3(256), 0, s, dst, m, d, primes);
                         break;
                     case OP_HAD:
                         hipLaunchKernelGGL(k_mod_mul, dim3(gx, K * d), dim3(256), 0, s, dst,
-                                           M + (size_t)op.src * reg_elems, L, d, primes, 0);
+                                           M + (size_t)op.src * reg_elems, m, 0, d, primes, 0);
                         break;
                     case OP_CORR: {
                         uint32_t *src = M + (size_t)op.src * reg_elems;
-                        st = ntt_forward(nullptr, d, K, src, L, primes, roots, L, s);
-                        if (st != CS_OK) return st;
-                        st = ntt_forward(nullptr, d, K, dst, L, primes, roots, L, s);
-                        if (st != CS_OK) return st;
-                        hipLaunchKernelGGL(k_mod_mul, dim3(gx, K * d), dim3(256), 0, s, dst, src, L, d, primes, 1);
-                        CSK_HIP(hipGetLastError());
-                        st = ntt_inverse(d, K, dst, L, primes, roots, L, s);
-                        if (st != CS_OK) return st;
+                        if (h.pow2) {
+                            st = ntt_forward(nullptr, d, K, src, L, primes, roots, L, s);
+                            if (st != CS_OK) return st;
+                            st = ntt_forward(nullptr, d, K, dst, L, primes, roots, L, s);
+                            if (st != CS_OK) return st;
+                            hipLaunchKernelGGL(k_mod_mul, dim3(gx, K * d), dim3(256), 0, s, dst, src, m, L, d, primes,
+                                               1);
+                            CSK_HIP(hipGetLastError());
+                            st = ntt_inverse(d, K, dst, L, primes, roots, L, s);
+                            if (st != CS_OK) return st;
+                        } else {
+                            // src star dst = reverse(src) circularly convolved with dst
+                            hipLaunchKernelGGL(k_mod_pad, dim3(gxM, K * d), dim3(256), 0, s, padA, src, m, Mlen, 1);
+                            hipLaunchKernelGGL(k_mod_pad, dim3(gxM, K * d), dim3(256), 0, s, padB, dst, m, Mlen, 0);
+                            CSK_HIP(hipGetLastError());
+                            st = ntt_forward(nullptr, d, K, padA, L, primes, roots, L, s);
+                            if (st != CS_OK) return st;
+                            st = ntt_forward(nullptr, d, K, padB, L, primes, roots, L, s);
+                            if (st != CS_OK) return st;
+                            hipLaunchKernelGGL(k_mod_mul, dim3(gxM, K * d), dim3(256), 0, s, padB, padA, Mlen, L, d,
+                                               primes, 0);
+                            CSK_HIP(hipGetLastError());
+                            st = ntt_inverse(d, K, padB, L, primes, roots, L, s);
+                            if (st != CS_OK) return st;
+                            hipLaunchKernelGGL(k_mod_fold, dim3(gx, K * d), dim3(256), 0, s, dst, padB, m, Mlen, d,
+                                               primes);
+                        }
                         break;
                     }
                     default:
@@ -1487,7 +1559,7 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
                 CSK_HIP(hipGetLastError());
             }
             hipLaunchKernelGGL(k_mod_sum, dim3(qd[q].nb, K * d), dim3(kThreads), 0, s,
-                               M + (size_t)h.g.result_reg * reg_elems, L, d, primes, qd[q].nb, d_rep, qd[q].rep_base,
+                               M + (size_t)h.g.result_reg * reg_elems, m, d, primes, qd[q].nb, d_rep, qd[q].rep_base,
                                mod_plane, d_modp);
             CSK_HIP(hipGetLastError());
         }

@@ -47,6 +47,7 @@ struct Handle {
     int device = 0;
     uint32_t m = 0;
     int32_t log2m = 0;
+    bool pow2 = true;
     uint32_t d = 0;
     uint64_t seed = 0;
     GraphPlan g;

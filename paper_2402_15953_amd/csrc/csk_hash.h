@@ -73,9 +73,29 @@ __device__ __forceinline__ uint64_t hash_deg3(const uint64_t *a, uint32_t x)
     return hcanon(hstep(hstep(hstep(a[3], x, a[2]), x, a[1]), x, a[0]));
 }
 
-// Per-relation hashing plan as the kernels read it: joins at each key column.
+// Bucket of a tuple: j = (sum of its columns' canonical bin values) mod m (the sum is
+// below 8 * 2^61 < 2^64).  A power-of-two m keeps the low bits; any other m uses a
+// Barrett reduction with mdiv = floor((2^64 - 1) / m), whose quotient estimate is at most
+// two below the true one.
+struct BinMod {
+    uint32_t m;
+    uint32_t pow2;
+    uint64_t mdiv;
+    __device__ __forceinline__ uint32_t reduce(uint64_t s) const
+    {
+        if (pow2) return (uint32_t)s & (m - 1);
+        uint64_t r = s - __umul64hi(s, mdiv) * (uint64_t)m;
+        if (r >= m) r -= m;
+        if (r >= m) r -= m;
+        return (uint32_t)r;
+    }
+};
+
+// Per-relation hashing plan as the kernels read it: joins at each key column and the
+// bucket reduction.
 struct DevPlan {
     int32_t n_edges[kMaxCols];
+    BinMod bm;
 };
 
 template <int NC>
@@ -95,17 +115,17 @@ __device__ __forceinline__ void load_keys(const uint32_t *__restrict__ keys, uin
 }
 
 // Hash one tuple for one repetition; `cf` points at that repetition's coefficients
-// (per column: b0, b1, then a0..a3 per join).  Returns the bin (mod 2^32; caller masks)
-// and the sign bit (1 = negative).
+// (per column: b0, b1, then a0..a3 per join).  Returns the bucket j in [0, m) and the
+// sign bit (1 = negative).
 template <int NC>
 __device__ __forceinline__ void hash_rep(const uint64_t *__restrict__ cf, const DevPlan &plan,
                                          const uint32_t (&x)[NC], uint32_t &j, uint32_t &neg)
 {
-    j = 0;
+    uint64_t js = 0;
     neg = 0;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        j += (uint32_t)hash_deg1(cf, x[c]);
+        js += hash_deg1(cf, x[c]);
         cf += 2;
         const int ne = plan.n_edges[c];
         for (int e = 0; e < ne; ++e) {
@@ -113,6 +133,47 @@ __device__ __forceinline__ void hash_rep(const uint64_t *__restrict__ cf, const 
             cf += 4;
         }
     }
+    j = plan.bm.reduce(js);
+}
+
+// Bucket only (for segments holding a bucket range, where signs are needed only for
+// tuples inside the range).
+template <int NC>
+__device__ __forceinline__ uint32_t hash_bin(const uint64_t *__restrict__ cf, const DevPlan &plan,
+                                             const uint32_t (&x)[NC])
+{
+    uint64_t js = 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        js += hash_deg1(cf, x[c]);
+        cf += 2 + 4 * plan.n_edges[c];
+    }
+    return plan.bm.reduce(js);
+}
+
+template <int NC>
+__device__ __forceinline__ uint32_t hash_neg(const uint64_t *__restrict__ cf, const DevPlan &plan,
+                                             const uint32_t (&x)[NC])
+{
+    uint32_t neg = 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        cf += 2;
+        for (int e = 0; e < plan.n_edges[c]; ++e) {
+            neg ^= (uint32_t)hash_deg3(cf, x[c]) & 1u;
+            cf += 4;
+        }
+    }
+    return neg;
+}
+
+__host__ __device__ inline BinMod make_binmod(uint32_t m)
+{
+    BinMod b;
+    b.m = m;
+    b.pow2 = (m & (m - 1)) == 0 ? 1u : 0u;
+    b.mdiv = ~0ull / m;
+    return b;
 }
 
 // Coefficients of one repetition for relations whose every key column takes part in

@@ -17,6 +17,7 @@ constexpr int kMaxCols = 8;          // attributes per relation
 constexpr int kMaxEdgesPerAttr = 8;  // joins per attribute
 constexpr int kMaxD = 64;
 constexpr int kMaxLog2M = 20;
+constexpr int kMaxLog2N = kMaxLog2M + 1;  // longest transform: a zero-padded correlation for m not a power of two
 constexpr int kMaxPrimes = 12;       // modular path: up to ~370-bit results
 constexpr uint64_t kP61 = (1ull << 61) - 1;
 
@@ -69,7 +70,7 @@ struct PrimeInfo {
     uint32_t neg2_64;    // (-2^64 * R) mod p: Montgomery form of -2^64
     uint32_t g;          // generator of the multiplicative group
 };
-// NTT primes p < 2^31 with 2^kMaxLog2M | p - 1, largest first (host table).
+// NTT primes p < 2^31 with 2^kMaxLog2N | p - 1, largest first (host table).
 const std::vector<PrimeInfo> &ntt_primes();
 
 // ------------------------------------------------------------------ device tables

@@ -32,7 +32,7 @@ struct PrimeDev {
     uint32_t r3;         // 2^96 mod p
     uint32_t neg2_64;    // Montgomery form of -2^64 mod p
     uint32_t one;        // Montgomery form of 1 (2^32 mod p)
-    uint32_t minv[kMaxLog2M + 1];  // Montgomery form of 2^-L mod p
+    uint32_t minv[kMaxLog2N + 1];  // Montgomery form of 2^-L mod p
 };
 
 // Position of frequency f in the output of the forward transform of length 2^log2m.

@@ -49,7 +49,6 @@ __global__ __launch_bounds__(kBlock) void k_update_global(const uint32_t *__rest
         for (int t = 0; t < d; ++t, cf += cpr) {
             uint32_t j, neg;
             hash_rep<NC>(cf, plan, x, j, neg);
-            j &= m - 1;
             const uint64_t val = neg ? (uint64_t)0 - (uint64_t)delta : (uint64_t)delta;
             atomicAdd(sketch + (size_t)t * m + j, (unsigned long long)val);
         }
@@ -90,7 +89,6 @@ __global__ __launch_bounds__(kBlock) void k_update_waveagg(const uint32_t *__res
         for (int t = 0; t < d; ++t, cf += cpr) {
             uint32_t j, neg;
             hash_rep<NC>(cf, plan, x, j, neg);
-            j &= m - 1;
             const uint64_t val = neg ? (uint64_t)0 - (uint64_t)delta : (uint64_t)delta;
             const uint32_t key = valid ? j : 0xFFFFFFFFu;
             s_bin[threadIdx.x] = key;
@@ -129,12 +127,12 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg(const uint32_t *__rest
 {
     extern __shared__ __align__(16) unsigned char s_raw[];
     CT *s_c = reinterpret_cast<CT *>(s_raw);
-    const uint64_t cells = (uint64_t)d << log2m;
+    const uint64_t cells = (uint64_t)d * m;
     const uint64_t cell0 = (uint64_t)blockIdx.y * R;
     const uint64_t cell1 = cell0 + R < cells ? cell0 + R : cells;
     const uint32_t span = (uint32_t)(cell1 - cell0);
-    const int t0 = (int)(cell0 >> log2m);
-    const int t1 = (int)((cell1 - 1) >> log2m);
+    const int t0 = (int)(cell0 / m);
+    const int t1 = (int)((cell1 - 1) / m);
     const bool whole = R >= m;
     for (uint32_t e = threadIdx.x; e < span; e += kSegBlock) s_c[e] = 0;
     __syncthreads();
@@ -145,40 +143,23 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg(const uint32_t *__rest
         const uint64_t *cf = coef + (size_t)t * cpr;
         CoefE1<NC> K;
         if constexpr (E1) K.load(cf);
-        const uint32_t row = (uint32_t)(((uint64_t)t << log2m) - cell0);  // may wrap; used mod 2^32
+        const uint32_t row = (uint32_t)((uint64_t)t * m - cell0);  // may wrap; used mod 2^32
         for (uint64_t i = begin + threadIdx.x; i < end; i += kSegBlock) {
             uint32_t x[NC];
             load_keys<NC>(keys, i, vec2, x);
             uint32_t j, neg;
-            if constexpr (E1) {
+            if constexpr (E1) {  // power-of-two m only
                 j = K.bin(x) & (m - 1);
                 const uint32_t loc = row + j;
                 if (!whole && loc >= span) continue;  // bucket outside this segment
                 neg = K.neg(x);
             } else if (whole) {
                 hash_rep<NC>(cf, plan, x, j, neg);
-                j &= m - 1;
             } else {
                 // bins first; signs only for buckets inside this segment
-                j = 0;
-                const uint64_t *cb = cf;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    j += (uint32_t)hash_deg1(cb, x[c]);
-                    cb += 2 + 4 * plan.n_edges[c];
-                }
-                j &= m - 1;
+                j = hash_bin<NC>(cf, plan, x);
                 if (row + j >= span) continue;
-                neg = 0;
-                const uint64_t *cs = cf;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    cs += 2;
-                    for (int e = 0; e < plan.n_edges[c]; ++e) {
-                        neg ^= (uint32_t)hash_deg3(cs, x[c]) & 1u;
-                        cs += 4;
-                    }
-                }
+                neg = hash_neg<NC>(cf, plan, x);
             }
             const uint32_t loc = row + j;
             const int64_t delta = weights ? weights[i] : 1;
@@ -288,12 +269,12 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16(const uint32_t *__re
 {
     extern __shared__ __align__(16) unsigned char s_raw[];
     uint32_t *s_w = reinterpret_cast<uint32_t *>(s_raw);  // [R / 2] words, two counters each
-    const uint64_t cells = (uint64_t)d << log2m;
+    const uint64_t cells = (uint64_t)d * m;
     const uint64_t cell0 = (uint64_t)blockIdx.y * R;
     const uint64_t cell1 = cell0 + R < cells ? cell0 + R : cells;
-    const uint32_t span = (uint32_t)(cell1 - cell0);  // even: R and m are even
-    const int t0 = (int)(cell0 >> log2m);
-    const int t1 = (int)((cell1 - 1) >> log2m);
+    const uint32_t span = (uint32_t)(cell1 - cell0);  // even: R is even (so is cells)
+    const int t0 = (int)(cell0 / m);
+    const int t1 = (int)((cell1 - 1) / m);
     for (uint32_t e = threadIdx.x; e < span / 2; e += kSegBlock) s_w[e] = (kBias16 << 16) | kBias16;
     __syncthreads();
     const uint64_t begin = (uint64_t)blockIdx.x * chunk;
@@ -302,8 +283,8 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16(const uint32_t *__re
         const uint64_t *cf = coef + (size_t)t * cpr;
         CoefE1<NC> K;
         if constexpr (E1) K.load(cf);
-        const uint32_t row = (uint32_t)(((uint64_t)t << log2m) - cell0);
-        unsigned long long *srow = sketch + ((uint64_t)t << log2m);
+        const uint32_t row = (uint32_t)((uint64_t)t * m - cell0);
+        unsigned long long *srow = sketch + (uint64_t)t * m;
         // Software pipeline: the next tuple's keys (and weight) are loaded while this one
         // is hashed, and the value an LDS add returns is checked one tuple later, so
         // neither latency stalls the wavefront.  Deferring the check lets a thread have
@@ -338,7 +319,6 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16(const uint32_t *__re
                 j &= m - 1;
             } else {
                 hash_rep<NC>(cf, plan, x, j, neg);
-                j &= m - 1;
             }
             if (wt < 0) neg ^= 1u;
             const uint32_t loc = row + j;
@@ -642,6 +622,8 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
 {
     DevPlan plan{};
     for (int c = 0; c < kMaxCols; ++c) plan.n_edges[c] = c < a.plan.n_cols ? a.plan.n_edges[c] : 0;
+    plan.bm = make_binmod(a.m);
+    const bool pow2 = plan.bm.pow2 != 0;
     const bool vec2 = NC == 2 && ((uintptr_t)a.keys % 8) == 0;
     auto *sk = reinterpret_cast<unsigned long long *>(a.sketch);
     int dev = 0;
@@ -683,6 +665,7 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
         while ((1u << log2m) < a.m) ++log2m;
         bool e1 = true;
         for (int c = 0; c < a.plan.n_cols; ++c) e1 = e1 && a.plan.n_edges[c] == 1;
+        e1 = e1 && pow2;  // the one-join kernels reduce buckets by masking
         auto launch = [&](auto kern, auto *part) -> cs_status {
             CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -694,7 +677,7 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
             return CS_OK;
         };
         cs_status st;
-        if (narrow && a.m <= (1u << 16) && a.m > (1u << 15) && a.counters16) {
+        if (narrow && a.m <= (1u << 16) && a.m > (1u << 15) && (a.m % 2) == 0 && a.counters16) {
             // 16-bit LDS counters: a whole repetition per workgroup
             SegGeom g16 = seg16_geometry(a.m, a.d, a.scratch_bytes, a.n);
             g16.chunks = chunks_for(g16.chunks, 2);
@@ -749,6 +732,7 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
     }
     if (strategy == CS_UPDATE_PARTITION) {
         if constexpr (NC > 2) return fail(CS_EINVAL, "the partition strategy handles at most 2 key columns");
+        if (!pow2) return fail(CS_EINVAL, "the partition strategy needs a power-of-two m");
         if (a.weights && !a.unit_weights)
             return fail(CS_EINVAL, "the partition strategy needs weights NULL or flagged as +-1");
         if (!a.scratch) return fail(CS_EINVAL, "the partition strategy needs a scratch buffer");

@@ -71,7 +71,7 @@ def test_partition_strategy_refuses_general_weights():
 
 def test_invalid_arguments_rejected():
     with pytest.raises(csk.CsError) as e:
-        csk.Sketch(W.chain(3), 1000, 5, 1)   # m not a power of two
+        csk.Sketch(W.chain(3), (1 << 20) + 1, 5, 1)   # m above 2^20
     assert e.value.status == csk.CS_EINVAL
     with pytest.raises(csk.CsError) as e:
         csk.Sketch(W.JoinGraph(3, (0, 1, 2), ((0, 1), (1, 2), (0, 2))), 1024, 5, 1)

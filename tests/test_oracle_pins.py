@@ -253,7 +253,7 @@ def _random_sketches(info, m, seed, lo=-9, hi=9):
 
 @pytest.mark.parametrize("graph", [W.single_join(), W.chain(3), W.chain(4), W.star(4), W.fig3_query(),
                                    W.multiway_star(3), W.chain(5)])
-@pytest.mark.parametrize("m", [1, 2, 4, 8])
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 6, 8])
 def test_eq5_equals_alg3_all_roots(graph, m):
     info = oracle.analyze(graph)
     c = _random_sketches(info, m, seed=m * 7 + info.n_rel)
@@ -268,6 +268,17 @@ def test_alg3_ntt_equals_direct_large_values():
     m = 32
     c = _random_sketches(info, m, seed=3, lo=-2 ** 62, hi=2 ** 62)
     assert oracle.estimate_alg3(info, c, m, method="ntt") == oracle.estimate_alg3(info, c, m, method="direct")
+
+
+@pytest.mark.parametrize("m", [24, 100])
+def test_alg3_modular_equals_direct_any_m(m):
+    """m not a power of two: the modular route (correlations by Def. 3.1 modulo each
+    prime, Chinese remaindering) against exact integer vectors, with values large enough
+    to need several primes."""
+    for graph in (W.chain(4), W.fig3_query(), W.multiway_star(3)):
+        info = oracle.analyze(graph)
+        c = _random_sketches(info, m, seed=m + info.n_rel, lo=-2 ** 40, hi=2 ** 40)
+        assert oracle.estimate_alg3(info, c, m, method="ntt") == oracle.estimate_alg3(info, c, m, method="direct")
 
 
 def test_fig3_closed_form():
