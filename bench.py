@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--batch-queries", type=int, default=4096,
                     help="batched section: chain/star queries (0 skips the section)")
     ap.add_argument("--serve-queries", type=int, default=256, help="serving section: live queries (0 skips)")
+    ap.add_argument("--anym", type=str, default="1000000,1048576",
+                    help="bucket-count section: chain-3 steps at these m with d = 5 (empty skips)")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="serving section: seconds per load level")
     ap.add_argument("--serve-rates", type=str, default="250,1000,4000,16000",
                     help="serving section: offered update-batch arrival rates (batches/s)")
@@ -256,6 +258,8 @@ def main():
     if args.filtered:
         out["filtered"] = bench_filtered(sk, keys, graph, dev, stream, args.steps)
     sk.close()
+    if args.anym:
+        out["any_m"] = [bench_any_m(int(x), keys, graph, dev, stream, args.steps) for x in args.anym.split(",") if x]
     del keys
     torch.cuda.empty_cache()
     if args.batch_queries > 0:
@@ -304,6 +308,52 @@ def bench_filtered(sk, keys, graph, dev, stream, steps):
     return {"workload": "chain-3 step with one range predicate per relation at ingestion (25% kept)",
             "input_tuples_per_s": total / dt, "kept_fraction": sum(kept) / total, "ms_per_step": dt * 1e3,
             "estimate": res["value"]}
+
+
+def bench_any_m(m, keys, graph, dev, stream, steps, d=5):
+    """The chain-3 step at the paper's sketch size (Sec. 4.1: m = 10^6 buckets, median of
+    5), next to the nearest power of two: update throughput and estimate latency."""
+    import torch
+
+    import paper_2402_15953_amd as csk
+    n = keys[0].shape[0]
+    sk = csk.Sketch(graph, m, d, 11)
+    tm = [csk.Timer() for _ in range(4 * steps)]
+    upd, est = [], []
+
+    def step(i):
+        sk.reset(stream=stream)
+        if i is not None:
+            tm[4 * i].record(stream)
+        for k in range(graph.n_rel):
+            sk.update(k, keys[k], None, stream=stream)
+        if i is not None:
+            tm[4 * i + 1].record(stream)
+            tm[4 * i + 2].record(stream)
+        r = sk.estimate(stream=stream)
+        if i is not None:
+            tm[4 * i + 3].record(stream)
+        return r
+
+    with torch.cuda.stream(stream):
+        step(None)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            res = step(i)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+    for i in range(steps):
+        upd.append(tm[4 * i].elapsed_ms(tm[4 * i + 1]))
+        est.append(tm[4 * i + 2].elapsed_ms(tm[4 * i + 3]))
+    plan = {csk.PLAN_DOT: "dot", csk.PLAN_SPECTRAL: "spectral", csk.PLAN_GENERAL: "general"}[sk.info()["plan"]]
+    sk.close()
+    for t in tm:
+        t.close()
+    total = n * graph.n_rel
+    return {"workload": f"chain-3 step, 1e7 tuples/relation, m={m}, d={d}", "m": m, "d": d, "plan": plan,
+            "tuples_per_s": total / dt, "ms_per_step": dt * 1e3, "update_ms": sorted(upd)[len(upd) // 2],
+            "estimate_ms": sorted(est)[len(est) // 2], "estimate": res["value"], "exact": res["exact"]}
 
 
 def bench_batched(n_queries, dev, stream):

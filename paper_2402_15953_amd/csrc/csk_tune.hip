@@ -143,7 +143,6 @@ cs_status cs_tune_update(cs_sketch *hs, int32_t rel, const uint32_t *keys, const
     cands.push_back({CS_UPDATE_GLOBAL_ATOMIC, 0, 0});
     cands.push_back({CS_UPDATE_WAVE_AGGREGATE, 0, 0});
     const uint64_t cells = (uint64_t)h.d * h.m;
-    const bool pow2 = (h.m & (h.m - 1)) == 0;
     if (narrow && h.m <= (1u << 16) && h.m > (1u << 15) && (h.m % 2) == 0) {
         const SegGeom g16 = seg16_geometry(h.m, (int32_t)h.d, (size_t)-1);
         const int32_t one_round = std::max(1, 256 / g16.segments);
@@ -159,7 +158,7 @@ cs_status cs_tune_update(cs_sketch *hs, int32_t rel, const uint32_t *keys, const
                 cands.push_back({CS_UPDATE_LDS_PRIVATE, one_round * mult, f16 | CS_UPDATE_NO_COMPACT});
         }
     }
-    if (unit && base.plan.n_cols <= 2 && pow2) cands.push_back({CS_UPDATE_PARTITION, 0, 0});
+    if (unit && base.plan.n_cols <= 2) cands.push_back({CS_UPDATE_PARTITION, 0, 0});
     if ((int)cands.size() > CS_TUNE_MAX_CANDIDATES) cands.resize(CS_TUNE_MAX_CANDIDATES);
 
     // ---- two private counter blocks: the reference's and the candidate's

@@ -509,7 +509,6 @@ __global__ __launch_bounds__(kPB) void k_part_hash(const uint32_t *__restrict__ 
             if (l < u) {
                 uint32_t j, neg;
                 hash_rep<NC>(cf, plan, x[k], j, neg);
-                j &= m - 1;
                 const int32_t val = neg ? -wv[k] : wv[k];
                 rec[k] = (j & rmask) | ((uint32_t)val << 13);
                 rng[k] = (uint16_t)(j >> log2R);
@@ -611,7 +610,8 @@ __global__ __launch_bounds__(kPAB) void k_part_accum(const uint32_t *__restrict_
     }
     __syncthreads();
     uint64_t *out = sketch + (size_t)t * m + ((size_t)r << log2R);
-    for (int e = threadIdx.x; e < R; e += kPAB) {
+    const int span = (int)min((uint32_t)R, m - ((uint32_t)r << log2R));  // the last range may be partial
+    for (int e = threadIdx.x; e < span; e += kPAB) {
         const int32_t v = s_acc[e];
         if (v) out[e] += (uint64_t)(int64_t)v;
     }
@@ -732,7 +732,6 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
     }
     if (strategy == CS_UPDATE_PARTITION) {
         if constexpr (NC > 2) return fail(CS_EINVAL, "the partition strategy handles at most 2 key columns");
-        if (!pow2) return fail(CS_EINVAL, "the partition strategy needs a power-of-two m");
         if (a.weights && !a.unit_weights)
             return fail(CS_EINVAL, "the partition strategy needs weights NULL or flagged as +-1");
         if (!a.scratch) return fail(CS_EINVAL, "the partition strategy needs a scratch buffer");
@@ -813,7 +812,8 @@ SegGeom seg16_geometry(uint32_t m, int32_t d, size_t scratch_bytes, uint64_t n)
 PartGeom part_geometry(uint32_t m, int32_t d, size_t scratch_bytes)
 {
     PartGeom g{};
-    // about 256+ (repetition, range) workgroups in pass 2; ranges a power of two
+    // about 256+ (repetition, range) workgroups in pass 2; ranges of 2^log2R buckets
+    // (the last one partial when m is not a power of two)
     int ranges = 1;
     while (ranges * d < 256 && ranges < kMaxPartRanges) ranges <<= 1;
     int log2m = 0;
@@ -822,7 +822,7 @@ PartGeom part_geometry(uint32_t m, int32_t d, size_t scratch_bytes)
     while ((1 << (log2m - log2R)) < ranges && log2R > 0) --log2R;
     if (log2R > 13) log2R = 13;       // pass-2 LDS: 2^13 int32 = 32 KB
     g.log2R = log2R;
-    g.ranges = 1 << (log2m - log2R);
+    g.ranges = (int)(((uint64_t)m + (1u << log2R) - 1) >> log2R);
     if (g.ranges > kMaxPartRanges) {  // m beyond 2^13 * kMaxPartRanges
         g.chunk = 0;
         return g;
@@ -860,12 +860,17 @@ int auto_update_strategy(uint32_t m, int32_t d, uint64_t n, int n_cols, bool uni
     // Global atomics run at about 2.4e10/s on the whole chip (and far slower on the hot
     // buckets of skewed keys), the hash at about 5e12 Horner steps/s: beyond a few
     // microseconds of atomics the update aggregates in LDS, on as many chunks as the
-    // input fills (seg_geometry).
-    (void)m;
-    (void)n_cols;
-    (void)unit;
+    // input fills (seg_geometry).  Beyond 2^16 buckets a repetition no longer fits one
+    // workgroup's LDS and each tuple's bucket would be hashed once per bucket range;
+    // there the partition strategy (each tuple hashed once, records sorted by range)
+    // measured 1.5-20x faster for m from 1.5 * 2^16 to 2^20, d from 3 to 9.  With
+    // general weights (no partition) the int64 segments lose to wavefront-aggregated
+    // atomics beyond 2^18 buckets.
     if (!has_scratch) return CS_UPDATE_GLOBAL_ATOMIC;
-    return n * (uint64_t)d >= 65536 ? CS_UPDATE_LDS_PRIVATE : CS_UPDATE_GLOBAL_ATOMIC;
+    if (n * (uint64_t)d < 65536) return CS_UPDATE_GLOBAL_ATOMIC;
+    if (m > (1u << 16) && unit && n_cols <= 2) return CS_UPDATE_PARTITION;
+    if (m > (1u << 18) && !unit) return CS_UPDATE_WAVE_AGGREGATE;
+    return CS_UPDATE_LDS_PRIVATE;
 }
 
 namespace {

@@ -59,13 +59,17 @@ SKETCH_CASES = [
     (W.multiway_star(4), 5_000, 3, 4, "zipf", 100, None),
     (W.chain(5), 30_000, 5_000, 15, "zipf", 10 ** 7, "pm1"),
     (W.single_join(), (1 << 21) + 77, 49_999, 2, "zipf", 10 ** 6, "pm1"),
+    (W.chain(3), 300_000, 1_000_000, 5, "zipf", 10 ** 6, "pm1"),  # partition: partial last range
+    (W.chain(3), 100_000, 99_991, 3, "uniform", 10 ** 6, None),
 ]
 
 
 @pytest.mark.parametrize("case", range(len(SKETCH_CASES)))
-@pytest.mark.parametrize("strategy", [0, 1, 2, 3])
+@pytest.mark.parametrize("strategy", [0, 1, 2, 3, 4])
 def test_sketch_bit_exact_any_m(case, strategy):
     graph, n, m, d, dist, D, wk = SKETCH_CASES[case]
+    if strategy == 4 and (wk == "big" or max(len(graph.columns(k)) for k in range(graph.n_rel)) > 2):
+        pytest.skip("partition strategy: +-1 weights and at most two key columns")
     _say("any-m sketch", case, graph.name, n, m, d, "strategy", strategy)
     rels = _rels(graph, n, dist, D, config=500 + case)
     weights = _weights(wk, graph, n)
@@ -76,15 +80,6 @@ def test_sketch_bit_exact_any_m(case, strategy):
         for k in range(graph.n_rel):
             assert np.array_equal(sk.read_sketch(k), ref[k]), (k, c16)
         sk.close()
-
-
-def test_partition_strategy_refuses_any_m():
-    sk = csk.Sketch(W.chain(3), 1000, 3, 1)
-    keys = torch.zeros(100, 1, dtype=torch.int32, device="cuda")
-    with pytest.raises(csk.CsError) as e:
-        sk.update(0, keys, strategy=csk.UPDATE_PARTITION)
-    assert e.value.status == csk.CS_EINVAL
-    sk.close()
 
 
 def test_invalid_m_rejected():
