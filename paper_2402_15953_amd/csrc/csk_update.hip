@@ -118,6 +118,22 @@ __global__ __launch_bounds__(kBlock) void k_update_waveagg(const uint32_t *__res
 // chunk's partial sums; k_seg_reduce adds the partials of all chunks into the sketch.
 // A segment holds whole repetitions when m <= R, else a bucket range of one
 // repetition (its tuples' signs are then only needed for in-range buckets).
+// (tuple chunk, segment) of a segmented launch's workgroup.  Workgroups go to the 8 XCDs
+// round-robin by linear id; the ids one XCD receives are given a contiguous run of the
+// chunk-major order, so the segments of one tuple chunk run on one XCD (two at a run's
+// ends) and that XCD's L2 fetches the chunk's keys once.
+struct SegTile {
+    uint32_t chunk, seg;
+};
+__device__ __forceinline__ SegTile seg_tile()
+{
+    const uint32_t G = gridDim.x * gridDim.y;
+    const uint32_t L = blockIdx.x + blockIdx.y * gridDim.x;
+    const uint32_t xcd = L & 7u, w = L >> 3;
+    const uint32_t P = xcd * (G >> 3) + min(xcd, G & 7u) + w;  // a bijection of [0, G)
+    return {P / gridDim.y, P % gridDim.y};
+}
+
 template <int NC, typename CT, bool E1>
 __global__ __launch_bounds__(kSegBlock) void k_update_seg(const uint32_t *__restrict__ keys,
                                                           const int64_t *__restrict__ weights, uint64_t n,
@@ -128,7 +144,8 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg(const uint32_t *__rest
     extern __shared__ __align__(16) unsigned char s_raw[];
     CT *s_c = reinterpret_cast<CT *>(s_raw);
     const uint64_t cells = (uint64_t)d * m;
-    const uint64_t cell0 = (uint64_t)blockIdx.y * R;
+    const SegTile wg = seg_tile();
+    const uint64_t cell0 = (uint64_t)wg.seg * R;
     const uint64_t cell1 = cell0 + R < cells ? cell0 + R : cells;
     const uint32_t span = (uint32_t)(cell1 - cell0);
     const int t0 = (int)(cell0 / m);
@@ -136,7 +153,7 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg(const uint32_t *__rest
     const bool whole = R >= m;
     for (uint32_t e = threadIdx.x; e < span; e += kSegBlock) s_c[e] = 0;
     __syncthreads();
-    const uint64_t begin = (uint64_t)blockIdx.x * chunk;
+    const uint64_t begin = (uint64_t)wg.chunk * chunk;
     const uint64_t end = begin + chunk < n ? begin + chunk : n;
     // repetition outermost: its coefficients stay in scalar registers over the tuples
     for (int t = t0; t <= t1; ++t) {
@@ -173,7 +190,7 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg(const uint32_t *__rest
         }
     }
     __syncthreads();
-    CT *out = partial + (size_t)blockIdx.x * cells + cell0;
+    CT *out = partial + (size_t)wg.chunk * cells + cell0;
     for (uint32_t e = threadIdx.x; e < span; e += kSegBlock) out[e] = s_c[e];
 }
 
@@ -200,14 +217,15 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg_compact(const uint32_t
     uint32_t *qx = q_x + wave * NC * kQCap;
     uint32_t *ql = q_l + wave * kQCap;
     const uint64_t cells = (uint64_t)d << log2m;
-    const uint64_t cell0 = (uint64_t)blockIdx.y * R;
+    const SegTile wg = seg_tile();
+    const uint64_t cell0 = (uint64_t)wg.seg * R;
     const int t = (int)(cell0 >> log2m);
     const uint32_t off = (uint32_t)(cell0 - ((uint64_t)t << log2m));  // first bucket of the range
     for (uint32_t e = threadIdx.x; e < R; e += kSegBlock) s_c[e] = 0;
     __syncthreads();
     CoefE1<NC> K;
     K.load(coef + (size_t)t * cpr);
-    const uint64_t begin = (uint64_t)blockIdx.x * chunk;
+    const uint64_t begin = (uint64_t)wg.chunk * chunk;
     const uint64_t end = begin + chunk < n ? begin + chunk : n;
     uint32_t head = 0, count = 0;  // wave-uniform queue state
     auto drain = [&](uint32_t k) {  // lanes < k take one queued entry each
@@ -254,7 +272,7 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg_compact(const uint32_t
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (count > 0) drain(count);
     __syncthreads();
-    int32_t *out = partial + (size_t)blockIdx.x * cells + cell0;
+    int32_t *out = partial + (size_t)wg.chunk * cells + cell0;
     for (uint32_t e = threadIdx.x; e < R; e += kSegBlock) out[e] = s_c[e];
 }
 
@@ -270,14 +288,15 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16(const uint32_t *__re
     extern __shared__ __align__(16) unsigned char s_raw[];
     uint32_t *s_w = reinterpret_cast<uint32_t *>(s_raw);  // [R / 2] words, two counters each
     const uint64_t cells = (uint64_t)d * m;
-    const uint64_t cell0 = (uint64_t)blockIdx.y * R;
+    const SegTile wg = seg_tile();
+    const uint64_t cell0 = (uint64_t)wg.seg * R;
     const uint64_t cell1 = cell0 + R < cells ? cell0 + R : cells;
     const uint32_t span = (uint32_t)(cell1 - cell0);  // even: R is even (so is cells)
     const int t0 = (int)(cell0 / m);
     const int t1 = (int)((cell1 - 1) / m);
     for (uint32_t e = threadIdx.x; e < span / 2; e += kSegBlock) s_w[e] = (kBias16 << 16) | kBias16;
     __syncthreads();
-    const uint64_t begin = (uint64_t)blockIdx.x * chunk;
+    const uint64_t begin = (uint64_t)wg.chunk * chunk;
     const uint64_t end = begin + chunk < n ? begin + chunk : n;
     for (int t = t0; t <= t1; ++t) {
         const uint64_t *cf = coef + (size_t)t * cpr;
@@ -343,7 +362,7 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16(const uint32_t *__re
     }
     __syncthreads();
     // partial sums leave as the biased 16-bit pairs: [chunk][cells / 2] words
-    uint32_t *out = partial + (size_t)blockIdx.x * (cells >> 1) + (cell0 >> 1);
+    uint32_t *out = partial + (size_t)wg.chunk * (cells >> 1) + (cell0 >> 1);
     for (uint32_t e = threadIdx.x; e < span / 2; e += kSegBlock) out[e] = s_w[e];
 }
 
