@@ -146,8 +146,7 @@ __device__ void run_segment16(const BItem &I, uint32_t seg, uint64_t begin, uint
         load_keys<NC>(I.keys, i, I.vec2 != 0, xn);
         if (I.weights) wn = I.weights[i];
     }
-    bool pend = false;
-    uint32_t p_old = 0, p_shift = 0, p_neg = 0;
+    uint32_t p_old = kBias16 * 0x10001u, p_inc = 0;  // before the first add: in range
     uint64_t p_g = 0;
     uint32_t *p_w = s_w;
     for (; i < end; i += kBBlock) {
@@ -173,25 +172,17 @@ __device__ void run_segment16(const BItem &I, uint32_t seg, uint64_t begin, uint
             if (wt < 0) neg ^= 1u;
             const uint64_t g = (uint64_t)t * I.m + j;
             const uint32_t loc = (uint32_t)(g - cell0);
-            const uint32_t shift = (loc & 1u) << 4;
             uint32_t *w = &s_w[loc >> 1];
-            const uint32_t old = atomicAdd(w, neg ? (0xFFFFFFFFu << shift) : (1u << shift));
-            if (pend) {
-                const uint32_t h = ((p_old >> p_shift) & 0xFFFFu) + (p_neg ? 0xFFFFFFFFu : 1u);
-                if (h >= kHi16 || h <= kLo16) spill16(p_w, p_shift, sk + p_g);
-            }
-            pend = true;
+            const uint32_t inc = inc16(neg, (loc & 1u) << 4);
+            const uint32_t old = atomicAdd(w, inc);
+            if (out16(p_old, p_inc)) spill16(p_w, shift16(p_inc), sk + p_g);
             p_old = old;
-            p_shift = shift;
-            p_neg = neg;
+            p_inc = inc;
             p_g = g;
             p_w = w;
         }
     }
-    if (pend) {
-        const uint32_t h = ((p_old >> p_shift) & 0xFFFFu) + (p_neg ? 0xFFFFFFFFu : 1u);
-        if (h >= kHi16 || h <= kLo16) spill16(p_w, p_shift, sk + p_g);
-    }
+    if (out16(p_old, p_inc)) spill16(p_w, shift16(p_inc), sk + p_g);
     __syncthreads();
     unsigned long long *out = sk + cell0;
     for (uint32_t e = threadIdx.x; e < span / 2; e += kBBlock) {

@@ -25,32 +25,26 @@ __device__ __forceinline__ uint64_t hstep(uint64_t v, uint32_t x, uint64_t a)
     const uint64_t lo = (uint64_t)(uint32_t)v * (uint64_t)x;  // < 2^64
     // v * x = t * 2^32 + (lo mod 2^32) with t = (v >> 32) * x + (lo >> 32) < 2^63 + 2^32
     const uint64_t t = (uint64_t)(uint32_t)(v >> 32) * (uint64_t)x + (lo >> 32);
-    // (v * x mod 2^61) + (v * x >> 61) + a, using 2^61 = 1 (mod p).  The low 61 bits
-    // are the pair (lo mod 2^32, t mod 2^29); adding s = (v * x >> 61) + a to that pair
-    // word by word with a carry keeps the compiler from materialising it (one
-    // instruction less per step than a 64-bit or-then-add).
+    // (v * x mod 2^61) + (v * x >> 61) + a, using 2^61 = 1 (mod p): the low 61 bits are
+    // the word pair (lo mod 2^32, t mod 2^29), built in the high half of lo's register
+    // pair, so the sum is one 64-bit add (seven instructions a step).  The add is
+    // written as the instruction itself: left to the compiler, it reassociates the three
+    // terms into zero-extended 64-bit adds.
+    const uint64_t low61 = ((uint64_t)((uint32_t)t & 0x1FFFFFFFu) << 32) | (uint32_t)lo;
     const uint64_t s = (t >> 29) + a;
-    unsigned int carry;
-    const uint32_t rl = __builtin_addc((uint32_t)lo, (uint32_t)s, 0u, &carry);
-    const uint32_t rh = __builtin_addc((uint32_t)t & 0x1FFFFFFFu, (uint32_t)(s >> 32), carry, &carry);
-    return ((uint64_t)rh << 32) | rl;
+    uint64_t r;
+    asm("v_lshl_add_u64 %0, %1, 0, %2" : "=v"(r) : "v"(low61), "v"(s));
+    return r;
 }
 
-// hstep on a value held as two 32-bit words (the form the kernels keep between steps:
-// joining and splitting 64-bit values costs the compiler extra moves).
+// hstep on a value held as two 32-bit words.
 struct HPair {
     uint32_t lo, hi;
 };
 __device__ __forceinline__ HPair hstep_p(HPair v, uint32_t x, uint64_t a)
 {
-    const uint64_t lo = (uint64_t)v.lo * (uint64_t)x;
-    const uint64_t t = (uint64_t)v.hi * (uint64_t)x + (lo >> 32);
-    const uint64_t s = (t >> 29) + a;
-    unsigned int carry;
-    HPair r;
-    r.lo = __builtin_addc((uint32_t)lo, (uint32_t)s, 0u, &carry);
-    r.hi = __builtin_addc((uint32_t)t & 0x1FFFFFFFu, (uint32_t)(s >> 32), carry, &carry);
-    return r;
+    const uint64_t r = hstep(((uint64_t)v.hi << 32) | v.lo, x, a);
+    return HPair{(uint32_t)r, (uint32_t)(r >> 32)};
 }
 __device__ __forceinline__ HPair hpair(uint64_t v) { return HPair{(uint32_t)v, (uint32_t)(v >> 32)}; }
 

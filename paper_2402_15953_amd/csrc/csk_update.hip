@@ -32,6 +32,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kSegBlock = 1024;
+constexpr uint32_t kSeg16Words = 1u << 15;  // 128 KB: 2^16 16-bit counters
 
 template <int NC>
 __global__ __launch_bounds__(kBlock) void k_update_global(const uint32_t *__restrict__ keys,
@@ -276,7 +277,7 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg_compact(const uint32_t
     for (uint32_t e = threadIdx.x; e < R; e += kSegBlock) out[e] = s_c[e];
 }
 
-template <int NC, bool E1>
+template <int NC, bool E1, bool HW>
 __global__ __launch_bounds__(kSegBlock) void k_update_seg16(const uint32_t *__restrict__ keys,
                                                             const int64_t *__restrict__ weights, uint64_t n,
                                                             const uint64_t *__restrict__ coef, int32_t cpr,
@@ -285,8 +286,9 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16(const uint32_t *__re
                                                             uint32_t *partial, unsigned long long *sketch,
                                                             uint32_t canon_thresh)
 {
-    extern __shared__ __align__(16) unsigned char s_raw[];
-    uint32_t *s_w = reinterpret_cast<uint32_t *>(s_raw);  // [R / 2] words, two counters each
+    // [R / 2] words, two counters each (R <= 2^16); a fixed array, so that its LDS
+    // address is a constant the compiler folds into the address arithmetic
+    __shared__ uint32_t s_w[kSeg16Words];
     const uint64_t cells = (uint64_t)d * m;
     const SegTile wg = seg_tile();
     const uint64_t cell0 = (uint64_t)wg.seg * R;
@@ -308,25 +310,10 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16(const uint32_t *__re
         // is hashed, and the value an LDS add returns is checked one tuple later, so
         // neither latency stalls the wavefront.  Deferring the check lets a thread have
         // two adds outstanding: a half still stays within 2^15 +- (2^14 + 2 * 1024).
-        uint64_t i = begin + threadIdx.x;
-        uint32_t xn[NC];
-        int64_t wn = 0;
-        if (i < end) {
-            load_keys<NC>(keys, i, vec2, xn);
-            if (weights) wn = weights[i];
-        }
-        bool pend = false;
-        uint32_t p_old = 0, p_shift = 0, p_neg = 0, p_j = 0;
+        // the previous add: word before it, its increment, its bucket, its word
+        uint32_t p_old = kBias16 * 0x10001u, p_inc = 0, p_j = 0;  // before the first add: in range
         uint32_t *p_w = s_w;
-        for (; i < end; i += kSegBlock) {
-            uint32_t x[NC];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) x[c] = xn[c];
-            const int64_t wt = wn;
-            if (i + kSegBlock < end) {
-                load_keys<NC>(keys, i + kSegBlock, vec2, xn);
-                if (weights) wn = weights[i + kSegBlock];
-            }
+        auto one = [&](const uint32_t (&x)[NC], int64_t wt) {
             uint32_t j, neg;
             if constexpr (E1) {
                 uint32_t flag;
@@ -339,26 +326,39 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16(const uint32_t *__re
             } else {
                 hash_rep<NC>(cf, plan, x, j, neg);
             }
-            if (wt < 0) neg ^= 1u;
+            if constexpr (HW) neg ^= (uint32_t)((uint64_t)wt >> 63);
             const uint32_t loc = row + j;
-            const uint32_t shift = (loc & 1u) << 4;
             uint32_t *w = &s_w[loc >> 1];
-            const uint32_t old = atomicAdd(w, neg ? (0xFFFFFFFFu << shift) : (1u << shift));
-            if (pend) {
-                const uint32_t h = ((p_old >> p_shift) & 0xFFFFu) + (p_neg ? 0xFFFFFFFFu : 1u);
-                if (h >= kHi16 || h <= kLo16) spill16(p_w, p_shift, srow + p_j);
-            }
-            pend = true;
+            const uint32_t inc = inc16(neg, (loc & 1u) << 4);
+            const uint32_t old = atomicAdd(w, inc);
+            if (out16(p_old, p_inc)) spill16(p_w, shift16(p_inc), srow + p_j);
             p_old = old;
-            p_shift = shift;
-            p_neg = neg;
+            p_inc = inc;
             p_j = j;
             p_w = w;
+        };
+        // two tuples per iteration in alternating registers: the keys of the next tuple
+        // are in flight while one is hashed, with no register copies between iterations
+        uint64_t i = begin + threadIdx.x;
+        uint32_t xa[NC], xb[NC];
+        int64_t wa = 0, wb = 0;
+        if (i < end) {
+            load_keys<NC>(keys, i, vec2, xa);
+            if constexpr (HW) wa = weights[i];
         }
-        if (pend) {
-            const uint32_t h = ((p_old >> p_shift) & 0xFFFFu) + (p_neg ? 0xFFFFFFFFu : 1u);
-            if (h >= kHi16 || h <= kLo16) spill16(p_w, p_shift, srow + p_j);
+        for (; i + kSegBlock < end; i += 2 * kSegBlock) {  // both tuples exist
+            const uint64_t i1 = i + kSegBlock;
+            load_keys<NC>(keys, i1, vec2, xb);
+            if constexpr (HW) wb = weights[i1];
+            one(xa, wa);
+            if (i1 + kSegBlock < end) {
+                load_keys<NC>(keys, i1 + kSegBlock, vec2, xa);
+                if constexpr (HW) wa = weights[i1 + kSegBlock];
+            }
+            one(xb, wb);
         }
+        if (i < end) one(xa, wa);  // an odd last tuple
+        if (out16(p_old, p_inc)) spill16(p_w, shift16(p_inc), srow + p_j);
     }
     __syncthreads();
     // partial sums leave as the biased 16-bit pairs: [chunk][cells / 2] words
@@ -702,13 +702,12 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
             g16.chunks = chunks_for(g16.chunks, 2);
             const uint64_t chunk16 = (a.n + g16.chunks - 1) / g16.chunks;
             dim3 grid16((unsigned)g16.chunks, (unsigned)g16.segments);
-            const size_t lds16 = (size_t)g16.R * 2;
+            if (g16.R > 2u * kSeg16Words) return fail(CS_EINVAL, "16-bit segment exceeds its LDS array");
             uint32_t *part = reinterpret_cast<uint32_t *>(a.scratch);
-            auto kern = e1 ? &k_update_seg16<NC, true> : &k_update_seg16<NC, false>;
-            CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds16));
+            auto kern = a.weights ? (e1 ? &k_update_seg16<NC, true, true> : &k_update_seg16<NC, false, true>)
+                                  : (e1 ? &k_update_seg16<NC, true, false> : &k_update_seg16<NC, false, false>);
             CSK_MARK(a.ev_start, s);
-            hipLaunchKernelGGL(kern, grid16, dim3(kSegBlock), lds16, s, a.keys, a.weights, a.n, a.coef,
+            hipLaunchKernelGGL(kern, grid16, dim3(kSegBlock), 0, s, a.keys, a.weights, a.n, a.coef,
                                a.plan.coef_per_rep, plan, a.m, log2m, a.d, g16.R, chunk16, vec2, part,
                                reinterpret_cast<unsigned long long *>(a.sketch), a.canon_thresh);
             CSK_HIP(hipGetLastError());
