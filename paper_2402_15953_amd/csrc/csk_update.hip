@@ -33,6 +33,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kSegBlock = 1024;
 constexpr uint32_t kSeg16Words = 1u << 15;  // 128 KB: 2^16 16-bit counters
+constexpr int kSeg16Group = 4;              // tuples hashed together by one thread
 
 template <int NC>
 __global__ __launch_bounds__(kBlock) void k_update_global(const uint32_t *__restrict__ keys,
@@ -306,59 +307,116 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16(const uint32_t *__re
         if constexpr (E1) K.load(cf);
         const uint32_t row = (uint32_t)((uint64_t)t * m - cell0);
         unsigned long long *srow = sketch + (uint64_t)t * m;
-        // Software pipeline: the next tuple's keys (and weight) are loaded while this one
-        // is hashed, and the value an LDS add returns is checked one tuple later, so
-        // neither latency stalls the wavefront.  Deferring the check lets a thread have
-        // two adds outstanding: a half still stays within 2^15 +- (2^14 + 2 * 1024).
-        // the previous add: word before it, its increment, its bucket, its word
-        uint32_t p_old = kBias16 * 0x10001u, p_inc = 0, p_j = 0;  // before the first add: in range
-        uint32_t *p_w = s_w;
-        auto one = [&](const uint32_t (&x)[NC], int64_t wt) {
-            uint32_t j, neg;
+        // Tuples go in groups of kSeg16Group: all are hashed in one straight-line block
+        // (independent chains for the scheduler, one test of the rare full-reduction
+        // flag), their LDS adds are issued, and only then are the words the previous
+        // group's adds returned checked; the next group's keys are in flight meanwhile.
+        // Neither the LDS latency nor the loads stall the wavefront.  A thread has at most
+        // 2 * kSeg16Group adds whose result it has not checked: with 1024 threads a half
+        // stays within 2^15 +- (2^14 + 8 * 1024).
+        constexpr int G = kSeg16Group;
+        struct Pend {
+            uint32_t old, inc, j;  // word before the add, the increment, the bucket
+            uint32_t *w;
+        };
+        Pend pend[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) pend[g] = Pend{kBias16 * 0x10001u, 0u, 0u, s_w};  // in range
+        auto check = [&]() {
+            bool any = false;
+#pragma unroll
+            for (int g = 0; g < G; ++g) any |= out16(pend[g].old, pend[g].inc);
+            if (any) {
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+                    if (out16(pend[g].old, pend[g].inc))
+                        spill16(pend[g].w, shift16(pend[g].inc), srow + pend[g].j);
+            }
+        };
+        auto hash1 = [&](const uint32_t (&x)[NC], uint32_t &j, uint32_t &neg, uint32_t &flag) {
             if constexpr (E1) {
-                uint32_t flag;
                 K.bin_neg_fast(x, j, neg, flag);
-                if (flag >= canon_thresh) {  // a hash may need the full reduction
-                    j = K.bin(x);
-                    neg = K.neg(x);
-                }
-                j &= m - 1;
             } else {
                 hash_rep<NC>(cf, plan, x, j, neg);
+                flag = 0;
             }
+        };
+        auto exact1 = [&](const uint32_t (&x)[NC], uint32_t &j, uint32_t &neg) {
+            if constexpr (E1) {
+                j = K.bin(x);
+                neg = K.neg(x);
+            }
+        };
+        auto add1 = [&](uint32_t j, uint32_t neg, int64_t wt) -> Pend {
+            if constexpr (E1) j &= m - 1;
             if constexpr (HW) neg ^= (uint32_t)((uint64_t)wt >> 63);
             const uint32_t loc = row + j;
             uint32_t *w = &s_w[loc >> 1];
             const uint32_t inc = inc16(neg, (loc & 1u) << 4);
-            const uint32_t old = atomicAdd(w, inc);
-            if (out16(p_old, p_inc)) spill16(p_w, shift16(p_inc), srow + p_j);
-            p_old = old;
-            p_inc = inc;
-            p_j = j;
-            p_w = w;
+            return Pend{atomicAdd(w, inc), inc, j, w};
         };
-        // two tuples per iteration in alternating registers: the keys of the next tuple
-        // are in flight while one is hashed, with no register copies between iterations
-        uint64_t i = begin + threadIdx.x;
-        uint32_t xa[NC], xb[NC];
-        int64_t wa = 0, wb = 0;
-        if (i < end) {
-            load_keys<NC>(keys, i, vec2, xa);
-            if constexpr (HW) wa = weights[i];
+        auto load = [&](uint64_t k, uint32_t (&x)[NC], int64_t &wt) {
+            load_keys<NC>(keys, k, vec2, x);
+            if constexpr (HW) wt = weights[k];
+        };
+        constexpr uint64_t B = kSegBlock;
+        uint64_t i = begin + threadIdx.x;  // this thread's tuples: i, i + B, i + 2B, ...
+        uint32_t xn[G][NC];
+        int64_t wn[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            wn[g] = 0;
+            if (i + g * B < end) load(i + g * B, xn[g], wn[g]);
         }
-        for (; i + kSegBlock < end; i += 2 * kSegBlock) {  // both tuples exist
-            const uint64_t i1 = i + kSegBlock;
-            load_keys<NC>(keys, i1, vec2, xb);
-            if constexpr (HW) wb = weights[i1];
-            one(xa, wa);
-            if (i1 + kSegBlock < end) {
-                load_keys<NC>(keys, i1 + kSegBlock, vec2, xa);
-                if constexpr (HW) wa = weights[i1 + kSegBlock];
+        for (; i + (G - 1) * B < end; i += G * B) {  // a whole group
+            uint32_t x[G][NC];
+            int64_t wt[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) x[g][c] = xn[g][c];
+                wt[g] = wn[g];
             }
-            one(xb, wb);
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                if (i + (G + g) * B < end) load(i + (G + g) * B, xn[g], wn[g]);
+            uint32_t j[G], neg[G], flag = 0;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                uint32_t f;
+                hash1(x[g], j[g], neg[g], f);
+                flag = max(flag, f);
+            }
+            if (flag >= canon_thresh) {  // a hash may need the full reduction
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    uint32_t jj, nn, f;
+                    hash1(x[g], jj, nn, f);
+                    if (f >= canon_thresh) exact1(x[g], j[g], neg[g]);
+                }
+            }
+            Pend now[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) now[g] = add1(j[g], neg[g], wt[g]);
+            check();
+#pragma unroll
+            for (int g = 0; g < G; ++g) pend[g] = now[g];
         }
-        if (i < end) one(xa, wa);  // an odd last tuple
-        if (out16(p_old, p_inc)) spill16(p_w, shift16(p_inc), srow + p_j);
+        // fewer than G tuples left, one at a time (their keys are in xn)
+#pragma unroll
+        for (int g = 0; g < G - 1; ++g) {
+            if (i + g * B < end) {
+                uint32_t jj, nn, f;
+                hash1(xn[g], jj, nn, f);
+                if (f >= canon_thresh) exact1(xn[g], jj, nn);
+                const Pend now = add1(jj, nn, wn[g]);
+                check();
+                pend[0] = now;
+#pragma unroll
+                for (int h = 1; h < G; ++h) pend[h] = Pend{kBias16 * 0x10001u, 0u, 0u, s_w};
+            }
+        }
+        check();
     }
     __syncthreads();
     // partial sums leave as the biased 16-bit pairs: [chunk][cells / 2] words
