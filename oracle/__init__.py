@@ -19,6 +19,10 @@ What it computes, each function citing the passage it follows:
                      or modulo primes with Chinese remaindering (through the NTT when
                      m is a power of two, term by term otherwise)
   median_lower       median of the d repetitions (Sec. 3.3; Sec. 4.1 uses l = 5)
+  create_ams_sketch  the AMS multi-join sketch of Eq. 1 (the baseline of Sec. 2; C
+                     implementation in csk_oracle.c), coefficients from
+                     draw_ams_coefficients
+  estimate_ams       its estimator X_t = (1/m) sum_j prod_k c_{k,t,j} (Thm. 2.3), exact
   join_size          the exact cardinality E[X] of Thm. 3.1
   variance_bound     3^(r-1)/m * prod ||F_k||_2^2 of Thm. 3.1
 
@@ -82,6 +86,10 @@ def lib():
             ctypes.c_int32, ctypes.c_uint64,
             ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
+        L.or_create_ams_sketch.restype = None
+        L.or_create_ams_sketch.argtypes = [
+            ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+            ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
         L.or_accumulate.restype = None
         L.or_accumulate.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p]
@@ -283,6 +291,63 @@ def create_sketch(info: QueryInfo, k: int, keys, weights, m: int, coeffs: Coeffi
                                coeffs.d, m, _ptr(sa), coeffs.n_edges, _ptr(ba), coeffs.n_comps,
                                _ptr(keys), _ptr(weights), n, _ptr(out))
     return out
+
+
+# --------------------------------------------------------------------------- AMS multi-join baseline (Eq. 1)
+
+def draw_ams_coefficients(seed: int, d: int, m: int, n_edges: int) -> np.ndarray:
+    """Sign polynomials of the AMS multi-join sketch (Eq. 1): one degree-3 polynomial
+    (4-wise independent) per join for every counter j of every repetition t, drawn from
+    the same SplitMix64 stream as Alg. 1's in the order t, j, join, a0..a3.
+    Returns uint64 [d][m][n_edges][4]."""
+    g = splitmix64(seed)
+    out = np.empty(d * m * n_edges * 4, dtype=np.uint64)
+    i = 0
+    while i < out.size:
+        c = next(g) >> 3
+        if c != P61:
+            out[i] = c
+            i += 1
+    return out.reshape(d, m, n_edges, 4)
+
+
+def create_ams_sketch(info: QueryInfo, k: int, keys, weights, m: int, coef: np.ndarray) -> np.ndarray:
+    """AMS multi-join sketch of relation R_k (Eq. 1): int64 [d][m], counter (t, j) the
+    sum over tuples of Delta times the product of the signs s_{t,j,{u,v}}(i_u) of every
+    join {u, v} at the relation's attributes."""
+    keys = np.ascontiguousarray(np.asarray(keys).astype(np.uint32, copy=False))
+    n = keys.shape[0] if keys.ndim else 0
+    a = len(info.omega[k])
+    d = coef.shape[0]
+    out = np.zeros((d, m), dtype=np.int64)
+    if n == 0:
+        return out
+    keys = keys.reshape(n, a)
+    if weights is not None:
+        weights = np.ascontiguousarray(np.asarray(weights, dtype=np.int64))
+    _comp, nedges, edges, max_e = _column_plan(info, k)
+    ca = np.ascontiguousarray(coef, dtype=np.uint64)
+    lib().or_create_ams_sketch(a, _ptr(nedges), _ptr(edges), max_e, d, m, _ptr(ca), ca.shape[2],
+                               _ptr(keys), _ptr(weights), n, _ptr(out))
+    return out
+
+
+def estimate_ams(sketches: Sequence[np.ndarray]):
+    """The AMS multi-join estimate (Eq. 1's estimator): per repetition t,
+    X_t = (1/m) sum_j prod_k c_{k,t,j}.  Returns the exact numerators S_t = m X_t (Python
+    integers) and the lower median of the S_t (the median of the X_t times m)."""
+    d, m = sketches[0].shape
+    nums = []
+    for t in range(d):
+        cols = [[int(v) for v in sk[t]] for sk in sketches]
+        total = 0
+        for j in range(m):
+            prod = 1
+            for c in cols:
+                prod *= c[j]
+            total += prod
+        nums.append(total)
+    return nums, median_lower(nums)
 
 
 def filter_rows(keys, weights, attrs, predicates):

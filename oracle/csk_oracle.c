@@ -9,6 +9,10 @@
  *   or_poly_hash     - a polynomial hash over the Mersenne prime field p = 2^61 - 1,
  *                      evaluated with exact 128-bit arithmetic and the C `%` operator
  *                      (Sec. 4 setup: random polynomials over a Mersenne prime field).
+ *   or_create_ams_sketch - the AMS multi-join sketch of Eq. 1 (the baseline of Sec. 2):
+ *                      every counter j of every repetition has its own sign polynomial
+ *                      per join; a tuple adds Delta times the product of its joins'
+ *                      signs to every counter.
  *   or_create_sketch - the sketch creation procedure (Alg. 2; Eq. 2-4): per tuple,
  *                      sum the bin hashes of the joined attributes modulo m, multiply
  *                      the sign hashes of every join the attribute takes part in, then
@@ -103,4 +107,39 @@ void or_accumulate(const uint64_t *bins, const int32_t *signs, const int64_t *we
     uint64_t *c = (uint64_t *)sketch;
     for (uint64_t i = 0; i < n; ++i)
         c[bins[i] % m] += (uint64_t)(int64_t)signs[i] * (uint64_t)weights[i];
+}
+
+/*
+ * AMS multi-join sketch (Eq. 1) of one relation R_k, all d x m counters:
+ *   c[t][j] = sum_i Delta_i * prod_{u in Omega(R_k)} prod_{v in Gamma(u)} s_{t,j,{u,v}}(i_u)
+ *
+ *   col_nedges  [n_cols] joins at each key column's attribute
+ *   col_edges   [n_cols][max_edges] edge index of each join
+ *   ams_coef    [d][m][n_edges][4]  sign polynomial a0..a3 of join e for counter j of
+ *               repetition t
+ *   keys, weights, n as in or_create_sketch; sketch [d][m] accumulated into.
+ */
+void or_create_ams_sketch(int32_t n_cols, const int32_t *col_nedges, const int32_t *col_edges,
+                          int32_t max_edges, int32_t d, uint64_t m, const uint64_t *ams_coef,
+                          int32_t n_edges, const uint32_t *keys, const int64_t *weights, uint64_t n,
+                          int64_t *sketch)
+{
+    for (int32_t t = 0; t < d; ++t) {
+        for (uint64_t j = 0; j < m; ++j) {
+            const uint64_t *a_tj = ams_coef + ((size_t)t * m + j) * n_edges * 4;
+            int64_t sum = 0;
+            for (uint64_t i = 0; i < n; ++i) {
+                int64_t x = 1;
+                for (int32_t col = 0; col < n_cols; ++col) {
+                    uint32_t key = keys[i * (uint64_t)n_cols + col];
+                    for (int32_t e = 0; e < col_nedges[col]; ++e)
+                        x = or_sign(a_tj + 4 * col_edges[col * max_edges + e], key) * x;
+                }
+                int64_t delta = weights ? weights[i] : 1;
+                sum = (int64_t)((uint64_t)sum + (uint64_t)x * (uint64_t)delta);
+            }
+            uint64_t *c = (uint64_t *)(sketch + (size_t)t * m + j);
+            *c += (uint64_t)sum;
+        }
+    }
 }

@@ -441,3 +441,95 @@ def test_unbiased_and_variance_bound(graph, m):
     var = sum((x - mean) ** 2 for x in xs) / (S - 1)
     assert abs(mean - J) <= 5 * math.sqrt(V / S), (mean, J, V)
     assert var <= 1.3 * V, (var, V)
+
+
+# --------------------------------------------------------------------------- AMS multi-join baseline (Eq. 1)
+
+def test_ams_coefficient_stream_order():
+    """With one counter, repetition 0's AMS sign polynomials are the first draws of the
+    stream, exactly where Alg. 1's sign polynomials of repetition 0 are."""
+    info = oracle.analyze(W.fig3_query())
+    E = len(info.edges)
+    ams = oracle.draw_ams_coefficients(23, 1, 1, E)
+    cs = oracle.draw_coefficients(23, 1, E, info.n_comp)
+    assert np.array_equal(ams[0, 0], cs.sign_array()[0])
+
+
+@pytest.mark.parametrize("graph", [W.chain(3), W.fig3_query(), W.multiway_star(3)])
+def test_ams_sketch_equals_definition(graph):
+    """Eq. 1 counter by counter with the power-sum hash in Python integers."""
+    info = oracle.analyze(graph)
+    m, d = 3, 2
+    coef = oracle.draw_ams_coefficients(5, d, m, len(info.edges))
+    for k in range(info.n_rel):
+        keys = W.random_small_relation(graph, k, 25, 6, seed=40 + k).numpy()
+        w = W.random_weights(25, -4, 4, seed=60 + k).numpy()
+        got = oracle.create_ams_sketch(info, k, keys, w, m, coef)
+        for t in range(d):
+            for j in range(m):
+                ref = 0
+                for tup, wt in zip(keys.tolist(), w.tolist()):
+                    s = 1
+                    for col, u in enumerate(info.omega[k]):
+                        for v in info.gamma[u]:
+                            s *= oracle.sign_value(coef[t, j, info.edge_of(u, v)].tolist(), tup[col])
+                    ref += s * wt
+                assert got[t, j] == ref, (k, t, j)
+
+
+def test_ams_one_counter_is_count_sketch_one_bin():
+    """A Count sketch with m = 1 has one counter per repetition holding Eq. 1's sum: fed
+    the same sign polynomials, Alg. 2 and Eq. 1 must agree (two independent routines)."""
+    graph = W.chain(4)
+    info = oracle.analyze(graph)
+    d = 3
+    cs = oracle.draw_coefficients(31, d, len(info.edges), info.n_comp)
+    ams = cs.sign_array().reshape(d, 1, len(info.edges), 4)
+    for k in range(info.n_rel):
+        keys = W.random_small_relation(graph, k, 200, 20, seed=k).numpy()
+        w = W.turnstile_weights(200, 0.2, seed=k).numpy()
+        a = oracle.create_sketch(info, k, keys, w, 1, cs)
+        b = oracle.create_ams_sketch(info, k, keys, w, 1, ams)
+        assert np.array_equal(a, b)
+
+
+def test_ams_estimate_definition_and_linearity():
+    graph = W.chain(3)
+    info = oracle.analyze(graph)
+    m, d = 5, 3
+    coef = oracle.draw_ams_coefficients(8, d, m, len(info.edges))
+    rels = [W.random_small_relation(graph, k, 60, 8, seed=k).numpy() for k in range(3)]
+    sk = [oracle.create_ams_sketch(info, k, rels[k], None, m, coef) for k in range(3)]
+    nums, med = oracle.estimate_ams(sk)
+    for t in range(d):
+        assert nums[t] == sum(int(sk[0][t, j]) * int(sk[1][t, j]) * int(sk[2][t, j]) for j in range(m))
+    assert med == sorted(nums)[(d - 1) // 2]
+    # insert then delete half of relation 1: the sketch of the rest
+    keys = rels[1]
+    w = np.concatenate([np.ones(60, dtype=np.int64), -np.ones(30, dtype=np.int64)])
+    both = oracle.create_ams_sketch(info, 1, np.concatenate([keys, keys[:30]]), w, m, coef)
+    rest = oracle.create_ams_sketch(info, 1, keys[30:], None, m, coef)
+    assert np.array_equal(both, rest)
+
+
+def test_ams_unbiased_within_variance_bound():
+    """Thm. 2.3: E[X] is the join size and Var(X) <= 3^(r-1)/m prod_k ||F_k||_2^2.  Over
+    400 independent seeds the mean of X must lie within 5 standard errors of the join
+    size computed from the frequency tables."""
+    graph = W.chain(3)
+    info = oracle.analyze(graph)
+    m = 4
+    rels = [W.random_small_relation(graph, k, 40, 5, seed=k).numpy() for k in range(3)]
+    freqs = [oracle.frequency_tensor(r) for r in rels]
+    J = oracle.join_size(info, freqs)
+    var_bound = 3 ** (info.n_rel - 1) / m * math.prod(sum(v * v for v in f.values()) for f in freqs)
+    xs = []
+    for seed in range(400):
+        coef = oracle.draw_ams_coefficients(1000 + seed, 1, m, len(info.edges))
+        sk = [oracle.create_ams_sketch(info, k, rels[k], None, m, coef) for k in range(3)]
+        nums, _ = oracle.estimate_ams(sk)
+        xs.append(nums[0] / m)
+    mean = sum(xs) / len(xs)
+    assert abs(mean - J) <= 5 * math.sqrt(var_bound / len(xs)), (mean, J, var_bound)
+    var = sum((x - mean) ** 2 for x in xs) / (len(xs) - 1)
+    assert var <= 1.5 * var_bound, (var, var_bound)
