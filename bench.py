@@ -33,11 +33,11 @@ METRIC = "tuple updates/s into d×m count sketches + estimates/s; batched vs pla
 HBM_PEAK_GBS = 8000.0
 # Horner-step peak (one v <- v * x + a mod 2^61 - 1 with a 32-bit key x): the chip
 # issues 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 VALU lane-instructions/s, and
-# the shortest step the compiler emits is 8 full-rate VALU instructions (2
-# v_mad_u64_u32, one move for the 64-bit addend, a 64-bit shift, a 64-bit add, an and,
-# an add with carry-out and one with carry-in), so 4.92e12 steps/s.  A kernel made of
-# nothing but independent steps reaches 4.91e12 steps/s on the chip.
-ALU_STEP_PEAK = 256 * 4 * 16 * 2.4e9 / 8.0
+# the shortest step is 7 full-rate VALU instructions (2 v_mad_u64_u32, one move for the
+# 64-bit addend, a 64-bit shift, an and, a 64-bit add of a and one 64-bit add folding
+# the low 61 bits), so 5.62e12 steps/s.  A kernel made of nothing but independent
+# steps reaches 5.32e12 steps/s on the chip.
+ALU_STEP_PEAK = 256 * 4 * 16 * 2.4e9 / 7.0
 
 
 def parse():
@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--batch-queries", type=int, default=4096,
                     help="batched section: chain/star queries (0 skips the section)")
     ap.add_argument("--serve-queries", type=int, default=256, help="serving section: live queries (0 skips)")
+    ap.add_argument("--no-ams", dest="ams", action="store_false",
+                    help="skip the AMS-baseline section (stream throughput at equal memory)")
     ap.add_argument("--anym", type=str, default="1000000,1048576",
                     help="bucket-count section: chain-3 steps at these m with d = 5 (empty skips)")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="serving section: seconds per load level")
@@ -260,6 +262,8 @@ def main():
     sk.close()
     if args.anym:
         out["any_m"] = [bench_any_m(int(x), keys, graph, dev, stream, args.steps) for x in args.anym.split(",") if x]
+    if args.ams:
+        out["ams_baseline"] = bench_ams(keys, graph, stream)
     del keys
     torch.cuda.empty_cache()
     if args.batch_queries > 0:
@@ -308,6 +312,59 @@ def bench_filtered(sk, keys, graph, dev, stream, steps):
     return {"workload": "chain-3 step with one range predicate per relation at ingestion (25% kept)",
             "input_tuples_per_s": total / dt, "kept_fraction": sum(kept) / total, "ms_per_step": dt * 1e3,
             "estimate": res["value"]}
+
+
+def bench_ams(keys, graph, stream, d=5):
+    """The stream-throughput comparison of Sec. 4 (its throughput table) on one GPU: the
+    AMS multi-join sketch of Eq. 1 against the convolution sketch, chain-3, d = 5, at
+    equal memory (counters plus hash coefficients) from 1 kB to 10 MB.  An AMS update
+    touches all d x m counters, so its input is cut to about 4e10 hash steps a level."""
+    import torch
+
+    import paper_2402_15953_amd as csk
+    r, E = graph.n_rel, len(graph.edges)
+    Q = E  # chain: one component per join
+    n_full = keys[0].shape[0]
+    out = []
+
+    def timed(fn, reps=3):
+        best = float("inf")
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        return best
+
+    for mem in (1e3, 1e4, 1e5, 1e6, 1e7):
+        m_ams = max(1, int(mem // (r * d * 8 + d * E * 4 * 8)))
+        m_cs = max(2, int((mem - d * (4 * E + 2 * Q) * 8) // (r * d * 8)))
+        n_ams = int(min(n_full, max(4096, 4e10 / (d * m_ams * 12))))
+        ams = csk.AmsSketch(graph, m_ams, d, 3)
+        cs = csk.Sketch(graph, m_cs, d, 3)
+        with torch.cuda.stream(stream):
+            def run_ams():
+                ams.reset(stream=stream)
+                for k in range(r):
+                    ams.update(k, keys[k][:n_ams], stream=stream)
+
+            def run_cs():
+                cs.reset(stream=stream)
+                for k in range(r):
+                    cs.update(k, keys[k], None, stream=stream)
+
+            run_ams()
+            run_cs()
+            t_ams = timed(run_ams)
+            t_cs = timed(run_cs)
+        out.append({"memory_bytes": mem, "ams_m": m_ams, "cs_m": m_cs, "ams_tuples": n_ams * r,
+                    "ams_tuples_per_s": n_ams * r / t_ams, "cs_tuples_per_s": n_full * r / t_cs,
+                    "ams_hash_steps_per_s": n_ams * d * m_ams * 3 * (2 * E) / t_ams})
+        ams.close()
+        cs.close()
+    return {"workload": "chain-3, d=5, Zipf(1.1) keys, equal memory (counters + hash coefficients)",
+            "levels": out}
 
 
 def bench_any_m(m, keys, graph, dev, stream, steps, d=5):

@@ -414,6 +414,54 @@ cs_status cs_timer_record(void *ev, void *stream);
 cs_status cs_timer_elapsed(void *start, void *stop, float *ms);
 cs_status cs_timer_destroy(void *ev);
 
+/* ------------------------------------------------------------------ AMS multi-join baseline */
+
+/* The AMS multi-join sketch of Eq. 1 (Dobra et al.; Sec. 2), the method the convolution
+ * sketch is measured against (Sec. 4): counter j of repetition t of relation R_k is
+ *   c_{k,t,j} = sum_i Delta_i prod_{u in Omega(R_k)} prod_{v in Gamma(u)} s_{t,j,{u,v}}(i_u),
+ * with its own degree-3 sign polynomial per join for every (t, j), drawn from the seeded
+ * SplitMix64 stream (each draw >> 3, redrawn when equal to 2^61 - 1) in the order t, j,
+ * join, a0..a3.  An update touches all d x m counters of the relation, O(d m) per tuple
+ * against the Count sketch's O(d).  The estimate of repetition t is
+ * X_t = (1/m) sum_j prod_k c_{k,t,j} (Thm. 2.3); the result is the lower median over t. */
+typedef struct cs_ams cs_ams;  /* opaque */
+
+typedef struct cs_ams_estimate_t {
+    double value;            /* median X_t (fp64 of the exact numerator / m when exact) */
+    int64_t num_lo, num_hi;  /* exact numerator S = m X of that repetition, two's
+                                complement int128 (when exact = 1) */
+    int32_t exact;           /* 1: every repetition's numerator is exact (|S_t| < 2^126) */
+    int32_t median_rep;      /* repetition the median comes from */
+} cs_ams_estimate_t;
+
+/* Validate the graph (as cs_create; every relation must have 1 to 8 joins), draw the
+ * coefficients, allocate r*d*m int64 counters on the current device and zero them.
+ * 1 <= m <= 2^20, 1 <= d <= 64.  Errors: CS_EINVAL, CS_EGRAPH, CS_ENOMEM, CS_EDEVICE. */
+cs_status cs_ams_create(const cs_graph *graph, uint32_t m, uint32_t d, uint64_t seed, cs_ams **out);
+
+/* Free the handle (synchronises the device first). */
+cs_status cs_ams_destroy(cs_ams *h);
+
+/* Add n tuples to relation rel: keys uint32 [n][a_rel] tuple-major (device), weights
+ * int64 [n] (device) or NULL for Delta = +1.  Stream-ordered; counters wrap mod 2^64. */
+cs_status cs_ams_update(cs_ams *h, int32_t rel, const uint32_t *keys, const int64_t *weights,
+                        uint64_t n, void *stream);
+
+/* Zero every counter (stream-ordered). */
+cs_status cs_ams_reset(cs_ams *h, void *stream);
+
+/* Estimate (synchronous on `stream`).  rep_lo / rep_hi / rep_exact: optional host arrays
+ * of d entries receiving each repetition's numerator S_t (wrapping int128 halves; exact
+ * where rep_exact is 1). */
+cs_status cs_ams_estimate(cs_ams *h, void *stream, cs_ams_estimate_t *out, int64_t *rep_lo,
+                          int64_t *rep_hi, int32_t *rep_exact);
+
+/* Copy relation rel's counters, int64 [d][m], to host memory (synchronises the device). */
+cs_status cs_ams_read(const cs_ams *h, int32_t rel, int64_t *host_out);
+
+/* Copy the sign coefficients, uint64 [d][m][n_edge][4], to host memory. */
+cs_status cs_ams_coefficients(const cs_ams *h, uint64_t *host_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,6 +35,8 @@ EXPORTED = [
     "cs_server_create", "cs_server_destroy", "cs_server_add_query", "cs_server_remove_query",
     "cs_server_sketch", "cs_server_submit_update", "cs_server_submit_estimate", "cs_server_poll",
     "cs_server_drain", "cs_server_stats",
+    "cs_ams_create", "cs_ams_destroy", "cs_ams_update", "cs_ams_reset", "cs_ams_estimate", "cs_ams_read",
+    "cs_ams_coefficients",
 ]
 
 
@@ -48,6 +50,11 @@ class _Graph(ctypes.Structure):
     _fields_ = [("n_rel", ctypes.c_int32), ("n_attr", ctypes.c_int32),
                 ("attr_rel", ctypes.POINTER(ctypes.c_int32)), ("n_edge", ctypes.c_int32),
                 ("edges", ctypes.POINTER(ctypes.c_int32))]
+
+
+class _AmsEstimate(ctypes.Structure):
+    _fields_ = [("value", ctypes.c_double), ("num_lo", ctypes.c_int64), ("num_hi", ctypes.c_int64),
+                ("exact", ctypes.c_int32), ("median_rep", ctypes.c_int32)]
 
 
 class _Estimate(ctypes.Structure):
@@ -165,6 +172,13 @@ def lib() -> ctypes.CDLL:
         L.cs_server_poll.argtypes = [vp, ctypes.POINTER(_Completion), i32, ctypes.POINTER(i32)]
         L.cs_server_drain.argtypes = [vp]
         L.cs_server_stats.argtypes = [vp, ctypes.POINTER(_ServerStats)]
+        L.cs_ams_create.argtypes = [ctypes.POINTER(_Graph), u32, u32, u64, ctypes.POINTER(vp)]
+        L.cs_ams_destroy.argtypes = [vp]
+        L.cs_ams_update.argtypes = [vp, i32, vp, vp, u64, vp]
+        L.cs_ams_reset.argtypes = [vp, vp]
+        L.cs_ams_estimate.argtypes = [vp, vp, ctypes.POINTER(_AmsEstimate), vp, vp, vp]
+        L.cs_ams_read.argtypes = [vp, i32, vp]
+        L.cs_ams_coefficients.argtypes = [vp, vp]
         _lib = L
     return _lib
 
@@ -562,3 +576,65 @@ class Server:
         st = _ServerStats()
         _check(lib().cs_server_stats(self._s, ctypes.byref(st)))
         return {f: getattr(st, f) for f, _ in _ServerStats._fields_ if f != "reserved"}
+
+
+def _i128(lo: int, hi: int) -> int:
+    v = (int(hi) & 0xFFFFFFFFFFFFFFFF) << 64 | (int(lo) & 0xFFFFFFFFFFFFFFFF)
+    return v - (1 << 128) if v >= (1 << 127) else v
+
+
+class AmsSketch:
+    """The AMS multi-join sketch of Eq. 1 (the baseline): d x m int64 counters per
+    relation, every tuple updating all of them."""
+
+    def __init__(self, graph, m: int, d: int, seed: int):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("csketch needs a HIP GPU; there is no CPU fallback")
+        self.graph = graph
+        self.m, self.d, self.seed = int(m), int(d), int(seed)
+        h = ctypes.c_void_p()
+        _check(lib().cs_ams_create(ctypes.byref(_graph_struct(graph)), self.m, self.d, self.seed, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cs_ams_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def update(self, rel: int, keys, weights=None, stream=None):
+        n = int(keys.shape[0])
+        _check(lib().cs_ams_update(self._h, int(rel), keys.data_ptr() if n else None,
+                                   None if weights is None else weights.data_ptr(), n, _stream_ptr(stream)))
+
+    def reset(self, stream=None):
+        _check(lib().cs_ams_reset(self._h, _stream_ptr(stream)))
+
+    def estimate(self, stream=None) -> dict:
+        """Median X_t with the exact numerators S_t = m X_t of every repetition."""
+        e = _AmsEstimate()
+        lo = np.zeros(self.d, dtype=np.int64)
+        hi = np.zeros(self.d, dtype=np.int64)
+        ex = np.zeros(self.d, dtype=np.int32)
+        _check(lib().cs_ams_estimate(self._h, _stream_ptr(stream), ctypes.byref(e), lo.ctypes.data, hi.ctypes.data,
+                                     ex.ctypes.data))
+        return {"value": e.value, "exact": bool(e.exact), "median_rep": e.median_rep,
+                "numerator": _i128(e.num_lo, e.num_hi) if e.exact else None,
+                "rep_numerators": [_i128(a, b) if c else None for a, b, c in zip(lo, hi, ex)]}
+
+    def read_sketch(self, rel: int) -> np.ndarray:
+        out = np.empty((self.d, self.m), dtype=np.int64)
+        _check(lib().cs_ams_read(self._h, int(rel), out.ctypes.data))
+        return out
+
+    def coefficients(self) -> np.ndarray:
+        n_edges = len(self.graph.edges)
+        out = np.empty((self.d, self.m, n_edges, 4), dtype=np.uint64)
+        _check(lib().cs_ams_coefficients(self._h, out.ctypes.data))
+        return out

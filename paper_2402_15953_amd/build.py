@@ -19,6 +19,7 @@ SOURCES = [
     "csk_estimate.hip",
     "csk_tune.hip",
     "csk_filter.hip",
+    "csk_ams.hip",
     "csk_batch.hip",
     "csk_serve.hip",
 ]

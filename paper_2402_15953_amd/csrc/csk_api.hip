@@ -33,25 +33,6 @@ __global__ void k_add_i64(int64_t *dst, const int64_t *src, size_t n)
         dst[i] = (int64_t)((uint64_t)dst[i] + (uint64_t)src[i]);
 }
 
-// SplitMix64 (Steele, Lea & Flood 2014).
-struct SplitMix64 {
-    uint64_t s;
-    uint64_t next()
-    {
-        s += 0x9E3779B97F4A7C15ull;
-        uint64_t z = s;
-        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-        return z ^ (z >> 31);
-    }
-    uint64_t coef()
-    {
-        for (;;) {
-            const uint64_t c = next() >> 3;
-            if (c != kP61) return c;
-        }
-    }
-};
 
 }  // namespace
 

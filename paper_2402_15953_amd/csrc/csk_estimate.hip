@@ -516,10 +516,13 @@ struct FinalizeArgs {
 };
 
 constexpr int kFinThreads = 256;
-constexpr int kStage = 4096;  // doubles staged through LDS per chunk
+constexpr int kStage = kMaxD * 3 * kMaxRel;  // doubles of per-repetition bound terms
 constexpr int kSpecPrimes = 5;                       // speculative modular step: primes (155 bits)
 constexpr size_t kSpecBudget = (size_t)1 << 30;      // and its largest workspace
 
+// One instantiation per stage: each holds only its stage's code (the kernel runs once
+// per estimate, so its code is fetched cold).
+template <int STAGE>
 __global__ __launch_bounds__(kFinThreads) void k_finalize(FinalizeArgs a)
 {
     __shared__ double s_val[kMaxD];
@@ -529,66 +532,68 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinalizeArgs a)
     // sketch (norms) or repetition (spectral sums), in a fixed order
     __shared__ double s_q2[kMaxRel * kMaxD], s_l1[kMaxRel * kMaxD];
     __shared__ double s_sum[kMaxD], s_sabs[kMaxD], s_mx[kMaxD * kMaxRel];
-    __shared__ double s_stage[kStage];
+    __shared__ double s_stage[kStage];  // scratch of the bound computation
     __shared__ uint32_t s_res[kMaxD * kMaxPrimes], s_dig[kMaxD * kMaxPrimes];
-    static_assert(kStage >= kMaxD * 3 * kMaxRel, "bound terms reuse the staging area");
     const QDesc Q = a.qs[blockIdx.x];
     const int t = threadIdx.x;
     const double u = 0x1p-53;
     const double m = (double)Q.m;
     const int plan = Q.plan;
-    if (a.stage == 1 && plan != CS_PLAN_DOT) {
-        // The partials of a query are contiguous: staged through LDS in chunks (every
-        // thread's loads of a chunk are in flight together), then each owner (sketch or
-        // repetition) adds its own records in index order.
+    const int wv = t >> 6, lane = t & 63;
+    constexpr int kWaves = kFinThreads / 64;
+    if (STAGE == 1 && plan != CS_PLAN_DOT) {
+        // The nb <= 64 block partials of each owner (a sketch for the norms, a repetition
+        // for the spectral sums) are reduced by one wavefront: lane b loads partial b and
+        // a shuffle tree of depth 6 adds them, in a fixed order.
         const RepDesc D0 = a.reps[Q.rep_base];
         const int nb = Q.nb;
         const int n_sk = Q.r * Q.d;
-        const int w = 2 + Q.r;
-        for (int j = t; j < n_sk; j += kFinThreads) s_q2[j] = s_l1[j] = 0.0;
-        for (int tt = t; tt < Q.d; tt += kFinThreads) {
-            s_sum[tt] = s_sabs[tt] = 0.0;
-            for (int k = 0; k < kMaxRel; ++k) s_mx[tt * kMaxRel + k] = 0.0;
+        const double *nrm = a.norms + a.sks[D0.sk_base].off * 2;
+        for (int o = wv; o < n_sk; o += kWaves) {
+            double q2 = 0.0, l1 = 0.0;
+            if (lane < nb) {
+                const double *p = nrm + ((int64_t)o * nb + lane) * 2;
+                q2 = p[0];
+                l1 = p[1];
+            }
+            q2 = warp_sum(q2);
+            l1 = warp_sum(l1);
+            if (lane == 0) {
+                s_q2[o] = q2;
+                s_l1[o] = l1;
+            }
         }
-        for (int pass = 0; pass < (plan == CS_PLAN_SPECTRAL ? 2 : 1); ++pass) {
-            // pass 0: norms, records of 2 doubles (sum of squares, sum of |c|), nb per sketch
-            // pass 1: spectral sums, records of w doubles, nb per repetition
-            const int rec = pass == 0 ? 2 : w;
-            const int n_own = pass == 0 ? n_sk : Q.d;
-            const double *src = pass == 0 ? a.norms + a.sks[D0.sk_base].off * 2 : a.spec + D0.spec_off;
-            const int64_t len = (int64_t)n_own * nb * rec;
-            const int64_t seg = (int64_t)nb * rec;
-            const int64_t chunk = (int64_t)(kStage / rec) * rec;  // whole records per chunk
-            for (int64_t c0 = 0; c0 < len; c0 += chunk) {
-                const int cl = (int)(len - c0 < chunk ? len - c0 : chunk);
-                __syncthreads();
-#pragma unroll 4
-                for (int i = t; i < cl; i += kFinThreads) s_stage[i] = src[c0 + i];
-                __syncthreads();
-                for (int o = t; o < n_own; o += kFinThreads) {
-                    const int64_t lo = std::max<int64_t>(c0, (int64_t)o * seg);
-                    const int64_t hi = std::min<int64_t>(c0 + cl, (int64_t)(o + 1) * seg);
-                    if (lo >= hi) continue;
-                    if (pass == 0) {
-                        double q2 = s_q2[o], l1 = s_l1[o];
-                        for (int64_t e = lo; e < hi; e += 2) {
-                            q2 += s_stage[e - c0];
-                            l1 += s_stage[e - c0 + 1];
-                        }
-                        s_q2[o] = q2;
-                        s_l1[o] = l1;
-                    } else {
-                        double sm = s_sum[o], sa = s_sabs[o];
-                        for (int64_t e = lo; e < hi; e += w) {
-                            sm += s_stage[e - c0];
-                            sa += s_stage[e - c0 + 1];
-                            for (int k = 0; k < Q.r; ++k)
-                                s_mx[o * kMaxRel + k] = fmax(s_mx[o * kMaxRel + k], s_stage[e - c0 + 2 + k]);
-                        }
-                        s_sum[o] = sm;
-                        s_sabs[o] = sa;
-                    }
+        if (plan == CS_PLAN_SPECTRAL) {
+            const int w = 2 + Q.r;
+            const double *spc = a.spec + D0.spec_off;
+            for (int o = wv; o < Q.d; o += kWaves) {
+                const double *p = spc + ((int64_t)o * nb + lane) * w;
+                double sm = lane < nb ? p[0] : 0.0, sa = lane < nb ? p[1] : 0.0;
+                sm = warp_sum(sm);
+                sa = warp_sum(sa);
+                if (lane == 0) {
+                    s_sum[o] = sm;
+                    s_sabs[o] = sa;
                 }
+                for (int k = 0; k < Q.r; ++k) {
+                    const double mk = wave_allmax(lane < nb ? p[2 + k] : 0.0);
+                    if (lane == 0) s_mx[o * kMaxRel + k] = mk;
+                }
+            }
+        }
+    }
+    if constexpr (STAGE == 2) {
+        // residues: the nb partials of each (repetition, prime) summed by one wavefront
+        for (int o = wv; o < Q.d; o += kWaves) {
+            const int K = a.rs[Q.rep_base + o].kprimes;
+            if (K <= 0 || K > a.kcap) continue;
+            const RepDesc D = a.reps[Q.rep_base + o];
+            for (int i = 0; i < K; ++i) {
+                const PrimeDev &P = a.primes[i];
+                const RingM R{P.p, P.pinv_neg};
+                uint32_t v = lane < D.nb ? a.modp[(size_t)i * a.mod_plane + D.mod_off + lane] : 0u;
+                for (int off = 32; off > 0; off >>= 1) v = R.add(v, __shfl_down(v, off, 64));
+                if (lane == 0) s_res[o * kMaxPrimes + i] = v;
             }
         }
     }
@@ -597,9 +602,12 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinalizeArgs a)
         const RepDesc D = a.reps[Q.rep_base + t];
         // this repetition's record lives in registers; written back once at the end
         RepDev rp = a.rs[Q.rep_base + t];
+        // additions on any term's path to a sum: its thread's serial sum (per_thread - 1),
+        // block_sum (6 shuffle levels, then the kThreads / 64 wavefront sums one after
+        // another) and the tree of depth 6 over the nb <= 64 block partials above
         const double per_thread = ceil(m / ((double)D.nb * kThreads));
-        const double n_eff = per_thread + 8.0 + D.nb;
-        if (a.stage == 1) {
+        const double n_eff = per_thread + 6.0 + kThreads / 64 + 6.0;
+        if constexpr (STAGE == 1) {
             rp.kprimes = 0;
             rp.status = 0;
             rp.window = 0;
@@ -633,7 +641,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinalizeArgs a)
                     const double eta = 2.0 * u + g4 * (1.41421356237309515 + 2.0 * u);
                     const double kappa = 2.0 * (Q.log2m + 3) * eta;
                     const double sm = sqrt(m) * (1.0 + 4.0 * u);
-                    double *e = s_stage + t * 3 * kMaxRel;  // the staging area is free now
+                    double *e = s_stage + t * 3 * kMaxRel;
                     double *N = e + kMaxRel;
                     double *M = N + kMaxRel;
                     const int n_sk = Q.r * Q.d;
@@ -716,8 +724,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinalizeArgs a)
             for (int i = 0; i < K; ++i) {
                 const PrimeDev &P = a.primes[i];
                 const RingM R{P.p, P.pinv_neg};
-                uint32_t s = 0;
-                for (int b = 0; b < D.nb; ++b) s = R.add(s, a.modp[(size_t)i * a.mod_plane + D.mod_off + b]);
+                uint32_t s = res[i];  // the sum of the block partials, from above
                 if (plan == CS_PLAN_SPECTRAL) s = R.mul(s, P.minv[Q.log2m]);
                 res[i] = R.mul(s, 1u);  // out of Montgomery form
             }
@@ -757,7 +764,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinalizeArgs a)
             }
         }
         a.rs[Q.rep_base + t] = rp;
-        if (a.stage == 1) a.kp[Q.rep_base + t] = rp.kprimes;
+        if constexpr (STAGE == 1) a.kp[Q.rep_base + t] = rp.kprimes;
         s_val[t] = rp.value;
         s_ex[t] = rp.exact;
         s_lo[t] = rp.lo;
@@ -1046,6 +1053,17 @@ namespace {
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Waits for the stream by polling: the results are a few kilobytes, due within
+// microseconds of the last kernel, and a blocking wait's wake-up costs more than that.
+cs_status wait_results(hipStream_t s)
+{
+    for (;;) {
+        const hipError_t e = hipStreamQuery(s);
+        if (e == hipSuccess) return CS_OK;
+        if (e != hipErrorNotReady) return fail(CS_EDEVICE, std::string("hipStreamQuery: ") + hipGetErrorString(e));
+    }
+}
+
 int ceil_log2(uint32_t x)
 {
     int L = 0;
@@ -1055,7 +1073,9 @@ int ceil_log2(uint32_t x)
 
 int nblocks_for(uint32_t m)
 {
-    size_t nb = (size_t)m / (kThreads * 8);
+    // two elements per thread: enough workgroups to fill the chip for small batches;
+    // at most 64, one partial per lane of the wavefront that reduces them (k_finalize)
+    size_t nb = (size_t)m / (kThreads * 2);
     if (nb < 1) nb = 1;
     if (nb > 64) nb = 64;
     return (int)nb;
@@ -1215,9 +1235,9 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
     const size_t o_spec = c.take(std::max<int64_t>(1, spec_off) * sizeof(double));
     const size_t o_dot = c.take(std::max<int64_t>(1, dot_off) * 2 * sizeof(unsigned long long));
     const size_t o_modp = c.take((size_t)kMaxPrimes * std::max<int64_t>(1, mod_plane) * sizeof(uint32_t));
-    const size_t o_rs = c.take((size_t)n_rep * sizeof(RepDev));
-    const size_t o_kp = c.take((size_t)n_rep * sizeof(int32_t));
+    const size_t o_rs = c.take((size_t)n_rep * sizeof(RepDev));  // [records | outputs]: one download
     const size_t o_outs = c.take((size_t)nq * sizeof(OutDev));
+    const size_t o_kp = c.take((size_t)n_rep * sizeof(int32_t));
     const size_t o_Z = c.take(z_total);
     if (ws.bytes < c.off) {
         if (ws.buf) {
@@ -1233,7 +1253,7 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
     // pinned host staging: [tables | repetition records | outputs | modular-step tables]
     Carve hc;
     const size_t h_img = hc.take(host_tables);
-    const size_t h_rs = hc.take((size_t)n_rep * sizeof(RepDev));
+    const size_t h_rs = hc.take((size_t)n_rep * sizeof(RepDev));  // same relative layout as the device's
     const size_t h_outs = hc.take((size_t)nq * sizeof(OutDev));
     const size_t h_mod = hc.take(align_up(sd.size() * sizeof(void *)) + align_up((size_t)n_rep * sizeof(int32_t)) +
                                  (size_t)(n_rep + 1 + (int)groups.size()) * sizeof(int64_t) +
@@ -1334,18 +1354,21 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
     fa.kp = d_kp;
     fa.kcap = kMaxPrimes;
     fa.stage = 1;
-    hipLaunchKernelGGL(k_finalize, dim3(nq), dim3(kFinThreads), 0, s, fa);
+    hipLaunchKernelGGL(k_finalize<1>, dim3(nq), dim3(kFinThreads), 0, s, fa);
     CSK_HIP(hipGetLastError());
 
     // ---- speculative modular step: when no query has a general plan and the workspace
-    // is modest, the residues of the first kSpecPrimes primes are computed right behind
-    // stage 1, without a round trip to the host; each repetition's blocks beyond the
-    // primes it needs (decided on the device by stage 1) return at once
+    // is modest, the residues of the first ks primes are computed right behind stage 1,
+    // without a round trip to the host; each repetition's blocks beyond the primes it
+    // needs (decided on the device by stage 1) return at once.  ks is what the previous
+    // estimate on this workspace needed (kSpecPrimes for the first): the transform grid
+    // then holds no idle prime, and a repetition that needs more takes the stage below.
     int kdone = 0;
+    const int ks = ws.spec_k > 0 ? std::min(ws.spec_k, kSpecPrimes) : kSpecPrimes;
     {
         size_t spec_bytes = 0;
         for (auto &kv : groups)
-            spec_bytes += align_up((size_t)kSpecPrimes * kv.second.mod_ptrs.size() * ((size_t)1 << kv.second.log2m) *
+            spec_bytes += align_up((size_t)ks * kv.second.mod_ptrs.size() * ((size_t)1 << kv.second.log2m) *
                                    sizeof(uint32_t));
         if (general_q.empty() && !groups.empty() && spec_bytes <= kSpecBudget) {
             if (ws.mod_bytes < spec_bytes) {
@@ -1363,12 +1386,12 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
                 if (!roots) return st;
                 const int vpp = (int)G.mod_ptrs.size();
                 uint32_t *N = reinterpret_cast<uint32_t *>(mod_cur);
-                mod_cur += align_up((size_t)kSpecPrimes * vpp * ((size_t)1 << G.log2m) * sizeof(uint32_t));
-                st = ntt_forward(reinterpret_cast<const int64_t *const *>(wb + o_gptr[gi]), vpp, kSpecPrimes, N,
+                mod_cur += align_up((size_t)ks * vpp * ((size_t)1 << G.log2m) * sizeof(uint32_t));
+                st = ntt_forward(reinterpret_cast<const int64_t *const *>(wb + o_gptr[gi]), vpp, ks, N,
                                  G.log2m, primes, roots, G.log2m, s,
                                  reinterpret_cast<const int32_t *>(wb + o_grepof[gi]), d_kp);
                 if (st != CS_OK) return st;
-                hipLaunchKernelGGL(k_spec_mod, dim3((unsigned)g_pre[gi].back(), kSpecPrimes), dim3(kThreads), 0, s,
+                hipLaunchKernelGGL(k_spec_mod, dim3((unsigned)g_pre[gi].back(), ks), dim3(kThreads), 0, s,
                                    N, vpp, d_rep, reinterpret_cast<const int32_t *>(wb + o_gidx[gi]),
                                    reinterpret_cast<const int64_t *>(wb + o_gpre[gi]), (int)G.rep_idx.size(),
                                    primes, mod_plane, d_modp, d_kp);
@@ -1376,15 +1399,20 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
                 ++gi;
             }
             fa.stage = 2;
-            fa.kcap = kSpecPrimes;
-            hipLaunchKernelGGL(k_finalize, dim3(nq), dim3(kFinThreads), 0, s, fa);
+            fa.kcap = ks;
+            hipLaunchKernelGGL(k_finalize<2>, dim3(nq), dim3(kFinThreads), 0, s, fa);
             CSK_HIP(hipGetLastError());
-            kdone = kSpecPrimes;
+            kdone = ks;
         }
     }
-    CSK_HIP(hipMemcpyAsync(hr, d_rs, n_rep * sizeof(RepDev), hipMemcpyDeviceToHost, s));
-    CSK_HIP(hipMemcpyAsync(ho, d_outs, nq * sizeof(OutDev), hipMemcpyDeviceToHost, s));
-    CSK_HIP(hipStreamSynchronize(s));
+    CSK_HIP(hipMemcpyAsync(hr, d_rs, (o_outs - o_rs) + nq * sizeof(OutDev), hipMemcpyDeviceToHost, s));
+    st = wait_results(s);
+    if (st != CS_OK) return st;
+    {
+        int kmax = 0;
+        for (int i = 0; i < n_rep; ++i) kmax = std::max(kmax, (int)hr[i].kprimes);
+        ws.spec_k = kmax;
+    }
 
     // ---- stage 2: modular residues for the repetitions still waiting for them
     bool any = false;
@@ -1565,7 +1593,7 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
         }
         fa.stage = 2;
         fa.kcap = kMaxPrimes;
-        hipLaunchKernelGGL(k_finalize, dim3(nq), dim3(kFinThreads), 0, s, fa);
+        hipLaunchKernelGGL(k_finalize<2>, dim3(nq), dim3(kFinThreads), 0, s, fa);
         CSK_HIP(hipGetLastError());
         CSK_HIP(hipMemcpyAsync(ho, d_outs, nq * sizeof(OutDev), hipMemcpyDeviceToHost, s));
         if (reps_out) CSK_HIP(hipMemcpyAsync(hr, d_rs, n_rep * sizeof(RepDev), hipMemcpyDeviceToHost, s));

@@ -21,6 +21,28 @@ constexpr int kMaxLog2N = kMaxLog2M + 1;  // longest transform: a zero-padded co
 constexpr int kMaxPrimes = 12;       // modular path: up to ~370-bit results
 constexpr uint64_t kP61 = (1ull << 61) - 1;
 
+// SplitMix64 (Steele, Lea & Flood 2014).
+// Coefficients are its outputs shifted right by 3, redrawn when equal to p.
+struct SplitMix64 {
+    uint64_t s;
+    uint64_t next()
+    {
+        s += 0x9E3779B97F4A7C15ull;
+        uint64_t z = s;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+    uint64_t coef()
+    {
+        for (;;) {
+            const uint64_t c = next() >> 3;
+            if (c != kP61) return c;
+        }
+    }
+};
+
+
 // ------------------------------------------------------------------ errors
 
 void set_error(const std::string &msg);

@@ -350,6 +350,29 @@ def test_empty_sketches_estimate_zero():
         sk.close()
 
 
+def test_estimate_prime_count_changes_between_calls():
+    """The speculative modular step sizes itself from the previous estimate: a later
+    estimate that needs more primes (large weights added) or fewer (the sketch reset and
+    refilled small) must still be exact."""
+    graph, n, m, d = W.chain(3), 4_000, 1 << 12, 5
+    rels = _rels(graph, n, "zipf", 10 ** 4, config=83)
+    info = oracle.analyze(graph)
+    sk = csk.Sketch(graph, m, d, 9)
+    big = [W.random_weights(n, -2 ** 45, 2 ** 45, seed=90 + k).numpy() for k in range(graph.n_rel)]
+    for phase, weights in enumerate((None, big, None)):
+        if phase == 2:
+            sk.reset()
+        for k in range(graph.n_rel):
+            wd = None if weights is None else torch.from_numpy(weights[k]).cuda()
+            sk.update(k, to_device_keys(rels[k]), wd)
+        torch.cuda.synchronize()
+        ref = [sk.read_sketch(k) for k in range(graph.n_rel)]
+        _say("phase", phase)
+        est = _check_estimate(graph, sk, ref, m, d, info)
+        _say("  modular reps", est["n_modular"])
+    sk.close()
+
+
 def test_estimate_is_deterministic():
     graph = W.chain(4)
     n, m, d = 50_000, 1 << 15, 5
