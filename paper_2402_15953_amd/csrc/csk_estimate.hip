@@ -520,8 +520,8 @@ constexpr int kStage = kMaxD * 3 * kMaxRel;  // doubles of per-repetition bound 
 constexpr int kSpecPrimes = 5;                       // speculative modular step: primes (155 bits)
 constexpr size_t kSpecBudget = (size_t)1 << 30;      // and its largest workspace
 
-// One instantiation per stage: each holds only its stage's code (the kernel runs once
-// per estimate, so its code is fetched cold).
+// STAGE 1: fp64 / dot / norms pass; 2: residues of the modular pass; 3: both in one
+// launch (the speculative residues were computed beside the fp64 pass).
 template <int STAGE>
 __global__ __launch_bounds__(kFinThreads) void k_finalize(FinalizeArgs a)
 {
@@ -541,7 +541,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinalizeArgs a)
     const int plan = Q.plan;
     const int wv = t >> 6, lane = t & 63;
     constexpr int kWaves = kFinThreads / 64;
-    if (STAGE == 1 && plan != CS_PLAN_DOT) {
+    if (STAGE != 2 && plan != CS_PLAN_DOT) {
         // The nb <= 64 block partials of each owner (a sketch for the norms, a repetition
         // for the spectral sums) are reduced by one wavefront: lane b loads partial b and
         // a shuffle tree of depth 6 adds them, in a fixed order.
@@ -582,10 +582,12 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinalizeArgs a)
             }
         }
     }
-    if constexpr (STAGE == 2) {
+    if constexpr (STAGE != 1) {
         // residues: the nb partials of each (repetition, prime) summed by one wavefront
-        for (int o = wv; o < Q.d; o += kWaves) {
-            const int K = a.rs[Q.rep_base + o].kprimes;
+        // (stage 3: every prime of the speculative pass, the repetition's count not
+        // being known yet)
+        for (int o = wv; o < Q.d && (STAGE == 2 || plan == CS_PLAN_SPECTRAL); o += kWaves) {
+            const int K = STAGE == 3 ? a.kcap : a.rs[Q.rep_base + o].kprimes;
             if (K <= 0 || K > a.kcap) continue;
             const RepDesc D = a.reps[Q.rep_base + o];
             for (int i = 0; i < K; ++i) {
@@ -607,7 +609,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinalizeArgs a)
         // another) and the tree of depth 6 over the nb <= 64 block partials above
         const double per_thread = ceil(m / ((double)D.nb * kThreads));
         const double n_eff = per_thread + 6.0 + kThreads / 64 + 6.0;
-        if constexpr (STAGE == 1) {
+        if constexpr (STAGE != 2) {
             rp.kprimes = 0;
             rp.status = 0;
             rp.window = 0;
@@ -718,7 +720,8 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinalizeArgs a)
                     }
                 }
             }
-        } else if (rp.kprimes > 0 && rp.kprimes <= a.kcap) {  // stage 2: residues -> exact value
+        }
+        if (STAGE != 1 && rp.kprimes > 0 && rp.kprimes <= a.kcap) {  // stage 2: residues -> exact value
             const int K = rp.kprimes;
             uint32_t *res = s_res + t * kMaxPrimes, *dig = s_dig + t * kMaxPrimes;
             for (int i = 0; i < K; ++i) {
@@ -764,7 +767,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinalizeArgs a)
             }
         }
         a.rs[Q.rep_base + t] = rp;
-        if constexpr (STAGE == 1) a.kp[Q.rep_base + t] = rp.kprimes;
+        if constexpr (STAGE != 2) a.kp[Q.rep_base + t] = rp.kprimes;
         s_val[t] = rp.value;
         s_ex[t] = rp.exact;
         s_lo[t] = rp.lo;
@@ -1338,6 +1341,50 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
             ++gi;
         }
     }
+    // ---- speculative modular step: when no query has a general plan and the workspace
+    // is modest, the residues of the first ks primes are computed for every repetition
+    // right behind the fp64 pass, and one finalize launch uses both (no round trip to
+    // the host); ks is what the previous estimate on this workspace needed (kSpecPrimes
+    // for the first).  A repetition that needs more primes takes the stage below.
+    int kdone = 0;
+    const int ks = ws.spec_k >= 0 ? std::min(ws.spec_k, kSpecPrimes) : kSpecPrimes;
+    bool spec = false;
+    if (ks > 0 && general_q.empty() && !groups.empty()) {
+        size_t spec_bytes = 0;
+        for (auto &kv : groups)
+            spec_bytes += align_up((size_t)ks * kv.second.mod_ptrs.size() * ((size_t)1 << kv.second.log2m) *
+                                   sizeof(uint32_t));
+        if (spec_bytes <= kSpecBudget) {
+            if (ws.mod_bytes < spec_bytes) {
+                CSK_HIP(hipStreamSynchronize(s));
+                if (ws.mod) hipFree(ws.mod);
+                ws.mod = nullptr;
+                ws.mod_bytes = 0;
+                if (hipMalloc(&ws.mod, spec_bytes) != hipSuccess) return fail(CS_ENOMEM, "modular workspace");
+                ws.mod_bytes = spec_bytes;
+            }
+            spec = true;
+            char *mod_cur = static_cast<char *>(ws.mod);
+            int gi = 0;
+            for (auto &kv : groups) {
+                Group &G = kv.second;
+                const uint32_t *roots = roots_mod(device, G.log2m, 0, false, s, &st);
+                if (!roots) return st;
+                const int vpp = (int)G.mod_ptrs.size();
+                uint32_t *N = reinterpret_cast<uint32_t *>(mod_cur);
+                mod_cur += align_up((size_t)ks * vpp * ((size_t)1 << G.log2m) * sizeof(uint32_t));
+                st = ntt_forward(reinterpret_cast<const int64_t *const *>(wb + o_gptr[gi]), vpp, ks, N, G.log2m,
+                                 primes, roots, G.log2m, s);
+                if (st != CS_OK) return st;
+                hipLaunchKernelGGL(k_spec_mod, dim3((unsigned)g_pre[gi].back(), ks), dim3(kThreads), 0, s, N, vpp,
+                                   d_rep, reinterpret_cast<const int32_t *>(wb + o_gidx[gi]),
+                                   reinterpret_cast<const int64_t *>(wb + o_gpre[gi]), (int)G.rep_idx.size(),
+                                   primes, mod_plane, d_modp, nullptr);
+                CSK_HIP(hipGetLastError());
+                ++gi;
+            }
+        }
+    }
     FinalizeArgs fa{};
     fa.qs = d_q;
     fa.reps = d_rep;
@@ -1353,57 +1400,17 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
     fa.outs = d_outs;
     fa.kp = d_kp;
     fa.kcap = kMaxPrimes;
-    fa.stage = 1;
-    hipLaunchKernelGGL(k_finalize<1>, dim3(nq), dim3(kFinThreads), 0, s, fa);
-    CSK_HIP(hipGetLastError());
-
-    // ---- speculative modular step: when no query has a general plan and the workspace
-    // is modest, the residues of the first ks primes are computed right behind stage 1,
-    // without a round trip to the host; each repetition's blocks beyond the primes it
-    // needs (decided on the device by stage 1) return at once.  ks is what the previous
-    // estimate on this workspace needed (kSpecPrimes for the first): the transform grid
-    // then holds no idle prime, and a repetition that needs more takes the stage below.
-    int kdone = 0;
-    const int ks = ws.spec_k > 0 ? std::min(ws.spec_k, kSpecPrimes) : kSpecPrimes;
-    {
-        size_t spec_bytes = 0;
-        for (auto &kv : groups)
-            spec_bytes += align_up((size_t)ks * kv.second.mod_ptrs.size() * ((size_t)1 << kv.second.log2m) *
-                                   sizeof(uint32_t));
-        if (general_q.empty() && !groups.empty() && spec_bytes <= kSpecBudget) {
-            if (ws.mod_bytes < spec_bytes) {
-                if (ws.mod) hipFree(ws.mod);
-                ws.mod = nullptr;
-                ws.mod_bytes = 0;
-                if (hipMalloc(&ws.mod, spec_bytes) != hipSuccess) return fail(CS_ENOMEM, "modular workspace");
-                ws.mod_bytes = spec_bytes;
-            }
-            char *mod_cur = static_cast<char *>(ws.mod);
-            int gi = 0;
-            for (auto &kv : groups) {
-                Group &G = kv.second;
-                const uint32_t *roots = roots_mod(device, G.log2m, 0, false, s, &st);
-                if (!roots) return st;
-                const int vpp = (int)G.mod_ptrs.size();
-                uint32_t *N = reinterpret_cast<uint32_t *>(mod_cur);
-                mod_cur += align_up((size_t)ks * vpp * ((size_t)1 << G.log2m) * sizeof(uint32_t));
-                st = ntt_forward(reinterpret_cast<const int64_t *const *>(wb + o_gptr[gi]), vpp, ks, N,
-                                 G.log2m, primes, roots, G.log2m, s,
-                                 reinterpret_cast<const int32_t *>(wb + o_grepof[gi]), d_kp);
-                if (st != CS_OK) return st;
-                hipLaunchKernelGGL(k_spec_mod, dim3((unsigned)g_pre[gi].back(), ks), dim3(kThreads), 0, s,
-                                   N, vpp, d_rep, reinterpret_cast<const int32_t *>(wb + o_gidx[gi]),
-                                   reinterpret_cast<const int64_t *>(wb + o_gpre[gi]), (int)G.rep_idx.size(),
-                                   primes, mod_plane, d_modp, d_kp);
-                CSK_HIP(hipGetLastError());
-                ++gi;
-            }
-            fa.stage = 2;
-            fa.kcap = ks;
-            hipLaunchKernelGGL(k_finalize<2>, dim3(nq), dim3(kFinThreads), 0, s, fa);
-            CSK_HIP(hipGetLastError());
-            kdone = ks;
-        }
+    if (spec) {
+        // both finalize stages in one launch
+        fa.stage = 3;
+        fa.kcap = ks;
+        hipLaunchKernelGGL(k_finalize<3>, dim3(nq), dim3(kFinThreads), 0, s, fa);
+        CSK_HIP(hipGetLastError());
+        kdone = ks;
+    } else {
+        fa.stage = 1;
+        hipLaunchKernelGGL(k_finalize<1>, dim3(nq), dim3(kFinThreads), 0, s, fa);
+        CSK_HIP(hipGetLastError());
     }
     CSK_HIP(hipMemcpyAsync(hr, d_rs, (o_outs - o_rs) + nq * sizeof(OutDev), hipMemcpyDeviceToHost, s));
     st = wait_results(s);

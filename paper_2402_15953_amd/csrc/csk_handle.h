@@ -39,7 +39,7 @@ struct EstimateWork {
     size_t mod_bytes = 0;
     void *host = nullptr;       // pinned host staging: tables up, results down
     size_t host_bytes = 0;
-    int spec_k = 0;             // primes the last estimate's repetitions needed (0: no estimate yet)
+    int spec_k = -1;            // primes the last estimate's repetitions needed (-1: no estimate yet)
 };
 // Frees every buffer of a workspace (the device must be idle for it).
 void release_work(EstimateWork &w);
