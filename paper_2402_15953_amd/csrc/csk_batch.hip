@@ -29,6 +29,7 @@ namespace csk {
 namespace {
 
 constexpr int kBBlock = 1024;
+constexpr int kBGroup = 4;  // tuples a thread hashes together (16-bit segment tasks)
 constexpr size_t kBLds = 128 * 1024;
 
 struct BItem {
@@ -140,15 +141,116 @@ __device__ void run_segment16(const BItem &I, uint32_t seg, uint64_t begin, uint
     for (uint32_t e = threadIdx.x; e < span / 2; e += kBBlock) s_w[e] = (kBias16 << 16) | kBias16;
     __syncthreads();
     uint64_t i = begin + threadIdx.x;
+    uint32_t p_old = kBias16 * 0x10001u, p_inc = 0;  // before the first add: in range
+    uint64_t p_g = 0;
+    uint32_t *p_w = s_w;
+    if constexpr (NC <= 2) {
+    if (whole) {
+        // Whole repetitions: a thread hashes kBGroup tuples per repetition in one
+        // straight-line block (independent chains), issues their LDS adds, and checks
+        // the words the previous block's adds returned only then; the next group's keys
+        // are loaded meanwhile.  At most 2 * kBGroup unchecked adds per thread: a half
+        // stays within 2^15 +- (2^14 + 8 * 1024).
+        constexpr int G = kBGroup;
+        // the task's fields as plain locals (kept in registers)
+        const uint32_t *keys = I.keys;
+        const int64_t *weights = I.weights;
+        const uint64_t *coef = I.coef;
+        const int cpr = I.cpr;
+        const uint32_t m = I.m;
+        const bool vec2 = I.vec2 != 0;
+        const DevPlan plan = I.plan;
+        struct Pend {
+            uint32_t old, inc;
+            uint64_t g;
+            uint32_t *w;
+        };
+        Pend pend[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) pend[k] = Pend{kBias16 * 0x10001u, 0u, 0ull, s_w};
+        auto check = [&]() {
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < G; ++k) any |= out16(pend[k].old, pend[k].inc);
+            if (any) {
+#pragma unroll
+                for (int k = 0; k < G; ++k)
+                    if (out16(pend[k].old, pend[k].inc)) spill16(pend[k].w, shift16(pend[k].inc), sk + pend[k].g);
+            }
+        };
+        auto add1 = [&](int t, uint32_t j, uint32_t neg, int64_t wt) -> Pend {
+            if (weights) neg ^= (uint32_t)((uint64_t)wt >> 63);
+            const uint64_t g = (uint64_t)t * m + j;
+            const uint32_t loc = (uint32_t)(g - cell0);
+            uint32_t *w = &s_w[loc >> 1];
+            const uint32_t inc = inc16(neg, (loc & 1u) << 4);
+            return Pend{atomicAdd(w, inc), inc, g, w};
+        };
+        constexpr uint64_t B = kBBlock;
+        uint32_t xn[G][NC];
+        int64_t wn[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            wn[k] = 0;
+            if (i + k * B < end) {
+                load_keys<NC>(keys, i + k * B, vec2, xn[k]);
+                if (weights) wn[k] = weights[i + k * B];
+            }
+        }
+        for (; i + (G - 1) * B < end; i += G * B) {  // a whole group
+            uint32_t x[G][NC];
+            int64_t wt[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) x[k][c] = xn[k][c];
+                wt[k] = wn[k];
+            }
+#pragma unroll
+            for (int k = 0; k < G; ++k)
+                if (i + (G + k) * B < end) {
+                    load_keys<NC>(keys, i + (G + k) * B, vec2, xn[k]);
+                    if (weights) wn[k] = weights[i + (G + k) * B];
+                }
+            for (int t = t0; t <= t1; ++t) {
+                const uint64_t *cf = coef + (size_t)t * cpr;
+                uint32_t j[G], neg[G];
+#pragma unroll
+                for (int k = 0; k < G; ++k) hash_rep<NC>(cf, plan, x[k], j[k], neg[k]);
+                Pend now[G];
+#pragma unroll
+                for (int k = 0; k < G; ++k) now[k] = add1(t, j[k], neg[k], wt[k]);
+                check();
+#pragma unroll
+                for (int k = 0; k < G; ++k) pend[k] = now[k];
+            }
+        }
+        // fewer than G tuples left, one at a time (their keys are in xn)
+#pragma unroll
+        for (int k = 0; k < G - 1; ++k) {
+            if (i + k * B < end) {
+                for (int t = t0; t <= t1; ++t) {
+                    const uint64_t *cf = coef + (size_t)t * cpr;
+                    uint32_t j, neg;
+                    hash_rep<NC>(cf, plan, xn[k], j, neg);
+                    const Pend now = add1(t, j, neg, wn[k]);
+                    check();
+                    pend[0] = now;
+#pragma unroll
+                    for (int h = 1; h < G; ++h) pend[h] = Pend{kBias16 * 0x10001u, 0u, 0ull, s_w};
+                }
+            }
+        }
+        check();
+        i = end;  // the loop below has nothing left
+    }
+    }
     uint32_t xn[NC];
     int64_t wn = 0;
     if (i < end) {
         load_keys<NC>(I.keys, i, I.vec2 != 0, xn);
         if (I.weights) wn = I.weights[i];
     }
-    uint32_t p_old = kBias16 * 0x10001u, p_inc = 0;  // before the first add: in range
-    uint64_t p_g = 0;
-    uint32_t *p_w = s_w;
     for (; i < end; i += kBBlock) {
         uint32_t x[NC];
 #pragma unroll
