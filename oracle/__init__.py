@@ -19,6 +19,9 @@ What it computes, each function citing the passage it follows:
                      or modulo primes with Chinese remaindering (through the NTT when
                      m is a power of two, term by term otherwise)
   median_lower       median of the d repetitions (Sec. 3.3; Sec. 4.1 uses l = 5)
+  create_attr_sketch per-attribute Count sketches with per-component hash functions
+                     (Sec. 3.4 reuse) and estimate_pairwise, the two-relation estimate
+                     from two of them
   create_ams_sketch  the AMS multi-join sketch of Eq. 1 (the baseline of Sec. 2; C
                      implementation in csk_oracle.c), coefficients from
                      draw_ams_coefficients
@@ -348,6 +351,63 @@ def estimate_ams(sketches: Sequence[np.ndarray]):
             total += prod
         nums.append(total)
     return nums, median_lower(nums)
+
+
+# --------------------------------------------------------------------------- per-attribute sketches (Sec. 3.4)
+
+def draw_attr_coefficients(seed: int, d: int, n_comps: int):
+    """Hash functions shared by every join inside a graph component, for sketches kept
+    per attribute (Sec. 3.4: an attribute's sketch is reused by every sub-query that
+    joins it once): per repetition t and component q, a sign polynomial a0..a3 then a
+    bin polynomial b0, b1, in that order from the SplitMix64 stream.
+    Returns (sign uint64 [d][Q][4], bin uint64 [d][Q][2])."""
+    g = splitmix64(seed)
+
+    def coef():
+        while True:
+            c = next(g) >> 3
+            if c != P61:
+                return c
+
+    sign = np.empty((d, n_comps, 4), dtype=np.uint64)
+    bins = np.empty((d, n_comps, 2), dtype=np.uint64)
+    for t in range(d):
+        for q in range(n_comps):
+            for i in range(4):
+                sign[t, q, i] = coef()
+            for i in range(2):
+                bins[t, q, i] = coef()
+    return sign, bins
+
+
+def create_attr_sketch(keys_col, weights, m: int, sign_q: np.ndarray, bin_q: np.ndarray) -> np.ndarray:
+    """Count sketch of one attribute (one key column) with its component's hash
+    functions: int64 [d][m], counter (t, h_t(x) mod m) += s_t(x) Delta (Alg. 2 with one
+    column and one join).  sign_q [d][4], bin_q [d][2]."""
+    keys = np.ascontiguousarray(np.asarray(keys_col).astype(np.uint32, copy=False).reshape(-1, 1))
+    n = keys.shape[0]
+    d = sign_q.shape[0]
+    out = np.zeros((d, m), dtype=np.int64)
+    if n == 0:
+        return out
+    if weights is not None:
+        weights = np.ascontiguousarray(np.asarray(weights, dtype=np.int64))
+    comp = np.zeros(1, dtype=np.int32)
+    nedges = np.ones(1, dtype=np.int32)
+    edges = np.zeros((1, 1), dtype=np.int32)
+    sa = np.ascontiguousarray(sign_q.reshape(d, 1, 4), dtype=np.uint64)
+    ba = np.ascontiguousarray(bin_q.reshape(d, 1, 2), dtype=np.uint64)
+    lib().or_create_sketch(1, _ptr(comp), _ptr(nedges), _ptr(edges), 1, d, m, _ptr(sa), 1, _ptr(ba), 1,
+                           _ptr(keys), _ptr(weights), n, _ptr(out))
+    return out
+
+
+def estimate_pairwise(a: np.ndarray, b: np.ndarray):
+    """Estimate of a two-relation equi-join from two attribute sketches of the same
+    component: per repetition the inner product (Eq. 5 with r = 2), then the lower
+    median.  Returns (per-repetition exact integers, median)."""
+    reps = [sum(int(x) * int(y) for x, y in zip(a[t], b[t])) for t in range(a.shape[0])]
+    return reps, median_lower(reps)
 
 
 def filter_rows(keys, weights, attrs, predicates):

@@ -533,3 +533,50 @@ def test_ams_unbiased_within_variance_bound():
     assert abs(mean - J) <= 5 * math.sqrt(var_bound / len(xs)), (mean, J, var_bound)
     var = sum((x - mean) ** 2 for x in xs) / (len(xs) - 1)
     assert var <= 1.5 * var_bound, (var, var_bound)
+
+
+# --------------------------------------------------------------------------- per-attribute sketches (Sec. 3.4)
+
+def test_attr_sketch_single_join_equals_query_sketch():
+    """For the one-join query, the component's hash functions are the join's: the
+    per-attribute sketches and the stream order coincide with Alg. 2's sketches of the
+    query (two independent routes to the same counters)."""
+    graph = W.single_join()
+    info = oracle.analyze(graph)
+    m, d = 64, 3
+    sign, bins = oracle.draw_attr_coefficients(77, d, info.n_comp)
+    co = oracle.draw_coefficients(77, d, len(info.edges), info.n_comp)
+    assert np.array_equal(sign, co.sign_array()) and np.array_equal(bins, co.bin_array())
+    for k in range(2):
+        keys = W.random_small_relation(graph, k, 500, 40, seed=k).numpy()
+        w = W.turnstile_weights(500, 0.2, seed=k).numpy()
+        a = oracle.create_attr_sketch(keys[:, 0], w, m, sign[:, 0], bins[:, 0])
+        assert np.array_equal(a, oracle.create_sketch(info, k, keys, w, m, co))
+
+
+def test_attr_sketch_definition_and_pairwise_estimate():
+    """Counter by counter from the power-sum hashes, and the pairwise estimate against
+    the inner-product definition; E[X] over seeds is the join size."""
+    m, d = 8, 2
+    x = W.uniform_keys(300, 12, seed=3).numpy().astype(np.uint32)
+    y = W.uniform_keys(200, 12, seed=4).numpy().astype(np.uint32)
+    sign, bins = oracle.draw_attr_coefficients(5, d, 1)
+    a = oracle.create_attr_sketch(x, None, m, sign[:, 0], bins[:, 0])
+    for t in range(d):
+        ref = [0] * m
+        for v in x.tolist():
+            ref[oracle.bin_value(bins[t, 0].tolist(), v, m)] += oracle.sign_value(sign[t, 0].tolist(), v)
+        assert a[t].tolist() == ref
+    b = oracle.create_attr_sketch(y, None, m, sign[:, 0], bins[:, 0])
+    reps, med = oracle.estimate_pairwise(a, b)
+    assert reps == [int(np.dot(a[t].astype(object), b[t].astype(object))) for t in range(d)]
+    fx, fy = oracle.frequency_tensor(x.reshape(-1, 1)), oracle.frequency_tensor(y.reshape(-1, 1))
+    J = sum(c * fy.get(k, 0) for k, c in fx.items())
+    est = []
+    for seed in range(300):
+        sg, bn = oracle.draw_attr_coefficients(900 + seed, 1, 1)
+        a1 = oracle.create_attr_sketch(x, None, m, sg[:, 0], bn[:, 0])
+        b1 = oracle.create_attr_sketch(y, None, m, sg[:, 0], bn[:, 0])
+        est.append(oracle.estimate_pairwise(a1, b1)[1])
+    var_bound = 3 / m * sum(v * v for v in fx.values()) * sum(v * v for v in fy.values())
+    assert abs(sum(est) / len(est) - J) <= 5 * math.sqrt(var_bound / len(est))
