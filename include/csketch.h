@@ -414,6 +414,50 @@ cs_status cs_timer_record(void *ev, void *stream);
 cs_status cs_timer_elapsed(void *start, void *stop, float *ms);
 cs_status cs_timer_destroy(void *ev);
 
+/* ------------------------------------------------------------------ per-attribute sketches */
+
+/* Sketches kept per attribute for query optimizers (Sec. 3.4): the sizes of many
+ * sub-queries are needed, and an attribute's sketch can serve every sub-query that joins
+ * the attribute once.  Every attribute u of `graph` gets one Count sketch int64 [d][m]
+ * built with the hash functions of its graph component Psi(u) (per repetition a degree-3
+ * sign polynomial and a degree-1 bin polynomial, drawn from the seeded SplitMix64 stream
+ * in the order t, component, a0..a3, b0, b1), so the two-relation join of any two
+ * attributes of one component is estimated from their two sketches.  For a graph with one
+ * join the sketches are those cs_create draws for it. */
+typedef struct cs_attr cs_attr;  /* opaque */
+
+/* As cs_create (2 <= m <= 2^20 any m, 1 <= d <= 64); allocates w*d*m int64 counters.
+ * Errors: CS_EINVAL, CS_EGRAPH, CS_ENOMEM, CS_EDEVICE. */
+cs_status cs_attr_create(const cs_graph *graph, uint32_t m, uint32_t d, uint64_t seed, cs_attr **out);
+
+/* Free the handle (synchronises the device first). */
+cs_status cs_attr_destroy(cs_attr *h);
+
+/* One pass over n tuples of relation rel (keys uint32 [n][a_rel], tuple-major, device;
+ * weights int64 [n] or NULL for Delta = +1; flags: CS_UPDATE_UNIT_WEIGHTS): the sketch of
+ * every attribute of rel is updated (Alg. 2 with one column and one join).  Stream-
+ * ordered; calls on one handle from different streams must not overlap (they share a
+ * column buffer). */
+cs_status cs_attr_update(cs_attr *h, int32_t rel, const uint32_t *keys, const int64_t *weights,
+                         uint64_t n, int32_t flags, void *stream);
+
+/* Zero every counter (stream-ordered). */
+cs_status cs_attr_reset(cs_attr *h, void *stream);
+
+/* Estimate of the equi-join of the relations owning attributes u and v on u = v (u != v,
+ * same component): per repetition the inner product of the two sketches (Eq. 5 with
+ * r = 2), then the lower median; exact as int128 whenever sum_j |c_u c_v| < 2^126
+ * (`exact`), else fp64.  reps: optional per-repetition detail.  Synchronous on stream.
+ * Errors: CS_EINVAL (attributes out of range, equal, or in different components). */
+cs_status cs_attr_estimate_join(cs_attr *h, int32_t u, int32_t v, void *stream, cs_estimate_t *out,
+                                const cs_reps_t *reps);
+
+/* Copy attribute u's counters, int64 [d][m], to host memory (synchronises the device). */
+cs_status cs_attr_read(const cs_attr *h, int32_t u, int64_t *host_out);
+
+/* Copy the hash coefficients: sign [d][n_comp][4], bin [d][n_comp][2] (either may be NULL). */
+cs_status cs_attr_coefficients(const cs_attr *h, uint64_t *sign_out, uint64_t *bin_out);
+
 /* ------------------------------------------------------------------ AMS multi-join baseline */
 
 /* The AMS multi-join sketch of Eq. 1 (Dobra et al.; Sec. 2), the method the convolution

@@ -37,6 +37,8 @@ EXPORTED = [
     "cs_server_drain", "cs_server_stats",
     "cs_ams_create", "cs_ams_destroy", "cs_ams_update", "cs_ams_reset", "cs_ams_estimate", "cs_ams_read",
     "cs_ams_coefficients",
+    "cs_attr_create", "cs_attr_destroy", "cs_attr_update", "cs_attr_reset", "cs_attr_estimate_join",
+    "cs_attr_read", "cs_attr_coefficients",
 ]
 
 
@@ -179,6 +181,13 @@ def lib() -> ctypes.CDLL:
         L.cs_ams_estimate.argtypes = [vp, vp, ctypes.POINTER(_AmsEstimate), vp, vp, vp]
         L.cs_ams_read.argtypes = [vp, i32, vp]
         L.cs_ams_coefficients.argtypes = [vp, vp]
+        L.cs_attr_create.argtypes = [ctypes.POINTER(_Graph), u32, u32, u64, ctypes.POINTER(vp)]
+        L.cs_attr_destroy.argtypes = [vp]
+        L.cs_attr_update.argtypes = [vp, i32, vp, vp, u64, i32, vp]
+        L.cs_attr_reset.argtypes = [vp, vp]
+        L.cs_attr_estimate_join.argtypes = [vp, i32, i32, vp, ctypes.POINTER(_Estimate), ctypes.POINTER(_Reps)]
+        L.cs_attr_read.argtypes = [vp, i32, vp]
+        L.cs_attr_coefficients.argtypes = [vp, vp, vp]
         _lib = L
     return _lib
 
@@ -638,3 +647,73 @@ class AmsSketch:
         out = np.empty((self.d, self.m, n_edges, 4), dtype=np.uint64)
         _check(lib().cs_ams_coefficients(self._h, out.ctypes.data))
         return out
+
+
+class AttrSketches:
+    """One Count sketch per attribute of a query graph, with per-component hash functions
+    (Sec. 3.4): one pass per relation updates all its attributes' sketches, and any two
+    attributes of one component give their two-relation join estimate."""
+
+    def __init__(self, graph, m: int, d: int, seed: int):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("csketch needs a HIP GPU; there is no CPU fallback")
+        self.graph = graph
+        self.m, self.d, self.seed = int(m), int(d), int(seed)
+        h = ctypes.c_void_p()
+        _check(lib().cs_attr_create(ctypes.byref(_graph_struct(graph)), self.m, self.d, self.seed, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cs_attr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def update(self, rel: int, keys, weights=None, stream=None, unit_weights: bool = False):
+        n = int(keys.shape[0])
+        _check(lib().cs_attr_update(self._h, int(rel), keys.data_ptr() if n else None,
+                                    None if weights is None else weights.data_ptr(), n,
+                                    UPDATE_UNIT_WEIGHTS if unit_weights else 0, _stream_ptr(stream)))
+
+    def reset(self, stream=None):
+        _check(lib().cs_attr_reset(self._h, _stream_ptr(stream)))
+
+    def estimate_join(self, u: int, v: int, stream=None, reps: bool = False) -> dict:
+        e = _Estimate()
+        rp, arrs = _reps_struct(self.d) if reps else (None, None)
+        _check(lib().cs_attr_estimate_join(self._h, int(u), int(v), _stream_ptr(stream), ctypes.byref(e),
+                                           ctypes.byref(rp) if rp is not None else None))
+        return _estimate_dict(e, arrs)
+
+    def read_sketch(self, u: int) -> np.ndarray:
+        out = np.empty((self.d, self.m), dtype=np.int64)
+        _check(lib().cs_attr_read(self._h, int(u), out.ctypes.data))
+        return out
+
+    def coefficients(self):
+        n_comp = _n_components(self.graph)
+        sign = np.empty((self.d, n_comp, 4), dtype=np.uint64)
+        bins = np.empty((self.d, n_comp, 2), dtype=np.uint64)
+        _check(lib().cs_attr_coefficients(self._h, sign.ctypes.data, bins.ctypes.data))
+        return sign, bins
+
+
+def _n_components(graph) -> int:
+    """Connected components of the join graph's attributes."""
+    parent = list(range(graph.n_attr))
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    for u, v in graph.edges:
+        parent[find(u)] = find(v)
+    return len({find(u) for u in range(graph.n_attr)})

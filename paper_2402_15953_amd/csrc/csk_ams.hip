@@ -248,14 +248,14 @@ cs_status cs_ams_create(const cs_graph *graph, uint32_t m, uint32_t d, uint64_t 
         return fail(CS_ENOMEM, "AMS counters");
     }
     if (hipMalloc(&h.coef_dev, tab.size() * sizeof(uint64_t)) != hipSuccess) {
-        hipFree(h.counters);
+        (void)hipFree(h.counters);
         delete hs;
         return fail(CS_ENOMEM, "AMS coefficients");
     }
     if (hipMemcpy(h.coef_dev, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(h.counters, 0, cbytes) != hipSuccess) {
-        hipFree(h.counters);
-        hipFree(h.coef_dev);
+        (void)hipFree(h.counters);
+        (void)hipFree(h.coef_dev);
         delete hs;
         return fail(CS_EDEVICE, "AMS initialisation");
     }
@@ -267,11 +267,11 @@ cs_status cs_ams_destroy(cs_ams *hs)
 {
     if (!hs) return CS_OK;
     AmsHandle &h = hs->h;
-    hipDeviceSynchronize();
-    if (h.counters) hipFree(h.counters);
-    if (h.coef_dev) hipFree(h.coef_dev);
-    if (h.work) hipFree(h.work);
-    if (h.host) hipHostFree(h.host);
+    (void)hipDeviceSynchronize();
+    if (h.counters) (void)hipFree(h.counters);
+    if (h.coef_dev) (void)hipFree(h.coef_dev);
+    if (h.work) (void)hipFree(h.work);
+    if (h.host) (void)hipHostFree(h.host);
     delete hs;
     return CS_OK;
 }
@@ -324,14 +324,14 @@ cs_status cs_ams_estimate(cs_ams *hs, void *stream, cs_ams_estimate_t *out, int6
     const size_t bytes = (size_t)h.d * nb * sizeof(AmsPartial);
     if (h.work_bytes < bytes) {
         CSK_HIP(hipStreamSynchronize(s));
-        if (h.work) hipFree(h.work);
+        if (h.work) (void)hipFree(h.work);
         h.work = nullptr;
         h.work_bytes = 0;
         if (hipMalloc(&h.work, bytes) != hipSuccess) return fail(CS_ENOMEM, "AMS estimate partials");
         h.work_bytes = bytes;
     }
     if (h.host_bytes < bytes) {
-        if (h.host) hipHostFree(h.host);
+        if (h.host) (void)hipHostFree(h.host);
         h.host = nullptr;
         h.host_bytes = 0;
         if (hipHostMalloc(&h.host, bytes, hipHostMallocDefault) != hipSuccess)
