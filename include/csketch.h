@@ -399,6 +399,22 @@ cs_status cs_read_coeffs(const cs_sketch *h, uint64_t *sign_out, uint64_t *bin_o
 /* Graph component of each attribute, int32 [n_attr] (host). */
 cs_status cs_read_components(const cs_sketch *h, int32_t *psi_out);
 
+/* ------------------------------------------------------------------ checkpoint and resume */
+
+/* A sketch is its counters plus what draws its hash functions (graph, m, d, seed), so a
+ * checkpoint re-creates an identical handle, and by linearity (Sec. 2.2) updates after a
+ * resume give the counters an uninterrupted run would have.
+ *   cs_export: *needed = blob size; when buf is not NULL and cap >= *needed, writes the
+ *              blob to host memory buf (synchronises the device).  Blob: "CSKETCH1",
+ *              uint32 version 1, m, d, n_rel, n_attr, n_edge, uint64 seed, int32
+ *              attr_rel[n_attr], int32 edges[n_edge][2], int64 counters[n_rel][d][m],
+ *              uint64 FNV-1a of every preceding byte; little-endian.
+ *   cs_import: validates the blob (magic, version, ranges, length, checksum: CS_EINVAL
+ *              before any device work when it fails), creates the handle on the current
+ *              device and uploads the counters. */
+cs_status cs_export(cs_sketch *h, void *buf, size_t cap, size_t *needed);
+cs_status cs_import(const void *buf, size_t len, cs_sketch **out);
+
 /* ------------------------------------------------------------------ timing */
 
 /* Timing events (hipEvent_t) for cs_update_timed and for marks between calls, created

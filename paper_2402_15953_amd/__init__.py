@@ -39,6 +39,7 @@ EXPORTED = [
     "cs_ams_coefficients",
     "cs_attr_create", "cs_attr_destroy", "cs_attr_update", "cs_attr_reset", "cs_attr_estimate_join",
     "cs_attr_read", "cs_attr_coefficients",
+    "cs_export", "cs_import",
 ]
 
 
@@ -188,6 +189,8 @@ def lib() -> ctypes.CDLL:
         L.cs_attr_estimate_join.argtypes = [vp, i32, i32, vp, ctypes.POINTER(_Estimate), ctypes.POINTER(_Reps)]
         L.cs_attr_read.argtypes = [vp, i32, vp]
         L.cs_attr_coefficients.argtypes = [vp, vp, vp]
+        L.cs_export.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+        L.cs_import.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(vp)]
         _lib = L
     return _lib
 
@@ -417,6 +420,14 @@ class Sketch:
         out = np.zeros((self.d, self.m), dtype=np.int64)
         _check(lib().cs_read_sketch(self._h, int(rel), out.ctypes.data))
         return out
+
+    def export(self) -> bytes:
+        """Checkpoint blob (cs_export): graph, m, d, seed and counters."""
+        need = ctypes.c_size_t()
+        _check(lib().cs_export(self._h, None, 0, ctypes.byref(need)))
+        buf = ctypes.create_string_buffer(need.value)
+        _check(lib().cs_export(self._h, buf, need.value, ctypes.byref(need)))
+        return buf.raw
 
     def device_ptr(self, rel: int) -> int:
         p = ctypes.c_void_p()
@@ -717,3 +728,17 @@ def _n_components(graph) -> int:
     for u, v in graph.edges:
         parent[find(u)] = find(v)
     return len({find(u) for u in range(graph.n_attr)})
+
+
+def import_sketch(blob: bytes, graph) -> "Sketch":
+    """Re-create a handle from a cs_export blob (`graph` is kept on the Python side; the
+    blob carries its own copy, which the library checks)."""
+    h = ctypes.c_void_p()
+    _check(lib().cs_import(blob, len(blob), ctypes.byref(h)))
+    sk = Sketch.__new__(Sketch)
+    sk.graph = graph
+    sk.m = int.from_bytes(blob[12:16], "little")
+    sk.d = int.from_bytes(blob[16:20], "little")
+    sk.seed = int.from_bytes(blob[32:40], "little")
+    sk._h = h
+    return sk

@@ -21,6 +21,7 @@ SOURCES = [
     "csk_filter.hip",
     "csk_ams.hip",
     "csk_attr.hip",
+    "csk_checkpoint.hip",
     "csk_batch.hip",
     "csk_serve.hip",
 ]

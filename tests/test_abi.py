@@ -76,3 +76,35 @@ def test_tune_table_file_roundtrip(tmp_path):
         csk.tune_load(str(tmp_path / "nohdr.txt"))
     csk.tune_clear()
     assert csk.tune_count() == 0
+
+
+def _blob(m=64, d=2, seed=5, counters=None, version=1):
+    """A checkpoint blob of the one-join query, built here from the documented layout."""
+    import struct
+    n_rel, n_attr, n_edge = 2, 2, 1
+    nc = n_rel * d * m
+    counters = list(range(nc)) if counters is None else counters
+    body = b"CSKETCH1" + struct.pack("<6IQ", version, m, d, n_rel, n_attr, n_edge, seed)
+    body += struct.pack("<2i", 0, 1) + struct.pack("<2i", 0, 1) + struct.pack("<%dq" % nc, *counters)
+    h = 1469598103934665603
+    for b in body:
+        h = ((h ^ b) * 1099511628211) & ((1 << 64) - 1)
+    return body + struct.pack("<Q", h)
+
+
+def test_checkpoint_blob_validation_before_any_device_work():
+    """cs_import refuses a malformed blob with CS_EINVAL before touching the device (so
+    this runs without a GPU): wrong magic, version, length, checksum, header ranges."""
+    import paper_2402_15953_amd as csk
+    L = csk.lib()
+    good = _blob()
+    bad = [b"", b"NOTASKETCH" + good[10:], _blob(version=2), good[:-9] + good[-8:], good[:-1] + bytes([good[-1] ^ 1]),
+           _blob(m=1, counters=[0] * 4), _blob(d=65, m=2, counters=[0] * 260)]
+    corrupt = bytearray(good)
+    corrupt[60] ^= 0xFF
+    bad.append(bytes(corrupt))
+    for blob in bad:
+        h = ctypes.c_void_p()
+        st = L.cs_import(blob, len(blob), ctypes.byref(h))
+        assert st == csk.CS_EINVAL, (blob[:12], st)
+        assert not h.value
