@@ -39,7 +39,7 @@ EXPORTED = [
     "cs_ams_coefficients",
     "cs_attr_create", "cs_attr_destroy", "cs_attr_update", "cs_attr_reset", "cs_attr_estimate_join",
     "cs_attr_read", "cs_attr_coefficients",
-    "cs_export", "cs_import",
+    "cs_export", "cs_import", "cs_estimate_async",
 ]
 
 
@@ -191,6 +191,7 @@ def lib() -> ctypes.CDLL:
         L.cs_attr_coefficients.argtypes = [vp, vp, vp]
         L.cs_export.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
         L.cs_import.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+        L.cs_estimate_async.argtypes = [vp, vp, vp]
         _lib = L
     return _lib
 
@@ -409,6 +410,11 @@ class Sketch:
         _check(lib().cs_estimate(self._h, _stream_ptr(stream), ctypes.byref(e),
                                  ctypes.byref(rp) if rp is not None else None))
         return _estimate_dict(e, arrs)
+
+    def estimate_async(self, out_ptr: int, stream=None):
+        """Enqueue an estimate whose cs_estimate_t lands at out_ptr (device memory or
+        pinned host memory) once the stream passes it; see read_estimate."""
+        _check(lib().cs_estimate_async(self._h, _stream_ptr(stream), ctypes.c_void_p(out_ptr)))
 
     def reset(self, stream=None):
         _check(lib().cs_reset(self._h, _stream_ptr(stream)))
@@ -742,3 +748,13 @@ def import_sketch(blob: bytes, graph) -> "Sketch":
     sk.seed = int.from_bytes(blob[32:40], "little")
     sk._h = h
     return sk
+
+
+ESTIMATE_BYTES = ctypes.sizeof(_Estimate)
+
+
+def read_estimate(buf) -> dict:
+    """A cs_estimate_t written by Sketch.estimate_async into a pinned host tensor (uint8,
+    at least ESTIMATE_BYTES); call after the stream has passed the estimate."""
+    e = _Estimate.from_buffer_copy(bytes(buf.numpy()[:ESTIMATE_BYTES]))
+    return _estimate_dict(e, None)

@@ -433,6 +433,12 @@ cs_status cs_estimate(cs_sketch *hs, void *stream, cs_estimate_t *out, const cs_
     return estimate_run(hs->h, static_cast<hipStream_t>(stream), out, reps);
 }
 
+cs_status cs_estimate_async(cs_sketch *hs, void *stream, cs_estimate_t *out)
+{
+    if (!hs || !out) return fail(CS_EINVAL, "null argument");
+    return estimate_run_async(hs->h, static_cast<hipStream_t>(stream), out);
+}
+
 cs_status cs_reset(cs_sketch *hs, void *stream)
 {
     if (!hs) return fail(CS_EINVAL, "null handle");

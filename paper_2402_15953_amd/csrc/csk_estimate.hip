@@ -811,6 +811,23 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinalizeArgs a)
     }
 }
 
+// Asynchronous results: the finalize outputs written as cs_estimate_t into memory the
+// caller reads after the stream passes (device memory or pinned host memory).
+__global__ void k_publish(const OutDev *__restrict__ outs, const QDesc *__restrict__ qs, int nq, cs_estimate_t *dst)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    const OutDev o = outs[q];
+    cs_estimate_t e;
+    e.value = o.value;
+    e.exact = o.exact;
+    e.fits_i64 = o.fits;
+    e.value_i64 = o.fits ? o.lo : 0;
+    e.d = qs[q].d;
+    e.n_modular = o.n_modular;
+    dst[q] = e;
+}
+
 // ---------------------------------------------------------------- host: primes and tables
 
 uint32_t host_mont_mul(uint32_t a, uint32_t b, uint32_t p, uint32_t pinv_neg)
@@ -1097,7 +1114,7 @@ struct Carve {
 }  // namespace
 
 cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t *outs, const cs_reps_t *reps_out,
-                         EstimateWork &ws)
+                         EstimateWork &ws, cs_estimate_t *async_out)
 {
     if (nq <= 0) return CS_OK;
     const int device = hs[0]->device;
@@ -1203,6 +1220,8 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
     }
     const int n_rep = (int)rd.size();
     const int64_t mod_plane = mod_off;
+    if (async_out && !general_q.empty())
+        return fail(CS_EINVAL, "asynchronous estimates need queries without the general plan");
 
     // ---- workspace layout
     Carve c;
@@ -1261,6 +1280,11 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
     const size_t h_mod = hc.take(align_up(sd.size() * sizeof(void *)) + align_up((size_t)n_rep * sizeof(int32_t)) +
                                  (size_t)(n_rep + 1 + (int)groups.size()) * sizeof(int64_t) +
                                  3 * 256 * (groups.size() + 1));
+    // an asynchronous estimate may still be uploading from the staging area
+    if (ws.upload_pending) {
+        CSK_HIP(hipEventSynchronize(ws.ev_upload));
+        ws.upload_pending = false;
+    }
     if (ws.host_bytes < hc.off) {
         if (ws.host) hipHostFree(ws.host);
         ws.host = nullptr;
@@ -1300,6 +1324,11 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
         }
     }
     CSK_HIP(hipMemcpyAsync(wb, img.data(), img.size(), hipMemcpyHostToDevice, s));
+    if (async_out) {
+        if (!ws.ev_upload) CSK_HIP(hipEventCreateWithFlags(&ws.ev_upload, hipEventDisableTiming));
+        CSK_HIP(hipEventRecord(ws.ev_upload, s));
+        ws.upload_pending = true;
+    }
     const QDesc *d_q = reinterpret_cast<const QDesc *>(wb + o_q);
     RepDesc *d_rep = reinterpret_cast<RepDesc *>(wb + o_rep);
     const SkDesc *d_sk = reinterpret_cast<const SkDesc *>(wb + o_sk);
@@ -1411,6 +1440,13 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
         fa.stage = 1;
         hipLaunchKernelGGL(k_finalize<1>, dim3(nq), dim3(kFinThreads), 0, s, fa);
         CSK_HIP(hipGetLastError());
+    }
+    if (async_out) {
+        // no host round trip: repetitions that need more primes than the speculative
+        // step computed keep their fp64 value and exact = 0
+        hipLaunchKernelGGL(k_publish, dim3((nq + 63) / 64), dim3(64), 0, s, d_outs, d_q, nq, async_out);
+        CSK_HIP(hipGetLastError());
+        return CS_OK;
     }
     CSK_HIP(hipMemcpyAsync(hr, d_rs, (o_outs - o_rs) + nq * sizeof(OutDev), hipMemcpyDeviceToHost, s));
     st = wait_results(s);
@@ -1634,13 +1670,20 @@ void release_work(EstimateWork &w)
     if (w.buf) hipFree(w.buf);
     if (w.mod) hipFree(w.mod);
     if (w.host) hipHostFree(w.host);
+    if (w.ev_upload) hipEventDestroy(w.ev_upload);
     w = EstimateWork{};
 }
 
 cs_status estimate_run(Handle &h, hipStream_t s, cs_estimate_t *out, const cs_reps_t *reps)
 {
     Handle *hp = &h;
-    return estimate_batch(&hp, 1, s, out, reps, h.work);
+    return estimate_batch(&hp, 1, s, out, reps, h.work, nullptr);
+}
+
+cs_status estimate_run_async(Handle &h, hipStream_t s, cs_estimate_t *out)
+{
+    Handle *hp = &h;
+    return estimate_batch(&hp, 1, s, nullptr, nullptr, h.work, out);
 }
 
 }  // namespace csk

@@ -40,6 +40,8 @@ struct EstimateWork {
     void *host = nullptr;       // pinned host staging: tables up, results down
     size_t host_bytes = 0;
     int spec_k = -1;            // primes the last estimate's repetitions needed (-1: no estimate yet)
+    hipEvent_t ev_upload = nullptr;  // an asynchronous estimate's table upload
+    bool upload_pending = false;     // host staging still being read by that upload
 };
 // Frees every buffer of a workspace (the device must be idle for it).
 void release_work(EstimateWork &w);
@@ -64,6 +66,7 @@ struct Handle {
 };
 
 cs_status estimate_run(Handle &h, hipStream_t s, cs_estimate_t *out, const cs_reps_t *reps);
+cs_status estimate_run_async(Handle &h, hipStream_t s, cs_estimate_t *out);
 }  // namespace csk
 struct cs_sketch;
 namespace csk {
@@ -73,7 +76,7 @@ cs_status create_handle(const cs_graph *graph, uint32_t m, uint32_t d, uint64_t 
 // Estimates of nq queries at once (one FFT launch per sketch length, one product-reduce
 // launch per length, one finalize launch); reps_out may be null or hold nq entries.
 cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t *outs, const cs_reps_t *reps_out,
-                         EstimateWork &ws);
+                         EstimateWork &ws, cs_estimate_t *async_out = nullptr);
 
 }  // namespace csk
 
