@@ -14,8 +14,8 @@ namespace csk {
 // a half found outside it hands +-2^14 to the int64 sketch (global atomic) and takes it
 // off its 16-bit half by compare-and-swap, only while it is still outside, so value +
 // spilled stays exact.  The kernels run at most 1024 threads per workgroup, each with at
-// most two adds whose result it has not checked yet, so a half stays within
-// [0x3800, 0xC800] and never carries into its neighbour.
+// most eight adds whose result it has not checked yet, so a half stays within
+// [0x2000, 0xDFFF] and never carries into its neighbour.
 constexpr uint32_t kBias16 = 0x8000u, kSpill16 = 0x4000u;
 
 // Word increment of Delta = -1 (neg) or +1 on the half at bit `shift` (0 or 16).

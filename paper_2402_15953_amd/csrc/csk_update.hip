@@ -18,6 +18,8 @@
 //                    costs one atomic per wavefront instead of one per lane.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -424,6 +426,190 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16(const uint32_t *__re
     for (uint32_t e = threadIdx.x; e < span / 2; e += kSegBlock) out[e] = s_w[e];
 }
 
+// The same 16-bit update for relations of one or two key columns when one repetition
+// fills the segment (R = m): a thread takes quads of four consecutive tuples, so a quad's
+// keys arrive in one 16-byte load per column pair (A16: keys and weights 16-byte aligned;
+// otherwise one load per key).  The next quad's loads are issued before the current quad
+// is hashed, at an index clamped into the chunk instead of behind a branch; the tuples
+// after the chunk's last whole quad (at most three) go one per thread at the end.  Two
+// sets of pending adds alternate between the halves of an unrolled loop, so a quad's
+// returned words are checked after the next quad's adds without register copies; a
+// thread never has more than two quads (eight adds) unchecked.
+template <int NC, bool E1, bool HW, bool A16>
+__global__ __launch_bounds__(kSegBlock) void k_update_seg16q(const uint32_t *__restrict__ keys,
+                                                             const int64_t *__restrict__ weights, uint64_t n,
+                                                             const uint64_t *__restrict__ coef, int32_t cpr,
+                                                             DevPlan plan, uint32_t m, uint64_t chunk,
+                                                             uint32_t *partial, unsigned long long *sketch,
+                                                             uint32_t canon_thresh)
+{
+    static_assert(NC == 1 || NC == 2, "quads of one- and two-column tuples");
+    __shared__ uint32_t s_w[kSeg16Words];
+    const uint64_t cells = (uint64_t)gridDim.y * m;  // one segment per repetition
+    const SegTile wg = seg_tile();
+    const int t = (int)wg.seg;
+    for (uint32_t e = threadIdx.x; e < m / 2; e += kSegBlock) s_w[e] = (kBias16 << 16) | kBias16;
+    __syncthreads();
+    const uint64_t begin = (uint64_t)wg.chunk * chunk;  // chunk is a multiple of 4
+    const uint64_t end = begin + chunk < n ? begin + chunk : n;
+    const uint64_t len = end > begin ? end - begin : 0;
+    const uint64_t nq = len >> 2;
+    const uint64_t *cf = coef + (size_t)t * cpr;
+    CoefE1<NC> K;
+    if constexpr (E1) K.load(cf);
+    unsigned long long *srow = sketch + (uint64_t)t * m;
+
+    struct Quad {
+        uint32_t x[4][NC];
+        int64_t w[4];
+    };
+    struct Pend {
+        uint32_t old, inc, j;  // word before the add, the increment, the bucket
+    };
+    auto load_quad = [&](uint64_t q, Quad &Q) {
+        const uint64_t i0 = begin + 4 * q;
+        if constexpr (A16) {
+            const uint4 *p = reinterpret_cast<const uint4 *>(keys + i0 * NC);
+            if constexpr (NC == 1) {
+                const uint4 v = p[0];
+                Q.x[0][0] = v.x;
+                Q.x[1][0] = v.y;
+                Q.x[2][0] = v.z;
+                Q.x[3][0] = v.w;
+            } else {
+                const uint4 a = p[0], b = p[1];
+                Q.x[0][0] = a.x;
+                Q.x[0][1] = a.y;
+                Q.x[1][0] = a.z;
+                Q.x[1][1] = a.w;
+                Q.x[2][0] = b.x;
+                Q.x[2][1] = b.y;
+                Q.x[3][0] = b.z;
+                Q.x[3][1] = b.w;
+            }
+            if constexpr (HW) {
+                const longlong2 *pw = reinterpret_cast<const longlong2 *>(weights + i0);
+                const longlong2 u = pw[0], v = pw[1];
+                Q.w[0] = u.x;
+                Q.w[1] = u.y;
+                Q.w[2] = v.x;
+                Q.w[3] = v.y;
+            }
+        } else {
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) Q.x[g][c] = keys[(i0 + g) * NC + c];
+                if constexpr (HW) Q.w[g] = weights[i0 + g];
+            }
+        }
+        if constexpr (!HW) {
+#pragma unroll
+            for (int g = 0; g < 4; ++g) Q.w[g] = 1;
+        }
+    };
+    auto hash1 = [&](const uint32_t (&x)[NC], uint32_t &j, uint32_t &neg, uint32_t &flag) {
+        if constexpr (E1) {
+            K.bin_neg_fast(x, j, neg, flag);
+        } else {
+            hash_rep<NC>(cf, plan, x, j, neg);
+            flag = 0;
+        }
+    };
+    auto exact1 = [&](const uint32_t (&x)[NC], uint32_t &j, uint32_t &neg) {
+        if constexpr (E1) {
+            j = K.bin(x);
+            neg = K.neg(x);
+        }
+    };
+    // j is the bucket before the mask (E1) or reduced (otherwise); the word's byte offset
+    // masks and scales in two instructions, and the half's shift uses only bit 0 of j
+    const uint32_t word_mask = E1 ? 2 * m - 4 : ~3u;
+    auto add1 = [&](uint32_t j, uint32_t neg, int64_t wt) -> Pend {
+        if constexpr (HW) neg ^= (uint32_t)((uint64_t)wt >> 63);
+        uint32_t sgn;  // 1 - 2 neg in one instruction
+        asm("v_mad_i32_i24 %0, %1, -2, 1" : "=v"(sgn) : "v"(neg));
+        const uint32_t inc = sgn << ((j & 1u) << 4);  // inc16(neg, bit 0 of j)
+        uint32_t *w = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(s_w) + ((j << 1) & word_mask));
+        return Pend{atomicAdd(w, inc), inc, j};
+    };
+    // out16 of four adds at once: every word's both halves must show the window bit
+    auto check = [&](const Pend (&P)[4]) {
+        uint32_t all = 0x80008000u;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) all &= P[g].old + P[g].inc + 0x40004000u;
+        if (all != 0x80008000u) {
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+                if (out16(P[g].old, P[g].inc)) {
+                    const uint32_t jm = E1 ? P[g].j & (m - 1) : P[g].j;
+                    spill16(&s_w[jm >> 1], shift16(P[g].inc), srow + jm);
+                }
+        }
+    };
+    auto process = [&](const Quad &Q, Pend (&P)[4]) {
+        uint32_t j[4], neg[4], flag = 0;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            uint32_t f;
+            hash1(Q.x[g], j[g], neg[g], f);
+            flag = max(flag, f);
+        }
+        if (flag >= canon_thresh) {  // a hash may need the full reduction
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                uint32_t jj, nn, f;
+                hash1(Q.x[g], jj, nn, f);
+                if (f >= canon_thresh) exact1(Q.x[g], j[g], neg[g]);
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < 4; ++g) P[g] = add1(j[g], neg[g], Q.w[g]);
+    };
+
+    Pend pa[4], pb[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) pa[g] = pb[g] = Pend{kBias16 * 0x10001u, 0u, 0u};  // in range
+    if (nq > 0) {
+        const uint64_t last = nq - 1;
+        uint64_t q = threadIdx.x;
+        Quad A, B;
+        load_quad(q < last ? q : last, A);
+        while (q < nq) {
+            load_quad(q + kSegBlock < last ? q + kSegBlock : last, B);
+            process(A, pa);
+            check(pb);
+            q += kSegBlock;
+            if (q >= nq) break;
+            load_quad(q + kSegBlock < last ? q + kSegBlock : last, A);
+            process(B, pb);
+            check(pa);
+            q += kSegBlock;
+        }
+    }
+    check(pa);
+    check(pb);
+    // the chunk's last len mod 4 tuples, one per thread
+    if ((uint64_t)threadIdx.x < (len & 3)) {
+        const uint64_t i = begin + 4 * nq + threadIdx.x;
+        uint32_t x[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) x[c] = keys[i * NC + c];
+        const int64_t wt = HW ? weights[i] : 1;
+        uint32_t j, neg, f;
+        hash1(x, j, neg, f);
+        if (f >= canon_thresh) exact1(x, j, neg);
+        Pend one[4];
+        one[0] = add1(j, neg, wt);
+#pragma unroll
+        for (int g = 1; g < 4; ++g) one[g] = Pend{kBias16 * 0x10001u, 0u, 0u};
+        check(one);
+    }
+    __syncthreads();
+    uint32_t *out = partial + (size_t)wg.chunk * (cells >> 1) + (((uint64_t)t * m) >> 1);
+    for (uint32_t e = threadIdx.x; e < m / 2; e += kSegBlock) out[e] = s_w[e];
+}
+
 // sketch[2w + h] += sum over chunks of (half h of partial[chunk][w]) - 2^15
 __global__ void k_seg_reduce16(const uint32_t *__restrict__ partial, int32_t C, uint64_t words,
                                unsigned long long *sketch)
@@ -758,16 +944,35 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
             // 16-bit LDS counters: a whole repetition per workgroup
             SegGeom g16 = seg16_geometry(a.m, a.d, a.scratch_bytes, a.n);
             g16.chunks = chunks_for(g16.chunks, 2);
-            const uint64_t chunk16 = (a.n + g16.chunks - 1) / g16.chunks;
             dim3 grid16((unsigned)g16.chunks, (unsigned)g16.segments);
             if (g16.R > 2u * kSeg16Words) return fail(CS_EINVAL, "16-bit segment exceeds its LDS array");
             uint32_t *part = reinterpret_cast<uint32_t *>(a.scratch);
-            auto kern = a.weights ? (e1 ? &k_update_seg16<NC, true, true> : &k_update_seg16<NC, false, true>)
-                                  : (e1 ? &k_update_seg16<NC, true, false> : &k_update_seg16<NC, false, false>);
+            auto *sk64 = reinterpret_cast<unsigned long long *>(a.sketch);
             CSK_MARK(a.ev_start, s);
-            hipLaunchKernelGGL(kern, grid16, dim3(kSegBlock), 0, s, a.keys, a.weights, a.n, a.coef,
-                               a.plan.coef_per_rep, plan, a.m, log2m, a.d, g16.R, chunk16, vec2, part,
-                               reinterpret_cast<unsigned long long *>(a.sketch), a.canon_thresh);
+            if constexpr (NC <= 2) {
+                // quads of consecutive tuples: one repetition per segment, chunks of whole quads
+                if (g16.R != a.m || g16.segments != a.d) return fail(CS_EINVAL, "16-bit segment geometry");
+                const uint64_t chunkq = ((a.n + g16.chunks - 1) / g16.chunks + 3) & ~(uint64_t)3;
+                const bool a16 = (reinterpret_cast<uintptr_t>(a.keys) & 15) == 0 &&
+                                 (reinterpret_cast<uintptr_t>(a.weights) & 15) == 0;
+                auto pick = [&](auto hw, auto al) {
+                    constexpr bool HWv = decltype(hw)::value, ALv = decltype(al)::value;
+                    return e1 ? &k_update_seg16q<NC, true, HWv, ALv> : &k_update_seg16q<NC, false, HWv, ALv>;
+                };
+                using T_ = std::true_type;
+                using F_ = std::false_type;
+                auto kern = a.weights ? (a16 ? pick(T_{}, T_{}) : pick(T_{}, F_{}))
+                                      : (a16 ? pick(F_{}, T_{}) : pick(F_{}, F_{}));
+                hipLaunchKernelGGL(kern, grid16, dim3(kSegBlock), 0, s, a.keys, a.weights, a.n, a.coef,
+                                   a.plan.coef_per_rep, plan, a.m, chunkq, part, sk64, a.canon_thresh);
+            } else {
+                const uint64_t chunk16 = (a.n + g16.chunks - 1) / g16.chunks;
+                auto kern = a.weights ? (e1 ? &k_update_seg16<NC, true, true> : &k_update_seg16<NC, false, true>)
+                                      : (e1 ? &k_update_seg16<NC, true, false> : &k_update_seg16<NC, false, false>);
+                hipLaunchKernelGGL(kern, grid16, dim3(kSegBlock), 0, s, a.keys, a.weights, a.n, a.coef,
+                                   a.plan.coef_per_rep, plan, a.m, log2m, a.d, g16.R, chunk16, vec2, part, sk64,
+                                   a.canon_thresh);
+            }
             CSK_HIP(hipGetLastError());
             CSK_MARK(a.ev_stop, s);
             const uint64_t words = cells / 2;

@@ -181,6 +181,35 @@ def test_counters16_spill(kind):
         sk.close()
 
 
+@pytest.mark.parametrize("offset", [0, 1, 2, 3])
+@pytest.mark.parametrize("n", [1, 3, 4, 4097, 100_003])
+def test_counters16_alignment_and_tails(offset, n):
+    """16-bit kernel: key and weight arrays starting at every 4-byte offset modulo 16 bytes
+    (the quad loads need 16-byte alignment, the other form takes any), chunk lengths
+    with 0-3 tuples after the last whole quad, one or several chunks, weights +1 (NULL)
+    and +-1."""
+    graph = W.chain(3)
+    m, d, seed = 1 << 16, 3, 5
+    _say("counters16 alignment", offset, n)
+    rels = _rels(graph, n + offset, "zipf", 10 ** 4, config=95)
+    weights = [W.turnstile_weights(n + offset, 0.2, seed=k).numpy() for k in range(graph.n_rel)]
+    refs = {}
+    for use_w in (False, True):
+        _, _, refs[use_w] = oracle_sketches(graph, [r[offset:] for r in rels],
+                                            [w[offset:] for w in weights] if use_w else None, m, d, seed)
+    for grid in (0, 3):
+        for use_w in (False, True):
+            sk = csk.Sketch(graph, m, d, seed)
+            for k in range(graph.n_rel):
+                kd = to_device_keys(rels[k])[offset:]
+                wd = torch.from_numpy(weights[k]).cuda()[offset:] if use_w else None
+                sk.update(k, kd, wd, strategy=2, grid=grid, unit_weights=True)
+            torch.cuda.synchronize()
+            for k in range(graph.n_rel):
+                assert np.array_equal(sk.read_sketch(k), refs[use_w][k]), (grid, use_w, k)
+            sk.close()
+
+
 @pytest.mark.parametrize("case", range(len(SKETCH_CASES)))
 @pytest.mark.parametrize("strategy", [0, 1, 2, 3, 4])
 def test_sketch_bit_exact(case, strategy):
