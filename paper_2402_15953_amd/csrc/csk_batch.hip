@@ -14,6 +14,8 @@
 // per-query path whatever the task order.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 #include <cstring>
 #include <new>
@@ -29,7 +31,6 @@ namespace csk {
 namespace {
 
 constexpr int kBBlock = 1024;
-constexpr int kBGroup = 4;  // tuples a thread hashes together (16-bit segment tasks)
 constexpr size_t kBLds = 128 * 1024;
 
 struct BItem {
@@ -46,6 +47,7 @@ struct BItem {
     uint32_t R;        // cells per segment (segment tasks)
     int32_t narrow;    // int32 LDS counters (Deltas +-1)
     int32_t vec2;      // two-column keys 8-byte aligned
+    int32_t e1;        // every key column in exactly one join and m a power of two
     DevPlan plan;
 };
 
@@ -127,6 +129,145 @@ __device__ void run_segment(const BItem &I, uint32_t seg, uint64_t begin, uint64
 // 128 KB, whole repetitions when m <= 2^16.  Keys of the next tuple are loaded while
 // this one is hashed, and each LDS add's returned value is checked one add later.
 // At the end, each non-zero counter is added into the sketch with one global atomic.
+// Whole repetitions in the segment, one or two key columns: a thread takes quads of four
+// consecutive tuples (loaded at an index clamped into the range, so no bounds branches),
+// and per repetition hashes the quad in one straight-line block, issues its four LDS adds
+// and checks the returned words right away (the other wavefronts cover the LDS latency).
+// E1 (every column in exactly one join, m a power of two): coefficients in registers and
+// the canonical reduction skipped unless a hash's flag asks for it.  The range's last
+// (end - begin) mod 4 tuples go one per thread.
+// Values the whole workgroup shares, moved into scalar registers (the compiler cannot
+// tell that fields read from the task table are uniform).
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni(uint64_t v)
+{
+    return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
+}
+template <typename T>
+__device__ __forceinline__ T *uni(T *p)
+{
+    return reinterpret_cast<T *>(uni(reinterpret_cast<uint64_t>(p)));
+}
+// global and constant address-space views of the item's arrays: global loads instead of
+// flat ones, and scalar loads for the coefficients
+using GU32 = const __attribute__((address_space(1))) uint32_t *;
+using GU64 = const __attribute__((address_space(1))) uint64_t *;
+using GI64 = const __attribute__((address_space(1))) int64_t *;
+using CU64 = const __attribute__((address_space(4))) uint64_t *;
+
+template <int NC, bool E1>
+__device__ __forceinline__ void seg16_quads(const BItem &I, uint64_t begin_, uint64_t end_, uint64_t cell0_, int t0_,
+                                            int t1_, uint32_t *s_w, unsigned long long *sk_)
+{
+    const GU32 keys = (GU32)uni(I.keys);
+    const GI64 weights = (GI64)uni(I.weights);
+    const CU64 coef = (CU64)uni(I.coef);
+    const int cpr = (int)uni((uint32_t)I.cpr);
+    const uint32_t m = uni(I.m);
+    const bool vec2 = uni((uint32_t)I.vec2) != 0;
+    const uint64_t begin = uni(begin_), end = uni(end_), cell0 = uni(cell0_);
+    const int t0 = (int)uni((uint32_t)t0_), t1 = (int)uni((uint32_t)t1_);
+    unsigned long long *sk = uni(sk_);
+    const DevPlan plan = I.plan;
+    const uint64_t len = end - begin, nq = len >> 2;
+    struct Quad {
+        uint32_t x[4][NC];
+        uint32_t wneg;  // bit g: tuple g's Delta is -1 (16-bit segments take Deltas +-1 only)
+    };
+    struct Pend {
+        uint32_t old, inc, loc;
+    };
+    auto load1 = [&](uint64_t i, uint32_t (&x)[NC]) {
+        if constexpr (NC == 2) {
+            if (vec2) {
+                const uint64_t v = ((GU64)keys)[i];  // little-endian: column 0 in the low word
+                x[0] = (uint32_t)v;
+                x[1] = (uint32_t)(v >> 32);
+                return;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) x[c] = keys[i * NC + c];
+    };
+    auto load_quad = [&](uint64_t q, Quad &Q) {
+        const uint64_t i0 = begin + 4 * q;
+        Q.wneg = 0;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            load1(i0 + g, Q.x[g]);
+            if (weights) Q.wneg |= (uint32_t)((uint64_t)weights[i0 + g] >> 63) << g;
+        }
+    };
+    auto add1 = [&](uint32_t row, uint32_t j, uint32_t neg) -> Pend {
+        if constexpr (E1) j &= m - 1;
+        const uint32_t loc = row + j;  // row is a multiple of m, so even
+        const uint32_t inc = inc16(neg, (j & 1u) << 4);
+        return Pend{atomicAdd(&s_w[loc >> 1], inc), inc, loc};
+    };
+    auto check = [&](const Pend *P, int k) {
+        uint32_t all = 0x80008000u;
+        for (int g = 0; g < k; ++g) all &= P[g].old + P[g].inc + 0x40004000u;
+        if (all != 0x80008000u) {
+            for (int g = 0; g < k; ++g)
+                if (out16(P[g].old, P[g].inc)) spill16(&s_w[P[g].loc >> 1], shift16(P[g].inc), sk + cell0 + P[g].loc);
+        }
+    };
+    // hash tuples [0, K) of a quad for repetition t, add them, check them
+    auto run = [&](const Quad &Q, auto kc, int t) {
+        constexpr int K = decltype(kc)::value;
+        const CU64 cf = coef + (size_t)t * cpr;
+        const uint32_t row = (uint32_t)((uint64_t)t * m - cell0);
+        uint32_t j[K], neg[K];
+        if constexpr (E1) {
+            CoefE1<NC> C;
+            C.load(cf);
+            uint32_t flag = 0;
+#pragma unroll
+            for (int g = 0; g < K; ++g) {
+                uint32_t f;
+                C.bin_neg_fast(Q.x[g], j[g], neg[g], f);
+                flag = max(flag, f);
+            }
+            if (flag >= 0xFFFFFFFFu) {  // a hash may need the full reduction
+#pragma unroll
+                for (int g = 0; g < K; ++g) {
+                    j[g] = C.bin(Q.x[g]);
+                    neg[g] = C.neg(Q.x[g]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int g = 0; g < K; ++g) hash_rep<NC>((const uint64_t *)cf, plan, Q.x[g], j[g], neg[g]);
+        }
+        Pend P[K];
+#pragma unroll
+        for (int g = 0; g < K; ++g) P[g] = add1(row, j[g], neg[g] ^ ((Q.wneg >> g) & 1u));
+        check(P, K);
+    };
+    if (nq > 0) {
+        const uint64_t last = nq - 1;
+        uint64_t q = threadIdx.x;
+        Quad A, B;
+        load_quad(q < last ? q : last, A);
+        while (q < nq) {
+            load_quad(q + kBBlock < last ? q + kBBlock : last, B);
+            for (int t = t0; t <= t1; ++t) run(A, std::integral_constant<int, 4>{}, t);
+            q += kBBlock;
+            if (q >= nq) break;
+            load_quad(q + kBBlock < last ? q + kBBlock : last, A);
+            for (int t = t0; t <= t1; ++t) run(B, std::integral_constant<int, 4>{}, t);
+            q += kBBlock;
+        }
+    }
+    if ((uint64_t)threadIdx.x < (len & 3)) {
+        const uint64_t i = begin + 4 * nq + threadIdx.x;
+        Quad Q;
+        load1(i, Q.x[0]);
+        Q.wneg = weights ? (uint32_t)((uint64_t)weights[i] >> 63) : 0u;
+        for (int t = t0; t <= t1; ++t) run(Q, std::integral_constant<int, 1>{}, t);
+    }
+}
+
 template <int NC>
 __device__ void run_segment16(const BItem &I, uint32_t seg, uint64_t begin, uint64_t end, uint32_t *s_w)
 {
@@ -145,105 +286,11 @@ __device__ void run_segment16(const BItem &I, uint32_t seg, uint64_t begin, uint
     uint64_t p_g = 0;
     uint32_t *p_w = s_w;
     if constexpr (NC <= 2) {
-    if (whole) {
-        // Whole repetitions: a thread hashes kBGroup tuples per repetition in one
-        // straight-line block (independent chains), issues their LDS adds, and checks
-        // the words the previous block's adds returned only then; the next group's keys
-        // are loaded meanwhile.  At most 2 * kBGroup unchecked adds per thread: a half
-        // stays within 2^15 +- (2^14 + 8 * 1024).
-        constexpr int G = kBGroup;
-        // the task's fields as plain locals (kept in registers)
-        const uint32_t *keys = I.keys;
-        const int64_t *weights = I.weights;
-        const uint64_t *coef = I.coef;
-        const int cpr = I.cpr;
-        const uint32_t m = I.m;
-        const bool vec2 = I.vec2 != 0;
-        const DevPlan plan = I.plan;
-        struct Pend {
-            uint32_t old, inc;
-            uint64_t g;
-            uint32_t *w;
-        };
-        Pend pend[G];
-#pragma unroll
-        for (int k = 0; k < G; ++k) pend[k] = Pend{kBias16 * 0x10001u, 0u, 0ull, s_w};
-        auto check = [&]() {
-            bool any = false;
-#pragma unroll
-            for (int k = 0; k < G; ++k) any |= out16(pend[k].old, pend[k].inc);
-            if (any) {
-#pragma unroll
-                for (int k = 0; k < G; ++k)
-                    if (out16(pend[k].old, pend[k].inc)) spill16(pend[k].w, shift16(pend[k].inc), sk + pend[k].g);
-            }
-        };
-        auto add1 = [&](int t, uint32_t j, uint32_t neg, int64_t wt) -> Pend {
-            if (weights) neg ^= (uint32_t)((uint64_t)wt >> 63);
-            const uint64_t g = (uint64_t)t * m + j;
-            const uint32_t loc = (uint32_t)(g - cell0);
-            uint32_t *w = &s_w[loc >> 1];
-            const uint32_t inc = inc16(neg, (loc & 1u) << 4);
-            return Pend{atomicAdd(w, inc), inc, g, w};
-        };
-        constexpr uint64_t B = kBBlock;
-        uint32_t xn[G][NC];
-        int64_t wn[G];
-#pragma unroll
-        for (int k = 0; k < G; ++k) {
-            wn[k] = 0;
-            if (i + k * B < end) {
-                load_keys<NC>(keys, i + k * B, vec2, xn[k]);
-                if (weights) wn[k] = weights[i + k * B];
-            }
+        if (whole) {
+            if (I.e1) seg16_quads<NC, true>(I, begin, end, cell0, t0, t1, s_w, sk);
+            else seg16_quads<NC, false>(I, begin, end, cell0, t0, t1, s_w, sk);
+            i = end;  // the loop below has nothing left
         }
-        for (; i + (G - 1) * B < end; i += G * B) {  // a whole group
-            uint32_t x[G][NC];
-            int64_t wt[G];
-#pragma unroll
-            for (int k = 0; k < G; ++k) {
-#pragma unroll
-                for (int c = 0; c < NC; ++c) x[k][c] = xn[k][c];
-                wt[k] = wn[k];
-            }
-#pragma unroll
-            for (int k = 0; k < G; ++k)
-                if (i + (G + k) * B < end) {
-                    load_keys<NC>(keys, i + (G + k) * B, vec2, xn[k]);
-                    if (weights) wn[k] = weights[i + (G + k) * B];
-                }
-            for (int t = t0; t <= t1; ++t) {
-                const uint64_t *cf = coef + (size_t)t * cpr;
-                uint32_t j[G], neg[G];
-#pragma unroll
-                for (int k = 0; k < G; ++k) hash_rep<NC>(cf, plan, x[k], j[k], neg[k]);
-                Pend now[G];
-#pragma unroll
-                for (int k = 0; k < G; ++k) now[k] = add1(t, j[k], neg[k], wt[k]);
-                check();
-#pragma unroll
-                for (int k = 0; k < G; ++k) pend[k] = now[k];
-            }
-        }
-        // fewer than G tuples left, one at a time (their keys are in xn)
-#pragma unroll
-        for (int k = 0; k < G - 1; ++k) {
-            if (i + k * B < end) {
-                for (int t = t0; t <= t1; ++t) {
-                    const uint64_t *cf = coef + (size_t)t * cpr;
-                    uint32_t j, neg;
-                    hash_rep<NC>(cf, plan, xn[k], j, neg);
-                    const Pend now = add1(t, j, neg, wn[k]);
-                    check();
-                    pend[0] = now;
-#pragma unroll
-                    for (int h = 1; h < G; ++h) pend[h] = Pend{kBias16 * 0x10001u, 0u, 0ull, s_w};
-                }
-            }
-        }
-        check();
-        i = end;  // the loop below has nothing left
-    }
     }
     uint32_t xn[NC];
     int64_t wn = 0;
@@ -320,7 +367,8 @@ __global__ __launch_bounds__(kBBlock) void k_batch_update(const BItem *__restric
     for (;;) {
         if (threadIdx.x == 0) s_task = (int)atomicAdd(counter, 1u);
         __syncthreads();
-        const int task = s_task;
+        // wave-uniform, so the task and item fields load into scalar registers
+        const int task = __builtin_amdgcn_readfirstlane(s_task);
         __syncthreads();
         if (task >= n_tasks) break;
         const BTask T = tasks[task];
@@ -389,6 +437,8 @@ cs_status plan_batch(BatchState &B, const cs_update_item *items, int32_t n_items
         I.vec2 = rp.n_cols == 2 && ((uintptr_t)it.keys % 8) == 0;
         for (int c = 0; c < kMaxCols; ++c) I.plan.n_edges[c] = c < rp.n_cols ? rp.n_edges[c] : 0;
         I.plan.bm = make_binmod(h.m);
+        I.e1 = (h.m & (h.m - 1)) == 0;
+        for (int c = 0; c < rp.n_cols; ++c) I.e1 = I.e1 && rp.n_edges[c] == 1;
         // LDS segment: 2^16 16-bit counters (Deltas +-1) or 2^14 int64 counters
         uint32_t R = I.narrow ? (1u << 16) : (1u << 14);
         if (h.m <= R) R = (R / h.m) * h.m;

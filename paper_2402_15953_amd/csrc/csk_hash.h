@@ -175,7 +175,8 @@ __host__ __device__ inline BinMod make_binmod(uint32_t m)
 template <int NC>
 struct CoefE1 {
     uint64_t b0[NC], b1[NC], a[NC][4];
-    __device__ __forceinline__ void load(const uint64_t *__restrict__ cf)
+    template <typename P>  // a generic, global or constant address-space pointer
+    __device__ __forceinline__ void load(P cf)
     {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {

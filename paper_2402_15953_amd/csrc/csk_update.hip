@@ -431,10 +431,11 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16(const uint32_t *__re
 // keys arrive in one 16-byte load per column pair (A16: keys and weights 16-byte aligned;
 // otherwise one load per key).  The next quad's loads are issued before the current quad
 // is hashed, at an index clamped into the chunk instead of behind a branch; the tuples
-// after the chunk's last whole quad (at most three) go one per thread at the end.  Two
-// sets of pending adds alternate between the halves of an unrolled loop, so a quad's
-// returned words are checked after the next quad's adds without register copies; a
-// thread never has more than two quads (eight adds) unchecked.
+// after the chunk's last whole quad (at most three) go one per thread at the end.  The
+// loop is unrolled twice so that the two quads' keys alternate between two register sets
+// without copies.  A quad's four returned words are checked right after its adds (the
+// other wavefronts of the SIMD cover the LDS latency; deferring the check to the next quad
+// measured slower, its register copies outweighing the wait).
 template <int NC, bool E1, bool HW, bool A16>
 __global__ __launch_bounds__(kSegBlock) void k_update_seg16q(const uint32_t *__restrict__ keys,
                                                              const int64_t *__restrict__ weights, uint64_t n,
@@ -567,9 +568,7 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16q(const uint32_t *__r
         for (int g = 0; g < 4; ++g) P[g] = add1(j[g], neg[g], Q.w[g]);
     };
 
-    Pend pa[4], pb[4];
-#pragma unroll
-    for (int g = 0; g < 4; ++g) pa[g] = pb[g] = Pend{kBias16 * 0x10001u, 0u, 0u};  // in range
+    Pend P[4];
     if (nq > 0) {
         const uint64_t last = nq - 1;
         uint64_t q = threadIdx.x;
@@ -577,18 +576,16 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16q(const uint32_t *__r
         load_quad(q < last ? q : last, A);
         while (q < nq) {
             load_quad(q + kSegBlock < last ? q + kSegBlock : last, B);
-            process(A, pa);
-            check(pb);
+            process(A, P);
+            check(P);
             q += kSegBlock;
             if (q >= nq) break;
             load_quad(q + kSegBlock < last ? q + kSegBlock : last, A);
-            process(B, pb);
-            check(pa);
+            process(B, P);
+            check(P);
             q += kSegBlock;
         }
     }
-    check(pa);
-    check(pb);
     // the chunk's last len mod 4 tuples, one per thread
     if ((uint64_t)threadIdx.x < (len & 3)) {
         const uint64_t i = begin + 4 * nq + threadIdx.x;
