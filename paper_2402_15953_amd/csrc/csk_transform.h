@@ -35,19 +35,26 @@ struct PrimeDev {
     uint32_t minv[kMaxLog2N + 1];  // Montgomery form of 2^-L mod p
 };
 
+// Row length 2^S of the two-pass transforms (lengths above 4096), which is also their
+// tile: the smallest S >= 10 that leaves the column pass at least 8 interleaved columns
+// (128 contiguous bytes of fp64 complex per row read): 1024 for 2^13..2^17, 2048 for
+// 2^18..2^19, 4096 for 2^20..2^21.
+__host__ __device__ inline int split_bits(int log2m) { return (log2m + 4) / 2 > 10 ? (log2m + 4) / 2 : 10; }
+
 // Position of frequency f in the output of the forward transform of length 2^log2m.
 __host__ __device__ inline uint32_t freq_pos(uint32_t f, int log2m)
 {
     if (log2m <= 12) return f;
-    const uint32_t n1 = 1u << (log2m - 12);
-    return ((f & (n1 - 1)) << 12) | (f >> (log2m - 12));
+    const int S = split_bits(log2m);
+    const uint32_t n1 = 1u << (log2m - S);
+    return ((f & (n1 - 1)) << S) | (f >> (log2m - S));
 }
 // Frequency held at position pos of the forward transform's output.
 __host__ __device__ inline uint32_t pos_freq(uint32_t pos, int log2m)
 {
     if (log2m <= 12) return pos;
-    const int l1 = log2m - 12;
-    return (pos >> 12) | ((pos & 4095u) << l1);
+    const int S = split_bits(log2m);
+    return (pos >> S) | ((pos & ((1u << S) - 1)) << (log2m - S));
 }
 
 // Forward fp64 FFTs of n_vec complex vectors re[v] + i im[v] (device pointer tables of

@@ -3,16 +3,19 @@
 // transform (same structure, Montgomery arithmetic modulo a 31-bit prime) used for the
 // exact modular evaluation.
 //
-// Lengths up to 4096 are done in one pass inside LDS.  Longer lengths m = N1 * 4096 use
-// the four-step decomposition (Bailey): element n = 4096 n1 + n2.
-//   forward: pass 1 transforms each column n2 over n1 (stride 4096) and multiplies
-//            output f1 by w_m^(f1 n2); pass 2 transforms each row over n2.  Position
-//            4096 f1 + f2 then holds frequency f = f1 + N1 f2 (no final transpose).
+// Lengths up to 4096 are done in one pass inside LDS.  Longer lengths m = N1 * N2 (N2 =
+// 2^S, S = split_bits(log2 m), from 1024 to 4096) use the four-step decomposition
+// (Bailey): element n = N2 n1 + n2.
+//   forward: pass 1 transforms each column n2 over n1 (stride N2) and multiplies output
+//            f1 by w_m^(f1 n2); pass 2 transforms each row over n2.  Position N2 f1 + f2
+//            then holds frequency f = f1 + N1 f2 (no final transpose).
 //   inverse: takes that permuted order back to natural order: row pass over f2 with
 //            w_m^(-n2 f1) applied to output n2, then the column pass over f1.
 // Inside LDS each tile is loaded in bit-reversed order and finished by radix-2
 // decimation-in-time stages; twiddles come from host-computed tables.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "csk_internal.h"
 #include "csk_rings.h"
@@ -22,8 +25,12 @@ namespace csk {
 
 namespace {
 
-constexpr int kTile = 4096;
-constexpr int kThreads = 1024;  // 16 wavefronts per tile: two butterflies per thread per stage
+// A block transforms one tile of TILE elements with TILE / 4 threads (two butterflies
+// per thread per stage).  Two-pass lengths use the smallest tile that keeps the column
+// pass's reads in runs of at least 8 elements: a 2^16-point transform is 64 blocks of
+// 1024 elements per vector (24 KB of LDS each, several blocks per CU) rather than 16
+// blocks of 4096 (96 KB, one per CU), so its passes fill the chip.
+constexpr int kSingleTile = 4096;
 
 __device__ __forceinline__ uint32_t bitrev(uint32_t x, int bits)
 {
@@ -32,10 +39,10 @@ __device__ __forceinline__ uint32_t bitrev(uint32_t x, int bits)
 
 // Copies w_L^j (j < L / 2, L = 2^log2L) from the table tw[k] = w_T^k, T = 2^log2T, into
 // LDS; every stage of a length-L transform takes its twiddles from there.
-template <class T>
+template <int NT, class T>
 __device__ __forceinline__ void load_stage_twiddles(T *stw, int log2L, const T *__restrict__ tw, int log2T)
 {
-    for (int j = threadIdx.x; j < (1 << (log2L - 1)); j += kThreads) stw[j] = tw[(size_t)j << (log2T - log2L)];
+    for (int j = threadIdx.x; j < (1 << (log2L - 1)); j += NT) stw[j] = tw[(size_t)j << (log2T - log2L)];
 }
 
 // Radix-2 DIT stages on C interleaved transforms of length 2^log2L held in LDS as
@@ -43,7 +50,7 @@ __device__ __forceinline__ void load_stage_twiddles(T *stw, int log2L, const T *
 // Stages go in pairs: a thread takes the four elements two consecutive stages combine,
 // applies both stages' radix-2 butterflies in registers (the same operations as two
 // separate stages, so the same rounding), and writes them back once.
-template <class Ring>
+template <int NT, class Ring>
 __device__ __forceinline__ void lds_stages(typename Ring::T *s, int log2L, int log2C, const Ring &R,
                                            const typename Ring::T *stw)
 {
@@ -53,7 +60,7 @@ __device__ __forceinline__ void lds_stages(typename Ring::T *s, int log2L, int l
     for (; lh + 1 < log2L; lh += 2) {
         const int half = 1 << lh;
         const int ngr = (1 << (log2L - 2)) << log2C;
-        for (int b = threadIdx.x; b < ngr; b += kThreads) {
+        for (int b = threadIdx.x; b < ngr; b += NT) {
             const int c = b & (C - 1);
             const int bb = b >> log2C;
             const int k = bb & (half - 1);
@@ -81,7 +88,7 @@ __device__ __forceinline__ void lds_stages(typename Ring::T *s, int log2L, int l
     const int nbf = (1 << (log2L - 1)) << log2C;
     for (; lh < log2L; ++lh) {  // the last stage when their number is odd
         const int half = 1 << lh;
-        for (int b = threadIdx.x; b < nbf; b += kThreads) {
+        for (int b = threadIdx.x; b < nbf; b += NT) {
             const int c = b & (C - 1);
             const int bb = b >> log2C;
             const int k = bb & (half - 1);
@@ -105,11 +112,13 @@ struct F64Src {
     const int64_t *const *im;  // [n_vec] sketch loaded as the imaginary part (entry null: 0)
 };
 
-__global__ __launch_bounds__(kThreads) void k_fft_f64(F64Src src, double2 *buf, PassGeom g,
-                                                      const double2 *__restrict__ tw, int log2T)
+template <int TILE>
+__global__ __launch_bounds__(TILE / 4) void k_fft_f64(F64Src src, double2 *buf, PassGeom g,
+                                                     const double2 *__restrict__ tw, int log2T)
 {
-    __shared__ double2 s[kTile];
-    __shared__ double2 stw[kTile / 2];
+    constexpr int NT = TILE / 4;
+    __shared__ double2 s[TILE];
+    __shared__ double2 stw[TILE / 2];
     const int v = blockIdx.x;
     const int blk = blockIdx.y;
     const int C = 1 << g.log2C;
@@ -121,24 +130,24 @@ __global__ __launch_bounds__(kThreads) void k_fft_f64(F64Src src, double2 *buf, 
     if (src.re) {
         const int64_t *re = src.re[v];
         const int64_t *im = src.im[v];
-        for (int idx = threadIdx.x; idx < total; idx += kThreads) {
+        for (int idx = threadIdx.x; idx < total; idx += NT) {
             const int n = idx >> g.log2C, c = idx & (C - 1);
             const int64_t pos = base + (int64_t)c * g.col_stride + (int64_t)n * g.elem_stride;
             s[(bitrev(n, g.log2L) << g.log2C) + c] =
                 make_double2((double)re[pos], im ? (double)im[pos] : 0.0);
         }
     } else {
-        for (int idx = threadIdx.x; idx < total; idx += kThreads) {
+        for (int idx = threadIdx.x; idx < total; idx += NT) {
             const int n = idx >> g.log2C, c = idx & (C - 1);
             const int64_t pos = base + (int64_t)c * g.col_stride + (int64_t)n * g.elem_stride;
             s[(bitrev(n, g.log2L) << g.log2C) + c] = vec[pos];
         }
     }
-    load_stage_twiddles(stw, g.log2L, tw, log2T);
+    load_stage_twiddles<NT>(stw, g.log2L, tw, log2T);
     __syncthreads();
     RingC R;
-    lds_stages<RingC>(s, g.log2L, g.log2C, R, stw);
-    for (int idx = threadIdx.x; idx < total; idx += kThreads) {
+    lds_stages<NT, RingC>(s, g.log2L, g.log2C, R, stw);
+    for (int idx = threadIdx.x; idx < total; idx += NT) {
         const int n = idx >> g.log2C, c = idx & (C - 1);
         const int64_t pos = base + (int64_t)c * g.col_stride + (int64_t)n * g.elem_stride;
         double2 val = s[(n << g.log2C) + c];
@@ -157,13 +166,15 @@ struct ModSrc {
     const int64_t *const *ptr;  // [vec_per_prime] sketch of vector v % vec_per_prime (null: in place)
 };
 
-__global__ __launch_bounds__(kThreads) void k_ntt(ModSrc src, uint32_t *buf, PassGeom g, int vec_per_prime,
-                                                  const PrimeDev *__restrict__ primes,
-                                                  const uint32_t *__restrict__ roots, int log2T, int inverse,
-                                                  const int32_t *__restrict__ rep_of, const int32_t *__restrict__ kp)
+template <int TILE>
+__global__ __launch_bounds__(TILE / 4) void k_ntt(ModSrc src, uint32_t *buf, PassGeom g, int vec_per_prime,
+                                                 const PrimeDev *__restrict__ primes,
+                                                 const uint32_t *__restrict__ roots, int log2T, int inverse,
+                                                 const int32_t *__restrict__ rep_of, const int32_t *__restrict__ kp)
 {
-    __shared__ uint32_t s[kTile];
-    __shared__ uint32_t stw[kTile / 2];
+    constexpr int NT = TILE / 4;
+    __shared__ uint32_t s[TILE];
+    __shared__ uint32_t stw[TILE / 2];
     const int v = blockIdx.x;
     const int pi = v / vec_per_prime;
     if (kp && pi >= kp[rep_of[v % vec_per_prime]]) return;  // prime not needed
@@ -179,22 +190,22 @@ __global__ __launch_bounds__(kThreads) void k_ntt(ModSrc src, uint32_t *buf, Pas
     const int total = L << g.log2C;
     if (src.ptr) {
         const int64_t *in = src.ptr[v % vec_per_prime];
-        for (int idx = threadIdx.x; idx < total; idx += kThreads) {
+        for (int idx = threadIdx.x; idx < total; idx += NT) {
             const int n = idx >> g.log2C, c = idx & (C - 1);
             const int64_t pos = base + (int64_t)c * g.col_stride + (int64_t)n * g.elem_stride;
             s[(bitrev(n, g.log2L) << g.log2C) + c] = mont_from_i64(R, in[pos], P.r2, P.r3, P.neg2_64);
         }
     } else {
-        for (int idx = threadIdx.x; idx < total; idx += kThreads) {
+        for (int idx = threadIdx.x; idx < total; idx += NT) {
             const int n = idx >> g.log2C, c = idx & (C - 1);
             const int64_t pos = base + (int64_t)c * g.col_stride + (int64_t)n * g.elem_stride;
             s[(bitrev(n, g.log2L) << g.log2C) + c] = vec[pos];
         }
     }
-    load_stage_twiddles(stw, g.log2L, tw, log2T);
+    load_stage_twiddles<NT>(stw, g.log2L, tw, log2T);
     __syncthreads();
-    lds_stages<RingM>(s, g.log2L, g.log2C, R, stw);
-    for (int idx = threadIdx.x; idx < total; idx += kThreads) {
+    lds_stages<NT, RingM>(s, g.log2L, g.log2C, R, stw);
+    for (int idx = threadIdx.x; idx < total; idx += NT) {
         const int n = idx >> g.log2C, c = idx & (C - 1);
         const int64_t pos = base + (int64_t)c * g.col_stride + (int64_t)n * g.elem_stride;
         uint32_t val = s[(n << g.log2C) + c];
@@ -208,32 +219,46 @@ __global__ __launch_bounds__(kThreads) void k_ntt(ModSrc src, uint32_t *buf, Pas
     }
 }
 
+// Two-pass lengths: tiles of N2 = 2^S elements, columns of N1 = 2^(log2m - S) <= N2.
 PassGeom column_pass(int log2m, bool twiddle)
 {
+    const int S = split_bits(log2m);
     PassGeom g{};
     g.log2m = log2m;
-    g.log2L = log2m - 12;
-    g.log2C = 12 - g.log2L;
-    g.elem_stride = kTile;
+    g.log2L = log2m - S;
+    g.log2C = S - g.log2L;
+    g.elem_stride = (int64_t)1 << S;
     g.col_stride = 1;
     g.block_stride = (int64_t)1 << g.log2C;
-    g.blocks = kTile >> g.log2C;
+    g.blocks = (1 << S) >> g.log2C;
     g.twiddle = twiddle;
     return g;
 }
 
 PassGeom row_pass(int log2m, bool twiddle)
 {
+    const int S = split_bits(log2m);
     PassGeom g{};
     g.log2m = log2m;
-    g.log2L = 12;
+    g.log2L = S;
     g.log2C = 0;
     g.elem_stride = 1;
     g.col_stride = 0;
-    g.block_stride = kTile;
-    g.blocks = 1 << (log2m - 12);
+    g.block_stride = (int64_t)1 << S;
+    g.blocks = 1 << (log2m - S);
     g.twiddle = twiddle;
     return g;
+}
+
+// Launch of one pass with the tile its geometry needs (single pass: the whole vector in
+// one 4096-element tile; two-pass lengths: 2^split_bits elements).
+template <class F>
+void with_tile(const PassGeom &g, bool single, F &&f)
+{
+    const int tile_bits = g.log2L + g.log2C;  // = split_bits(log2m) for both passes
+    if (single || tile_bits == 12) f(std::integral_constant<int, kSingleTile>{});
+    else if (tile_bits == 10) f(std::integral_constant<int, 1024>{});
+    else f(std::integral_constant<int, 2048>{});
 }
 
 PassGeom single_pass(int log2m)
@@ -256,20 +281,35 @@ cs_status fft_f64_forward(const int64_t *const *re, const int64_t *const *im, in
     if (n_vec == 0) return CS_OK;
     F64Src first{re, im};
     F64Src self{nullptr, nullptr};
+    auto pass = [&](const PassGeom &g, bool single, const F64Src &src) {
+        with_tile(g, single, [&](auto tile) {
+            constexpr int T = decltype(tile)::value;
+            hipLaunchKernelGGL(k_fft_f64<T>, dim3(n_vec, g.blocks), dim3(T / 4), 0, s, src, buf, g, tw, log2T);
+        });
+        return hipGetLastError();
+    };
     if (log2m <= 12) {
-        PassGeom g = single_pass(log2m);
-        hipLaunchKernelGGL(k_fft_f64, dim3(n_vec, g.blocks), dim3(kThreads), 0, s, first, buf, g, tw, log2T);
-        CSK_HIP(hipGetLastError());
+        CSK_HIP(pass(single_pass(log2m), true, first));
         return CS_OK;
     }
-    PassGeom g1 = column_pass(log2m, true);
-    hipLaunchKernelGGL(k_fft_f64, dim3(n_vec, g1.blocks), dim3(kThreads), 0, s, first, buf, g1, tw, log2T);
-    CSK_HIP(hipGetLastError());
-    PassGeom g2 = row_pass(log2m, false);
-    hipLaunchKernelGGL(k_fft_f64, dim3(n_vec, g2.blocks), dim3(kThreads), 0, s, self, buf, g2, tw, log2T);
-    CSK_HIP(hipGetLastError());
+    CSK_HIP(pass(column_pass(log2m, true), false, first));
+    CSK_HIP(pass(row_pass(log2m, false), false, self));
     return CS_OK;
 }
+
+namespace {
+hipError_t ntt_pass(const PassGeom &g, bool single, const ModSrc &src, int n_vec, uint32_t *buf, int vec_per_prime,
+                    const PrimeDev *primes, const uint32_t *roots, int log2T, int inverse, const int32_t *rep_of,
+                    const int32_t *kp, hipStream_t s)
+{
+    with_tile(g, single, [&](auto tile) {
+        constexpr int T = decltype(tile)::value;
+        hipLaunchKernelGGL(k_ntt<T>, dim3(n_vec, g.blocks), dim3(T / 4), 0, s, src, buf, g, vec_per_prime, primes,
+                           roots, log2T, inverse, rep_of, kp);
+    });
+    return hipGetLastError();
+}
+}  // namespace
 
 cs_status ntt_forward(const int64_t *const *ptrs, int vec_per_prime, int n_primes, uint32_t *buf, int log2m,
                       const PrimeDev *primes, const uint32_t *roots, int log2T, hipStream_t s,
@@ -279,21 +319,16 @@ cs_status ntt_forward(const int64_t *const *ptrs, int vec_per_prime, int n_prime
     if (n_vec == 0) return CS_OK;
     ModSrc first{ptrs};
     ModSrc self{nullptr};
+    const ModSrc &in = ptrs ? first : self;
     if (log2m <= 12) {
-        PassGeom g = single_pass(log2m);
-        hipLaunchKernelGGL(k_ntt, dim3(n_vec, g.blocks), dim3(kThreads), 0, s, ptrs ? first : self, buf, g,
-                           vec_per_prime, primes, roots, log2T, 0, rep_of, kp);
-        CSK_HIP(hipGetLastError());
+        CSK_HIP(ntt_pass(single_pass(log2m), true, in, n_vec, buf, vec_per_prime, primes, roots, log2T, 0, rep_of,
+                         kp, s));
         return CS_OK;
     }
-    PassGeom g1 = column_pass(log2m, true);
-    hipLaunchKernelGGL(k_ntt, dim3(n_vec, g1.blocks), dim3(kThreads), 0, s, ptrs ? first : self, buf, g1,
-                       vec_per_prime, primes, roots, log2T, 0, rep_of, kp);
-    CSK_HIP(hipGetLastError());
-    PassGeom g2 = row_pass(log2m, false);
-    hipLaunchKernelGGL(k_ntt, dim3(n_vec, g2.blocks), dim3(kThreads), 0, s, self, buf, g2, vec_per_prime,
-                       primes, roots, log2T, 0, rep_of, kp);
-    CSK_HIP(hipGetLastError());
+    CSK_HIP(ntt_pass(column_pass(log2m, true), false, in, n_vec, buf, vec_per_prime, primes, roots, log2T, 0, rep_of,
+                     kp, s));
+    CSK_HIP(ntt_pass(row_pass(log2m, false), false, self, n_vec, buf, vec_per_prime, primes, roots, log2T, 0, rep_of,
+                     kp, s));
     return CS_OK;
 }
 
@@ -306,20 +341,14 @@ cs_status ntt_inverse(int vec_per_prime, int n_primes, uint32_t *buf, int log2m,
     if (log2m <= 12) {
         PassGeom g = single_pass(log2m);
         g.scale = 1;
-        hipLaunchKernelGGL(k_ntt, dim3(n_vec, g.blocks), dim3(kThreads), 0, s, self, buf, g, vec_per_prime,
-                           primes, roots, log2T, 1, nullptr, nullptr);
-        CSK_HIP(hipGetLastError());
+        CSK_HIP(ntt_pass(g, true, self, n_vec, buf, vec_per_prime, primes, roots, log2T, 1, nullptr, nullptr, s));
         return CS_OK;
     }
-    PassGeom g1 = row_pass(log2m, true);
-    hipLaunchKernelGGL(k_ntt, dim3(n_vec, g1.blocks), dim3(kThreads), 0, s, self, buf, g1, vec_per_prime,
-                       primes, roots, log2T, 1, nullptr, nullptr);
-    CSK_HIP(hipGetLastError());
+    CSK_HIP(ntt_pass(row_pass(log2m, true), false, self, n_vec, buf, vec_per_prime, primes, roots, log2T, 1, nullptr,
+                     nullptr, s));
     PassGeom g2 = column_pass(log2m, false);
     g2.scale = 1;
-    hipLaunchKernelGGL(k_ntt, dim3(n_vec, g2.blocks), dim3(kThreads), 0, s, self, buf, g2, vec_per_prime,
-                       primes, roots, log2T, 1, nullptr, nullptr);
-    CSK_HIP(hipGetLastError());
+    CSK_HIP(ntt_pass(g2, false, self, n_vec, buf, vec_per_prime, primes, roots, log2T, 1, nullptr, nullptr, s));
     return CS_OK;
 }
 
