@@ -515,15 +515,18 @@ struct FinalizeArgs {
     int32_t kcap;   // stage 2 finishes repetitions needing at most kcap primes
 };
 
-constexpr int kFinThreads = 256;
+// A finalize block per query: 1024 threads (16 wavefronts, so each reduces one or two
+// partial sets and the chains of dependent loads are short) when the queries fit one
+// round of blocks, 256 for large batches.
+constexpr int kFinThreadsFew = 1024, kFinThreadsMany = 256;
 constexpr int kStage = kMaxD * 3 * kMaxRel;  // doubles of per-repetition bound terms
 constexpr int kSpecPrimes = 5;                       // speculative modular step: primes (155 bits)
 constexpr size_t kSpecBudget = (size_t)1 << 30;      // and its largest workspace
 
 // STAGE 1: fp64 / dot / norms pass; 2: residues of the modular pass; 3: both in one
 // launch (the speculative residues were computed beside the fp64 pass).
-template <int STAGE>
-__global__ __launch_bounds__(kFinThreads) void k_finalize(FinalizeArgs a)
+template <int STAGE, int NT>
+__global__ __launch_bounds__(NT) void k_finalize(FinalizeArgs a)
 {
     __shared__ double s_val[kMaxD];
     __shared__ int64_t s_lo[kMaxD], s_hi[kMaxD];
@@ -540,7 +543,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(FinalizeArgs a)
     const double m = (double)Q.m;
     const int plan = Q.plan;
     const int wv = t >> 6, lane = t & 63;
-    constexpr int kWaves = kFinThreads / 64;
+    constexpr int kWaves = NT / 64;
     if (STAGE != 2 && plan != CS_PLAN_DOT) {
         // The nb <= 64 block partials of each owner (a sketch for the norms, a repetition
         // for the spectral sums) are reduced by one wavefront: lane b loads partial b and
@@ -1433,12 +1436,14 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
         // both finalize stages in one launch
         fa.stage = 3;
         fa.kcap = ks;
-        hipLaunchKernelGGL(k_finalize<3>, dim3(nq), dim3(kFinThreads), 0, s, fa);
+        if (nq <= 256) hipLaunchKernelGGL((k_finalize<3, kFinThreadsFew>), dim3(nq), dim3(kFinThreadsFew), 0, s, fa);
+        else hipLaunchKernelGGL((k_finalize<3, kFinThreadsMany>), dim3(nq), dim3(kFinThreadsMany), 0, s, fa);
         CSK_HIP(hipGetLastError());
         kdone = ks;
     } else {
         fa.stage = 1;
-        hipLaunchKernelGGL(k_finalize<1>, dim3(nq), dim3(kFinThreads), 0, s, fa);
+        if (nq <= 256) hipLaunchKernelGGL((k_finalize<1, kFinThreadsFew>), dim3(nq), dim3(kFinThreadsFew), 0, s, fa);
+        else hipLaunchKernelGGL((k_finalize<1, kFinThreadsMany>), dim3(nq), dim3(kFinThreadsMany), 0, s, fa);
         CSK_HIP(hipGetLastError());
     }
     if (async_out) {
@@ -1636,7 +1641,8 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
         }
         fa.stage = 2;
         fa.kcap = kMaxPrimes;
-        hipLaunchKernelGGL(k_finalize<2>, dim3(nq), dim3(kFinThreads), 0, s, fa);
+        if (nq <= 256) hipLaunchKernelGGL((k_finalize<2, kFinThreadsFew>), dim3(nq), dim3(kFinThreadsFew), 0, s, fa);
+        else hipLaunchKernelGGL((k_finalize<2, kFinThreadsMany>), dim3(nq), dim3(kFinThreadsMany), 0, s, fa);
         CSK_HIP(hipGetLastError());
         CSK_HIP(hipMemcpyAsync(ho, d_outs, nq * sizeof(OutDev), hipMemcpyDeviceToHost, s));
         if (reps_out) CSK_HIP(hipMemcpyAsync(hr, d_rs, n_rep * sizeof(RepDev), hipMemcpyDeviceToHost, s));
