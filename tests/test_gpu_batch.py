@@ -69,6 +69,10 @@ def test_batched_update_equals_plain(weights_kind):
                               n_range=(50, 60_000))
     specs.append(W.QuerySpec(W.fig3_query(), 512, 5, (3000, 4000, 100, 2000), 99))
     specs.append(W.QuerySpec(W.single_join(), 1 << 16, 9, (200_000, 150_000), 98))
+    # LDS segment tasks off the one-join fast hash: an attribute in two joins, and m not
+    # a power of two
+    specs.append(W.QuerySpec(W.fig3_query(), 512, 5, (40_001, 30_002, 20_003, 50_000), 95))
+    specs.append(W.QuerySpec(W.chain(3), 1000, 5, (50_001, 60_002, 40_003), 94))
     _say("batch", weights_kind, len(specs), "queries")
     data = _make_inputs(specs, weights_kind=weights_kind)
     unit = weights_kind == "pm1"
@@ -84,7 +88,7 @@ def test_batched_update_equals_plain(weights_kind):
         for k in range(sp.graph.n_rel):
             assert np.array_equal(a.read_sketch(k), p.read_sketch(k)), (qi, k)
     # a few queries against the oracle directly
-    for qi in (0, len(specs) - 2, len(specs) - 1):
+    for qi in (0, len(specs) - 4, len(specs) - 3, len(specs) - 2, len(specs) - 1):
         sp = specs[qi]
         rels = [r[0] for r in data[qi]]
         ws = None if weights_kind is None else [r[1] for r in data[qi]]
