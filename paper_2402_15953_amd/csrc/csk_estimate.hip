@@ -1104,6 +1104,10 @@ int nblocks_for(uint32_t m)
     return (int)nb;
 }
 
+// Workspace growth by at least half the current size, so that batches of varying size
+// (the serving loop's) reallocate a logarithmic number of times.
+size_t grown(size_t have, size_t need) { return std::max(need, have + have / 2); }
+
 struct Carve {
     size_t off = 0;
     size_t take(size_t bytes)
@@ -1269,10 +1273,11 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
             CSK_HIP(hipStreamSynchronize(s));
             hipFree(ws.buf);
         }
+        const size_t want = grown(ws.bytes, c.off);
         ws.buf = nullptr;
         ws.bytes = 0;
-        if (hipMalloc(&ws.buf, c.off) != hipSuccess) return fail(CS_ENOMEM, "estimate workspace");
-        ws.bytes = c.off;
+        if (hipMalloc(&ws.buf, want) != hipSuccess) return fail(CS_ENOMEM, "estimate workspace");
+        ws.bytes = want;
     }
     char *wb = static_cast<char *>(ws.buf);
     // pinned host staging: [tables | repetition records | outputs | modular-step tables]
@@ -1289,12 +1294,13 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
         ws.upload_pending = false;
     }
     if (ws.host_bytes < hc.off) {
+        const size_t want = grown(ws.host_bytes, hc.off);
         if (ws.host) hipHostFree(ws.host);
         ws.host = nullptr;
         ws.host_bytes = 0;
-        if (hipHostMalloc(&ws.host, hc.off, hipHostMallocDefault) != hipSuccess)
+        if (hipHostMalloc(&ws.host, want, hipHostMallocDefault) != hipSuccess)
             return fail(CS_ENOMEM, "estimate host staging");
-        ws.host_bytes = hc.off;
+        ws.host_bytes = want;
     }
     char *hb = static_cast<char *>(ws.host);
     RepDev *hr = reinterpret_cast<RepDev *>(hb + h_rs);
@@ -1389,11 +1395,12 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
         if (spec_bytes <= kSpecBudget) {
             if (ws.mod_bytes < spec_bytes) {
                 CSK_HIP(hipStreamSynchronize(s));
+                const size_t want = grown(ws.mod_bytes, spec_bytes);
                 if (ws.mod) hipFree(ws.mod);
                 ws.mod = nullptr;
                 ws.mod_bytes = 0;
-                if (hipMalloc(&ws.mod, spec_bytes) != hipSuccess) return fail(CS_ENOMEM, "modular workspace");
-                ws.mod_bytes = spec_bytes;
+                if (hipMalloc(&ws.mod, want) != hipSuccess) return fail(CS_ENOMEM, "modular workspace");
+                ws.mod_bytes = want;
             }
             spec = true;
             char *mod_cur = static_cast<char *>(ws.mod);
@@ -1495,11 +1502,13 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
                                          sizeof(uint32_t));
         }
         if (ws.mod_bytes < mod_need) {
+            const size_t want = grown(ws.mod_bytes, mod_need);
+            CSK_HIP(hipStreamSynchronize(s));
             if (ws.mod) hipFree(ws.mod);
             ws.mod = nullptr;
             ws.mod_bytes = 0;
-            if (hipMalloc(&ws.mod, mod_need) != hipSuccess) return fail(CS_ENOMEM, "modular workspace");
-            ws.mod_bytes = mod_need;
+            if (hipMalloc(&ws.mod, want) != hipSuccess) return fail(CS_ENOMEM, "modular workspace");
+            ws.mod_bytes = want;
         }
         char *mod_cur = static_cast<char *>(ws.mod);
         char *mod_host = hb + h_mod;
