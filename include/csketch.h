@@ -286,8 +286,9 @@ cs_status cs_estimate(cs_sketch *h, void *stream, cs_estimate_t *out, const cs_r
  * asynchronous estimate on this handle needed, at most 5 = about 155 bits of window;
  * 5 on the first call) keeps its fp64 value, and out->exact is then 0.  Stream-ordered
  * with the handle's updates and estimates; calls on other streams must not overlap it.
- * Errors (returned at once): CS_EINVAL for queries with the general plan (their
- * estimate needs host round trips). */
+ * Errors (returned at once, nothing enqueued): CS_EINVAL for queries with the general
+ * plan (their estimate needs host round trips) and for an `out` that is not device
+ * memory of the handle's device or pinned / managed host memory. */
 cs_status cs_estimate_async(cs_sketch *h, void *stream, cs_estimate_t *out);
 
 /* ------------------------------------------------------------------ batched mode */

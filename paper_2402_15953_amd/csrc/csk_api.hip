@@ -436,6 +436,17 @@ cs_status cs_estimate(cs_sketch *hs, void *stream, cs_estimate_t *out, const cs_
 cs_status cs_estimate_async(cs_sketch *hs, void *stream, cs_estimate_t *out)
 {
     if (!hs || !out) return fail(CS_EINVAL, "null argument");
+    // the result is written by a kernel: refuse memory the device cannot reach (pageable
+    // host memory would fault the GPU) before anything is enqueued
+    hipPointerAttribute_t attr{};
+    if (hipPointerGetAttributes(&attr, out) != hipSuccess) {
+        (void)hipGetLastError();  // clear the lookup's error for the caller's next call
+        return fail(CS_EINVAL, "estimate destination is neither device nor pinned host memory");
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeHost && attr.type != hipMemoryTypeManaged)
+        return fail(CS_EINVAL, "estimate destination is neither device nor pinned host memory");
+    if (attr.type == hipMemoryTypeDevice && attr.device != hs->h.device)
+        return fail(CS_EINVAL, "estimate destination on another device");
     return estimate_run_async(hs->h, static_cast<hipStream_t>(stream), out);
 }
 

@@ -124,3 +124,20 @@ def test_async_refuses_general_plan():
     assert not dev.cpu().any()
     assert sk.estimate()["exact"]
     sk.close()
+
+
+def test_async_refuses_pageable_destination():
+    """A destination the device cannot write (pageable host memory) is refused before
+    anything is enqueued; the handle keeps working."""
+    graph = W.chain(3)
+    sk = csk.Sketch(graph, 1 << 12, 3, 2)
+    page = np.zeros(csk.ESTIMATE_BYTES, dtype=np.uint8)
+    with pytest.raises(csk.CsError) as e:
+        sk.estimate_async(page.ctypes.data)
+    assert e.value.status == csk.CS_EINVAL
+    assert not page.any()
+    host = _pinned()
+    sk.estimate_async(host.data_ptr())
+    torch.cuda.synchronize()
+    assert csk.read_estimate(host)["exact"]
+    sk.close()
