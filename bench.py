@@ -122,6 +122,11 @@ def horner_steps_per_tuple(graph, k, d):
     return d * steps
 
 
+def progress(msg: str):
+    """One line per finished section on stderr (the JSON line stays alone on stdout)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -245,6 +250,7 @@ def main():
     hbm_achieved = bytes_dom / dur_s / 1e9
     traffic = measured_traffic(args.strategy)
 
+    progress("plain step timed")
     out = {
         "metric": METRIC,
         "value": value,
@@ -279,16 +285,21 @@ def main():
 
     if args.filtered:
         out["filtered"] = bench_filtered(sk, keys, graph, dev, stream, args.steps)
+        progress("filtered section done")
     sk.close()
     if args.anym:
         out["any_m"] = [bench_any_m(int(x), keys, graph, dev, stream, args.steps) for x in args.anym.split(",") if x]
+        progress("any-m section done")
     if args.ams:
         out["ams_baseline"] = bench_ams(keys, graph, stream)
+        progress("AMS section done")
     out["attr_sketches"] = bench_attr(keys, graph, stream, args.steps)
+    progress("attribute-sketch section done")
     del keys
     torch.cuda.empty_cache()
     if args.batch_queries > 0:
         out["batched"] = bench_batched(args.batch_queries, dev, stream)
+        progress("batched section done")
         torch.cuda.empty_cache()
     if args.serve_queries > 0:
         out["serving"] = bench_serving(args.serve_queries, dev, args.serve_seconds,
@@ -298,6 +309,7 @@ def main():
         keys_cpu = [W.relation_keys(graph, k, args.cpu_tuples, "zipf", config=config, s=s, D=D).to(torch.int32)
                     for k in range(graph.n_rel)]
         out["cpu_baseline"] = cpu_baseline(graph, keys_cpu, m, d, seed, args.cpu_tuples)
+        progress("CPU baseline done")
 
     print(json.dumps(out), flush=True)
 
@@ -566,12 +578,15 @@ def bench_serving(n_queries, dev, seconds, rates):
     levels = []
     rng = random.Random(9)
     inserted = {}
-    for rate in rates:
-        # warm-up burst, then the timed window
+    # an unrecorded first window at the lowest rate (1 s) takes the one-time costs that
+    # real-sized sketches bring (first modular estimates, workspace growth) out of the
+    # measured levels
+    for li, rate in enumerate([rates[0]] + list(rates)):
+        window = 1.0 if li == 0 else seconds
         plan = []
         t = 0.0
         total_rate = rate * 1.25          # update batches + estimates (1:4)
-        while t < seconds:
+        while t < window:
             t += rng.expovariate(total_rate)
             q = rng.randrange(n_queries)
             if rng.random() < 0.2:
@@ -614,6 +629,9 @@ def bench_serving(n_queries, dev, seconds, rates):
         def pct(a, p):
             return float(np.percentile(a, p)) if len(a) else None
 
+        progress("serving window at %g batches/s done%s" % (rate, " (warm-up)" if li == 0 else ""))
+        if li == 0:
+            continue
         levels.append({"offered_update_batches_per_s": rate, "offered_estimates_per_s": rate / 4,
                        "seconds": wall, "tuples_per_s": tuples / wall, "estimates_per_s": n_e / wall,
                        "update_p50_ms": pct(lat_u, 50), "update_p99_ms": pct(lat_u, 99),

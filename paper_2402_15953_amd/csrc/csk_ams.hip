@@ -284,6 +284,11 @@ cs_status cs_ams_update(cs_ams *hs, int32_t rel, const uint32_t *keys, const int
     if (rel < 0 || rel >= h.g.n_rel) return fail(CS_EINVAL, "relation out of range");
     if (n == 0) return CS_OK;
     if (!keys) return fail(CS_EINVAL, "null keys");
+    {
+        cs_status chk = check_device_array(keys, n * h.g.omega[rel].size() * sizeof(uint32_t), h.device, "keys");
+        if (chk == CS_OK && weights) chk = check_device_array(weights, n * sizeof(int64_t), h.device, "weights");
+        if (chk != CS_OK) return chk;
+    }
     const int n_cols = (int)h.g.omega[rel].size();
     JoinCols jc{};
     for (int q = 0; q < h.joins[rel]; ++q) jc.col[q] = h.join_col[rel][q];

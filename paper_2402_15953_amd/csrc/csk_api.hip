@@ -44,6 +44,26 @@ cs_status fail(cs_status st, const std::string &msg)
     return st;
 }
 
+cs_status check_device_array(const void *p, size_t bytes, int device, const char *what)
+{
+    if (bytes == 0) return CS_OK;
+    if (!p) return fail(CS_EINVAL, std::string("null ") + what);
+    const char *c = static_cast<const char *>(p);
+    for (const char *q : {c, c + bytes - 1}) {
+        hipPointerAttribute_t attr{};
+        if (hipPointerGetAttributes(&attr, q) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CS_EINVAL, std::string(what) + " is not device or pinned host memory");
+        }
+        if (attr.type == hipMemoryTypeDevice) {
+            if (attr.device != device) return fail(CS_EINVAL, std::string(what) + " is on another device");
+        } else if (attr.type != hipMemoryTypeHost && attr.type != hipMemoryTypeManaged) {
+            return fail(CS_EINVAL, std::string(what) + " is not device or pinned host memory");
+        }
+    }
+    return CS_OK;
+}
+
 // Graph analysis (Sec. 2.6, Table 1): Omega, Gamma, Psi; validity; estimate plan.
 cs_status analyze_graph(const cs_graph *g, GraphPlan *out)
 {
@@ -364,6 +384,9 @@ cs_status cs_update_timed(cs_sketch *hs, int32_t rel, const uint32_t *keys, cons
     if (n == 0) return CS_OK;
     if (!keys) return fail(CS_EINVAL, "null keys");
     if (strategy < CS_UPDATE_AUTO || strategy > CS_UPDATE_PARTITION) return fail(CS_EINVAL, "bad strategy");
+    cs_status chk = check_device_array(keys, n * h.g.rel[rel].n_cols * sizeof(uint32_t), h.device, "keys");
+    if (chk == CS_OK && weights) chk = check_device_array(weights, n * sizeof(int64_t), h.device, "weights");
+    if (chk != CS_OK) return chk;
     UpdateArgs a;
     a.keys = keys;
     a.weights = weights;
@@ -397,6 +420,13 @@ cs_status cs_update_filtered(cs_sketch *hs, int32_t rel, const uint32_t *keys, c
     if (n_preds < 0 || n_preds > CS_MAX_PREDICATES) return fail(CS_EINVAL, "too many predicates");
     if (n_preds > 0 && (!preds || !attrs || n_attrs <= 0 || n_attrs > CS_MAX_PREDICATES))
         return fail(CS_EINVAL, "predicates need attribute columns");
+    {
+        cs_status chk = check_device_array(keys, n * h.g.rel[rel].n_cols * sizeof(uint32_t), h.device, "keys");
+        if (chk == CS_OK && weights) chk = check_device_array(weights, n * sizeof(int64_t), h.device, "weights");
+        if (chk == CS_OK && n_preds > 0)
+            chk = check_device_array(attrs, n * (size_t)n_attrs * sizeof(uint32_t), h.device, "attribute columns");
+        if (chk != CS_OK) return chk;
+    }
     FilterSpec f{};
     f.n = n_preds;
     for (int i = 0; i < n_preds; ++i) {

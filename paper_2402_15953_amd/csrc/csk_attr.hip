@@ -212,6 +212,11 @@ cs_status cs_attr_update(cs_attr *hs, int32_t rel, const uint32_t *keys, const i
     if (rel < 0 || rel >= h.g.n_rel) return fail(CS_EINVAL, "relation out of range");
     if (n == 0) return CS_OK;
     if (!keys) return fail(CS_EINVAL, "null keys");
+    {
+        cs_status chk = check_device_array(keys, n * h.g.omega[rel].size() * sizeof(uint32_t), h.device, "keys");
+        if (chk == CS_OK && weights) chk = check_device_array(weights, n * sizeof(int64_t), h.device, "weights");
+        if (chk != CS_OK) return chk;
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     const std::vector<int32_t> &cols = h.g.omega[rel];
     const int a = (int)cols.size();

@@ -421,6 +421,12 @@ cs_status plan_batch(BatchState &B, const cs_update_item *items, int32_t n_items
         if (B.device < 0) B.device = h.device;
         if (h.device != B.device) return fail(CS_EINVAL, "batch items on different devices");
         const RelPlan &rp = h.g.rel[it.rel];
+        {
+            cs_status chk = check_device_array(it.keys, it.n * rp.n_cols * sizeof(uint32_t), h.device, "batch keys");
+            if (chk == CS_OK && it.weights)
+                chk = check_device_array(it.weights, it.n * sizeof(int64_t), h.device, "batch weights");
+            if (chk != CS_OK) return chk;
+        }
         BItem I{};
         I.keys = it.keys;
         I.weights = it.weights;

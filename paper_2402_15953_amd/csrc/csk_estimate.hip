@@ -1009,9 +1009,40 @@ const double *twiddles_f64(int device, int log2m, hipStream_t s, cs_status *st)
     const size_t m = (size_t)1 << log2m;
     std::vector<double2> h(m);
     const long double two_pi = 6.283185307179586476925286766559005768L;
+    // w^k = (cos, -sin)(2 pi k / m): the long-double cosine and sine are evaluated on the
+    // first octant only and the rest follows by the exact symmetries
+    // (c, s)(pi/2 - x) = (s, c), (c, s)(pi/2 + x) = (-s, c), (c, s)(pi + x) = (-c, -s)
+    auto cs = [&](size_t k) -> std::pair<double, double> {  // (cos, sin)(2 pi k / m), k <= m / 8
+        const long double a = two_pi * (long double)k / (long double)m;
+        return {(double)cosl(a), (double)sinl(a)};
+    };
+    auto trig = [&](size_t k) -> std::pair<double, double> {
+        if (m < 8) return cs(k);
+        const size_t q = m / 4, o = m / 8;
+        bool neg = false;
+        if (k >= 2 * q) {  // pi + x
+            k -= 2 * q;
+            neg = true;
+        }
+        std::pair<double, double> v;
+        if (k <= o) {
+            v = cs(k);
+        } else if (k <= q) {  // pi/2 - x, x = 2 pi (q - k) / m
+            const auto t = cs(q - k);
+            v = {t.second, t.first};
+        } else if (k <= q + o) {  // pi/2 + x, x = 2 pi (k - q) / m
+            const auto t = cs(k - q);
+            v = {-t.second, t.first};
+        } else {  // pi - x, x = 2 pi (2q - k) / m: (c, s)(pi - x) = (-c, s)
+            const auto t = cs(2 * q - k);
+            v = {-t.first, t.second};
+        }
+        if (neg) v = {-v.first, -v.second};
+        return v;
+    };
     for (size_t k = 0; k < m; ++k) {
-        const long double ang = -two_pi * (long double)k / (long double)m;
-        h[k] = make_double2((double)cosl(ang), (double)sinl(ang));
+        const auto v = trig(k);
+        h[k] = make_double2(v.first, -v.second);
     }
     double2 *dp = nullptr;
     if (hipMalloc(&dp, m * sizeof(double2)) != hipSuccess) {
@@ -1044,14 +1075,16 @@ const uint32_t *roots_mod(int device, int log2m, int /*prime*/, bool /*inverse*/
         const uint64_t p = P[i].p;
         const uint64_t w = powmod(P[i].g, (p - 1) >> log2m, p);
         const uint64_t wi = powmod(w, p - 2, p);
+        // p < 2^31: products of two residues fit 64 bits; the table holds the Montgomery
+        // forms w^k 2^32 mod p, stepped directly
         const uint64_t R = (1ull << 32) % p;
         for (int dir = 0; dir < 2; ++dir) {
-            uint64_t acc = 1;
+            uint64_t acc = R;  // Montgomery form of w^0
             const uint64_t step = dir ? wi : w;
             uint32_t *dst = h.data() + ((size_t)(2 * i + dir) << log2m);
             for (size_t k = 0; k < m; ++k) {
-                dst[k] = (uint32_t)((unsigned __int128)acc * R % p);
-                acc = (unsigned __int128)acc * step % p;
+                dst[k] = (uint32_t)acc;
+                acc = acc * step % p;
             }
         }
     }

@@ -47,6 +47,12 @@ struct SplitMix64 {
 
 void set_error(const std::string &msg);
 cs_status fail(cs_status st, const std::string &msg);
+// CS_OK when the bytes [p, p + bytes) start and end in memory the given device's kernels
+// can read (its own device memory, or pinned / managed host memory); otherwise
+// CS_EINVAL naming `what`.  A null p with bytes == 0 passes.  Kernels reading pageable
+// host memory would fault the GPU, so every entry point that hands caller arrays to a
+// kernel checks them first.
+cs_status check_device_array(const void *p, size_t bytes, int device, const char *what);
 #define CSK_HIP(call)                                                                  \
     do {                                                                               \
         hipError_t _e = (call);                                                        \

@@ -410,7 +410,16 @@ cs_status cs_server_sketch(cs_server *S, int32_t qid, cs_sketch **out)
 static cs_status submit(cs_server *S, Request r, uint64_t *ticket)
 {
     std::lock_guard<std::mutex> lk(S->mu);
-    if (S->queries.find(r.qid) == S->queries.end()) return fail(CS_EINVAL, "unknown query");
+    auto qit = S->queries.find(r.qid);
+    if (qit == S->queries.end()) return fail(CS_EINVAL, "unknown query");
+    if (r.kind == 0 && r.n > 0 && !qit->second.removed) {
+        const Handle &h = qit->second.sk->h;
+        if (r.rel < 0 || r.rel >= h.g.n_rel) return fail(CS_EINVAL, "relation out of range");
+        cs_status chk = check_device_array(r.keys, r.n * h.g.rel[r.rel].n_cols * sizeof(uint32_t), h.device, "keys");
+        if (chk == CS_OK && r.weights)
+            chk = check_device_array(r.weights, r.n * sizeof(int64_t), h.device, "weights");
+        if (chk != CS_OK) return chk;
+    }
     if (S->cfg.max_pending > 0 && (int64_t)(S->submitted - S->completed) >= S->cfg.max_pending)
         return fail(CS_EBUSY, "request queue full");
     r.ticket = S->next_ticket++;
