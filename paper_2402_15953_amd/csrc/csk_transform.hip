@@ -166,13 +166,12 @@ struct ModSrc {
     const int64_t *const *ptr;  // [vec_per_prime] sketch of vector v % vec_per_prime (null: in place)
 };
 
-template <int TILE>
-__global__ __launch_bounds__(TILE / 4) void k_ntt(ModSrc src, uint32_t *buf, PassGeom g, int vec_per_prime,
-                                                 const PrimeDev *__restrict__ primes,
-                                                 const uint32_t *__restrict__ roots, int log2T, int inverse,
-                                                 const int32_t *__restrict__ rep_of, const int32_t *__restrict__ kp)
+template <int TILE, int NT>
+__global__ __launch_bounds__(NT) void k_ntt(ModSrc src, uint32_t *buf, PassGeom g, int vec_per_prime,
+                                           const PrimeDev *__restrict__ primes,
+                                           const uint32_t *__restrict__ roots, int log2T, int inverse,
+                                           const int32_t *__restrict__ rep_of, const int32_t *__restrict__ kp)
 {
-    constexpr int NT = TILE / 4;
     __shared__ uint32_t s[TILE];
     __shared__ uint32_t stw[TILE / 2];
     const int v = blockIdx.x;
@@ -298,15 +297,38 @@ cs_status fft_f64_forward(const int64_t *const *re, const int64_t *const *im, in
 }
 
 namespace {
+// The column pass of the NTT reads its columns in runs of C 4-byte residues; with the
+// split shared with the fp64 FFT (runs of >= 8 complex doubles = 128 bytes) C can be as
+// low as 8 (32 bytes), so NTT column passes take at least 32 columns per block (tiles up
+// to 16384 residues, 64 KB of LDS, 1024 threads).  The decomposition, and with it the
+// output order, is unchanged.
+PassGeom widen_columns(PassGeom g)
+{
+    while (g.log2C < 5 && g.blocks > 1) {
+        ++g.log2C;
+        g.block_stride <<= 1;
+        g.blocks >>= 1;
+    }
+    return g;
+}
+
 hipError_t ntt_pass(const PassGeom &g, bool single, const ModSrc &src, int n_vec, uint32_t *buf, int vec_per_prime,
                     const PrimeDev *primes, const uint32_t *roots, int log2T, int inverse, const int32_t *rep_of,
                     const int32_t *kp, hipStream_t s)
 {
-    with_tile(g, single, [&](auto tile) {
+    auto go = [&](auto tile) {
         constexpr int T = decltype(tile)::value;
-        hipLaunchKernelGGL(k_ntt<T>, dim3(n_vec, g.blocks), dim3(T / 4), 0, s, src, buf, g, vec_per_prime, primes,
-                           roots, log2T, inverse, rep_of, kp);
-    });
+        constexpr int NT = T / 4 < 1024 ? T / 4 : 1024;
+        hipLaunchKernelGGL((k_ntt<T, NT>), dim3(n_vec, g.blocks), dim3(NT), 0, s, src, buf, g, vec_per_prime,
+                           primes, roots, log2T, inverse, rep_of, kp);
+    };
+    const int tile_bits = g.log2L + g.log2C;
+    if (single) go(std::integral_constant<int, kSingleTile>{});
+    else if (tile_bits <= 10) go(std::integral_constant<int, 1024>{});
+    else if (tile_bits == 11) go(std::integral_constant<int, 2048>{});
+    else if (tile_bits == 12) go(std::integral_constant<int, 4096>{});
+    else if (tile_bits == 13) go(std::integral_constant<int, 8192>{});
+    else go(std::integral_constant<int, 16384>{});
     return hipGetLastError();
 }
 }  // namespace
@@ -325,8 +347,8 @@ cs_status ntt_forward(const int64_t *const *ptrs, int vec_per_prime, int n_prime
                          kp, s));
         return CS_OK;
     }
-    CSK_HIP(ntt_pass(column_pass(log2m, true), false, in, n_vec, buf, vec_per_prime, primes, roots, log2T, 0, rep_of,
-                     kp, s));
+    CSK_HIP(ntt_pass(widen_columns(column_pass(log2m, true)), false, in, n_vec, buf, vec_per_prime, primes, roots,
+                     log2T, 0, rep_of, kp, s));
     CSK_HIP(ntt_pass(row_pass(log2m, false), false, self, n_vec, buf, vec_per_prime, primes, roots, log2T, 0, rep_of,
                      kp, s));
     return CS_OK;
@@ -346,7 +368,7 @@ cs_status ntt_inverse(int vec_per_prime, int n_primes, uint32_t *buf, int log2m,
     }
     CSK_HIP(ntt_pass(row_pass(log2m, true), false, self, n_vec, buf, vec_per_prime, primes, roots, log2T, 1, nullptr,
                      nullptr, s));
-    PassGeom g2 = column_pass(log2m, false);
+    PassGeom g2 = widen_columns(column_pass(log2m, false));
     g2.scale = 1;
     CSK_HIP(ntt_pass(g2, false, self, n_vec, buf, vec_per_prime, primes, roots, log2T, 1, nullptr, nullptr, s));
     return CS_OK;
