@@ -130,8 +130,8 @@ def progress(msg: str):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus %d is not supported" % args.gpus}))
-        print("bench.py runs on exactly one GPU (no multi-GPU path in this build)", file=sys.stderr)
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus %d is not supported" % args.gpus}))
+        print("bench.py runs on exactly one GPU (there is no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
     if args.copy_probe > 0:
         copy_probe(args.copy_probe)
