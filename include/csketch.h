@@ -96,8 +96,10 @@ typedef enum cs_update_strategy {
     CS_UPDATE_AUTO = 0,           /* the autotuner's choice when it has one for this class;
                                      else global atomics below 65536 tuple-repetitions,
                                      PARTITION beyond 2^16 buckets (weights NULL or +-1,
-                                     <= 2 columns), WAVE_AGGREGATE beyond 2^18 buckets
-                                     with general weights, LDS_PRIVATE otherwise */
+                                     <= 2 columns) except LDS_PRIVATE at m = 2^17 with
+                                     d <= 9 and every column in one join,
+                                     WAVE_AGGREGATE beyond 2^18 buckets with general
+                                     weights, LDS_PRIVATE otherwise */
     CS_UPDATE_GLOBAL_ATOMIC = 1,  /* one device-scope int64 atomic per tuple and repetition */
     CS_UPDATE_LDS_PRIVATE = 2,    /* the d x m counters cut into LDS-sized segments;
                                      each workgroup accumulates one segment for one chunk

@@ -165,6 +165,7 @@ cs_status filter_tuples(int device, const uint32_t *keys, int n_cols, const int6
                         const uint32_t **keys_out, const int64_t **weights_out, uint64_t *kept);
 // Tuned (strategy, grid, flags) for this update's class on `device`, if one was tuned.
 bool tune_lookup(const UpdateArgs &a, int device, int *strategy, int *grid, int *flags);
-int auto_update_strategy(uint32_t m, int32_t d, uint64_t n, int n_cols, bool unit, bool has_scratch);
+int auto_update_strategy(uint32_t m, int32_t d, uint64_t n, int n_cols, bool unit, bool has_scratch,
+                         bool e1_pow2);
 
 }  // namespace csk

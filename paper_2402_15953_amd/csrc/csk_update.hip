@@ -607,6 +607,122 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16q(const uint32_t *__r
     for (uint32_t e = threadIdx.x; e < m / 2; e += kSegBlock) out[e] = s_w[e];
 }
 
+// 16-bit counters beyond 2^16 buckets (m a power of two, one or two key columns, each in
+// one join, Deltas +-1): a workgroup owns a range of 2^16 buckets of one repetition.
+// Each wavefront hashes the bins of 64 tuples (the fast reduction, exact when flagged),
+// queues those whose bucket falls in the range (keys, offset in the range, sign of
+// Delta) in LDS and hashes their signs only once 64 are queued, so the sign work runs
+// at full SIMD width; every tuple's bin is hashed once per range of its repetition,
+// its sign once.  Each add's returned word is checked right away (one unchecked add per
+// thread).  Partial sums leave as biased 16-bit pairs, like k_update_seg16q's.
+template <int NC, bool HW>
+__global__ __launch_bounds__(kSegBlock) void k_update_seg16c(const uint32_t *__restrict__ keys,
+                                                             const int64_t *__restrict__ weights, uint64_t n,
+                                                             const uint64_t *__restrict__ coef, int32_t cpr,
+                                                             uint32_t m, uint64_t chunk, bool vec2,
+                                                             uint32_t *partial, unsigned long long *sketch,
+                                                             uint32_t canon_thresh)
+{
+    static_assert(NC == 1 || NC == 2, "one- and two-column relations");
+    constexpr uint32_t kRange = 1u << 16;
+    constexpr int kWavesPB = kSegBlock / 64;
+    __shared__ uint32_t s_w[kSeg16Words];
+    __shared__ uint32_t s_qx[kWavesPB][NC][kQCap];
+    __shared__ uint32_t s_ql[kWavesPB][kQCap];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t cells = (uint64_t)gridDim.y * kRange;  // d * m
+    const SegTile wg = seg_tile();
+    const uint64_t cell0 = (uint64_t)wg.seg * kRange;
+    const int t = (int)(cell0 / m);
+    const uint32_t off = (uint32_t)(cell0 - (uint64_t)t * m);  // first bucket of the range
+    for (uint32_t e = threadIdx.x; e < kSeg16Words; e += kSegBlock) s_w[e] = (kBias16 << 16) | kBias16;
+    __syncthreads();
+    CoefE1<NC> K;
+    K.load(coef + (size_t)t * cpr);
+    unsigned long long *srow = sketch + (uint64_t)t * m + off;
+    const uint64_t begin = (uint64_t)wg.chunk * chunk;
+    const uint64_t end = begin + chunk < n ? begin + chunk : n;
+    // bin and sign without the canonical reduction (CoefE1::bin_neg_fast split in two)
+    auto bin_fast = [&](const uint32_t (&x)[NC], uint32_t &flag) {
+        uint32_t j = 0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const HPair rb = hstep_p(hpair(K.b1[c]), x[c], K.b0[c]);
+            j += rb.lo + (rb.hi >> 29);
+            flag = max(flag, rb.hi | 0xE0000000u);
+        }
+        return j;
+    };
+    auto neg_fast = [&](const uint32_t (&x)[NC], uint32_t &flag) {
+        uint32_t neg = 0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const HPair rs = hstep_p(hstep_p(hstep_p(hpair(K.a[c][3]), x[c], K.a[c][2]), x[c], K.a[c][1]), x[c],
+                                     K.a[c][0]);
+            neg ^= rs.lo ^ (rs.hi >> 29);
+            flag = max(flag, rs.hi | 0xE0000000u);
+        }
+        return neg & 1u;
+    };
+    uint32_t head = 0, count = 0;  // wave-uniform queue state
+    auto drain = [&](uint32_t k) {  // lanes < k take one queued tuple each
+        if ((uint32_t)lane < k) {
+            const uint32_t slot = (head + lane) & (kQCap - 1);
+            uint32_t x[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) x[c] = s_qx[wave][c][slot];
+            const uint32_t l = s_ql[wave][slot];
+            uint32_t flag = 0;
+            uint32_t neg = neg_fast(x, flag);
+            if (flag >= canon_thresh) neg = K.neg(x);
+            neg ^= l >> 31;
+            const uint32_t j = l & (kRange - 1);
+            const uint32_t inc = inc16(neg, (j & 1u) << 4);
+            uint32_t *w = &s_w[j >> 1];
+            const uint32_t old = atomicAdd(w, inc);
+            if (out16(old, inc)) spill16(w, shift16(inc), srow + j);
+        }
+        head = (head + k) & (kQCap - 1);
+        count -= k;
+    };
+    for (uint64_t base = begin + (uint64_t)wave * 64; base < end; base += kSegBlock) {
+        const uint64_t i = base + lane;
+        bool in = false;
+        uint32_t x[NC], loc = 0;
+        if (i < end) {
+            load_keys<NC>(keys, i, vec2, x);
+            uint32_t flag = 0;
+            uint32_t j = bin_fast(x, flag);
+            if (flag >= canon_thresh) j = K.bin(x);
+            j = (j & (m - 1)) - off;
+            if (j < kRange) {
+                in = true;
+                loc = j | ((HW && weights[i] < 0) ? 0x80000000u : 0u);
+            }
+        }
+        const uint64_t mask = __ballot(in);
+        if (in) {
+            const uint32_t pos = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+            const uint32_t slot = (head + count + pos) & (kQCap - 1);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) s_qx[wave][c][slot] = x[c];
+            s_ql[wave][slot] = loc;
+        }
+        count += (uint32_t)__popcll(mask);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (count >= 64) drain(64);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (count > 0) drain(count);
+    __syncthreads();
+    uint32_t *out = partial + (size_t)wg.chunk * (cells >> 1) + (cell0 >> 1);
+    for (uint32_t e = threadIdx.x; e < kSeg16Words; e += kSegBlock) out[e] = s_w[e];
+}
+
 // sketch[2w + h] += sum over chunks of (half h of partial[chunk][w]) - 2^15
 __global__ void k_seg_reduce16(const uint32_t *__restrict__ partial, int32_t C, uint64_t words,
                                unsigned long long *sketch)
@@ -976,6 +1092,27 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
             hipLaunchKernelGGL(k_seg_reduce16, dim3((unsigned)std::min<uint64_t>((words + 255) / 256, 8192)),
                                dim3(256), 0, s, part, g16.chunks, words,
                                reinterpret_cast<unsigned long long *>(a.sketch));
+        } else if (narrow && e1 && a.m > (1u << 16) && NC <= 2 && a.compact && a.counters16) {
+            // 16-bit bucket ranges of 2^16 with compaction (e1 implies m a power of two)
+            if constexpr (NC <= 2) {
+                SegGeom gc = seg16_geometry(a.m, a.d, a.scratch_bytes, a.n);
+                gc.chunks = chunks_for(gc.chunks, 2);
+                if (gc.R != (1u << 16) || (uint64_t)gc.segments * gc.R != cells)
+                    return fail(CS_EINVAL, "16-bit range geometry");
+                const uint64_t chunkc = (a.n + gc.chunks - 1) / gc.chunks;
+                uint32_t *part = reinterpret_cast<uint32_t *>(a.scratch);
+                auto *sk64 = reinterpret_cast<unsigned long long *>(a.sketch);
+                auto kern = a.weights ? &k_update_seg16c<NC, true> : &k_update_seg16c<NC, false>;
+                CSK_MARK(a.ev_start, s);
+                hipLaunchKernelGGL(kern, dim3((unsigned)gc.chunks, (unsigned)gc.segments), dim3(kSegBlock), 0, s,
+                                   a.keys, a.weights, a.n, a.coef, a.plan.coef_per_rep, a.m, chunkc, vec2, part, sk64,
+                                   a.canon_thresh);
+                CSK_HIP(hipGetLastError());
+                CSK_MARK(a.ev_stop, s);
+                const uint64_t words = cells / 2;
+                hipLaunchKernelGGL(k_seg_reduce16, dim3((unsigned)std::min<uint64_t>((words + 255) / 256, 8192)),
+                                   dim3(256), 0, s, part, gc.chunks, words, sk64);
+            }
         } else if (narrow && e1 && sg.R < a.m && NC <= 2 && a.compact) {
             // bucket-range segments: compacting kernel (queue after the counters in LDS)
             int32_t *part = reinterpret_cast<int32_t *>(a.scratch);
@@ -1133,7 +1270,7 @@ size_t seg_scratch_bytes(uint32_t m, int32_t d)
     return best;
 }
 
-int auto_update_strategy(uint32_t m, int32_t d, uint64_t n, int n_cols, bool unit, bool has_scratch)
+int auto_update_strategy(uint32_t m, int32_t d, uint64_t n, int n_cols, bool unit, bool has_scratch, bool e1_pow2)
 {
     // Global atomics run at about 2.4e10/s on the whole chip (and far slower on the hot
     // buckets of skewed keys), the hash at about 5e12 Horner steps/s: beyond a few
@@ -1141,12 +1278,17 @@ int auto_update_strategy(uint32_t m, int32_t d, uint64_t n, int n_cols, bool uni
     // input fills (seg_geometry).  Beyond 2^16 buckets a repetition no longer fits one
     // workgroup's LDS and each tuple's bucket would be hashed once per bucket range;
     // there the partition strategy (each tuple hashed once, records sorted by range)
-    // measured 1.5-20x faster for m from 1.5 * 2^16 to 2^20, d from 3 to 9.  With
-    // general weights (no partition) the int64 segments lose to wavefront-aggregated
-    // atomics beyond 2^18 buckets.
+    // measured 1.5-20x faster for m from 1.5 * 2^16 to 2^20, d from 3 to 9, than the int32
+    // segments.  The 16-bit compacting kernel (ranges of 2^16 buckets, one-join columns,
+    // m a power of two) beats it at two ranges per repetition (3e7 Zipf tuples, d = 5:
+    // 0.82 vs 1.33 ms at m = 2^17), ties at four (m = 2^18, d = 5) and loses beyond
+    // (2^18 with d = 15: 4.5 vs 2.6 ms; 2^20: 5.7 vs 1.4 ms).  With general weights (no
+    // partition) the int64 segments lose to wavefront-aggregated atomics beyond 2^18
+    // buckets.
     if (!has_scratch) return CS_UPDATE_GLOBAL_ATOMIC;
     if (n * (uint64_t)d < 65536) return CS_UPDATE_GLOBAL_ATOMIC;
-    if (m > (1u << 16) && unit && n_cols <= 2) return CS_UPDATE_PARTITION;
+    if (m > (1u << 16) && unit && n_cols <= 2)
+        return m <= (1u << 17) && d <= 9 && e1_pow2 ? CS_UPDATE_LDS_PRIVATE : CS_UPDATE_PARTITION;
     if (m > (1u << 18) && !unit) return CS_UPDATE_WAVE_AGGREGATE;
     return CS_UPDATE_LDS_PRIVATE;
 }
@@ -1205,7 +1347,9 @@ cs_status launch_update(const UpdateArgs &a_in, int strategy, int grid_blocks, h
             a.compact = a.compact && (tf & CS_UPDATE_NO_COMPACT) == 0;
             a.counters16 = a.counters16 && (tf & CS_UPDATE_NO_COUNTERS16) == 0;
         } else {
-            strategy = auto_update_strategy(a.m, a.d, a.n, a.plan.n_cols, unit, true);
+            bool e1_pow2 = (a.m & (a.m - 1)) == 0;
+            for (int c = 0; c < a.plan.n_cols; ++c) e1_pow2 = e1_pow2 && a.plan.n_edges[c] == 1;
+            strategy = auto_update_strategy(a.m, a.d, a.n, a.plan.n_cols, unit, true, e1_pow2);
         }
     }
     if (strategy != CS_UPDATE_LDS_PRIVATE && strategy != CS_UPDATE_PARTITION) return dispatch_nc(a, strategy, grid_blocks, s);

@@ -148,12 +148,13 @@ def test_sketch_full_reduction_path(case, strategy):
     sk.close()
 
 
+@pytest.mark.parametrize("m", [1 << 16, 1 << 17])
 @pytest.mark.parametrize("kind", ["all_plus", "all_minus", "alternating", "two_hot"])
-def test_counters16_spill(kind):
+def test_counters16_spill(kind, m):
     """16-bit LDS counters hand multiples of 2^14 to the int64 sketch; counters driven far
     past +-2^15 in either direction, or swinging across the spill thresholds, stay exact."""
     graph = W.single_join()
-    n, m, d, seed = 400_000, 1 << 16, 5, 77
+    n, d, seed = 400_000, 5, 77
     rng = np.random.default_rng(9)
     if kind == "two_hot":
         k0 = rng.choice(np.array([3, 11], dtype=np.uint32), size=(n, 1))
@@ -181,16 +182,17 @@ def test_counters16_spill(kind):
         sk.close()
 
 
+@pytest.mark.parametrize("m", [1 << 16, 1 << 18])
 @pytest.mark.parametrize("offset", [0, 1, 2, 3])
 @pytest.mark.parametrize("n", [1, 3, 4, 4097, 100_003])
-def test_counters16_alignment_and_tails(offset, n):
+def test_counters16_alignment_and_tails(offset, n, m):
     """16-bit kernel: key and weight arrays starting at every 4-byte offset modulo 16 bytes
     (the quad loads need 16-byte alignment, the other form takes any), chunk lengths
     with 0-3 tuples after the last whole quad, one or several chunks, weights +1 (NULL)
     and +-1."""
     graph = W.chain(3)
-    m, d, seed = 1 << 16, 3, 5
-    _say("counters16 alignment", offset, n)
+    d, seed = 3, 5
+    _say("counters16 alignment", offset, n, m)
     rels = _rels(graph, n + offset, "zipf", 10 ** 4, config=95)
     weights = [W.turnstile_weights(n + offset, 0.2, seed=k).numpy() for k in range(graph.n_rel)]
     refs = {}
