@@ -795,13 +795,13 @@ __device__ __forceinline__ void unpack_key(uint64_t k, uint32_t (&x)[NC])
 // record per tile.  Each distinct tuple is then hashed per repetition into a 32-bit
 // record: bucket offset inside its range (13 bits) and signed sum of Deltas times the
 // sign (19 bits; |sum| <= kPartTile).
-template <int NC>
+template <int NC, bool E1>
 __global__ __launch_bounds__(kPB) void k_part_hash(const uint32_t *__restrict__ keys,
                                                       const int64_t *__restrict__ weights, uint64_t n,
                                                       const uint64_t *__restrict__ coef, int32_t cpr,
                                                       DevPlan plan, uint32_t m, int32_t d, int32_t log2R,
                                                       int32_t ranges, bool vec2, uint32_t *rec_out,
-                                                      int32_t *tab)
+                                                      int32_t *tab, uint32_t canon_thresh)
 {
     __shared__ uint64_t s_key[kDedupSlots + 1];  // slot kDedupSlots: the tuple whose packed key is kEmptyKey
     __shared__ int32_t s_w[kDedupSlots + 1];
@@ -879,12 +879,26 @@ __global__ __launch_bounds__(kPB) void k_part_hash(const uint32_t *__restrict__ 
         uint32_t rec[kPartPerThread];
         uint16_t rng[kPartPerThread];
         uint16_t pos[kPartPerThread];
+        // E1 (every column in one join, m a power of two): coefficients in registers and
+        // the canonical reduction only when a hash's flag asks for it
+        CoefE1<NC> K;
+        if constexpr (E1) K.load(cf);
 #pragma unroll
         for (int k = 0; k < kPartPerThread; ++k) {
             const int l = threadIdx.x + k * kPB;
             if (l < u) {
                 uint32_t j, neg;
-                hash_rep<NC>(cf, plan, x[k], j, neg);
+                if constexpr (E1) {
+                    uint32_t flag;
+                    K.bin_neg_fast(x[k], j, neg, flag);
+                    if (flag >= canon_thresh) {
+                        j = K.bin(x[k]);
+                        neg = K.neg(x[k]);
+                    }
+                    j &= m - 1;
+                } else {
+                    hash_rep<NC>(cf, plan, x[k], j, neg);
+                }
                 const int32_t val = neg ? -wv[k] : wv[k];
                 rec[k] = (j & rmask) | ((uint32_t)val << 13);
                 rng[k] = (uint16_t)(j >> log2R);
@@ -1152,6 +1166,8 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
         if (!a.scratch) return fail(CS_EINVAL, "the partition strategy needs a scratch buffer");
         const PartGeom pg = part_geometry(a.m, a.d, a.scratch_bytes);
         if (pg.chunk == 0) return fail(CS_EINVAL, "scratch buffer too small for the partition strategy");
+        bool e1 = pow2;  // one-join columns and m a power of two: the fast hash
+        for (int c = 0; c < a.plan.n_cols; ++c) e1 = e1 && a.plan.n_edges[c] == 1;
         uint32_t *rec = reinterpret_cast<uint32_t *>(a.scratch);
         int32_t *tab = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(a.scratch) + pg.tab_offset);
         const size_t max_tiles = pg.chunk / kPartTile;
@@ -1162,9 +1178,10 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
             const int tiles = (int)((cn + kPartTile - 1) / kPartTile);
             const uint32_t *kb = a.keys + base * a.plan.n_cols;
             const bool v2 = NC == 2 && ((uintptr_t)kb % 8) == 0;
-            hipLaunchKernelGGL(k_part_hash<NC>, dim3(tiles), dim3(kPB), 0, s, kb,
+            auto hash_kern = e1 ? &k_part_hash<NC, true> : &k_part_hash<NC, false>;
+            hipLaunchKernelGGL(hash_kern, dim3(tiles), dim3(kPB), 0, s, kb,
                                a.weights ? a.weights + base : nullptr, cn, a.coef, a.plan.coef_per_rep, plan, a.m,
-                               a.d, pg.log2R, pg.ranges, v2, rec, tab);
+                               a.d, pg.log2R, pg.ranges, v2, rec, tab, a.canon_thresh);
             CSK_HIP(hipGetLastError());
             hipLaunchKernelGGL(k_part_accum, dim3(pg.ranges, a.d), dim3(kPAB), lds, s, rec, tab, tiles, a.d,
                                pg.ranges, pg.log2R, a.m, a.sketch);
