@@ -238,6 +238,10 @@ struct RepDesc {
 struct QDesc {
     int32_t plan, r, d, log2m, rep_base, nb;
     uint32_t m;
+    // where this query's partials start (its first sketch's norm pair, its first
+    // repetition's spectral sums and residues): the finalize reads them without going
+    // through the repetition and sketch descriptors first
+    int64_t norm_off0, spec_off0, mod_off0;
 };
 
 // ---------------------------------------------------------------- kernels
@@ -548,10 +552,9 @@ __global__ __launch_bounds__(NT) void k_finalize(FinalizeArgs a)
         // The nb <= 64 block partials of each owner (a sketch for the norms, a repetition
         // for the spectral sums) are reduced by one wavefront: lane b loads partial b and
         // a shuffle tree of depth 6 adds them, in a fixed order.
-        const RepDesc D0 = a.reps[Q.rep_base];
         const int nb = Q.nb;
         const int n_sk = Q.r * Q.d;
-        const double *nrm = a.norms + a.sks[D0.sk_base].off * 2;
+        const double *nrm = a.norms + Q.norm_off0 * 2;
         for (int o = wv; o < n_sk; o += kWaves) {
             double q2 = 0.0, l1 = 0.0;
             if (lane < nb) {
@@ -568,7 +571,7 @@ __global__ __launch_bounds__(NT) void k_finalize(FinalizeArgs a)
         }
         if (plan == CS_PLAN_SPECTRAL) {
             const int w = 2 + Q.r;
-            const double *spc = a.spec + D0.spec_off;
+            const double *spc = a.spec + Q.spec_off0;
             for (int o = wv; o < Q.d; o += kWaves) {
                 const double *p = spc + ((int64_t)o * nb + lane) * w;
                 double sm = lane < nb ? p[0] : 0.0, sa = lane < nb ? p[1] : 0.0;
@@ -592,11 +595,11 @@ __global__ __launch_bounds__(NT) void k_finalize(FinalizeArgs a)
         for (int o = wv; o < Q.d && (STAGE == 2 || plan == CS_PLAN_SPECTRAL); o += kWaves) {
             const int K = STAGE == 3 ? a.kcap : a.rs[Q.rep_base + o].kprimes;
             if (K <= 0 || K > a.kcap) continue;
-            const RepDesc D = a.reps[Q.rep_base + o];
+            const int64_t mod_off = Q.mod_off0 + (int64_t)o * Q.nb;  // repetitions' residues follow each other
             for (int i = 0; i < K; ++i) {
                 const PrimeDev &P = a.primes[i];
                 const RingM R{P.p, P.pinv_neg};
-                uint32_t v = lane < D.nb ? a.modp[(size_t)i * a.mod_plane + D.mod_off + lane] : 0u;
+                uint32_t v = lane < Q.nb ? a.modp[(size_t)i * a.mod_plane + mod_off + lane] : 0u;
                 for (int off = 32; off > 0; off >>= 1) v = R.add(v, __shfl_down(v, off, 64));
                 if (lane == 0) s_res[o * kMaxPrimes + i] = v;
             }
@@ -1193,6 +1196,9 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
         Q.m = h.m;
         Q.rep_base = (int32_t)rd.size();
         Q.nb = nb;
+        Q.norm_off0 = norm_off;
+        Q.spec_off0 = spec_off;
+        Q.mod_off0 = mod_off;
         const int sk_base = (int)sd.size();
         const size_t m = h.m;
         if (Q.plan != CS_PLAN_DOT) {
