@@ -976,27 +976,37 @@ __global__ __launch_bounds__(kPAB) void k_part_accum(const uint32_t *__restrict_
     }
     __syncthreads();
     const int total = s_pre[tiles];
-    for (int g0 = threadIdx.x; g0 < total; g0 += 4 * kPAB) {
-        uint32_t v[4];
-        bool ok[4];
+    // The tile of record g is the largest tile with s_pre[tile] <= g: a binary search
+    // with the same number of steps for every record, so that a thread's searches for
+    // its kAccU records advance together (independent LDS loads in flight, then
+    // independent global loads) instead of one data-dependent loop after another.
+    constexpr int kAccU = 4;
+    int top = 0;  // largest power of two <= tiles - 1
+    if (tiles > 1) {
+        top = 1;
+        while (2 * top <= tiles - 1) top *= 2;
+    }
+    for (int g0 = threadIdx.x; g0 < total; g0 += kAccU * kPAB) {
+        int g[kAccU], lo[kAccU];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int g = g0 + u * kPAB;
-            ok[u] = g < total;
-            v[u] = 0;
-            if (ok[u]) {
-                int lo = 0, hi = tiles - 1;  // tile with s_pre[tile] <= g < s_pre[tile + 1]
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (s_pre[mid] <= g) lo = mid;
-                    else hi = mid - 1;
-                }
-                v[u] = rec[((size_t)lo * d + t) * kPartTile + s_beg[lo] + (g - s_pre[lo])];
+        for (int u = 0; u < kAccU; ++u) {
+            g[u] = g0 + u * kPAB;
+            lo[u] = 0;
+        }
+        for (int step = top; step > 0; step >>= 1) {
+#pragma unroll
+            for (int u = 0; u < kAccU; ++u) {
+                const int c = lo[u] + step;
+                if (c < tiles && s_pre[c] <= g[u]) lo[u] = c;
             }
         }
+        uint32_t v[kAccU];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (ok[u]) atomicAdd(&s_acc[v[u] & 0x1FFFu], (int32_t)v[u] >> 13);
+        for (int u = 0; u < kAccU; ++u)
+            v[u] = g[u] < total ? rec[((size_t)lo[u] * d + t) * kPartTile + s_beg[lo[u]] + (g[u] - s_pre[lo[u]])] : 0u;
+#pragma unroll
+        for (int u = 0; u < kAccU; ++u)
+            if (g[u] < total) atomicAdd(&s_acc[v[u] & 0x1FFFu], (int32_t)v[u] >> 13);
     }
     __syncthreads();
     uint64_t *out = sketch + (size_t)t * m + ((size_t)r << log2R);
