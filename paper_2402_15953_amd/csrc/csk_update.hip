@@ -1308,8 +1308,8 @@ int auto_update_strategy(uint32_t m, int32_t d, uint64_t n, int n_cols, bool uni
     // measured 1.5-20x faster for m from 1.5 * 2^16 to 2^20, d from 3 to 9, than the int32
     // segments.  The 16-bit compacting kernel (ranges of 2^16 buckets, one-join columns,
     // m a power of two) beats it at two ranges per repetition (3e7 Zipf tuples, d = 5:
-    // 0.82 vs 1.33 ms at m = 2^17), ties at four (m = 2^18, d = 5) and loses beyond
-    // (2^18 with d = 15: 4.5 vs 2.6 ms; 2^20: 5.7 vs 1.4 ms).  With general weights (no
+    // 0.82 vs 1.22 ms at m = 2^17) and loses from four on (m = 2^18, d = 5: 1.37 vs
+    // 1.21 ms; d = 15: 4.5 vs 2.2 ms; 2^20: 5.7 vs 1.4 ms).  With general weights (no
     // partition) the int64 segments lose to wavefront-aggregated atomics beyond 2^18
     // buckets.
     if (!has_scratch) return CS_UPDATE_GLOBAL_ATOMIC;
