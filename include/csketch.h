@@ -280,13 +280,14 @@ cs_status cs_tune_count(int32_t *n_out);
  * `reps` may be NULL.  Errors: CS_EINVAL, CS_EDEVICE, CS_ENOMEM. */
 cs_status cs_estimate(cs_sketch *h, void *stream, cs_estimate_t *out, const cs_reps_t *reps);
 
-/* Asynchronous estimate: the whole computation is enqueued on `stream` and the result is
- * written to *out, which must be memory the device can write (device memory, or pinned
- * host memory from hipHostMalloc), once the stream passes the call; the call returns
- * without waiting.  No host round trip happens, so a repetition that needs more primes
- * than the speculative modular step computes (as many as the previous synchronous or
- * asynchronous estimate on this handle needed, at most 5 = about 155 bits of window;
- * 5 on the first call) keeps its fp64 value, and out->exact is then 0.  Stream-ordered
+/* Asynchronous estimate: the same result as cs_estimate (Eq. 5 per repetition through
+ * Alg. 3, median over the repetitions, Sec. 3.3), with the whole computation enqueued on
+ * `stream` and the result written to *out, which must be memory the device can write
+ * (device memory, or pinned host memory from hipHostMalloc), once the stream passes the
+ * call; the call returns without waiting.  No host round trip happens, so a repetition
+ * that needs more primes than the speculative modular step computes (as many as the
+ * handle's last synchronous estimate needed, at most 5 = about 155 bits of window; 5
+ * before the first) keeps its fp64 value, and out->exact is then 0.  Stream-ordered
  * with the handle's updates and estimates; calls on other streams must not overlap it.
  * Errors (returned at once, nothing enqueued): CS_EINVAL for queries with the general
  * plan (their estimate needs host round trips) and for an `out` that is not device
