@@ -172,18 +172,21 @@ const char *cs_last_error(void);
 
 /* ------------------------------------------------------------------ update (Alg. 2) */
 
-/* Stream n tuples of relation `rel` into its sketch (Alg. 2 for each repetition).
+/* Stream n tuples of relation `rel` into its sketch (Alg. 2 for each repetition;
+ * Eq. 2-4 define the counters it produces).
  * Calls on one handle must be ordered (one stream, or event dependencies).  The
  * segmented and partition strategies use one scratch buffer per device shared by all
  * handles; it grows, once, to the largest (m, d) seen: the only allocation on this
  * path.  Its reuse is ordered by the stream while consecutive users share one; a call on
  * another stream than the previous user's first waits for the device to be idle.
- *   keys:    device, uint32 [n][a_rel] tuple-major; column c is the c-th attribute of
- *            `rel` in ascending attribute id.
- *   weights: device, int64 [n] frequency changes Delta (turnstile model, Sec. 2.1),
- *            or NULL for Delta = +1.
+ *   keys:    device (or pinned / managed host) memory, uint32 [n][a_rel] tuple-major;
+ *            column c is the c-th attribute of `rel` in ascending attribute id.
+ *   weights: the same kinds of memory, int64 [n] frequency changes Delta (turnstile
+ *            model, Sec. 2.1), or NULL for Delta = +1.
  * Asynchronous and ordered on `stream`.  n = 0 is a no-op.
- * Errors: CS_EINVAL (bad handle, rel out of range, keys NULL with n > 0). */
+ * Errors: CS_EINVAL (bad handle, rel out of range, keys NULL with n > 0, keys or weights
+ * in memory the device cannot read, such as pageable host memory: checked on the host
+ * before anything is enqueued). */
 cs_status cs_update(cs_sketch *h, int32_t rel, const uint32_t *keys, const int64_t *weights,
                     uint64_t n, void *stream);
 
