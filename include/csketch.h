@@ -104,7 +104,7 @@ typedef enum cs_update_strategy {
     CS_UPDATE_LDS_PRIVATE = 2,    /* the d x m counters cut into LDS-sized segments;
                                      each workgroup accumulates one segment for one chunk
                                      of tuples in LDS, stores partial sums to the
-                                     device's scratch pool, and a reduce kernel adds
+                                     handle's scratch buffer, and a reduce kernel adds
                                      them into the counters */
     CS_UPDATE_WAVE_AGGREGATE = 3, /* equal buckets of one wavefront merged before the atomic */
     CS_UPDATE_PARTITION = 4       /* sort by bucket: identical tuples of a tile merged in
@@ -175,10 +175,8 @@ const char *cs_last_error(void);
 /* Stream n tuples of relation `rel` into its sketch (Alg. 2 for each repetition;
  * Eq. 2-4 define the counters it produces).
  * Calls on one handle must be ordered (one stream, or event dependencies).  The
- * segmented and partition strategies use one scratch buffer per device shared by all
- * handles; it grows, once, to the largest (m, d) seen: the only allocation on this
- * path.  Its reuse is ordered by the stream while consecutive users share one; a call on
- * another stream than the previous user's first waits for the device to be idle.
+ * segmented and partition strategies use the handle's own scratch buffer, allocated by
+ * cs_create: the call allocates nothing and never waits on the host.
  *   keys:    device (or pinned / managed host) memory, uint32 [n][a_rel] tuple-major;
  *            column c is the c-th attribute of `rel` in ascending attribute id.
  *   weights: the same kinds of memory, int64 [n] frequency changes Delta (turnstile
@@ -207,6 +205,26 @@ cs_status cs_update_ex(cs_sketch *h, int32_t rel, const uint32_t *keys, const in
 cs_status cs_update_timed(cs_sketch *h, int32_t rel, const uint32_t *keys, const int64_t *weights,
                           uint64_t n, void *stream, int32_t strategy, int32_t grid_blocks,
                           int32_t flags, void *ev_start, void *ev_stop);
+
+/* cs_update for callers that cannot allocate device memory while they run (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * counters as cs_update (automatic strategy), but the strategies' scratch buffer
+ * (partial sums, records) is a file-scope device array of
+ * cs_update_noalloc_scratch_bytes() bytes (64 MiB) that each GPU holds until the process
+ * ends, instead of the handle's.  The call allocates nothing (no hipMalloc / hipFree, no
+ * allocating library routine).
+ *   flags: 0 or CS_UPDATE_UNIT_WEIGHTS.  Other arguments as cs_update.
+ * The handle's device must be the current device.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (different streams without an ordering
+ * between them, or several host threads) race on it and must be ordered by the caller;
+ * consecutive calls on one stream are ordered by it.  Nothing the array keeps from an
+ * earlier call is read.
+ * Errors: as cs_update, and CS_EINVAL when the strategy for this (m, d) would need more
+ * scratch than the array holds (e.g. general weights with d * m beyond 2^23 counters),
+ * refused before anything is enqueued. */
+cs_status cs_update_noalloc(cs_sketch *h, int32_t rel, const uint32_t *keys, const int64_t *weights,
+                            uint64_t n, int32_t flags, void *stream);
+size_t cs_update_noalloc_scratch_bytes(void);
 
 /* ------------------------------------------------------------------ filtered ingestion */
 
@@ -380,7 +398,10 @@ cs_status cs_server_destroy(cs_server *s);
 /* Admission: CS_EBUSY when the query's counters do not fit the memory budget. */
 cs_status cs_server_add_query(cs_server *s, const cs_graph *graph, uint32_t m, uint32_t d, uint64_t seed,
                               int32_t *qid);
-/* Waits for all submitted requests, then frees the query's memory. */
+/* Marks the query removed at once (later submissions for it are refused with
+ * CS_EINVAL; its requests still queued complete with CS_EINVAL), waits for this query's
+ * own requests already on the GPU, then frees its memory.  Requests of other queries keep
+ * flowing meanwhile.  A second removal of the same qid returns CS_EINVAL. */
 cs_status cs_server_remove_query(cs_server *s, int32_t qid);
 /* The handle of a live query (for reading its sketches; do not update it directly). */
 cs_status cs_server_sketch(cs_server *s, int32_t qid, cs_sketch **out);

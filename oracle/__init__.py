@@ -546,6 +546,54 @@ class _ModRing:
         return int(np.sum(x, dtype=np.uint64)) % self.p
 
 
+class _SparseRing:
+    """Vectors of Python integers held as {index: nonzero value}; cross-correlation by
+    Def. 3.1 over the nonzero entries only: (a star x)_j collects a_i x_l at j = (l - i)
+    mod m.  Exact for any m; the cost follows the supports, so it serves sketches of
+    few tuples at large m (where the dense rings cost O(m^2) or O(m log m) per prime).
+    The all-ones vector of CombineSketches is kept symbolic (None)."""
+
+    def __init__(self, m):
+        self.m = m
+
+    def vec(self, c):
+        return {int(j): int(v) for j, v in enumerate(c) if v != 0} if not isinstance(c, np.ndarray) else \
+            {int(j): int(c[j]) for j in np.flatnonzero(c)}
+
+    def ones(self):
+        return None
+
+    def hadamard(self, a, b):
+        if a is None:
+            return b
+        if b is None:
+            return a
+        if len(a) > len(b):
+            a, b = b, a
+        return {j: v * b[j] for j, v in a.items() if j in b}
+
+    def correlate(self, a, x):
+        if a is None or x is None:
+            raise ValueError("correlation with the all-ones vector does not occur in a valid query")
+        m = self.m
+        out: Dict[int, int] = {}
+        for i, ai in a.items():
+            for l, xl in x.items():
+                j = (l - i) % m
+                out[j] = out.get(j, 0) + ai * xl
+        return {j: v for j, v in out.items() if v != 0}
+
+    def total(self, x):
+        return sum(x.values())
+
+
+def estimate_sparse(info: QueryInfo, sketches: Sequence[Sequence[int]], m: int, root: int = 0) -> int:
+    """GetQueryEstimate of Alg. 3 for one repetition in exact integers over the sketches'
+    nonzero counters (_SparseRing): the same ring operations as estimate_alg3, any m."""
+    ring = _SparseRing(m)
+    return ring.total(_combine_sketches(root, set(), info, sketches, ring))
+
+
 def _combine_sketches(u: int, V: set, info: QueryInfo, c, ring):
     """CombineSketches of Alg. 3."""
     k = info.attr_rel[u]

@@ -26,7 +26,8 @@ PLAN_DOT, PLAN_SPECTRAL, PLAN_GENERAL = 1, 2, 3
 
 EXPORTED = [
     "cs_create", "cs_destroy", "cs_sketch_bytes", "cs_get_info", "cs_last_error",
-    "cs_update", "cs_update_ex", "cs_update_timed", "cs_update_filtered", "cs_estimate", "cs_reset", "cs_merge", "cs_read_sketch",
+    "cs_update", "cs_update_ex", "cs_update_timed", "cs_update_noalloc", "cs_update_noalloc_scratch_bytes",
+    "cs_update_filtered", "cs_estimate", "cs_reset", "cs_merge", "cs_read_sketch",
     "cs_sketch_device_ptr", "cs_read_coeffs", "cs_read_components",
     "cs_timer_create", "cs_timer_record", "cs_timer_elapsed", "cs_timer_destroy",
     "cs_tune_update", "cs_tune_clear", "cs_tune_save", "cs_tune_load", "cs_tune_count",
@@ -139,6 +140,9 @@ def lib() -> ctypes.CDLL:
         L.cs_update.argtypes = [vp, i32, vp, vp, u64, vp]
         L.cs_update_ex.argtypes = [vp, i32, vp, vp, u64, vp, i32, i32, i32]
         L.cs_update_timed.argtypes = [vp, i32, vp, vp, u64, vp, i32, i32, i32, vp, vp]
+        L.cs_update_noalloc.argtypes = [vp, i32, vp, vp, u64, i32, vp]
+        L.cs_update_noalloc_scratch_bytes.argtypes = []
+        L.cs_update_noalloc_scratch_bytes.restype = ctypes.c_size_t
         L.cs_update_filtered.argtypes = [vp, i32, vp, vp, u64, vp, i32, ctypes.POINTER(_Predicate), i32, i32, vp,
                                          ctypes.POINTER(u64)]
         L.cs_estimate.argtypes = [vp, vp, ctypes.POINTER(_Estimate), ctypes.POINTER(_Reps)]
@@ -378,6 +382,22 @@ class Sketch:
             e0, e1 = _event_ptr(timing[0]), _event_ptr(timing[1])
             _check(lib().cs_update_timed(self._h, int(rel), ctypes.c_void_p(keys.data_ptr()), wp, int(n),
                                          _stream_ptr(stream), int(strategy), int(grid), flags, e0, e1))
+
+    def update_noalloc(self, rel: int, keys, weights=None, stream=None, unit_weights: bool = False):
+        """cs_update_noalloc: the automatic update with the library's static scratch array
+        (nothing is allocated); same arguments and counters as update()."""
+        import torch
+        if keys.dtype not in (torch.int32, torch.uint32) or not keys.is_cuda or not keys.is_contiguous():
+            raise TypeError("keys must be a contiguous int32/uint32 device tensor")
+        n = keys.shape[0]
+        wp = None
+        if weights is not None:
+            if weights.dtype != torch.int64 or not weights.is_cuda or not weights.is_contiguous() \
+                    or weights.shape[0] != n:
+                raise TypeError("weights must be a contiguous int64 device tensor of length n")
+            wp = ctypes.c_void_p(weights.data_ptr())
+        _check(lib().cs_update_noalloc(self._h, int(rel), ctypes.c_void_p(keys.data_ptr()), wp, int(n),
+                                       UPDATE_UNIT_WEIGHTS if unit_weights else 0, _stream_ptr(stream)))
 
     def update_filtered(self, rel: int, keys, attrs, predicates, weights=None, stream=None,
                         unit_weights: bool = False) -> int:

@@ -316,7 +316,17 @@ cs_status create_handle(const cs_graph *graph, uint32_t m, uint32_t d, uint64_t 
         delete hs;
         return fail(CS_ENOMEM, "coefficient allocation failed");
     }
-    (void)with_scratch;  // update scratch is a per-device pool shared by all handles
+    // the update's scratch (partial sums, records) belongs to the handle: cs_update
+    // then neither allocates nor orders itself against other handles' updates
+    if (with_scratch) {
+        h.scratch_bytes = seg_scratch_bytes(m, (int32_t)d);
+        if (hipMalloc(&h.scratch, h.scratch_bytes) != hipSuccess) {
+            hipFree(h.counters);
+            hipFree(h.coef_dev);
+            delete hs;
+            return fail(CS_ENOMEM, "update scratch allocation failed");
+        }
+    }
     if (hipMemcpy(h.coef_dev, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(h.counters, 0, n_ctr * sizeof(int64_t)) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
@@ -374,20 +384,23 @@ cs_status cs_update_ex(cs_sketch *hs, int32_t rel, const uint32_t *keys, const i
     return cs_update_timed(hs, rel, keys, weights, n, stream, strategy, grid_blocks, flags, nullptr, nullptr);
 }
 
-cs_status cs_update_timed(cs_sketch *hs, int32_t rel, const uint32_t *keys, const int64_t *weights, uint64_t n,
-                          void *stream, int32_t strategy, int32_t grid_blocks, int32_t flags, void *ev_start,
-                          void *ev_stop)
+}  // extern "C"
+
+namespace csk {
+
+cs_status update_args(cs_sketch *hs, int32_t rel, const uint32_t *keys, const int64_t *weights, uint64_t n,
+                      int32_t flags, UpdateArgs *out)
 {
     if (!hs) return fail(CS_EINVAL, "null handle");
     Handle &h = hs->h;
     if (rel < 0 || rel >= h.g.n_rel) return fail(CS_EINVAL, "relation out of range");
-    if (n == 0) return CS_OK;
-    if (!keys) return fail(CS_EINVAL, "null keys");
-    if (strategy < CS_UPDATE_AUTO || strategy > CS_UPDATE_PARTITION) return fail(CS_EINVAL, "bad strategy");
-    cs_status chk = check_device_array(keys, n * h.g.rel[rel].n_cols * sizeof(uint32_t), h.device, "keys");
-    if (chk == CS_OK && weights) chk = check_device_array(weights, n * sizeof(int64_t), h.device, "weights");
-    if (chk != CS_OK) return chk;
-    UpdateArgs a;
+    if (n > 0 && !keys) return fail(CS_EINVAL, "null keys");
+    if (n > 0) {
+        cs_status chk = check_device_array(keys, n * h.g.rel[rel].n_cols * sizeof(uint32_t), h.device, "keys");
+        if (chk == CS_OK && weights) chk = check_device_array(weights, n * sizeof(int64_t), h.device, "weights");
+        if (chk != CS_OK) return chk;
+    }
+    UpdateArgs &a = *out;
     a.keys = keys;
     a.weights = weights;
     a.n = n;
@@ -396,12 +409,27 @@ cs_status cs_update_timed(cs_sketch *hs, int32_t rel, const uint32_t *keys, cons
     a.m = h.m;
     a.d = (int32_t)h.d;
     a.plan = h.g.rel[rel];
-    a.scratch = nullptr;
-    a.scratch_bytes = 0;
+    a.scratch = h.scratch;
+    a.scratch_bytes = h.scratch_bytes;
     a.unit_weights = (flags & CS_UPDATE_UNIT_WEIGHTS) != 0;
     a.compact = (flags & CS_UPDATE_NO_COMPACT) == 0;
     a.counters16 = (flags & CS_UPDATE_NO_COUNTERS16) == 0;
     if (flags & CS_UPDATE_TEST_FULL_REDUCTION) a.canon_thresh = 0xF0000000u;
+    return CS_OK;
+}
+
+}  // namespace csk
+
+extern "C" {
+
+cs_status cs_update_timed(cs_sketch *hs, int32_t rel, const uint32_t *keys, const int64_t *weights, uint64_t n,
+                          void *stream, int32_t strategy, int32_t grid_blocks, int32_t flags, void *ev_start,
+                          void *ev_stop)
+{
+    if (strategy < CS_UPDATE_AUTO || strategy > CS_UPDATE_PARTITION) return fail(CS_EINVAL, "bad strategy");
+    UpdateArgs a;
+    cs_status st = update_args(hs, rel, keys, weights, n, flags, &a);
+    if (st != CS_OK || n == 0) return st;
     a.ev_start = static_cast<hipEvent_t>(ev_start);
     a.ev_stop = static_cast<hipEvent_t>(ev_stop);
     return launch_update(a, strategy, grid_blocks, static_cast<hipStream_t>(stream));
@@ -440,15 +468,12 @@ cs_status cs_update_filtered(cs_sketch *hs, int32_t rel, const uint32_t *keys, c
         return cs_update_ex(hs, rel, keys, weights, n, stream, CS_UPDATE_AUTO, 0, flags);
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const uint32_t *fkeys = nullptr;
-    const int64_t *fw = nullptr;
-    uint64_t kept = 0;
-    cs_status st = filter_tuples(h.device, keys, h.g.rel[rel].n_cols, weights, n, attrs, n_attrs, f, s, &fkeys, &fw,
-                                 &kept);
-    if (st != CS_OK) return st;
-    if (n_kept) *n_kept = kept;
-    if (kept == 0) return CS_OK;
-    return cs_update_ex(hs, rel, fkeys, fw, kept, stream, CS_UPDATE_AUTO, 0, flags);
+    return filter_tuples(h.device, keys, h.g.rel[rel].n_cols, weights, n, attrs, n_attrs, f, s,
+                         [&](const uint32_t *fkeys, const int64_t *fw, uint64_t kept) -> cs_status {
+                             if (n_kept) *n_kept = kept;
+                             if (kept == 0) return CS_OK;
+                             return cs_update_ex(hs, rel, fkeys, fw, kept, stream, CS_UPDATE_AUTO, 0, flags);
+                         });
 }
 
 cs_status cs_update(cs_sketch *hs, int32_t rel, const uint32_t *keys, const int64_t *weights, uint64_t n,

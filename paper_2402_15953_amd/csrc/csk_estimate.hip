@@ -231,7 +231,7 @@ struct RepDesc {
     int32_t sk_base;       // first sketch (k * d + t order) of query q in the SkDesc table
     int32_t mod_vec_base;  // modular pass: first vector of query q in its group's buffer
     int64_t spec_off;      // fp64 spectral partials, (2 + r) doubles per block
-    int64_t dot_off;       // DOT partials, 2 u64 per block
+    int64_t dot_off;       // DOT partials, 4 words per block (int128 sum, fp64 sum, fp64 sum of |terms|)
     int64_t mod_off;       // modular partials (per prime plane)
 };
 
@@ -282,29 +282,43 @@ __global__ __launch_bounds__(kThreads) void k_norms(const SkDesc *__restrict__ s
     }
 }
 
-// 128-bit inner product of c_0[t] and c_1[t], per block.
+// 128-bit inner product of c_0[t] and c_1[t], per block, wrapping modulo 2^128, with
+// an fp64 sum of the products and an fp64 sum of their absolute values beside it: the
+// latter bounds every partial sum, so the finalize knows whether the wrapped integer is
+// the true one (the sum of |terms| stays below 2^126).
 __global__ __launch_bounds__(kThreads) void k_dot(const RepDesc *__restrict__ reps, const int32_t *__restrict__ idx,
                                                   const int64_t *__restrict__ prefix, int n_items,
                                                   unsigned long long *partials)
 {
     __shared__ unsigned __int128 sh[kThreads];
+    __shared__ double shf[kThreads / 64];
     const int item = find_item(prefix, n_items, blockIdx.x);
     const RepDesc D = reps[idx[item]];
     const int blk = (int)(blockIdx.x - prefix[item]);
     const int64_t m = D.m;
     __int128 acc = 0;
-    for (int64_t j = (int64_t)blk * kThreads + threadIdx.x; j < m; j += (int64_t)D.nb * kThreads)
-        acc += (__int128)D.c0[j] * (__int128)D.c1[j];
+    double fs = 0.0, fa = 0.0;
+    for (int64_t j = (int64_t)blk * kThreads + threadIdx.x; j < m; j += (int64_t)D.nb * kThreads) {
+        const int64_t x = D.c0[j], y = D.c1[j];
+        acc += (__int128)x * (__int128)y;
+        const double p = (double)x * (double)y;
+        fs += p;
+        fa += fabs(p);
+    }
     sh[threadIdx.x] = (unsigned __int128)acc;
+    const double bs = block_sum(fs, shf);
+    const double ba = block_sum(fa, shf);
     __syncthreads();
     for (int s = kThreads / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        unsigned long long *o = partials + (D.dot_off + blk) * 2;
+        unsigned long long *o = partials + (D.dot_off + blk) * 4;
         o[0] = (unsigned long long)(uint64_t)sh[0];
         o[1] = (unsigned long long)(uint64_t)(sh[0] >> 64);
+        o[2] = (unsigned long long)__double_as_longlong(bs);
+        o[3] = (unsigned long long)__double_as_longlong(ba);
     }
 }
 
@@ -622,16 +636,33 @@ __global__ __launch_bounds__(NT) void k_finalize(FinalizeArgs a)
             rp.bound = 0.0;
             if (plan == CS_PLAN_DOT) {
                 unsigned __int128 s = 0;
+                double fs = 0.0, fa = 0.0;
                 for (int b = 0; b < D.nb; ++b) {
-                    const unsigned long long *p = a.dot + (D.dot_off + b) * 2;
+                    const unsigned long long *p = a.dot + (D.dot_off + b) * 4;
                     s += ((unsigned __int128)p[1] << 64) | p[0];
+                    fs += __longlong_as_double((long long)p[2]);
+                    fa += __longlong_as_double((long long)p[3]);
                 }
-                const __int128 x = (__int128)s;
-                rp.lo = (int64_t)(uint64_t)s;
-                rp.hi = (int64_t)(uint64_t)(s >> 64);
-                rp.exact = 1;
-                rp.value = i128_to_double(x);
-                rp.xf = rp.value;
+                // fa sums |x_j y_j| with at most n_eff + nb additions per term (each
+                // product rounded once): the true sum of |terms| is at most
+                // fa (1 + (n_eff + nb + 2) u) and bounds every partial sum, so below 2^126
+                // the wrapped 128-bit integer is the exact inner product
+                const double bnd = fa * (1.0 + (n_eff + D.nb + 4.0) * u * 1.01);
+                if (bnd < 0x1p126) {
+                    const __int128 x = (__int128)s;
+                    rp.lo = (int64_t)(uint64_t)s;
+                    rp.hi = (int64_t)(uint64_t)(s >> 64);
+                    rp.exact = 1;
+                    rp.value = i128_to_double(x);
+                    rp.xf = rp.value;
+                } else {
+                    rp.lo = rp.hi = 0;
+                    rp.exact = 0;
+                    rp.status = 1;
+                    rp.value = fs;
+                    rp.xf = fs;
+                    rp.bound = bnd;
+                }
             } else {
                 // norms of each relation's sketch at this repetition (upper bounds)
                 // per-relation values live in LDS (indexed loops over r would
@@ -1301,7 +1332,7 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
     const size_t host_tables = c.off;
     const size_t o_norms = c.take(std::max<int64_t>(1, norm_off) * 2 * sizeof(double));
     const size_t o_spec = c.take(std::max<int64_t>(1, spec_off) * sizeof(double));
-    const size_t o_dot = c.take(std::max<int64_t>(1, dot_off) * 2 * sizeof(unsigned long long));
+    const size_t o_dot = c.take(std::max<int64_t>(1, dot_off) * 4 * sizeof(unsigned long long));
     const size_t o_modp = c.take((size_t)kMaxPrimes * std::max<int64_t>(1, mod_plane) * sizeof(uint32_t));
     const size_t o_rs = c.take((size_t)n_rep * sizeof(RepDev));  // [records | outputs]: one download
     const size_t o_outs = c.take((size_t)nq * sizeof(OutDev));

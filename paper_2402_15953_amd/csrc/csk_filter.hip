@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <map>
 #include <mutex>
 
@@ -96,9 +97,11 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 cs_status filter_tuples(int device, const uint32_t *keys, int n_cols, const int64_t *weights, uint64_t n,
                         const uint32_t *attrs, int n_attrs, const FilterSpec &f, hipStream_t s,
-                        const uint32_t **keys_out, const int64_t **weights_out, uint64_t *kept)
+                        const std::function<cs_status(const uint32_t *, const int64_t *, uint64_t)> &consume)
 {
     FilterBuf &B = fbuf_of(device);
+    // held until `consume` has enqueued its reads of the buffer: another caller on this
+    // device cannot overwrite or reallocate the buffer in between
     std::lock_guard<std::mutex> lk(B.mu);
     // the buffer's last reader (an update on another stream) must have finished
     if (B.used && s != B.last_stream) CSK_HIP(hipDeviceSynchronize());
@@ -131,10 +134,7 @@ cs_status filter_tuples(int device, const uint32_t *keys, int n_cols, const int6
     CSK_HIP(hipStreamSynchronize(s));
     B.used = true;
     B.last_stream = s;
-    *keys_out = okeys;
-    *weights_out = ow;
-    *kept = *B.host_count;
-    return CS_OK;
+    return consume(okeys, ow, (uint64_t)*B.host_count);
 }
 
 }  // namespace csk

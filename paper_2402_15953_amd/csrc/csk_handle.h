@@ -73,6 +73,10 @@ namespace csk {
 // Handle creation; without scratch the handle serves batched and served updates only.
 cs_status create_handle(const cs_graph *graph, uint32_t m, uint32_t d, uint64_t seed, bool with_scratch,
                         cs_sketch **out);
+// Checks the arguments of an update of relation rel and fills the launcher's arguments
+// (keys, weights, coefficients, counters, the handle's scratch, flags).
+cs_status update_args(cs_sketch *hs, int32_t rel, const uint32_t *keys, const int64_t *weights, uint64_t n,
+                      int32_t flags, UpdateArgs *out);
 // Estimates of nq queries at once (one FFT launch per sketch length, one product-reduce
 // launch per length, one finalize launch); reps_out may be null or hold nq entries.
 cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t *outs, const cs_reps_t *reps_out,

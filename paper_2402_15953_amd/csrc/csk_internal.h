@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -159,10 +160,12 @@ struct FilterSpec {
     uint32_t lo[CS_MAX_PREDICATES], hi[CS_MAX_PREDICATES];
 };
 // Copies the tuples (keys, and weights when given) that satisfy f into a per-device
-// buffer and returns it with their count (synchronous on s: the count is read back).
+// buffer (synchronous on s: the count is read back), then calls consume(keys, weights,
+// count) while still holding the buffer's lock, so the reads consume enqueues on s are
+// ordered before any later use of the buffer.
 cs_status filter_tuples(int device, const uint32_t *keys, int n_cols, const int64_t *weights, uint64_t n,
                         const uint32_t *attrs, int n_attrs, const FilterSpec &f, hipStream_t s,
-                        const uint32_t **keys_out, const int64_t **weights_out, uint64_t *kept);
+                        const std::function<cs_status(const uint32_t *, const int64_t *, uint64_t)> &consume);
 // Tuned (strategy, grid, flags) for this update's class on `device`, if one was tuned.
 bool tune_lookup(const UpdateArgs &a, int device, int *strategy, int *grid, int *flags);
 int auto_update_strategy(uint32_t m, int32_t d, uint64_t n, int n_cols, bool unit, bool has_scratch,

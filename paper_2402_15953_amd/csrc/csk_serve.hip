@@ -56,7 +56,9 @@ struct LiveQuery {
     cs_sketch *sk = nullptr;
     uint64_t bytes = 0;
     int inflight_estimates = 0;   // estimates handed to the estimate thread, not finished
-    hipEvent_t last_update = nullptr;
+    uint64_t pending = 0;         // submitted requests of this query not yet completed
+    hipEvent_t last_update = nullptr;  // recorded behind the query's latest update launch
+    int last_stream = -1;              // update stream of that launch (-1: none yet)
     bool has_update_event = false;
     bool removed = false;
 };
@@ -100,6 +102,13 @@ struct UpdDone {
     std::vector<cs_completion> done;
 };
 
+// One request of query qid completed (the caller holds S->mu).
+void query_request_done(cs_server *S, int32_t qid)
+{
+    auto it = S->queries.find(qid);
+    if (it != S->queries.end() && it->second.pending > 0) it->second.pending--;
+}
+
 void on_updates_done(void *p)
 {
     UpdDone *u = static_cast<UpdDone *>(p);
@@ -109,6 +118,7 @@ void on_updates_done(void *p)
         for (auto &c : u->done) {
             c.done_us = t;
             u->S->completions.push_back(c);
+            query_request_done(u->S, c.qid);
         }
         u->S->completed += u->done.size();
     }
@@ -190,6 +200,20 @@ void scheduler_loop(cs_server *S)
             }
             const int si = S->rr++ % (int)S->upd_streams.size();
             hipStream_t st = S->upd_streams[si];
+            // A query's updates run in submission order: an earlier launch of one of
+            // these queries on another update stream may still be running, so this
+            // launch waits for it.  The query's last-update event then covers every
+            // update of the query, and an estimate waiting on it sees all of them.
+            {
+                std::map<int32_t, bool> waited;  // queries already waited for
+                for (const Request &r : ups) {
+                    auto it = S->queries.find(r.qid);
+                    if (it == S->queries.end() || !it->second.has_update_event) continue;
+                    if (it->second.last_stream == si || waited[r.qid]) continue;  // same stream: ordered by it
+                    hipStreamWaitEvent(st, it->second.last_update, 0);
+                    waited[r.qid] = true;
+                }
+            }
             lk.unlock();
             cs_status rc = cs_batch_update(S->upd_batches[si], items.data(), (int32_t)items.size(), st);
             lk.lock();
@@ -205,6 +229,7 @@ void scheduler_loop(cs_server *S)
                 if (!it->second.last_update) hipEventCreateWithFlags(&it->second.last_update, hipEventDisableTiming);
                 hipEventRecord(it->second.last_update, st);
                 it->second.has_update_event = true;
+                it->second.last_stream = si;
             }
             hipLaunchHostFunc(st, on_updates_done, done);
         }
@@ -274,6 +299,7 @@ void estimate_loop(cs_server *S)
             S->completions.push_back(c);
             auto it = S->queries.find(jobs[i].req.qid);
             if (it != S->queries.end()) it->second.inflight_estimates--;
+            query_request_done(S, jobs[i].req.qid);
         }
         if (rc != CS_OK) S->last_error = cs_last_error();
         S->completed += jobs.size();
@@ -385,15 +411,33 @@ cs_status cs_server_remove_query(cs_server *S, int32_t qid)
 {
     if (!S) return fail(CS_EINVAL, "null server");
     std::unique_lock<std::mutex> lk(S->mu);
+    {
+        auto it = S->queries.find(qid);
+        if (it == S->queries.end()) return fail(CS_EINVAL, "unknown query");
+        if (it->second.removed) return fail(CS_EINVAL, "query is already being removed");
+        // later submissions of the query complete with CS_EINVAL without touching it
+        it->second.removed = true;
+    }
+    // wait for this query's own requests only (others keep flowing); the map entry
+    // stays until then, so it is looked up again after the wait
+    S->cv_done.wait(lk, [&] {
+        auto it = S->queries.find(qid);
+        return it == S->queries.end() || it->second.pending == 0;
+    });
     auto it = S->queries.find(qid);
     if (it == S->queries.end()) return fail(CS_EINVAL, "unknown query");
-    // wait until every submitted request has completed, then release the memory
-    S->cv_done.wait(lk, [&] { return S->completed >= S->submitted; });
-    hipDeviceSynchronize();
-    if (it->second.last_update) hipEventDestroy(it->second.last_update);
-    cs_destroy(it->second.sk);
-    S->used_bytes -= it->second.bytes;
+    LiveQuery q = it->second;
     S->queries.erase(it);
+    S->used_bytes -= q.bytes;
+    lk.unlock();
+    // every update of the query has passed its stream (its completion callback ran) and
+    // every estimate has returned; the event may still be queued behind them, so wait
+    // for it before releasing the counters
+    if (q.last_update) {
+        hipEventSynchronize(q.last_update);
+        hipEventDestroy(q.last_update);
+    }
+    cs_destroy(q.sk);
     return CS_OK;
 }
 
@@ -412,7 +456,8 @@ static cs_status submit(cs_server *S, Request r, uint64_t *ticket)
     std::lock_guard<std::mutex> lk(S->mu);
     auto qit = S->queries.find(r.qid);
     if (qit == S->queries.end()) return fail(CS_EINVAL, "unknown query");
-    if (r.kind == 0 && r.n > 0 && !qit->second.removed) {
+    if (qit->second.removed) return fail(CS_EINVAL, "query is being removed");
+    if (r.kind == 0 && r.n > 0) {
         const Handle &h = qit->second.sk->h;
         if (r.rel < 0 || r.rel >= h.g.n_rel) return fail(CS_EINVAL, "relation out of range");
         cs_status chk = check_device_array(r.keys, r.n * h.g.rel[r.rel].n_cols * sizeof(uint32_t), h.device, "keys");
@@ -426,6 +471,7 @@ static cs_status submit(cs_server *S, Request r, uint64_t *ticket)
     r.submit_us = now_us();
     S->queue.push_back(r);
     S->submitted++;
+    qit->second.pending++;
     if (ticket) *ticket = r.ticket;
     S->cv_sched.notify_one();
     return CS_OK;

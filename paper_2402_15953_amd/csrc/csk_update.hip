@@ -25,6 +25,7 @@
 #include <mutex>
 
 #include "csk_counters16.h"
+#include "csk_handle.h"
 #include "csk_hash.h"
 #include "csk_internal.h"
 
@@ -1059,6 +1060,8 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
         SegGeom sg = seg_geometry(a.m, a.d, narrow, a.scratch_bytes, a.n);
         sg.chunks = chunks_for(sg.chunks, narrow ? 4 : 8);
         const uint64_t chunk = (a.n + sg.chunks - 1) / sg.chunks;
+        // every kernel below writes whole partial-sum planes: refuse a buffer they overrun
+        auto fits = [&](int32_t chunks, size_t elem) { return (uint64_t)chunks * cells * elem <= a.scratch_bytes; };
         dim3 grid((unsigned)sg.chunks, (unsigned)sg.segments);
         const size_t lds = (size_t)sg.R * (narrow ? 4 : 8);
         int log2m = 0;
@@ -1081,6 +1084,7 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
             // 16-bit LDS counters: a whole repetition per workgroup
             SegGeom g16 = seg16_geometry(a.m, a.d, a.scratch_bytes, a.n);
             g16.chunks = chunks_for(g16.chunks, 2);
+            if (!fits(g16.chunks, 2)) return fail(CS_EINVAL, "update scratch buffer too small for d * m 16-bit partial sums");
             dim3 grid16((unsigned)g16.chunks, (unsigned)g16.segments);
             if (g16.R > 2u * kSeg16Words) return fail(CS_EINVAL, "16-bit segment exceeds its LDS array");
             uint32_t *part = reinterpret_cast<uint32_t *>(a.scratch);
@@ -1121,6 +1125,8 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
             if constexpr (NC <= 2) {
                 SegGeom gc = seg16_geometry(a.m, a.d, a.scratch_bytes, a.n);
                 gc.chunks = chunks_for(gc.chunks, 2);
+                if (!fits(gc.chunks, 2))
+                    return fail(CS_EINVAL, "update scratch buffer too small for d * m 16-bit partial sums");
                 if (gc.R != (1u << 16) || (uint64_t)gc.segments * gc.R != cells)
                     return fail(CS_EINVAL, "16-bit range geometry");
                 const uint64_t chunkc = (a.n + gc.chunks - 1) / gc.chunks;
@@ -1139,6 +1145,7 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
             }
         } else if (narrow && e1 && sg.R < a.m && NC <= 2 && a.compact) {
             // bucket-range segments: compacting kernel (queue after the counters in LDS)
+            if (!fits(sg.chunks, 4)) return fail(CS_EINVAL, "update scratch buffer too small for d * m int32 partial sums");
             int32_t *part = reinterpret_cast<int32_t *>(a.scratch);
             const size_t lds_c = (size_t)sg.R * 4 + (size_t)(kSegBlock / 64) * (NC + 1) * kQCap * 4;
             CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_update_seg_compact<NC>),
@@ -1152,6 +1159,7 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
                                dim3(256), 0, s, reinterpret_cast<const int32_t *>(a.scratch), sg.chunks, cells,
                                a.sketch);
         } else if (narrow) {
+            if (!fits(sg.chunks, 4)) return fail(CS_EINVAL, "update scratch buffer too small for d * m int32 partial sums");
             int32_t *part = reinterpret_cast<int32_t *>(a.scratch);
             st = e1 ? launch(&k_update_seg<NC, int32_t, true>, part) : launch(&k_update_seg<NC, int32_t, false>, part);
             if (st != CS_OK) return st;
@@ -1159,6 +1167,7 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
                                dim3(256), 0, s, reinterpret_cast<const int32_t *>(a.scratch), sg.chunks, cells,
                                a.sketch);
         } else {
+            if (!fits(sg.chunks, 8)) return fail(CS_EINVAL, "update scratch buffer too small for d * m int64 partial sums");
             int64_t *part = reinterpret_cast<int64_t *>(a.scratch);
             st = e1 ? launch(&k_update_seg<NC, int64_t, true>, part) : launch(&k_update_seg<NC, int64_t, false>, part);
             if (st != CS_OK) return st;
@@ -1290,10 +1299,13 @@ size_t seg_scratch_bytes(uint32_t m, int32_t d)
         const SegGeom g16 = seg16_geometry(m, d, (size_t)-1);
         best = std::max<size_t>(best, (size_t)g16.chunks * cells * 2);
     }
-    // the partition strategy's chunk of kPartMaxChunk tuples
-    const PartGeom pg = part_geometry(m, d, (size_t)-1);
-    const uint64_t tiles = kPartMaxChunk / kPartTile;
-    best = std::max<size_t>(best, (size_t)(tiles * kPartTile * d * 4 + tiles * d * (pg.ranges + 1) * 4));
+    // the partition strategy's chunk of kPartMaxChunk tuples where it is the automatic
+    // choice (m > 2^16); below, it runs in whatever chunks the buffer holds
+    if (m > (1u << 16)) {
+        const PartGeom pg = part_geometry(m, d, (size_t)-1);
+        const uint64_t tiles = kPartMaxChunk / kPartTile;
+        best = std::max<size_t>(best, (size_t)(tiles * kPartTile * d * 4 + tiles * d * (pg.ranges + 1) * 4));
+    }
     return best;
 }
 
@@ -1322,8 +1334,9 @@ int auto_update_strategy(uint32_t m, int32_t d, uint64_t n, int n_cols, bool uni
 
 namespace {
 
-// One scratch buffer per device, shared by every handle's segmented / partition
-// updates.  Reuse is stream-ordered: each user waits for the previous user's event.
+// One scratch buffer per device for callers without a buffer of their own (per-attribute
+// sketches, the autotuner).  Reuse is stream-ordered while consecutive users share a
+// stream; a user on another stream first drains the device.
 struct ScratchPool {
     std::mutex mu;
     void *buf = nullptr;
@@ -1380,13 +1393,16 @@ cs_status launch_update(const UpdateArgs &a_in, int strategy, int grid_blocks, h
         }
     }
     if (strategy != CS_UPDATE_LDS_PRIVATE && strategy != CS_UPDATE_PARTITION) return dispatch_nc(a, strategy, grid_blocks, s);
+    // A caller-owned scratch buffer (a handle's, allocated with it; or the static one of
+    // the allocation-free entry point): its uses are ordered like the caller's updates.
+    if (a.scratch) return dispatch_nc(a, strategy, grid_blocks, s);
     ScratchPool &P = pool_of(dev);
     std::lock_guard<std::mutex> lk(P.mu);
     const size_t need = seg_scratch_bytes(a.m, a.d);
     if (P.bytes < need) {
-        // grows to the largest (m, d) seen; the only allocation on the update path
+        // grows to the largest (m, d) seen by callers without a buffer of their own
         CSK_HIP(hipDeviceSynchronize());
-        if (P.buf) hipFree(P.buf);
+        if (P.buf) (void)hipFree(P.buf);
         P.buf = nullptr;
         P.bytes = 0;
         if (hipMalloc(&P.buf, need) != hipSuccess) return fail(CS_ENOMEM, "update scratch allocation failed");
@@ -1406,3 +1422,68 @@ cs_status launch_update(const UpdateArgs &a_in, int strategy, int grid_blocks, h
 }
 
 }  // namespace csk
+
+// ---------------------------------------------------------------- allocation-free update
+//
+// For callers that cannot allocate device memory while they run (code under graph
+// capture, tight serving loops): the update's scratch buffer is this file-scope device
+// array instead of the handle's.  Every GPU the library runs on holds one copy, at its
+// own address, until the process ends.  In host code `scratch` names a host-side
+// stand-in, not device memory: its device address is taken once per device with
+// hipGetSymbolAddress and only that address is ever handed to kernels.
+
+constexpr size_t kStaticScratchBytes = 64ull << 20;  // 64 MiB
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace csk {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be the current device.
+cs_status static_scratch(int device, void **out)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(CS_EINVAL, "device id beyond the static scratch table");
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(CS_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_static_ptr[device] = p;
+    }
+    *out = g_static_ptr[device];
+    return CS_OK;
+}
+
+}  // namespace
+}  // namespace csk
+
+extern "C" {
+
+size_t cs_update_noalloc_scratch_bytes(void) { return kStaticScratchBytes; }
+
+cs_status cs_update_noalloc(cs_sketch *hs, int32_t rel, const uint32_t *keys, const int64_t *weights, uint64_t n,
+                            int32_t flags, void *stream)
+{
+    using namespace csk;
+    UpdateArgs a;
+    cs_status st = update_args(hs, rel, keys, weights, n, flags & CS_UPDATE_UNIT_WEIGHTS, &a);
+    if (st != CS_OK || n == 0) return st;
+    int dev = -1;
+    CSK_HIP(hipGetDevice(&dev));
+    if (dev != hs->h.device) return fail(CS_EINVAL, "the handle's device must be the current device");
+    void *p = nullptr;
+    st = static_scratch(dev, &p);
+    if (st != CS_OK) return st;
+    a.scratch = p;
+    a.scratch_bytes = kStaticScratchBytes;
+    // the kernels fully write every partial sum and record they later read, so nothing
+    // left in the array by an earlier call is ever read; a geometry the array cannot hold
+    // is refused inside the launcher (CS_EINVAL) before anything is enqueued
+    return launch_update(a, CS_UPDATE_AUTO, 0, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

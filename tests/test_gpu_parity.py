@@ -412,3 +412,31 @@ def test_estimate_is_deterministic():
     a = sk.estimate(reps=True)
     b = sk.estimate(reps=True)
     assert a == b
+
+
+def test_inner_product_beyond_int128_is_flagged():
+    """The two-relation plan sums int64 products in 128-bit integers: when the sum of
+    |products| may reach 2^127 the repetition is returned as an fp64 value flagged
+    inexact (within 1e-12 of the exact sum), never as a wrapped integer.  Weights of
+    1.5 * 2^62 on 13 keys over 4 buckets drive two repetitions past 2^127 (values
+    computed exactly by the oracle in Python integers)."""
+    graph, m, d, seed = W.single_join(), 4, 9, 3
+    keys = (np.arange(13, dtype=np.uint32) * 7919).reshape(-1, 1)
+    w = np.full(13, 2 ** 62 + 2 ** 61, dtype=np.int64)
+    info, co, ref = oracle_sketches(graph, [keys, keys], [w, w], m, d, seed)
+    sk = _run_gpu(graph, [keys, keys], [w, w], m, d, seed)
+    est = sk.estimate(reps=True)
+    reps = [oracle.estimate_alg3(info, [ref[0][t], ref[1][t]], m, method="ntt") for t in range(d)]
+    assert sum(x >= 2 ** 127 for x in reps) >= 1
+    flagged = 0
+    for t, x in enumerate(reps):
+        if est["rep_ints"][t] is not None:
+            assert est["rep_ints"][t] == x and x < 2 ** 127, (t, x)
+        else:
+            flagged += 1
+            assert x >= 2 ** 125
+            assert abs(est["rep_values"][t] - x) <= 1e-12 * abs(x), (t, est["rep_values"][t], x)
+    assert flagged >= sum(x >= 2 ** 127 for x in reps)
+    med = oracle.median_lower(reps)
+    assert abs(est["value"] - med) <= 1e-12 * abs(med)
+    sk.close()

@@ -144,3 +144,61 @@ def test_queue_limit():
     sk = srv.sketch(q)
     assert int(np.abs(sk.read_sketch(0)).sum(axis=1)[0]) == n_ok * (1 << 20)
     srv.close()
+
+
+def test_update_order_across_streams():
+    """A query updated by a large batch on one update stream and then by a tiny batch on
+    another: its next estimate must include both (the second launch waits for the first)."""
+    g = W.chain(3)
+    m, d = 1 << 16, 9
+    big_n, tiny_n = 1 << 23, 17
+    keys = [to_device_keys(keys_u32(W.relation_keys(g, k, big_n, "zipf", config=760, s=1.1, D=10 ** 6)))
+            for k in range(g.n_rel)]
+    srv = csk.Server(n_streams=2, max_batch_items=1)
+    q = srv.add_query(g, m, d, 11)
+    alone = csk.Sketch(g, m, d, 11)
+    for rnd in range(2):
+        for k in range(g.n_rel):
+            srv.submit_update(q, k, keys[k])                   # one epoch, stream A
+            srv.submit_update(q, k, keys[k][:tiny_n])          # next epoch, stream B
+            alone.update(k, keys[k])
+            alone.update(k, keys[k][:tiny_n])
+        t = srv.submit_estimate(q)
+        srv.drain()
+        comps = {c["ticket"]: c for c in srv.poll(1000)}
+        assert comps[t]["status"] == 0
+        assert comps[t]["estimate"] == alone.estimate(), rnd
+    for k in range(g.n_rel):
+        assert np.array_equal(srv.sketch(q).read_sketch(k), alone.read_sketch(k)), k
+    alone.close()
+    srv.close()
+
+
+def test_remove_query_while_others_flow():
+    """Removing one query waits only for its own requests; later submissions for it are
+    refused; the other query's estimates still equal the same query computed alone."""
+    g = W.chain(3)
+    n = 1 << 16
+    keys = [to_device_keys(keys_u32(W.relation_keys(g, k, n, "zipf", config=761, s=1.1, D=10 ** 5)))
+            for k in range(g.n_rel)]
+    srv = csk.Server(n_streams=2, max_batch_items=4)
+    a = srv.add_query(g, 1 << 12, 5, 1)
+    b = srv.add_query(g, 1 << 12, 5, 2)
+    alone = csk.Sketch(g, 1 << 12, 5, 2)
+    for k in range(g.n_rel):
+        srv.submit_update(a, k, keys[k])
+        srv.submit_update(b, k, keys[k])
+        alone.update(k, keys[k])
+    srv.remove_query(a)
+    with pytest.raises(csk.CsError) as e:
+        srv.submit_update(a, 0, keys[0])
+    assert e.value.status == csk.CS_EINVAL
+    with pytest.raises(csk.CsError):
+        srv.remove_query(a)
+    t = srv.submit_estimate(b)
+    srv.drain()
+    comps = {c["ticket"]: c for c in srv.poll(1000)}
+    assert comps[t]["status"] == 0 and comps[t]["estimate"] == alone.estimate()
+    assert srv.stats()["live_queries"] == 1
+    alone.close()
+    srv.close()

@@ -281,6 +281,53 @@ def test_alg3_modular_equals_direct_any_m(m):
         assert oracle.estimate_alg3(info, c, m, method="ntt") == oracle.estimate_alg3(info, c, m, method="direct")
 
 
+@pytest.mark.parametrize("graph", [W.single_join(), W.chain(3), W.chain(4), W.star(4), W.fig3_query(),
+                                   W.multiway_star(3), W.chain(5)])
+@pytest.mark.parametrize("m", [1, 2, 3, 5, 6, 8])
+def test_sparse_alg3_equals_eq5_all_roots(graph, m):
+    """The sparse exact evaluation against Eq. 5 by enumeration, with zeros planted in the
+    counters (the ring skips them), for every root."""
+    info = oracle.analyze(graph)
+    c = _random_sketches(info, m, seed=m * 11 + info.n_rel)
+    for k, v in enumerate(c):
+        v[(k + np.arange(m)) % 3 == 0] = 0
+    ref = oracle.estimate_eq5(info, c, m)
+    for root in range(info.n_attr):
+        assert oracle.estimate_sparse(info, c, m, root=root) == ref
+
+
+@pytest.mark.parametrize("m", [97, 1 << 10, 1000])
+def test_sparse_alg3_equals_dense_on_sparse_sketches(m):
+    """Sketches of few tuples at larger m (the regime the sparse ring serves): equal to the
+    dense modular route (NTT for powers of two, Def. 3.1 term by term otherwise), with
+    values near 2^62 that need several primes there."""
+    for graph in (W.chain(3), W.chain(5), W.star(4), W.fig3_query()):
+        info = oracle.analyze(graph)
+        rng = np.random.default_rng(m + info.n_rel)
+        c = []
+        for _ in range(info.n_rel):
+            v = np.zeros(m, dtype=np.int64)
+            idx = rng.choice(m, size=min(m, 40), replace=False)
+            v[idx] = rng.integers(-2 ** 62, 2 ** 62, size=len(idx))
+            c.append(v)
+        assert oracle.estimate_sparse(info, c, m) == oracle.estimate_alg3(info, c, m, method="ntt")
+
+
+def test_sparse_reversed_correlation_is_detected():
+    """Planted mistake in the sparse ring (operands of Def. 3.1 swapped): Eq. 5 catches it."""
+
+    class Reversed(oracle._SparseRing):
+        def correlate(self, a, x):
+            return super().correlate(x, a)
+
+    info = oracle.analyze(W.chain(3))
+    m = 7
+    c = _random_sketches(info, m, seed=5)
+    ref = oracle.estimate_eq5(info, c, m)
+    ring = Reversed(m)
+    assert ring.total(oracle._combine_sketches(0, set(), info, c, ring)) != ref
+
+
 def test_fig3_closed_form():
     info = oracle.analyze(W.fig3_query())
     for m in (3, 5, 8):
