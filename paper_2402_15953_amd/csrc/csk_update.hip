@@ -1220,7 +1220,7 @@ constexpr uint64_t kSegTuplesPerChunk = 32768;
 
 int32_t chunks_for_n(int32_t C, uint64_t n)
 {
-    const uint64_t by_n = (n + kSegTuplesPerChunk - 1) / kSegTuplesPerChunk;
+    const uint64_t by_n = n / kSegTuplesPerChunk + (n % kSegTuplesPerChunk != 0);  // no wrap at n = 2^64 - 1
     return (int32_t)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)C, by_n));
 }
 
