@@ -1300,10 +1300,10 @@ size_t seg_scratch_bytes(uint32_t m, int32_t d)
         best = std::max<size_t>(best, (size_t)g16.chunks * cells * 2);
     }
     // the partition strategy's chunk of kPartMaxChunk tuples where it is the automatic
-    // choice (m > 2^16); below, it runs in whatever chunks the buffer holds
-    if (m > (1u << 16)) {
+    // choice (m > 2^16); below, chunks of 32 tiles (it runs there only when asked for)
+    {
         const PartGeom pg = part_geometry(m, d, (size_t)-1);
-        const uint64_t tiles = kPartMaxChunk / kPartTile;
+        const uint64_t tiles = m > (1u << 16) ? kPartMaxChunk / kPartTile : 32;
         best = std::max<size_t>(best, (size_t)(tiles * kPartTile * d * 4 + tiles * d * (pg.ranges + 1) * 4));
     }
     return best;
