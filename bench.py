@@ -1,21 +1,28 @@
 """Benchmark of the sketch update + estimate hot path on one MI355X.
 
-Workload (the metric's configuration): a 3-relation chain R1(A) - R2(A, B) - R3(B),
-10^7 tuples per relation, uint32 keys Zipf(s = 1.1) over a domain of 10^6 per
-attribute, m = 2^16 buckets, d = 9 repetitions, int64 counters, weights +1.  Keys are
-generated on the GPU and resident in HBM before timing.
+Headline workload (the largest single-GPU configuration of the metric): a 5-relation
+chain R1(A) - R2(A, B) - R3(B, C) - R4(C, D) - R5(D), each relation streamed as 96 calls
+of 2^20 tuples (100,663,296 tuples per relation), uint32 keys Zipf(s) over a domain of
+10^7 per attribute for s in {0.5, 1.0, 1.5}, m = 2^18 buckets, d = 15 repetitions,
+int64 counters, weights +1.  Keys are generated on the GPU and resident in HBM (9.7 GB)
+before timing.
 
-One step = the whole plain hot path over one batch: zero the counters, stream every
-relation's tuples into its d x m sketches (one update launch per relation), then the
-estimate (fp64 FFT spectral product-reduce, exactness step, median over d).
+One step = the whole plain hot path over one batch: for each of the three exponents,
+zero that query's counters, stream every relation's tuples into its d x m sketches
+(480 update calls), then the estimate (fp64 FFT spectral product-reduce, exactness
+step, median over d).
 
 Printed: one JSON line.  `value` is tuple updates per second over whole steps.
-`roofline` describes the dominant kernel (the hashing kernel of the two-column
-relation), timed inside the timed steps with HIP events the library records around it
-on the stream it runs on (events without the system-scope fence, so recording them
-flushes no caches).  The per-relation update and estimate times come from a few
-diagnostic steps after the timed ones.  `cpu_baseline` is the CPU oracle on a bounded
-prefix of the same input, on this host.
+`roofline` describes the dominant kernel (the hashing pass of a two-column relation's
+update), timed inside the timed steps with HIP events the library records around it on
+the stream it runs on (events without the system-scope fence, so recording them flushes
+no caches), against the Horner-step peak; the same run measures that peak and the HBM
+stream-read rate with the library's probe kernels (`k0`).  Per-relation update and
+estimate times come from a diagnostic step after the timed ones.  Sections: the
+3-relation chain (10^7 tuples per relation, m = 2^16, d = 9), the single join (10^5
+tuples, m = 1024, d = 5), filtered ingestion, the paper's m = 10^6, the AMS baseline,
+per-attribute sketches, 4096 batched queries, the serving loop.  `cpu_baseline` is the
+CPU oracle on a bounded prefix of the headline input, on this host's cores.
 """
 from __future__ import annotations
 
@@ -35,29 +42,28 @@ HBM_PEAK_GBS = 8000.0
 # issues 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 VALU lane-instructions/s, and
 # the shortest step is 7 full-rate VALU instructions (2 v_mad_u64_u32, one move for the
 # 64-bit addend, a 64-bit shift, an and, a 64-bit add of a and one 64-bit add folding
-# the low 61 bits), so 5.62e12 steps/s.  A kernel made of nothing but independent
-# steps reaches 5.32e12 steps/s on the chip.
+# the low 61 bits), so 5.62e12 steps/s.  The probe kernel of independent steps
+# (cs_k0_horner) measures what the chip sustains in the same run.
 ALU_STEP_PEAK = 256 * 4 * 16 * 2.4e9 / 7.0
+SECTIONS = ("chain5", "chain3", "single", "k0", "filtered", "anym", "ams", "attr", "batched", "serving", "cpu")
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=10 ** 7, help="tuples per relation")
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--sections", type=str, default=",".join(SECTIONS),
+                    help="comma-separated subset of " + ",".join(SECTIONS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-tuples", type=int, default=1 << 22, help="oracle sample per relation")
+    ap.add_argument("--cpu-slices", type=int, default=8,
+                    help="CPU baseline: 2^20-tuple slices per relation for the threaded oracle")
     ap.add_argument("--strategy", type=int, default=0)
-    ap.add_argument("--no-filtered", dest="filtered", action="store_false",
-                    help="skip the filtered-ingestion section")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a device copy of this many bytes (counter calibration) and exit")
     ap.add_argument("--batch-queries", type=int, default=4096,
                     help="batched section: chain/star queries (0 skips the section)")
     ap.add_argument("--serve-queries", type=int, default=256, help="serving section: live queries (0 skips)")
-    ap.add_argument("--no-ams", dest="ams", action="store_false",
-                    help="skip the AMS-baseline section (stream throughput at equal memory)")
     ap.add_argument("--anym", type=str, default="1000000,1048576",
                     help="bucket-count section: chain-3 steps at these m with d = 5 (empty skips)")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="serving section: seconds per load level")
@@ -66,7 +72,11 @@ def parse():
     return ap.parse_args()
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "update_seg16_chain3_1e7_m65536_d9_traffic.md")
+TRAFFIC_PROFILES = {
+    # dominant kernel -> committed FETCH_SIZE / WRITE_SIZE summary
+    "chain5": os.path.join(ROOT, "profiles", "part_hash_chain5_2p20_m262144_d15_traffic.md"),
+    "chain3": os.path.join(ROOT, "profiles", "update_seg16_chain3_1e7_m65536_d9_traffic.md"),
+}
 KERNEL_SOURCES = ["csk_update.hip", "csk_hash.h", "csk_counters16.h", "csk_internal.h"]
 
 
@@ -79,15 +89,16 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(strategy: int):
+def measured_traffic(which: str, strategy: int):
     """HBM bytes per launch of the dominant kernel from the committed FETCH_SIZE and
     WRITE_SIZE counter summary (scaled by a copy kernel of known size), or None when the
     summary is missing, was taken for another strategy, or the kernel sources changed
     since the counters were taken."""
-    if strategy != 0 or not os.path.exists(TRAFFIC_PROFILE):
+    path = TRAFFIC_PROFILES.get(which)
+    if strategy != 0 or not path or not os.path.exists(path):
         return None
     fields = {}
-    with open(TRAFFIC_PROFILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and line.startswith("- "):
                 k, v = line[2:].split(":", 1)
@@ -127,77 +138,72 @@ def progress(msg: str):
     print("bench: " + msg, file=sys.stderr, flush=True)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus %d is not supported" % args.gpus}))
-        print("bench.py runs on exactly one GPU (there is no multi-GPU path)", file=sys.stderr)
-        sys.exit(2)
-    if args.copy_probe > 0:
-        copy_probe(args.copy_probe)
-        return
+def median(xs):
+    s = sorted(xs)
+    return s[len(s) // 2]
 
-    import numpy as np
+
+def bench_chain5(args, dev, stream):
+    """The headline: 5-chain, 96 calls of 2^20 tuples per relation, m = 2^18, d = 15, for
+    each of Zipf s in {0.5, 1.0, 1.5} (one query handle per exponent)."""
     import torch
 
     import paper_2402_15953_amd as csk
     import workloads as W
 
-    torch.cuda.set_device(0)
-    dev = torch.device("cuda", 0)
-    graph = W.chain(3)
-    m, d, seed, n = 1 << 16, 9, 7, args.n
-    s, D, config = 1.1, 10 ** 6, 2
-
-    # ---- inputs resident in HBM (generated on the GPU, outside any timed region)
-    keys = []
-    for k in range(graph.n_rel):
-        kk = W.relation_keys(graph, k, n, "zipf", config=config, s=s, D=D, device=dev)
-        keys.append(kk.to(torch.int32).contiguous())
+    graph = W.chain(5)
+    m, d, seed, D, config = 1 << 18, 15, 8, 10 ** 7, 3
+    n_call, calls = 1 << 20, 96
+    n = n_call * calls
+    exps = (0.5, 1.0, 1.5)
+    r = graph.n_rel
+    keys = {}
+    for sx in exps:
+        keys[sx] = [W.relation_keys(graph, k, n, "zipf", config=config, s=sx, D=D, device=dev)
+                    .to(torch.int32).contiguous() for k in range(r)]
     torch.cuda.synchronize()
-
-    stream = torch.cuda.Stream()
+    progress("chain5 keys resident (%.1f GB)" % (sum(x.numel() * 4 for v in keys.values() for x in v) / 1e9))
     t0 = time.perf_counter()
-    sk = csk.Sketch(graph, m, d, seed)
-    init_ms = (time.perf_counter() - t0) * 1e3
-
-    n_rel = graph.n_rel
-    ev = {k: [] for k in range(n_rel)}
-    kev = {k: [] for k in range(n_rel)}   # around the hashing kernel alone (cs_update_timed)
-    est_ev = []
-
-    # timing events, made before the timed region (recording one costs no cache flush)
-    n_diag = 3
-    timers = iter([csk.Timer() for _ in range(args.steps * 2 * n_rel + n_diag * (n_rel + 2))])
+    sks = {sx: csk.Sketch(graph, m, d, seed) for sx in exps}
+    init_ms = (time.perf_counter() - t0) * 1e3 / len(exps)
+    sampled_calls = (0, 31, 63, 95)
+    kev = {k: [] for k in range(r)}
+    n_timers = args.steps * len(exps) * r * len(sampled_calls) * 2 + len(exps) * (r + 2) + 8
+    timers = iter([csk.Timer() for _ in range(n_timers)])
+    diag = {}
 
     def step(mode):
-        """mode 0: untimed; 1: timed step, the library records a pair around each hashing
-        kernel; 2: diagnostic step (after the timed region), marks where each relation's
-        update starts and around the estimate."""
-        sk.reset(stream=stream)
-        marks = []
-        for k in range(n_rel):
-            if mode == 1:
-                ka, kb = next(timers), next(timers)
-                sk.update(k, keys[k], None, stream=stream, strategy=args.strategy, timing=(ka, kb))
-                kev[k].append((ka, kb))
-                continue
+        """mode 0: untimed; 1: timed, the library records a pair around the hashing
+        kernel of sampled calls; 2: diagnostic, marks at each relation's start and
+        around the estimate."""
+        out = {}
+        for sx in exps:
+            sk = sks[sx]
+            ks = keys[sx]
+            sk.reset(stream=stream)
+            marks = []
+            for k in range(r):
+                if mode == 2:
+                    a_ = next(timers)
+                    a_.record(stream)
+                    marks.append(a_)
+                for c in range(calls):
+                    part = ks[k][c * n_call:(c + 1) * n_call]
+                    if mode == 1 and c in sampled_calls:
+                        ka, kb = next(timers), next(timers)
+                        sk.update(k, part, None, stream=stream, strategy=args.strategy, timing=(ka, kb))
+                        kev[k].append((ka, kb))
+                    else:
+                        sk.update(k, part, None, stream=stream, strategy=args.strategy)
             if mode == 2:
-                a = next(timers)
-                a.record(stream)
-                marks.append(a)
-            sk.update(k, keys[k], None, stream=stream, strategy=args.strategy)
-        if mode == 2:
-            a, b = next(timers), next(timers)
-            a.record(stream)
-            marks.append(a)
-            for k in range(n_rel):
-                ev[k].append((marks[k], marks[k + 1]))
-        res = sk.estimate(stream=stream)
-        if mode == 2:
-            b.record(stream)
-            est_ev.append((a, b))
-        return res
+                a_, b_ = next(timers), next(timers)
+                a_.record(stream)
+                marks.append(a_)
+            out[sx] = sk.estimate(stream=stream)
+            if mode == 2:
+                b_.record(stream)
+                diag[sx] = (marks, b_)
+        return out
 
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
@@ -208,13 +214,125 @@ def main():
             res = step(1)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
+        step(2)
+        torch.cuda.synchronize()
+
+    tuples_per_step = n * r * len(exps)
+    value = tuples_per_step * args.steps / elapsed
+    kern_ms = {k: sum(a_.elapsed_ms(b_) for a_, b_ in kev[k]) / len(kev[k]) for k in range(r)}
+    upd_ms = {}   # per exponent and relation: the 96 calls, both passes
+    est_ms = {}
+    for sx in exps:
+        marks, b_ = diag[sx]
+        upd_ms[str(sx)] = {str(k): marks[k].elapsed_ms(marks[k + 1]) for k in range(r)}
+        est_ms[str(sx)] = marks[r].elapsed_ms(b_)
+    kdom = max(kern_ms, key=kern_ms.get)
+    a_dom = len(graph.columns(kdom))
+    steps_dom = n_call * horner_steps_per_tuple(graph, kdom, d)
+    bytes_dom = n_call * 4 * a_dom
+    dur_s = kern_ms[kdom] / 1e3
+    alu_achieved = steps_dom / dur_s
+    hbm_achieved = bytes_dom / dur_s / 1e9
+    steps_all = sum(n * horner_steps_per_tuple(graph, k, d) for k in range(r))
+    upd_all_ms = {sx: sum(v.values()) for sx, v in upd_ms.items()}
+    est_bytes = r * d * m * 8
+    est_mean = sum(est_ms.values()) / len(est_ms)
+    out = {
+        "value": value, "ms_per_step": elapsed * 1e3 / args.steps, "tuples_per_step": tuples_per_step,
+        "config": {"workload": "chain5 R1(A)-R2(A,B)-R3(B,C)-R4(C,D)-R5(D), 96 update calls of 2^20 tuples per "
+                               "relation, Zipf s in {0.5, 1.0, 1.5} over 1e7, m=2^18, d=15, weights +1 (NULL); "
+                               "one step = all three exponents' streams and estimates",
+                   "relations": r, "tuples_per_relation": n, "calls_per_relation": calls, "tuples_per_call": n_call,
+                   "m": m, "d": d, "zipf_s": list(exps), "domain": D, "sketch_seed": seed,
+                   "data_seed_base": W.DATA_SEED_BASE},
+        "roofline": {"bound": "alu", "achieved": alu_achieved / 1e12, "peak": ALU_STEP_PEAK / 1e12,
+                     "unit": "T Horner-steps/s", "frac": alu_achieved / ALU_STEP_PEAK,
+                     "traffic": measured_traffic("chain5", args.strategy),
+                     "kernel": f"hashing pass (k_part_hash) of relation {kdom}'s update ({a_dom} key columns), "
+                               f"one launch per 2^20-tuple call",
+                     "kernel_ms": kern_ms[kdom], "algorithmic_steps": steps_dom, "algorithmic_bytes": bytes_dom,
+                     "hbm_GBps": hbm_achieved, "hbm_frac": hbm_achieved / HBM_PEAK_GBS},
+        "hash_kernel_ms_per_call": {str(k): v for k, v in kern_ms.items()},
+        "update_ms_per_relation": upd_ms,
+        "update_step_frac": {sx: steps_all / (v / 1e3) / ALU_STEP_PEAK for sx, v in upd_all_ms.items()},
+        "update_tuples_per_s": {sx: n * r / (v / 1e3) for sx, v in upd_all_ms.items()},
+        "estimate_ms": est_ms,
+        "estimates_per_s": 1e3 / est_mean,
+        "estimate_roofline": {"bound": "hbm", "algorithmic_bytes": est_bytes,
+                              "achieved_GBps": est_bytes / (est_mean / 1e3) / 1e9,
+                              "frac": est_bytes / (est_mean / 1e3) / 1e9 / HBM_PEAK_GBS},
+        "init_ms": init_ms,
+        "estimates": {str(sx): {"value": v["value"], "exact": v["exact"], "n_modular": v["n_modular"]}
+                      for sx, v in res.items()},
+    }
+    for sk in sks.values():
+        sk.close()
+    host0 = [keys[1.0][k][:n_call * args.cpu_slices].cpu() for k in range(r)]
+    probe_buf = keys[1.0][1]
+    return out, host0, probe_buf, keys
+
+
+def bench_chain3(args, dev, stream):
+    """The 3-relation chain: 10^7 tuples per relation, Zipf(1.1) over 10^6, m = 2^16, d = 9."""
+    import torch
+
+    import paper_2402_15953_amd as csk
+    import workloads as W
+
+    graph = W.chain(3)
+    m, d, seed, n = 1 << 16, 9, 7, 10 ** 7
+    s, D, config = 1.1, 10 ** 6, 2
+    keys = [W.relation_keys(graph, k, n, "zipf", config=config, s=s, D=D, device=dev).to(torch.int32).contiguous()
+            for k in range(graph.n_rel)]
+    torch.cuda.synchronize()
+    sk = csk.Sketch(graph, m, d, seed)
+    n_rel = graph.n_rel
+    ev = {k: [] for k in range(n_rel)}
+    kev = {k: [] for k in range(n_rel)}
+    est_ev = []
+    n_diag = 3
+    timers = iter([csk.Timer() for _ in range(args.steps * 2 * n_rel + n_diag * (n_rel + 2))])
+
+    def step(mode):
+        sk.reset(stream=stream)
+        marks = []
+        for k in range(n_rel):
+            if mode == 1:
+                ka, kb = next(timers), next(timers)
+                sk.update(k, keys[k], None, stream=stream, strategy=args.strategy, timing=(ka, kb))
+                kev[k].append((ka, kb))
+                continue
+            if mode == 2:
+                a_ = next(timers)
+                a_.record(stream)
+                marks.append(a_)
+            sk.update(k, keys[k], None, stream=stream, strategy=args.strategy)
+        if mode == 2:
+            a_, b_ = next(timers), next(timers)
+            a_.record(stream)
+            marks.append(a_)
+            for k in range(n_rel):
+                ev[k].append((marks[k], marks[k + 1]))
+        res_ = sk.estimate(stream=stream)
+        if mode == 2:
+            b_.record(stream)
+            est_ev.append((a_, b_))
+        return res_
+
+    with torch.cuda.stream(stream):
+        for _ in range(max(1, args.warmup)):
+            step(0)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for _ in range(args.steps):
+            res = step(1)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
         for _ in range(n_diag):
             step(2)
         torch.cuda.synchronize()
-
     # the same steps with the estimate published by the device (cs_estimate_async into
-    # pinned memory, no host round trip per step); every step's result is checked after
-    # the timed region against the synchronous estimate of the same counters
+    # pinned memory, no host round trip per step), checked against the synchronous one
     pinned = [torch.zeros(csk.ESTIMATE_BYTES, dtype=torch.uint8, pin_memory=True) for _ in range(args.steps)]
     with torch.cuda.stream(stream):
         torch.cuda.synchronize()
@@ -227,124 +345,209 @@ def main():
         torch.cuda.synchronize()
         elapsed_p = time.perf_counter() - t_p
     pub = [csk.read_estimate(b) for b in pinned]
-    pipelined = {"tuples_per_s": n * n_rel * args.steps / elapsed_p, "ms_per_step": elapsed_p * 1e3 / args.steps,
-                 "identical_estimates": all(e["value"] == res["value"] and e["exact"] == res["exact"]
-                                            and e["value_i64"] == res["value_i64"] for e in pub)}
-
-    ms_per_step = elapsed * 1e3 / args.steps
-    tuples_per_step = n * n_rel
-    value = tuples_per_step * args.steps / elapsed
-    upd_ms = {k: sum(a.elapsed_ms(b) for a, b in ev[k]) / len(ev[k]) for k in range(n_rel)}
-    est_ms = sum(a.elapsed_ms(b) for a, b in est_ev) / len(est_ev)
-    upd_total_ms = sum(upd_ms.values())
-
-    kern_ms = {k: sum(a.elapsed_ms(b) for a, b in kev[k]) / len(kev[k]) for k in range(n_rel)}
-
-    # dominant kernel: the slowest hashing kernel (one launch per relation and step)
+    kern_ms = {k: sum(a_.elapsed_ms(b_) for a_, b_ in kev[k]) / len(kev[k]) for k in range(n_rel)}
+    upd_ms = {k: sum(a_.elapsed_ms(b_) for a_, b_ in ev[k]) / len(ev[k]) for k in range(n_rel)}
+    est_ms = sum(a_.elapsed_ms(b_) for a_, b_ in est_ev) / len(est_ev)
     kdom = max(kern_ms, key=kern_ms.get)
     a_dom = len(graph.columns(kdom))
-    bytes_dom = n * 4 * a_dom                       # uint32 keys, weights NULL
     steps_dom = n * horner_steps_per_tuple(graph, kdom, d)
     dur_s = kern_ms[kdom] / 1e3
-    alu_achieved = steps_dom / dur_s
-    hbm_achieved = bytes_dom / dur_s / 1e9
-    traffic = measured_traffic(args.strategy)
-
-    progress("plain step timed")
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "tuple updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int64",
-        "data": "synthetic",
-        "config": {"workload": "chain3 R1(A)-R2(A,B)-R3(B), 1e7 tuples/relation, Zipf(1.1) over 1e6, "
-                               "m=2^16, d=9, weights +1 (NULL)",
-                   "relations": n_rel, "tuples_per_relation": n, "m": m, "d": d, "zipf_s": s, "domain": D,
-                   "sketch_seed": seed, "data_seed_base": W.DATA_SEED_BASE},
-        "roofline": {"bound": "alu", "achieved": alu_achieved / 1e12, "peak": ALU_STEP_PEAK / 1e12,
-                     "unit": "T Horner-steps/s", "frac": alu_achieved / ALU_STEP_PEAK, "traffic": traffic,
-                     "kernel": f"hashing kernel of relation {kdom}'s update ({a_dom} key columns)",
-                     "kernel_ms": kern_ms[kdom], "algorithmic_bytes": bytes_dom,
-                     "hbm_GBps": hbm_achieved, "hbm_frac": hbm_achieved / HBM_PEAK_GBS},
-        "update_ms_per_relation": {str(k): v for k, v in upd_ms.items()},
-        "hash_kernel_ms_per_relation": {str(k): v for k, v in kern_ms.items()},
-        "update_tuples_per_s": tuples_per_step / (upd_total_ms / 1e3),
-        "estimate_ms": est_ms,
-        "estimates_per_s": 1e3 / est_ms,
-        "init_ms": init_ms,
-        "estimate": {"value": res["value"], "exact": res["exact"], "n_modular": res["n_modular"]},
-        "pipelined_async_estimate": pipelined,
-    }
-
-    if args.filtered:
-        out["filtered"] = bench_filtered(sk, keys, graph, dev, stream, args.steps)
-        progress("filtered section done")
+    est_bytes = n_rel * d * m * 8
     sk.close()
-    if args.anym:
-        out["any_m"] = [bench_any_m(int(x), keys, graph, dev, stream, args.steps) for x in args.anym.split(",") if x]
-        progress("any-m section done")
-    if args.ams:
-        out["ams_baseline"] = bench_ams(keys, graph, stream)
-        progress("AMS section done")
-    out["attr_sketches"] = bench_attr(keys, graph, stream, args.steps)
-    progress("attribute-sketch section done")
-    del keys
-    torch.cuda.empty_cache()
-    if args.batch_queries > 0:
-        out["batched"] = bench_batched(args.batch_queries, dev, stream)
-        progress("batched section done")
-        torch.cuda.empty_cache()
-    if args.serve_queries > 0:
-        out["serving"] = bench_serving(args.serve_queries, dev, args.serve_seconds,
-                                       [float(x) for x in args.serve_rates.split(",") if x])
-        torch.cuda.empty_cache()
-    if not args.no_cpu:
-        keys_cpu = [W.relation_keys(graph, k, args.cpu_tuples, "zipf", config=config, s=s, D=D).to(torch.int32)
-                    for k in range(graph.n_rel)]
-        out["cpu_baseline"] = cpu_baseline(graph, keys_cpu, m, d, seed, args.cpu_tuples)
-        progress("CPU baseline done")
+    tuples_per_step = n * n_rel
+    return {
+        "workload": "chain3 R1(A)-R2(A,B)-R3(B), 1e7 tuples/relation (one update call each), Zipf(1.1) over 1e6, "
+                    "m=2^16, d=9, weights +1 (NULL)",
+        "tuples_per_s": tuples_per_step * args.steps / elapsed, "ms_per_step": elapsed * 1e3 / args.steps,
+        "roofline": {"bound": "alu", "achieved": steps_dom / dur_s / 1e12, "peak": ALU_STEP_PEAK / 1e12,
+                     "unit": "T Horner-steps/s", "frac": steps_dom / dur_s / ALU_STEP_PEAK,
+                     "traffic": measured_traffic("chain3", args.strategy),
+                     "kernel": f"hashing kernel of relation {kdom}'s update ({a_dom} key columns)",
+                     "kernel_ms": kern_ms[kdom], "algorithmic_bytes": n * 4 * a_dom,
+                     "hbm_frac": n * 4 * a_dom / dur_s / 1e9 / HBM_PEAK_GBS},
+        "hash_kernel_ms_per_relation": {str(k): v for k, v in kern_ms.items()},
+        "update_ms_per_relation": {str(k): v for k, v in upd_ms.items()},
+        "update_tuples_per_s": tuples_per_step / (sum(upd_ms.values()) / 1e3),
+        "estimate_ms": est_ms, "estimates_per_s": 1e3 / est_ms,
+        "estimate_roofline": {"bound": "hbm", "algorithmic_bytes": est_bytes,
+                              "achieved_GBps": est_bytes / (est_ms / 1e3) / 1e9,
+                              "frac": est_bytes / (est_ms / 1e3) / 1e9 / HBM_PEAK_GBS},
+        "estimate": {"value": res["value"], "exact": res["exact"], "n_modular": res["n_modular"]},
+        "pipelined_async_estimate": {
+            "tuples_per_s": tuples_per_step * args.steps / elapsed_p, "ms_per_step": elapsed_p * 1e3 / args.steps,
+            "identical_estimates": all(e["value"] == res["value"] and e["exact"] == res["exact"]
+                                       and e["value_i64"] == res["value_i64"] for e in pub)},
+    }, keys
 
-    print(json.dumps(out), flush=True)
 
-
-def bench_filtered(sk, keys, graph, dev, stream, steps):
-    """The same chain-3 step with a filter at ingestion (Sec. 4.1): one uniform attribute
-    column per relation over 0..99, kept when <= 24 (25% of the tuples pass)."""
+def bench_single(args, dev, stream):
+    """The single equi-join R1(A) - R2(A): 10^5 tuples each, keys uniform on [0, 10^4),
+    m = 1024, d = 5 (the inner-product plan), against the exact join size."""
+    import numpy as np
     import torch
 
+    import paper_2402_15953_amd as csk
     import workloads as W
-    n = keys[0].shape[0]
-    attrs = [W.uniform_keys(n, 100, seed=W.data_seed(7, k, 9), device=dev).to(torch.int32).contiguous()
-             for k in range(graph.n_rel)]
-    preds = [(0, 0, 24)]
-    kept = []
+
+    graph = W.single_join()
+    n, m, d, seed = 10 ** 5, 1024, 5, 7
+    keys = [W.relation_keys(graph, k, n, "uniform", config=1, D=10 ** 4, device=dev).to(torch.int32).contiguous()
+            for k in range(2)]
+    torch.cuda.synchronize()
+    sk = csk.Sketch(graph, m, d, seed)
+    reps = 200
 
     def step():
         sk.reset(stream=stream)
-        kept.clear()
-        for k in range(graph.n_rel):
-            kept.append(sk.update_filtered(k, keys[k], attrs[k], preds, stream=stream))
+        for k in range(2):
+            sk.update(k, keys[k], None, stream=stream)
         return sk.estimate(stream=stream)
 
     with torch.cuda.stream(stream):
         step()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
+        for _ in range(reps):
             res = step()
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / steps
+        dt = (time.perf_counter() - t0) / reps
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            sk.estimate(stream=stream)
+        de = (time.perf_counter() - t1) / reps
+    h = [np.bincount(keys[k].cpu().numpy().ravel(), minlength=10 ** 4) for k in range(2)]
+    exact = int(np.dot(h[0].astype(np.int64), h[1].astype(np.int64)))
+    sk.close()
+    return {"workload": "single join R1(A)-R2(A), 1e5 tuples each, uniform keys on [0,1e4), m=1024, d=5, weights +1",
+            "tuples_per_s": 2 * n / dt, "ms_per_step": dt * 1e3, "estimates_per_s": 1 / de,
+            "estimate": res["value"], "exact": res["exact"], "true_join_size": exact,
+            "relative_error": abs(res["value"] - exact) / exact}
+
+
+def bench_k0(probe_buf):
+    """The two machine-balance rates measured by the library's probe kernels."""
+    import paper_2402_15953_amd as csk
+    steps = max(csk.k0_horner(1 << 14) for _ in range(3))
+    read = max(csk.k0_stream_read(probe_buf, 5) for _ in range(2))
+    return {"horner_steps_per_s": steps, "horner_frac_of_peak": steps / ALU_STEP_PEAK,
+            "stream_read_GBps": read / 1e9, "stream_read_frac_of_peak": read / 1e9 / HBM_PEAK_GBS,
+            "stream_read_bytes": probe_buf.numel() * probe_buf.element_size()}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus %d is not supported" % args.gpus}))
+        print("bench.py runs on exactly one GPU (there is no multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_probe > 0:
+        copy_probe(args.copy_probe)
+        return
+    sections = set(x for x in args.sections.split(",") if x)
+    if args.no_cpu:
+        sections.discard("cpu")
+
+    import torch
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.Stream()
+    out = {"metric": METRIC, "value": None, "unit": "tuple updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int64", "data": "synthetic"}
+    host0 = None
+    if "chain5" in sections:
+        head, host0, probe_buf, keys5 = bench_chain5(args, dev, stream)
+        out["value"] = head.pop("value")
+        out["ms_per_step"] = head.pop("ms_per_step")
+        out["config"] = head.pop("config")
+        out["roofline"] = head.pop("roofline")
+        out.update(head)
+        progress("chain5 headline timed")
+        if "k0" in sections:
+            out["k0"] = bench_k0(probe_buf)
+            out["roofline"]["frac_of_k0"] = out["roofline"]["achieved"] * 1e12 / out["k0"]["horner_steps_per_s"]
+            progress("k0 probes done")
+        del probe_buf, keys5
+        torch.cuda.empty_cache()
+    keys3 = None
+    if "chain3" in sections:
+        out["chain3"], keys3 = bench_chain3(args, dev, stream)
+        progress("chain3 section done")
+    if "single" in sections:
+        out["single_join"] = bench_single(args, dev, stream)
+        progress("single-join section done")
+    if keys3 is not None:
+        import workloads as W
+        g3 = W.chain(3)
+        if "filtered" in sections:
+            out["filtered"] = bench_filtered(keys3, g3, dev, stream, args.steps)
+            progress("filtered section done")
+        if "anym" in sections and args.anym:
+            out["any_m"] = [bench_any_m(int(x), keys3, g3, dev, stream, args.steps) for x in args.anym.split(",") if x]
+            progress("any-m section done")
+        if "ams" in sections:
+            out["ams_baseline"] = bench_ams(keys3, g3, stream)
+            progress("AMS section done")
+        if "attr" in sections:
+            out["attr_sketches"] = bench_attr(keys3, g3, stream, args.steps)
+            progress("attribute-sketch section done")
+        del keys3
+        torch.cuda.empty_cache()
+    if "batched" in sections and args.batch_queries > 0:
+        out["batched"] = bench_batched(args.batch_queries, dev, stream)
+        progress("batched section done")
+        torch.cuda.empty_cache()
+    if "serving" in sections and args.serve_queries > 0:
+        out["serving"] = bench_serving(args.serve_queries, dev, args.serve_seconds,
+                                       [float(x) for x in args.serve_rates.split(",") if x])
+        torch.cuda.empty_cache()
+    if "cpu" in sections and host0 is not None:
+        out["cpu_baseline"] = cpu_baseline(host0)
+        progress("CPU baseline done")
+    print(json.dumps(out), flush=True)
+
+
+def bench_filtered(keys, graph, dev, stream, steps, m=1 << 16, d=9):
+    """The chain-3 step with a filter at ingestion (Sec. 4.1): one uniform attribute column
+    per relation over 0..99, kept when <= 24 (25% of the tuples pass), beside the same
+    step unfiltered."""
+    import torch
+
+    import paper_2402_15953_amd as csk
+    import workloads as W
+    n = keys[0].shape[0]
+    attrs = [W.uniform_keys(n, 100, seed=W.data_seed(7, k, 9), device=dev).to(torch.int32).contiguous()
+             for k in range(graph.n_rel)]
+    preds = [(0, 0, 24)]
+    sk = csk.Sketch(graph, m, d, 7)
+
+    def step(filtered):
+        sk.reset(stream=stream)
+        for k in range(graph.n_rel):
+            if filtered:
+                sk.update_filtered(k, keys[k], attrs[k], preds, stream=stream)
+            else:
+                sk.update(k, keys[k], None, stream=stream)
+        return sk.estimate(stream=stream)
+
+    times = {}
+    with torch.cuda.stream(stream):
+        for filtered in (False, True):
+            step(filtered)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                res = step(filtered)
+            torch.cuda.synchronize()
+            times[filtered] = (time.perf_counter() - t0) / steps
+    kept = [int(((a >= 0) & (a <= 24)).sum().item()) for a in attrs]
+    sk.close()
     total = n * graph.n_rel
     return {"workload": "chain-3 step with one range predicate per relation at ingestion (25% kept)",
-            "input_tuples_per_s": total / dt, "kept_fraction": sum(kept) / total, "ms_per_step": dt * 1e3,
-            "estimate": res["value"]}
+            "input_tuples_per_s": total / times[True], "kept_fraction": sum(kept) / total,
+            "ms_per_step": times[True] * 1e3, "unfiltered_ms_per_step": times[False] * 1e3,
+            "filtered_over_unfiltered": times[True] / times[False], "estimate": res["value"]}
 
 
 def bench_attr(keys, graph, stream, steps, m=1 << 16, d=9):
@@ -645,26 +848,67 @@ def bench_serving(n_queries, dev, seconds, rates):
             "update_launches": int(st["update_launches"]), "estimate_batches": int(st["estimate_batches"])}
 
 
-def cpu_baseline(graph, keys, m, d, seed, n_sample):
-    """The oracle (plain C sketch loop + exact NTT estimate) on the first n_sample
-    tuples of every relation: tuples per second of the same step on this host."""
+def cpu_baseline(host_keys):
+    """The oracle (plain C Alg. 2 loop) on a prefix of the headline input (Zipf 1.0),
+    on this host: one thread on one 2^20-tuple slice per relation, and one thread per
+    core of this process's CPU share (at most 16) on more slices, each thread sketching
+    its own slices into private counters that are then summed (the sketch is linear,
+    Sec. 2.2).  The exact estimate of one repetition (number-theoretic transforms of
+    2^18 points) is timed once and reported per estimate of all d repetitions."""
+    import platform
+    from concurrent.futures import ThreadPoolExecutor
+
     import numpy as np
 
     import oracle
+    import workloads as W
 
+    graph = W.chain(5)
+    m, d, seed = 1 << 18, 15, 8
+    n_call = 1 << 20
     info = oracle.analyze(graph)
     co = oracle.draw_coefficients(seed, d, len(info.edges), info.n_comp)
-    host = [k[:n_sample].cpu().numpy().view(np.uint32).reshape(n_sample, -1) for k in keys]
+    host = [k.numpy().view(np.uint32).reshape(k.shape[0], -1) for k in host_keys]
+    slices = host[0].shape[0] // n_call
     t0 = time.perf_counter()
-    sks = [oracle.create_sketch(info, k, host[k], None, m, co) for k in range(graph.n_rel)]
+    one = [oracle.create_sketch(info, k, host[k][:n_call], None, m, co) for k in range(graph.n_rel)]
     t1 = time.perf_counter()
-    oracle.estimate(info, sks, m, method="ntt")
+    try:
+        share = len(os.sched_getaffinity(0))
+    except AttributeError:
+        share = os.cpu_count() or 1
+    threads = max(1, min(16, share))
+    jobs = [(k, i) for k in range(graph.n_rel) for i in range(slices)]
     t2 = time.perf_counter()
-    tuples = n_sample * graph.n_rel
-    return {"value": tuples / (t2 - t0), "unit": "tuple updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n_sample} tuples of each of the {graph.n_rel} relations "
-                      f"(sketch {t1 - t0:.2f} s + exact estimate {t2 - t1:.2f} s)",
-            "update_only_tuples_per_s": tuples / (t1 - t0), "estimate_s": t2 - t1}
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        parts = list(ex.map(lambda ki: (ki[0], oracle.create_sketch(info, ki[0], host[ki[0]][ki[1] * n_call:(ki[1] + 1) * n_call],
+                                                                    None, m, co)), jobs))
+    sums = [np.zeros((d, m), dtype=np.int64) for _ in range(graph.n_rel)]
+    for k, sk in parts:
+        sums[k] += sk
+    t3 = time.perf_counter()
+    t4 = time.perf_counter()
+    oracle.estimate_alg3(info, [one[k][0] for k in range(graph.n_rel)], m, method="ntt")
+    t5 = time.perf_counter()
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        model = platform.processor()
+    tuples1 = n_call * graph.n_rel
+    tuplesn = n_call * slices * graph.n_rel
+    return {"value": tuples1 / (t1 - t0), "unit": "tuple updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"first 2^20 tuples of each of the 5 relations of the Zipf(1.0) stream (m=2^18, d=15), "
+                      f"one thread: {t1 - t0:.2f} s",
+            "threaded": {"value": tuplesn / (t3 - t2), "cores": threads,
+                         "sample": f"first {slices} x 2^20 tuples of each relation, {len(jobs)} slices over "
+                                   f"{threads} threads with private sketches summed: {t3 - t2:.2f} s"},
+            "estimate_s_per_repetition": t5 - t4, "estimates_per_s": 1.0 / ((t5 - t4) * d),
+            "nproc": os.cpu_count(), "cpu_share": share, "cpu_model": model}
 
 
 if __name__ == "__main__":

@@ -107,11 +107,12 @@ typedef enum cs_update_strategy {
                                      handle's scratch buffer, and a reduce kernel adds
                                      them into the counters */
     CS_UPDATE_WAVE_AGGREGATE = 3, /* equal buckets of one wavefront merged before the atomic */
-    CS_UPDATE_PARTITION = 4       /* sort by bucket: identical tuples of a tile merged in
-                                     LDS, each distinct tuple hashed once per repetition
-                                     into 32-bit records partitioned by (repetition, bucket
-                                     range) through LDS, then one workgroup per partition
-                                     sums its records in LDS (segmented reduce); needs
+    CS_UPDATE_PARTITION = 4       /* sort by bucket range: every tuple hashed once per
+                                     repetition into a 16-bit record, grouped by
+                                     (repetition, range of 2^14 buckets) per wavefront
+                                     (up to two hot tuples per 1024-tuple segment summed
+                                     instead), then one workgroup per group sums its
+                                     records in LDS and owns those counters; needs
                                      weights NULL or CS_UPDATE_UNIT_WEIGHTS, <= 2 columns */
 } cs_update_strategy;
 
@@ -198,7 +199,8 @@ cs_status cs_update_ex(cs_sketch *h, int32_t rel, const uint32_t *keys, const in
 
 /* cs_update_ex that also records two caller-created hipEvent_t on `stream`: ev_start just
  * before the update's hashing kernel and ev_stop just after it (the segmented strategy's
- * reduction of partial sums falls outside; for the partition strategy both passes over
+ * reduction of partial sums and the partition strategy's accumulation pass fall outside;
+ * a partition update of more than 2^21 tuples runs in chunks, and then both passes of
  * every chunk fall inside).  Either event may be NULL.  Per-kernel timing for monitoring
  * and tuning; the counters are the same as cs_update's.  Errors as cs_update_ex, and
  * CS_EDEVICE if an event cannot be recorded. */
@@ -225,6 +227,19 @@ cs_status cs_update_timed(cs_sketch *h, int32_t rel, const uint32_t *keys, const
 cs_status cs_update_noalloc(cs_sketch *h, int32_t rel, const uint32_t *keys, const int64_t *weights,
                             uint64_t n, int32_t flags, void *stream);
 size_t cs_update_noalloc_scratch_bytes(void);
+
+/* ------------------------------------------------------------------ machine-balance probes */
+
+/* The two rates the update is judged against, measured on the current device (the
+ * update's hashes are Horner steps v <- v * x + a mod 2^61 - 1, Sec. 4; Alg. 2):
+ * cs_k0_horner runs a kernel of nothing but independent Horner steps (the library's own
+ * step, 16 wavefronts per CU, 8 chains per lane, `iters` steps per chain) and returns
+ * steps per second; cs_k0_stream_read reads `bytes` of device memory at `buf` (caller
+ * owned, at least 16 bytes) `passes` times and returns bytes per second.  Synchronous
+ * (null stream); each allocates and frees a small output buffer.  Benchmarking only.
+ * Errors: CS_EINVAL (bad arguments, memory the device cannot read), CS_EDEVICE. */
+cs_status cs_k0_horner(uint64_t iters, double *steps_per_s);
+cs_status cs_k0_stream_read(const void *buf, uint64_t bytes, int32_t passes, double *bytes_per_s);
 
 /* ------------------------------------------------------------------ filtered ingestion */
 

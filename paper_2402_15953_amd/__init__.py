@@ -27,6 +27,7 @@ PLAN_DOT, PLAN_SPECTRAL, PLAN_GENERAL = 1, 2, 3
 EXPORTED = [
     "cs_create", "cs_destroy", "cs_sketch_bytes", "cs_get_info", "cs_last_error",
     "cs_update", "cs_update_ex", "cs_update_timed", "cs_update_noalloc", "cs_update_noalloc_scratch_bytes",
+    "cs_k0_horner", "cs_k0_stream_read",
     "cs_update_filtered", "cs_estimate", "cs_reset", "cs_merge", "cs_read_sketch",
     "cs_sketch_device_ptr", "cs_read_coeffs", "cs_read_components",
     "cs_timer_create", "cs_timer_record", "cs_timer_elapsed", "cs_timer_destroy",
@@ -141,6 +142,8 @@ def lib() -> ctypes.CDLL:
         L.cs_update_ex.argtypes = [vp, i32, vp, vp, u64, vp, i32, i32, i32]
         L.cs_update_timed.argtypes = [vp, i32, vp, vp, u64, vp, i32, i32, i32, vp, vp]
         L.cs_update_noalloc.argtypes = [vp, i32, vp, vp, u64, i32, vp]
+        L.cs_k0_horner.argtypes = [u64, ctypes.POINTER(ctypes.c_double)]
+        L.cs_k0_stream_read.argtypes = [vp, u64, i32, ctypes.POINTER(ctypes.c_double)]
         L.cs_update_noalloc_scratch_bytes.argtypes = []
         L.cs_update_noalloc_scratch_bytes.restype = ctypes.c_size_t
         L.cs_update_filtered.argtypes = [vp, i32, vp, vp, u64, vp, i32, ctypes.POINTER(_Predicate), i32, i32, vp,
@@ -317,6 +320,21 @@ def tune_count() -> int:
     n = ctypes.c_int32()
     _check(lib().cs_tune_count(ctypes.byref(n)))
     return n.value
+
+
+def k0_horner(iters: int = 1 << 14) -> float:
+    """Horner steps per second of a kernel made of nothing but independent steps."""
+    r = ctypes.c_double()
+    _check(lib().cs_k0_horner(int(iters), ctypes.byref(r)))
+    return r.value
+
+
+def k0_stream_read(buf, passes: int = 5) -> float:
+    """Bytes per second of a kernel streaming the device tensor `buf` (read only)."""
+    r = ctypes.c_double()
+    _check(lib().cs_k0_stream_read(ctypes.c_void_p(buf.data_ptr()), int(buf.numel() * buf.element_size()),
+                                   int(passes), ctypes.byref(r)))
+    return r.value
 
 
 def sketch_bytes(graph, m: int, d: int) -> int:

@@ -24,6 +24,7 @@ SOURCES = [
     "csk_checkpoint.hip",
     "csk_batch.hip",
     "csk_serve.hip",
+    "csk_probe.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -142,13 +142,22 @@ struct SegGeom {
 // n: tuples of the update (chunks shrink for small inputs); the default sizes buffers.
 SegGeom seg_geometry(uint32_t m, int32_t d, bool narrow, size_t scratch_bytes, uint64_t n = ~0ull);
 SegGeom seg16_geometry(uint32_t m, int32_t d, size_t scratch_bytes, uint64_t n = ~0ull);
-constexpr int kMaxPartRanges = 512;
-constexpr uint64_t kPartMaxChunk = 1ull << 21;
+constexpr int kMaxPartRanges = 64;           // bucket ranges of 2^14 per repetition (m <= 2^20)
+constexpr uint64_t kPartMaxChunk = 1ull << 21;  // tuples per pass pair
+// One segment's hot tuples for the partition strategy (see k_part_hash): up to two
+// tuples (keys; column 1 unused for one-column relations) and their Delta sums.
+struct PartHot {
+    uint32_t key[2][2];
+    int32_t sum[2];
+};
 struct PartGeom {
-    int32_t log2R;      // bucket range = 2^log2R buckets
-    int32_t ranges;     // ranges per repetition
-    uint64_t chunk;     // tuples per pass pair
-    size_t tab_offset;  // range table after the records in the scratch buffer
+    int32_t ranges;          // bucket ranges of 2^14 per repetition (the last may be partial)
+    uint64_t chunk;          // tuples per pass pair (a multiple of the 1024-tuple segment)
+    uint64_t nseg;           // segments per chunk
+    size_t tab_offset;       // range starts after the records in the scratch buffer
+    size_t hot_offset;       // hot-tuple list after the range starts
+    int32_t groups;          // pass-1 repetition groups
+    int32_t reps_per_group;
 };
 PartGeom part_geometry(uint32_t m, int32_t d, size_t scratch_bytes);
 size_t seg_scratch_bytes(uint32_t m, int32_t d);

@@ -756,266 +756,396 @@ __global__ void k_seg_reduce(const CT *__restrict__ partial, int32_t C, uint64_t
     }
 }
 
-// ---------------------------------------------------------------- sort by bucket
+// ---------------------------------------------------------------- sort by bucket range
 //
-// Partition strategy for large m: the tuples are processed in chunks of at most
-// kPartMaxChunk.  Pass 1 (k_part_hash) merges the identical tuples of a tile of
-// kPartTile tuples, hashes every distinct tuple once per repetition, and writes one
-// 32-bit record per (distinct tuple, repetition) -- the bucket's offset inside its
-// bucket range and the signed Delta sum -- sorted by bucket range through an LDS
-// counting sort, plus the start of each range's run.  Pass 2
-// (k_part_accum) gives each (repetition, bucket range) to one workgroup, which sums
-// its records from every tile in LDS and adds the sums into the sketch.  Each tuple is
-// hashed once; global memory sees only coalesced record traffic.  Deltas must be +1
-// (weights NULL) or +-1 (flag CS_UPDATE_UNIT_WEIGHTS).
+// Partition strategy for m beyond what one workgroup's LDS holds (and any m when asked
+// for): every (tuple, repetition) is hashed exactly once into a 16-bit record, the
+// records are grouped by (repetition, bucket range of 2^14 buckets), and one workgroup
+// per group sums them in LDS and adds the sums into the int64 counters it alone owns.
+// Deltas must be +1 (weights NULL) or +-1 (flag CS_UPDATE_UNIT_WEIGHTS).  The tuples
+// run in chunks of at most kPartMaxChunk (two kernels per chunk).
+//
+// Pass 1 (k_part_hash): a wavefront owns a segment of kPartSeg consecutive tuples,
+// loads its keys once (quads of consecutive tuples per lane, 16-byte loads) and loops
+// over a group of repetitions.  Per repetition it hashes its tuples, counts them per
+// bucket range in its own LDS histogram (the add's returned value is each record's
+// rank; four sub-histograms by lane & 3 keep lanes of one wavefront apart), scans the
+// histogram across its lanes, scatters the records into its LDS staging area by range,
+// and stores the segment's records and range starts, both coalesced.  No workgroup
+// barrier: the wavefronts of a workgroup are independent.
+//
+// Zipf-skewed keys put a large share of a stream on a few tuples; left alone, pass 2's
+// LDS adds on their buckets would serialise (same-address atomics) and the workgroup of
+// their range would carry most records.  Each wavefront therefore elects up to two hot
+// tuples among a sample of its segment, sums their Deltas instead of emitting records
+// for them, and leaves (tuple, Delta sum) in a per-segment list that pass 2 hashes once
+// per repetition.  The sketch is linear (Sec. 2.2): n equal tuples with Deltas
+// Delta_i add sum_i Delta_i at their one counter, so the counters are unchanged.
+//
+// Pass 2 (k_part_accum): workgroup (range r, repetition t) zeroes 2^14 int32 LDS
+// counters, adds +-1 for every record of its group from every segment, adds the hot
+// tuples whose bucket falls in its range, and adds the non-zero sums into the sketch
+// (it owns those counters: plain read-modify-write, no atomics).
 
-constexpr int kPartTile = 2048;
-constexpr int kPB = 512;                            // pass-1 workgroup
-constexpr int kPartPerThread = kPartTile / kPB;     // 4
-constexpr int kPAB = 1024;                          // pass-2 workgroup
-constexpr int kDedupSlots = 2 * kPartTile;          // open-addressing table, load <= 1/2
-static_assert(kDedupSlots < 0xFFFF, "slot codes are 16-bit, 0xFFFF marks the reserved slot");
-constexpr uint64_t kEmptyKey = ~0ull;
+constexpr int kPartLog2R = 14;                   // buckets per range (pass-2 LDS: 64 KB of int32)
+constexpr uint32_t kPartR = 1u << kPartLog2R;
+constexpr int kPartQuads = 4;                    // quads of tuples per lane and segment
+constexpr int kPartSlots = 4 * kPartQuads;       // tuples per lane and segment
+constexpr int kPartSeg = 64 * kPartSlots;        // 1024 tuples per wavefront segment
+constexpr int kPartHS = 4;                       // sub-histograms per range
+constexpr int kPB = 256;                         // pass-1 workgroup: 4 independent wavefronts
+constexpr int kPAB = 512;                        // pass-2 workgroup
+constexpr uint32_t kPartNone = 0xFFFFFFFFu;      // a slot without a record
+static_assert(kMaxPartRanges * kPartHS <= 64 * kPartHS && kMaxPartRanges <= 64, "one lane per bucket range");
+static_assert(kPartSeg <= 0xFFFF, "range starts are 16-bit");
+static_assert(sizeof(PartHot) == 24, "hot-tuple entry layout");
 
 template <int NC>
-__device__ __forceinline__ uint64_t pack_key(const uint32_t (&x)[NC])
+__device__ __forceinline__ bool same_key(const uint32_t (&a)[NC], const uint32_t (&b)[NC])
 {
-    if constexpr (NC == 1) return (uint64_t)x[0];
-    else return (uint64_t)x[0] | ((uint64_t)x[1] << 32);
+    bool e = true;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) e = e && a[c] == b[c];
+    return e;
 }
 
-template <int NC>
-__device__ __forceinline__ void unpack_key(uint64_t k, uint32_t (&x)[NC])
+__device__ __forceinline__ void wave_sync()
 {
-    x[0] = (uint32_t)k;
-    if constexpr (NC == 2) x[1] = (uint32_t)(k >> 32);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Pass 1.  A tile's identical tuples are first merged in an LDS hash table (their
-// Deltas summed: the sketch is linear, Sec. 2.2), so a hot key costs one hash and one
-// record per tile.  Each distinct tuple is then hashed per repetition into a 32-bit
-// record: bucket offset inside its range (13 bits) and signed sum of Deltas times the
-// sign (19 bits; |sum| <= kPartTile).
-template <int NC, bool E1>
-__global__ __launch_bounds__(kPB) void k_part_hash(const uint32_t *__restrict__ keys,
+__device__ __forceinline__ int32_t wave_sum_i32(int32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Bucket j in [0, m) and sign bit of one tuple for one repetition: the one-join fast
+// hash (m a power of two; the full reduction only when a hash's flag asks for it, see
+// CoefE1::bin_neg_fast), or the general one (any m, any joins per column).
+template <int NC, bool FAST>
+struct PartHasher {
+    CoefE1<NC> K;
+    const uint64_t *cf;
+    DevPlan plan;
+    uint32_t mmask, canon_thresh;
+    __device__ __forceinline__ void load(const uint64_t *coef_t)
+    {
+        cf = coef_t;
+        if constexpr (FAST) K.load(coef_t);
+    }
+    __device__ __forceinline__ void hash(const uint32_t (&x)[NC], uint32_t &j, uint32_t &neg, uint32_t &flag) const
+    {
+        if constexpr (FAST) {
+            K.bin_neg_fast(x, j, neg, flag);
+        } else {
+            hash_rep<NC>(cf, plan, x, j, neg);
+            flag = 0;
+        }
+    }
+    __device__ __forceinline__ void exact(const uint32_t (&x)[NC], uint32_t &j, uint32_t &neg) const
+    {
+        if constexpr (FAST) {
+            j = K.bin(x);
+            neg = K.neg(x);
+        }
+    }
+    __device__ __forceinline__ uint32_t bucket(uint32_t j) const { return FAST ? (j & mmask) : j; }
+};
+
+// Pass 1.  Grid (segment blocks, repetition groups), mapped by seg_tile() so that the
+// groups of one segment block share an XCD (its L2 fetches the keys once).
+template <int NC, bool FAST, bool HW, bool A16>
+__global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict__ keys,
                                                       const int64_t *__restrict__ weights, uint64_t n,
                                                       const uint64_t *__restrict__ coef, int32_t cpr,
-                                                      DevPlan plan, uint32_t m, int32_t d, int32_t log2R,
-                                                      int32_t ranges, bool vec2, uint32_t *rec_out,
-                                                      int32_t *tab, uint32_t canon_thresh)
+                                                      DevPlan plan, uint32_t m, int32_t d, int32_t ranges,
+                                                      int32_t reps_per_group, uint64_t nseg, uint16_t *rec_out,
+                                                      uint16_t *tab, PartHot *hot, uint32_t canon_thresh)
 {
-    __shared__ uint64_t s_key[kDedupSlots + 1];  // slot kDedupSlots: the tuple whose packed key is kEmptyKey
-    __shared__ int32_t s_w[kDedupSlots + 1];
-    __shared__ uint16_t s_list[kPartTile];
-    __shared__ int32_t s_cnt[kMaxPartRanges + 1];
-    __shared__ int32_t s_nlist;
-    uint32_t *s_rec = reinterpret_cast<uint32_t *>(s_key);  // reused once the list is in registers
+    static_assert(NC == 1 || NC == 2, "one- and two-column relations");
+    __shared__ __align__(16) uint32_t s_hist[kPB / 64][64 * kPartHS];
+    __shared__ __align__(16) uint16_t s_stage[kPB / 64][kPartSeg];
+    const SegTile wg = seg_tile();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t seg = (uint64_t)wg.chunk * (kPB / 64) + wave;
+    if (seg >= nseg) return;  // wave-uniform; this kernel has no workgroup barrier
+    const int t0 = (int)wg.seg * reps_per_group;
+    const int t1 = min(d, t0 + reps_per_group);
+    const uint64_t base = seg * kPartSeg;
+    const bool full = base + kPartSeg <= n;
 
-    const uint64_t i0 = (uint64_t)blockIdx.x * kPartTile;
-    const int nv = (int)(n - i0 < (uint64_t)kPartTile ? n - i0 : (uint64_t)kPartTile);
-    for (int e = threadIdx.x; e <= kDedupSlots; e += kPB) {
-        s_key[e] = kEmptyKey;
-        s_w[e] = 0;
-    }
-    if (threadIdx.x == 0) s_nlist = 0;
-    __syncthreads();
-    // ---- merge identical tuples
+    // ---- keys of the segment: slot s = 4 q + g is tuple base + 4 (64 q + lane) + g
+    uint32_t x[kPartSlots][NC];
+    uint32_t valid = 0, wneg = 0;  // bit s: slot s holds a tuple / its Delta is -1
 #pragma unroll
-    for (int k = 0; k < kPartPerThread; ++k) {
-        const int e = threadIdx.x + k * kPB;
-        if (e < nv) {
-            uint32_t xx[NC];
-            load_keys<NC>(keys, i0 + e, vec2, xx);
-            const int32_t w = weights ? (weights[i0 + e] < 0 ? -1 : 1) : 1;
-            const uint64_t key = pack_key<NC>(xx);
-            if (key == kEmptyKey) {
-                atomicAdd(&s_w[kDedupSlots], w);
+    for (int q = 0; q < kPartQuads; ++q) {
+        const uint64_t i0 = base + 4 * ((uint64_t)q * 64 + lane);
+        if (A16 && full) {
+            const uint4 *p = reinterpret_cast<const uint4 *>(keys + i0 * NC);
+            if constexpr (NC == 1) {
+                const uint4 v = p[0];
+                x[4 * q + 0][0] = v.x;
+                x[4 * q + 1][0] = v.y;
+                x[4 * q + 2][0] = v.z;
+                x[4 * q + 3][0] = v.w;
             } else {
-                uint32_t slot = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 52) & (kDedupSlots - 1);
-                for (;;) {
-                    const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long *>(&s_key[slot]),
-                                                             (unsigned long long)kEmptyKey, (unsigned long long)key);
-                    if (old == kEmptyKey || old == key) {
-                        atomicAdd(&s_w[slot], w);
-                        break;
-                    }
-                    slot = (slot + 1) & (kDedupSlots - 1);
-                }
+                const uint4 a = p[0], b = p[1];
+                x[4 * q + 0][0] = a.x;
+                x[4 * q + 0][1] = a.y;
+                x[4 * q + 1][0] = a.z;
+                x[4 * q + 1][1] = a.w;
+                x[4 * q + 2][0] = b.x;
+                x[4 * q + 2][1] = b.y;
+                x[4 * q + 3][0] = b.z;
+                x[4 * q + 3][1] = b.w;
             }
-        }
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e <= kDedupSlots; e += kPB) {
-        const bool used = e == kDedupSlots ? true : s_key[e] != kEmptyKey;
-        if (used && s_w[e] != 0) s_list[atomicAdd(&s_nlist, 1)] = (uint16_t)(e < kDedupSlots ? e : 0xFFFF);
-    }
-    __syncthreads();
-    const int u = s_nlist;
-    uint32_t x[kPartPerThread][NC];
-    int32_t wv[kPartPerThread];
-#pragma unroll
-    for (int k = 0; k < kPartPerThread; ++k) {
-        const int l = threadIdx.x + k * kPB;
-        wv[k] = 0;
-        if (l < u) {
-            const uint32_t code = s_list[l];
-            const int slot = code == 0xFFFFu ? kDedupSlots : (int)code;
-            uint32_t xx[NC];
-            unpack_key<NC>(s_key[slot], xx);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) x[k][c] = xx[c];
-            wv[k] = s_w[slot];
+            if constexpr (HW) {
+                const longlong2 *pw = reinterpret_cast<const longlong2 *>(weights + i0);
+                const longlong2 u = pw[0], v = pw[1];
+                wneg |= ((uint32_t)((uint64_t)u.x >> 63) | ((uint32_t)((uint64_t)u.y >> 63) << 1) |
+                         ((uint32_t)((uint64_t)v.x >> 63) << 2) | ((uint32_t)((uint64_t)v.y >> 63) << 3))
+                        << (4 * q);
+            }
+            valid |= 0xFu << (4 * q);
         } else {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) x[k][c] = 0;
+            for (int g = 0; g < 4; ++g) {
+                const uint64_t i = i0 + g;
+                const bool in = i < n;
+                const uint64_t ic = in ? i : 0;  // clamped: every load stays in bounds
+#pragma unroll
+                for (int c = 0; c < NC; ++c) x[4 * q + g][c] = keys[ic * NC + c];
+                if constexpr (HW) wneg |= (uint32_t)((uint64_t)weights[ic] >> 63) << (4 * q + g);
+                valid |= (uint32_t)in << (4 * q + g);
+            }
         }
     }
-    __syncthreads();
-    // ---- per repetition: hash, counting sort by bucket range, coalesced store
-    const uint32_t rmask = (1u << log2R) - 1;
-    for (int t = 0; t < d; ++t) {
-        for (int r = threadIdx.x; r <= ranges; r += kPB) s_cnt[r] = 0;
-        __syncthreads();
-        const uint64_t *cf = coef + (size_t)t * cpr;
-        uint32_t rec[kPartPerThread];
-        uint16_t rng[kPartPerThread];
-        uint16_t pos[kPartPerThread];
-        // E1 (every column in one join, m a power of two): coefficients in registers and
-        // the canonical reduction only when a hash's flag asks for it
-        CoefE1<NC> K;
-        if constexpr (E1) K.load(cf);
+    wneg &= valid;
+
+    // ---- hot tuples: candidates are the first tuples of lanes 0..7, scored by their
+    // count among the first two quads of every lane (512 tuples); the two best with at
+    // least 8 hits are taken out of the record stream
+    uint32_t H[2][NC];
+    int nh = 0;
+    {
+        uint32_t best[2] = {0u, 0u};
+        uint32_t bk[2][NC];
 #pragma unroll
-        for (int k = 0; k < kPartPerThread; ++k) {
-            const int l = threadIdx.x + k * kPB;
-            if (l < u) {
-                uint32_t j, neg;
-                if constexpr (E1) {
-                    uint32_t flag;
-                    K.bin_neg_fast(x[k], j, neg, flag);
-                    if (flag >= canon_thresh) {
-                        j = K.bin(x[k]);
-                        neg = K.neg(x[k]);
-                    }
-                    j &= m - 1;
-                } else {
-                    hash_rep<NC>(cf, plan, x[k], j, neg);
+        for (int c = 0; c < NC; ++c) bk[0][c] = bk[1][c] = 0u;
+        for (int cand = 0; cand < 8; ++cand) {
+            uint32_t kc[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) kc[c] = __builtin_amdgcn_readlane(x[0][c], cand);
+            if (!((__builtin_amdgcn_readlane(valid, cand)) & 1u)) continue;
+            uint32_t cnt = 0;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) cnt += (uint32_t)__popcll(__ballot(((valid >> s) & 1u) && same_key<NC>(x[s], kc)));
+            if (best[0] > 0 && same_key<NC>(kc, bk[0])) continue;
+            if (best[1] > 0 && same_key<NC>(kc, bk[1])) continue;
+            if (cnt > best[0]) {
+                best[1] = best[0];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    bk[1][c] = bk[0][c];
+                    bk[0][c] = kc[c];
                 }
-                const int32_t val = neg ? -wv[k] : wv[k];
-                rec[k] = (j & rmask) | ((uint32_t)val << 13);
-                rng[k] = (uint16_t)(j >> log2R);
-                pos[k] = (uint16_t)atomicAdd(&s_cnt[rng[k]], 1);
+                best[0] = cnt;
+            } else if (cnt > best[1]) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) bk[1][c] = kc[c];
+                best[1] = cnt;
             }
         }
-        __syncthreads();
-        // exclusive scan of the range counts (ranges <= kMaxPartRanges), one wave
-        if (threadIdx.x < 64) {
-            int carry = 0;
-            for (int base = 0; base < ranges; base += 64) {
-                const int r = base + (int)threadIdx.x;
-                const int v = r < ranges ? s_cnt[r] : 0;
-                int incl = v;
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int y = __shfl_up(incl, o, 64);
-                    if ((int)threadIdx.x >= o) incl += y;
-                }
-                if (r < ranges) s_cnt[r] = carry + incl - v;
-                carry += __shfl(incl, 63, 64);
-            }
-            if (threadIdx.x == 0) s_cnt[ranges] = carry;
-        }
-        __syncthreads();
+        nh = (best[0] >= 8) + (best[1] >= 8);
 #pragma unroll
-        for (int k = 0; k < kPartPerThread; ++k) {
-            const int l = threadIdx.x + k * kPB;
-            if (l < u) s_rec[s_cnt[rng[k]] + pos[k]] = rec[k];
+        for (int c = 0; c < NC; ++c) {
+            H[0][c] = bk[0][c];
+            H[1][c] = bk[1][c];
         }
-        int32_t *tb = tab + ((size_t)blockIdx.x * d + t) * (ranges + 1);
-        for (int r = threadIdx.x; r <= ranges; r += kPB) tb[r] = s_cnt[r];
-        __syncthreads();
-        uint32_t *o = rec_out + ((size_t)blockIdx.x * d + t) * kPartTile;
-        for (int e = threadIdx.x; e < u; e += kPB) o[e] = s_rec[e];
-        __syncthreads();
+    }
+    int32_t hsum[2] = {0, 0};
+    uint32_t live = valid;  // slots that emit records
+    if (nh > 0) {
+#pragma unroll
+        for (int s = 0; s < kPartSlots; ++s) {
+            if (!((valid >> s) & 1u)) continue;
+            const int32_t dl = ((wneg >> s) & 1u) ? -1 : 1;
+            if (same_key<NC>(x[s], H[0])) {
+                hsum[0] += dl;
+                live &= ~(1u << s);
+            } else if (nh > 1 && same_key<NC>(x[s], H[1])) {
+                hsum[1] += dl;
+                live &= ~(1u << s);
+            }
+        }
+    }
+    hsum[0] = wave_sum_i32(hsum[0]);
+    hsum[1] = wave_sum_i32(hsum[1]);
+    if (wg.seg == 0 && lane == 0) {
+        PartHot h;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            h.key[k][0] = H[k][0];
+            h.key[k][1] = NC == 2 ? H[k][NC - 1] : 0u;
+            h.sum[k] = k < nh ? hsum[k] : 0;
+        }
+        hot[seg] = h;
+    }
+
+    // ---- per repetition: hash, rank by range, scan, scatter, store
+    PartHasher<NC, FAST> hs;
+    hs.plan = plan;
+    hs.mmask = m - 1;
+    hs.canon_thresh = canon_thresh;
+    uint32_t *hist = s_hist[wave];
+    uint16_t *stage = s_stage[wave];
+    const uint32_t sub = lane & (kPartHS - 1);
+    for (int t = t0; t < t1; ++t) {
+        hs.load(coef + (size_t)t * cpr);
+        reinterpret_cast<uint4 *>(hist)[lane] = make_uint4(0u, 0u, 0u, 0u);
+        wave_sync();
+        uint32_t P[kPartSlots];
+        // tuples hashed together: four one-column or two two-column tuples (eight or
+        // four independent Horner chains) keep the register count near 100
+        constexpr int G = NC == 1 ? 4 : 2;
+#pragma unroll
+        for (int q = 0; q < kPartSlots / G; ++q) {
+            uint32_t j[G], ng[G], flag = 0;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                uint32_t f;
+                hs.hash(x[G * q + g], j[g], ng[g], f);
+                flag = max(flag, f);
+            }
+            if (flag >= canon_thresh) {  // a hash may need the full reduction
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    uint32_t jj, nn, f;
+                    hs.hash(x[G * q + g], jj, nn, f);
+                    if (f >= canon_thresh) hs.exact(x[G * q + g], j[g], ng[g]);
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int s = G * q + g;
+                P[s] = kPartNone;
+                if ((live >> s) & 1u) {
+                    const uint32_t b = hs.bucket(j[g]);
+                    const uint32_t r = b >> kPartLog2R;
+                    const uint32_t rc = (b & (kPartR - 1)) | (((ng[g] ^ (wneg >> s)) & 1u) << kPartLog2R);
+                    const uint32_t pos = atomicAdd(&hist[r * kPartHS + sub], 1u);
+                    P[s] = rc | (r << 15) | (pos << 21);
+                }
+            }
+        }
+        wave_sync();
+        // exclusive scan over (range, sub-histogram): lane L holds range L's four counts
+        const uint4 h4 = reinterpret_cast<const uint4 *>(hist)[lane];
+        const uint32_t e1 = h4.x, e2 = e1 + h4.y, e3 = e2 + h4.z, tot = e3 + h4.w;
+        uint32_t incl = tot;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += y;
+        }
+        const uint32_t excl = incl - tot;
+        reinterpret_cast<uint4 *>(hist)[lane] = make_uint4(excl, excl + e1, excl + e2, excl + e3);
+        uint16_t *tb = tab + ((uint64_t)t * nseg + seg) * (uint64_t)(ranges + 1);
+        if (lane < ranges) tb[lane] = (uint16_t)excl;
+        const uint32_t total = __shfl(incl, 63, 64);
+        if (lane == 0) tb[ranges] = (uint16_t)total;
+        wave_sync();
+#pragma unroll
+        for (int s = 0; s < kPartSlots; ++s) {
+            if (P[s] != kPartNone) {
+                const uint32_t r = (P[s] >> 15) & 63u;
+                stage[hist[r * kPartHS + sub] + (P[s] >> 21)] = (uint16_t)(P[s] & 0x7FFFu);
+            }
+        }
+        wave_sync();
+        uint4 *dst = reinterpret_cast<uint4 *>(rec_out + ((uint64_t)t * nseg + seg) * kPartSeg);
+        const uint4 *src = reinterpret_cast<const uint4 *>(stage);
+        constexpr int kVec = kPartSeg * 2 / 16;  // 16-byte pieces of the staging area
+#pragma unroll
+        for (int v = lane; v < kVec; v += 64) {
+            if ((uint32_t)v * 8 < total) dst[v] = src[v];
+        }
+        wave_sync();
     }
 }
 
-// Block (range r, repetition t): sum the records of every tile, add into the sketch.
-// The tiles' run bounds are loaded in parallel first; the records of all tiles are then
-// walked as one flattened index space, four independent loads per thread in flight.
-__global__ __launch_bounds__(kPAB) void k_part_accum(const uint32_t *__restrict__ rec,
-                                                     const int32_t *__restrict__ tab, int32_t tiles,
-                                                     int32_t d, int32_t ranges, int32_t log2R, uint32_t m,
-                                                     uint64_t *sketch)
+// Pass 2.  Block (range r, repetition t).
+template <int NC, bool FAST>
+__global__ __launch_bounds__(kPAB) void k_part_accum(const uint16_t *__restrict__ rec,
+                                                     const uint16_t *__restrict__ tab,
+                                                     const PartHot *__restrict__ hot, uint64_t nseg,
+                                                     int32_t ranges, uint32_t m, const uint64_t *__restrict__ coef,
+                                                     int32_t cpr, DevPlan plan, uint64_t *sketch,
+                                                     uint32_t canon_thresh)
 {
-    extern __shared__ int32_t s_dyn[];
-    int32_t *s_acc = s_dyn;                    // [R]
-    int32_t *s_pre = s_dyn + (1 << log2R);     // [tiles + 1] prefix of run lengths
-    int32_t *s_beg = s_pre + tiles + 1;        // [tiles]
+    extern __shared__ __align__(16) uint32_t s_dyn[];
+    int32_t *s_cnt = reinterpret_cast<int32_t *>(s_dyn);  // [kPartR]
+    uint32_t *s_run = s_dyn + kPartR;                      // [nseg]: start | length << 16
     const int r = blockIdx.x, t = blockIdx.y;
-    const int R = 1 << log2R;
-    for (int e = threadIdx.x; e < R; e += kPAB) s_acc[e] = 0;
-    for (int tile = threadIdx.x; tile < tiles; tile += kPAB) {
-        const int32_t *tb = tab + ((size_t)tile * d + t) * (ranges + 1);
-        const int beg = tb[r], end = tb[r + 1];
-        s_beg[tile] = beg;
-        s_pre[tile + 1] = end - beg;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int kWaves = kPAB / 64;
+    for (uint32_t e = threadIdx.x; e < kPartR / 4; e += kPAB) reinterpret_cast<int4 *>(s_cnt)[e] = make_int4(0, 0, 0, 0);
+    for (uint64_t s = threadIdx.x; s < nseg; s += kPAB) {
+        const uint16_t *tb = tab + ((uint64_t)t * nseg + s) * (uint64_t)(ranges + 1);
+        const uint32_t beg = tb[r], end = tb[r + 1];
+        s_run[s] = beg | ((end - beg) << 16);
     }
-    if (threadIdx.x == 0) s_pre[0] = 0;
     __syncthreads();
-    // inclusive scan of run lengths (tiles <= kPartMaxChunk / kPartTile), one wave
-    if (threadIdx.x < 64) {
-        int carry = 0;
-        for (int base = 1; base <= tiles; base += 64) {
-            const int i = base + (int)threadIdx.x;
-            int v = i <= tiles ? s_pre[i] : 0;
-            for (int o = 1; o < 64; o <<= 1) {
-                const int y = __shfl_up(v, o, 64);
-                if ((int)threadIdx.x >= o) v += y;
-            }
-            if (i <= tiles) s_pre[i] = carry + v;
-            carry += __shfl(v, 63, 64);
+    // records: each wavefront takes every kWaves-th segment, two at a time so that two
+    // loads are in flight before their LDS adds
+    const uint16_t *rt = rec + (uint64_t)t * nseg * kPartSeg;
+    for (uint64_t s = wave; s < nseg; s += 2 * kWaves) {
+        const uint64_t s2 = s + kWaves;
+        const uint32_t ra = s_run[s], rb = s2 < nseg ? s_run[s2] : 0u;
+        const uint16_t *pa = rt + s * kPartSeg + (ra & 0xFFFFu);
+        const uint16_t *pb = rt + s2 * kPartSeg + (rb & 0xFFFFu);
+        const uint32_t la = ra >> 16, lb = rb >> 16;
+        const uint32_t lm = max(la, lb);
+        for (uint32_t i = lane; i < lm; i += 64) {
+            const uint32_t va = i < la ? pa[i] : 0xFFFFu;
+            const uint32_t vb = i < lb ? pb[i] : 0xFFFFu;
+            if (va != 0xFFFFu) atomicAdd(&s_cnt[va & (kPartR - 1)], (va >> kPartLog2R) & 1u ? -1 : 1);
+            if (vb != 0xFFFFu) atomicAdd(&s_cnt[vb & (kPartR - 1)], (vb >> kPartLog2R) & 1u ? -1 : 1);
+        }
+    }
+    // hot tuples of every segment whose bucket falls in this range
+    PartHasher<NC, FAST> hs;
+    hs.plan = plan;
+    hs.mmask = m - 1;
+    hs.canon_thresh = canon_thresh;
+    hs.load(coef + (size_t)t * cpr);
+    for (uint64_t s = threadIdx.x; s < nseg; s += kPAB) {
+        const PartHot h = hot[s];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            if (h.sum[k] == 0) continue;
+            uint32_t x[NC];
+            x[0] = h.key[k][0];
+            if constexpr (NC == 2) x[1] = h.key[k][1];
+            uint32_t j, ng, f;
+            hs.hash(x, j, ng, f);
+            if (f >= canon_thresh) hs.exact(x, j, ng);
+            const uint32_t b = hs.bucket(j);
+            if ((int)(b >> kPartLog2R) == r) atomicAdd(&s_cnt[b & (kPartR - 1)], ng ? -h.sum[k] : h.sum[k]);
         }
     }
     __syncthreads();
-    const int total = s_pre[tiles];
-    // The tile of record g is the largest tile with s_pre[tile] <= g: a binary search
-    // with the same number of steps for every record, so that a thread's searches for
-    // its kAccU records advance together (independent LDS loads in flight, then
-    // independent global loads) instead of one data-dependent loop after another.
-    constexpr int kAccU = 4;
-    int top = 0;  // largest power of two <= tiles - 1
-    if (tiles > 1) {
-        top = 1;
-        while (2 * top <= tiles - 1) top *= 2;
-    }
-    for (int g0 = threadIdx.x; g0 < total; g0 += kAccU * kPAB) {
-        int g[kAccU], lo[kAccU];
-#pragma unroll
-        for (int u = 0; u < kAccU; ++u) {
-            g[u] = g0 + u * kPAB;
-            lo[u] = 0;
-        }
-        for (int step = top; step > 0; step >>= 1) {
-#pragma unroll
-            for (int u = 0; u < kAccU; ++u) {
-                const int c = lo[u] + step;
-                if (c < tiles && s_pre[c] <= g[u]) lo[u] = c;
-            }
-        }
-        uint32_t v[kAccU];
-#pragma unroll
-        for (int u = 0; u < kAccU; ++u)
-            v[u] = g[u] < total ? rec[((size_t)lo[u] * d + t) * kPartTile + s_beg[lo[u]] + (g[u] - s_pre[lo[u]])] : 0u;
-#pragma unroll
-        for (int u = 0; u < kAccU; ++u)
-            if (g[u] < total) atomicAdd(&s_acc[v[u] & 0x1FFFu], (int32_t)v[u] >> 13);
-    }
-    __syncthreads();
-    uint64_t *out = sketch + (size_t)t * m + ((size_t)r << log2R);
-    const int span = (int)min((uint32_t)R, m - ((uint32_t)r << log2R));  // the last range may be partial
-    for (int e = threadIdx.x; e < span; e += kPAB) {
-        const int32_t v = s_acc[e];
+    uint64_t *out = sketch + (uint64_t)t * m + ((uint64_t)r << kPartLog2R);
+    const uint32_t span = min(kPartR, m - ((uint32_t)r << kPartLog2R));  // the last range may be partial
+    for (uint32_t e = threadIdx.x; e < span; e += kPAB) {
+        const int32_t v = s_cnt[e];
         if (v) out[e] += (uint64_t)(int64_t)v;
     }
+    (void)lane;
 }
 
 template <int NC>
@@ -1180,34 +1310,59 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
     }
     if (strategy == CS_UPDATE_PARTITION) {
         if constexpr (NC > 2) return fail(CS_EINVAL, "the partition strategy handles at most 2 key columns");
-        if (a.weights && !a.unit_weights)
-            return fail(CS_EINVAL, "the partition strategy needs weights NULL or flagged as +-1");
-        if (!a.scratch) return fail(CS_EINVAL, "the partition strategy needs a scratch buffer");
-        const PartGeom pg = part_geometry(a.m, a.d, a.scratch_bytes);
-        if (pg.chunk == 0) return fail(CS_EINVAL, "scratch buffer too small for the partition strategy");
-        bool e1 = pow2;  // one-join columns and m a power of two: the fast hash
-        for (int c = 0; c < a.plan.n_cols; ++c) e1 = e1 && a.plan.n_edges[c] == 1;
-        uint32_t *rec = reinterpret_cast<uint32_t *>(a.scratch);
-        int32_t *tab = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(a.scratch) + pg.tab_offset);
-        const size_t max_tiles = pg.chunk / kPartTile;
-        const size_t lds = (((size_t)1 << pg.log2R) + 2 * max_tiles + 1) * sizeof(int32_t);
-        CSK_MARK(a.ev_start, s);  // both passes over every chunk
-        for (uint64_t base = 0; base < a.n; base += pg.chunk) {
-            const uint64_t cn = a.n - base < pg.chunk ? a.n - base : pg.chunk;
-            const int tiles = (int)((cn + kPartTile - 1) / kPartTile);
-            const uint32_t *kb = a.keys + base * a.plan.n_cols;
-            const bool v2 = NC == 2 && ((uintptr_t)kb % 8) == 0;
-            auto hash_kern = e1 ? &k_part_hash<NC, true> : &k_part_hash<NC, false>;
-            hipLaunchKernelGGL(hash_kern, dim3(tiles), dim3(kPB), 0, s, kb,
-                               a.weights ? a.weights + base : nullptr, cn, a.coef, a.plan.coef_per_rep, plan, a.m,
-                               a.d, pg.log2R, pg.ranges, v2, rec, tab, a.canon_thresh);
-            CSK_HIP(hipGetLastError());
-            hipLaunchKernelGGL(k_part_accum, dim3(pg.ranges, a.d), dim3(kPAB), lds, s, rec, tab, tiles, a.d,
-                               pg.ranges, pg.log2R, a.m, a.sketch);
-            CSK_HIP(hipGetLastError());
+        else {
+            if (a.weights && !a.unit_weights)
+                return fail(CS_EINVAL, "the partition strategy needs weights NULL or flagged as +-1");
+            if (!a.scratch) return fail(CS_EINVAL, "the partition strategy needs a scratch buffer");
+            const PartGeom pg = part_geometry(a.m, a.d, a.scratch_bytes);
+            if (pg.chunk == 0) return fail(CS_EINVAL, "scratch buffer too small for the partition strategy");
+            bool fast = pow2;  // one-join columns and m a power of two: the fast hash
+            for (int c = 0; c < a.plan.n_cols; ++c) fast = fast && a.plan.n_edges[c] == 1;
+            uint16_t *rec = reinterpret_cast<uint16_t *>(a.scratch);
+            uint16_t *tab = reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(a.scratch) + pg.tab_offset);
+            PartHot *hot = reinterpret_cast<PartHot *>(reinterpret_cast<char *>(a.scratch) + pg.hot_offset);
+            // timing events: around the hashing pass when the call is one chunk, else
+            // around both passes of every chunk
+            const bool one_chunk = a.n <= pg.chunk;
+            CSK_MARK(a.ev_start, s);
+            for (uint64_t base = 0; base < a.n; base += pg.chunk) {
+                const uint64_t cn = a.n - base < pg.chunk ? a.n - base : pg.chunk;
+                const uint64_t nseg = (cn + kPartSeg - 1) / kPartSeg;
+                const uint32_t *kb = a.keys + base * NC;
+                const int64_t *wb = a.weights ? a.weights + base : nullptr;
+                const bool a16 = (reinterpret_cast<uintptr_t>(kb) & 15) == 0 && (reinterpret_cast<uintptr_t>(wb) & 15) == 0;
+                // enough repetition groups for about 20 wavefronts per CU
+                int per = (int)std::max<uint64_t>(1, (uint64_t)a.d * nseg / ((uint64_t)n_cu * 20));
+                per = std::min(per, a.d);
+                const int groups = (a.d + per - 1) / per;
+                auto pick = [&](auto fst, auto hw, auto al) {
+                    constexpr bool F = decltype(fst)::value, H = decltype(hw)::value, A = decltype(al)::value;
+                    return &k_part_hash<NC, F, H, A>;
+                };
+                using T_ = std::true_type;
+                using F_ = std::false_type;
+                auto hk = fast ? (wb ? (a16 ? pick(T_{}, T_{}, T_{}) : pick(T_{}, T_{}, F_{}))
+                                     : (a16 ? pick(T_{}, F_{}, T_{}) : pick(T_{}, F_{}, F_{})))
+                               : (wb ? (a16 ? pick(F_{}, T_{}, T_{}) : pick(F_{}, T_{}, F_{}))
+                                     : (a16 ? pick(F_{}, F_{}, T_{}) : pick(F_{}, F_{}, F_{})));
+                const uint64_t sblocks = (nseg + kPB / 64 - 1) / (kPB / 64);
+                hipLaunchKernelGGL(hk, dim3((unsigned)sblocks, (unsigned)groups), dim3(kPB), 0, s, kb, wb, cn, a.coef,
+                                   a.plan.coef_per_rep, plan, a.m, a.d, pg.ranges, per, nseg, rec, tab, hot,
+                                   a.canon_thresh);
+                CSK_HIP(hipGetLastError());
+                if (one_chunk) CSK_MARK(a.ev_stop, s);
+                auto ak = fast ? &k_part_accum<NC, true> : &k_part_accum<NC, false>;
+                const size_t lds = (size_t)kPartR * 4 + (size_t)nseg * 4;
+                CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(ak),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+                hipLaunchKernelGGL(ak, dim3((unsigned)pg.ranges, (unsigned)a.d), dim3(kPAB), lds, s, rec, tab, hot,
+                                   nseg, pg.ranges, a.m, a.coef, a.plan.coef_per_rep, plan, a.sketch,
+                                   a.canon_thresh);
+                CSK_HIP(hipGetLastError());
+            }
+            if (!one_chunk) CSK_MARK(a.ev_stop, s);
+            return CS_OK;
         }
-        CSK_MARK(a.ev_stop, s);
-        return CS_OK;
     }
     return fail(CS_EINVAL, "unknown update strategy");
 }
@@ -1260,30 +1415,34 @@ SegGeom seg16_geometry(uint32_t m, int32_t d, size_t scratch_bytes, uint64_t n)
     return g;
 }
 
+// Records (2 bytes per tuple and repetition), range starts (2 bytes per range and
+// repetition, plus a total) and the hot-tuple entry, per 1024-tuple segment.
+static size_t part_bytes_per_segment(int32_t d, int32_t ranges)
+{
+    return (size_t)d * kPartSeg * 2 + (size_t)d * (ranges + 1) * 2 + sizeof(PartHot);
+}
+
 PartGeom part_geometry(uint32_t m, int32_t d, size_t scratch_bytes)
 {
     PartGeom g{};
-    // about 256+ (repetition, range) workgroups in pass 2; ranges of 2^log2R buckets
-    // (the last one partial when m is not a power of two)
-    int ranges = 1;
-    while (ranges * d < 256 && ranges < kMaxPartRanges) ranges <<= 1;
-    int log2m = 0;
-    while ((1u << log2m) < m) ++log2m;
-    int log2R = log2m;
-    while ((1 << (log2m - log2R)) < ranges && log2R > 0) --log2R;
-    if (log2R > 13) log2R = 13;       // pass-2 LDS: 2^13 int32 = 32 KB
-    g.log2R = log2R;
-    g.ranges = (int)(((uint64_t)m + (1u << log2R) - 1) >> log2R);
-    if (g.ranges > kMaxPartRanges) {  // m beyond 2^13 * kMaxPartRanges
-        g.chunk = 0;
-        return g;
+    g.ranges = (int32_t)(((uint64_t)m + kPartR - 1) >> kPartLog2R);
+    if (g.ranges > kMaxPartRanges) return g;  // chunk 0: not applicable
+    uint64_t nseg = scratch_bytes / part_bytes_per_segment(d, g.ranges);
+    nseg = std::min<uint64_t>(nseg, kPartMaxChunk / kPartSeg);
+    g.nseg = nseg;
+    g.chunk = nseg * kPartSeg;
+    // 256-byte aligned pieces: records, then range starts, then hot tuples
+    const size_t rec_bytes = (size_t)d * nseg * kPartSeg * 2;
+    const size_t tab_bytes = (size_t)d * nseg * (g.ranges + 1) * 2;
+    g.tab_offset = rec_bytes;
+    g.hot_offset = (g.tab_offset + tab_bytes + 255) & ~(size_t)255;
+    if (g.hot_offset + nseg * sizeof(PartHot) > scratch_bytes && nseg > 0) {  // alignment slack
+        --nseg;
+        g.nseg = nseg;
+        g.chunk = nseg * kPartSeg;
+        g.tab_offset = (size_t)d * nseg * kPartSeg * 2;
+        g.hot_offset = (g.tab_offset + (size_t)d * nseg * (g.ranges + 1) * 2 + 255) & ~(size_t)255;
     }
-    // chunk: records (4 bytes per distinct tuple and repetition) + range table per tile
-    const uint64_t per_tile = (uint64_t)kPartTile * d * 4 + (uint64_t)d * (g.ranges + 1) * 4;
-    uint64_t tiles = scratch_bytes / per_tile;
-    if (tiles > (kPartMaxChunk / kPartTile)) tiles = kPartMaxChunk / kPartTile;
-    g.chunk = tiles * kPartTile;
-    g.tab_offset = (size_t)tiles * kPartTile * d * 4;
     return g;
 }
 
@@ -1300,11 +1459,11 @@ size_t seg_scratch_bytes(uint32_t m, int32_t d)
         best = std::max<size_t>(best, (size_t)g16.chunks * cells * 2);
     }
     // the partition strategy's chunk of kPartMaxChunk tuples where it is the automatic
-    // choice (m > 2^16); below, chunks of 32 tiles (it runs there only when asked for)
+    // choice (m > 2^16); below, chunks of 64 segments (it runs there only when asked for)
     {
-        const PartGeom pg = part_geometry(m, d, (size_t)-1);
-        const uint64_t tiles = m > (1u << 16) ? kPartMaxChunk / kPartTile : 32;
-        best = std::max<size_t>(best, (size_t)(tiles * kPartTile * d * 4 + tiles * d * (pg.ranges + 1) * 4));
+        const int32_t ranges = (int32_t)(((uint64_t)m + kPartR - 1) >> kPartLog2R);
+        const uint64_t nseg = m > (1u << 16) ? kPartMaxChunk / kPartSeg : 64;
+        best = std::max<size_t>(best, (size_t)nseg * part_bytes_per_segment(d, ranges) + 512);
     }
     return best;
 }
