@@ -765,39 +765,43 @@ __global__ void k_seg_reduce(const CT *__restrict__ partial, int32_t C, uint64_t
 // Deltas must be +1 (weights NULL) or +-1 (flag CS_UPDATE_UNIT_WEIGHTS).  The tuples
 // run in chunks of at most kPartMaxChunk (two kernels per chunk).
 //
-// Pass 1 (k_part_hash): a wavefront owns a segment of kPartSeg consecutive tuples,
-// loads its keys once (quads of consecutive tuples per lane, 16-byte loads) and loops
-// over a group of repetitions.  Per repetition it hashes its tuples, counts them per
-// bucket range in its own LDS histogram (the add's returned value is each record's
-// rank; four sub-histograms by lane & 3 keep lanes of one wavefront apart), scans the
-// histogram across its lanes, scatters the records into its LDS staging area by range,
-// and stores the segment's records and range starts, both coalesced.  No workgroup
-// barrier: the wavefronts of a workgroup are independent.
+// Pass 1 (k_part_hash): a workgroup owns a block of kPartBlk consecutive tuples; each
+// of its four wavefronts loads the keys of its quarter once (quads of consecutive
+// tuples per lane, 16-byte loads) and the workgroup loops over a group of repetitions.
+// Per repetition every wavefront hashes its tuples and ranks them per bucket range in
+// its own LDS histogram (the add's returned value is the record's rank; four
+// sub-histograms by lane & 3 keep a wavefront's lanes apart); one scan across ranges
+// and wavefronts places each range's run, padded to a multiple of four records, in the
+// block's LDS staging area; the block's records and run starts leave coalesced.
 //
 // Zipf-skewed keys put a large share of a stream on a few tuples; left alone, pass 2's
 // LDS adds on their buckets would serialise (same-address atomics) and the workgroup of
 // their range would carry most records.  Each wavefront therefore elects up to two hot
-// tuples among a sample of its segment, sums their Deltas instead of emitting records
-// for them, and leaves (tuple, Delta sum) in a per-segment list that pass 2 hashes once
-// per repetition.  The sketch is linear (Sec. 2.2): n equal tuples with Deltas
-// Delta_i add sum_i Delta_i at their one counter, so the counters are unchanged.
+// tuples among a sample of its quarter, sums their Deltas instead of emitting records
+// for them, and leaves (tuple, Delta sum) in a list that pass 2 hashes once per
+// repetition.  The sketch is linear (Sec. 2.2): n equal tuples with Deltas Delta_i add
+// sum_i Delta_i at their one counter, so the counters are unchanged.
 //
 // Pass 2 (k_part_accum): workgroup (range r, repetition t) zeroes 2^14 int32 LDS
-// counters, adds +-1 for every record of its group from every segment, adds the hot
-// tuples whose bucket falls in its range, and adds the non-zero sums into the sketch
-// (it owns those counters: plain read-modify-write, no atomics).
+// counters, adds +-1 for every record of its group from every block (8-byte loads of
+// four records, four runs in flight per wavefront), adds the hot tuples whose bucket
+// falls in its range, and adds the non-zero sums into the sketch (it owns those
+// counters: plain read-modify-write, no atomics).
 
 constexpr int kPartLog2R = 14;                   // buckets per range (pass-2 LDS: 64 KB of int32)
 constexpr uint32_t kPartR = 1u << kPartLog2R;
-constexpr int kPartQuads = 4;                    // quads of tuples per lane and segment
-constexpr int kPartSlots = 4 * kPartQuads;       // tuples per lane and segment
-constexpr int kPartSeg = 64 * kPartSlots;        // 1024 tuples per wavefront segment
+constexpr int kPartQuads = 4;                    // quads of tuples per lane
+constexpr int kPartSlots = 4 * kPartQuads;       // tuples per lane
+constexpr int kPartWave = 64 * kPartSlots;       // 1024 tuples per wavefront
+constexpr int kPB = 256;                         // pass-1 workgroup: 4 wavefronts
+constexpr int kPartBlk = kPartWave * (kPB / 64); // 4096 tuples per block
+constexpr int kPartBlkCap = kPartBlk + 4 * 64;   // records of a block and repetition, runs padded to 4
 constexpr int kPartHS = 4;                       // sub-histograms per range
-constexpr int kPB = 256;                         // pass-1 workgroup: 4 independent wavefronts
-constexpr int kPAB = 512;                        // pass-2 workgroup
+constexpr int kPAB = 1024;                       // pass-2 workgroup
 constexpr uint32_t kPartNone = 0xFFFFFFFFu;      // a slot without a record
-static_assert(kMaxPartRanges * kPartHS <= 64 * kPartHS && kMaxPartRanges <= 64, "one lane per bucket range");
-static_assert(kPartSeg <= 0xFFFF, "range starts are 16-bit");
+constexpr uint16_t kPartPad = 0xFFFFu;           // padding record (bit 15 set: never a real one)
+static_assert(kMaxPartRanges <= 64, "one lane per bucket range");
+static_assert(kPartBlkCap <= 0xFFFF && kPartBlkCap % 8 == 0, "16-bit run starts, 16-byte stores");
 static_assert(sizeof(PartHot) == 24, "hot-tuple entry layout");
 
 template <int NC>
@@ -831,7 +835,7 @@ struct PartHasher {
     CoefE1<NC> K;
     const uint64_t *cf;
     DevPlan plan;
-    uint32_t mmask, canon_thresh;
+    uint32_t mmask;
     __device__ __forceinline__ void load(const uint64_t *coef_t)
     {
         cf = coef_t;
@@ -856,29 +860,29 @@ struct PartHasher {
     __device__ __forceinline__ uint32_t bucket(uint32_t j) const { return FAST ? (j & mmask) : j; }
 };
 
-// Pass 1.  Grid (segment blocks, repetition groups), mapped by seg_tile() so that the
-// groups of one segment block share an XCD (its L2 fetches the keys once).
+// Pass 1.  Grid (blocks, repetition groups), mapped by seg_tile() so that the groups of
+// one block share an XCD (its L2 fetches the keys once).
 template <int NC, bool FAST, bool HW, bool A16>
 __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict__ keys,
-                                                      const int64_t *__restrict__ weights, uint64_t n,
-                                                      const uint64_t *__restrict__ coef, int32_t cpr,
-                                                      DevPlan plan, uint32_t m, int32_t d, int32_t ranges,
-                                                      int32_t reps_per_group, uint64_t nseg, uint16_t *rec_out,
-                                                      uint16_t *tab, PartHot *hot, uint32_t canon_thresh)
+                                                         const int64_t *__restrict__ weights, uint64_t n,
+                                                         const uint64_t *__restrict__ coef, int32_t cpr,
+                                                         DevPlan plan, uint32_t m, int32_t d, int32_t ranges,
+                                                         int32_t reps_per_group, uint64_t nblk, uint16_t *rec_out,
+                                                         uint16_t *tab, PartHot *hot, uint32_t canon_thresh)
 {
     static_assert(NC == 1 || NC == 2, "one- and two-column relations");
     __shared__ __align__(16) uint32_t s_hist[kPB / 64][64 * kPartHS];
-    __shared__ __align__(16) uint16_t s_stage[kPB / 64][kPartSeg];
+    __shared__ uint32_t s_tot[kPB / 64][64];
+    __shared__ __align__(16) uint16_t s_stage[kPartBlkCap];
     const SegTile wg = seg_tile();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint64_t seg = (uint64_t)wg.chunk * (kPB / 64) + wave;
-    if (seg >= nseg) return;  // wave-uniform; this kernel has no workgroup barrier
+    const uint64_t blk = wg.chunk;
     const int t0 = (int)wg.seg * reps_per_group;
     const int t1 = min(d, t0 + reps_per_group);
-    const uint64_t base = seg * kPartSeg;
-    const bool full = base + kPartSeg <= n;
+    const uint64_t base = blk * kPartBlk + (uint64_t)wave * kPartWave;
+    const bool full = base + kPartWave <= n;
 
-    // ---- keys of the segment: slot s = 4 q + g is tuple base + 4 (64 q + lane) + g
+    // ---- keys of this wavefront's quarter: slot s = 4 q + g is tuple base + 4 (64 q + lane) + g
     uint32_t x[kPartSlots][NC];
     uint32_t valid = 0, wneg = 0;  // bit s: slot s holds a tuple / its Delta is -1
 #pragma unroll
@@ -941,11 +945,11 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
 #pragma unroll
             for (int c = 0; c < NC; ++c) kc[c] = __builtin_amdgcn_readlane(x[0][c], cand);
             if (!((__builtin_amdgcn_readlane(valid, cand)) & 1u)) continue;
+            if (best[0] > 0 && same_key<NC>(kc, bk[0])) continue;
+            if (best[1] > 0 && same_key<NC>(kc, bk[1])) continue;
             uint32_t cnt = 0;
 #pragma unroll
             for (int s = 0; s < 8; ++s) cnt += (uint32_t)__popcll(__ballot(((valid >> s) & 1u) && same_key<NC>(x[s], kc)));
-            if (best[0] > 0 && same_key<NC>(kc, bk[0])) continue;
-            if (best[1] > 0 && same_key<NC>(kc, bk[1])) continue;
             if (cnt > best[0]) {
                 best[1] = best[0];
 #pragma unroll
@@ -993,16 +997,14 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
             h.key[k][1] = NC == 2 ? H[k][NC - 1] : 0u;
             h.sum[k] = k < nh ? hsum[k] : 0;
         }
-        hot[seg] = h;
+        hot[blk * (kPB / 64) + wave] = h;
     }
 
     // ---- per repetition: hash, rank by range, scan, scatter, store
     PartHasher<NC, FAST> hs;
     hs.plan = plan;
     hs.mmask = m - 1;
-    hs.canon_thresh = canon_thresh;
     uint32_t *hist = s_hist[wave];
-    uint16_t *stage = s_stage[wave];
     const uint32_t sub = lane & (kPartHS - 1);
     for (int t = t0; t < t1; ++t) {
         hs.load(coef + (size_t)t * cpr);
@@ -1010,7 +1012,7 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
         wave_sync();
         uint32_t P[kPartSlots];
         // tuples hashed together: four one-column or two two-column tuples (eight or
-        // four independent Horner chains) keep the register count near 100
+        // four independent Horner chains) keep the register count within 128
         constexpr int G = NC == 1 ? 4 : 2;
 #pragma unroll
         for (int q = 0; q < kPartSlots / G; ++q) {
@@ -1037,44 +1039,55 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
                     const uint32_t b = hs.bucket(j[g]);
                     const uint32_t r = b >> kPartLog2R;
                     const uint32_t rc = (b & (kPartR - 1)) | (((ng[g] ^ (wneg >> s)) & 1u) << kPartLog2R);
-                    const uint32_t pos = atomicAdd(&hist[r * kPartHS + sub], 1u);
+                    const uint32_t pos = atomicAdd(&hist[r * kPartHS + sub], 1u);  // < 256
                     P[s] = rc | (r << 15) | (pos << 21);
                 }
             }
         }
         wave_sync();
-        // exclusive scan over (range, sub-histogram): lane L holds range L's four counts
+        // run of range L: this wavefront's four sub-counts, their prefix, the totals of
+        // every wavefront; the block's runs padded to multiples of four records
         const uint4 h4 = reinterpret_cast<const uint4 *>(hist)[lane];
         const uint32_t e1 = h4.x, e2 = e1 + h4.y, e3 = e2 + h4.z, tot = e3 + h4.w;
-        uint32_t incl = tot;
+        s_tot[wave][lane] = tot;
+        __syncthreads();
+        uint32_t before = 0, rtot = 0;
+#pragma unroll
+        for (int w = 0; w < kPB / 64; ++w) {
+            const uint32_t v = s_tot[w][lane];
+            before += w < wave ? v : 0u;
+            rtot += v;
+        }
+        const uint32_t padded = (rtot + 3u) & ~3u;
+        uint32_t incl = padded;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const uint32_t y = __shfl_up(incl, o, 64);
             if (lane >= o) incl += y;
         }
-        const uint32_t excl = incl - tot;
-        reinterpret_cast<uint4 *>(hist)[lane] = make_uint4(excl, excl + e1, excl + e2, excl + e3);
-        uint16_t *tb = tab + ((uint64_t)t * nseg + seg) * (uint64_t)(ranges + 1);
-        if (lane < ranges) tb[lane] = (uint16_t)excl;
+        const uint32_t start = incl - padded;
+        const uint32_t wb = start + before;
+        reinterpret_cast<uint4 *>(hist)[lane] = make_uint4(wb, wb + e1, wb + e2, wb + e3);
         const uint32_t total = __shfl(incl, 63, 64);
-        if (lane == 0) tb[ranges] = (uint16_t)total;
+        if (wave == 0) {
+            uint16_t *tb = tab + ((uint64_t)t * nblk + blk) * (uint64_t)(ranges + 1);
+            if (lane < ranges) tb[lane] = (uint16_t)start;
+            if (lane == 0) tb[ranges] = (uint16_t)total;
+            for (uint32_t e = start + rtot; e < start + padded; ++e) s_stage[e] = kPartPad;
+        }
         wave_sync();
 #pragma unroll
         for (int s = 0; s < kPartSlots; ++s) {
             if (P[s] != kPartNone) {
                 const uint32_t r = (P[s] >> 15) & 63u;
-                stage[hist[r * kPartHS + sub] + (P[s] >> 21)] = (uint16_t)(P[s] & 0x7FFFu);
+                s_stage[hist[r * kPartHS + sub] + (P[s] >> 21)] = (uint16_t)(P[s] & 0x7FFFu);
             }
         }
-        wave_sync();
-        uint4 *dst = reinterpret_cast<uint4 *>(rec_out + ((uint64_t)t * nseg + seg) * kPartSeg);
-        const uint4 *src = reinterpret_cast<const uint4 *>(stage);
-        constexpr int kVec = kPartSeg * 2 / 16;  // 16-byte pieces of the staging area
-#pragma unroll
-        for (int v = lane; v < kVec; v += 64) {
-            if ((uint32_t)v * 8 < total) dst[v] = src[v];
-        }
-        wave_sync();
+        __syncthreads();
+        uint4 *dst = reinterpret_cast<uint4 *>(rec_out + ((uint64_t)t * nblk + blk) * kPartBlkCap);
+        const uint4 *src = reinterpret_cast<const uint4 *>(s_stage);
+        for (uint32_t v = threadIdx.x; v * 8 < total; v += kPB) dst[v] = src[v];
+        __syncthreads();
     }
 }
 
@@ -1082,49 +1095,61 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
 template <int NC, bool FAST>
 __global__ __launch_bounds__(kPAB) void k_part_accum(const uint16_t *__restrict__ rec,
                                                      const uint16_t *__restrict__ tab,
-                                                     const PartHot *__restrict__ hot, uint64_t nseg,
+                                                     const PartHot *__restrict__ hot, uint64_t nblk,
                                                      int32_t ranges, uint32_t m, const uint64_t *__restrict__ coef,
                                                      int32_t cpr, DevPlan plan, uint64_t *sketch,
                                                      uint32_t canon_thresh)
 {
     extern __shared__ __align__(16) uint32_t s_dyn[];
     int32_t *s_cnt = reinterpret_cast<int32_t *>(s_dyn);  // [kPartR]
-    uint32_t *s_run = s_dyn + kPartR;                      // [nseg]: start | length << 16
+    uint32_t *s_run = s_dyn + kPartR;                      // [nblk]: start / 4 | words << 16
     const int r = blockIdx.x, t = blockIdx.y;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     constexpr int kWaves = kPAB / 64;
+    constexpr int kInFlight = 4;  // runs per wavefront whose loads are issued together
     for (uint32_t e = threadIdx.x; e < kPartR / 4; e += kPAB) reinterpret_cast<int4 *>(s_cnt)[e] = make_int4(0, 0, 0, 0);
-    for (uint64_t s = threadIdx.x; s < nseg; s += kPAB) {
-        const uint16_t *tb = tab + ((uint64_t)t * nseg + s) * (uint64_t)(ranges + 1);
-        const uint32_t beg = tb[r], end = tb[r + 1];
-        s_run[s] = beg | ((end - beg) << 16);
+    for (uint64_t b = threadIdx.x; b < nblk; b += kPAB) {
+        const uint16_t *tb = tab + ((uint64_t)t * nblk + b) * (uint64_t)(ranges + 1);
+        const uint32_t beg = tb[r], end = tb[r + 1];  // multiples of 4
+        s_run[b] = (beg >> 2) | (((end - beg) >> 2) << 16);
     }
     __syncthreads();
-    // records: each wavefront takes every kWaves-th segment, two at a time so that two
-    // loads are in flight before their LDS adds
-    const uint16_t *rt = rec + (uint64_t)t * nseg * kPartSeg;
-    for (uint64_t s = wave; s < nseg; s += 2 * kWaves) {
-        const uint64_t s2 = s + kWaves;
-        const uint32_t ra = s_run[s], rb = s2 < nseg ? s_run[s2] : 0u;
-        const uint16_t *pa = rt + s * kPartSeg + (ra & 0xFFFFu);
-        const uint16_t *pb = rt + s2 * kPartSeg + (rb & 0xFFFFu);
-        const uint32_t la = ra >> 16, lb = rb >> 16;
-        const uint32_t lm = max(la, lb);
-        for (uint32_t i = lane; i < lm; i += 64) {
-            const uint32_t va = i < la ? pa[i] : 0xFFFFu;
-            const uint32_t vb = i < lb ? pb[i] : 0xFFFFu;
-            if (va != 0xFFFFu) atomicAdd(&s_cnt[va & (kPartR - 1)], (va >> kPartLog2R) & 1u ? -1 : 1);
-            if (vb != 0xFFFFu) atomicAdd(&s_cnt[vb & (kPartR - 1)], (vb >> kPartLog2R) & 1u ? -1 : 1);
+    auto add4 = [&](uint2 w) {
+        const uint32_t v[4] = {w.x & 0xFFFFu, w.x >> 16, w.y & 0xFFFFu, w.y >> 16};
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (v[k] != kPartPad) atomicAdd(&s_cnt[v[k] & (kPartR - 1)], (v[k] >> kPartLog2R) & 1u ? -1 : 1);
+    };
+    // records: wavefront w takes blocks w, w + kWaves, ..., kInFlight of them at a time;
+    // a run of L words is read by lanes 0..L-1 (one 8-byte word of four records each)
+    const uint2 *rt = reinterpret_cast<const uint2 *>(rec + (uint64_t)t * nblk * kPartBlkCap);
+    for (uint64_t b0 = wave; b0 < nblk; b0 += (uint64_t)kWaves * kInFlight) {
+        uint32_t run[kInFlight];
+        const uint2 *p[kInFlight];
+        uint32_t lmax = 0;
+#pragma unroll
+        for (int u = 0; u < kInFlight; ++u) {
+            const uint64_t b = b0 + (uint64_t)u * kWaves;
+            run[u] = b < nblk ? s_run[b] : 0u;
+            p[u] = rt + (b < nblk ? b : 0) * (kPartBlkCap / 4) + (run[u] & 0xFFFFu);
+            lmax = max(lmax, run[u] >> 16);
+        }
+        for (uint32_t i = lane; i < lmax; i += 64) {
+            uint2 w[kInFlight];
+#pragma unroll
+            for (int u = 0; u < kInFlight; ++u) w[u] = i < (run[u] >> 16) ? p[u][i] : make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
+#pragma unroll
+            for (int u = 0; u < kInFlight; ++u) add4(w[u]);
         }
     }
-    // hot tuples of every segment whose bucket falls in this range
+    // hot tuples of every wavefront quarter whose bucket falls in this range
     PartHasher<NC, FAST> hs;
     hs.plan = plan;
     hs.mmask = m - 1;
-    hs.canon_thresh = canon_thresh;
     hs.load(coef + (size_t)t * cpr);
-    for (uint64_t s = threadIdx.x; s < nseg; s += kPAB) {
-        const PartHot h = hot[s];
+    const uint64_t nhot = nblk * (kPB / 64);
+    for (uint64_t e = threadIdx.x; e < nhot; e += kPAB) {
+        const PartHot h = hot[e];
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             if (h.sum[k] == 0) continue;
@@ -1327,14 +1352,16 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
             CSK_MARK(a.ev_start, s);
             for (uint64_t base = 0; base < a.n; base += pg.chunk) {
                 const uint64_t cn = a.n - base < pg.chunk ? a.n - base : pg.chunk;
-                const uint64_t nseg = (cn + kPartSeg - 1) / kPartSeg;
+                const uint64_t nblk = (cn + kPartBlk - 1) / kPartBlk;
                 const uint32_t *kb = a.keys + base * NC;
                 const int64_t *wb = a.weights ? a.weights + base : nullptr;
                 const bool a16 = (reinterpret_cast<uintptr_t>(kb) & 15) == 0 && (reinterpret_cast<uintptr_t>(wb) & 15) == 0;
-                // enough repetition groups for about 20 wavefronts per CU
-                int per = (int)std::max<uint64_t>(1, (uint64_t)a.d * nseg / ((uint64_t)n_cu * 20));
-                per = std::min(per, a.d);
-                const int groups = (a.d + per - 1) / per;
+                // repetition groups: the fewest rounds of four workgroups per CU that
+                // leave every workgroup at least one repetition
+                const uint64_t slots = (uint64_t)n_cu * 4;  // resident pass-1 workgroups (128 VGPRs)
+                int groups = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)a.d, slots / std::max<uint64_t>(1, nblk)));
+                const int per = (a.d + groups - 1) / groups;
+                groups = (a.d + per - 1) / per;
                 auto pick = [&](auto fst, auto hw, auto al) {
                     constexpr bool F = decltype(fst)::value, H = decltype(hw)::value, A = decltype(al)::value;
                     return &k_part_hash<NC, F, H, A>;
@@ -1345,18 +1372,17 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
                                      : (a16 ? pick(T_{}, F_{}, T_{}) : pick(T_{}, F_{}, F_{})))
                                : (wb ? (a16 ? pick(F_{}, T_{}, T_{}) : pick(F_{}, T_{}, F_{}))
                                      : (a16 ? pick(F_{}, F_{}, T_{}) : pick(F_{}, F_{}, F_{})));
-                const uint64_t sblocks = (nseg + kPB / 64 - 1) / (kPB / 64);
-                hipLaunchKernelGGL(hk, dim3((unsigned)sblocks, (unsigned)groups), dim3(kPB), 0, s, kb, wb, cn, a.coef,
-                                   a.plan.coef_per_rep, plan, a.m, a.d, pg.ranges, per, nseg, rec, tab, hot,
+                hipLaunchKernelGGL(hk, dim3((unsigned)nblk, (unsigned)groups), dim3(kPB), 0, s, kb, wb, cn, a.coef,
+                                   a.plan.coef_per_rep, plan, a.m, a.d, pg.ranges, per, nblk, rec, tab, hot,
                                    a.canon_thresh);
                 CSK_HIP(hipGetLastError());
                 if (one_chunk) CSK_MARK(a.ev_stop, s);
                 auto ak = fast ? &k_part_accum<NC, true> : &k_part_accum<NC, false>;
-                const size_t lds = (size_t)kPartR * 4 + (size_t)nseg * 4;
+                const size_t lds = (size_t)kPartR * 4 + (size_t)nblk * 4;
                 CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(ak),
                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
                 hipLaunchKernelGGL(ak, dim3((unsigned)pg.ranges, (unsigned)a.d), dim3(kPAB), lds, s, rec, tab, hot,
-                                   nseg, pg.ranges, a.m, a.coef, a.plan.coef_per_rep, plan, a.sketch,
+                                   nblk, pg.ranges, a.m, a.coef, a.plan.coef_per_rep, plan, a.sketch,
                                    a.canon_thresh);
                 CSK_HIP(hipGetLastError());
             }
@@ -1415,11 +1441,11 @@ SegGeom seg16_geometry(uint32_t m, int32_t d, size_t scratch_bytes, uint64_t n)
     return g;
 }
 
-// Records (2 bytes per tuple and repetition), range starts (2 bytes per range and
-// repetition, plus a total) and the hot-tuple entry, per 1024-tuple segment.
-static size_t part_bytes_per_segment(int32_t d, int32_t ranges)
+// Records (2 bytes per tuple and repetition, runs padded), run starts (2 bytes per range
+// and repetition, plus a total) and the hot-tuple entries, per 4096-tuple block.
+static size_t part_bytes_per_block(int32_t d, int32_t ranges)
 {
-    return (size_t)d * kPartSeg * 2 + (size_t)d * (ranges + 1) * 2 + sizeof(PartHot);
+    return (size_t)d * kPartBlkCap * 2 + (size_t)d * (ranges + 1) * 2 + (kPB / 64) * sizeof(PartHot);
 }
 
 PartGeom part_geometry(uint32_t m, int32_t d, size_t scratch_bytes)
@@ -1427,22 +1453,16 @@ PartGeom part_geometry(uint32_t m, int32_t d, size_t scratch_bytes)
     PartGeom g{};
     g.ranges = (int32_t)(((uint64_t)m + kPartR - 1) >> kPartLog2R);
     if (g.ranges > kMaxPartRanges) return g;  // chunk 0: not applicable
-    uint64_t nseg = scratch_bytes / part_bytes_per_segment(d, g.ranges);
-    nseg = std::min<uint64_t>(nseg, kPartMaxChunk / kPartSeg);
-    g.nseg = nseg;
-    g.chunk = nseg * kPartSeg;
-    // 256-byte aligned pieces: records, then range starts, then hot tuples
-    const size_t rec_bytes = (size_t)d * nseg * kPartSeg * 2;
-    const size_t tab_bytes = (size_t)d * nseg * (g.ranges + 1) * 2;
-    g.tab_offset = rec_bytes;
+    const size_t slack = 512;                 // two 256-byte alignments
+    uint64_t nblk = scratch_bytes > slack ? (scratch_bytes - slack) / part_bytes_per_block(d, g.ranges) : 0;
+    nblk = std::min<uint64_t>(nblk, kPartMaxChunk / kPartBlk);
+    g.nseg = nblk;
+    g.chunk = nblk * kPartBlk;
+    // 256-byte aligned pieces: records, then run starts, then hot tuples
+    const size_t rec_bytes = (size_t)d * nblk * kPartBlkCap * 2;
+    const size_t tab_bytes = (size_t)d * nblk * (g.ranges + 1) * 2;
+    g.tab_offset = (rec_bytes + 255) & ~(size_t)255;
     g.hot_offset = (g.tab_offset + tab_bytes + 255) & ~(size_t)255;
-    if (g.hot_offset + nseg * sizeof(PartHot) > scratch_bytes && nseg > 0) {  // alignment slack
-        --nseg;
-        g.nseg = nseg;
-        g.chunk = nseg * kPartSeg;
-        g.tab_offset = (size_t)d * nseg * kPartSeg * 2;
-        g.hot_offset = (g.tab_offset + (size_t)d * nseg * (g.ranges + 1) * 2 + 255) & ~(size_t)255;
-    }
     return g;
 }
 
@@ -1459,11 +1479,11 @@ size_t seg_scratch_bytes(uint32_t m, int32_t d)
         best = std::max<size_t>(best, (size_t)g16.chunks * cells * 2);
     }
     // the partition strategy's chunk of kPartMaxChunk tuples where it is the automatic
-    // choice (m > 2^16); below, chunks of 64 segments (it runs there only when asked for)
+    // choice (m > 2^16); below, chunks of 16 blocks (it runs there only when asked for)
     {
         const int32_t ranges = (int32_t)(((uint64_t)m + kPartR - 1) >> kPartLog2R);
-        const uint64_t nseg = m > (1u << 16) ? kPartMaxChunk / kPartSeg : 64;
-        best = std::max<size_t>(best, (size_t)nseg * part_bytes_per_segment(d, ranges) + 512);
+        const uint64_t nblk = m > (1u << 16) ? kPartMaxChunk / kPartBlk : 16;
+        best = std::max<size_t>(best, (size_t)nblk * part_bytes_per_block(d, ranges) + 512);
     }
     return best;
 }
