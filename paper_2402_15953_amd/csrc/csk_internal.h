@@ -144,11 +144,12 @@ SegGeom seg_geometry(uint32_t m, int32_t d, bool narrow, size_t scratch_bytes, u
 SegGeom seg16_geometry(uint32_t m, int32_t d, size_t scratch_bytes, uint64_t n = ~0ull);
 constexpr int kMaxPartRanges = 64;           // bucket ranges of 2^14 per repetition (m <= 2^20)
 constexpr uint64_t kPartMaxChunk = 1ull << 21;  // tuples per pass pair
-// One segment's hot tuples for the partition strategy (see k_part_hash): up to two
+// One block's hot tuples for the partition strategy (see k_part_hash): up to eight
 // tuples (keys; column 1 unused for one-column relations) and their Delta sums.
+constexpr int kPartHot = 8;
 struct PartHot {
-    uint32_t key[2][2];
-    int32_t sum[2];
+    uint32_t key[kPartHot][2];
+    int32_t sum[kPartHot];
 };
 struct PartGeom {
     int32_t ranges;          // bucket ranges of 2^14 per repetition (the last may be partial)

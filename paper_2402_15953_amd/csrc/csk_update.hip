@@ -776,11 +776,13 @@ __global__ void k_seg_reduce(const CT *__restrict__ partial, int32_t C, uint64_t
 //
 // Zipf-skewed keys put a large share of a stream on a few tuples; left alone, pass 2's
 // LDS adds on their buckets would serialise (same-address atomics) and the workgroup of
-// their range would carry most records.  Each wavefront therefore elects up to two hot
-// tuples among a sample of its quarter, sums their Deltas instead of emitting records
-// for them, and leaves (tuple, Delta sum) in a list that pass 2 hashes once per
-// repetition.  The sketch is linear (Sec. 2.2): n equal tuples with Deltas Delta_i add
-// sum_i Delta_i at their one counter, so the counters are unchanged.
+// their range would carry most records.  Each block therefore elects up to kPartHot hot
+// tuples (sixteen candidates, the first tuples of four lanes of every wavefront, counted
+// over the first four quads of the block's lanes; kept when they hold at least 1/64 of
+// that sample), sums their Deltas instead of emitting records for them, and leaves
+// (tuple, Delta sum) in a list that pass 2 hashes once per repetition.  The sketch is
+// linear (Sec. 2.2): n equal tuples with Deltas Delta_i add sum_i Delta_i at their one
+// counter, so the counters are unchanged.
 //
 // Pass 2 (k_part_accum): workgroup (range r, repetition t) zeroes 2^14 int32 LDS
 // counters, adds +-1 for every record of its group from every block (8-byte loads of
@@ -802,7 +804,7 @@ constexpr uint32_t kPartNone = 0xFFFFFFFFu;      // a slot without a record
 constexpr uint16_t kPartPad = 0xFFFFu;           // padding record (bit 15 set: never a real one)
 static_assert(kMaxPartRanges <= 64, "one lane per bucket range");
 static_assert(kPartBlkCap <= 0xFFFF && kPartBlkCap % 8 == 0, "16-bit run starts, 16-byte stores");
-static_assert(sizeof(PartHot) == 24, "hot-tuple entry layout");
+static_assert(sizeof(PartHot) == 12 * kPartHot, "hot-tuple entry layout");
 
 template <int NC>
 __device__ __forceinline__ bool same_key(const uint32_t (&a)[NC], const uint32_t (&b)[NC])
@@ -930,74 +932,91 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
     }
     wneg &= valid;
 
-    // ---- hot tuples: candidates are the first tuples of lanes 0..7, scored by their
-    // count among the first two quads of every lane (512 tuples); the two best with at
-    // least 8 hits are taken out of the record stream
-    uint32_t H[2][NC];
-    int nh = 0;
-    {
-        uint32_t best[2] = {0u, 0u};
-        uint32_t bk[2][NC];
+    // ---- hot tuples of the block (see above)
+    constexpr int kCand = kPB / 64 * 4;
+    __shared__ uint32_t s_cand[kCand][NC];
+    __shared__ uint32_t s_ccnt[kPB / 64][kCand];
+    __shared__ uint32_t s_hot[kPartHot][NC];
+    __shared__ int32_t s_hsum[kPB / 64][kPartHot];
+    __shared__ int32_t s_nh;
+    if (lane < 4) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) bk[0][c] = bk[1][c] = 0u;
-        for (int cand = 0; cand < 8; ++cand) {
-            uint32_t kc[NC];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) kc[c] = __builtin_amdgcn_readlane(x[0][c], cand);
-            if (!((__builtin_amdgcn_readlane(valid, cand)) & 1u)) continue;
-            if (best[0] > 0 && same_key<NC>(kc, bk[0])) continue;
-            if (best[1] > 0 && same_key<NC>(kc, bk[1])) continue;
-            uint32_t cnt = 0;
-#pragma unroll
-            for (int s = 0; s < 8; ++s) cnt += (uint32_t)__popcll(__ballot(((valid >> s) & 1u) && same_key<NC>(x[s], kc)));
-            if (cnt > best[0]) {
-                best[1] = best[0];
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    bk[1][c] = bk[0][c];
-                    bk[0][c] = kc[c];
-                }
-                best[0] = cnt;
-            } else if (cnt > best[1]) {
-#pragma unroll
-                for (int c = 0; c < NC; ++c) bk[1][c] = kc[c];
-                best[1] = cnt;
-            }
-        }
-        nh = (best[0] >= 8) + (best[1] >= 8);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            H[0][c] = bk[0][c];
-            H[1][c] = bk[1][c];
-        }
+        for (int c = 0; c < NC; ++c) s_cand[wave * 4 + lane][c] = x[0][c];
     }
-    int32_t hsum[2] = {0, 0};
+    __syncthreads();
+    for (int ci = 0; ci < kCand; ++ci) {
+        uint32_t kc[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) kc[c] = s_cand[ci][c];
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int sl = 0; sl < 4; ++sl) cnt += (uint32_t)__popcll(__ballot(((valid >> sl) & 1u) && same_key<NC>(x[sl], kc)));
+        if (lane == 0) s_ccnt[wave][ci] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // candidates by total count over the 1024 sampled tuples, distinct keys, at
+        // least 16 hits (1/64), at most kPartHot of them
+        uint32_t tot[kCand];
+#pragma unroll
+        for (int ci = 0; ci < kCand; ++ci) {
+            uint32_t v = 0;
+            for (int w = 0; w < kPB / 64; ++w) v += s_ccnt[w][ci];
+#pragma unroll
+            for (int cj = 0; cj < ci; ++cj) {
+                bool same = true;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) same = same && s_cand[cj][c] == s_cand[ci][c];
+                v = same ? 0u : v;
+            }
+            tot[ci] = v;
+        }
+        int nh = 0;
+        for (int k = 0; k < kPartHot; ++k) {
+            uint32_t bv = 15u, bi = kCand;
+#pragma unroll
+            for (int ci = 0; ci < kCand; ++ci) {
+                const bool better = tot[ci] > bv;
+                bv = better ? tot[ci] : bv;
+                bi = better ? (uint32_t)ci : bi;
+            }
+            if (bi == (uint32_t)kCand) break;
+#pragma unroll
+            for (int ci = 0; ci < kCand; ++ci) tot[ci] = (uint32_t)ci == bi ? 0u : tot[ci];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) s_hot[nh][c] = s_cand[bi][c];
+            ++nh;
+        }
+        s_nh = nh;
+    }
+    __syncthreads();
+    const int nh = s_nh;
     uint32_t live = valid;  // slots that emit records
-    if (nh > 0) {
+    for (int k = 0; k < nh; ++k) {
+        uint32_t hk[NC];
 #pragma unroll
-        for (int s = 0; s < kPartSlots; ++s) {
-            if (!((valid >> s) & 1u)) continue;
-            const int32_t dl = ((wneg >> s) & 1u) ? -1 : 1;
-            if (same_key<NC>(x[s], H[0])) {
-                hsum[0] += dl;
-                live &= ~(1u << s);
-            } else if (nh > 1 && same_key<NC>(x[s], H[1])) {
-                hsum[1] += dl;
-                live &= ~(1u << s);
-            }
+        for (int c = 0; c < NC; ++c) hk[c] = s_hot[k][c];
+        int32_t sum = 0;
+#pragma unroll
+        for (int sl = 0; sl < kPartSlots; ++sl) {
+            const bool mt = ((live >> sl) & 1u) && same_key<NC>(x[sl], hk);
+            const uint64_t pos = __ballot(mt && !((wneg >> sl) & 1u));
+            const uint64_t neg = __ballot(mt && ((wneg >> sl) & 1u));
+            sum += (int32_t)__popcll(pos) - (int32_t)__popcll(neg);
+            live &= mt ? ~(1u << sl) : ~0u;
         }
+        if (lane == 0) s_hsum[wave][k] = sum;
     }
-    hsum[0] = wave_sum_i32(hsum[0]);
-    hsum[1] = wave_sum_i32(hsum[1]);
-    if (wg.seg == 0 && lane == 0) {
-        PartHot h;
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            h.key[k][0] = H[k][0];
-            h.key[k][1] = NC == 2 ? H[k][NC - 1] : 0u;
-            h.sum[k] = k < nh ? hsum[k] : 0;
-        }
-        hot[blk * (kPB / 64) + wave] = h;
+    __syncthreads();
+    if (wg.seg == 0 && threadIdx.x < kPartHot) {
+        const int k = threadIdx.x;
+        int32_t v = 0;
+        if (k < nh)
+            for (int w = 0; w < kPB / 64; ++w) v += s_hsum[w][k];
+        PartHot *h = hot + blk;
+        h->key[k][0] = k < nh ? s_hot[k][0] : 0u;
+        h->key[k][1] = k < nh ? s_hot[k][NC - 1] : 0u;
+        h->sum[k] = v;
     }
 
     // ---- per repetition: hash, rank by range, scan, scatter, store
@@ -1147,11 +1166,10 @@ __global__ __launch_bounds__(kPAB) void k_part_accum(const uint16_t *__restrict_
     hs.plan = plan;
     hs.mmask = m - 1;
     hs.load(coef + (size_t)t * cpr);
-    const uint64_t nhot = nblk * (kPB / 64);
-    for (uint64_t e = threadIdx.x; e < nhot; e += kPAB) {
-        const PartHot h = hot[e];
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
+    for (uint64_t e = threadIdx.x; e < nblk * kPartHot; e += kPAB) {
+        const PartHot &h = hot[e / kPartHot];
+        const int k = (int)(e % kPartHot);
+        {
             if (h.sum[k] == 0) continue;
             uint32_t x[NC];
             x[0] = h.key[k][0];
@@ -1445,7 +1463,7 @@ SegGeom seg16_geometry(uint32_t m, int32_t d, size_t scratch_bytes, uint64_t n)
 // and repetition, plus a total) and the hot-tuple entries, per 4096-tuple block.
 static size_t part_bytes_per_block(int32_t d, int32_t ranges)
 {
-    return (size_t)d * kPartBlkCap * 2 + (size_t)d * (ranges + 1) * 2 + (kPB / 64) * sizeof(PartHot);
+    return (size_t)d * kPartBlkCap * 2 + (size_t)d * (ranges + 1) * 2 + sizeof(PartHot);
 }
 
 PartGeom part_geometry(uint32_t m, int32_t d, size_t scratch_bytes)
