@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--cpu-slices", type=int, default=8,
                     help="CPU baseline: 2^20-tuple slices per relation for the threaded oracle")
     ap.add_argument("--strategy", type=int, default=0)
+    ap.add_argument("--chain5-calls", type=int, default=96,
+                    help="headline: update calls of 2^20 tuples per relation (fewer only for profiling)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a device copy of this many bytes (counter calibration) and exit")
     ap.add_argument("--batch-queries", type=int, default=4096,
@@ -153,7 +155,7 @@ def bench_chain5(args, dev, stream):
 
     graph = W.chain(5)
     m, d, seed, D, config = 1 << 18, 15, 8, 10 ** 7, 3
-    n_call, calls = 1 << 20, 96
+    n_call, calls = 1 << 20, args.chain5_calls
     n = n_call * calls
     exps = (0.5, 1.0, 1.5)
     r = graph.n_rel
@@ -166,7 +168,7 @@ def bench_chain5(args, dev, stream):
     t0 = time.perf_counter()
     sks = {sx: csk.Sketch(graph, m, d, seed) for sx in exps}
     init_ms = (time.perf_counter() - t0) * 1e3 / len(exps)
-    sampled_calls = (0, 31, 63, 95)
+    sampled_calls = tuple(sorted(set(min(calls - 1, c) for c in (0, 31, 63, 95))))
     kev = {k: [] for k in range(r)}
     n_timers = args.steps * len(exps) * r * len(sampled_calls) * 2 + len(exps) * (r + 2) + 8
     timers = iter([csk.Timer() for _ in range(n_timers)])

@@ -829,6 +829,17 @@ __device__ __forceinline__ int32_t wave_sum_i32(int32_t v)
     return v;
 }
 
+// Entry of a tuple in the direct-mapped table of a block's hot tuples (multiplicative
+// hashing of the key words).
+constexpr int kPartHotTab = 256;
+template <int NC>
+__device__ __forceinline__ uint32_t part_hot_slot(const uint32_t (&x)[NC])
+{
+    uint32_t h = x[0] * 0x9E3779B1u;
+    if constexpr (NC == 2) h ^= x[1] * 0x85EBCA77u;
+    return h >> 24;  // 256 entries
+}
+
 // Bucket j in [0, m) and sign bit of one tuple for one repetition: the one-join fast
 // hash (m a power of two; the full reduction only when a hash's flag asks for it, see
 // CoefE1::bin_neg_fast), or the general one (any m, any joins per column).
@@ -939,10 +950,12 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
     __shared__ uint32_t s_hot[kPartHot][NC];
     __shared__ int32_t s_hsum[kPB / 64][kPartHot];
     __shared__ int32_t s_nh;
+    __shared__ uint4 s_htab[kPartHotTab];  // key(s), index into s_hot (kPartNone: empty)
     if (lane < 4) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) s_cand[wave * 4 + lane][c] = x[0][c];
     }
+    for (int e = threadIdx.x; e < kPartHotTab; e += kPB) s_htab[e] = make_uint4(0u, 0u, kPartNone, 0u);
     __syncthreads();
     for (int ci = 0; ci < kCand; ++ci) {
         uint32_t kc[NC];
@@ -983,8 +996,14 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
             if (bi == (uint32_t)kCand) break;
 #pragma unroll
             for (int ci = 0; ci < kCand; ++ci) tot[ci] = (uint32_t)ci == bi ? 0u : tot[ci];
+            uint32_t kc[NC];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) s_hot[nh][c] = s_cand[bi][c];
+            for (int c = 0; c < NC; ++c) kc[c] = s_cand[bi][c];
+            uint4 &slot = s_htab[part_hot_slot<NC>(kc)];
+            if (slot.z != kPartNone) continue;  // entry taken by a hotter tuple
+            slot = make_uint4(kc[0], kc[NC - 1], (uint32_t)nh, 0u);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) s_hot[nh][c] = kc[c];
             ++nh;
         }
         s_nh = nh;
@@ -992,20 +1011,21 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
     __syncthreads();
     const int nh = s_nh;
     uint32_t live = valid;  // slots that emit records
-    for (int k = 0; k < nh; ++k) {
-        uint32_t hk[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) hk[c] = s_hot[k][c];
-        int32_t sum = 0;
-#pragma unroll
+    if (nh > 0) {
+        // each tuple probes one entry of a direct-mapped LDS table of the hot tuples
+        // (thread 0 placed them; a hot tuple whose entry was taken stays an ordinary
+        // one) and hot ones add their Delta to their tuple's sum
+        if (lane < kPartHot) s_hsum[wave][lane] = 0;
+        wave_sync();
         for (int sl = 0; sl < kPartSlots; ++sl) {
-            const bool mt = ((live >> sl) & 1u) && same_key<NC>(x[sl], hk);
-            const uint64_t pos = __ballot(mt && !((wneg >> sl) & 1u));
-            const uint64_t neg = __ballot(mt && ((wneg >> sl) & 1u));
-            sum += (int32_t)__popcll(pos) - (int32_t)__popcll(neg);
-            live &= mt ? ~(1u << sl) : ~0u;
+            if (!((valid >> sl) & 1u)) continue;
+            const uint4 e = s_htab[part_hot_slot<NC>(x[sl])];
+            const bool mt = e.z != kPartNone && e.x == x[sl][0] && (NC == 1 || e.y == x[sl][NC - 1]);
+            if (mt) {
+                atomicAdd(&s_hsum[wave][e.z], ((wneg >> sl) & 1u) ? -1 : 1);
+                live &= ~(1u << sl);
+            }
         }
-        if (lane == 0) s_hsum[wave][k] = sum;
     }
     __syncthreads();
     if (wg.seg == 0 && threadIdx.x < kPartHot) {
