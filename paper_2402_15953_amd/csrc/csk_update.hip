@@ -784,13 +784,15 @@ __global__ void k_seg_reduce(const CT *__restrict__ partial, int32_t C, uint64_t
 // linear (Sec. 2.2): n equal tuples with Deltas Delta_i add sum_i Delta_i at their one
 // counter, so the counters are unchanged.
 //
-// Pass 2 (k_part_accum): workgroup (range r, repetition t) zeroes 2^14 int32 LDS
-// counters, adds +-1 for every record of its group from every block (8-byte loads of
-// four records, four runs in flight per wavefront), adds the hot tuples whose bucket
-// falls in its range, and adds the non-zero sums into the sketch (it owns those
-// counters: plain read-modify-write, no atomics).
+// Pass 2 (k_part_accum): workgroup (range r, repetition t) zeroes two copies of 2^14
+// int32 LDS counters (even and odd lanes add to different copies, which halves the
+// lanes of one add that meet on a skewed bucket's word), adds +-1 for every record of
+// its group from every block (8-byte loads of four records, four runs in flight per
+// wavefront), adds the hot tuples whose bucket falls in its range, and adds the non-zero
+// sums of the two copies into the sketch (it owns those counters: plain
+// read-modify-write, no atomics).
 
-constexpr int kPartLog2R = 14;                   // buckets per range (pass-2 LDS: 64 KB of int32)
+constexpr int kPartLog2R = 14;                   // buckets per range (pass-2 LDS: two copies of 2^14 int32, 128 KB)
 constexpr uint32_t kPartR = 1u << kPartLog2R;
 constexpr int kPartQuads = 4;                    // quads of tuples per lane
 constexpr int kPartSlots = 4 * kPartQuads;       // tuples per lane
@@ -1140,13 +1142,16 @@ __global__ __launch_bounds__(kPAB) void k_part_accum(const uint16_t *__restrict_
                                                      uint32_t canon_thresh)
 {
     extern __shared__ __align__(16) uint32_t s_dyn[];
-    int32_t *s_cnt = reinterpret_cast<int32_t *>(s_dyn);  // [kPartR]
-    uint32_t *s_run = s_dyn + kPartR;                      // [nblk]: start / 4 | words << 16
+    // two copies of the counters, taken by even and odd lanes: the lanes of one add that
+    // hit a skewed bucket's word are split over two words
+    int32_t *s_cnt = reinterpret_cast<int32_t *>(s_dyn);   // [2][kPartR]
+    uint32_t *s_run = s_dyn + 2 * kPartR;                   // [nblk]: start / 4 | words << 16
     const int r = blockIdx.x, t = blockIdx.y;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int32_t *my_cnt = s_cnt + (lane & 1) * kPartR;
     constexpr int kWaves = kPAB / 64;
     constexpr int kInFlight = 4;  // runs per wavefront whose loads are issued together
-    for (uint32_t e = threadIdx.x; e < kPartR / 4; e += kPAB) reinterpret_cast<int4 *>(s_cnt)[e] = make_int4(0, 0, 0, 0);
+    for (uint32_t e = threadIdx.x; e < 2 * kPartR / 4; e += kPAB) reinterpret_cast<int4 *>(s_cnt)[e] = make_int4(0, 0, 0, 0);
     for (uint64_t b = threadIdx.x; b < nblk; b += kPAB) {
         const uint16_t *tb = tab + ((uint64_t)t * nblk + b) * (uint64_t)(ranges + 1);
         const uint32_t beg = tb[r], end = tb[r + 1];  // multiples of 4
@@ -1157,7 +1162,7 @@ __global__ __launch_bounds__(kPAB) void k_part_accum(const uint16_t *__restrict_
         const uint32_t v[4] = {w.x & 0xFFFFu, w.x >> 16, w.y & 0xFFFFu, w.y >> 16};
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            if (v[k] != kPartPad) atomicAdd(&s_cnt[v[k] & (kPartR - 1)], (v[k] >> kPartLog2R) & 1u ? -1 : 1);
+            if (v[k] != kPartPad) atomicAdd(&my_cnt[v[k] & (kPartR - 1)], (v[k] >> kPartLog2R) & 1u ? -1 : 1);
     };
     // records: wavefront w takes blocks w, w + kWaves, ..., kInFlight of them at a time;
     // a run of L words is read by lanes 0..L-1 (one 8-byte word of four records each)
@@ -1198,17 +1203,16 @@ __global__ __launch_bounds__(kPAB) void k_part_accum(const uint16_t *__restrict_
             hs.hash(x, j, ng, f);
             if (f >= canon_thresh) hs.exact(x, j, ng);
             const uint32_t b = hs.bucket(j);
-            if ((int)(b >> kPartLog2R) == r) atomicAdd(&s_cnt[b & (kPartR - 1)], ng ? -h.sum[k] : h.sum[k]);
+            if ((int)(b >> kPartLog2R) == r) atomicAdd(&my_cnt[b & (kPartR - 1)], ng ? -h.sum[k] : h.sum[k]);
         }
     }
     __syncthreads();
     uint64_t *out = sketch + (uint64_t)t * m + ((uint64_t)r << kPartLog2R);
     const uint32_t span = min(kPartR, m - ((uint32_t)r << kPartLog2R));  // the last range may be partial
     for (uint32_t e = threadIdx.x; e < span; e += kPAB) {
-        const int32_t v = s_cnt[e];
-        if (v) out[e] += (uint64_t)(int64_t)v;
+        const int64_t v = (int64_t)s_cnt[e] + (int64_t)s_cnt[kPartR + e];
+        if (v) out[e] += (uint64_t)v;
     }
-    (void)lane;
 }
 
 template <int NC>
@@ -1416,7 +1420,7 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
                 CSK_HIP(hipGetLastError());
                 if (one_chunk) CSK_MARK(a.ev_stop, s);
                 auto ak = fast ? &k_part_accum<NC, true> : &k_part_accum<NC, false>;
-                const size_t lds = (size_t)kPartR * 4 + (size_t)nblk * 4;
+                const size_t lds = (size_t)kPartR * 8 + (size_t)nblk * 4;
                 CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(ak),
                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
                 hipLaunchKernelGGL(ak, dim3((unsigned)pg.ranges, (unsigned)a.d), dim3(kPAB), lds, s, rec, tab, hot,
