@@ -259,12 +259,15 @@ typedef struct cs_predicate {
  *          (1 <= n_attrs <= CS_MAX_PREDICATES); may be NULL when n_preds = 0.
  *   preds: host array of n_preds (0..CS_MAX_PREDICATES) predicates.
  *   flags: as cs_update_ex (CS_UPDATE_UNIT_WEIGHTS ...).
- *   n_kept: optional, receives the number of tuples that passed.
- * The qualifying tuples are first copied (keys, and weights when given; their order is
- * not kept, which the counters do not depend on) into a per-device buffer that grows
- * to the largest n seen; the call waits on `stream` for that pass to read the count
- * back, then updates asynchronously like cs_update.
- * Errors: CS_EINVAL (arguments), CS_ENOMEM, CS_EDEVICE. */
+ *   n_kept: optional.  NULL: the call is asynchronous and ordered on `stream` like
+ *           cs_update.  Non-NULL: the kernels also count the tuples that passed and the
+ *           call waits on `stream` for that count.
+ * The update kernels evaluate the predicates themselves and hash only the tuples that
+ * pass (no copy of the tuples, nothing allocated): 16-bit LDS counters for m <= 2^16 and
+ * the partition strategy beyond, when every key column takes part in one join, m is a
+ * power of two, the Deltas are +-1 and the relation has at most two key columns; global
+ * atomics otherwise.
+ * Errors: CS_EINVAL (arguments), CS_EDEVICE. */
 cs_status cs_update_filtered(cs_sketch *h, int32_t rel, const uint32_t *keys, const int64_t *weights,
                              uint64_t n, const uint32_t *attrs, int32_t n_attrs,
                              const cs_predicate *preds, int32_t n_preds, int32_t flags, void *stream,

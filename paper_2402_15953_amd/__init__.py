@@ -418,10 +418,11 @@ class Sketch:
                                        UPDATE_UNIT_WEIGHTS if unit_weights else 0, _stream_ptr(stream)))
 
     def update_filtered(self, rel: int, keys, attrs, predicates, weights=None, stream=None,
-                        unit_weights: bool = False) -> int:
+                        unit_weights: bool = False, count: bool = True):
         """Stream only the tuples whose attrs satisfy every (column, lo, hi) predicate
         (lo <= attrs[i][column] <= hi); attrs: device int32/uint32 tensor [n, n_attrs].
-        Returns the number of tuples kept."""
+        count: return the number of tuples kept (the call then waits for it); with
+        count=False the call is asynchronous and returns None."""
         import torch
         if keys.dtype not in (torch.int32, torch.uint32) or not keys.is_cuda or not keys.is_contiguous():
             raise TypeError("keys must be a contiguous int32/uint32 device tensor")
@@ -439,8 +440,8 @@ class Sketch:
         kept = ctypes.c_uint64()
         _check(lib().cs_update_filtered(self._h, int(rel), ctypes.c_void_p(keys.data_ptr()), wp, int(n), ap, n_attrs,
                                         arr, len(preds), UPDATE_UNIT_WEIGHTS if unit_weights else 0,
-                                        _stream_ptr(stream), ctypes.byref(kept)))
-        return kept.value
+                                        _stream_ptr(stream), ctypes.byref(kept) if count else None))
+        return kept.value if count else None
 
     def estimate(self, stream=None, reps: bool = False) -> dict:
         e = _Estimate()

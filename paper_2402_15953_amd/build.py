@@ -18,7 +18,6 @@ SOURCES = [
     "csk_transform.hip",
     "csk_estimate.hip",
     "csk_tune.hip",
-    "csk_filter.hip",
     "csk_ams.hip",
     "csk_attr.hip",
     "csk_checkpoint.hip",

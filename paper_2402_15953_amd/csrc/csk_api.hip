@@ -327,7 +327,8 @@ cs_status create_handle(const cs_graph *graph, uint32_t m, uint32_t d, uint64_t 
             return fail(CS_ENOMEM, "update scratch allocation failed");
         }
     }
-    if (hipMemcpy(h.coef_dev, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice) != hipSuccess ||
+    if (hipMalloc(&h.kept_dev, sizeof(unsigned long long)) != hipSuccess ||
+        hipMemcpy(h.coef_dev, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(h.counters, 0, n_ctr * sizeof(int64_t)) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         hipFree(h.counters);
@@ -356,6 +357,7 @@ cs_status cs_destroy(cs_sketch *hs)
     if (h.coef_dev) hipFree(h.coef_dev);
     release_work(h.work);
     if (h.scratch) hipFree(h.scratch);
+    if (h.kept_dev) hipFree(h.kept_dev);
     hipSetDevice(cur);
     delete hs;
     return CS_OK;
@@ -468,12 +470,24 @@ cs_status cs_update_filtered(cs_sketch *hs, int32_t rel, const uint32_t *keys, c
         return cs_update_ex(hs, rel, keys, weights, n, stream, CS_UPDATE_AUTO, 0, flags);
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return filter_tuples(h.device, keys, h.g.rel[rel].n_cols, weights, n, attrs, n_attrs, f, s,
-                         [&](const uint32_t *fkeys, const int64_t *fw, uint64_t kept) -> cs_status {
-                             if (n_kept) *n_kept = kept;
-                             if (kept == 0) return CS_OK;
-                             return cs_update_ex(hs, rel, fkeys, fw, kept, stream, CS_UPDATE_AUTO, 0, flags);
-                         });
+    UpdateArgs a;
+    cs_status st = update_args(hs, rel, keys, weights, n, flags, &a);
+    if (st != CS_OK) return st;
+    a.filter = &f;
+    a.attrs = attrs;
+    a.n_attrs = n_attrs;
+    if (n_kept) {
+        a.kept = h.kept_dev;
+        st = zero_device_u64(h.kept_dev, s);
+        if (st != CS_OK) return st;
+    }
+    st = launch_update(a, CS_UPDATE_AUTO, 0, s);
+    if (st != CS_OK || !n_kept) return st;
+    unsigned long long cnt = 0;
+    CSK_HIP(hipMemcpyAsync(&cnt, h.kept_dev, sizeof(cnt), hipMemcpyDeviceToHost, s));
+    CSK_HIP(hipStreamSynchronize(s));
+    *n_kept = cnt;
+    return CS_OK;
 }
 
 cs_status cs_update(cs_sketch *hs, int32_t rel, const uint32_t *keys, const int64_t *weights, uint64_t n,

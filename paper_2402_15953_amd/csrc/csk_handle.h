@@ -63,6 +63,7 @@ struct Handle {
     void *scratch = nullptr;           // partial sums of the LDS-segmented update
     size_t scratch_bytes = 0;
     void *result_host = nullptr;       // pinned host staging for results
+    unsigned long long *kept_dev = nullptr;  // device count of a filtered update's kept tuples
 };
 
 cs_status estimate_run(Handle &h, hipStream_t s, cs_estimate_t *out, const cs_reps_t *reps);

@@ -114,6 +114,13 @@ const uint32_t *roots_mod(int device, int log2m, int prime, bool inverse, hipStr
 
 // ------------------------------------------------------------------ launchers
 
+// Conjunction of range predicates lo <= attrs[i][col] <= hi (ingestion filters).
+struct FilterSpec {
+    int32_t n;
+    int32_t col[CS_MAX_PREDICATES];
+    uint32_t lo[CS_MAX_PREDICATES], hi[CS_MAX_PREDICATES];
+};
+
 struct UpdateArgs {
     const uint32_t *keys;
     const int64_t *weights;
@@ -133,6 +140,13 @@ struct UpdateArgs {
     uint32_t canon_thresh = 0xFFFFFFFFu;
     hipEvent_t ev_start = nullptr;  // recorded just before / after the hashing kernel(s)
     hipEvent_t ev_stop = nullptr;
+    // ingestion filter (cs_update_filtered): only tuples whose attribute columns
+    // attrs [n][n_attrs] pass every predicate are sketched; kept, when set, is a device
+    // counter the kernels add the number of kept tuples to
+    const FilterSpec *filter = nullptr;
+    const uint32_t *attrs = nullptr;
+    int32_t n_attrs = 0;
+    unsigned long long *kept = nullptr;
 };
 struct SegGeom {
     uint32_t R;        // counter cells per segment
@@ -163,19 +177,9 @@ struct PartGeom {
 PartGeom part_geometry(uint32_t m, int32_t d, size_t scratch_bytes);
 size_t seg_scratch_bytes(uint32_t m, int32_t d);
 cs_status launch_update(const UpdateArgs &a, int strategy, int grid_blocks, hipStream_t s);
-// Conjunction of range predicates lo <= attrs[i][col] <= hi (ingestion filters).
-struct FilterSpec {
-    int32_t n;
-    int32_t col[CS_MAX_PREDICATES];
-    uint32_t lo[CS_MAX_PREDICATES], hi[CS_MAX_PREDICATES];
-};
-// Copies the tuples (keys, and weights when given) that satisfy f into a per-device
-// buffer (synchronous on s: the count is read back), then calls consume(keys, weights,
-// count) while still holding the buffer's lock, so the reads consume enqueues on s are
-// ordered before any later use of the buffer.
-cs_status filter_tuples(int device, const uint32_t *keys, int n_cols, const int64_t *weights, uint64_t n,
-                        const uint32_t *attrs, int n_attrs, const FilterSpec &f, hipStream_t s,
-                        const std::function<cs_status(const uint32_t *, const int64_t *, uint64_t)> &consume);
+// Sets a device word to zero with a one-thread kernel on s (no memset node, so it can be
+// captured into a graph).
+cs_status zero_device_u64(unsigned long long *p, hipStream_t s);
 // Tuned (strategy, grid, flags) for this update's class on `device`, if one was tuned.
 bool tune_lookup(const UpdateArgs &a, int device, int *strategy, int *grid, int *flags);
 int auto_update_strategy(uint32_t m, int32_t d, uint64_t n, int n_cols, bool unit, bool has_scratch,

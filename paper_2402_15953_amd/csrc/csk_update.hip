@@ -60,6 +60,58 @@ __global__ __launch_bounds__(kBlock) void k_update_global(const uint32_t *__rest
     }
 }
 
+// ---------------------------------------------------------------- ingestion filters
+//
+// Sec. 4.1 applies each query's filter predicates while its relations stream in: only
+// the tuples whose attribute columns pass every predicate reach the sketch.  The
+// filtered kernels evaluate the predicates on attrs [n][n_attrs] (tuple-major uint32)
+// themselves and hash only the tuples that pass; the sketch is that of the kept tuples.
+
+// Whether tuple i passes every predicate of f (lo <= attrs[i][col] <= hi).
+__device__ __forceinline__ bool passes(const uint32_t *__restrict__ attrs, int n_attrs, uint64_t i,
+                                       const FilterSpec &f)
+{
+    bool k = true;
+    for (int p = 0; p < f.n; ++p) {
+        const uint32_t v = attrs[i * (uint64_t)n_attrs + f.col[p]];
+        k = k && v >= f.lo[p] && v <= f.hi[p];
+    }
+    return k;
+}
+
+// Global-atomic update of the kept tuples (every shape of relation, any weights).
+template <int NC>
+__global__ __launch_bounds__(kBlock) void k_update_global_f(const uint32_t *__restrict__ keys,
+                                                            const int64_t *__restrict__ weights, uint64_t n,
+                                                            const uint64_t *__restrict__ coef, int32_t cpr,
+                                                            unsigned long long *sketch, uint32_t m, int32_t d,
+                                                            DevPlan plan, bool vec2,
+                                                            const uint32_t *__restrict__ attrs, int32_t n_attrs,
+                                                            FilterSpec f, unsigned long long *kept)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    uint32_t mine = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        if (!passes(attrs, n_attrs, i, f)) continue;
+        ++mine;
+        uint32_t x[NC];
+        load_keys<NC>(keys, i, vec2, x);
+        const int64_t delta = weights ? weights[i] : 1;
+        const uint64_t *cf = coef;
+        for (int t = 0; t < d; ++t, cf += cpr) {
+            uint32_t j, neg;
+            hash_rep<NC>(cf, plan, x, j, neg);
+            const uint64_t val = neg ? (uint64_t)0 - (uint64_t)delta : (uint64_t)delta;
+            atomicAdd(sketch + (size_t)t * m + j, (unsigned long long)val);
+        }
+    }
+    if (kept) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o, 64);
+        if ((threadIdx.x & 63) == 0 && mine) atomicAdd(kept, (unsigned long long)mine);
+    }
+}
+
 // Wave-aggregated variant: per repetition, every lane writes its (bucket, value) into a
 // per-wave LDS slot; lanes then find the first lane of the wave with the same bucket
 // (a scan over the wave's 64 slots, LDS broadcast reads); the first lane sums the
@@ -724,6 +776,100 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16c(const uint32_t *__r
     for (uint32_t e = threadIdx.x; e < kSeg16Words; e += kSegBlock) out[e] = s_w[e];
 }
 
+// 16-bit update of the tuples that pass a filter (m <= 2^16 even, one or two key
+// columns each in one join, m a power of two, Deltas +-1): workgroup (tuple chunk,
+// repetition) holds the repetition's m counters as biased 16-bit pairs, like
+// k_update_seg16q.  Each wavefront takes 64 consecutive tuples at a time, evaluates the
+// predicates on their attribute columns, loads the keys of the tuples that pass only,
+// queues them in LDS (keys, sign of Delta) and hashes them once 64 are queued: the hash,
+// which sets the update's cost, is spent on kept tuples only.  Partial sums leave as
+// k_update_seg16q's do (k_seg_reduce16 adds them into the sketch).
+template <int NC, bool HW>
+__global__ __launch_bounds__(kSegBlock) void k_update_seg16f(const uint32_t *__restrict__ keys,
+                                                             const int64_t *__restrict__ weights, uint64_t n,
+                                                             const uint64_t *__restrict__ coef, int32_t cpr,
+                                                             uint32_t m, uint64_t chunk, bool vec2,
+                                                             const uint32_t *__restrict__ attrs, int32_t n_attrs,
+                                                             FilterSpec f, uint32_t *partial,
+                                                             unsigned long long *sketch, uint32_t canon_thresh,
+                                                             unsigned long long *kept)
+{
+    static_assert(NC == 1 || NC == 2, "one- and two-column relations");
+    constexpr int kWavesPB = kSegBlock / 64;
+    __shared__ uint32_t s_w[kSeg16Words];
+    __shared__ uint32_t s_qx[kWavesPB][NC][kQCap];
+    __shared__ uint32_t s_qn[kWavesPB][kQCap / 32];  // sign of Delta per queue entry (bit)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const SegTile wg = seg_tile();
+    const int t = (int)wg.seg;  // one repetition per workgroup
+    for (uint32_t e = threadIdx.x; e < m / 2; e += kSegBlock) s_w[e] = (kBias16 << 16) | kBias16;
+    if (lane < kQCap / 32) s_qn[wave][lane] = 0u;
+    __syncthreads();
+    CoefE1<NC> K;
+    K.load(coef + (size_t)t * cpr);
+    unsigned long long *srow = sketch + (uint64_t)t * m;
+    const uint64_t begin = (uint64_t)wg.chunk * chunk;
+    const uint64_t end = begin + chunk < n ? begin + chunk : n;
+    uint32_t head = 0, count = 0;  // wave-uniform queue state
+    uint32_t n_kept = 0;
+    auto drain = [&](uint32_t k) {  // lanes < k take one queued tuple each
+        if ((uint32_t)lane < k) {
+            const uint32_t slot = (head + lane) & (kQCap - 1);
+            uint32_t x[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) x[c] = s_qx[wave][c][slot];
+            uint32_t j, neg, flag;
+            K.bin_neg_fast(x, j, neg, flag);
+            if (flag >= canon_thresh) {
+                j = K.bin(x);
+                neg = K.neg(x);
+            }
+            if constexpr (HW) neg ^= (s_qn[wave][slot >> 5] >> (slot & 31)) & 1u;
+            j &= m - 1;
+            const uint32_t inc = inc16(neg, (j & 1u) << 4);
+            uint32_t *w = &s_w[j >> 1];
+            const uint32_t old = atomicAdd(w, inc);
+            if (out16(old, inc)) spill16(w, shift16(inc), srow + j);
+        }
+        head = (head + k) & (kQCap - 1);
+        count -= k;
+    };
+    for (uint64_t base = begin + (uint64_t)wave * 64; base < end; base += kSegBlock) {
+        const uint64_t i = base + lane;
+        const bool in = i < end && passes(attrs, n_attrs, i, f);
+        const uint64_t mask = __ballot(in);
+        if (in) {
+            uint32_t x[NC];
+            load_keys<NC>(keys, i, vec2, x);
+            const uint32_t pos = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+            const uint32_t slot = (head + count + pos) & (kQCap - 1);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) s_qx[wave][c][slot] = x[c];
+            if constexpr (HW) {
+                const uint32_t bit = 1u << (slot & 31);
+                if (weights[i] < 0) atomicOr(&s_qn[wave][slot >> 5], bit);
+                else atomicAnd(&s_qn[wave][slot >> 5], ~bit);
+            }
+        }
+        const uint32_t c = (uint32_t)__popcll(mask);
+        count += c;
+        n_kept += c;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (count >= 64) drain(64);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (count > 0) drain(count);
+    if (kept && t == 0 && lane == 0 && n_kept) atomicAdd(kept, (unsigned long long)n_kept);
+    __syncthreads();
+    const uint64_t cells = (uint64_t)gridDim.y * m;
+    uint32_t *out = partial + (size_t)wg.chunk * (cells >> 1) + (((uint64_t)t * m) >> 1);
+    for (uint32_t e = threadIdx.x; e < m / 2; e += kSegBlock) out[e] = s_w[e];
+}
+
 // sketch[2w + h] += sum over chunks of (half h of partial[chunk][w]) - 2^15
 __global__ void k_seg_reduce16(const uint32_t *__restrict__ partial, int32_t C, uint64_t words,
                                unsigned long long *sketch)
@@ -877,13 +1023,15 @@ struct PartHasher {
 
 // Pass 1.  Grid (blocks, repetition groups), mapped by seg_tile() so that the groups of
 // one block share an XCD (its L2 fetches the keys once).
-template <int NC, bool FAST, bool HW, bool A16>
+template <int NC, bool FAST, bool HW, bool A16, bool FILT>
 __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict__ keys,
                                                          const int64_t *__restrict__ weights, uint64_t n,
                                                          const uint64_t *__restrict__ coef, int32_t cpr,
                                                          DevPlan plan, uint32_t m, int32_t d, int32_t ranges,
                                                          int32_t reps_per_group, uint64_t nblk, uint16_t *rec_out,
-                                                         uint16_t *tab, PartHot *hot, uint32_t canon_thresh)
+                                                         uint16_t *tab, PartHot *hot, uint32_t canon_thresh,
+                                                         const uint32_t *__restrict__ attrs, int32_t n_attrs,
+                                                         FilterSpec f, unsigned long long *kept)
 {
     static_assert(NC == 1 || NC == 2, "one- and two-column relations");
     __shared__ __align__(16) uint32_t s_hist[kPB / 64][64 * kPartHS];
@@ -944,6 +1092,47 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
         }
     }
     wneg &= valid;
+    // With a filter, the kept tuples of this wavefront's quarter are compacted (through
+    // LDS) into its first ceil(kept / 64) slots, and the repetition loop hashes only those.
+    int nslots = kPartSlots;
+    if constexpr (FILT) {
+        extern __shared__ __align__(16) uint32_t s_list[];  // [waves][NC + HW][kPartWave]
+        constexpr int kW = NC + (HW ? 1 : 0);
+        uint32_t *lst = s_list + (size_t)wave * kW * kPartWave;
+        uint32_t off = 0;
+#pragma unroll
+        for (int q = 0; q < kPartQuads; ++q) {
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int sl = 4 * q + g;
+                const uint64_t i = base + 4 * ((uint64_t)q * 64 + lane) + g;
+                const bool kp = ((valid >> sl) & 1u) && passes(attrs, n_attrs, i, f);
+                const uint64_t bal = __ballot(kp);
+                if (kp) {
+                    const uint32_t dst = off + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) lst[c * kPartWave + dst] = x[sl][c];
+                    if constexpr (HW) lst[NC * kPartWave + dst] = (wneg >> sl) & 1u;
+                }
+                off += (uint32_t)__popcll(bal);
+            }
+        }
+        wave_sync();
+        const uint32_t total = off;
+        nslots = (int)((total + 63) / 64);
+        valid = 0;
+        wneg = 0;
+#pragma unroll
+        for (int sl = 0; sl < kPartSlots; ++sl) {
+            const uint32_t e = (uint32_t)sl * 64 + lane;
+            const bool in = e < total;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) x[sl][c] = in ? lst[c * kPartWave + e] : 0u;
+            if constexpr (HW) wneg |= (in ? lst[NC * kPartWave + e] : 0u) << sl;
+            valid |= (uint32_t)in << sl;
+        }
+        if (kept && wg.seg == 0 && lane == 0 && total) atomicAdd(kept, (unsigned long long)total);
+    }
 
     // ---- hot tuples of the block (see above)
     constexpr int kCand = kPB / 64 * 4;
@@ -1057,6 +1246,11 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
         constexpr int G = NC == 1 ? 4 : 2;
 #pragma unroll
         for (int q = 0; q < kPartSlots / G; ++q) {
+            if (FILT && G * q >= nslots) {  // no kept tuple in these slots (wave-uniform)
+#pragma unroll
+                for (int g = 0; g < G; ++g) P[G * q + g] = kPartNone;
+                continue;
+            }
             uint32_t j[G], ng[G], flag = 0;
 #pragma unroll
             for (int g = 0; g < G; ++g) {
@@ -1215,6 +1409,10 @@ __global__ __launch_bounds__(kPAB) void k_part_accum(const uint16_t *__restrict_
     }
 }
 
+}  // namespace
+int32_t chunks_for_n(int32_t C, uint64_t n);
+namespace {
+
 template <int NC>
 cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStream_t s)
 {
@@ -1229,6 +1427,51 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
     int n_cu = 256;
     CSK_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     const uint64_t need = (a.n + kBlock - 1) / kBlock;
+    if (a.filter) {
+        // Filtered ingestion: 16-bit LDS counters for m <= 2^16, the partition strategy
+        // beyond (one-join columns, m a power of two, Deltas +-1, at most two columns);
+        // global atomics for every other shape.
+        bool e1 = pow2;
+        for (int c = 0; c < a.plan.n_cols; ++c) e1 = e1 && a.plan.n_edges[c] == 1;
+        const bool unit = a.weights == nullptr || a.unit_weights;
+        if constexpr (NC <= 2) {
+            if (e1 && unit && a.scratch && a.m > (1u << 16)) {
+                strategy = CS_UPDATE_PARTITION;  // handled below with the filter
+            } else if (e1 && unit && a.scratch && a.m >= 2) {
+                const uint64_t cells = (uint64_t)a.d * a.m;
+                int32_t C = std::max(1, 256 / a.d);
+                C = (int32_t)std::min<uint64_t>((uint64_t)C, a.scratch_bytes / (cells * 2));
+                C = chunks_for_n(std::min(C, 64), a.n);
+                if ((uint64_t)C * cells * 2 > a.scratch_bytes)
+                    return fail(CS_EINVAL, "update scratch buffer too small for d * m 16-bit partial sums");
+                const uint64_t chunk = (a.n + C - 1) / C;
+                uint32_t *part = reinterpret_cast<uint32_t *>(a.scratch);
+                auto kern = a.weights ? &k_update_seg16f<NC, true> : &k_update_seg16f<NC, false>;
+                CSK_MARK(a.ev_start, s);
+                hipLaunchKernelGGL(kern, dim3((unsigned)C, (unsigned)a.d), dim3(kSegBlock), 0, s, a.keys, a.weights, a.n,
+                                   a.coef, a.plan.coef_per_rep, a.m, chunk, vec2, a.attrs, a.n_attrs, *a.filter, part,
+                                   sk, a.canon_thresh, a.kept);
+                CSK_HIP(hipGetLastError());
+                CSK_MARK(a.ev_stop, s);
+                const uint64_t words = cells / 2;
+                hipLaunchKernelGGL(k_seg_reduce16, dim3((unsigned)std::min<uint64_t>((words + 255) / 256, 8192)),
+                                   dim3(256), 0, s, part, C, words, sk);
+                CSK_HIP(hipGetLastError());
+                return CS_OK;
+            }
+        }
+        if (strategy != CS_UPDATE_PARTITION) {
+            uint64_t blocks = (uint64_t)n_cu * 16;
+            if (blocks > need) blocks = need;
+            CSK_MARK(a.ev_start, s);
+            hipLaunchKernelGGL(k_update_global_f<NC>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a.keys, a.weights,
+                               a.n, a.coef, a.plan.coef_per_rep, sk, a.m, a.d, plan, vec2, a.attrs, a.n_attrs,
+                               *a.filter, a.kept);
+            CSK_HIP(hipGetLastError());
+            CSK_MARK(a.ev_stop, s);
+            return CS_OK;
+        }
+    }
     if (strategy == CS_UPDATE_GLOBAL_ATOMIC || strategy == CS_UPDATE_WAVE_AGGREGATE) {
         uint64_t blocks = grid_blocks > 0 ? (uint64_t)grid_blocks : (uint64_t)n_cu * 16;
         if (blocks > need) blocks = need;
@@ -1404,19 +1647,27 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
                 int groups = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)a.d, slots / std::max<uint64_t>(1, nblk)));
                 const int per = (a.d + groups - 1) / groups;
                 groups = (a.d + per - 1) / per;
-                auto pick = [&](auto fst, auto hw, auto al) {
-                    constexpr bool F = decltype(fst)::value, H = decltype(hw)::value, A = decltype(al)::value;
-                    return &k_part_hash<NC, F, H, A>;
-                };
                 using T_ = std::true_type;
                 using F_ = std::false_type;
+                const bool filt = a.filter != nullptr;
+                auto pick = [&](auto fst, auto hw, auto al) {
+                    constexpr bool F = decltype(fst)::value, H = decltype(hw)::value, A = decltype(al)::value;
+                    return filt ? &k_part_hash<NC, F, H, A, true> : &k_part_hash<NC, F, H, A, false>;
+                };
                 auto hk = fast ? (wb ? (a16 ? pick(T_{}, T_{}, T_{}) : pick(T_{}, T_{}, F_{}))
                                      : (a16 ? pick(T_{}, F_{}, T_{}) : pick(T_{}, F_{}, F_{})))
                                : (wb ? (a16 ? pick(F_{}, T_{}, T_{}) : pick(F_{}, T_{}, F_{}))
                                      : (a16 ? pick(F_{}, F_{}, T_{}) : pick(F_{}, F_{}, F_{})));
-                hipLaunchKernelGGL(hk, dim3((unsigned)nblk, (unsigned)groups), dim3(kPB), 0, s, kb, wb, cn, a.coef,
+                // the filtered variant compacts each wavefront's kept tuples in LDS
+                const size_t lds_f = filt ? (size_t)(kPB / 64) * (NC + (wb ? 1 : 0)) * kPartWave * 4 : 0;
+                if (filt)
+                    CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(hk),
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_f));
+                const uint32_t *ab = filt ? a.attrs + base * (uint64_t)a.n_attrs : nullptr;
+                const FilterSpec fs = filt ? *a.filter : FilterSpec{};
+                hipLaunchKernelGGL(hk, dim3((unsigned)nblk, (unsigned)groups), dim3(kPB), lds_f, s, kb, wb, cn, a.coef,
                                    a.plan.coef_per_rep, plan, a.m, a.d, pg.ranges, per, nblk, rec, tab, hot,
-                                   a.canon_thresh);
+                                   a.canon_thresh, ab, a.n_attrs, fs, a.kept);
                 CSK_HIP(hipGetLastError());
                 if (one_chunk) CSK_MARK(a.ev_stop, s);
                 auto ak = fast ? &k_part_accum<NC, true> : &k_part_accum<NC, false>;
@@ -1642,6 +1893,19 @@ cs_status launch_update(const UpdateArgs &a_in, int strategy, int grid_blocks, h
     return st;
 }
 
+}  // namespace csk
+
+namespace csk {
+namespace {
+__global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
+}  // namespace
+
+cs_status zero_device_u64(unsigned long long *p, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, p);
+    CSK_HIP(hipGetLastError());
+    return CS_OK;
+}
 }  // namespace csk
 
 // ---------------------------------------------------------------- allocation-free update

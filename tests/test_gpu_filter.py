@@ -23,11 +23,15 @@ def _say(*a):
 
 CASES = [
     # graph, n, m, d, weights, predicates (column, lo, hi) over 3 attribute columns
-    (W.chain(3), 200_000, 1 << 16, 9, None, [(0, 0, 2 ** 31)]),
-    (W.chain(3), 150_000, 1 << 12, 5, "pm1", [(1, 3, 6), (2, 0, 2 ** 32 - 1)]),
-    (W.star(4), 100_001, 1 << 14, 5, "big", [(0, 2 ** 30, 3 * 2 ** 30), (1, 0, 7), (2, 5, 5)]),
+    (W.chain(3), 200_000, 1 << 16, 9, None, [(0, 0, 2 ** 31)]),                   # 16-bit LDS
+    (W.chain(3), 150_000, 1 << 12, 5, "pm1", [(1, 3, 6), (2, 0, 2 ** 32 - 1)]),    # 16-bit, +-1
+    (W.star(4), 100_001, 1 << 14, 5, "big", [(0, 2 ** 30, 3 * 2 ** 30), (1, 0, 7), (2, 5, 5)]),  # atomics
     (W.single_join(), 5_000, 1024, 3, None, [(1, 9, 8)]),            # keeps nothing
     (W.chain(3), 3_000_000, 1 << 16, 9, None, [(1, 0, 9)]),           # keeps everything
+    (W.chain(5), (1 << 21) + 777, 1 << 18, 7, "pm1", [(1, 0, 2)]),   # partition, 30%, two chunks
+    (W.chain(3), 300_001, 1 << 20, 3, None, [(2, 1, 1), (1, 0, 8)]), # partition, one column kept in 8
+    (W.multiway_star(3), 80_000, 1 << 17, 5, None, [(1, 0, 4)]),     # a column in two joins: atomics
+    (W.chain(3), 90_000, 100_003, 5, "pm1", [(0, 0, 2 ** 30)]),      # m not a power of two: atomics
 ]
 
 
@@ -79,3 +83,23 @@ def test_filtered_update_rejects_bad_predicates():
         sk.update_filtered(0, keys, attrs, [(0, 0, 1)] * 9)    # more than 8 predicates
     assert sk.update_filtered(0, keys, attrs, []) == 10        # no predicate: every tuple
     sk.close()
+
+
+def test_filtered_update_asynchronous_equals_counted():
+    """Without a count the call only enqueues; the counters equal the counted call's."""
+    g, n, m, d = W.chain(3), 400_000, 1 << 18, 5
+    rels = [keys_u32(W.relation_keys(g, k, n, "zipf", config=650, s=1.2, D=10 ** 6)) for k in range(g.n_rel)]
+    attrs = [_attrs(n, 90 + k) for k in range(g.n_rel)]
+    preds = [(1, 2, 4)]
+    a = csk.Sketch(g, m, d, 4)
+    b = csk.Sketch(g, m, d, 4)
+    for k in range(g.n_rel):
+        kd = to_device_keys(rels[k])
+        ad = torch.from_numpy(attrs[k].view(np.int32)).cuda()
+        assert a.update_filtered(k, kd, ad, preds, count=False) is None
+        b.update_filtered(k, kd, ad, preds)
+    torch.cuda.synchronize()
+    for k in range(g.n_rel):
+        assert np.array_equal(a.read_sketch(k), b.read_sketch(k)), k
+    a.close()
+    b.close()
