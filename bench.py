@@ -528,7 +528,7 @@ def bench_filtered(keys, graph, dev, stream, steps, m=1 << 16, d=9):
         sk.reset(stream=stream)
         for k in range(graph.n_rel):
             if filtered:
-                sk.update_filtered(k, keys[k], attrs[k], preds, stream=stream)
+                sk.update_filtered(k, keys[k], attrs[k], preds, stream=stream, count=False)
             else:
                 sk.update(k, keys[k], None, stream=stream)
         return sk.estimate(stream=stream)

@@ -834,30 +834,48 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16f(const uint32_t *__r
         head = (head + k) & (kQCap - 1);
         count -= k;
     };
-    for (uint64_t base = begin + (uint64_t)wave * 64; base < end; base += kSegBlock) {
-        const uint64_t i = base + lane;
-        const bool in = i < end && passes(attrs, n_attrs, i, f);
-        const uint64_t mask = __ballot(in);
-        if (in) {
-            uint32_t x[NC];
-            load_keys<NC>(keys, i, vec2, x);
-            const uint32_t pos = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-            const uint32_t slot = (head + count + pos) & (kQCap - 1);
+    // kU groups of 64 consecutive tuples per pass: every attribute and key load of the
+    // pass is issued before the first predicate is evaluated (indexes clamped into the
+    // chunk, so the loads need no branch), then the groups are queued one by one
+    constexpr int kU = 4;
+    const uint64_t last = end > begin ? end - 1 : begin;
+    for (uint64_t base = begin + (uint64_t)wave * 64 * kU; base < end; base += (uint64_t)kSegBlock * kU) {
+        uint32_t av[kU][CS_MAX_PREDICATES];
+        uint32_t x[kU][NC];
+        bool neg_w[kU];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) s_qx[wave][c][slot] = x[c];
-            if constexpr (HW) {
-                const uint32_t bit = 1u << (slot & 31);
-                if (weights[i] < 0) atomicOr(&s_qn[wave][slot >> 5], bit);
-                else atomicAnd(&s_qn[wave][slot >> 5], ~bit);
-            }
+        for (int u = 0; u < kU; ++u) {
+            const uint64_t i = base + (uint64_t)u * 64 + lane;
+            const uint64_t ic = i < end ? i : last;
+            for (int p = 0; p < f.n; ++p) av[u][p] = attrs[ic * (uint64_t)n_attrs + f.col[p]];
+            load_keys<NC>(keys, ic, vec2, x[u]);
+            neg_w[u] = HW ? weights[ic] < 0 : false;
         }
-        const uint32_t c = (uint32_t)__popcll(mask);
-        count += c;
-        n_kept += c;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (count >= 64) drain(64);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const uint64_t i = base + (uint64_t)u * 64 + lane;
+            bool in = i < end;
+            for (int p = 0; p < f.n; ++p) in = in && av[u][p] >= f.lo[p] && av[u][p] <= f.hi[p];
+            const uint64_t mask = __ballot(in);
+            if (in) {
+                const uint32_t pos = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+                const uint32_t slot = (head + count + pos) & (kQCap - 1);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) s_qx[wave][c][slot] = x[u][c];
+                if constexpr (HW) {
+                    const uint32_t bit = 1u << (slot & 31);
+                    if (neg_w[u]) atomicOr(&s_qn[wave][slot >> 5], bit);
+                    else atomicAnd(&s_qn[wave][slot >> 5], ~bit);
+                }
+            }
+            const uint32_t c = (uint32_t)__popcll(mask);
+            count += c;
+            n_kept += c;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (count >= 64) drain(64);
+        }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
