@@ -784,7 +784,7 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16c(const uint32_t *__r
 // queues them in LDS (keys, sign of Delta) and hashes them once 64 are queued: the hash,
 // which sets the update's cost, is spent on kept tuples only.  Partial sums leave as
 // k_update_seg16q's do (k_seg_reduce16 adds them into the sketch).
-template <int NC, bool HW>
+template <int NC, bool HW, int MAXP>
 __global__ __launch_bounds__(kSegBlock) void k_update_seg16f(const uint32_t *__restrict__ keys,
                                                              const int64_t *__restrict__ weights, uint64_t n,
                                                              const uint64_t *__restrict__ coef, int32_t cpr,
@@ -834,37 +834,49 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16f(const uint32_t *__r
         head = (head + k) & (kQCap - 1);
         count -= k;
     };
-    // kU groups of 64 consecutive tuples per pass: every attribute and key load of the
-    // pass is issued before the first predicate is evaluated (indexes clamped into the
-    // chunk, so the loads need no branch), then the groups are queued one by one
-    constexpr int kU = 4;
-    const uint64_t last = end > begin ? end - 1 : begin;
-    for (uint64_t base = begin + (uint64_t)wave * 64 * kU; base < end; base += (uint64_t)kSegBlock * kU) {
-        uint32_t av[kU][CS_MAX_PREDICATES];
+    // Passes of kU groups of 64 consecutive tuples: every attribute and key load of a
+    // pass is issued before the pass ahead of it is evaluated (two register sets that
+    // alternate, indexes clamped into the chunk so the loads need no branch); a pass's
+    // groups are then queued one by one.  At most MAXP predicates are held per tuple.
+    constexpr int kU = MAXP > 2 ? 1 : 4;
+    struct Pass {
+        uint32_t av[kU][MAXP];
         uint32_t x[kU][NC];
-        bool neg_w[kU];
+        uint32_t negw;  // bit u: Delta of this lane's tuple of group u is -1
+    };
+    const uint64_t last = end > begin ? end - 1 : begin;
+    const uint64_t step = (uint64_t)kSegBlock * kU;
+    const int np = f.n;
+    auto load_pass = [&](uint64_t base, Pass &P) {
+        P.negw = 0;
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             const uint64_t i = base + (uint64_t)u * 64 + lane;
             const uint64_t ic = i < end ? i : last;
-            for (int p = 0; p < f.n; ++p) av[u][p] = attrs[ic * (uint64_t)n_attrs + f.col[p]];
-            load_keys<NC>(keys, ic, vec2, x[u]);
-            neg_w[u] = HW ? weights[ic] < 0 : false;
+#pragma unroll
+            for (int p = 0; p < MAXP; ++p)
+                if (p < np) P.av[u][p] = attrs[ic * (uint64_t)n_attrs + f.col[p]];
+            load_keys<NC>(keys, ic, vec2, P.x[u]);
+            if constexpr (HW) P.negw |= (uint32_t)(weights[ic] < 0) << u;
         }
+    };
+    auto run_pass = [&](uint64_t base, const Pass &P) {
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             const uint64_t i = base + (uint64_t)u * 64 + lane;
             bool in = i < end;
-            for (int p = 0; p < f.n; ++p) in = in && av[u][p] >= f.lo[p] && av[u][p] <= f.hi[p];
+#pragma unroll
+            for (int p = 0; p < MAXP; ++p)
+                if (p < np) in = in && P.av[u][p] >= f.lo[p] && P.av[u][p] <= f.hi[p];
             const uint64_t mask = __ballot(in);
             if (in) {
                 const uint32_t pos = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
                 const uint32_t slot = (head + count + pos) & (kQCap - 1);
 #pragma unroll
-                for (int c = 0; c < NC; ++c) s_qx[wave][c][slot] = x[u][c];
+                for (int c = 0; c < NC; ++c) s_qx[wave][c][slot] = P.x[u][c];
                 if constexpr (HW) {
                     const uint32_t bit = 1u << (slot & 31);
-                    if (neg_w[u]) atomicOr(&s_qn[wave][slot >> 5], bit);
+                    if ((P.negw >> u) & 1u) atomicOr(&s_qn[wave][slot >> 5], bit);
                     else atomicAnd(&s_qn[wave][slot >> 5], ~bit);
                 }
             }
@@ -875,6 +887,23 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16f(const uint32_t *__r
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             if (count >= 64) drain(64);
+        }
+    };
+    uint64_t base = begin + (uint64_t)wave * 64 * kU;
+    if (base < end) {
+        Pass A, B;
+        load_pass(base, A);
+        for (;;) {
+            const uint64_t nb = base + step;
+            if (nb < end) load_pass(nb, B);
+            run_pass(base, A);
+            base = nb;
+            if (base >= end) break;
+            const uint64_t nb2 = base + step;
+            if (nb2 < end) load_pass(nb2, A);
+            run_pass(base, B);
+            base = nb2;
+            if (base >= end) break;
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1464,7 +1493,9 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
                     return fail(CS_EINVAL, "update scratch buffer too small for d * m 16-bit partial sums");
                 const uint64_t chunk = (a.n + C - 1) / C;
                 uint32_t *part = reinterpret_cast<uint32_t *>(a.scratch);
-                auto kern = a.weights ? &k_update_seg16f<NC, true> : &k_update_seg16f<NC, false>;
+                auto kern = a.filter->n <= 2 ? (a.weights ? &k_update_seg16f<NC, true, 2> : &k_update_seg16f<NC, false, 2>)
+                                             : (a.weights ? &k_update_seg16f<NC, true, CS_MAX_PREDICATES>
+                                                          : &k_update_seg16f<NC, false, CS_MAX_PREDICATES>);
                 CSK_MARK(a.ev_start, s);
                 hipLaunchKernelGGL(kern, dim3((unsigned)C, (unsigned)a.d), dim3(kSegBlock), 0, s, a.keys, a.weights, a.n,
                                    a.coef, a.plan.coef_per_rep, a.m, chunk, vec2, a.attrs, a.n_attrs, *a.filter, part,
