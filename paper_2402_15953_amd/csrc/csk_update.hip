@@ -776,23 +776,47 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16c(const uint32_t *__r
     for (uint32_t e = threadIdx.x; e < kSeg16Words; e += kSegBlock) out[e] = s_w[e];
 }
 
-// 16-bit update of the tuples that pass a filter (m <= 2^16 even, one or two key
-// columns each in one join, m a power of two, Deltas +-1): workgroup (tuple chunk,
+// Predicate pass of a filtered update with 16-bit counters: one bit per tuple, word w
+// of `mask` covering tuples 64 w .. 64 w + 63 (bit l: tuple 64 w + l passes), counted
+// into `kept` when it is set.  The predicates are evaluated once per tuple here instead
+// of once per repetition in the update kernel.
+__global__ __launch_bounds__(kBlock) void k_filter_mask(const uint32_t *__restrict__ attrs, int32_t n_attrs,
+                                                        uint64_t n, FilterSpec f, unsigned long long *mask,
+                                                        unsigned long long *kept)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t words = (n + 63) / 64;
+    uint32_t mine = 0;
+    for (uint64_t w = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / 64; w < words;
+         w += (uint64_t)gridDim.x * kBlock / 64) {
+        const uint64_t i = w * 64 + lane;
+        const bool in = i < n && passes(attrs, n_attrs, i, f);
+        const uint64_t b = __ballot(in);
+        if (lane == 0) {
+            mask[w] = b;
+            mine += (uint32_t)__popcll(b);
+        }
+    }
+    if (kept && lane == 0 && mine) atomicAdd(kept, (unsigned long long)mine);
+}
+
+// 16-bit update of the tuples a predicate pass kept (m <= 2^16 even, m a power of two,
+// one or two key columns each in one join, Deltas +-1): workgroup (tuple chunk,
 // repetition) holds the repetition's m counters as biased 16-bit pairs, like
-// k_update_seg16q.  Each wavefront takes 64 consecutive tuples at a time, evaluates the
-// predicates on their attribute columns, loads the keys of the tuples that pass only,
-// queues them in LDS (keys, sign of Delta) and hashes them once 64 are queued: the hash,
-// which sets the update's cost, is spent on kept tuples only.  Partial sums leave as
-// k_update_seg16q's do (k_seg_reduce16 adds them into the sketch).
-template <int NC, bool HW, int MAXP>
+// k_update_seg16q.  Each wavefront takes 64 consecutive tuples at a time, reads their
+// 64 mask bits with one scalar load, loads the keys of the kept tuples only, queues them
+// in LDS (keys, sign of Delta) and hashes them once 64 are queued: the hash, which sets
+// the update's cost, is spent on kept tuples only.  The key loads of a pass of kU groups
+// are issued before the previous pass is queued (two register sets that alternate).
+// Partial sums leave as k_update_seg16q's do (k_seg_reduce16 adds them into the sketch).
+template <int NC, bool HW>
 __global__ __launch_bounds__(kSegBlock) void k_update_seg16f(const uint32_t *__restrict__ keys,
                                                              const int64_t *__restrict__ weights, uint64_t n,
                                                              const uint64_t *__restrict__ coef, int32_t cpr,
                                                              uint32_t m, uint64_t chunk, bool vec2,
-                                                             const uint32_t *__restrict__ attrs, int32_t n_attrs,
-                                                             FilterSpec f, uint32_t *partial,
-                                                             unsigned long long *sketch, uint32_t canon_thresh,
-                                                             unsigned long long *kept)
+                                                             const unsigned long long *__restrict__ mask,
+                                                             uint32_t *partial, unsigned long long *sketch,
+                                                             uint32_t canon_thresh)
 {
     static_assert(NC == 1 || NC == 2, "one- and two-column relations");
     constexpr int kWavesPB = kSegBlock / 64;
@@ -808,10 +832,10 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16f(const uint32_t *__r
     CoefE1<NC> K;
     K.load(coef + (size_t)t * cpr);
     unsigned long long *srow = sketch + (uint64_t)t * m;
+    // chunks are whole mask words (multiples of 64 tuples)
     const uint64_t begin = (uint64_t)wg.chunk * chunk;
     const uint64_t end = begin + chunk < n ? begin + chunk : n;
     uint32_t head = 0, count = 0;  // wave-uniform queue state
-    uint32_t n_kept = 0;
     auto drain = [&](uint32_t k) {  // lanes < k take one queued tuple each
         if ((uint32_t)lane < k) {
             const uint32_t slot = (head + lane) & (kQCap - 1);
@@ -834,43 +858,32 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16f(const uint32_t *__r
         head = (head + k) & (kQCap - 1);
         count -= k;
     };
-    // Passes of kU groups of 64 consecutive tuples: every attribute and key load of a
-    // pass is issued before the pass ahead of it is evaluated (two register sets that
-    // alternate, indexes clamped into the chunk so the loads need no branch); a pass's
-    // groups are then queued one by one.  At most MAXP predicates are held per tuple.
-    constexpr int kU = MAXP > 2 ? 1 : 4;
+    constexpr int kU = 4;
     struct Pass {
-        uint32_t av[kU][MAXP];
+        uint64_t bits[kU];  // wave-uniform mask words
         uint32_t x[kU][NC];
-        uint32_t negw;  // bit u: Delta of this lane's tuple of group u is -1
+        uint32_t negw;
     };
-    const uint64_t last = end > begin ? end - 1 : begin;
     const uint64_t step = (uint64_t)kSegBlock * kU;
-    const int np = f.n;
     auto load_pass = [&](uint64_t base, Pass &P) {
         P.negw = 0;
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-            const uint64_t i = base + (uint64_t)u * 64 + lane;
-            const uint64_t ic = i < end ? i : last;
-#pragma unroll
-            for (int p = 0; p < MAXP; ++p)
-                if (p < np) P.av[u][p] = attrs[ic * (uint64_t)n_attrs + f.col[p]];
-            load_keys<NC>(keys, ic, vec2, P.x[u]);
-            if constexpr (HW) P.negw |= (uint32_t)(weights[ic] < 0) << u;
+            const uint64_t g0 = base + (uint64_t)u * 64;
+            P.bits[u] = g0 < end ? mask[g0 / 64] : 0ull;
+            const uint64_t i = g0 + lane;
+            if ((P.bits[u] >> lane) & 1ull) {  // kept tuples only (i < end)
+                load_keys<NC>(keys, i, vec2, P.x[u]);
+                if constexpr (HW) P.negw |= (uint32_t)(weights[i] < 0) << u;
+            }
         }
     };
-    auto run_pass = [&](uint64_t base, const Pass &P) {
+    auto run_pass = [&](const Pass &P) {
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-            const uint64_t i = base + (uint64_t)u * 64 + lane;
-            bool in = i < end;
-#pragma unroll
-            for (int p = 0; p < MAXP; ++p)
-                if (p < np) in = in && P.av[u][p] >= f.lo[p] && P.av[u][p] <= f.hi[p];
-            const uint64_t mask = __ballot(in);
-            if (in) {
-                const uint32_t pos = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+            const uint64_t b = P.bits[u];
+            if ((b >> lane) & 1ull) {
+                const uint32_t pos = (uint32_t)__popcll(b & ((1ull << lane) - 1ull));
                 const uint32_t slot = (head + count + pos) & (kQCap - 1);
 #pragma unroll
                 for (int c = 0; c < NC; ++c) s_qx[wave][c][slot] = P.x[u][c];
@@ -880,9 +893,7 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16f(const uint32_t *__r
                     else atomicAnd(&s_qn[wave][slot >> 5], ~bit);
                 }
             }
-            const uint32_t c = (uint32_t)__popcll(mask);
-            count += c;
-            n_kept += c;
+            count += (uint32_t)__popcll(b);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -896,12 +907,12 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16f(const uint32_t *__r
         for (;;) {
             const uint64_t nb = base + step;
             if (nb < end) load_pass(nb, B);
-            run_pass(base, A);
+            run_pass(A);
             base = nb;
             if (base >= end) break;
             const uint64_t nb2 = base + step;
             if (nb2 < end) load_pass(nb2, A);
-            run_pass(base, B);
+            run_pass(B);
             base = nb2;
             if (base >= end) break;
         }
@@ -910,7 +921,6 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16f(const uint32_t *__r
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (count > 0) drain(count);
-    if (kept && t == 0 && lane == 0 && n_kept) atomicAdd(kept, (unsigned long long)n_kept);
     __syncthreads();
     const uint64_t cells = (uint64_t)gridDim.y * m;
     uint32_t *out = partial + (size_t)wg.chunk * (cells >> 1) + (((uint64_t)t * m) >> 1);
@@ -1485,27 +1495,40 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
             if (e1 && unit && a.scratch && a.m > (1u << 16)) {
                 strategy = CS_UPDATE_PARTITION;  // handled below with the filter
             } else if (e1 && unit && a.scratch && a.m >= 2) {
+                // predicate pass into a bit mask after the partial sums, then the 16-bit
+                // update of the kept tuples, in rounds of as many tuples as the mask holds
                 const uint64_t cells = (uint64_t)a.d * a.m;
-                int32_t C = std::max(1, 256 / a.d);
-                C = (int32_t)std::min<uint64_t>((uint64_t)C, a.scratch_bytes / (cells * 2));
-                C = chunks_for_n(std::min(C, 64), a.n);
-                if ((uint64_t)C * cells * 2 > a.scratch_bytes)
-                    return fail(CS_EINVAL, "update scratch buffer too small for d * m 16-bit partial sums");
-                const uint64_t chunk = (a.n + C - 1) / C;
+                int32_t C0 = std::max(1, std::min(64, 256 / a.d));
+                while (C0 > 1 && (uint64_t)C0 * cells * 2 + (1u << 20) > a.scratch_bytes) --C0;
+                const size_t part_bytes = (((size_t)C0 * cells * 2) + 255) & ~(size_t)255;
+                if (part_bytes + 4096 > a.scratch_bytes)
+                    return fail(CS_EINVAL, "update scratch buffer too small for a filtered update");
+                const uint64_t round_max = (uint64_t)((a.scratch_bytes - part_bytes) / 8) * 64;  // tuples per mask
                 uint32_t *part = reinterpret_cast<uint32_t *>(a.scratch);
-                auto kern = a.filter->n <= 2 ? (a.weights ? &k_update_seg16f<NC, true, 2> : &k_update_seg16f<NC, false, 2>)
-                                             : (a.weights ? &k_update_seg16f<NC, true, CS_MAX_PREDICATES>
-                                                          : &k_update_seg16f<NC, false, CS_MAX_PREDICATES>);
+                auto *mask = reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(a.scratch) + part_bytes);
+                auto kern = a.weights ? &k_update_seg16f<NC, true> : &k_update_seg16f<NC, false>;
                 CSK_MARK(a.ev_start, s);
-                hipLaunchKernelGGL(kern, dim3((unsigned)C, (unsigned)a.d), dim3(kSegBlock), 0, s, a.keys, a.weights, a.n,
-                                   a.coef, a.plan.coef_per_rep, a.m, chunk, vec2, a.attrs, a.n_attrs, *a.filter, part,
-                                   sk, a.canon_thresh, a.kept);
-                CSK_HIP(hipGetLastError());
+                for (uint64_t r0 = 0; r0 < a.n; r0 += round_max) {
+                    const uint64_t rn = std::min<uint64_t>(a.n - r0, round_max);
+                    const uint32_t *kb = a.keys + r0 * NC;
+                    const int64_t *wb = a.weights ? a.weights + r0 : nullptr;
+                    const bool v2 = NC == 2 && ((uintptr_t)kb % 8) == 0;
+                    const uint64_t mwords = (rn + 63) / 64;
+                    hipLaunchKernelGGL(k_filter_mask, dim3((unsigned)std::min<uint64_t>((mwords + 3) / 4, 4096)),
+                                       dim3(kBlock), 0, s, a.attrs + r0 * (uint64_t)a.n_attrs, a.n_attrs, rn,
+                                       *a.filter, mask, a.kept);
+                    CSK_HIP(hipGetLastError());
+                    const int32_t C = chunks_for_n(C0, rn);
+                    const uint64_t chunk = ((rn + C - 1) / C + 63) & ~(uint64_t)63;  // whole mask words
+                    hipLaunchKernelGGL(kern, dim3((unsigned)C, (unsigned)a.d), dim3(kSegBlock), 0, s, kb, wb, rn,
+                                       a.coef, a.plan.coef_per_rep, a.m, chunk, v2, mask, part, sk, a.canon_thresh);
+                    CSK_HIP(hipGetLastError());
+                    const uint64_t words = cells / 2;
+                    hipLaunchKernelGGL(k_seg_reduce16, dim3((unsigned)std::min<uint64_t>((words + 255) / 256, 8192)),
+                                       dim3(256), 0, s, part, C, words, sk);
+                    CSK_HIP(hipGetLastError());
+                }
                 CSK_MARK(a.ev_stop, s);
-                const uint64_t words = cells / 2;
-                hipLaunchKernelGGL(k_seg_reduce16, dim3((unsigned)std::min<uint64_t>((words + 255) / 256, 8192)),
-                                   dim3(256), 0, s, part, C, words, sk);
-                CSK_HIP(hipGetLastError());
                 return CS_OK;
             }
         }
