@@ -262,11 +262,14 @@ typedef struct cs_predicate {
  *   n_kept: optional.  NULL: the call is asynchronous and ordered on `stream` like
  *           cs_update.  Non-NULL: the kernels also count the tuples that passed and the
  *           call waits on `stream` for that count.
- * The update kernels evaluate the predicates themselves and hash only the tuples that
- * pass (no copy of the tuples, nothing allocated): 16-bit LDS counters for m <= 2^16 and
- * the partition strategy beyond, when every key column takes part in one join, m is a
- * power of two, the Deltas are +-1 and the relation has at most two key columns; global
- * atomics otherwise.
+ * Nothing is allocated and nothing read back unless n_kept asks for the count.  When
+ * every key column takes part in one join, m is a power of two, the Deltas are +-1 and
+ * the relation has at most two key columns: for m in (2^15, 2^16] one compaction pass
+ * evaluates the predicates once per tuple and writes the kept tuples' keys into the
+ * handle's scratch buffer (in rounds when they do not fit), and the 16-bit update reads
+ * their count on the device; beyond 2^16 buckets the partition strategy's hashing pass
+ * evaluates the predicates itself and compacts the kept tuples in LDS before hashing.
+ * Every other shape takes global atomics that skip the tuples failing the predicates.
  * Errors: CS_EINVAL (arguments), CS_EDEVICE. */
 cs_status cs_update_filtered(cs_sketch *h, int32_t rel, const uint32_t *keys, const int64_t *weights,
                              uint64_t n, const uint32_t *attrs, int32_t n_attrs,

@@ -495,8 +495,13 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16q(const uint32_t *__r
                                                              const uint64_t *__restrict__ coef, int32_t cpr,
                                                              DevPlan plan, uint32_t m, uint64_t chunk,
                                                              uint32_t *partial, unsigned long long *sketch,
-                                                             uint32_t canon_thresh)
+                                                             uint32_t canon_thresh,
+                                                             const unsigned long long *__restrict__ n_dev)
 {
+    if (n_dev) {  // tuple count known only on the device (a filtered update's kept tuples)
+        n = *n_dev;
+        chunk = ((n + gridDim.x - 1) / gridDim.x + 3) & ~(uint64_t)3;
+    }
     static_assert(NC == 1 || NC == 2, "quads of one- and two-column tuples");
     __shared__ uint32_t s_w[kSeg16Words];
     const uint64_t cells = (uint64_t)gridDim.y * m;  // one segment per repetition
@@ -776,155 +781,70 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16c(const uint32_t *__r
     for (uint32_t e = threadIdx.x; e < kSeg16Words; e += kSegBlock) out[e] = s_w[e];
 }
 
-// Predicate pass of a filtered update with 16-bit counters: one bit per tuple, word w
-// of `mask` covering tuples 64 w .. 64 w + 63 (bit l: tuple 64 w + l passes), counted
-// into `kept` when it is set.  The predicates are evaluated once per tuple here instead
-// of once per repetition in the update kernel.
-__global__ __launch_bounds__(kBlock) void k_filter_mask(const uint32_t *__restrict__ attrs, int32_t n_attrs,
-                                                        uint64_t n, FilterSpec f, unsigned long long *mask,
-                                                        unsigned long long *kept)
-{
-    const int lane = threadIdx.x & 63;
-    const uint64_t words = (n + 63) / 64;
-    uint32_t mine = 0;
-    for (uint64_t w = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / 64; w < words;
-         w += (uint64_t)gridDim.x * kBlock / 64) {
-        const uint64_t i = w * 64 + lane;
-        const bool in = i < n && passes(attrs, n_attrs, i, f);
-        const uint64_t b = __ballot(in);
-        if (lane == 0) {
-            mask[w] = b;
-            mine += (uint32_t)__popcll(b);
-        }
-    }
-    if (kept && lane == 0 && mine) atomicAdd(kept, (unsigned long long)mine);
-}
-
-// 16-bit update of the tuples a predicate pass kept (m <= 2^16 even, m a power of two,
-// one or two key columns each in one join, Deltas +-1): workgroup (tuple chunk,
-// repetition) holds the repetition's m counters as biased 16-bit pairs, like
-// k_update_seg16q.  Each wavefront takes 64 consecutive tuples at a time, reads their
-// 64 mask bits with one scalar load, loads the keys of the kept tuples only, queues them
-// in LDS (keys, sign of Delta) and hashes them once 64 are queued: the hash, which sets
-// the update's cost, is spent on kept tuples only.  The key loads of a pass of kU groups
-// are issued before the previous pass is queued (two register sets that alternate).
-// Partial sums leave as k_update_seg16q's do (k_seg_reduce16 adds them into the sketch).
+// Compaction pass of a filtered update with 16-bit counters: the keys (and Deltas) of the
+// tuples that pass f are written contiguously to okeys / ow, and their number is added to
+// *count (and to *kept when set).  A workgroup takes a tile of kPB x 16 tuples: each
+// wavefront loads the attribute columns and keys of its 16 groups of 64 consecutive
+// tuples at once, evaluates the predicates (one ballot per group), and the workgroup
+// reserves its tile's slots with one atomic.  The kept tuples' order is not kept: the
+// counters, integer sums, do not depend on it.  Each tuple's predicates are evaluated
+// once here, instead of once per repetition in the update kernel.
+constexpr int kCompactGroups = 16;
+constexpr int kCB = 256;  // compaction workgroup: 4 wavefronts
 template <int NC, bool HW>
-__global__ __launch_bounds__(kSegBlock) void k_update_seg16f(const uint32_t *__restrict__ keys,
-                                                             const int64_t *__restrict__ weights, uint64_t n,
-                                                             const uint64_t *__restrict__ coef, int32_t cpr,
-                                                             uint32_t m, uint64_t chunk, bool vec2,
-                                                             const unsigned long long *__restrict__ mask,
-                                                             uint32_t *partial, unsigned long long *sketch,
-                                                             uint32_t canon_thresh)
+__global__ __launch_bounds__(kCB) void k_filter_compact(const uint32_t *__restrict__ keys,
+                                                        const int64_t *__restrict__ weights, uint64_t n,
+                                                        const uint32_t *__restrict__ attrs, int32_t n_attrs,
+                                                        FilterSpec f, uint32_t *okeys, int64_t *ow,
+                                                        unsigned long long *count, unsigned long long *kept)
 {
-    static_assert(NC == 1 || NC == 2, "one- and two-column relations");
-    constexpr int kWavesPB = kSegBlock / 64;
-    __shared__ uint32_t s_w[kSeg16Words];
-    __shared__ uint32_t s_qx[kWavesPB][NC][kQCap];
-    __shared__ uint32_t s_qn[kWavesPB][kQCap / 32];  // sign of Delta per queue entry (bit)
+    __shared__ uint32_t s_cnt[kCB / 64];
+    __shared__ unsigned long long s_base[kCB / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const SegTile wg = seg_tile();
-    const int t = (int)wg.seg;  // one repetition per workgroup
-    for (uint32_t e = threadIdx.x; e < m / 2; e += kSegBlock) s_w[e] = (kBias16 << 16) | kBias16;
-    if (lane < kQCap / 32) s_qn[wave][lane] = 0u;
-    __syncthreads();
-    CoefE1<NC> K;
-    K.load(coef + (size_t)t * cpr);
-    unsigned long long *srow = sketch + (uint64_t)t * m;
-    // chunks are whole mask words (multiples of 64 tuples)
-    const uint64_t begin = (uint64_t)wg.chunk * chunk;
-    const uint64_t end = begin + chunk < n ? begin + chunk : n;
-    uint32_t head = 0, count = 0;  // wave-uniform queue state
-    auto drain = [&](uint32_t k) {  // lanes < k take one queued tuple each
-        if ((uint32_t)lane < k) {
-            const uint32_t slot = (head + lane) & (kQCap - 1);
-            uint32_t x[NC];
+    const uint64_t tile = (uint64_t)kCB * kCompactGroups;
+    for (uint64_t t0 = (uint64_t)blockIdx.x * tile; t0 < n; t0 += (uint64_t)gridDim.x * tile) {
+        const uint64_t g0 = t0 + (uint64_t)wave * 64 * kCompactGroups;
+        uint32_t x[kCompactGroups][NC];
+        int64_t w[kCompactGroups];
+        uint64_t bal[kCompactGroups];
+        uint32_t total = 0;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) x[c] = s_qx[wave][c][slot];
-            uint32_t j, neg, flag;
-            K.bin_neg_fast(x, j, neg, flag);
-            if (flag >= canon_thresh) {
-                j = K.bin(x);
-                neg = K.neg(x);
-            }
-            if constexpr (HW) neg ^= (s_qn[wave][slot >> 5] >> (slot & 31)) & 1u;
-            j &= m - 1;
-            const uint32_t inc = inc16(neg, (j & 1u) << 4);
-            uint32_t *w = &s_w[j >> 1];
-            const uint32_t old = atomicAdd(w, inc);
-            if (out16(old, inc)) spill16(w, shift16(inc), srow + j);
+        for (int g = 0; g < kCompactGroups; ++g) {
+            const uint64_t i = g0 + (uint64_t)g * 64 + lane;
+            const bool in = i < n && passes(attrs, n_attrs, i, f);
+            bal[g] = __ballot(in);
+            total += (uint32_t)__popcll(bal[g]);
+            const uint64_t ic = i < n ? i : 0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) x[g][c] = keys[ic * NC + c];
+            if constexpr (HW) w[g] = weights[ic];
         }
-        head = (head + k) & (kQCap - 1);
-        count -= k;
-    };
-    constexpr int kU = 4;
-    struct Pass {
-        uint64_t bits[kU];  // wave-uniform mask words
-        uint32_t x[kU][NC];
-        uint32_t negw;
-    };
-    const uint64_t step = (uint64_t)kSegBlock * kU;
-    auto load_pass = [&](uint64_t base, Pass &P) {
-        P.negw = 0;
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const uint64_t g0 = base + (uint64_t)u * 64;
-            P.bits[u] = g0 < end ? mask[g0 / 64] : 0ull;
-            const uint64_t i = g0 + lane;
-            if ((P.bits[u] >> lane) & 1ull) {  // kept tuples only (i < end)
-                load_keys<NC>(keys, i, vec2, P.x[u]);
-                if constexpr (HW) P.negw |= (uint32_t)(weights[i] < 0) << u;
+        if (lane == 0) s_cnt[wave] = total;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t sum = 0;
+            for (int v = 0; v < kCB / 64; ++v) sum += s_cnt[v];
+            unsigned long long b = sum ? atomicAdd(count, (unsigned long long)sum) : 0ull;
+            if (kept && sum) atomicAdd(kept, (unsigned long long)sum);
+            for (int v = 0; v < kCB / 64; ++v) {
+                s_base[v] = b;
+                b += s_cnt[v];
             }
         }
-    };
-    auto run_pass = [&](const Pass &P) {
+        __syncthreads();
+        unsigned long long o = s_base[wave];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const uint64_t b = P.bits[u];
-            if ((b >> lane) & 1ull) {
-                const uint32_t pos = (uint32_t)__popcll(b & ((1ull << lane) - 1ull));
-                const uint32_t slot = (head + count + pos) & (kQCap - 1);
+        for (int g = 0; g < kCompactGroups; ++g) {
+            if ((bal[g] >> lane) & 1ull) {
+                const uint64_t dst = o + (uint64_t)__popcll(bal[g] & ((1ull << lane) - 1ull));
 #pragma unroll
-                for (int c = 0; c < NC; ++c) s_qx[wave][c][slot] = P.x[u][c];
-                if constexpr (HW) {
-                    const uint32_t bit = 1u << (slot & 31);
-                    if ((P.negw >> u) & 1u) atomicOr(&s_qn[wave][slot >> 5], bit);
-                    else atomicAnd(&s_qn[wave][slot >> 5], ~bit);
-                }
+                for (int c = 0; c < NC; ++c) okeys[dst * NC + c] = x[g][c];
+                if constexpr (HW) ow[dst] = w[g];
             }
-            count += (uint32_t)__popcll(b);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (count >= 64) drain(64);
+            o += (uint64_t)__popcll(bal[g]);
         }
-    };
-    uint64_t base = begin + (uint64_t)wave * 64 * kU;
-    if (base < end) {
-        Pass A, B;
-        load_pass(base, A);
-        for (;;) {
-            const uint64_t nb = base + step;
-            if (nb < end) load_pass(nb, B);
-            run_pass(A);
-            base = nb;
-            if (base >= end) break;
-            const uint64_t nb2 = base + step;
-            if (nb2 < end) load_pass(nb2, A);
-            run_pass(B);
-            base = nb2;
-            if (base >= end) break;
-        }
+        __syncthreads();  // s_cnt / s_base are rewritten by the next tile
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (count > 0) drain(count);
-    __syncthreads();
-    const uint64_t cells = (uint64_t)gridDim.y * m;
-    uint32_t *out = partial + (size_t)wg.chunk * (cells >> 1) + (((uint64_t)t * m) >> 1);
-    for (uint32_t e = threadIdx.x; e < m / 2; e += kSegBlock) out[e] = s_w[e];
 }
 
 // sketch[2w + h] += sum over chunks of (half h of partial[chunk][w]) - 2^15
@@ -1494,38 +1414,45 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
         if constexpr (NC <= 2) {
             if (e1 && unit && a.scratch && a.m > (1u << 16)) {
                 strategy = CS_UPDATE_PARTITION;  // handled below with the filter
-            } else if (e1 && unit && a.scratch && a.m >= 2) {
-                // predicate pass into a bit mask after the partial sums, then the 16-bit
-                // update of the kept tuples, in rounds of as many tuples as the mask holds
+            } else if (e1 && unit && a.scratch && a.m > (1u << 15) && a.m % 2 == 0) {
+                // one compaction pass per round (predicates evaluated once per tuple, kept
+                // keys written contiguously, their count left on the device), then the
+                // 16-bit quad kernel over the kept tuples, reading that count
                 const uint64_t cells = (uint64_t)a.d * a.m;
-                int32_t C0 = std::max(1, std::min(64, 256 / a.d));
-                while (C0 > 1 && (uint64_t)C0 * cells * 2 + (1u << 20) > a.scratch_bytes) --C0;
-                const size_t part_bytes = (((size_t)C0 * cells * 2) + 255) & ~(size_t)255;
-                if (part_bytes + 4096 > a.scratch_bytes)
+                SegGeom g16 = seg16_geometry(a.m, a.d, a.scratch_bytes / 2, a.n);
+                const size_t part_bytes = (((size_t)g16.chunks * cells * 2) + 255) & ~(size_t)255;
+                const size_t per_tuple = (size_t)NC * 4 + (a.weights ? 8 : 0);
+                if (part_bytes + 512 + 64 * per_tuple > a.scratch_bytes)
                     return fail(CS_EINVAL, "update scratch buffer too small for a filtered update");
-                const uint64_t round_max = (uint64_t)((a.scratch_bytes - part_bytes) / 8) * 64;  // tuples per mask
+                const uint64_t round_max = ((a.scratch_bytes - part_bytes - 512) / per_tuple) & ~(uint64_t)63;
                 uint32_t *part = reinterpret_cast<uint32_t *>(a.scratch);
-                auto *mask = reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(a.scratch) + part_bytes);
-                auto kern = a.weights ? &k_update_seg16f<NC, true> : &k_update_seg16f<NC, false>;
+                auto *cnt = reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(a.scratch) + part_bytes);
+                uint32_t *okeys = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(a.scratch) + part_bytes + 256);
+                const size_t wo = (((size_t)round_max * NC * 4) + 255) & ~(size_t)255;
+                int64_t *ow = a.weights ? reinterpret_cast<int64_t *>(reinterpret_cast<char *>(okeys) + wo) : nullptr;
+                if (a.weights && (part_bytes + 256 + wo + round_max * 8) > a.scratch_bytes)
+                    return fail(CS_EINVAL, "update scratch buffer too small for a filtered update");
+                auto ck = a.weights ? &k_filter_compact<NC, true> : &k_filter_compact<NC, false>;
+                auto kern = a.weights ? &k_update_seg16q<NC, true, true, true> : &k_update_seg16q<NC, true, false, true>;
+                dim3 grid16((unsigned)g16.chunks, (unsigned)g16.segments);
+                if (g16.R != a.m || g16.segments != a.d) return fail(CS_EINVAL, "16-bit segment geometry");
                 CSK_MARK(a.ev_start, s);
                 for (uint64_t r0 = 0; r0 < a.n; r0 += round_max) {
                     const uint64_t rn = std::min<uint64_t>(a.n - r0, round_max);
-                    const uint32_t *kb = a.keys + r0 * NC;
-                    const int64_t *wb = a.weights ? a.weights + r0 : nullptr;
-                    const bool v2 = NC == 2 && ((uintptr_t)kb % 8) == 0;
-                    const uint64_t mwords = (rn + 63) / 64;
-                    hipLaunchKernelGGL(k_filter_mask, dim3((unsigned)std::min<uint64_t>((mwords + 3) / 4, 4096)),
-                                       dim3(kBlock), 0, s, a.attrs + r0 * (uint64_t)a.n_attrs, a.n_attrs, rn,
-                                       *a.filter, mask, a.kept);
+                    cs_status zs = zero_device_u64(cnt, s);
+                    if (zs != CS_OK) return zs;
+                    const uint64_t tile = (uint64_t)kCB * kCompactGroups;
+                    hipLaunchKernelGGL(ck, dim3((unsigned)std::min<uint64_t>((rn + tile - 1) / tile, 8192)), dim3(kCB), 0,
+                                       s, a.keys + r0 * NC, a.weights ? a.weights + r0 : nullptr, rn,
+                                       a.attrs + r0 * (uint64_t)a.n_attrs, a.n_attrs, *a.filter, okeys, ow, cnt, a.kept);
                     CSK_HIP(hipGetLastError());
-                    const int32_t C = chunks_for_n(C0, rn);
-                    const uint64_t chunk = ((rn + C - 1) / C + 63) & ~(uint64_t)63;  // whole mask words
-                    hipLaunchKernelGGL(kern, dim3((unsigned)C, (unsigned)a.d), dim3(kSegBlock), 0, s, kb, wb, rn,
-                                       a.coef, a.plan.coef_per_rep, a.m, chunk, v2, mask, part, sk, a.canon_thresh);
+                    hipLaunchKernelGGL(kern, grid16, dim3(kSegBlock), 0, s, okeys, ow, rn, a.coef, a.plan.coef_per_rep,
+                                       plan, a.m, (uint64_t)4, part, sk, a.canon_thresh,
+                                       (const unsigned long long *)cnt);
                     CSK_HIP(hipGetLastError());
                     const uint64_t words = cells / 2;
                     hipLaunchKernelGGL(k_seg_reduce16, dim3((unsigned)std::min<uint64_t>((words + 255) / 256, 8192)),
-                                       dim3(256), 0, s, part, C, words, sk);
+                                       dim3(256), 0, s, part, g16.chunks, words, sk);
                     CSK_HIP(hipGetLastError());
                 }
                 CSK_MARK(a.ev_stop, s);
@@ -1617,7 +1544,8 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
                 auto kern = a.weights ? (a16 ? pick(T_{}, T_{}) : pick(T_{}, F_{}))
                                       : (a16 ? pick(F_{}, T_{}) : pick(F_{}, F_{}));
                 hipLaunchKernelGGL(kern, grid16, dim3(kSegBlock), 0, s, a.keys, a.weights, a.n, a.coef,
-                                   a.plan.coef_per_rep, plan, a.m, chunkq, part, sk64, a.canon_thresh);
+                                   a.plan.coef_per_rep, plan, a.m, chunkq, part, sk64, a.canon_thresh,
+                                   (const unsigned long long *)nullptr);
             } else {
                 const uint64_t chunk16 = (a.n + g16.chunks - 1) / g16.chunks;
                 auto kern = a.weights ? (e1 ? &k_update_seg16<NC, true, true> : &k_update_seg16<NC, false, true>)

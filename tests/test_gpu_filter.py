@@ -32,7 +32,8 @@ CASES = [
     (W.chain(3), 300_001, 1 << 20, 3, None, [(2, 1, 1), (1, 0, 8)]), # partition, one column kept in 8
     (W.multiway_star(3), 80_000, 1 << 17, 5, None, [(1, 0, 4)]),     # a column in two joins: atomics
     (W.chain(3), 90_000, 100_003, 5, "pm1", [(0, 0, 2 ** 30)]),      # m not a power of two: atomics
-    (W.chain(3), 120_000, 1 << 15, 5, None, [(0, 0, 2 ** 31), (1, 0, 6), (2, 1, 7)]),  # 16-bit, 3 predicates
+    (W.chain(3), 120_000, 1 << 16, 5, "pm1", [(0, 0, 2 ** 31), (1, 0, 6), (2, 1, 7)]),  # compacted, 3 predicates
+    (W.chain(3), 70_000, 1 << 15, 5, None, [(1, 0, 4)]),             # m = 2^15: atomics
 ]
 
 
