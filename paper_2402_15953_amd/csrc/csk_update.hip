@@ -1419,7 +1419,7 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
                 // keys written contiguously, their count left on the device), then the
                 // 16-bit quad kernel over the kept tuples, reading that count
                 const uint64_t cells = (uint64_t)a.d * a.m;
-                SegGeom g16 = seg16_geometry(a.m, a.d, a.scratch_bytes / 2, a.n);
+                SegGeom g16 = seg16_geometry(a.m, a.d, a.scratch_bytes / 2, a.n);  // at most half for partial sums
                 const size_t part_bytes = (((size_t)g16.chunks * cells * 2) + 255) & ~(size_t)255;
                 const size_t per_tuple = (size_t)NC * 4 + (a.weights ? 8 : 0);
                 if (part_bytes + 512 + 64 * per_tuple > a.scratch_bytes)
@@ -1777,6 +1777,13 @@ size_t seg_scratch_bytes(uint32_t m, int32_t d)
         const int32_t ranges = (int32_t)(((uint64_t)m + kPartR - 1) >> kPartLog2R);
         const uint64_t nblk = m > (1u << 16) ? kPartMaxChunk / kPartBlk : 16;
         best = std::max<size_t>(best, (size_t)nblk * part_bytes_per_block(d, ranges) + 512);
+    }
+    // a filtered update with 16-bit counters (2^15 < m <= 2^16): half the buffer for the
+    // partial sums, the rest for the kept tuples' keys, in rounds of 2^23 two-column tuples
+    if (m > (1u << 15) && m <= (1u << 16)) {
+        const SegGeom g16 = seg16_geometry(m, d, (size_t)-1);
+        const size_t part = (size_t)g16.chunks * (size_t)d * m * 2;
+        best = std::max<size_t>(best, std::max<size_t>(2 * part, part + ((size_t)8 << 23)) + 1024);
     }
     return best;
 }
