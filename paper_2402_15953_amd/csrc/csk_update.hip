@@ -789,35 +789,47 @@ __global__ __launch_bounds__(kSegBlock) void k_update_seg16c(const uint32_t *__r
 // reserves its tile's slots with one atomic.  The kept tuples' order is not kept: the
 // counters, integer sums, do not depend on it.  Each tuple's predicates are evaluated
 // once here, instead of once per repetition in the update kernel.
-constexpr int kCompactGroups = 16;
 constexpr int kCB = 256;  // compaction workgroup: 4 wavefronts
-template <int NC, bool HW>
+template <int NC, bool HW, int MAXP>
 __global__ __launch_bounds__(kCB) void k_filter_compact(const uint32_t *__restrict__ keys,
                                                         const int64_t *__restrict__ weights, uint64_t n,
                                                         const uint32_t *__restrict__ attrs, int32_t n_attrs,
-                                                        FilterSpec f, uint32_t *okeys, int64_t *ow,
+                                                        FilterSpec f, bool vec2, uint32_t *okeys, int64_t *ow,
                                                         unsigned long long *count, unsigned long long *kept)
 {
+    // groups of 64 tuples per wavefront and tile: all their loads are issued before the
+    // first predicate is evaluated (at most MAXP attribute values held per tuple)
+    constexpr int kG = MAXP > 2 ? 4 : 16;
     __shared__ uint32_t s_cnt[kCB / 64];
     __shared__ unsigned long long s_base[kCB / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint64_t tile = (uint64_t)kCB * kCompactGroups;
+    const uint64_t tile = (uint64_t)kCB * kG;
+    const int np = f.n;
     for (uint64_t t0 = (uint64_t)blockIdx.x * tile; t0 < n; t0 += (uint64_t)gridDim.x * tile) {
-        const uint64_t g0 = t0 + (uint64_t)wave * 64 * kCompactGroups;
-        uint32_t x[kCompactGroups][NC];
-        int64_t w[kCompactGroups];
-        uint64_t bal[kCompactGroups];
+        const uint64_t g0 = t0 + (uint64_t)wave * 64 * kG;
+        uint32_t av[kG][MAXP];
+        uint32_t x[kG][NC];
+        int64_t w[kG];
+#pragma unroll
+        for (int g = 0; g < kG; ++g) {
+            const uint64_t i = g0 + (uint64_t)g * 64 + lane;
+            const uint64_t ic = i < n ? i : n - 1;  // clamped: every load stays in bounds
+#pragma unroll
+            for (int p = 0; p < MAXP; ++p)
+                if (p < np) av[g][p] = attrs[ic * (uint64_t)n_attrs + f.col[p]];
+            load_keys<NC>(keys, ic, vec2, x[g]);
+            if constexpr (HW) w[g] = weights[ic];
+        }
+        uint64_t bal[kG];
         uint32_t total = 0;
 #pragma unroll
-        for (int g = 0; g < kCompactGroups; ++g) {
-            const uint64_t i = g0 + (uint64_t)g * 64 + lane;
-            const bool in = i < n && passes(attrs, n_attrs, i, f);
+        for (int g = 0; g < kG; ++g) {
+            bool in = g0 + (uint64_t)g * 64 + lane < n;
+#pragma unroll
+            for (int p = 0; p < MAXP; ++p)
+                if (p < np) in = in && av[g][p] >= f.lo[p] && av[g][p] <= f.hi[p];
             bal[g] = __ballot(in);
             total += (uint32_t)__popcll(bal[g]);
-            const uint64_t ic = i < n ? i : 0;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) x[g][c] = keys[ic * NC + c];
-            if constexpr (HW) w[g] = weights[ic];
         }
         if (lane == 0) s_cnt[wave] = total;
         __syncthreads();
@@ -834,11 +846,15 @@ __global__ __launch_bounds__(kCB) void k_filter_compact(const uint32_t *__restri
         __syncthreads();
         unsigned long long o = s_base[wave];
 #pragma unroll
-        for (int g = 0; g < kCompactGroups; ++g) {
+        for (int g = 0; g < kG; ++g) {
             if ((bal[g] >> lane) & 1ull) {
                 const uint64_t dst = o + (uint64_t)__popcll(bal[g] & ((1ull << lane) - 1ull));
+                if constexpr (NC == 2) {
+                    reinterpret_cast<uint2 *>(okeys)[dst] = make_uint2(x[g][0], x[g][1]);
+                } else {
 #pragma unroll
-                for (int c = 0; c < NC; ++c) okeys[dst * NC + c] = x[g][c];
+                    for (int c = 0; c < NC; ++c) okeys[dst * NC + c] = x[g][c];
+                }
                 if constexpr (HW) ow[dst] = w[g];
             }
             o += (uint64_t)__popcll(bal[g]);
@@ -1432,7 +1448,10 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
                 int64_t *ow = a.weights ? reinterpret_cast<int64_t *>(reinterpret_cast<char *>(okeys) + wo) : nullptr;
                 if (a.weights && (part_bytes + 256 + wo + round_max * 8) > a.scratch_bytes)
                     return fail(CS_EINVAL, "update scratch buffer too small for a filtered update");
-                auto ck = a.weights ? &k_filter_compact<NC, true> : &k_filter_compact<NC, false>;
+                const bool few = a.filter->n <= 2;
+                auto ck = a.weights ? (few ? &k_filter_compact<NC, true, 2> : &k_filter_compact<NC, true, CS_MAX_PREDICATES>)
+                                    : (few ? &k_filter_compact<NC, false, 2> : &k_filter_compact<NC, false, CS_MAX_PREDICATES>);
+                const uint64_t tile = (uint64_t)kCB * (few ? 16 : 4);
                 auto kern = a.weights ? &k_update_seg16q<NC, true, true, true> : &k_update_seg16q<NC, true, false, true>;
                 dim3 grid16((unsigned)g16.chunks, (unsigned)g16.segments);
                 if (g16.R != a.m || g16.segments != a.d) return fail(CS_EINVAL, "16-bit segment geometry");
@@ -1441,10 +1460,12 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
                     const uint64_t rn = std::min<uint64_t>(a.n - r0, round_max);
                     cs_status zs = zero_device_u64(cnt, s);
                     if (zs != CS_OK) return zs;
-                    const uint64_t tile = (uint64_t)kCB * kCompactGroups;
+                    const uint32_t *kb = a.keys + r0 * NC;
+                    const bool v2 = NC == 2 && ((uintptr_t)kb % 8) == 0;
                     hipLaunchKernelGGL(ck, dim3((unsigned)std::min<uint64_t>((rn + tile - 1) / tile, 8192)), dim3(kCB), 0,
-                                       s, a.keys + r0 * NC, a.weights ? a.weights + r0 : nullptr, rn,
-                                       a.attrs + r0 * (uint64_t)a.n_attrs, a.n_attrs, *a.filter, okeys, ow, cnt, a.kept);
+                                       s, kb, a.weights ? a.weights + r0 : nullptr, rn,
+                                       a.attrs + r0 * (uint64_t)a.n_attrs, a.n_attrs, *a.filter, v2, okeys, ow, cnt,
+                                       a.kept);
                     CSK_HIP(hipGetLastError());
                     hipLaunchKernelGGL(kern, grid16, dim3(kSegBlock), 0, s, okeys, ow, rn, a.coef, a.plan.coef_per_rep,
                                        plan, a.m, (uint64_t)4, part, sk, a.canon_thresh,
@@ -1778,12 +1799,13 @@ size_t seg_scratch_bytes(uint32_t m, int32_t d)
         const uint64_t nblk = m > (1u << 16) ? kPartMaxChunk / kPartBlk : 16;
         best = std::max<size_t>(best, (size_t)nblk * part_bytes_per_block(d, ranges) + 512);
     }
-    // a filtered update with 16-bit counters (2^15 < m <= 2^16): half the buffer for the
-    // partial sums, the rest for the kept tuples' keys, in rounds of 2^23 two-column tuples
+    // a filtered update with 16-bit counters (2^15 < m <= 2^16): the partial sums, then
+    // the kept tuples' keys (and Deltas) in rounds of 2^23 tuples of two columns with
+    // weights (16 bytes each), or 2^24 of two columns without
     if (m > (1u << 15) && m <= (1u << 16)) {
         const SegGeom g16 = seg16_geometry(m, d, (size_t)-1);
         const size_t part = (size_t)g16.chunks * (size_t)d * m * 2;
-        best = std::max<size_t>(best, std::max<size_t>(2 * part, part + ((size_t)8 << 23)) + 1024);
+        best = std::max<size_t>(best, std::max<size_t>(2 * part, part + ((size_t)16 << 23)) + 1024);
     }
     return best;
 }
