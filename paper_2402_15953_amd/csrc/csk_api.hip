@@ -327,7 +327,8 @@ cs_status create_handle(const cs_graph *graph, uint32_t m, uint32_t d, uint64_t 
             return fail(CS_ENOMEM, "update scratch allocation failed");
         }
     }
-    if (hipMalloc(&h.kept_dev, sizeof(unsigned long long)) != hipSuccess ||
+    if (hipMalloc(&h.kept_dev, 2 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMemset(h.kept_dev, 0, 2 * sizeof(unsigned long long)) != hipSuccess ||
         hipMemcpy(h.coef_dev, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(h.counters, 0, n_ctr * sizeof(int64_t)) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
@@ -413,6 +414,7 @@ cs_status update_args(cs_sketch *hs, int32_t rel, const uint32_t *keys, const in
     a.plan = h.g.rel[rel];
     a.scratch = h.scratch;
     a.scratch_bytes = h.scratch_bytes;
+    a.filter_count = h.kept_dev ? h.kept_dev + 1 : nullptr;
     a.unit_weights = (flags & CS_UPDATE_UNIT_WEIGHTS) != 0;
     a.compact = (flags & CS_UPDATE_NO_COMPACT) == 0;
     a.counters16 = (flags & CS_UPDATE_NO_COUNTERS16) == 0;

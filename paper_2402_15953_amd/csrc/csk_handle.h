@@ -63,7 +63,9 @@ struct Handle {
     void *scratch = nullptr;           // partial sums of the LDS-segmented update
     size_t scratch_bytes = 0;
     void *result_host = nullptr;       // pinned host staging for results
-    unsigned long long *kept_dev = nullptr;  // device count of a filtered update's kept tuples
+    // two device words: [0] the kept tuples of a filtered update that asked for the
+    // count, [1] the per-round count of the filtered 16-bit path (zero between updates)
+    unsigned long long *kept_dev = nullptr;
 };
 
 cs_status estimate_run(Handle &h, hipStream_t s, cs_estimate_t *out, const cs_reps_t *reps);

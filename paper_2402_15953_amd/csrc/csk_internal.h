@@ -147,6 +147,9 @@ struct UpdateArgs {
     const uint32_t *attrs = nullptr;
     int32_t n_attrs = 0;
     unsigned long long *kept = nullptr;
+    // a device word that is zero between filtered updates (the handle's), used by the
+    // filtered 16-bit path for its per-round count of kept tuples
+    unsigned long long *filter_count = nullptr;
 };
 struct SegGeom {
     uint32_t R;        // counter cells per segment

@@ -864,9 +864,12 @@ __global__ __launch_bounds__(kCB) void k_filter_compact(const uint32_t *__restri
 }
 
 // sketch[2w + h] += sum over chunks of (half h of partial[chunk][w]) - 2^15
+// reset, when set, is a device count the update kernel has finished reading (a filtered
+// update's kept tuples): it is set back to zero for the handle's next filtered update.
 __global__ void k_seg_reduce16(const uint32_t *__restrict__ partial, int32_t C, uint64_t words,
-                               unsigned long long *sketch)
+                               unsigned long long *sketch, unsigned long long *reset = nullptr)
 {
+    if (reset && blockIdx.x == 0 && threadIdx.x == 0) *reset = 0ull;
     for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words;
          w += (uint64_t)gridDim.x * blockDim.x) {
         int64_t lo = 0, hi = 0;
@@ -1442,7 +1445,10 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
                     return fail(CS_EINVAL, "update scratch buffer too small for a filtered update");
                 const uint64_t round_max = ((a.scratch_bytes - part_bytes - 512) / per_tuple) & ~(uint64_t)63;
                 uint32_t *part = reinterpret_cast<uint32_t *>(a.scratch);
-                auto *cnt = reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(a.scratch) + part_bytes);
+                // the handle's kept-tuple counter: zero between filtered updates (set at
+                // creation, and back to zero by the reduction of every round)
+                unsigned long long *cnt = a.filter_count;
+                if (!cnt) return fail(CS_EINVAL, "filtered update without a device counter");
                 uint32_t *okeys = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(a.scratch) + part_bytes + 256);
                 const size_t wo = (((size_t)round_max * NC * 4) + 255) & ~(size_t)255;
                 int64_t *ow = a.weights ? reinterpret_cast<int64_t *>(reinterpret_cast<char *>(okeys) + wo) : nullptr;
@@ -1458,8 +1464,6 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
                 CSK_MARK(a.ev_start, s);
                 for (uint64_t r0 = 0; r0 < a.n; r0 += round_max) {
                     const uint64_t rn = std::min<uint64_t>(a.n - r0, round_max);
-                    cs_status zs = zero_device_u64(cnt, s);
-                    if (zs != CS_OK) return zs;
                     const uint32_t *kb = a.keys + r0 * NC;
                     const bool v2 = NC == 2 && ((uintptr_t)kb % 8) == 0;
                     hipLaunchKernelGGL(ck, dim3((unsigned)std::min<uint64_t>((rn + tile - 1) / tile, 8192)), dim3(kCB), 0,
@@ -1473,7 +1477,7 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
                     CSK_HIP(hipGetLastError());
                     const uint64_t words = cells / 2;
                     hipLaunchKernelGGL(k_seg_reduce16, dim3((unsigned)std::min<uint64_t>((words + 255) / 256, 8192)),
-                                       dim3(256), 0, s, part, g16.chunks, words, sk);
+                                       dim3(256), 0, s, part, g16.chunks, words, sk, cnt);
                     CSK_HIP(hipGetLastError());
                 }
                 CSK_MARK(a.ev_stop, s);
@@ -1580,7 +1584,7 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
             const uint64_t words = cells / 2;
             hipLaunchKernelGGL(k_seg_reduce16, dim3((unsigned)std::min<uint64_t>((words + 255) / 256, 8192)),
                                dim3(256), 0, s, part, g16.chunks, words,
-                               reinterpret_cast<unsigned long long *>(a.sketch));
+                               reinterpret_cast<unsigned long long *>(a.sketch), (unsigned long long *)nullptr);
         } else if (narrow && e1 && a.m > (1u << 16) && NC <= 2 && a.compact && a.counters16) {
             // 16-bit bucket ranges of 2^16 with compaction (e1 implies m a power of two)
             if constexpr (NC <= 2) {
@@ -1602,7 +1606,7 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
                 CSK_MARK(a.ev_stop, s);
                 const uint64_t words = cells / 2;
                 hipLaunchKernelGGL(k_seg_reduce16, dim3((unsigned)std::min<uint64_t>((words + 255) / 256, 8192)),
-                                   dim3(256), 0, s, part, gc.chunks, words, sk64);
+                                   dim3(256), 0, s, part, gc.chunks, words, sk64, (unsigned long long *)nullptr);
             }
         } else if (narrow && e1 && sg.R < a.m && NC <= 2 && a.compact) {
             // bucket-range segments: compacting kernel (queue after the counters in LDS)
