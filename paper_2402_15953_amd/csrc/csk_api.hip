@@ -331,7 +331,7 @@ cs_status create_handle(const cs_graph *graph, uint32_t m, uint32_t d, uint64_t 
         hipMemset(h.kept_dev, 0, 2 * sizeof(unsigned long long)) != hipSuccess ||
         hipMemcpy(h.coef_dev, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(h.counters, 0, n_ctr * sizeof(int64_t)) != hipSuccess ||
-        hipDeviceSynchronize() != hipSuccess) {
+        hipStreamSynchronize(nullptr) != hipSuccess) {  // the null stream only: other streams' work is not waited for
         hipFree(h.counters);
         hipFree(h.coef_dev);
         hipFree(h.scratch);

@@ -1031,14 +1031,20 @@ const std::vector<PrimeInfo> &ntt_primes()
     return P;
 }
 
+// The table builders compute on the host and upload outside the table lock (a thread
+// that needs a table never waits on the lock while another thread's allocation or copy
+// is in flight); when two threads build the same table at once, the first insert wins and
+// the other frees its copy.
 const double *twiddles_f64(int device, int log2m, hipStream_t s, cs_status *st)
 {
-    std::lock_guard<std::mutex> lk(g_tab_mu);
-    DeviceTables &T = g_tabs[device];
-    auto it = T.tw.find(log2m);
-    if (it != T.tw.end()) {
-        *st = CS_OK;
-        return reinterpret_cast<const double *>(it->second);
+    {
+        std::lock_guard<std::mutex> lk(g_tab_mu);
+        DeviceTables &T = g_tabs[device];
+        auto it = T.tw.find(log2m);
+        if (it != T.tw.end()) {
+            *st = CS_OK;
+            return reinterpret_cast<const double *>(it->second);
+        }
     }
     const size_t m = (size_t)1 << log2m;
     std::vector<double2> h(m);
@@ -1084,23 +1090,29 @@ const double *twiddles_f64(int device, int log2m, hipStream_t s, cs_status *st)
         return nullptr;
     }
     if (hipMemcpy(dp, h.data(), m * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(dp);
         *st = fail(CS_EDEVICE, "twiddle upload failed");
         return nullptr;
     }
     (void)s;
-    T.tw[log2m] = dp;
+    std::lock_guard<std::mutex> lk(g_tab_mu);
+    DeviceTables &T = g_tabs[device];
+    auto ins = T.tw.emplace(log2m, dp);
+    if (!ins.second) (void)hipFree(dp);  // built meanwhile by another thread
     *st = CS_OK;
-    return reinterpret_cast<const double *>(dp);
+    return reinterpret_cast<const double *>(ins.first->second);
 }
 
 const uint32_t *roots_mod(int device, int log2m, int /*prime*/, bool /*inverse*/, hipStream_t s, cs_status *st)
 {
-    std::lock_guard<std::mutex> lk(g_tab_mu);
-    DeviceTables &T = g_tabs[device];
-    auto it = T.roots.find(log2m);
-    if (it != T.roots.end()) {
-        *st = CS_OK;
-        return it->second;
+    {
+        std::lock_guard<std::mutex> lk(g_tab_mu);
+        DeviceTables &T = g_tabs[device];
+        auto it = T.roots.find(log2m);
+        if (it != T.roots.end()) {
+            *st = CS_OK;
+            return it->second;
+        }
     }
     const auto &P = ntt_primes();
     const size_t m = (size_t)1 << log2m;
@@ -1128,13 +1140,17 @@ const uint32_t *roots_mod(int device, int log2m, int /*prime*/, bool /*inverse*/
         return nullptr;
     }
     if (hipMemcpy(dp, h.data(), h.size() * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(dp);
         *st = fail(CS_EDEVICE, "root table upload failed");
         return nullptr;
     }
     (void)s;
-    T.roots[log2m] = dp;
+    std::lock_guard<std::mutex> lk(g_tab_mu);
+    DeviceTables &T = g_tabs[device];
+    auto ins = T.roots.emplace(log2m, dp);
+    if (!ins.second) (void)hipFree(dp);  // built meanwhile by another thread
     *st = CS_OK;
-    return dp;
+    return ins.first->second;
 }
 
 // ---------------------------------------------------------------- host: batched estimate engine
