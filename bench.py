@@ -45,7 +45,8 @@ HBM_PEAK_GBS = 8000.0
 # the low 61 bits), so 5.62e12 steps/s.  The probe kernel of independent steps
 # (cs_k0_horner) measures what the chip sustains in the same run.
 ALU_STEP_PEAK = 256 * 4 * 16 * 2.4e9 / 7.0
-SECTIONS = ("chain5", "chain3", "single", "k0", "filtered", "anym", "ams", "attr", "batched", "serving", "cpu")
+SECTIONS = ("chain5", "chain3", "single", "k0", "filtered", "anym", "ams", "attr", "subq", "batched", "serving",
+            "cpu")
 
 
 def parse():
@@ -496,6 +497,10 @@ def main():
             progress("attribute-sketch section done")
         del keys3
         torch.cuda.empty_cache()
+    if "subq" in sections:
+        out["subqueries"] = bench_subq(dev, stream, args.steps)
+        progress("sub-query section done")
+        torch.cuda.empty_cache()
     if "batched" in sections and args.batch_queries > 0:
         out["batched"] = bench_batched(args.batch_queries, dev, stream)
         progress("batched section done")
@@ -595,6 +600,82 @@ def bench_attr(keys, graph, stream, steps, m=1 << 16, d=9):
     return {"workload": f"chain-3 attribute sketches (4 attributes), 1e7 tuples/relation, m={m}, d={d}, "
                         "then both pairwise joins", "input_tuples_per_s": total / dt, "ms_per_step": dt * 1e3,
             "estimates": [r["value"] for r in res]}
+
+
+def bench_subq(dev, stream, steps, calls=4, m=1 << 18, d=15):
+    """Sub-query sketches for a join-order search (Sec. 3.4): every connected sub-chain
+    of the 5-chain (10 sub-queries), 4 calls of 2^20 tuples per relation, Zipf(1.0) over
+    10^7, m = 2^18, d = 15.  One pass per relation fills the 11 distinct sketches
+    (cs_subq_update), then one batched estimate of all sub-queries; beside it the plain
+    path builds one query handle per sub-query (30 relation sketches, each relation's
+    keys read once per sub-query it is in, its kept columns prepared beforehand) and
+    estimates them one by one."""
+    import torch
+
+    import paper_2402_15953_amd as csk
+    import workloads as W
+    g = W.chain(5)
+    masks = W.connected_subqueries(g)
+    n_call = 1 << 20
+    n = calls * n_call
+    keys = [W.relation_keys(g, k, n, "zipf", config=3, s=1.0, D=10 ** 7, device=dev).to(torch.int32).contiguous()
+            for k in range(g.n_rel)]
+    sq = csk.SubQueries(g, masks, m, d, 21)
+    n_targets, _ = sq.layout()
+    plain = []
+    for mk in masks:
+        gq, rels, cols = W.subquery_graph(g, mk)
+        sub_keys = [keys[k][:, c].contiguous() for k, c in zip(rels, cols)]
+        plain.append((csk.Sketch(gq, m, d, 21), sub_keys))
+    torch.cuda.synchronize()
+
+    def subq_step(ev=None):
+        sq.reset(stream=stream)
+        for k in range(g.n_rel):
+            for c in range(calls):
+                sq.update(k, keys[k][c * n_call:(c + 1) * n_call], stream=stream)
+        if ev:
+            ev.record(stream)
+        return sq.estimate_all(stream=stream)
+
+    def plain_step(ev=None):
+        for sk, sub_keys in plain:
+            sk.reset(stream=stream)
+            for i, kk in enumerate(sub_keys):
+                for c in range(calls):
+                    sk.update(i, kk[c * n_call:(c + 1) * n_call], None, stream=stream)
+        if ev:
+            ev.record(stream)
+        return [sk.estimate(stream=stream) for sk, _ in plain]
+
+    res = {}
+    with torch.cuda.stream(stream):
+        for name, fn in (("subq", subq_step), ("plain", plain_step)):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                fn()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            ta, tb = csk.Timer(), csk.Timer()
+            ta.record(stream)
+            fn(tb)
+            torch.cuda.synchronize()
+            res[name] = (dt, ta.elapsed_ms(tb))
+    sq.close()
+    for sk, _ in plain:
+        sk.close()
+    total = n * g.n_rel
+    return {"workload": "all 10 connected sub-chains of the 5-chain, 4 x 2^20 tuples per relation, "
+                        f"Zipf(1.0) over 1e7, m={m}, d={d}",
+            "sub_queries": len(masks), "targets": n_targets,
+            "plain_relation_sketches": sum(len(W.subquery_graph(g, mk)[1]) for mk in masks),
+            "base_tuples_per_step": total,
+            "subq_tuples_per_s": total / res["subq"][0], "plain_tuples_per_s": total / res["plain"][0],
+            "speedup": res["plain"][0] / res["subq"][0],
+            "subq_ms_per_step": res["subq"][0] * 1e3, "plain_ms_per_step": res["plain"][0] * 1e3,
+            "subq_update_ms": res["subq"][1], "plain_update_ms": res["plain"][1]}
 
 
 def bench_ams(keys, graph, stream, d=5):

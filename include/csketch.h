@@ -535,6 +535,61 @@ cs_status cs_attr_read(const cs_attr *h, int32_t u, int64_t *host_out);
 /* Copy the hash coefficients: sign [d][n_comp][4], bin [d][n_comp][2] (either may be NULL). */
 cs_status cs_attr_coefficients(const cs_attr *h, uint64_t *sign_out, uint64_t *bin_out);
 
+/* ------------------------------------------------------------------ sub-query sketches */
+
+/* Sketches of the sub-queries a query optimizer evaluates (Sec. 3.4), built in one pass
+ * over each relation.  A sub-query is a connected set of the base query's joins, given
+ * as a bit mask (bit e = join e of `graph`); it is the query on the relations those
+ * joins touch, renumbered in ascending base order (relations, then attributes that one
+ * of its joins names, then its joins).
+ *
+ * Hash functions (drawn from SplitMix64(seed), each coefficient its output >> 3,
+ * redrawn when equal to p = 2^61 - 1): first, for each repetition t and base component
+ * q, a shared sign polynomial a0..a3 and a bin polynomial b0, b1 (the order and values
+ * cs_attr_create draws); then, for each repetition t and join e, a sign polynomial
+ * a0..a3.  In a sub-query, an attribute's bin hash is its base component's; a join's
+ * sign hash is its component's shared polynomial when it is the only join of that
+ * component in the sub-query (so an attribute's sketch is reused by every sub-query
+ * that joins it once, e.g. a pairwise join), and the join's own polynomial when the
+ * component holds two or more of the sub-query's joins (an attribute joined twice needs
+ * independent signs).  A relation's sketch in a sub-query is then fixed by its joined
+ * columns and their sign polynomials; the distinct sketches ("targets", int64 [d][m]
+ * each) are kept once and every sub-query reads its relations' targets.
+ *
+ * cs_subq_create: 2 <= m <= 2^20 (any m), 1 <= d <= 64, 1 <= n_sub <= 4096 masks,
+ *   relations of at most 4 attributes, at most 16 targets and 16 distinct (column, sign
+ *   polynomial) pairs per relation; allocates the targets' counters and a pass-1
+ *   buffer of at most ~256 MB.  Errors: CS_EINVAL (a mask that is empty, names no join
+ *   of the graph or is not connected; limits), CS_EGRAPH, CS_ENOMEM, CS_EDEVICE.
+ * cs_subq_update: one pass over n tuples of base relation rel (keys uint32 [n][a_rel]
+ *   as cs_update takes them, weights int64 [n] or NULL; device or pinned memory) adds
+ *   every target of rel (Alg. 2 with each target's columns and hash functions).
+ *   Deltas +1 (NULL) or +-1 with CS_UPDATE_UNIT_WEIGHTS take the two-pass record path;
+ *   other weights one global atomic per (tuple, target, repetition).  Stream-ordered,
+ *   allocates nothing; calls on one handle must not overlap (they share the pass-1
+ *   buffer).
+ * cs_subq_reset: zero every counter (stream-ordered).
+ * cs_subq_estimate: the estimate of sub-query q (Eq. 5 / Alg. 3 as cs_estimate, with
+ *   its plan), synchronous on stream; reps optional as for cs_estimate.
+ * cs_subq_estimate_all: every sub-query's estimate in one batched estimate (outs[n_sub]).
+ * cs_subq_layout: *n_targets, and target_of [n_sub][n_rel] = the target holding base
+ *   relation k's sketch in sub-query q (-1 when k is not in q); either may be NULL.
+ * cs_subq_read: copy target i's counters, int64 [d][m], to host memory (synchronises).
+ * cs_subq_coefficients: comp_sign [d][Q][4], bin [d][Q][2], join_sign [d][E][4] (any
+ *   may be NULL). */
+typedef struct cs_subq cs_subq;  /* opaque */
+cs_status cs_subq_create(const cs_graph *graph, const uint32_t *sub_joins, int32_t n_sub, uint32_t m,
+                         uint32_t d, uint64_t seed, cs_subq **out);
+cs_status cs_subq_destroy(cs_subq *h);
+cs_status cs_subq_update(cs_subq *h, int32_t rel, const uint32_t *keys, const int64_t *weights, uint64_t n,
+                         int32_t flags, void *stream);
+cs_status cs_subq_reset(cs_subq *h, void *stream);
+cs_status cs_subq_estimate(cs_subq *h, int32_t q, void *stream, cs_estimate_t *out, const cs_reps_t *reps);
+cs_status cs_subq_estimate_all(cs_subq *h, void *stream, cs_estimate_t *outs);
+cs_status cs_subq_layout(const cs_subq *h, int32_t *n_targets, int32_t *target_of);
+cs_status cs_subq_read(const cs_subq *h, int32_t target, int64_t *host_out);
+cs_status cs_subq_coefficients(const cs_subq *h, uint64_t *comp_sign, uint64_t *bin, uint64_t *join_sign);
+
 /* ------------------------------------------------------------------ AMS multi-join baseline */
 
 /* The AMS multi-join sketch of Eq. 1 (Dobra et al.; Sec. 2), the method the convolution

@@ -44,6 +44,7 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
+import types
 import os
 import subprocess
 from typing import Callable, Dict, List, Optional, Sequence, Tuple
@@ -408,6 +409,125 @@ def estimate_pairwise(a: np.ndarray, b: np.ndarray):
     median.  Returns (per-repetition exact integers, median)."""
     reps = [sum(int(x) * int(y) for x, y in zip(a[t], b[t])) for t in range(a.shape[0])]
     return reps, median_lower(reps)
+
+
+# --------------------------------------------------------------------------- sub-query sketches (Sec. 3.4)
+
+def draw_subq_coefficients(seed: int, d: int, n_comps: int, n_joins: int):
+    """Hash functions of sub-query sketches (Sec. 3.4): first, per repetition t and
+    component q, a shared sign polynomial a0..a3 and a bin polynomial b0, b1 (the draw
+    of `draw_attr_coefficients`); then, per repetition t and join e, a sign polynomial
+    a0..a3; all from one SplitMix64 stream.
+    Returns (comp_sign [d][Q][4], bins [d][Q][2], join_sign [d][E][4])."""
+    g = splitmix64(seed)
+
+    def coef():
+        while True:
+            c = next(g) >> 3
+            if c != P61:
+                return c
+
+    comp_sign = np.empty((d, n_comps, 4), dtype=np.uint64)
+    bins = np.empty((d, n_comps, 2), dtype=np.uint64)
+    join_sign = np.empty((d, n_joins, 4), dtype=np.uint64)
+    for t in range(d):
+        for q in range(n_comps):
+            for i in range(4):
+                comp_sign[t, q, i] = coef()
+            for i in range(2):
+                bins[t, q, i] = coef()
+    for t in range(d):
+        for e in range(n_joins):
+            for i in range(4):
+                join_sign[t, e, i] = coef()
+    return comp_sign, bins, join_sign
+
+
+@dataclasses.dataclass
+class SubQuery:
+    """One sub-query of a base query: a connected set of its joins."""
+    joins: List[int]                  # base join ids, ascending
+    relations: List[int]              # base relations it touches, ascending
+    graph: object                     # the sub-query as a join query (n_rel, attr_rel, edges), renumbered
+    # per relation of the sub-query (in `relations` order): its joined columns as
+    # (column index in the base relation, base component, sign functions), where a sign
+    # function is ("comp", q) for component q's shared polynomial or ("join", e)
+    columns: List[List[Tuple[int, int, Tuple[Tuple[str, int], ...]]]]
+
+
+def subquery(base_graph, joins: Sequence[int]) -> SubQuery:
+    """The sub-query of `base_graph` made of the given joins, with its hash assignment.
+
+    The sub-query is the join query on the relations its joins touch, keeping only the
+    attributes those joins name; relations, attributes and joins are renumbered in
+    ascending base order.  Hash functions (Sec. 3.4: an attribute's sketch can be reused
+    by every join involving it): an attribute's bin hash is that of its base component;
+    inside the sub-query, a component with a single join signs both of its attributes
+    with the component's shared polynomial, and a component with two or more joins signs
+    each join with that join's own polynomial (independent signs, as Alg. 2 draws one
+    sign hash per join)."""
+    info = analyze(base_graph)
+    joins = sorted(set(int(e) for e in joins))
+    if not joins or any(not (0 <= e < len(info.edges)) for e in joins):
+        raise GraphError("sub-query joins out of range")
+    attrs = sorted({u for e in joins for u in info.edges[e]})
+    rels = sorted({info.attr_rel[u] for u in attrs})
+    rel_local = {k: i for i, k in enumerate(rels)}
+    attr_local = {u: i for i, u in enumerate(attrs)}
+    graph = types.SimpleNamespace(
+        n_rel=len(rels), attr_rel=tuple(rel_local[info.attr_rel[u]] for u in attrs),
+        edges=tuple((attr_local[info.edges[e][0]], attr_local[info.edges[e][1]]) for e in joins))
+    sub_info = analyze(graph)  # raises when the joins are not connected
+    # joins of each component of the sub-query (components of its own attribute graph)
+    comp_joins: Dict[int, List[int]] = {}
+    for i, e in enumerate(joins):
+        comp_joins.setdefault(sub_info.psi[graph.edges[i][0]], []).append(e)
+    columns = []
+    for k in rels:
+        cols = []
+        for c, u in enumerate(info.omega[k]):
+            if u not in attr_local:
+                continue
+            mine = [e for e in joins if u in info.edges[e]]
+            in_comp = comp_joins[sub_info.psi[attr_local[u]]]
+            if len(in_comp) == 1:
+                signs = (("comp", info.psi[u]),)
+            else:
+                signs = tuple(("join", e) for e in mine)
+            cols.append((c, info.psi[u], signs))
+        columns.append(cols)
+    return SubQuery(joins, rels, graph, columns)
+
+
+def create_subq_sketch(base_info: QueryInfo, columns, keys, weights, m: int, comp_sign: np.ndarray,
+                       bins: np.ndarray, join_sign: np.ndarray) -> np.ndarray:
+    """Alg. 2 for one relation of a sub-query: int64 [d][m], with bucket (sum over the
+    listed columns of their component's bin hash) mod m and sign the product of every
+    listed sign function over the columns.  keys: the base relation's [n][a] keys;
+    columns: one entry of `SubQuery.columns`."""
+    keys = np.asarray(keys).astype(np.uint32, copy=False)
+    n = keys.shape[0]
+    d = bins.shape[0]
+    Q = comp_sign.shape[1]
+    out = np.zeros((d, m), dtype=np.int64)
+    if n == 0:
+        return out
+    cols = [c for c, _, _ in columns]
+    sub = np.ascontiguousarray(keys.reshape(n, -1)[:, cols])
+    comp = np.array([q for _, q, _ in columns], dtype=np.int32)
+    nedges = np.array([len(sg) for _, _, sg in columns], dtype=np.int32)
+    max_e = int(nedges.max())
+    edges = np.zeros((len(cols), max_e), dtype=np.int32)
+    for i, (_, _, sg) in enumerate(columns):
+        for j, (kind, idx) in enumerate(sg):
+            edges[i, j] = idx if kind == "comp" else Q + idx   # the table below: shared signs, then joins
+    table = np.ascontiguousarray(np.concatenate([comp_sign, join_sign], axis=1), dtype=np.uint64)
+    ba = np.ascontiguousarray(bins, dtype=np.uint64)
+    if weights is not None:
+        weights = np.ascontiguousarray(np.asarray(weights, dtype=np.int64))
+    lib().or_create_sketch(len(cols), _ptr(comp), _ptr(nedges), _ptr(edges), max_e, d, m, _ptr(table),
+                           table.shape[1], _ptr(ba), base_info.n_comp, _ptr(sub), _ptr(weights), n, _ptr(out))
+    return out
 
 
 def filter_rows(keys, weights, attrs, predicates):

@@ -41,6 +41,8 @@ EXPORTED = [
     "cs_ams_coefficients",
     "cs_attr_create", "cs_attr_destroy", "cs_attr_update", "cs_attr_reset", "cs_attr_estimate_join",
     "cs_attr_read", "cs_attr_coefficients",
+    "cs_subq_create", "cs_subq_destroy", "cs_subq_update", "cs_subq_reset", "cs_subq_estimate",
+    "cs_subq_estimate_all", "cs_subq_layout", "cs_subq_read", "cs_subq_coefficients",
     "cs_export", "cs_import", "cs_estimate_async",
 ]
 
@@ -196,6 +198,15 @@ def lib() -> ctypes.CDLL:
         L.cs_attr_estimate_join.argtypes = [vp, i32, i32, vp, ctypes.POINTER(_Estimate), ctypes.POINTER(_Reps)]
         L.cs_attr_read.argtypes = [vp, i32, vp]
         L.cs_attr_coefficients.argtypes = [vp, vp, vp]
+        L.cs_subq_create.argtypes = [ctypes.POINTER(_Graph), vp, i32, u32, u32, u64, ctypes.POINTER(vp)]
+        L.cs_subq_destroy.argtypes = [vp]
+        L.cs_subq_update.argtypes = [vp, i32, vp, vp, u64, i32, vp]
+        L.cs_subq_reset.argtypes = [vp, vp]
+        L.cs_subq_estimate.argtypes = [vp, i32, vp, ctypes.POINTER(_Estimate), ctypes.POINTER(_Reps)]
+        L.cs_subq_estimate_all.argtypes = [vp, vp, vp]
+        L.cs_subq_layout.argtypes = [vp, vp, vp]
+        L.cs_subq_read.argtypes = [vp, i32, vp]
+        L.cs_subq_coefficients.argtypes = [vp, vp, vp, vp]
         L.cs_export.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
         L.cs_import.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(vp)]
         L.cs_estimate_async.argtypes = [vp, vp, vp]
@@ -758,6 +769,80 @@ class AttrSketches:
         bins = np.empty((self.d, n_comp, 2), dtype=np.uint64)
         _check(lib().cs_attr_coefficients(self._h, sign.ctypes.data, bins.ctypes.data))
         return sign, bins
+
+
+class SubQueries:
+    """Sketches of many sub-queries of one base query (Sec. 3.4): `sub_joins` lists each
+    sub-query as a bit mask of the base graph's joins.  One pass per base relation
+    updates every distinct sketch of that relation; sub-queries that join an attribute
+    once share its sketch."""
+
+    def __init__(self, graph, sub_joins, m: int, d: int, seed: int):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("csketch needs a HIP GPU; there is no CPU fallback")
+        self.graph = graph
+        self.sub_joins = [int(x) for x in sub_joins]
+        self.m, self.d, self.seed = int(m), int(d), int(seed)
+        masks = np.array(self.sub_joins, dtype=np.uint32)
+        h = ctypes.c_void_p()
+        _check(lib().cs_subq_create(ctypes.byref(_graph_struct(graph)), masks.ctypes.data, len(self.sub_joins),
+                                    self.m, self.d, self.seed, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cs_subq_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def update(self, rel: int, keys, weights=None, stream=None, unit_weights: bool = False):
+        n = int(keys.shape[0])
+        _check(lib().cs_subq_update(self._h, int(rel), keys.data_ptr() if n else None,
+                                    None if weights is None else weights.data_ptr(), n,
+                                    UPDATE_UNIT_WEIGHTS if unit_weights else 0, _stream_ptr(stream)))
+
+    def reset(self, stream=None):
+        _check(lib().cs_subq_reset(self._h, _stream_ptr(stream)))
+
+    def estimate(self, q: int, stream=None, reps: bool = False) -> dict:
+        e = _Estimate()
+        rp, arrs = _reps_struct(self.d) if reps else (None, None)
+        _check(lib().cs_subq_estimate(self._h, int(q), _stream_ptr(stream), ctypes.byref(e),
+                                      ctypes.byref(rp) if rp is not None else None))
+        return _estimate_dict(e, arrs)
+
+    def estimate_all(self, stream=None) -> list:
+        n = len(self.sub_joins)
+        outs = (_Estimate * n)()
+        _check(lib().cs_subq_estimate_all(self._h, _stream_ptr(stream), outs))
+        return [_estimate_dict(outs[i], None) for i in range(n)]
+
+    def layout(self):
+        """(number of targets, target_of [n_sub][n_rel], -1 where a relation is absent)."""
+        nt = ctypes.c_int32()
+        tof = np.empty((len(self.sub_joins), self.graph.n_rel), dtype=np.int32)
+        _check(lib().cs_subq_layout(self._h, ctypes.byref(nt), tof.ctypes.data))
+        return nt.value, tof
+
+    def read_target(self, target: int) -> np.ndarray:
+        out = np.empty((self.d, self.m), dtype=np.int64)
+        _check(lib().cs_subq_read(self._h, int(target), out.ctypes.data))
+        return out
+
+    def coefficients(self):
+        n_comp = _n_components(self.graph)
+        n_edge = len(self.graph.edges)
+        cs = np.empty((self.d, n_comp, 4), dtype=np.uint64)
+        bn = np.empty((self.d, n_comp, 2), dtype=np.uint64)
+        es = np.empty((self.d, max(1, n_edge), 4), dtype=np.uint64)
+        _check(lib().cs_subq_coefficients(self._h, cs.ctypes.data, bn.ctypes.data, es.ctypes.data))
+        return cs, bn, es[:, :n_edge]
 
 
 def _n_components(graph) -> int:

@@ -20,6 +20,7 @@ SOURCES = [
     "csk_tune.hip",
     "csk_ams.hip",
     "csk_attr.hip",
+    "csk_subq.hip",
     "csk_checkpoint.hip",
     "csk_batch.hip",
     "csk_serve.hip",

@@ -1252,7 +1252,7 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
             for (int k = 0; k < r; ++k)
                 for (int t = 0; t < d; ++t) {
                     SkDesc S;
-                    S.p = h.counters + ((size_t)k * d + t) * m;
+                    S.p = rel_counters(h, k) + (size_t)t * m;
                     S.log2m = L;
                     S.m = h.m;
                     S.nb = nb;
@@ -1283,8 +1283,8 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
         if (Q.plan == CS_PLAN_GENERAL) general_q.push_back(q);
         for (int t = 0; t < d; ++t) {
             RepDesc D{};
-            D.c0 = h.counters + (size_t)t * m;
-            D.c1 = h.counters + ((size_t)d + t) * m;
+            D.c0 = rel_counters(h, 0) + (size_t)t * m;
+            D.c1 = rel_counters(h, 1) + (size_t)t * m;
             D.q = q;
             D.t = t;
             D.log2m = L;
@@ -1619,7 +1619,7 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
             for (int q : needq) {
                 const int base = (int)ptrs.size();
                 for (int k = 0; k < qd[q].r; ++k)
-                    for (int t = 0; t < qd[q].d; ++t) ptrs.push_back(hs[q]->counters + ((size_t)k * qd[q].d + t) * hs[q]->m);
+                    for (int t = 0; t < qd[q].d; ++t) ptrs.push_back(rel_counters(*hs[q], k) + (size_t)t * hs[q]->m);
                 for (int t = 0; t < qd[q].d; ++t) {
                     rd[qd[q].rep_base + t].mod_vec_base = base;
                     idx.push_back(qd[q].rep_base + t);
@@ -1684,7 +1684,7 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
                 switch (op.code) {
                     case OP_LOAD:
                         hipLaunchKernelGGL(k_mod_load, dim3(gx, K * d), dim3(256), 0, s, dst,
-                                           h.counters + (size_t)op.src * d * m, m, d, primes);
+                                           rel_counters(h, op.src), m, d, primes);
                         break;
                     case OP_ONES:
                         hipLaunchKernelGGL(k_mod_ones, dim3(gx, K * d), dim3(256), 0, s, dst, m, d, primes);

@@ -57,6 +57,9 @@ struct Handle {
     std::vector<uint64_t> sign_coef;   // [d][E][4]
     std::vector<uint64_t> bin_coef;    // [d][Q][2]
     int64_t *counters = nullptr;       // [r][d][m]
+    // when set, relation k's [d][m] counters live at rel_ptr[k] instead (handles that
+    // only estimate, over sketches owned elsewhere)
+    std::vector<int64_t *> rel_ptr;
     uint64_t *coef_dev = nullptr;      // per relation: [d][coef_per_rep], concatenated
     std::vector<size_t> coef_off;      // offset of relation k's table in coef_dev
     EstimateWork work;
@@ -67,6 +70,12 @@ struct Handle {
     // count, [1] the per-round count of the filtered 16-bit path (zero between updates)
     unsigned long long *kept_dev = nullptr;
 };
+
+// Relation k's counters [d][m].
+inline int64_t *rel_counters(const Handle &h, int k)
+{
+    return h.rel_ptr.empty() ? h.counters + (size_t)k * h.d * h.m : h.rel_ptr[k];
+}
 
 cs_status estimate_run(Handle &h, hipStream_t s, cs_estimate_t *out, const cs_reps_t *reps);
 cs_status estimate_run_async(Handle &h, hipStream_t s, cs_estimate_t *out);

@@ -161,6 +161,22 @@ __device__ __forceinline__ uint32_t hash_neg(const uint64_t *__restrict__ cf, co
     return neg;
 }
 
+// (tuple chunk, segment) of a two-dimensional launch's workgroup.  Workgroups go to the 8 XCDs
+// round-robin by linear id; the ids one XCD receives are given a contiguous run of the
+// chunk-major order, so the segments of one tuple chunk run on one XCD (two at a run's
+// ends) and that XCD's L2 fetches the chunk's keys once.
+struct SegTile {
+    uint32_t chunk, seg;
+};
+__device__ __forceinline__ SegTile seg_tile()
+{
+    const uint32_t G = gridDim.x * gridDim.y;
+    const uint32_t L = blockIdx.x + blockIdx.y * gridDim.x;
+    const uint32_t xcd = L & 7u, w = L >> 3;
+    const uint32_t P = xcd * (G >> 3) + min(xcd, G & 7u) + w;  // a bijection of [0, G)
+    return {P / gridDim.y, P % gridDim.y};
+}
+
 __host__ __device__ inline BinMod make_binmod(uint32_t m)
 {
     BinMod b;

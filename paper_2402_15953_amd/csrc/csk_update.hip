@@ -175,21 +175,6 @@ __global__ __launch_bounds__(kBlock) void k_update_waveagg(const uint32_t *__res
 // chunk's partial sums; k_seg_reduce adds the partials of all chunks into the sketch.
 // A segment holds whole repetitions when m <= R, else a bucket range of one
 // repetition (its tuples' signs are then only needed for in-range buckets).
-// (tuple chunk, segment) of a segmented launch's workgroup.  Workgroups go to the 8 XCDs
-// round-robin by linear id; the ids one XCD receives are given a contiguous run of the
-// chunk-major order, so the segments of one tuple chunk run on one XCD (two at a run's
-// ends) and that XCD's L2 fetches the chunk's keys once.
-struct SegTile {
-    uint32_t chunk, seg;
-};
-__device__ __forceinline__ SegTile seg_tile()
-{
-    const uint32_t G = gridDim.x * gridDim.y;
-    const uint32_t L = blockIdx.x + blockIdx.y * gridDim.x;
-    const uint32_t xcd = L & 7u, w = L >> 3;
-    const uint32_t P = xcd * (G >> 3) + min(xcd, G & 7u) + w;  // a bijection of [0, G)
-    return {P / gridDim.y, P % gridDim.y};
-}
 
 template <int NC, typename CT, bool E1>
 __global__ __launch_bounds__(kSegBlock) void k_update_seg(const uint32_t *__restrict__ keys,

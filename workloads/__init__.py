@@ -152,6 +152,39 @@ def multiway_star(r: int) -> JoinGraph:
     return JoinGraph(r, attr_rel, edges, f"mstar{r}")
 
 
+def connected_subqueries(graph: JoinGraph, min_joins: int = 1) -> List[int]:
+    """Every connected set of the query's joins (as a bit mask of join ids), with at
+    least `min_joins` joins: the sub-queries a join-order enumeration asks about.  The
+    relations and joins form a tree, so a join set is connected exactly when it touches
+    one relation more than it has joins."""
+    out = []
+    E = len(graph.edges)
+    for mask in range(1, 1 << E):
+        js = [e for e in range(E) if (mask >> e) & 1]
+        if len(js) < min_joins:
+            continue
+        rels = {graph.attr_rel[u] for e in js for u in graph.edges[e]}
+        if len(rels) == len(js) + 1:
+            out.append(mask)
+    return out
+
+
+def subquery_graph(graph: JoinGraph, mask: int):
+    """The sub-query made of the joins in `mask` as a join query of its own: its
+    relations, its attributes (those its joins name) and its joins, renumbered in
+    ascending base order.  Returns (JoinGraph, base relations, per relation the base
+    key-column indices it keeps)."""
+    js = [e for e in range(len(graph.edges)) if (mask >> e) & 1]
+    attrs = sorted({u for e in js for u in graph.edges[e]})
+    rels = sorted({graph.attr_rel[u] for u in attrs})
+    rl = {k: i for i, k in enumerate(rels)}
+    al = {u: i for i, u in enumerate(attrs)}
+    g = JoinGraph(len(rels), tuple(rl[graph.attr_rel[u]] for u in attrs),
+                  tuple((al[graph.edges[e][0]], al[graph.edges[e][1]]) for e in js), f"{graph.name}/sub{mask}")
+    cols = [[c for c, u in enumerate(graph.columns(k)) if u in al] for k in rels]
+    return g, rels, cols
+
+
 # --------------------------------------------------------------------------- relations
 
 
