@@ -832,8 +832,33 @@ def bench_batched(n_queries, dev, stream):
     est_batch = b.estimate(sks, stream=stream)
     t_est_batch = time.perf_counter() - t0
     stats = b.stats()
-    b.close()
     identical = est_batch == est_plain
+    # the autotuner: task kind and chunk per item class, split per transform length;
+    # then the same batch planned and estimated with the tuned table
+    csk.tune_clear()
+    t0 = time.perf_counter()
+    trep = b.tune(items, stream=stream)
+    splits = {}
+    for L in sorted({(sp.m - 1).bit_length() for sp in specs}):
+        if L > 12:
+            splits[L] = csk.tune_transform(L, n_vec=64, stream=stream)["best"]["split"]
+    t_tune = time.perf_counter() - t0
+    reset_all()
+    b.capture(items, stream=stream)
+    b.replay(stream=stream)
+    torch.cuda.synchronize()
+    b.estimate(sks, stream=stream)
+    reset_all()
+    t0 = time.perf_counter()
+    b.replay(stream=stream)
+    torch.cuda.synchronize()
+    t_up_tuned = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    est_tuned = b.estimate(sks, stream=stream)
+    t_est_tuned = time.perf_counter() - t0
+    stats_tuned = b.stats()
+    csk.tune_clear()
+    b.close()
     for sk_ in sks:
         sk_.close()
     return {"workload": f"{n_queries} chain/star queries, 2-6 relations, n log-uniform [1e3,1e6], "
@@ -842,7 +867,13 @@ def bench_batched(n_queries, dev, stream):
             "plain_update_tuples_per_s": tuples / t_up_plain, "batched_update_tuples_per_s": tuples / t_up_batch,
             "plain_estimates_per_s": n_queries / t_est_plain, "batched_estimates_per_s": n_queries / t_est_batch,
             "update_speedup": t_up_plain / t_up_batch, "estimate_speedup": t_est_plain / t_est_batch,
-            "batched_plan_s": t_plan, "tasks": stats, "identical_estimates": identical}
+            "batched_plan_s": t_plan, "tasks": stats, "identical_estimates": identical,
+            "tuned": {"update_tuples_per_s": tuples / t_up_tuned, "estimates_per_s": n_queries / t_est_tuned,
+                      "update_over_rule": t_up_batch / t_up_tuned, "estimate_over_rule": t_est_batch / t_est_tuned,
+                      "classes": trep["classes"], "rejected": trep["rejected"],
+                      "class_sum_rule_ms": trep["rule_ms"], "class_sum_tuned_ms": trep["tuned_ms"],
+                      "splits": splits, "tuning_s": t_tune, "tasks": stats_tuned,
+                      "identical_estimates": est_tuned == est_plain}}
 
 
 def bench_serving(n_queries, dev, seconds, rates):

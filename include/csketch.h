@@ -279,6 +279,12 @@ cs_status cs_update_filtered(cs_sketch *h, int32_t rel, const uint32_t *keys, co
 /* ------------------------------------------------------------------ autotuner */
 
 #define CS_TUNE_MAX_CANDIDATES 16
+/* Strategy codes of tuning-table entries that are not cs_update strategies (they appear
+ * in files written by cs_tune_save): a batched task class's kind, and a transform
+ * length's split. */
+#define CS_TUNE_BATCH_ATOMIC 16
+#define CS_TUNE_BATCH_SEGMENT 17
+#define CS_TUNE_TRANSFORM_SPLIT 32
 
 typedef struct cs_tune_candidate {
     int32_t strategy;          /* cs_update_strategy */
@@ -377,6 +383,36 @@ cs_status cs_batch_estimate(cs_batch *b, cs_sketch *const *sketches, int32_t n, 
 
 /* Task counts of the last planned batch update. */
 cs_status cs_batch_stats(const cs_batch *b, uint64_t *tasks_atomic, uint64_t *tasks_segment);
+
+/* Autotuner of the batched update's tasks: the items are grouped into classes (m, d,
+ * key columns, one-join columns, unit weights, floor(log2 n)), and for each class the
+ * class's items alone run as one persistent launch with every task choice -- global
+ * atomics, or LDS segments over tuple chunks of 2^14, 2^16, 2^18 or 2^20 -- into private
+ * counters (the handles' sketches are left untouched); a choice whose counters differ
+ * from the global-atomic run's is never taken, the fastest (median of three) is stored
+ * in the tuning table, and cs_batch_update / cs_batch_capture plan that class with it
+ * from then on (cs_tune_save / cs_tune_load persist it).  The fixed rule the planner
+ * otherwise uses is timed beside them.  Synchronous; allocates two buffers of the largest
+ * class's counters.  Errors: CS_EINVAL, CS_ENOMEM, CS_EDEVICE. */
+typedef struct cs_tune_batch_report {
+    int32_t classes;   /* classes tuned */
+    int32_t rejected;  /* candidate runs whose counters differed from the reference */
+    float rule_ms;     /* sum over classes of the fixed rule's time */
+    float tuned_ms;    /* sum over classes of the chosen candidate's time */
+} cs_tune_batch_report;
+cs_status cs_tune_batch_update(cs_batch *b, const cs_update_item *items, int32_t n_items, void *stream,
+                               cs_tune_batch_report *out);
+
+/* Autotuner of the two-pass transforms (lengths 2^13..2^21) the estimate runs: for each
+ * row length 2^S (S = 10..12 with S < log2m <= 2S) it times the fp64 FFT and one
+ * prime's number-theoretic transform of n_vec synthetic vectors of length 2^log2m,
+ * checks that the number-theoretic spectrum equals the default split's at every
+ * frequency (exact arithmetic; the split only permutes the output), and stores the
+ * fastest for this device and length: later estimates of that length use it (an
+ * estimate in flight keeps the split it started with).  out->cand[i].grid_blocks holds
+ * S, .ms the median of three runs.  Synchronous.  Errors: CS_EINVAL (log2m outside
+ * 13..21, n_vec outside 1..4096), CS_ENOMEM, CS_EDEVICE. */
+cs_status cs_tune_transform(int32_t log2m, int32_t n_vec, void *stream, cs_tune_report *out);
 
 /* ------------------------------------------------------------------ serving */
 

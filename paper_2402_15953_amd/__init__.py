@@ -32,6 +32,7 @@ EXPORTED = [
     "cs_sketch_device_ptr", "cs_read_coeffs", "cs_read_components",
     "cs_timer_create", "cs_timer_record", "cs_timer_elapsed", "cs_timer_destroy",
     "cs_tune_update", "cs_tune_clear", "cs_tune_save", "cs_tune_load", "cs_tune_count",
+    "cs_tune_batch_update", "cs_tune_transform",
     "cs_batch_create", "cs_batch_destroy", "cs_batch_update", "cs_batch_capture", "cs_batch_replay",
     "cs_batch_estimate", "cs_batch_stats",
     "cs_server_create", "cs_server_destroy", "cs_server_add_query", "cs_server_remove_query",
@@ -91,6 +92,11 @@ TUNE_MAX_CANDIDATES = 16
 
 class _TuneReport(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("best", ctypes.c_int32), ("cand", _TuneCand * TUNE_MAX_CANDIDATES)]
+
+
+class _TuneBatchReport(ctypes.Structure):
+    _fields_ = [("classes", ctypes.c_int32), ("rejected", ctypes.c_int32), ("rule_ms", ctypes.c_float),
+                ("tuned_ms", ctypes.c_float)]
 
 
 class _Item(ctypes.Structure):
@@ -166,6 +172,8 @@ def lib() -> ctypes.CDLL:
         L.cs_tune_save.argtypes = [ctypes.c_char_p]
         L.cs_tune_load.argtypes = [ctypes.c_char_p]
         L.cs_tune_count.argtypes = [ctypes.POINTER(ctypes.c_int32)]
+        L.cs_tune_batch_update.argtypes = [vp, vp, i32, vp, ctypes.POINTER(_TuneBatchReport)]
+        L.cs_tune_transform.argtypes = [i32, i32, vp, ctypes.POINTER(_TuneReport)]
         L.cs_batch_create.argtypes = [ctypes.POINTER(vp)]
         L.cs_batch_destroy.argtypes = [vp]
         L.cs_batch_update.argtypes = [vp, ctypes.POINTER(_Item), i32, vp]
@@ -312,6 +320,18 @@ def tune_update(sketch: "Sketch", rel: int, keys, weights=None, unit_weights: bo
                                 _stream_ptr(stream), UPDATE_UNIT_WEIGHTS if unit_weights else 0, ctypes.byref(rep)))
     cands = [dict(strategy=STRATEGY_NAMES.get(c.strategy, c.strategy), grid=c.grid_blocks, flags=c.flags,
                   valid=int(c.valid), ms=float(c.ms)) for c in rep.cand[:rep.n]]
+    return {"candidates": cands, "best": cands[rep.best], "best_index": rep.best}
+
+
+TUNE_BATCH_ATOMIC, TUNE_BATCH_SEGMENT, TUNE_TRANSFORM_SPLIT = 16, 17, 32
+
+
+def tune_transform(log2m: int, n_vec: int = 64, stream=None) -> dict:
+    """Autotune the row length of the two-pass transforms of length 2^log2m
+    (cs_tune_transform); returns each split's median time and the chosen one."""
+    rep = _TuneReport()
+    _check(lib().cs_tune_transform(int(log2m), int(n_vec), _stream_ptr(stream), ctypes.byref(rep)))
+    cands = [dict(split=c.grid_blocks, valid=int(c.valid), ms=float(c.ms)) for c in rep.cand[:rep.n]]
     return {"candidates": cands, "best": cands[rep.best], "best_index": rep.best}
 
 
@@ -546,6 +566,13 @@ class Batch:
 
     def replay(self, stream=None):
         _check(lib().cs_batch_replay(self._b, _stream_ptr(stream)))
+
+    def tune(self, items, stream=None) -> dict:
+        """Autotune the task choice of every item class in this batch (cs_tune_batch_update)."""
+        arr, n = self._items(items)
+        rep = _TuneBatchReport()
+        _check(lib().cs_tune_batch_update(self._b, arr, n, _stream_ptr(stream), ctypes.byref(rep)))
+        return {"classes": rep.classes, "rejected": rep.rejected, "rule_ms": rep.rule_ms, "tuned_ms": rep.tuned_ms}
 
     def stats(self):
         a, b = ctypes.c_uint64(), ctypes.c_uint64()

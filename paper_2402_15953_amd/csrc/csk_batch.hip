@@ -17,6 +17,8 @@
 #include <type_traits>
 
 #include <algorithm>
+#include <map>
+#include <tuple>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -386,6 +388,18 @@ __global__ __launch_bounds__(kBBlock) void k_batch_update(const BItem *__restric
     }
 }
 
+__global__ void k_batch_zero(uint64_t *p, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+__global__ void k_batch_diff(const uint64_t *__restrict__ x, const uint64_t *__restrict__ y, size_t n,
+                             unsigned int *flag)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        if (x[i] != y[i]) atomicOr(flag, 1u);
+}
+
 }  // namespace
 
 // Host side of a batch: work-list planning, device tables, optional graph.
@@ -405,83 +419,109 @@ struct BatchState {
 
 namespace {
 
-cs_status plan_batch(BatchState &B, const cs_update_item *items, int32_t n_items, hipStream_t s)
+// One item's table entry and what its task planning needs.
+struct ItemInfo {
+    BItem I;
+    int steps;         // Horner steps per tuple and repetition
+    int e1, unit;
+};
+
+cs_status make_item(const cs_update_item &it, BItem &I, ItemInfo &info)
 {
-    std::vector<BItem> bi;
-    std::vector<BTask> bt;
-    std::vector<double> cost;
-    B.tasks_atomic = B.tasks_segment = 0;
-    for (int32_t i = 0; i < n_items; ++i) {
-        const cs_update_item &it = items[i];
-        if (!it.sketch) return fail(CS_EINVAL, "batch item without handle");
-        const Handle &h = it.sketch->h;
-        if (it.rel < 0 || it.rel >= h.g.n_rel) return fail(CS_EINVAL, "batch item relation out of range");
-        if (it.n == 0) continue;
-        if (!it.keys) return fail(CS_EINVAL, "batch item without keys");
-        if (B.device < 0) B.device = h.device;
-        if (h.device != B.device) return fail(CS_EINVAL, "batch items on different devices");
-        const RelPlan &rp = h.g.rel[it.rel];
-        {
-            cs_status chk = check_device_array(it.keys, it.n * rp.n_cols * sizeof(uint32_t), h.device, "batch keys");
-            if (chk == CS_OK && it.weights)
-                chk = check_device_array(it.weights, it.n * sizeof(int64_t), h.device, "batch weights");
-            if (chk != CS_OK) return chk;
-        }
-        BItem I{};
-        I.keys = it.keys;
-        I.weights = it.weights;
-        I.coef = h.coef_dev + h.coef_off[it.rel];
-        I.sketch = reinterpret_cast<uint64_t *>(h.counters + (size_t)it.rel * h.d * h.m);
-        I.n = it.n;
-        I.cpr = rp.coef_per_rep;
-        I.n_cols = rp.n_cols;
-        I.m = h.m;
-        I.log2m = h.log2m;
-        I.d = (int32_t)h.d;
-        const bool unit = it.weights == nullptr || (it.flags & CS_UPDATE_UNIT_WEIGHTS);
-        I.narrow = unit && it.n < (1ull << 31) && (h.m % 2) == 0;  // 16-bit pairs need even segments
-        I.vec2 = rp.n_cols == 2 && ((uintptr_t)it.keys % 8) == 0;
-        for (int c = 0; c < kMaxCols; ++c) I.plan.n_edges[c] = c < rp.n_cols ? rp.n_edges[c] : 0;
-        I.plan.bm = make_binmod(h.m);
-        I.e1 = (h.m & (h.m - 1)) == 0;
-        for (int c = 0; c < rp.n_cols; ++c) I.e1 = I.e1 && rp.n_edges[c] == 1;
-        // LDS segment: 2^16 16-bit counters (Deltas +-1) or 2^14 int64 counters
-        uint32_t R = I.narrow ? (1u << 16) : (1u << 14);
-        if (h.m <= R) R = (R / h.m) * h.m;
-        I.R = R;
-        const int idx = (int)bi.size();
-        bi.push_back(I);
-        int steps = 0;
-        for (int c = 0; c < rp.n_cols; ++c) steps += 1 + 3 * rp.n_edges[c];
-        const uint64_t cells = (uint64_t)h.d * h.m;
-        const uint64_t tuple_reps = it.n * h.d;
-        // atomics only where aggregation cannot pay: a few microseconds of them at most
-        // (the segment task's fixed cost is zeroing and flushing its LDS counters)
-        if (tuple_reps < 65536 || tuple_reps < cells / 4) {
-            // few tuples per counter: global atomics
-            const uint64_t chunk = 1u << 16;
-            for (uint64_t b = 0; b < it.n; b += chunk) {
-                BTask T{idx, 0, 0, 0, b, std::min<uint64_t>(it.n, b + chunk)};
-                bt.push_back(T);
-                cost.push_back((double)(T.end - T.begin) * h.d * (steps + 40));
-                ++B.tasks_atomic;
-            }
-        } else {
-            const uint32_t segs = (uint32_t)((cells + R - 1) / R);
-            const uint64_t C = (it.n + (1u << 18) - 1) >> 18;
-            const uint64_t chunk = (it.n + C - 1) / C;
-            const int reps_per_seg = R >= h.m ? (int)(R / h.m) : 1;
-            const int ranges = R >= h.m ? 1 : (int)(h.m / R);
-            for (uint32_t sg = 0; sg < segs; ++sg)
-                for (uint64_t b = 0; b < it.n; b += chunk) {
-                    BTask T{idx, 1, sg, 0, b, std::min<uint64_t>(it.n, b + chunk)};
-                    bt.push_back(T);
-                    cost.push_back((double)(T.end - T.begin) * reps_per_seg * (steps + ranges) + R);
-                    ++B.tasks_segment;
-                }
-        }
+    const Handle &h = it.sketch->h;
+    const RelPlan &rp = h.g.rel[it.rel];
+    cs_status chk = check_device_array(it.keys, it.n * rp.n_cols * sizeof(uint32_t), h.device, "batch keys");
+    if (chk == CS_OK && it.weights) chk = check_device_array(it.weights, it.n * sizeof(int64_t), h.device, "batch weights");
+    if (chk != CS_OK) return chk;
+    I = BItem{};
+    I.keys = it.keys;
+    I.weights = it.weights;
+    I.coef = h.coef_dev + h.coef_off[it.rel];
+    I.sketch = reinterpret_cast<uint64_t *>(h.counters + (size_t)it.rel * h.d * h.m);
+    I.n = it.n;
+    I.cpr = rp.coef_per_rep;
+    I.n_cols = rp.n_cols;
+    I.m = h.m;
+    I.log2m = h.log2m;
+    I.d = (int32_t)h.d;
+    const bool unit = it.weights == nullptr || (it.flags & CS_UPDATE_UNIT_WEIGHTS);
+    I.narrow = unit && it.n < (1ull << 31) && (h.m % 2) == 0;  // 16-bit pairs need even segments
+    I.vec2 = rp.n_cols == 2 && ((uintptr_t)it.keys % 8) == 0;
+    for (int c = 0; c < kMaxCols; ++c) I.plan.n_edges[c] = c < rp.n_cols ? rp.n_edges[c] : 0;
+    I.plan.bm = make_binmod(h.m);
+    I.e1 = (h.m & (h.m - 1)) == 0;
+    for (int c = 0; c < rp.n_cols; ++c) I.e1 = I.e1 && rp.n_edges[c] == 1;
+    // LDS segment: 2^16 16-bit counters (Deltas +-1) or 2^14 int64 counters
+    uint32_t R = I.narrow ? (1u << 16) : (1u << 14);
+    if (h.m <= R) R = (R / h.m) * h.m;
+    I.R = R;
+    info.I = I;
+    info.steps = 0;
+    for (int c = 0; c < rp.n_cols; ++c) info.steps += 1 + 3 * rp.n_edges[c];
+    info.e1 = 1;
+    for (int c = 0; c < rp.n_cols; ++c) info.e1 = info.e1 && rp.n_edges[c] == 1;
+    info.unit = unit ? 1 : 0;
+    return CS_OK;
+}
+
+// The fixed rule: global atomics where aggregation cannot pay (a few microseconds of
+// them at most; a segment task's fixed cost is zeroing and flushing its LDS counters),
+// else LDS segments over tuple chunks of at most 2^18 (chunk_log2 -1: balanced chunks).
+void rule_choice(const BItem &I, int *kind, int *chunk_log2)
+{
+    const uint64_t cells = (uint64_t)I.d * I.m;
+    const uint64_t tuple_reps = I.n * I.d;
+    if (tuple_reps < 65536 || tuple_reps < cells / 4) {
+        *kind = 0;
+        *chunk_log2 = 16;
+    } else {
+        *kind = 1;
+        *chunk_log2 = -1;
     }
-    // largest first
+}
+
+// Tasks of item idx with the given kind and tuple chunk (2^chunk_log2, or for -1 the
+// balanced chunks of at most 2^18).
+void add_tasks(int idx, const ItemInfo &info, int kind, int chunk_log2, std::vector<BTask> &bt,
+               std::vector<double> &cost, uint64_t &n_atomic, uint64_t &n_segment)
+{
+    const BItem &I = info.I;
+    const uint64_t n = I.n;
+    const uint64_t cells = (uint64_t)I.d * I.m;
+    uint64_t chunk;
+    if (chunk_log2 < 0) {
+        const uint64_t C = (n + (1u << 18) - 1) >> 18;
+        chunk = (n + C - 1) / C;
+    } else {
+        const uint64_t C = (n + (1ull << chunk_log2) - 1) >> chunk_log2;
+        chunk = (n + C - 1) / C;
+    }
+    if (kind == 0) {
+        for (uint64_t b = 0; b < n; b += chunk) {
+            BTask T{idx, 0, 0, 0, b, std::min<uint64_t>(n, b + chunk)};
+            bt.push_back(T);
+            cost.push_back((double)(T.end - T.begin) * I.d * (info.steps + 40));
+            ++n_atomic;
+        }
+    } else {
+        const uint32_t R = I.R;
+        const uint32_t segs = (uint32_t)((cells + R - 1) / R);
+        const int reps_per_seg = R >= I.m ? (int)(R / I.m) : 1;
+        const int ranges = R >= I.m ? 1 : (int)(I.m / R);
+        for (uint32_t sg = 0; sg < segs; ++sg)
+            for (uint64_t b = 0; b < n; b += chunk) {
+                BTask T{idx, 1, sg, 0, b, std::min<uint64_t>(n, b + chunk)};
+                bt.push_back(T);
+                cost.push_back((double)(T.end - T.begin) * reps_per_seg * (info.steps + ranges) + R);
+                ++n_segment;
+            }
+    }
+}
+
+// Sorts the tasks largest first and uploads items and tasks.
+cs_status upload_tables(BatchState &B, const std::vector<BItem> &bi, const std::vector<BTask> &bt,
+                        const std::vector<double> &cost, hipStream_t s)
+{
     std::vector<int> order(bt.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
@@ -511,6 +551,35 @@ cs_status plan_batch(BatchState &B, const cs_update_item *items, int32_t n_items
     B.o_tasks = o_tasks;
     B.o_counter = o_counter;
     return CS_OK;
+}
+
+cs_status plan_batch(BatchState &B, const cs_update_item *items, int32_t n_items, hipStream_t s)
+{
+    std::vector<BItem> bi;
+    std::vector<BTask> bt;
+    std::vector<double> cost;
+    B.tasks_atomic = B.tasks_segment = 0;
+    for (int32_t i = 0; i < n_items; ++i) {
+        const cs_update_item &it = items[i];
+        if (!it.sketch) return fail(CS_EINVAL, "batch item without handle");
+        const Handle &h = it.sketch->h;
+        if (it.rel < 0 || it.rel >= h.g.n_rel) return fail(CS_EINVAL, "batch item relation out of range");
+        if (it.n == 0) continue;
+        if (!it.keys) return fail(CS_EINVAL, "batch item without keys");
+        if (B.device < 0) B.device = h.device;
+        if (h.device != B.device) return fail(CS_EINVAL, "batch items on different devices");
+        BItem I;
+        ItemInfo info;
+        cs_status st = make_item(it, I, info);
+        if (st != CS_OK) return st;
+        int kind, chunk_log2;
+        if (!tune_lookup_batch(h.device, h.m, (int)h.d, I.n_cols, info.e1, info.unit, it.n, &kind, &chunk_log2))
+            rule_choice(I, &kind, &chunk_log2);
+        const int idx = (int)bi.size();
+        bi.push_back(I);
+        add_tasks(idx, info, kind, chunk_log2, bt, cost, B.tasks_atomic, B.tasks_segment);
+    }
+    return upload_tables(B, bi, bt, cost, s);
 }
 
 cs_status launch_batch(BatchState &B, hipStream_t s)
@@ -632,6 +701,144 @@ cs_status cs_batch_stats(const cs_batch *b, uint64_t *tasks_atomic, uint64_t *ta
     if (tasks_atomic) *tasks_atomic = b->b.tasks_atomic;
     if (tasks_segment) *tasks_segment = b->b.tasks_segment;
     return CS_OK;
+}
+
+cs_status cs_tune_batch_update(cs_batch *b, const cs_update_item *items, int32_t n_items, void *stream,
+                               cs_tune_batch_report *out)
+{
+    if (!b || !out || (n_items > 0 && !items)) return fail(CS_EINVAL, "null argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::memset(out, 0, sizeof(*out));
+    // classes: (m, d, key columns, one-join columns, unit weights, floor(log2 n))
+    using Key = std::tuple<uint32_t, int, int, int, int, int>;
+    std::map<Key, std::vector<int>> classes;
+    std::vector<ItemInfo> info(n_items);
+    int device = -1;
+    for (int32_t i = 0; i < n_items; ++i) {
+        const cs_update_item &it = items[i];
+        if (!it.sketch) return fail(CS_EINVAL, "batch item without handle");
+        const Handle &h = it.sketch->h;
+        if (it.rel < 0 || it.rel >= h.g.n_rel) return fail(CS_EINVAL, "batch item relation out of range");
+        if (it.n == 0) continue;
+        if (!it.keys) return fail(CS_EINVAL, "batch item without keys");
+        if (device < 0) device = h.device;
+        if (h.device != device) return fail(CS_EINVAL, "batch items on different devices");
+        BItem I;
+        cs_status st = make_item(it, I, info[i]);
+        if (st != CS_OK) return st;
+        int lg = 0;
+        while ((it.n >> (lg + 1)) != 0) ++lg;
+        classes[Key{h.m, (int)h.d, I.n_cols, info[i].e1, info[i].unit, lg}].push_back(i);
+    }
+    if (classes.empty()) return CS_OK;
+    size_t max_cells = 0;
+    for (auto &kv : classes) {
+        size_t c = 0;
+        for (int i : kv.second) c += (size_t)info[i].I.d * info[i].I.m;
+        max_cells = std::max(max_cells, c);
+    }
+    uint64_t *ref = nullptr, *tmp = nullptr;
+    unsigned int *flag = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    BatchState T;
+    T.device = device;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(s);
+        if (ref) (void)hipFree(ref);
+        if (tmp) (void)hipFree(tmp);
+        if (flag) (void)hipFree(flag);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (T.tables) (void)hipFree(T.tables);
+    };
+    if (hipMalloc(&ref, max_cells * 8) != hipSuccess || hipMalloc(&tmp, max_cells * 8) != hipSuccess ||
+        hipMalloc(&flag, sizeof(unsigned int)) != hipSuccess) {
+        cleanup();
+        return fail(CS_ENOMEM, "batch tuning buffers");
+    }
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return fail(CS_EDEVICE, "batch tuning events");
+    }
+    // candidates: (kind, log2 tuples per task); index 0, global atomics, is the reference;
+    // index 1 is the fixed rule (measured for the report, never stored)
+    const int cands[][2] = {{0, 16}, {-1, -1}, {1, 14}, {1, 16}, {1, 18}, {1, 20}};
+    const int n_cand = (int)(sizeof(cands) / sizeof(cands[0]));
+    cs_status st = CS_OK;
+    for (auto &kv : classes) {
+        const std::vector<int> &members = kv.second;
+        size_t cells = 0;
+        std::vector<size_t> off;
+        for (int i : members) {
+            off.push_back(cells);
+            cells += (size_t)info[i].I.d * info[i].I.m;
+        }
+        const unsigned zb = (unsigned)std::min<size_t>((cells + 255) / 256, 4096);
+        float best_ms = -1.0f, rule_ms = -1.0f;
+        int best_kind = 0, best_chunk = 16;
+        for (int ci = 0; ci < n_cand && st == CS_OK; ++ci) {
+            uint64_t *dst = ci == 0 ? ref : tmp;
+            std::vector<BItem> bi;
+            std::vector<BTask> bt;
+            std::vector<double> cost;
+            uint64_t na = 0, ns = 0;
+            for (size_t j = 0; j < members.size(); ++j) {
+                ItemInfo ii = info[members[j]];
+                ii.I.sketch = dst + off[j];
+                int kind = cands[ci][0], chunk = cands[ci][1];
+                if (kind < 0) rule_choice(ii.I, &kind, &chunk);
+                bi.push_back(ii.I);
+                add_tasks((int)j, ii, kind, chunk, bt, cost, na, ns);
+            }
+            if ((st = upload_tables(T, bi, bt, cost, s)) != CS_OK) break;
+            hipLaunchKernelGGL(k_batch_zero, dim3(zb), dim3(256), 0, s, dst, cells);
+            if ((st = launch_batch(T, s)) != CS_OK) break;
+            if (ci > 0) {
+                unsigned int hflag = 0;
+                hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, flag);
+                hipLaunchKernelGGL(k_batch_diff, dim3(zb), dim3(256), 0, s, tmp, ref, cells, flag);
+                if (hipMemcpyAsync(&hflag, flag, sizeof(unsigned int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    hipStreamSynchronize(s) != hipSuccess) {
+                    st = fail(CS_EDEVICE, "batch tuning: compare");
+                    break;
+                }
+                if (hflag) {  // counters differ from the reference: never chosen
+                    out->rejected++;
+                    continue;
+                }
+            }
+            float t[3];
+            bool ok = true;
+            for (int r = 0; r < 3 && ok; ++r)
+                ok = hipEventRecord(e0, s) == hipSuccess && launch_batch(T, s) == CS_OK &&
+                     hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                     hipEventElapsedTime(&t[r], e0, e1) == hipSuccess;
+            if (!ok) {
+                st = fail(CS_EDEVICE, "batch tuning: timing");
+                break;
+            }
+            std::sort(t, t + 3);
+            if (ci == 1) {
+                rule_ms = t[1];
+                continue;
+            }
+            if (best_ms < 0.0f || t[1] < best_ms) {
+                best_ms = t[1];
+                best_kind = cands[ci][0];
+                best_chunk = cands[ci][1];
+            }
+        }
+        if (st != CS_OK) break;
+        const Key &k = kv.first;
+        const ItemInfo &i0 = info[members[0]];
+        tune_store_batch(device, std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k),
+                         i0.I.n, best_kind, best_chunk, best_ms);
+        out->classes++;
+        out->rule_ms += rule_ms < 0.0f ? best_ms : rule_ms;
+        out->tuned_ms += best_ms;
+    }
+    cleanup();
+    return st;
 }
 
 }  // extern "C"

@@ -224,6 +224,7 @@ struct RepDesc {
     const int64_t *c0;     // DOT plan: relation 0 and 1 at repetition t
     const int64_t *c1;
     int32_t q, t, log2m, r, d;
+    int32_t S;             // row length 2^S of the two-pass transforms of this length
     uint32_t m;            // buckets (log2m is exact only for powers of two)
     uint32_t conj;         // SPECTRAL: relations taken conjugated
     int32_t vec_base;      // SPECTRAL: first packed vector of query q in its group's buffer
@@ -335,7 +336,7 @@ __global__ __launch_bounds__(kThreads) void k_spec_f64(const double2 *__restrict
     const int item = find_item(prefix, n_items, blockIdx.x);
     const RepDesc D = reps[idx[item]];
     const int blk = (int)(blockIdx.x - prefix[item]);
-    const int log2m = D.log2m;
+    const int log2m = D.log2m, S = D.S;
     const uint32_t m = 1u << log2m;
     const int r = D.r;
     double acc = 0.0, acc_abs = 0.0;
@@ -343,8 +344,8 @@ __global__ __launch_bounds__(kThreads) void k_spec_f64(const double2 *__restrict
 #pragma unroll
     for (int k = 0; k < kMaxRel; ++k) mx[k] = 0.0;
     for (uint32_t pos = blk * kThreads + threadIdx.x; pos < m; pos += (uint32_t)D.nb * kThreads) {
-        const uint32_t f = pos_freq(pos, log2m);
-        const uint32_t npos = freq_pos((m - f) & (m - 1), log2m);
+        const uint32_t f = pos_freq(pos, log2m, S);
+        const uint32_t npos = freq_pos((m - f) & (m - 1), log2m, S);
         double pr = 1.0, pi = 0.0;
 #pragma unroll
         for (int k = 0; k < kMaxRel; ++k) {
@@ -399,13 +400,13 @@ __global__ __launch_bounds__(kThreads) void k_spec_mod(const uint32_t *__restric
     const int pi = blockIdx.y;
     const PrimeDev P = primes[pi];
     const RingM R{P.p, P.pinv_neg};
-    const int log2m = D.log2m;
+    const int log2m = D.log2m, S = D.S;
     const uint32_t m = 1u << log2m;
     const uint32_t *base = N + (size_t)pi * vpp * m;
     uint32_t acc = 0;
     for (uint32_t pos = blk * kThreads + threadIdx.x; pos < m; pos += (uint32_t)D.nb * kThreads) {
-        const uint32_t f = pos_freq(pos, log2m);
-        const uint32_t npos = freq_pos((m - f) & (m - 1), log2m);
+        const uint32_t f = pos_freq(pos, log2m, S);
+        const uint32_t npos = freq_pos((m - f) & (m - 1), log2m, S);
         uint32_t prod = P.one;
         for (int k = 0; k < D.r; ++k) {
             const uint32_t *v = base + (size_t)(D.mod_vec_base + k * D.d + D.t) * m;
@@ -447,7 +448,7 @@ __global__ void k_mod_ones(uint32_t *reg, uint32_t m, int d, const PrimeDev *__r
 
 // dst = dst o src (time domain) or dst[pos] = src[-f] * dst[f] (frequency domain, the
 // pointwise step of the cross-correlation src star dst).
-__global__ void k_mod_mul(uint32_t *dst, const uint32_t *__restrict__ src, uint32_t m, int log2m, int d,
+__global__ void k_mod_mul(uint32_t *dst, const uint32_t *__restrict__ src, uint32_t m, int log2m, int S, int d,
                           const PrimeDev *__restrict__ primes, int negate_src)
 {
     const int v = blockIdx.y;
@@ -457,7 +458,7 @@ __global__ void k_mod_mul(uint32_t *dst, const uint32_t *__restrict__ src, uint3
     const uint32_t *a = src + (size_t)v * m;
     for (uint32_t pos = blockIdx.x * blockDim.x + threadIdx.x; pos < m; pos += gridDim.x * blockDim.x) {
         uint32_t sp = pos;
-        if (negate_src) sp = freq_pos((m - pos_freq(pos, log2m)) & (m - 1), log2m);
+        if (negate_src) sp = freq_pos((m - pos_freq(pos, log2m, S)) & (m - 1), log2m, S);
         o[pos] = R.mul(o[pos], a[sp]);
     }
 }
@@ -1208,6 +1209,16 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
 {
     if (nq <= 0) return CS_OK;
     const int device = hs[0]->device;
+    // one split per transform length for the whole estimate (the tuning table may change
+    // between estimates, never inside one)
+    std::map<int, int> split_cache;
+    auto split_of = [&](int L) {
+        auto it = split_cache.find(L);
+        if (it != split_cache.end()) return it->second;
+        const int S = split_for(device, L);
+        split_cache.emplace(L, S);
+        return S;
+    };
     for (int q = 0; q < nq; ++q)
         if (hs[q]->device != device) return fail(CS_EINVAL, "batched estimate: handles on different devices");
     PrimeDev *primes = nullptr;
@@ -1220,7 +1231,7 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
     std::vector<SkDesc> sd;
     std::vector<int32_t> dot_idx;
     struct Group {
-        int log2m;
+        int log2m, S;
         std::vector<int> queries;
         std::vector<int32_t> rep_idx;
         std::vector<const int64_t *> re, im;
@@ -1266,6 +1277,7 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
         if (Q.plan == CS_PLAN_SPECTRAL) {
             G = &groups[L];
             G->log2m = L;
+            G->S = split_of(L);
             G->queries.push_back(q);
             vec_base = (int)G->re.size();
             const int n_sk = r * d;
@@ -1288,6 +1300,7 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
             D.q = q;
             D.t = t;
             D.log2m = L;
+            D.S = split_of(L);
             D.m = h.m;
             D.r = r;
             D.d = d;
@@ -1456,7 +1469,7 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
             double2 *Z = reinterpret_cast<double2 *>(wb + o_Z + G.z_off);
             st = fft_f64_forward(reinterpret_cast<const int64_t *const *>(wb + o_gre[gi]),
                                  reinterpret_cast<const int64_t *const *>(wb + o_gim[gi]), (int)G.re.size(), Z,
-                                 G.log2m, reinterpret_cast<const double2 *>(tw), G.log2m, s);
+                                 G.log2m, G.S, reinterpret_cast<const double2 *>(tw), G.log2m, s);
             if (st != CS_OK) return st;
             hipLaunchKernelGGL(k_spec_f64, dim3((unsigned)g_pre[gi].back()), dim3(kThreads), 0, s, Z, d_rep,
                                reinterpret_cast<const int32_t *>(wb + o_gidx[gi]),
@@ -1499,7 +1512,7 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
                 uint32_t *N = reinterpret_cast<uint32_t *>(mod_cur);
                 mod_cur += align_up((size_t)ks * vpp * ((size_t)1 << G.log2m) * sizeof(uint32_t));
                 st = ntt_forward(reinterpret_cast<const int64_t *const *>(wb + o_gptr[gi]), vpp, ks, N, G.log2m,
-                                 primes, roots, G.log2m, s);
+                                 G.S, primes, roots, G.log2m, s);
                 if (st != CS_OK) return st;
                 hipLaunchKernelGGL(k_spec_mod, dim3((unsigned)g_pre[gi].back(), ks), dim3(kThreads), 0, s, N, vpp,
                                    d_rep, reinterpret_cast<const int32_t *>(wb + o_gidx[gi]),
@@ -1644,7 +1657,7 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
                 CSK_HIP(hipMemcpyAsync(d_rep + qd[q].rep_base, rd.data() + qd[q].rep_base, qd[q].d * sizeof(RepDesc),
                                        hipMemcpyHostToDevice, s));
             uint32_t *N = reinterpret_cast<uint32_t *>(mbc + tab_bytes);
-            st = ntt_forward(reinterpret_cast<const int64_t *const *>(mbc), vpp, K, N, G.log2m, primes, roots,
+            st = ntt_forward(reinterpret_cast<const int64_t *const *>(mbc), vpp, K, N, G.log2m, G.S, primes, roots,
                              G.log2m, s);
             if (st != CS_OK) return st;
             hipLaunchKernelGGL(k_spec_mod, dim3((unsigned)mpre.back(), K), dim3(kThreads), 0, s, N, vpp, d_rep,
@@ -1665,6 +1678,7 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
             // LM >= 2m - 1 of a zero-padded linear convolution
             const int L = h.pow2 ? h.log2m : ceil_log2(2 * m - 1);
             const uint32_t Mlen = 1u << L;
+            const int S = split_of(L);
             const uint32_t *roots = roots_mod(device, L, 0, false, s, &st);
             if (!roots) return st;
             const size_t reg_elems = (size_t)K * d * m;
@@ -1691,33 +1705,33 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
                         break;
                     case OP_HAD:
                         hipLaunchKernelGGL(k_mod_mul, dim3(gx, K * d), dim3(256), 0, s, dst,
-                                           M + (size_t)op.src * reg_elems, m, 0, d, primes, 0);
+                                           M + (size_t)op.src * reg_elems, m, 0, S, d, primes, 0);
                         break;
                     case OP_CORR: {
                         uint32_t *src = M + (size_t)op.src * reg_elems;
                         if (h.pow2) {
-                            st = ntt_forward(nullptr, d, K, src, L, primes, roots, L, s);
+                            st = ntt_forward(nullptr, d, K, src, L, S, primes, roots, L, s);
                             if (st != CS_OK) return st;
-                            st = ntt_forward(nullptr, d, K, dst, L, primes, roots, L, s);
+                            st = ntt_forward(nullptr, d, K, dst, L, S, primes, roots, L, s);
                             if (st != CS_OK) return st;
-                            hipLaunchKernelGGL(k_mod_mul, dim3(gx, K * d), dim3(256), 0, s, dst, src, m, L, d, primes,
-                                               1);
+                            hipLaunchKernelGGL(k_mod_mul, dim3(gx, K * d), dim3(256), 0, s, dst, src, m, L, S, d,
+                                               primes, 1);
                             CSK_HIP(hipGetLastError());
-                            st = ntt_inverse(d, K, dst, L, primes, roots, L, s);
+                            st = ntt_inverse(d, K, dst, L, S, primes, roots, L, s);
                             if (st != CS_OK) return st;
                         } else {
                             // src star dst = reverse(src) circularly convolved with dst
                             hipLaunchKernelGGL(k_mod_pad, dim3(gxM, K * d), dim3(256), 0, s, padA, src, m, Mlen, 1);
                             hipLaunchKernelGGL(k_mod_pad, dim3(gxM, K * d), dim3(256), 0, s, padB, dst, m, Mlen, 0);
                             CSK_HIP(hipGetLastError());
-                            st = ntt_forward(nullptr, d, K, padA, L, primes, roots, L, s);
+                            st = ntt_forward(nullptr, d, K, padA, L, S, primes, roots, L, s);
                             if (st != CS_OK) return st;
-                            st = ntt_forward(nullptr, d, K, padB, L, primes, roots, L, s);
+                            st = ntt_forward(nullptr, d, K, padB, L, S, primes, roots, L, s);
                             if (st != CS_OK) return st;
-                            hipLaunchKernelGGL(k_mod_mul, dim3(gxM, K * d), dim3(256), 0, s, padB, padA, Mlen, L, d,
+                            hipLaunchKernelGGL(k_mod_mul, dim3(gxM, K * d), dim3(256), 0, s, padB, padA, Mlen, L, S, d,
                                                primes, 0);
                             CSK_HIP(hipGetLastError());
-                            st = ntt_inverse(d, K, padB, L, primes, roots, L, s);
+                            st = ntt_inverse(d, K, padB, L, S, primes, roots, L, s);
                             if (st != CS_OK) return st;
                             hipLaunchKernelGGL(k_mod_fold, dim3(gx, K * d), dim3(256), 0, s, dst, padB, m, Mlen, d,
                                                primes);
@@ -1788,3 +1802,158 @@ cs_status estimate_run_async(Handle &h, hipStream_t s, cs_estimate_t *out)
 }
 
 }  // namespace csk
+
+namespace csk {
+namespace {
+
+// Synthetic int64 vectors for timing transforms: a SplitMix64 mix of the index, shifted
+// into a sketch-like magnitude.
+__global__ void k_tune_fill(int64_t *x, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        uint64_t z = (uint64_t)i + 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        x[i] = (int64_t)(z ^ (z >> 31)) >> 40;
+    }
+}
+
+// flag |= spectrum a (row length 2^Sa) differs from b (2^Sb) at some frequency
+__global__ void k_tune_cmp(const uint32_t *__restrict__ a, const uint32_t *__restrict__ b, int n_vec, int log2m,
+                           int Sa, int Sb, unsigned int *flag)
+{
+    const size_t m = (size_t)1 << log2m;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)n_vec * m;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const size_t v = i >> log2m;
+        const uint32_t f = (uint32_t)(i & (m - 1));
+        if (a[v * m + freq_pos(f, log2m, Sa)] != b[v * m + freq_pos(f, log2m, Sb)]) atomicOr(flag, 1u);
+    }
+}
+
+__global__ void k_tune_flag0(unsigned int *p) { *p = 0u; }
+
+}  // namespace
+}  // namespace csk
+
+extern "C" cs_status cs_tune_transform(int32_t log2m, int32_t n_vec, void *stream, cs_tune_report *out)
+{
+    using namespace csk;
+    if (!out) return fail(CS_EINVAL, "null report");
+    if (log2m <= 12 || log2m > kMaxLog2N) return fail(CS_EINVAL, "two-pass transform lengths are 2^13..2^21");
+    if (n_vec < 1 || n_vec > 4096) return fail(CS_EINVAL, "n_vec must be in [1, 4096]");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int device = 0;
+    CSK_HIP(hipGetDevice(&device));
+    cs_status st = CS_OK;
+    const double *tw = twiddles_f64(device, log2m, s, &st);
+    if (!tw) return st;
+    const uint32_t *roots = roots_mod(device, log2m, 0, false, s, &st);
+    if (!roots) return st;
+    PrimeDev *primes = nullptr;
+    if ((st = device_primes(device, s, &primes)) != CS_OK) return st;
+    const size_t m = (size_t)1 << log2m;
+    const size_t elems = (size_t)n_vec * m;
+    int64_t *src = nullptr;
+    double2 *Z = nullptr;
+    uint32_t *N = nullptr, *Nref = nullptr;
+    void **ptrs = nullptr;
+    unsigned int *flag = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(s);
+        if (src) (void)hipFree(src);
+        if (Z) (void)hipFree(Z);
+        if (N) (void)hipFree(N);
+        if (Nref) (void)hipFree(Nref);
+        if (ptrs) (void)hipFree(ptrs);
+        if (flag) (void)hipFree(flag);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    // packed pairs: vector v's real part is vector 2v of src, its imaginary part 2v + 1
+    if (hipMalloc(&src, 2 * elems * sizeof(int64_t)) != hipSuccess || hipMalloc(&Z, elems * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&N, elems * sizeof(uint32_t)) != hipSuccess || hipMalloc(&Nref, elems * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&ptrs, 3 * (size_t)n_vec * sizeof(void *)) != hipSuccess ||
+        hipMalloc(&flag, sizeof(unsigned int)) != hipSuccess) {
+        cleanup();
+        return fail(CS_ENOMEM, "transform tuning buffers");
+    }
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return fail(CS_EDEVICE, "transform tuning events");
+    }
+    std::vector<const int64_t *> tab(3 * (size_t)n_vec);
+    for (int v = 0; v < n_vec; ++v) {
+        tab[v] = src + (size_t)(2 * v) * m;               // fp64: real parts
+        tab[n_vec + v] = src + (size_t)(2 * v + 1) * m;   // fp64: imaginary parts
+        tab[2 * n_vec + v] = src + (size_t)v * m;         // NTT: one sketch per vector
+    }
+    hipLaunchKernelGGL(k_tune_fill, dim3(4096), dim3(256), 0, s, src, 2 * elems);
+    if (hipMemcpyAsync(ptrs, tab.data(), tab.size() * sizeof(void *), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        cleanup();
+        return fail(CS_EDEVICE, "transform tuning inputs");
+    }
+    const int64_t *const *re = reinterpret_cast<const int64_t *const *>(ptrs);
+    const int64_t *const *im = re + n_vec;
+    const int64_t *const *nt = re + 2 * n_vec;
+    const int S0 = default_split_bits(log2m);
+    std::memset(out, 0, sizeof(*out));
+    out->best = -1;
+    float best_ms = 0.0f;
+    // the default split first: its number-theoretic spectrum is the reference
+    std::vector<int> cand{S0};
+    for (int S = 10; S <= 12; ++S)
+        if (S != S0 && split_ok(log2m, S)) cand.push_back(S);
+    for (size_t ci = 0; ci < cand.size() && st == CS_OK; ++ci) {
+        const int S = cand[ci];
+        cs_tune_candidate &o = out->cand[ci];
+        o.strategy = CS_TUNE_TRANSFORM_SPLIT;
+        o.grid_blocks = S;
+        o.flags = 0;
+        o.valid = 0;
+        o.ms = -1.0f;
+        uint32_t *dst = ci == 0 ? Nref : N;
+        if ((st = ntt_forward(nt, n_vec, 1, dst, log2m, S, primes, roots, log2m, s)) != CS_OK) break;
+        if (ci > 0) {
+            unsigned int hflag = 0;
+            hipLaunchKernelGGL(k_tune_flag0, dim3(1), dim3(1), 0, s, flag);
+            hipLaunchKernelGGL(k_tune_cmp, dim3(4096), dim3(256), 0, s, N, Nref, n_vec, log2m, S, S0, flag);
+            if (hipMemcpyAsync(&hflag, flag, sizeof(unsigned int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                st = fail(CS_EDEVICE, "transform tuning: compare");
+                break;
+            }
+            if (hflag) {
+                o.valid = -1;
+                continue;
+            }
+        }
+        float t[3];
+        bool ok = true;
+        for (int r = 0; r < 3 && ok; ++r)
+            ok = hipEventRecord(e0, s) == hipSuccess &&
+                 fft_f64_forward(re, im, n_vec, Z, log2m, S, reinterpret_cast<const double2 *>(tw), log2m, s) == CS_OK &&
+                 ntt_forward(nt, n_vec, 1, N, log2m, S, primes, roots, log2m, s) == CS_OK &&
+                 hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                 hipEventElapsedTime(&t[r], e0, e1) == hipSuccess;
+        if (!ok) {
+            st = fail(CS_EDEVICE, "transform tuning: timing");
+            break;
+        }
+        std::sort(t, t + 3);
+        o.ms = t[1];
+        o.valid = 1;
+        if (out->best < 0 || o.ms < best_ms) {
+            out->best = (int32_t)ci;
+            best_ms = o.ms;
+        }
+    }
+    out->n = (int32_t)cand.size();
+    cleanup();
+    if (st != CS_OK) return st;
+    if (out->best < 0) return fail(CS_EDEVICE, "transform tuning: no split ran");
+    tune_store_split(device, log2m, out->cand[out->best].grid_blocks, best_ms);
+    return CS_OK;
+}

@@ -185,6 +185,19 @@ cs_status launch_update(const UpdateArgs &a, int strategy, int grid_blocks, hipS
 cs_status zero_device_u64(unsigned long long *p, hipStream_t s);
 // Tuned (strategy, grid, flags) for this update's class on `device`, if one was tuned.
 bool tune_lookup(const UpdateArgs &a, int device, int *strategy, int *grid, int *flags);
+// Batched update tasks: kind (0 global atomics, 1 LDS segment) and log2 of the tuples per
+// task tuned for the class (device, m, d, key columns, one-join columns, unit weights,
+// floor(log2 n)).
+bool tune_lookup_batch(int device, uint32_t m, int d, int n_cols, int e1, int unit, uint64_t n, int *kind,
+                       int *chunk_log2);
+void tune_store_batch(int device, uint32_t m, int d, int n_cols, int e1, int unit, uint64_t n, int kind,
+                      int chunk_log2, float ms);
+// Row length 2^S tuned for two-pass transforms of length 2^log2m (0: none tuned).
+int tune_split(int device, int log2m);
+void tune_store_split(int device, int log2m, int S, float ms);
+// Whether 2^S is a usable row length for a two-pass transform of length 2^log2m: tiles of
+// 2^10..2^12 elements, columns no longer than rows.
+inline bool split_ok(int log2m, int S) { return S >= 10 && S <= 12 && 2 * S >= log2m && S < log2m; }
 int auto_update_strategy(uint32_t m, int32_t d, uint64_t n, int n_cols, bool unit, bool has_scratch,
                          bool e1_pow2);
 

@@ -4,7 +4,7 @@
 // exact modular evaluation.
 //
 // Lengths up to 4096 are done in one pass inside LDS.  Longer lengths m = N1 * N2 (N2 =
-// 2^S, S = split_bits(log2 m), from 1024 to 4096) use the four-step decomposition
+// 2^S, from 1024 to 4096, default_split_bits() or the tuned split) use the four-step decomposition
 // (Bailey): element n = N2 n1 + n2.
 //   forward: pass 1 transforms each column n2 over n1 (stride N2) and multiplies output
 //            f1 by w_m^(f1 n2); pass 2 transforms each row over n2.  Position N2 f1 + f2
@@ -219,9 +219,8 @@ __global__ __launch_bounds__(NT) void k_ntt(ModSrc src, uint32_t *buf, PassGeom 
 }
 
 // Two-pass lengths: tiles of N2 = 2^S elements, columns of N1 = 2^(log2m - S) <= N2.
-PassGeom column_pass(int log2m, bool twiddle)
+PassGeom column_pass(int log2m, int S, bool twiddle)
 {
-    const int S = split_bits(log2m);
     PassGeom g{};
     g.log2m = log2m;
     g.log2L = log2m - S;
@@ -234,9 +233,8 @@ PassGeom column_pass(int log2m, bool twiddle)
     return g;
 }
 
-PassGeom row_pass(int log2m, bool twiddle)
+PassGeom row_pass(int log2m, int S, bool twiddle)
 {
-    const int S = split_bits(log2m);
     PassGeom g{};
     g.log2m = log2m;
     g.log2L = S;
@@ -250,11 +248,11 @@ PassGeom row_pass(int log2m, bool twiddle)
 }
 
 // Launch of one pass with the tile its geometry needs (single pass: the whole vector in
-// one 4096-element tile; two-pass lengths: 2^split_bits elements).
+// one 4096-element tile; two-pass lengths: 2^S elements).
 template <class F>
 void with_tile(const PassGeom &g, bool single, F &&f)
 {
-    const int tile_bits = g.log2L + g.log2C;  // = split_bits(log2m) for both passes
+    const int tile_bits = g.log2L + g.log2C;  // = S for both passes
     if (single || tile_bits == 12) f(std::integral_constant<int, kSingleTile>{});
     else if (tile_bits == 10) f(std::integral_constant<int, 1024>{});
     else f(std::integral_constant<int, 2048>{});
@@ -274,8 +272,14 @@ PassGeom single_pass(int log2m)
 
 }  // namespace
 
+int split_for(int device, int log2m)
+{
+    const int t = tune_split(device, log2m);
+    return t && split_ok(log2m, t) ? t : default_split_bits(log2m);
+}
+
 cs_status fft_f64_forward(const int64_t *const *re, const int64_t *const *im, int n_vec, double2 *buf, int log2m,
-                          const double2 *tw, int log2T, hipStream_t s)
+                          int S, const double2 *tw, int log2T, hipStream_t s)
 {
     if (n_vec == 0) return CS_OK;
     F64Src first{re, im};
@@ -291,20 +295,20 @@ cs_status fft_f64_forward(const int64_t *const *re, const int64_t *const *im, in
         CSK_HIP(pass(single_pass(log2m), true, first));
         return CS_OK;
     }
-    CSK_HIP(pass(column_pass(log2m, true), false, first));
-    CSK_HIP(pass(row_pass(log2m, false), false, self));
+    CSK_HIP(pass(column_pass(log2m, S, true), false, first));
+    CSK_HIP(pass(row_pass(log2m, S, false), false, self));
     return CS_OK;
 }
 
 namespace {
 // The column pass of the NTT reads its columns in runs of C 4-byte residues; with the
 // split shared with the fp64 FFT (runs of >= 8 complex doubles = 128 bytes) C can be as
-// low as 8 (32 bytes), so NTT column passes take at least 32 columns per block (tiles up
+// low as 8 (32 bytes), so NTT column passes take up to 32 columns per block (tiles up
 // to 16384 residues, 64 KB of LDS, 1024 threads).  The decomposition, and with it the
 // output order, is unchanged.
 PassGeom widen_columns(PassGeom g)
 {
-    while (g.log2C < 5 && g.blocks > 1) {
+    while (g.log2C < 5 && g.blocks > 1 && g.log2L + g.log2C < 14) {
         ++g.log2C;
         g.block_stride <<= 1;
         g.blocks >>= 1;
@@ -333,7 +337,7 @@ hipError_t ntt_pass(const PassGeom &g, bool single, const ModSrc &src, int n_vec
 }
 }  // namespace
 
-cs_status ntt_forward(const int64_t *const *ptrs, int vec_per_prime, int n_primes, uint32_t *buf, int log2m,
+cs_status ntt_forward(const int64_t *const *ptrs, int vec_per_prime, int n_primes, uint32_t *buf, int log2m, int S,
                       const PrimeDev *primes, const uint32_t *roots, int log2T, hipStream_t s,
                       const int32_t *rep_of, const int32_t *kp)
 {
@@ -347,14 +351,14 @@ cs_status ntt_forward(const int64_t *const *ptrs, int vec_per_prime, int n_prime
                          kp, s));
         return CS_OK;
     }
-    CSK_HIP(ntt_pass(widen_columns(column_pass(log2m, true)), false, in, n_vec, buf, vec_per_prime, primes, roots,
-                     log2T, 0, rep_of, kp, s));
-    CSK_HIP(ntt_pass(row_pass(log2m, false), false, self, n_vec, buf, vec_per_prime, primes, roots, log2T, 0, rep_of,
-                     kp, s));
+    CSK_HIP(ntt_pass(widen_columns(column_pass(log2m, S, true)), false, in, n_vec, buf, vec_per_prime, primes,
+                     roots, log2T, 0, rep_of, kp, s));
+    CSK_HIP(ntt_pass(row_pass(log2m, S, false), false, self, n_vec, buf, vec_per_prime, primes, roots, log2T, 0,
+                     rep_of, kp, s));
     return CS_OK;
 }
 
-cs_status ntt_inverse(int vec_per_prime, int n_primes, uint32_t *buf, int log2m, const PrimeDev *primes,
+cs_status ntt_inverse(int vec_per_prime, int n_primes, uint32_t *buf, int log2m, int S, const PrimeDev *primes,
                       const uint32_t *roots, int log2T, hipStream_t s)
 {
     const int n_vec = vec_per_prime * n_primes;
@@ -366,9 +370,9 @@ cs_status ntt_inverse(int vec_per_prime, int n_primes, uint32_t *buf, int log2m,
         CSK_HIP(ntt_pass(g, true, self, n_vec, buf, vec_per_prime, primes, roots, log2T, 1, nullptr, nullptr, s));
         return CS_OK;
     }
-    CSK_HIP(ntt_pass(row_pass(log2m, true), false, self, n_vec, buf, vec_per_prime, primes, roots, log2T, 1, nullptr,
-                     nullptr, s));
-    PassGeom g2 = widen_columns(column_pass(log2m, false));
+    CSK_HIP(ntt_pass(row_pass(log2m, S, true), false, self, n_vec, buf, vec_per_prime, primes, roots, log2T, 1,
+                     nullptr, nullptr, s));
+    PassGeom g2 = widen_columns(column_pass(log2m, S, false));
     g2.scale = 1;
     CSK_HIP(ntt_pass(g2, false, self, n_vec, buf, vec_per_prime, primes, roots, log2T, 1, nullptr, nullptr, s));
     return CS_OK;

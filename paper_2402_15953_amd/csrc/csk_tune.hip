@@ -24,14 +24,17 @@ namespace csk {
 
 namespace {
 
+// scope 0: plain update (cs_update's strategy); 1: a batched update task (kind and
+// tuple chunk of k_batch_update's tasks); 2: the split of two-pass transforms of length m.
 struct TuneKey {
     std::string arch;  // gcnArchName and compute-unit count
+    int32_t scope = 0;
     uint32_t m;
     int32_t d, n_cols, e1, unit, n_class;
     bool operator<(const TuneKey &o) const
     {
-        return std::tie(arch, m, d, n_cols, e1, unit, n_class) <
-               std::tie(o.arch, o.m, o.d, o.n_cols, o.e1, o.unit, o.n_class);
+        return std::tie(scope, arch, m, d, n_cols, e1, unit, n_class) <
+               std::tie(o.scope, o.arch, o.m, o.d, o.n_cols, o.e1, o.unit, o.n_class);
     }
 };
 struct TuneChoice {
@@ -66,9 +69,17 @@ int n_class_of(uint64_t n)
     return c;  // floor(log2 n)
 }
 
+int scope_of_strategy(int32_t strategy)
+{
+    if (strategy == CS_TUNE_BATCH_ATOMIC || strategy == CS_TUNE_BATCH_SEGMENT) return 1;
+    if (strategy == CS_TUNE_TRANSFORM_SPLIT) return 2;
+    return 0;
+}
+
 TuneKey key_of(const UpdateArgs &a, int device)
 {
     TuneKey k;
+    k.scope = 0;
     k.arch = arch_of(device);
     k.m = a.m;
     k.d = a.d;
@@ -104,6 +115,68 @@ bool tune_lookup(const UpdateArgs &a, int device, int *strategy, int *grid, int 
     *grid = it->second.grid;
     *flags = it->second.flags;
     return true;
+}
+
+TuneKey batch_key(int device, uint32_t m, int d, int n_cols, int e1, int unit, uint64_t n)
+{
+    TuneKey k;
+    k.arch = arch_of(device);
+    k.scope = 1;
+    k.m = m;
+    k.d = d;
+    k.n_cols = n_cols;
+    k.e1 = e1;
+    k.unit = unit;
+    k.n_class = n_class_of(n);
+    return k;
+}
+
+TuneKey split_key(int device, int log2m)
+{
+    TuneKey k;
+    k.arch = arch_of(device);
+    k.scope = 2;
+    k.m = 1u << log2m;
+    k.d = 0;
+    k.n_cols = 0;
+    k.e1 = 0;
+    k.unit = 0;
+    k.n_class = 0;
+    return k;
+}
+
+bool tune_lookup_batch(int device, uint32_t m, int d, int n_cols, int e1, int unit, uint64_t n, int *kind,
+                       int *chunk_log2)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (g_tune.empty()) return false;
+    auto it = g_tune.find(batch_key(device, m, d, n_cols, e1, unit, n));
+    if (it == g_tune.end()) return false;
+    *kind = it->second.strategy == CS_TUNE_BATCH_ATOMIC ? 0 : 1;
+    *chunk_log2 = it->second.grid;
+    return true;
+}
+
+void tune_store_batch(int device, uint32_t m, int d, int n_cols, int e1, int unit, uint64_t n, int kind,
+                      int chunk_log2, float ms)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[batch_key(device, m, d, n_cols, e1, unit, n)] =
+        TuneChoice{kind == 0 ? CS_TUNE_BATCH_ATOMIC : CS_TUNE_BATCH_SEGMENT, chunk_log2, 0, ms};
+}
+
+int tune_split(int device, int log2m)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (g_tune.empty()) return 0;
+    auto it = g_tune.find(split_key(device, log2m));
+    return it == g_tune.end() ? 0 : it->second.grid;
+}
+
+void tune_store_split(int device, int log2m, int S, float ms)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[split_key(device, log2m)] = TuneChoice{CS_TUNE_TRANSFORM_SPLIT, S, 0, ms};
 }
 
 }  // namespace csk
@@ -300,8 +373,19 @@ cs_status cs_tune_load(const char *path)
         TuneChoice c;
         const int nf = std::sscanf(line, "%127s %u %d %d %d %d %d %d %d %d %f", arch, &k.m, &k.d, &k.n_cols, &k.e1,
                                    &k.unit, &k.n_class, &c.strategy, &c.grid, &c.flags, &c.ms);
-        ok = nf == 11 && c.strategy > CS_UPDATE_AUTO && c.strategy <= CS_UPDATE_PARTITION && k.d >= 1 &&
-             k.d <= kMaxD && k.m >= 1 && c.grid >= 0;
+        k.scope = scope_of_strategy(c.strategy);
+        if (nf != 11) {
+            ok = false;
+        } else if (k.scope == 0) {
+            ok = c.strategy > CS_UPDATE_AUTO && c.strategy <= CS_UPDATE_PARTITION && k.d >= 1 && k.d <= kMaxD &&
+                 k.m >= 1 && c.grid >= 0;
+        } else if (k.scope == 1) {  // grid: log2 of the tuples per task
+            ok = k.d >= 1 && k.d <= kMaxD && k.m >= 1 && c.grid >= 12 && c.grid <= 22;
+        } else {  // grid: log2 of the row length of the two-pass transform of length m
+            const bool pow2 = k.m >= 2 && (k.m & (k.m - 1)) == 0;
+            const int L = pow2 ? 31 - __builtin_clz(k.m) : 0;
+            ok = pow2 && L > 12 && L <= kMaxLog2N && split_ok(L, c.grid);
+        }
         if (ok) {
             k.arch = arch;
             got[k] = c;

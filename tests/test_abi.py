@@ -108,3 +108,34 @@ def test_checkpoint_blob_validation_before_any_device_work():
         st = L.cs_import(blob, len(blob), ctypes.byref(h))
         assert st == csk.CS_EINVAL, (blob[:12], st)
         assert not h.value
+
+
+def test_tune_table_batch_and_split_entries(tmp_path):
+    """Batched-task and transform-split entries share the table file with plain-update
+    entries (their own scope: same class fields, different entries) and are validated
+    on load: chunk exponents 12..22, splits 2^S with S = 10..12 and S < log2 m <= 2S."""
+    import paper_2402_15953_amd as csk
+    csk.tune_clear()
+    good = tmp_path / "tune.txt"
+    good.write_text("csketch-tune 1\n"
+                    "gfx950-256cu 65536 9 2 1 1 17 17 18 0 0.500000\n"
+                    "gfx950-256cu 1024 5 1 1 1 12 16 16 0 0.010000\n"
+                    "gfx950-256cu 262144 0 0 0 0 0 32 11 0 0.200000\n"
+                    "gfx950-256cu 65536 9 2 1 1 17 2 28 0 0.290000\n")
+    csk.tune_load(str(good))
+    assert csk.tune_count() == 4
+    out = tmp_path / "again.txt"
+    csk.tune_save(str(out))
+    assert sorted(out.read_text().splitlines()[1:]) == sorted(good.read_text().splitlines()[1:])
+    for bad_line in ("gfx950-256cu 262144 0 0 0 0 0 32 9 0 0.2",      # tile below 2^10
+                     "gfx950-256cu 4096 0 0 0 0 0 32 10 0 0.2",        # one-pass length
+                     "gfx950-256cu 1048576 0 0 0 0 0 32 13 0 0.2",     # tile above 2^12
+                     "gfx950-256cu 100000 0 0 0 0 0 32 11 0 0.2",      # not a power of two
+                     "gfx950-256cu 65536 9 2 1 1 17 17 30 0 0.5",      # chunk beyond 2^22
+                     "gfx950-256cu 65536 9 2 1 1 17 33 18 0 0.5"):     # no such strategy code
+        bad = tmp_path / "bad.txt"
+        bad.write_text("csketch-tune 1\n" + bad_line + "\n")
+        with pytest.raises(csk.CsError):
+            csk.tune_load(str(bad))
+    assert csk.tune_count() == 4
+    csk.tune_clear()

@@ -67,3 +67,90 @@ def test_tuned_update_matches_oracle(case):
     finally:
         sk.close()
         csk.tune_clear()
+
+
+def _arch_of_table(path):
+    for line in open(path).read().splitlines()[1:]:
+        if line.strip():
+            return line.split()[0]
+    raise AssertionError("empty tuning table")
+
+
+def test_batch_tuner_keeps_counters_and_plans_with_its_choice(tmp_path):
+    """cs_tune_batch_update: every candidate's counters equal the global-atomic run's
+    (none rejected), the chosen class entries are stored, and a batch planned with them
+    gives exactly the per-query path's sketches."""
+    from tests.test_gpu_batch import _batched_items, _make_inputs, _plain
+    csk.tune_clear()
+    specs = W.batched_queries(48, seed=21, m_log2=(10, 16), n_range=(50, 200_000))
+    _say("batch tuner", len(specs), "queries")
+    data = _make_inputs(specs)
+    plain = _plain(specs, data)
+    sks, items, keep = _batched_items(specs, data)
+    b = csk.Batch()
+    rep = b.tune(items)
+    _say("  report", rep)
+    assert rep["classes"] >= 1 and rep["rejected"] == 0
+    assert rep["tuned_ms"] > 0 and rep["rule_ms"] > 0
+    assert csk.tune_count() == rep["classes"]
+    path = tmp_path / "tuned.txt"
+    csk.tune_save(str(path))
+    codes = {int(l.split()[7]) for l in path.read_text().splitlines()[1:]}
+    assert codes <= {csk.TUNE_BATCH_ATOMIC, csk.TUNE_BATCH_SEGMENT}
+    # the handles' counters were not touched by tuning
+    for sk in sks:
+        for k in range(sk.graph.n_rel):
+            assert not sk.read_sketch(k).any()
+    b.update(items)
+    torch.cuda.synchronize()
+    for qi, (sp, a, p) in enumerate(zip(specs, sks, plain)):
+        for k in range(sp.graph.n_rel):
+            assert np.array_equal(a.read_sketch(k), p.read_sketch(k)), (qi, k)
+    ests = b.estimate(sks)
+    for e, p in zip(ests, plain):
+        assert e["value"] == p.estimate()["value"]
+    b.close()
+    csk.tune_clear()
+
+
+SPLIT_CASES = [
+    # graph, m, d, n per relation (the transform length is m, or 2^ceil(log2(2m - 1)))
+    (W.chain(4), 1 << 16, 3, 20_000),     # spectral plan, 2^16
+    (W.chain(4), 1 << 18, 2, 3000),       # spectral plan, 2^18
+    (W.fig3_query(), 1 << 14, 3, 3000),   # general plan, 2^14
+    (W.chain(3), 3000, 3, 5000),          # general plan, zero-padded 2^13
+]
+
+
+@pytest.mark.parametrize("case", range(len(SPLIT_CASES)))
+def test_every_transform_split_gives_the_exact_estimate(case, tmp_path):
+    """cs_tune_transform runs every legal split with identical spectra; then each split,
+    forced through the tuning table, gives the oracle's exact per-repetition estimates."""
+    import oracle
+    graph, m, d, n = SPLIT_CASES[case]
+    L = (m - 1).bit_length() if m & (m - 1) == 0 else (2 * m - 2).bit_length()
+    csk.tune_clear()
+    rep = csk.tune_transform(L, n_vec=8)
+    _say("split", case, graph.name, m, "length 2^%d" % L, rep)
+    assert all(c["valid"] == 1 for c in rep["candidates"])
+    splits = [c["split"] for c in rep["candidates"]]
+    assert len(splits) >= 2
+    path = tmp_path / "t.txt"
+    csk.tune_save(str(path))
+    arch = _arch_of_table(path)
+    rels = [keys_u32(W.relation_keys(graph, k, n, "zipf", config=890 + case, s=1.1, D=10 ** 4))
+            for k in range(graph.n_rel)]
+    info, co, ref = oracle_sketches(graph, rels, None, m, d, 77)
+    want = [oracle.estimate_alg3(info, [c[t] for c in ref], m, method="ntt") for t in range(d)]
+    sk = csk.Sketch(graph, m, d, 77)
+    for k in range(graph.n_rel):
+        sk.update(k, to_device_keys(rels[k]))
+    for S in splits:
+        f = tmp_path / ("s%d.txt" % S)
+        f.write_text("csketch-tune 1\n%s %d 0 0 0 0 0 %d %d 0 0.1\n" % (arch, 1 << L, csk.TUNE_TRANSFORM_SPLIT, S))
+        csk.tune_clear()
+        csk.tune_load(str(f))
+        got = sk.estimate(reps=True)
+        assert got["exact"] and got["rep_ints"] == want, (S, got["rep_ints"], want)
+    sk.close()
+    csk.tune_clear()
