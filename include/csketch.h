@@ -262,15 +262,18 @@ typedef struct cs_predicate {
  *   n_kept: optional.  NULL: the call is asynchronous and ordered on `stream` like
  *           cs_update.  Non-NULL: the kernels also count the tuples that passed and the
  *           call waits on `stream` for that count.
- * Nothing is allocated and nothing read back unless n_kept asks for the count.  When
- * every key column takes part in one join, m is a power of two, the Deltas are +-1 and
- * the relation has at most two key columns: for m in (2^15, 2^16] one compaction pass
- * evaluates the predicates once per tuple and writes the kept tuples' keys into the
- * handle's scratch buffer (in rounds when they do not fit), and the 16-bit update reads
- * their count on the device; beyond 2^16 buckets the partition strategy's hashing pass
- * evaluates the predicates itself and compacts the kept tuples in LDS before hashing.
- * Every other shape takes global atomics that skip the tuples failing the predicates.
- * Errors: CS_EINVAL (arguments), CS_EDEVICE. */
+ * Nothing is read back unless n_kept asks for the count.  When every key column takes
+ * part in one join, m is a power of two, the Deltas are +-1 and the relation has at
+ * most two key columns: for m in (2^15, 2^16] one compaction pass evaluates the
+ * predicates once per tuple and writes the kept tuples' keys into a buffer of the
+ * handle (in rounds of 2^23 or 2^24 tuples), and the 16-bit update reads their count on
+ * the device -- that buffer (partial sums plus a round, about 160 MB at d = 9) is
+ * allocated by the handle's first filtered update for m in (2^15, 2^16], after waiting
+ * for `stream`, and kept until cs_destroy; nothing else is allocated.  Beyond 2^16
+ * buckets the partition strategy's hashing pass evaluates the predicates itself and
+ * compacts the kept tuples in LDS before hashing.  Every other shape takes global
+ * atomics that skip the tuples failing the predicates.
+ * Errors: CS_EINVAL (arguments), CS_ENOMEM, CS_EDEVICE. */
 cs_status cs_update_filtered(cs_sketch *h, int32_t rel, const uint32_t *keys, const int64_t *weights,
                              uint64_t n, const uint32_t *attrs, int32_t n_attrs,
                              const cs_predicate *preds, int32_t n_preds, int32_t flags, void *stream,
@@ -389,16 +392,19 @@ cs_status cs_batch_stats(const cs_batch *b, uint64_t *tasks_atomic, uint64_t *ta
  * class's items alone run as one persistent launch with every task choice -- global
  * atomics, or LDS segments over tuple chunks of 2^14, 2^16, 2^18 or 2^20 -- into private
  * counters (the handles' sketches are left untouched); a choice whose counters differ
- * from the global-atomic run's is never taken, the fastest (median of three) is stored
- * in the tuning table, and cs_batch_update / cs_batch_capture plan that class with it
- * from then on (cs_tune_save / cs_tune_load persist it).  The fixed rule the planner
- * otherwise uses is timed beside them.  Synchronous; allocates two buffers of the largest
- * class's counters.  Errors: CS_EINVAL, CS_ENOMEM, CS_EDEVICE. */
+ * from the global-atomic run's is never taken.  Each choice is then timed (median of
+ * three) on enough copies of the class's work, each into its own counters, to fill the
+ * chip, so that the time per copy is the class's cost inside a large batch; the fastest
+ * is stored in the tuning table, and cs_batch_update / cs_batch_capture plan that class
+ * with it from then on (cs_tune_save / cs_tune_load persist it).  The fixed rule the
+ * planner otherwise uses is timed beside them.  Synchronous; allocates two buffers of
+ * the largest class's counters and up to 1 GiB for the copies.
+ * Errors: CS_EINVAL, CS_ENOMEM, CS_EDEVICE. */
 typedef struct cs_tune_batch_report {
     int32_t classes;   /* classes tuned */
     int32_t rejected;  /* candidate runs whose counters differed from the reference */
-    float rule_ms;     /* sum over classes of the fixed rule's time */
-    float tuned_ms;    /* sum over classes of the chosen candidate's time */
+    float rule_ms;     /* sum over classes of the fixed rule's time per copy */
+    float tuned_ms;    /* sum over classes of the chosen candidate's time per copy */
 } cs_tune_batch_report;
 cs_status cs_tune_batch_update(cs_batch *b, const cs_update_item *items, int32_t n_items, void *stream,
                                cs_tune_batch_report *out);

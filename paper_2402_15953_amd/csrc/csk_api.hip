@@ -358,6 +358,7 @@ cs_status cs_destroy(cs_sketch *hs)
     if (h.coef_dev) hipFree(h.coef_dev);
     release_work(h.work);
     if (h.scratch) hipFree(h.scratch);
+    if (h.filter_scratch) hipFree(h.filter_scratch);
     if (h.kept_dev) hipFree(h.kept_dev);
     hipSetDevice(cur);
     delete hs;
@@ -478,6 +479,21 @@ cs_status cs_update_filtered(cs_sketch *hs, int32_t rel, const uint32_t *keys, c
     a.filter = &f;
     a.attrs = attrs;
     a.n_attrs = n_attrs;
+    const size_t fb = filter_scratch_bytes(h.m, (int32_t)h.d);
+    if (fb > 0 && a.scratch) {
+        // the 16-bit filtered path keeps a round of kept keys beside its partial sums:
+        // allocated once per handle, on its first filtered update
+        if (!h.filter_scratch) {
+            CSK_HIP(hipStreamSynchronize(s));
+            if (hipMalloc(&h.filter_scratch, fb) != hipSuccess) {
+                h.filter_scratch = nullptr;
+                return fail(CS_ENOMEM, "filtered update buffer");
+            }
+            h.filter_scratch_bytes = fb;
+        }
+        a.scratch = h.filter_scratch;
+        a.scratch_bytes = h.filter_scratch_bytes;
+    }
     if (n_kept) {
         a.kept = h.kept_dev;
         st = zero_device_u64(h.kept_dev, s);

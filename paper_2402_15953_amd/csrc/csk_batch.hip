@@ -737,7 +737,9 @@ cs_status cs_tune_batch_update(cs_batch *b, const cs_update_item *items, int32_t
         for (int i : kv.second) c += (size_t)info[i].I.d * info[i].I.m;
         max_cells = std::max(max_cells, c);
     }
-    uint64_t *ref = nullptr, *tmp = nullptr;
+    uint64_t *ref = nullptr, *tmp = nullptr, *rep = nullptr;
+    // replicas of a class for timing: up to 64 copies, at most 1 GiB
+    const size_t rep_cells = std::max<size_t>(max_cells, std::min<size_t>(64 * max_cells, ((size_t)1 << 30) / 8));
     unsigned int *flag = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     BatchState T;
@@ -746,12 +748,14 @@ cs_status cs_tune_batch_update(cs_batch *b, const cs_update_item *items, int32_t
         (void)hipStreamSynchronize(s);
         if (ref) (void)hipFree(ref);
         if (tmp) (void)hipFree(tmp);
+        if (rep) (void)hipFree(rep);
         if (flag) (void)hipFree(flag);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
         if (T.tables) (void)hipFree(T.tables);
     };
     if (hipMalloc(&ref, max_cells * 8) != hipSuccess || hipMalloc(&tmp, max_cells * 8) != hipSuccess ||
+        hipMalloc(&rep, rep_cells * 8) != hipSuccess ||
         hipMalloc(&flag, sizeof(unsigned int)) != hipSuccess) {
         cleanup();
         return fail(CS_ENOMEM, "batch tuning buffers");
@@ -777,20 +781,27 @@ cs_status cs_tune_batch_update(cs_batch *b, const cs_update_item *items, int32_t
         float best_ms = -1.0f, rule_ms = -1.0f;
         int best_kind = 0, best_chunk = 16;
         for (int ci = 0; ci < n_cand && st == CS_OK; ++ci) {
+            // the class's items with this candidate's tasks, `copies` times over, copy c
+            // adding into dst + c * cells
+            auto build = [&](uint64_t *dst, int copies) {
+                std::vector<BItem> bi;
+                std::vector<BTask> bt;
+                std::vector<double> cost;
+                uint64_t na = 0, ns = 0;
+                for (int c = 0; c < copies; ++c)
+                    for (size_t j = 0; j < members.size(); ++j) {
+                        ItemInfo ii = info[members[j]];
+                        ii.I.sketch = dst + (size_t)c * cells + off[j];
+                        int kind = cands[ci][0], chunk = cands[ci][1];
+                        if (kind < 0) rule_choice(ii.I, &kind, &chunk);
+                        const int idx = (int)bi.size();
+                        bi.push_back(ii.I);
+                        add_tasks(idx, ii, kind, chunk, bt, cost, na, ns);
+                    }
+                return upload_tables(T, bi, bt, cost, s);
+            };
             uint64_t *dst = ci == 0 ? ref : tmp;
-            std::vector<BItem> bi;
-            std::vector<BTask> bt;
-            std::vector<double> cost;
-            uint64_t na = 0, ns = 0;
-            for (size_t j = 0; j < members.size(); ++j) {
-                ItemInfo ii = info[members[j]];
-                ii.I.sketch = dst + off[j];
-                int kind = cands[ci][0], chunk = cands[ci][1];
-                if (kind < 0) rule_choice(ii.I, &kind, &chunk);
-                bi.push_back(ii.I);
-                add_tasks((int)j, ii, kind, chunk, bt, cost, na, ns);
-            }
-            if ((st = upload_tables(T, bi, bt, cost, s)) != CS_OK) break;
+            if ((st = build(dst, 1)) != CS_OK) break;
             hipLaunchKernelGGL(k_batch_zero, dim3(zb), dim3(256), 0, s, dst, cells);
             if ((st = launch_batch(T, s)) != CS_OK) break;
             if (ci > 0) {
@@ -807,6 +818,14 @@ cs_status cs_tune_batch_update(cs_batch *b, const cs_update_item *items, int32_t
                     continue;
                 }
             }
+            // timed: median of three runs of enough copies of the class's work to fill the
+            // chip (its cost inside a large batch is its throughput, not the latency of a
+            // launch of it alone), each copy adding into its own counters (never into the
+            // reference, which later candidates are checked against)
+            const int copies = (int)std::max<int64_t>(
+                1, std::min<int64_t>({(2048 + T.n_tasks - 1) / std::max<int32_t>(1, T.n_tasks), 64,
+                                      (int64_t)(rep_cells / std::max<size_t>(1, cells))}));
+            if ((st = build(rep, copies)) != CS_OK) break;
             float t[3];
             bool ok = true;
             for (int r = 0; r < 3 && ok; ++r)
@@ -818,6 +837,7 @@ cs_status cs_tune_batch_update(cs_batch *b, const cs_update_item *items, int32_t
                 break;
             }
             std::sort(t, t + 3);
+            t[1] /= (float)copies;
             if (ci == 1) {
                 rule_ms = t[1];
                 continue;

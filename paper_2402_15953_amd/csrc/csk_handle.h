@@ -65,6 +65,8 @@ struct Handle {
     EstimateWork work;
     void *scratch = nullptr;           // partial sums of the LDS-segmented update
     size_t scratch_bytes = 0;
+    void *filter_scratch = nullptr;    // filtered 16-bit path: partial sums and a round of kept keys
+    size_t filter_scratch_bytes = 0;   //   (allocated by the first filtered update that needs it)
     void *result_host = nullptr;       // pinned host staging for results
     // two device words: [0] the kept tuples of a filtered update that asked for the
     // count, [1] the per-round count of the filtered 16-bit path (zero between updates)

@@ -179,6 +179,9 @@ struct PartGeom {
 };
 PartGeom part_geometry(uint32_t m, int32_t d, size_t scratch_bytes);
 size_t seg_scratch_bytes(uint32_t m, int32_t d);
+// Scratch of the filtered 16-bit path (2^15 < m <= 2^16; 0 elsewhere): a handle
+// allocates it on its first filtered update of that shape.
+size_t filter_scratch_bytes(uint32_t m, int32_t d);
 cs_status launch_update(const UpdateArgs &a, int strategy, int grid_blocks, hipStream_t s);
 // Sets a device word to zero with a one-thread kernel on s (no memset node, so it can be
 // captured into a graph).

@@ -1788,15 +1788,18 @@ size_t seg_scratch_bytes(uint32_t m, int32_t d)
         const uint64_t nblk = m > (1u << 16) ? kPartMaxChunk / kPartBlk : 16;
         best = std::max<size_t>(best, (size_t)nblk * part_bytes_per_block(d, ranges) + 512);
     }
+    return best;
+}
+
+size_t filter_scratch_bytes(uint32_t m, int32_t d)
+{
     // a filtered update with 16-bit counters (2^15 < m <= 2^16): the partial sums, then
     // the kept tuples' keys (and Deltas) in rounds of 2^23 tuples of two columns with
     // weights (16 bytes each), or 2^24 of two columns without
-    if (m > (1u << 15) && m <= (1u << 16)) {
-        const SegGeom g16 = seg16_geometry(m, d, (size_t)-1);
-        const size_t part = (size_t)g16.chunks * (size_t)d * m * 2;
-        best = std::max<size_t>(best, std::max<size_t>(2 * part, part + ((size_t)16 << 23)) + 1024);
-    }
-    return best;
+    if (m <= (1u << 15) || m > (1u << 16)) return 0;
+    const SegGeom g16 = seg16_geometry(m, d, (size_t)-1);
+    const size_t part = (size_t)g16.chunks * (size_t)d * m * 2;
+    return std::max<size_t>(2 * part, part + ((size_t)16 << 23)) + 1024;
 }
 
 int auto_update_strategy(uint32_t m, int32_t d, uint64_t n, int n_cols, bool unit, bool has_scratch, bool e1_pow2)
