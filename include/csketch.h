@@ -176,8 +176,12 @@ const char *cs_last_error(void);
 /* Stream n tuples of relation `rel` into its sketch (Alg. 2 for each repetition;
  * Eq. 2-4 define the counters it produces).
  * Calls on one handle must be ordered (one stream, or event dependencies).  The
- * segmented and partition strategies use the handle's own scratch buffer, allocated by
- * cs_create: the call allocates nothing and never waits on the host.
+ * segmented and partition strategies use the handle's own scratch buffer (partial sums,
+ * records), never another handle's: the first update that needs it allocates it, sized
+ * for that call (at most ~67 MB, depending on m, d, n and the weight kind), after
+ * waiting for `stream`; a later call that can use more grows it the same way; every
+ * other call allocates nothing and never waits on the host (cs_update_noalloc never
+ * allocates).
  *   keys:    device (or pinned / managed host) memory, uint32 [n][a_rel] tuple-major;
  *            column c is the c-th attribute of `rel` in ascending attribute id.
  *   weights: the same kinds of memory, int64 [n] frequency changes Delta (turnstile
@@ -185,7 +189,7 @@ const char *cs_last_error(void);
  * Asynchronous and ordered on `stream`.  n = 0 is a no-op.
  * Errors: CS_EINVAL (bad handle, rel out of range, keys NULL with n > 0, keys or weights
  * in memory the device cannot read, such as pageable host memory: checked on the host
- * before anything is enqueued). */
+ * before anything is enqueued), CS_ENOMEM (the scratch buffer). */
 cs_status cs_update(cs_sketch *h, int32_t rel, const uint32_t *keys, const int64_t *weights,
                     uint64_t n, void *stream);
 

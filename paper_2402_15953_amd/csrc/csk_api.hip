@@ -317,16 +317,9 @@ cs_status create_handle(const cs_graph *graph, uint32_t m, uint32_t d, uint64_t 
         return fail(CS_ENOMEM, "coefficient allocation failed");
     }
     // the update's scratch (partial sums, records) belongs to the handle: cs_update
-    // then neither allocates nor orders itself against other handles' updates
-    if (with_scratch) {
-        h.scratch_bytes = seg_scratch_bytes(m, (int32_t)d);
-        if (hipMalloc(&h.scratch, h.scratch_bytes) != hipSuccess) {
-            hipFree(h.counters);
-            hipFree(h.coef_dev);
-            delete hs;
-            return fail(CS_ENOMEM, "update scratch allocation failed");
-        }
-    }
+    // orders itself against no other handle's updates; it is allocated by the first
+    // update that needs it, sized for that update (and grown by a larger one)
+    h.own_scratch = with_scratch;
     if (hipMalloc(&h.kept_dev, 2 * sizeof(unsigned long long)) != hipSuccess ||
         hipMemset(h.kept_dev, 0, 2 * sizeof(unsigned long long)) != hipSuccess ||
         hipMemcpy(h.coef_dev, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice) != hipSuccess ||
@@ -392,6 +385,25 @@ cs_status cs_update_ex(cs_sketch *hs, int32_t rel, const uint32_t *keys, const i
 
 namespace csk {
 
+cs_status ensure_scratch(cs_sketch *hs, uint64_t n, const int64_t *weights, int32_t flags, hipStream_t s)
+{
+    Handle &h = hs->h;
+    if (!h.own_scratch || n == 0) return CS_OK;
+    const bool unit = weights == nullptr || (flags & CS_UPDATE_UNIT_WEIGHTS) != 0;
+    const size_t need = update_scratch_bytes(h.m, (int32_t)h.d, n, unit);
+    if (h.scratch_bytes >= need) return CS_OK;
+    CSK_HIP(hipStreamSynchronize(s));
+    if (h.scratch) (void)hipFree(h.scratch);
+    h.scratch = nullptr;
+    h.scratch_bytes = 0;
+    if (hipMalloc(&h.scratch, need) != hipSuccess) {
+        h.scratch = nullptr;
+        return fail(CS_ENOMEM, "update scratch allocation failed");
+    }
+    h.scratch_bytes = need;
+    return CS_OK;
+}
+
 cs_status update_args(cs_sketch *hs, int32_t rel, const uint32_t *keys, const int64_t *weights, uint64_t n,
                       int32_t flags, UpdateArgs *out)
 {
@@ -435,6 +447,9 @@ cs_status cs_update_timed(cs_sketch *hs, int32_t rel, const uint32_t *keys, cons
     UpdateArgs a;
     cs_status st = update_args(hs, rel, keys, weights, n, flags, &a);
     if (st != CS_OK || n == 0) return st;
+    if ((st = ensure_scratch(hs, n, weights, flags, static_cast<hipStream_t>(stream))) != CS_OK) return st;
+    a.scratch = hs->h.scratch;
+    a.scratch_bytes = hs->h.scratch_bytes;
     a.ev_start = static_cast<hipEvent_t>(ev_start);
     a.ev_stop = static_cast<hipEvent_t>(ev_stop);
     return launch_update(a, strategy, grid_blocks, static_cast<hipStream_t>(stream));
@@ -476,6 +491,9 @@ cs_status cs_update_filtered(cs_sketch *hs, int32_t rel, const uint32_t *keys, c
     UpdateArgs a;
     cs_status st = update_args(hs, rel, keys, weights, n, flags, &a);
     if (st != CS_OK) return st;
+    if ((st = ensure_scratch(hs, n, weights, flags, s)) != CS_OK) return st;
+    a.scratch = h.scratch;
+    a.scratch_bytes = h.scratch_bytes;
     a.filter = &f;
     a.attrs = attrs;
     a.n_attrs = n_attrs;

@@ -63,7 +63,8 @@ struct Handle {
     uint64_t *coef_dev = nullptr;      // per relation: [d][coef_per_rep], concatenated
     std::vector<size_t> coef_off;      // offset of relation k's table in coef_dev
     EstimateWork work;
-    void *scratch = nullptr;           // partial sums of the LDS-segmented update
+    bool own_scratch = false;          // the handle keeps its own update scratch (grown on demand)
+    void *scratch = nullptr;           // partial sums of the LDS-segmented update, partition records
     size_t scratch_bytes = 0;
     void *filter_scratch = nullptr;    // filtered 16-bit path: partial sums and a round of kept keys
     size_t filter_scratch_bytes = 0;   //   (allocated by the first filtered update that needs it)
@@ -87,6 +88,10 @@ namespace csk {
 // Handle creation; without scratch the handle serves batched and served updates only.
 cs_status create_handle(const cs_graph *graph, uint32_t m, uint32_t d, uint64_t seed, bool with_scratch,
                         cs_sketch **out);
+// Grows the handle's own update scratch to what an update of n tuples can use (waiting
+// for `s` before freeing the old buffer; calls on one handle are ordered by their
+// stream); handles without their own scratch are left alone.
+cs_status ensure_scratch(cs_sketch *hs, uint64_t n, const int64_t *weights, int32_t flags, hipStream_t s);
 // Checks the arguments of an update of relation rel and fills the launcher's arguments
 // (keys, weights, coefficients, counters, the handle's scratch, flags).
 cs_status update_args(cs_sketch *hs, int32_t rel, const uint32_t *keys, const int64_t *weights, uint64_t n,

@@ -179,6 +179,9 @@ struct PartGeom {
 };
 PartGeom part_geometry(uint32_t m, int32_t d, size_t scratch_bytes);
 size_t seg_scratch_bytes(uint32_t m, int32_t d);
+// What the update strategies can use for one call of n tuples (unit: Deltas +-1), no
+// more than seg_scratch_bytes.
+size_t update_scratch_bytes(uint32_t m, int32_t d, uint64_t n, bool unit);
 // Scratch of the filtered 16-bit path (2^15 < m <= 2^16; 0 elsewhere): a handle
 // allocates it on its first filtered update of that shape.
 size_t filter_scratch_bytes(uint32_t m, int32_t d);

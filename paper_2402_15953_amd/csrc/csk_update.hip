@@ -1791,6 +1791,25 @@ size_t seg_scratch_bytes(uint32_t m, int32_t d)
     return best;
 }
 
+size_t update_scratch_bytes(uint32_t m, int32_t d, uint64_t n, bool unit)
+{
+    const uint64_t cells = (uint64_t)d * m;
+    const bool narrow = unit && n < (1ull << 31);
+    const SegGeom g = seg_geometry(m, d, narrow, (size_t)-1, n);
+    size_t best = (size_t)g.chunks * cells * (narrow ? 4 : 8);
+    if (unit) {
+        const SegGeom g16 = seg16_geometry(m, d, (size_t)-1, n);
+        best = std::max<size_t>(best, (size_t)g16.chunks * cells * 2);
+        // partition: the blocks of one chunk of this input (up to kPartMaxChunk tuples
+        // where it is the automatic choice, 16 blocks below 2^16 buckets)
+        const int32_t ranges = (int32_t)(((uint64_t)m + kPartR - 1) >> kPartLog2R);
+        const uint64_t cap = m > (1u << 16) ? kPartMaxChunk / kPartBlk : 16;
+        const uint64_t nblk = std::min<uint64_t>(cap, n / kPartBlk + (n % kPartBlk != 0));
+        best = std::max<size_t>(best, (size_t)nblk * part_bytes_per_block(d, ranges) + 512);
+    }
+    return best;
+}
+
 size_t filter_scratch_bytes(uint32_t m, int32_t d)
 {
     // a filtered update with 16-bit counters (2^15 < m <= 2^16): the partial sums, then
