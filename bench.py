@@ -507,7 +507,7 @@ def main():
         torch.cuda.empty_cache()
     if "serving" in sections and args.serve_queries > 0:
         out["serving"] = bench_serving(args.serve_queries, dev, args.serve_seconds,
-                                       [float(x) for x in args.serve_rates.split(",") if x])
+                                       [float(x) for x in args.serve_rates.split(",") if x], stream)
         torch.cuda.empty_cache()
     if "cpu" in sections and host0 is not None:
         out["cpu_baseline"] = cpu_baseline(host0)
@@ -876,7 +876,7 @@ def bench_batched(n_queries, dev, stream):
                       "identical_estimates": est_tuned == est_plain}}
 
 
-def bench_serving(n_queries, dev, seconds, rates):
+def bench_serving(n_queries, dev, seconds, rates, stream):
     """Live chain/star queries (m = 2^14..2^18, d = 9), Poisson arrivals of turnstile update
     batches (2^U[10,18] tuples, 10% deletes of earlier batches, weights +-1) and estimate
     requests at 1 estimate per 4 update batches; latency per request = completion - arrival."""
@@ -906,6 +906,13 @@ def bench_serving(n_queries, dev, seconds, rates):
         srv.submit_update(qids[qi], 0, pools[qi][0][:1024], minus[:1024], unit_weights=True)
     srv.drain()
     srv.poll(1 << 20)
+    plain_sks = [csk.Sketch(sp.graph, sp.m, sp.d, sp.sketch_seed) for sp in specs]
+    with torch.cuda.stream(stream):
+        for qi, sp in enumerate(specs):  # the same warm-up as the served queries
+            plain_sks[qi].update(0, pools[qi][0][:1024], ones[:1024], stream=stream, unit_weights=True)
+            plain_sks[qi].estimate(stream=stream)
+            plain_sks[qi].update(0, pools[qi][0][:1024], minus[:1024], stream=stream, unit_weights=True)
+    torch.cuda.synchronize()
     levels = []
     rng = random.Random(9)
     inserted = {}
@@ -938,7 +945,8 @@ def bench_serving(n_queries, dev, seconds, rates):
         t0 = time.perf_counter()
         tuples = 0
         busy = 0
-        for (ta, kind, q, k, off, ln, sign) in plan:
+        est_ticket = {}
+        for ri, (ta, kind, q, k, off, ln, sign) in enumerate(plan):
             while time.perf_counter() - t0 < ta:
                 pass
             try:
@@ -947,7 +955,7 @@ def bench_serving(n_queries, dev, seconds, rates):
                                       (ones if sign > 0 else minus)[off:off + ln], unit_weights=True)
                     tuples += ln
                 else:
-                    srv.submit_estimate(qids[q])
+                    est_ticket[srv.submit_estimate(qids[q])] = ri
             except csk.CsError:
                 busy += 1
         srv.drain()
@@ -956,24 +964,75 @@ def bench_serving(n_queries, dev, seconds, rates):
         lat_u = np.array([c["done_us"] - c["submit_us"] for c in comps if c["kind"] == 0]) / 1e3
         lat_e = np.array([c["done_us"] - c["submit_us"] for c in comps if c["kind"] == 1]) / 1e3
         n_e = int(len(lat_e))
+        served_est = {est_ticket[c["ticket"]]: c["estimate"]["value"] for c in comps
+                      if c["kind"] == 1 and c["ticket"] in est_ticket}
 
         def pct(a, p):
             return float(np.percentile(a, p)) if len(a) else None
 
         progress("serving window at %g batches/s done%s" % (rate, " (warm-up)" if li == 0 else ""))
+        # the plain per-query path on the same trace: one handle per query (same seeds,
+        # so the same hash functions), each request issued at its arrival time in order,
+        # updates asynchronous on one stream, estimates synchronous (cs_estimate)
+        plain_lv = replay_plain(plan, plain_sks, pools, ones, minus, stream)
+        same = all(plain_lv["estimates"].get(ri) == v for ri, v in served_est.items())
+        progress("plain window at %g batches/s done" % rate)
         if li == 0:
             continue
         levels.append({"offered_update_batches_per_s": rate, "offered_estimates_per_s": rate / 4,
                        "seconds": wall, "tuples_per_s": tuples / wall, "estimates_per_s": n_e / wall,
                        "update_p50_ms": pct(lat_u, 50), "update_p99_ms": pct(lat_u, 99),
                        "estimate_p50_ms": pct(lat_e, 50), "estimate_p99_ms": pct(lat_e, 99),
-                       "requests": len(comps), "refused": busy})
+                       "requests": len(comps), "refused": busy,
+                       "plain": {k: v for k, v in plain_lv.items() if k != "estimates"},
+                       "identical_estimates": bool(same and len(served_est) == n_e)})
     st = srv.stats()
     srv.close()
+    for sk_ in plain_sks:
+        sk_.close()
     return {"workload": f"{n_queries} live chain/star queries, m=2^14..2^18, d=9, Zipf(1.1) over 1e6, "
                         "update batches 2^U[10,18] tuples, 10% deletes, estimate:update = 1:4, Poisson arrivals",
             "resident_counter_bytes": int(st["used_bytes"]), "levels": levels,
             "update_launches": int(st["update_launches"]), "estimate_batches": int(st["estimate_batches"])}
+
+
+def replay_plain(plan, sks, pools, ones, minus, stream):
+    """One serving window on the plain per-query path: requests in arrival order, each
+    issued no earlier than its arrival; an update's completion is a timing event recorded
+    behind it on the stream, an estimate's the return of the synchronous cs_estimate."""
+    import numpy as np
+    import torch
+    t0 = time.perf_counter()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    lat_u, lat_e, ev_u, ests = [], [], [], {}
+    tuples = 0
+    with torch.cuda.stream(stream):
+        for ri, (ta, kind, q, k, off, ln, sign) in enumerate(plan):
+            while time.perf_counter() - t0 < ta:
+                pass
+            if kind == "U":
+                sks[q].update(k, pools[q][k][off:off + ln], (ones if sign > 0 else minus)[off:off + ln],
+                              stream=stream, unit_weights=True)
+                ev = torch.cuda.Event(enable_timing=True)
+                ev.record(stream)
+                ev_u.append((ta, ev))
+                tuples += ln
+            else:
+                e = sks[q].estimate(stream=stream)
+                lat_e.append((time.perf_counter() - t0 - ta) * 1e3)
+                ests[ri] = e["value"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for ta, ev in ev_u:
+        lat_u.append(ev0.elapsed_time(ev) - ta * 1e3)
+
+    def pct(a, p):
+        return float(np.percentile(np.array(a), p)) if len(a) else None
+
+    return {"seconds": wall, "tuples_per_s": tuples / wall, "estimates_per_s": len(lat_e) / wall,
+            "update_p50_ms": pct(lat_u, 50), "update_p99_ms": pct(lat_u, 99),
+            "estimate_p50_ms": pct(lat_e, 50), "estimate_p99_ms": pct(lat_e, 99), "estimates": ests}
 
 
 def cpu_baseline(host_keys):

@@ -1139,46 +1139,57 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
         if (lane == 0) s_ccnt[wave][ci] = cnt;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (wave == 0) {
         // candidates by total count over the 1024 sampled tuples, distinct keys, at
-        // least 16 hits (1/64), at most kPartHot of them
-        uint32_t tot[kCand];
+        // least 16 hits (1/64), the kPartHot hottest (ties: lower candidate index); lane
+        // ci < kCand holds candidate ci.  A candidate enters the direct-mapped table
+        // unless a hotter elected one has the same entry (it stays an ordinary tuple);
+        // entries are numbered in hotness order.
+        const int ci = lane < kCand ? lane : 0;
+        uint32_t kc[NC];
 #pragma unroll
-        for (int ci = 0; ci < kCand; ++ci) {
-            uint32_t v = 0;
-            for (int w = 0; w < kPB / 64; ++w) v += s_ccnt[w][ci];
+        for (int c = 0; c < NC; ++c) kc[c] = s_cand[ci][c];
+        uint32_t v = 0;
+        for (int w = 0; w < kPB / 64; ++w) v += s_ccnt[w][ci];
+        for (int cj = 0; cj < ci; ++cj) {
+            bool same = true;
 #pragma unroll
-            for (int cj = 0; cj < ci; ++cj) {
-                bool same = true;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) same = same && s_cand[cj][c] == s_cand[ci][c];
-                v = same ? 0u : v;
-            }
-            tot[ci] = v;
+            for (int c = 0; c < NC; ++c) same = same && s_cand[cj][c] == kc[c];
+            v = same ? 0u : v;
         }
-        int nh = 0;
-        for (int k = 0; k < kPartHot; ++k) {
-            uint32_t bv = 15u, bi = kCand;
+        if (lane >= kCand) v = 0;
+        int rank = 0;
 #pragma unroll
-            for (int ci = 0; ci < kCand; ++ci) {
-                const bool better = tot[ci] > bv;
-                bv = better ? tot[ci] : bv;
-                bi = better ? (uint32_t)ci : bi;
-            }
-            if (bi == (uint32_t)kCand) break;
-#pragma unroll
-            for (int ci = 0; ci < kCand; ++ci) tot[ci] = (uint32_t)ci == bi ? 0u : tot[ci];
-            uint32_t kc[NC];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) kc[c] = s_cand[bi][c];
-            uint4 &slot = s_htab[part_hot_slot<NC>(kc)];
-            if (slot.z != kPartNone) continue;  // entry taken by a hotter tuple
-            slot = make_uint4(kc[0], kc[NC - 1], (uint32_t)nh, 0u);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) s_hot[nh][c] = kc[c];
-            ++nh;
+        for (int cj = 0; cj < kCand; ++cj) {
+            const uint32_t vj = __shfl(v, cj, 64);
+            rank += (vj > v || (vj == v && cj < ci)) ? 1 : 0;
         }
-        s_nh = nh;
+        const bool elig = lane < kCand && rank < kPartHot && v >= 16u;
+        const uint32_t slot = part_hot_slot<NC>(kc);
+        bool blocked = false;
+        int idx = 0;
+#pragma unroll
+        for (int cj = 0; cj < kCand; ++cj) {
+            const int rj = __shfl(rank, cj, 64);
+            const bool ej = __shfl((int)elig, cj, 64) != 0;
+            const uint32_t sj = __shfl(slot, cj, 64);
+            blocked = blocked || (ej && rj < rank && sj == slot);
+        }
+        const bool ins = elig && !blocked;
+        // entry number: the inserted candidates of lower rank
+#pragma unroll
+        for (int cj = 0; cj < kCand; ++cj) {
+            const int rj = __shfl(rank, cj, 64);
+            const bool ij = __shfl((int)ins, cj, 64) != 0;
+            idx += (ij && rj < rank) ? 1 : 0;
+        }
+        if (ins) {
+            s_htab[slot] = make_uint4(kc[0], kc[NC - 1], (uint32_t)idx, 0u);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) s_hot[idx][c] = kc[c];
+        }
+        const uint64_t bal = __ballot(ins);
+        if (lane == 0) s_nh = (int32_t)__popcll(bal);
     }
     __syncthreads();
     const int nh = s_nh;
