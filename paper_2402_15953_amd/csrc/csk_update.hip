@@ -1017,7 +1017,7 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
     static_assert(NC == 1 || NC == 2, "one- and two-column relations");
     __shared__ __align__(16) uint32_t s_hist[kPB / 64][64 * kPartHS];
     __shared__ uint32_t s_tot[kPB / 64][64];
-    __shared__ __align__(16) uint16_t s_stage[kPartBlkCap];
+    __shared__ __align__(16) uint16_t s_stage[kPartBlkCap + 64];  // + one sink entry per lane
     const SegTile wg = seg_tile();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint64_t blk = wg.chunk;
@@ -1303,12 +1303,19 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
             for (uint32_t e = start + rtot; e < start + padded; ++e) s_stage[e] = kPartPad;
         }
         wave_sync();
+        // placement, eight slots at a time: their run bases are read before any of
+        // their records is written (a slot without a record reads entry 0 and writes its
+        // lane's sink entry, never stored)
 #pragma unroll
-        for (int s = 0; s < kPartSlots; ++s) {
-            if (P[s] != kPartNone) {
-                const uint32_t r = (P[s] >> 15) & 63u;
-                s_stage[hist[r * kPartHS + sub] + (P[s] >> 21)] = (uint16_t)(P[s] & 0x7FFFu);
-            }
+        for (int s0 = 0; s0 < kPartSlots; s0 += 8) {
+            uint32_t at[8];
+#pragma unroll
+            for (int s = 0; s < 8; ++s)
+                at[s] = hist[P[s0 + s] != kPartNone ? ((P[s0 + s] >> 15) & 63u) * kPartHS + sub : 0u];
+#pragma unroll
+            for (int s = 0; s < 8; ++s)
+                s_stage[P[s0 + s] != kPartNone ? at[s] + (P[s0 + s] >> 21) : (uint32_t)kPartBlkCap + lane] =
+                    (uint16_t)(P[s0 + s] & 0x7FFFu);
         }
         __syncthreads();
         uint4 *dst = reinterpret_cast<uint4 *>(rec_out + ((uint64_t)t * nblk + blk) * kPartBlkCap);
