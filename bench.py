@@ -1002,9 +1002,12 @@ def replay_plain(plan, sks, pools, ones, minus, stream):
     behind it on the stream, an estimate's the return of the synchronous cs_estimate."""
     import numpy as np
     import torch
-    t0 = time.perf_counter()
+    # the reference event completes before the window's clock starts, so the device
+    # times of later events measured from it are never earlier than the host's
     ev0 = torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
+    ev0.synchronize()
+    t0 = time.perf_counter()
     lat_u, lat_e, ev_u, ests = [], [], [], {}
     tuples = 0
     with torch.cuda.stream(stream):
