@@ -204,7 +204,7 @@ cs_status cs_update_ex(cs_sketch *h, int32_t rel, const uint32_t *keys, const in
 /* cs_update_ex that also records two caller-created hipEvent_t on `stream`: ev_start just
  * before the update's hashing kernel and ev_stop just after it (the segmented strategy's
  * reduction of partial sums and the partition strategy's accumulation pass fall outside;
- * a partition update of more than 2^21 tuples runs in chunks, and then both passes of
+ * a partition update of more than 2^23 tuples runs in chunks, and then both passes of
  * every chunk fall inside).  Either event may be NULL.  Per-kernel timing for monitoring
  * and tuning; the counters are the same as cs_update's.  Errors as cs_update_ex, and
  * CS_EDEVICE if an event cannot be recorded. */

@@ -160,7 +160,7 @@ struct SegGeom {
 SegGeom seg_geometry(uint32_t m, int32_t d, bool narrow, size_t scratch_bytes, uint64_t n = ~0ull);
 SegGeom seg16_geometry(uint32_t m, int32_t d, size_t scratch_bytes, uint64_t n = ~0ull);
 constexpr int kMaxPartRanges = 64;           // bucket ranges of 2^14 per repetition (m <= 2^20)
-constexpr uint64_t kPartMaxChunk = 1ull << 21;  // tuples per pass pair
+constexpr uint64_t kPartMaxChunk = 1ull << 23;  // tuples per pass pair (2048 blocks: pass 2 keeps a run word per block in LDS)
 // One block's hot tuples for the partition strategy (see k_part_hash): up to eight
 // tuples (keys; column 1 unused for one-column relations) and their Delta sums.
 constexpr int kPartHot = 8;

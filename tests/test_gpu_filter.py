@@ -28,7 +28,7 @@ CASES = [
     (W.star(4), 100_001, 1 << 14, 5, "big", [(0, 2 ** 30, 3 * 2 ** 30), (1, 0, 7), (2, 5, 5)]),  # atomics
     (W.single_join(), 5_000, 1024, 3, None, [(1, 9, 8)]),            # keeps nothing
     (W.chain(3), 3_000_000, 1 << 16, 9, None, [(1, 0, 9)]),           # keeps everything
-    (W.chain(5), (1 << 21) + 777, 1 << 18, 7, "pm1", [(1, 0, 2)]),   # partition, 30%, two chunks
+    (W.chain(3), (1 << 23) + 777, 1 << 18, 7, "pm1", [(1, 0, 2)]),   # partition, 30%, two chunks
     (W.chain(3), 300_001, 1 << 20, 3, None, [(2, 1, 1), (1, 0, 8)]), # partition, one column kept in 8
     (W.multiway_star(3), 80_000, 1 << 17, 5, None, [(1, 0, 4)]),     # a column in two joins: atomics
     (W.chain(3), 90_000, 100_003, 5, "pm1", [(0, 0, 2 ** 30)]),      # m not a power of two: atomics

@@ -51,8 +51,8 @@ CASES = [
     (W.chain(3), 1, 1 << 17, 3, 1.1, 10 ** 6, None, 0),
     (W.chain(3), 1023, 1 << 20, 3, 1.1, 10 ** 6, None, 0),
     (W.chain(3), 1025, 1 << 19, 3, 1.1, 10 ** 6, "pm1", 3),
-    (W.chain(3), (1 << 21) + 4097, 1 << 18, 3, 1.2, 10 ** 6, None, 0),
-    (W.chain(3), (1 << 21) + 4097, 1 << 18, 3, 1.2, 10 ** 6, None, 1),
+    (W.chain(3), (1 << 23) + 4097, 1 << 18, 3, 1.2, 10 ** 6, None, 0),
+    (W.chain(3), (1 << 23) + 4097, 1 << 18, 3, 1.2, 10 ** 6, None, 1),
     (W.chain(3), 150_000, 300_007, 5, 1.1, 10 ** 6, "pm1", 0),
     (W.multiway_star(3), 100_000, 1 << 18, 3, 1.3, 1000, None, 0),
     (W.star(3), 100_000, 1 << 16, 5, 1.1, 10 ** 5, None, 0),
