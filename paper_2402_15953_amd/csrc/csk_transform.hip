@@ -32,6 +32,14 @@ namespace {
 // blocks of 4096 (96 KB, one per CU), so its passes fill the chip.
 constexpr int kSingleTile = 4096;
 
+// LDS position of tile element i: one padding word after every 32, so that the
+// bit-reversed loads (whose first 64 positions are multiples of the tile length / 64)
+// and the butterflies at small strides spread over the banks instead of meeting on a
+// few of them.
+__device__ __forceinline__ int lp(int i) { return i + (i >> 5); }
+template <int TILE>
+constexpr int lds_len() { return TILE + TILE / 32; }
+
 __device__ __forceinline__ uint32_t bitrev(uint32_t x, int bits)
 {
     return bits ? (__brev(x) >> (32 - bits)) : 0u;
@@ -46,7 +54,7 @@ __device__ __forceinline__ void load_stage_twiddles(T *stw, int log2L, const T *
 }
 
 // Radix-2 DIT stages on C interleaved transforms of length 2^log2L held in LDS as
-// s[n * C + c] (bit-reversed input, natural output); stw from load_stage_twiddles.
+// s[lp(n * C + c)] (bit-reversed input, natural output); stw from load_stage_twiddles.
 // Stages go in pairs: a thread takes the four elements two consecutive stages combine,
 // applies both stages' radix-2 butterflies in registers (the same operations as two
 // separate stages, so the same rounding), and writes them back once.
@@ -66,7 +74,7 @@ __device__ __forceinline__ void lds_stages(typename Ring::T *s, int log2L, int l
             const int k = bb & (half - 1);
             const int i0 = ((bb >> lh) << (lh + 2)) + k;
             const int i1 = i0 + half, i2 = i0 + 2 * half, i3 = i0 + 3 * half;
-            const T x0 = s[i0 * C + c], x1 = s[i1 * C + c], x2 = s[i2 * C + c], x3 = s[i3 * C + c];
+            const T x0 = s[lp(i0 * C + c)], x1 = s[lp(i1 * C + c)], x2 = s[lp(i2 * C + c)], x3 = s[lp(i3 * C + c)];
             // stage lh: pairs (i0, i1) and (i2, i3), twiddle w_{2 half}^k
             const T w1 = stw[k << (log2L - lh - 1)];
             T v = R.mul(x1, w1);
@@ -77,11 +85,11 @@ __device__ __forceinline__ void lds_stages(typename Ring::T *s, int log2L, int l
             const T w2 = stw[k << (log2L - lh - 2)];
             const T w3 = stw[(k + half) << (log2L - lh - 2)];
             v = R.mul(y2, w2);
-            s[i0 * C + c] = R.add(y0, v);
-            s[i2 * C + c] = R.sub(y0, v);
+            s[lp(i0 * C + c)] = R.add(y0, v);
+            s[lp(i2 * C + c)] = R.sub(y0, v);
             v = R.mul(y3, w3);
-            s[i1 * C + c] = R.add(y1, v);
-            s[i3 * C + c] = R.sub(y1, v);
+            s[lp(i1 * C + c)] = R.add(y1, v);
+            s[lp(i3 * C + c)] = R.sub(y1, v);
         }
         __syncthreads();
     }
@@ -94,10 +102,10 @@ __device__ __forceinline__ void lds_stages(typename Ring::T *s, int log2L, int l
             const int k = bb & (half - 1);
             const int i0 = ((bb >> lh) << (lh + 1)) + k;
             const int i1 = i0 + half;
-            const typename Ring::T u = s[i0 * C + c];
-            const typename Ring::T v = R.mul(s[i1 * C + c], stw[k << (log2L - lh - 1)]);
-            s[i0 * C + c] = R.add(u, v);
-            s[i1 * C + c] = R.sub(u, v);
+            const typename Ring::T u = s[lp(i0 * C + c)];
+            const typename Ring::T v = R.mul(s[lp(i1 * C + c)], stw[k << (log2L - lh - 1)]);
+            s[lp(i0 * C + c)] = R.add(u, v);
+            s[lp(i1 * C + c)] = R.sub(u, v);
         }
         __syncthreads();
     }
@@ -117,7 +125,7 @@ __global__ __launch_bounds__(TILE / 4) void k_fft_f64(F64Src src, double2 *buf, 
                                                      const double2 *__restrict__ tw, int log2T)
 {
     constexpr int NT = TILE / 4;
-    __shared__ double2 s[TILE];
+    __shared__ double2 s[lds_len<TILE>()];
     __shared__ double2 stw[TILE / 2];
     const int v = blockIdx.x;
     const int blk = blockIdx.y;
@@ -133,14 +141,14 @@ __global__ __launch_bounds__(TILE / 4) void k_fft_f64(F64Src src, double2 *buf, 
         for (int idx = threadIdx.x; idx < total; idx += NT) {
             const int n = idx >> g.log2C, c = idx & (C - 1);
             const int64_t pos = base + (int64_t)c * g.col_stride + (int64_t)n * g.elem_stride;
-            s[(bitrev(n, g.log2L) << g.log2C) + c] =
+            s[lp((bitrev(n, g.log2L) << g.log2C) + c)] =
                 make_double2((double)re[pos], im ? (double)im[pos] : 0.0);
         }
     } else {
         for (int idx = threadIdx.x; idx < total; idx += NT) {
             const int n = idx >> g.log2C, c = idx & (C - 1);
             const int64_t pos = base + (int64_t)c * g.col_stride + (int64_t)n * g.elem_stride;
-            s[(bitrev(n, g.log2L) << g.log2C) + c] = vec[pos];
+            s[lp((bitrev(n, g.log2L) << g.log2C) + c)] = vec[pos];
         }
     }
     load_stage_twiddles<NT>(stw, g.log2L, tw, log2T);
@@ -150,7 +158,7 @@ __global__ __launch_bounds__(TILE / 4) void k_fft_f64(F64Src src, double2 *buf, 
     for (int idx = threadIdx.x; idx < total; idx += NT) {
         const int n = idx >> g.log2C, c = idx & (C - 1);
         const int64_t pos = base + (int64_t)c * g.col_stride + (int64_t)n * g.elem_stride;
-        double2 val = s[(n << g.log2C) + c];
+        double2 val = s[lp((n << g.log2C) + c)];
         if (g.twiddle) {
             const int64_t colid = (int64_t)blk * C + c;
             const int64_t e = ((int64_t)n * colid) & (m - 1);
@@ -172,7 +180,7 @@ __global__ __launch_bounds__(NT) void k_ntt(ModSrc src, uint32_t *buf, PassGeom 
                                            const uint32_t *__restrict__ roots, int log2T, int inverse,
                                            const int32_t *__restrict__ rep_of, const int32_t *__restrict__ kp)
 {
-    __shared__ uint32_t s[TILE];
+    __shared__ uint32_t s[lds_len<TILE>()];
     __shared__ uint32_t stw[TILE / 2];
     const int v = blockIdx.x;
     const int pi = v / vec_per_prime;
@@ -192,13 +200,13 @@ __global__ __launch_bounds__(NT) void k_ntt(ModSrc src, uint32_t *buf, PassGeom 
         for (int idx = threadIdx.x; idx < total; idx += NT) {
             const int n = idx >> g.log2C, c = idx & (C - 1);
             const int64_t pos = base + (int64_t)c * g.col_stride + (int64_t)n * g.elem_stride;
-            s[(bitrev(n, g.log2L) << g.log2C) + c] = mont_from_i64(R, in[pos], P.r2, P.r3, P.neg2_64);
+            s[lp((bitrev(n, g.log2L) << g.log2C) + c)] = mont_from_i64(R, in[pos], P.r2, P.r3, P.neg2_64);
         }
     } else {
         for (int idx = threadIdx.x; idx < total; idx += NT) {
             const int n = idx >> g.log2C, c = idx & (C - 1);
             const int64_t pos = base + (int64_t)c * g.col_stride + (int64_t)n * g.elem_stride;
-            s[(bitrev(n, g.log2L) << g.log2C) + c] = vec[pos];
+            s[lp((bitrev(n, g.log2L) << g.log2C) + c)] = vec[pos];
         }
     }
     load_stage_twiddles<NT>(stw, g.log2L, tw, log2T);
@@ -207,7 +215,7 @@ __global__ __launch_bounds__(NT) void k_ntt(ModSrc src, uint32_t *buf, PassGeom 
     for (int idx = threadIdx.x; idx < total; idx += NT) {
         const int n = idx >> g.log2C, c = idx & (C - 1);
         const int64_t pos = base + (int64_t)c * g.col_stride + (int64_t)n * g.elem_stride;
-        uint32_t val = s[(n << g.log2C) + c];
+        uint32_t val = s[lp((n << g.log2C) + c)];
         if (g.twiddle) {
             const int64_t colid = (int64_t)blk * C + c;
             const int64_t e = ((int64_t)n * colid) & (m - 1);
