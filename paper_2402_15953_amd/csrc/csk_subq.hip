@@ -456,7 +456,6 @@ cs_status cs_subq_create(const cs_graph *graph, const uint32_t *sub_joins, int32
     h.m = m;
     h.d = d;
     h.seed = seed;
-    if (hipGetDevice(&h.device) != hipSuccess) return bail(fail(CS_EDEVICE, "no HIP device"));
     // hash functions: per repetition and component a shared sign polynomial and a bin
     // polynomial; then per repetition and join its own sign polynomial
     h.comp_sign.resize((size_t)d * Q * 4);
@@ -520,7 +519,6 @@ cs_status cs_subq_create(const cs_graph *graph, const uint32_t *sub_joins, int32
         Handle &V = S.view;
         st = analyze_graph(&lg, &V.g);
         if (st != CS_OK) return bail(st);
-        V.device = h.device;
         V.m = m;
         V.log2m = 31 - __builtin_clz(m);
         V.pow2 = (m & (m - 1)) == 0;
@@ -561,6 +559,7 @@ cs_status cs_subq_create(const cs_graph *graph, const uint32_t *sub_joins, int32
         }
     }
     // per relation: its sign evaluations, target masks and coefficient table
+    std::vector<std::vector<uint64_t>> tabs(r);
     for (int k = 0; k < r; ++k) {
         SqRel &R = h.rel[k];
         if ((int)R.targets.size() > kSqMaxTargets)
@@ -602,9 +601,18 @@ cs_status cs_subq_create(const cs_graph *graph, const uint32_t *sub_joins, int32
                 for (int i = 0; i < 4; ++i) o[2 * R.a + 4 * e + i] = src[i];
             }
         }
-        if (hipMalloc(&R.coef_dev, tab.size() * sizeof(uint64_t)) != hipSuccess)
+        tabs[k] = std::move(tab);
+    }
+    // the plan is complete and valid (checked on the host): from here on the device
+    if (hipGetDevice(&h.device) != hipSuccess) return bail(fail(CS_EDEVICE, "no HIP device"));
+    for (SqQuery &S : h.sub) S.view.device = h.device;
+    for (int k = 0; k < r; ++k) {
+        SqRel &R = h.rel[k];
+        if (tabs[k].empty()) continue;
+        if (hipMalloc(&R.coef_dev, tabs[k].size() * sizeof(uint64_t)) != hipSuccess)
             return bail(fail(CS_ENOMEM, "sub-query coefficients"));
-        if (hipMemcpy(R.coef_dev, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice) != hipSuccess)
+        if (hipMemcpy(R.coef_dev, tabs[k].data(), tabs[k].size() * sizeof(uint64_t), hipMemcpyHostToDevice) !=
+            hipSuccess)
             return bail(fail(CS_EDEVICE, "sub-query coefficient upload"));
     }
     // counters and the pass-1 scratch of one chunk

@@ -139,3 +139,24 @@ def test_tune_table_batch_and_split_entries(tmp_path):
             csk.tune_load(str(bad))
     assert csk.tune_count() == 4
     csk.tune_clear()
+
+
+def test_subquery_masks_validated_on_the_host():
+    """cs_subq_create checks every sub-query (non-empty, joins of the graph, connected)
+    and the per-relation limits before any device work: CS_EINVAL here without a GPU."""
+    import paper_2402_15953_amd as csk
+    import workloads as W
+    L = csk.lib()
+
+    def create(graph, masks):
+        arr = (ctypes.c_uint32 * len(masks))(*masks)
+        h = ctypes.c_void_p()
+        st = L.cs_subq_create(ctypes.byref(csk._graph_struct(graph)), arr, len(masks), 1024, 2, 1, ctypes.byref(h))
+        if h.value:
+            L.cs_subq_destroy(h)
+        return st
+
+    for graph, masks in ((W.chain(4), [0b101]), (W.chain(4), [0]), (W.chain(4), [0b1000]),
+                         (W.star(6), W.connected_subqueries(W.star(6)))):
+        assert create(graph, masks) == csk.CS_EINVAL, (graph.name, masks)
+    assert create(W.chain(5), W.connected_subqueries(W.chain(5))) in (csk.CS_OK, csk.CS_EDEVICE)
