@@ -33,8 +33,8 @@ struct RingM {
     {
         const uint64_t t = (uint64_t)a * w;
         const uint32_t q = (uint32_t)t * pinv_neg;
-        const uint32_t u = (uint32_t)((t + (uint64_t)q * p) >> 32);
-        return u >= p ? u - p : u;
+        const uint32_t u = (uint32_t)((t + (uint64_t)q * p) >> 32);  // < 2p
+        return min(u, u - p);  // u - p wraps above u when u < p
     }
 };
 

@@ -58,54 +58,62 @@ __device__ __forceinline__ void load_stage_twiddles(T *stw, int log2L, const T *
 // Stages go in pairs: a thread takes the four elements two consecutive stages combine,
 // applies both stages' radix-2 butterflies in registers (the same operations as two
 // separate stages, so the same rounding), and writes them back once.
+//
+// Addressing: with D = half * C the tile distance between a group's elements, group b
+// starts at idx0 = ((b >> log2 D) << (log2 D + 2)) + (b & (D - 1)), and its block of 4D
+// tile positions starts at a multiple of 4D.  A power-of-two block of at most 32
+// positions then lies inside one 32-position stretch, and larger ones start on one, so
+// element j sits jD + (jD >> 5) padded positions after element 0 for every group: one
+// padded address per group, the other three at offsets uniform over the stage.
 template <int NT, class Ring>
 __device__ __forceinline__ void lds_stages(typename Ring::T *s, int log2L, int log2C, const Ring &R,
                                            const typename Ring::T *stw)
 {
     using T = typename Ring::T;
-    const int C = 1 << log2C;
     int lh = 0;
     for (; lh + 1 < log2L; lh += 2) {
-        const int half = 1 << lh;
+        const int sD = lh + log2C;
+        const int D = 1 << sD;
+        const int o1 = D + (D >> 5), o2 = 2 * D + ((2 * D) >> 5), o3 = 3 * D + ((3 * D) >> 5);
+        const int sh2 = log2L - lh - 2;           // twiddle index shift of the second stage
+        const int quarter = 1 << (log2L - 2);     // (k + half) << sh2 = (k << sh2) + quarter
+        const int kmask = (1 << lh) - 1;
         const int ngr = (1 << (log2L - 2)) << log2C;
         for (int b = threadIdx.x; b < ngr; b += NT) {
-            const int c = b & (C - 1);
-            const int bb = b >> log2C;
-            const int k = bb & (half - 1);
-            const int i0 = ((bb >> lh) << (lh + 2)) + k;
-            const int i1 = i0 + half, i2 = i0 + 2 * half, i3 = i0 + 3 * half;
-            const T x0 = s[lp(i0 * C + c)], x1 = s[lp(i1 * C + c)], x2 = s[lp(i2 * C + c)], x3 = s[lp(i3 * C + c)];
-            // stage lh: pairs (i0, i1) and (i2, i3), twiddle w_{2 half}^k
-            const T w1 = stw[k << (log2L - lh - 1)];
+            T *e = s + lp(((b >> sD) << (sD + 2)) + (b & (D - 1)));
+            const int w2i = ((b >> log2C) & kmask) << sh2;
+            const T x0 = e[0], x1 = e[o1], x2 = e[o2], x3 = e[o3];
+            // stage lh: pairs (0, 1) and (2, 3), twiddle w_{2 half}^k
+            const T w1 = stw[w2i << 1];
             T v = R.mul(x1, w1);
             const T y0 = R.add(x0, v), y1 = R.sub(x0, v);
             v = R.mul(x3, w1);
             const T y2 = R.add(x2, v), y3 = R.sub(x2, v);
-            // stage lh + 1: pairs (i0, i2) with w_{4 half}^k and (i1, i3) with w_{4 half}^(k + half)
-            const T w2 = stw[k << (log2L - lh - 2)];
-            const T w3 = stw[(k + half) << (log2L - lh - 2)];
+            // stage lh + 1: pairs (0, 2) with w_{4 half}^k and (1, 3) with w_{4 half}^(k + half)
+            const T w2 = stw[w2i];
+            const T w3 = stw[w2i + quarter];
             v = R.mul(y2, w2);
-            s[lp(i0 * C + c)] = R.add(y0, v);
-            s[lp(i2 * C + c)] = R.sub(y0, v);
+            e[0] = R.add(y0, v);
+            e[o2] = R.sub(y0, v);
             v = R.mul(y3, w3);
-            s[lp(i1 * C + c)] = R.add(y1, v);
-            s[lp(i3 * C + c)] = R.sub(y1, v);
+            e[o1] = R.add(y1, v);
+            e[o3] = R.sub(y1, v);
         }
         __syncthreads();
     }
-    const int nbf = (1 << (log2L - 1)) << log2C;
     for (; lh < log2L; ++lh) {  // the last stage when their number is odd
-        const int half = 1 << lh;
+        const int sD = lh + log2C;
+        const int D = 1 << sD;
+        const int o1 = D + (D >> 5);
+        const int sh = log2L - lh - 1;
+        const int kmask = (1 << lh) - 1;
+        const int nbf = (1 << (log2L - 1)) << log2C;
         for (int b = threadIdx.x; b < nbf; b += NT) {
-            const int c = b & (C - 1);
-            const int bb = b >> log2C;
-            const int k = bb & (half - 1);
-            const int i0 = ((bb >> lh) << (lh + 1)) + k;
-            const int i1 = i0 + half;
-            const typename Ring::T u = s[lp(i0 * C + c)];
-            const typename Ring::T v = R.mul(s[lp(i1 * C + c)], stw[k << (log2L - lh - 1)]);
-            s[lp(i0 * C + c)] = R.add(u, v);
-            s[lp(i1 * C + c)] = R.sub(u, v);
+            T *e = s + lp(((b >> sD) << (sD + 1)) + (b & (D - 1)));
+            const T u = e[0];
+            const T v = R.mul(e[o1], stw[((b >> log2C) & kmask) << sh]);
+            e[0] = R.add(u, v);
+            e[o1] = R.sub(u, v);
         }
         __syncthreads();
     }
