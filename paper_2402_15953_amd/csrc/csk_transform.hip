@@ -25,8 +25,11 @@ namespace csk {
 
 namespace {
 
-// A block transforms one tile of TILE elements with TILE / 4 threads (two butterflies
-// per thread per stage).  Two-pass lengths use the smallest tile that keeps the column
+// A block transforms one tile of TILE elements: the fp64 FFT with TILE / 4 threads (two
+// butterflies per thread per stage; the pass is bound by memory and wants the loads of
+// many wavefronts), the NTT with TILE / 8 (four per thread: its passes wait on their
+// barriers, and two independent butterfly groups per thread between two barriers
+// measured 13-20% faster than one; four per thread were slower again).  Two-pass lengths use the smallest tile that keeps the column
 // pass's reads in runs of at least 8 elements: a 2^16-point transform is 64 blocks of
 // 1024 elements per vector (24 KB of LDS each, several blocks per CU) rather than 16
 // blocks of 4096 (96 KB, one per CU), so its passes fill the chip.
@@ -338,7 +341,7 @@ hipError_t ntt_pass(const PassGeom &g, bool single, const ModSrc &src, int n_vec
 {
     auto go = [&](auto tile) {
         constexpr int T = decltype(tile)::value;
-        constexpr int NT = T / 4 < 1024 ? T / 4 : 1024;
+        constexpr int NT = T / 8 < 1024 ? T / 8 : 1024;
         hipLaunchKernelGGL((k_ntt<T, NT>), dim3(n_vec, g.blocks), dim3(NT), 0, s, src, buf, g, vec_per_prime,
                            primes, roots, log2T, inverse, rep_of, kp);
     };
