@@ -42,6 +42,9 @@ struct EstimateWork {
     int spec_k = -1;            // primes the last estimate's repetitions needed (-1: no estimate yet)
     hipEvent_t ev_upload = nullptr;  // an asynchronous estimate's table upload
     bool upload_pending = false;     // host staging still being read by that upload
+    hipStream_t side = nullptr;      // the speculative modular chain's stream (default priority)
+    hipEvent_t ev_fork = nullptr;    // its start behind the table upload
+    hipEvent_t ev_join = nullptr;    // its end, waited on before the finalize
 };
 // Frees every buffer of a workspace (the device must be idle for it).
 void release_work(EstimateWork &w);
