@@ -404,15 +404,32 @@ __global__ __launch_bounds__(kThreads) void k_spec_mod(const uint32_t *__restric
     const uint32_t m = 1u << log2m;
     const uint32_t *base = N + (size_t)pi * vpp * m;
     uint32_t acc = 0;
-    for (uint32_t pos = blk * kThreads + threadIdx.x; pos < m; pos += (uint32_t)D.nb * kThreads) {
-        const uint32_t f = pos_freq(pos, log2m, S);
-        const uint32_t npos = freq_pos((m - f) & (m - 1), log2m, S);
-        uint32_t prod = P.one;
+    // four positions per pass, their loads of one relation's factors issued together
+    // (the sum is exact in Z_p, so its order does not matter)
+    constexpr int U = 8;
+    const uint32_t stride = (uint32_t)D.nb * kThreads;
+    for (uint32_t p0 = blk * kThreads + threadIdx.x; p0 < m; p0 += U * stride) {
+        uint32_t ps[U], nps[U], prod[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t q = p0 + u * stride;
+            ps[u] = q < m ? q : 0u;  // a position past the end reads position 0 and is not added
+            const uint32_t f = pos_freq(ps[u], log2m, S);
+            nps[u] = freq_pos((m - f) & (m - 1), log2m, S);
+            prod[u] = P.one;
+        }
         for (int k = 0; k < D.r; ++k) {
             const uint32_t *v = base + (size_t)(D.mod_vec_base + k * D.d + D.t) * m;
-            prod = R.mul(prod, ((D.conj >> k) & 1u) ? v[npos] : v[pos]);
+            const bool cj = (D.conj >> k) & 1u;
+            uint32_t val[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) val[u] = v[cj ? nps[u] : ps[u]];
+#pragma unroll
+            for (int u = 0; u < U; ++u) prod[u] = R.mul(prod[u], val[u]);
         }
-        acc = R.add(acc, prod);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (p0 + u * stride < m) acc = R.add(acc, prod[u]);
     }
     sh[threadIdx.x] = acc;
     __syncthreads();
