@@ -929,7 +929,13 @@ constexpr int kPartBlk = kPartWave * (kPB / 64); // 4096 tuples per block
 constexpr int kPartBlkCap = kPartBlk + 4 * 64;   // records of a block and repetition, runs padded to 4
 constexpr int kPartHS = 4;                       // sub-histograms per range
 constexpr int kPAB = 1024;                       // pass-2 workgroup
-constexpr uint32_t kPartNone = 0xFFFFFFFFu;      // a slot without a record
+constexpr uint32_t kPartNone = 0xFFFFFFFFu;      // an empty hot-table entry
+// Word of a slot in pass 1: record (15 bits: offset in its range, sign) | 0 (bit 15) |
+// range (bits 16-22) | rank in its sub-histogram (bits 23-30, < 256).  A slot without a
+// record carries range kPartSinkRange, whose sub-histogram entries permanently point at
+// the staging area's sink entries, so placement needs no test.
+constexpr uint32_t kPartSinkRange = 64;
+constexpr uint32_t kPartSink = kPartSinkRange << 16;
 constexpr uint16_t kPartPad = 0xFFFFu;           // padding record (bit 15 set: never a real one)
 static_assert(kMaxPartRanges <= 64, "one lane per bucket range");
 static_assert(kPartBlkCap <= 0xFFFF && kPartBlkCap % 8 == 0, "16-bit run starts, 16-byte stores");
@@ -1015,7 +1021,7 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
                                                          FilterSpec f, unsigned long long *kept)
 {
     static_assert(NC == 1 || NC == 2, "one- and two-column relations");
-    __shared__ __align__(16) uint32_t s_hist[kPB / 64][64 * kPartHS];
+    __shared__ __align__(16) uint32_t s_hist[kPB / 64][(kPartSinkRange + 1) * kPartHS];
     __shared__ uint32_t s_tot[kPB / 64][64];
     __shared__ __align__(16) uint16_t s_stage[kPartBlkCap + 64];  // + one sink entry per lane
     const SegTile wg = seg_tile();
@@ -1228,6 +1234,7 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
     hs.mmask = m - 1;
     uint32_t *hist = s_hist[wave];
     const uint32_t sub = lane & (kPartHS - 1);
+    if (lane < kPartHS) hist[kPartSinkRange * kPartHS + lane] = (uint32_t)kPartBlkCap + lane;  // never cleared
     for (int t = t0; t < t1; ++t) {
         hs.load(coef + (size_t)t * cpr);
         reinterpret_cast<uint4 *>(hist)[lane] = make_uint4(0u, 0u, 0u, 0u);
@@ -1240,7 +1247,7 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
         for (int q = 0; q < kPartSlots / G; ++q) {
             if (FILT && G * q >= nslots) {  // no kept tuple in these slots (wave-uniform)
 #pragma unroll
-                for (int g = 0; g < G; ++g) P[G * q + g] = kPartNone;
+                for (int g = 0; g < G; ++g) P[G * q + g] = kPartSink;
                 continue;
             }
             uint32_t j[G], ng[G], flag = 0;
@@ -1261,13 +1268,13 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 const int s = G * q + g;
-                P[s] = kPartNone;
+                P[s] = kPartSink;
                 if ((live >> s) & 1u) {
                     const uint32_t b = hs.bucket(j[g]);
                     const uint32_t r = b >> kPartLog2R;
                     const uint32_t rc = (b & (kPartR - 1)) | (((ng[g] ^ (wneg >> s)) & 1u) << kPartLog2R);
                     const uint32_t pos = atomicAdd(&hist[r * kPartHS + sub], 1u);  // < 256
-                    P[s] = rc | (r << 15) | (pos << 21);
+                    P[s] = rc | (r << 16) | (pos << 23);
                 }
             }
         }
@@ -1304,18 +1311,15 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
         }
         wave_sync();
         // placement, eight slots at a time: their run bases are read before any of
-        // their records is written (a slot without a record reads entry 0 and writes its
-        // lane's sink entry, never stored)
+        // their records is written (a slot without a record reads its sub-histogram's
+        // sink entry and writes a sink entry of the staging area, never stored)
 #pragma unroll
         for (int s0 = 0; s0 < kPartSlots; s0 += 8) {
             uint32_t at[8];
 #pragma unroll
-            for (int s = 0; s < 8; ++s)
-                at[s] = hist[P[s0 + s] != kPartNone ? ((P[s0 + s] >> 15) & 63u) * kPartHS + sub : 0u];
+            for (int s = 0; s < 8; ++s) at[s] = hist[((P[s0 + s] >> 16) & 127u) * kPartHS + sub];
 #pragma unroll
-            for (int s = 0; s < 8; ++s)
-                s_stage[P[s0 + s] != kPartNone ? at[s] + (P[s0 + s] >> 21) : (uint32_t)kPartBlkCap + lane] =
-                    (uint16_t)(P[s0 + s] & 0x7FFFu);
+            for (int s = 0; s < 8; ++s) s_stage[at[s] + (P[s0 + s] >> 23)] = (uint16_t)P[s0 + s];
         }
         __syncthreads();
         uint4 *dst = reinterpret_cast<uint4 *>(rec_out + ((uint64_t)t * nblk + blk) * kPartBlkCap);
