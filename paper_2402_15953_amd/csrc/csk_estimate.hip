@@ -559,6 +559,7 @@ constexpr int kStage = kMaxD * 3 * kMaxRel;  // doubles of per-repetition bound 
 constexpr int kSpecPrimes = 5;                       // speculative modular step: primes (155 bits)
 constexpr size_t kSpecBudget = (size_t)1 << 30;      // and its largest workspace
 constexpr int kOverlapPrimes = 3;                    // at most this many: beside the fp64 chain
+constexpr size_t kOverlapMinResidues = (size_t)1 << 24;  // and at least this many residues
 
 // STAGE 1: fp64 / dot / norms pass; 2: residues of the modular pass; 3: both in one
 // launch (the speculative residues were computed beside the fp64 pass).
@@ -1471,12 +1472,14 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
     // beside the fp64 pass, and one finalize launch uses both (no round trip to the
     // host); ks is what the previous estimate on this workspace needed (kSpecPrimes for
     // the first).  A repetition that needs more primes takes the stage below.  The two
-    // chains share nothing until the finalize: with at most kOverlapPrimes primes the
-    // modular one runs on the workspace's side stream (forked behind the table upload,
-    // joined before the finalize), so that the launches of either overlap the other's;
-    // with more it fills the chip alone and follows the fp64 chain on the caller's
-    // stream (measured: overlapping five primes at m = 2^18 with 75 sketch vectors made
-    // the estimate 10% slower, two or three primes 1-13% faster).
+    // chains share nothing until the finalize: with at most kOverlapPrimes primes and at
+    // least kOverlapMinResidues residues the modular one runs on the workspace's side
+    // stream (forked behind the table upload, joined before the finalize), so that the
+    // launches of either overlap the other's.  Measured: overlapping five primes at
+    // m = 2^18 with 75 sketch vectors made the estimate 10% slower (the modular chain
+    // fills the chip alone), two or three primes 1-13% faster; for small estimates
+    // (thousands of handles with m <= 2^16, one estimate each) the fork and join cost
+    // more than they save and halved the estimates per second.
     int kdone = 0;
     const int ks = ws.spec_k >= 0 ? std::min(ws.spec_k, kSpecPrimes) : kSpecPrimes;
     bool spec = false, overlap = false;
@@ -1487,7 +1490,7 @@ cs_status estimate_batch(Handle *const *hs, int nq, hipStream_t s, cs_estimate_t
             spec_bytes += align_up((size_t)ks * kv.second.mod_ptrs.size() * ((size_t)1 << kv.second.log2m) *
                                    sizeof(uint32_t));
         if (spec_bytes <= kSpecBudget) {
-            overlap = ks <= kOverlapPrimes;
+            overlap = ks <= kOverlapPrimes && spec_bytes / sizeof(uint32_t) >= kOverlapMinResidues;
             if (overlap && !ws.side) {
                 CSK_HIP(hipStreamCreateWithFlags(&ws.side, hipStreamNonBlocking));
                 CSK_HIP(hipEventCreateWithFlags(&ws.ev_fork, hipEventDisableTiming));
