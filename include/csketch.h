@@ -291,6 +291,7 @@ cs_status cs_update_filtered(cs_sketch *h, int32_t rel, const uint32_t *keys, co
  * length's split. */
 #define CS_TUNE_BATCH_ATOMIC 16
 #define CS_TUNE_BATCH_SEGMENT 17
+#define CS_TUNE_BATCH_SORT 18
 #define CS_TUNE_TRANSFORM_SPLIT 32
 
 typedef struct cs_tune_candidate {
@@ -390,11 +391,16 @@ cs_status cs_batch_estimate(cs_batch *b, cs_sketch *const *sketches, int32_t n, 
 
 /* Task counts of the last planned batch update. */
 cs_status cs_batch_stats(const cs_batch *b, uint64_t *tasks_atomic, uint64_t *tasks_segment);
+/* The same with the sort-reduce tasks counted apart (each pointer may be NULL). */
+cs_status cs_batch_task_counts(const cs_batch *b, uint64_t *tasks_atomic, uint64_t *tasks_segment,
+                               uint64_t *tasks_sort_reduce);
 
 /* Autotuner of the batched update's tasks: the items are grouped into classes (m, d,
  * key columns, one-join columns, unit weights, floor(log2 n)), and for each class the
  * class's items alone run as one persistent launch with every task choice -- global
- * atomics, or LDS segments over tuple chunks of 2^14, 2^16, 2^18 or 2^20 -- into private
+ * atomics; sort-reduce (per repetition, each wavefront sorts the counter indices of its
+ * 64 tuples, sums the runs of equal ones and adds each run with one global atomic); or
+ * LDS segments over tuple chunks of 2^14, 2^16, 2^18 or 2^20 -- into private
  * counters (the handles' sketches are left untouched); a choice whose counters differ
  * from the global-atomic run's is never taken.  Each choice is then timed (median of
  * three) on enough copies of the class's work, each into its own counters, to fill the

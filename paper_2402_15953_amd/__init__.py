@@ -34,7 +34,7 @@ EXPORTED = [
     "cs_tune_update", "cs_tune_clear", "cs_tune_save", "cs_tune_load", "cs_tune_count",
     "cs_tune_batch_update", "cs_tune_transform",
     "cs_batch_create", "cs_batch_destroy", "cs_batch_update", "cs_batch_capture", "cs_batch_replay",
-    "cs_batch_estimate", "cs_batch_stats",
+    "cs_batch_estimate", "cs_batch_stats", "cs_batch_task_counts",
     "cs_server_create", "cs_server_destroy", "cs_server_add_query", "cs_server_remove_query",
     "cs_server_sketch", "cs_server_submit_update", "cs_server_submit_estimate", "cs_server_poll",
     "cs_server_drain", "cs_server_stats",
@@ -182,6 +182,7 @@ def lib() -> ctypes.CDLL:
         L.cs_batch_estimate.argtypes = [vp, ctypes.POINTER(vp), i32, vp, ctypes.POINTER(_Estimate),
                                         ctypes.POINTER(_Reps)]
         L.cs_batch_stats.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64)]
+        L.cs_batch_task_counts.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64)]
         L.cs_server_create.argtypes = [ctypes.POINTER(_ServerConfig), ctypes.POINTER(vp)]
         L.cs_server_destroy.argtypes = [vp]
         L.cs_server_add_query.argtypes = [vp, ctypes.POINTER(_Graph), u32, u32, u64, ctypes.POINTER(i32)]
@@ -323,7 +324,7 @@ def tune_update(sketch: "Sketch", rel: int, keys, weights=None, unit_weights: bo
     return {"candidates": cands, "best": cands[rep.best], "best_index": rep.best}
 
 
-TUNE_BATCH_ATOMIC, TUNE_BATCH_SEGMENT, TUNE_TRANSFORM_SPLIT = 16, 17, 32
+TUNE_BATCH_ATOMIC, TUNE_BATCH_SEGMENT, TUNE_BATCH_SORT, TUNE_TRANSFORM_SPLIT = 16, 17, 18, 32
 
 
 def tune_transform(log2m: int, n_vec: int = 64, stream=None) -> dict:
@@ -575,9 +576,9 @@ class Batch:
         return {"classes": rep.classes, "rejected": rep.rejected, "rule_ms": rep.rule_ms, "tuned_ms": rep.tuned_ms}
 
     def stats(self):
-        a, b = ctypes.c_uint64(), ctypes.c_uint64()
-        _check(lib().cs_batch_stats(self._b, ctypes.byref(a), ctypes.byref(b)))
-        return {"tasks_atomic": a.value, "tasks_segment": b.value}
+        a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().cs_batch_task_counts(self._b, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"tasks_atomic": a.value, "tasks_segment": b.value, "tasks_sort_reduce": c.value}
 
     def estimate(self, sketches, stream=None, reps: bool = False):
         sketches = list(sketches)

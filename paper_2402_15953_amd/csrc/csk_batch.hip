@@ -9,9 +9,13 @@
 //                  range's tuples hashed (bins first; signs only for in-segment buckets
 //                  when the segment is a bucket range), then the non-zero counters are
 //                  added into the sketch with one global atomic each;
-//   atomic task  - few tuples per counter: one global atomic per tuple and repetition.
+//   atomic task  - few tuples per counter: one global atomic per tuple and repetition;
+//   sort-reduce task - each wavefront takes 64 tuples at a time and, per repetition,
+//                  sorts their 64 (counter, value) pairs across its lanes, sums the runs
+//                  of equal counters and adds each run with one global atomic (skewed
+//                  keys then meet in registers instead of on a counter's cache line).
 // Counters are int64 and all adds commute, so the result is bit-identical to the plain
-// per-query path whatever the task order.
+// per-query path whatever the task kind or order.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -55,7 +59,7 @@ struct BItem {
 
 struct BTask {
     int32_t item;
-    int32_t kind;      // 0: atomic, 1: LDS segment
+    int32_t kind;      // 0: atomic, 1: LDS segment, 2: sort-reduce
     uint32_t seg;
     uint32_t pad;
     uint64_t begin, end;
@@ -77,6 +81,64 @@ __device__ void run_atomic(const BItem &I, uint64_t begin, uint64_t end)
             const uint64_t val = neg ? (uint64_t)0 - (uint64_t)delta : (uint64_t)delta;
             atomicAdd(reinterpret_cast<unsigned long long *>(I.sketch) + (size_t)t * I.m + j,
                       (unsigned long long)val);
+        }
+    }
+}
+
+// Sort-reduce task.  The loop over 64-tuple groups is uniform in each wavefront, so every
+// lane takes part in every exchange; lanes past the range carry an empty counter index
+// that sorts last and is never added.  Bitonic network over the 64 lanes: in stage
+// (k, jj) lane l exchanges with l ^ jj and keeps the smaller index when it is the lower
+// lane of an ascending pair (l & k == 0) or the upper lane of a descending one.  Equal
+// indices are never exchanged, so both lanes of a pair always decide alike.  The sums are
+// taken mod 2^64, as every counter add is.
+template <int NC>
+__device__ void run_sortreduce(const BItem &I, uint64_t begin, uint64_t end)
+{
+    constexpr uint32_t kEmpty = 0xFFFFFFFFu;  // above every bucket (m <= 2^20)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    unsigned long long *sk = reinterpret_cast<unsigned long long *>(I.sketch);
+    for (uint64_t g0 = begin + (uint64_t)wave * 64; g0 < end; g0 += (uint64_t)kBBlock) {
+        const uint64_t i = g0 + lane;
+        const bool valid = i < end;
+        uint32_t x[NC];
+        if (valid) {
+            load_keys<NC>(I.keys, i, I.vec2 != 0, x);
+        } else {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) x[c] = 0u;
+        }
+        const int64_t delta = valid ? (I.weights ? I.weights[i] : 1) : 0;
+        const uint64_t *cf = I.coef;
+        for (int t = 0; t < I.d; ++t, cf += I.cpr) {
+            uint32_t j, neg;
+            hash_rep<NC>(cf, I.plan, x, j, neg);
+            uint32_t key = valid ? j : kEmpty;
+            uint64_t val = neg ? (uint64_t)0 - (uint64_t)delta : (uint64_t)delta;
+#pragma unroll
+            for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+                for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                    const uint32_t ok = __shfl_xor(key, jj, 64);
+                    const uint64_t ov = __shfl_xor(val, jj, 64);
+                    const bool asc = (lane & k) == 0;
+                    const bool low = (lane & jj) == 0;
+                    if (low == asc ? ok < key : ok > key) {
+                        key = ok;
+                        val = ov;
+                    }
+                }
+            }
+            // inclusive sums within runs of equal indices (a run is contiguous once sorted)
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t uk = __shfl_up(key, o, 64);
+                const uint64_t uv = __shfl_up(val, o, 64);
+                if (lane >= o && uk == key) val += uv;
+            }
+            const uint32_t nk = __shfl_down(key, 1, 64);
+            if ((lane == 63 || nk != key) && key != kEmpty && val != 0)
+                atomicAdd(sk + (size_t)t * I.m + key, (unsigned long long)val);
         }
     }
 }
@@ -351,6 +413,8 @@ __device__ void run_task(const BItem &I, const BTask &T, unsigned char *lds)
 {
     if (T.kind == 0) {
         run_atomic<NC>(I, T.begin, T.end);
+    } else if (T.kind == 2) {
+        run_sortreduce<NC>(I, T.begin, T.end);
     } else if (I.narrow) {
         run_segment16<NC>(I, T.seg, T.begin, T.end, reinterpret_cast<uint32_t *>(lds));
     } else {
@@ -414,7 +478,7 @@ struct BatchState {
     hipStream_t capture_stream = nullptr;
     EstimateWork est;
     std::vector<Handle *> est_handles;
-    uint64_t tasks_atomic = 0, tasks_segment = 0;
+    uint64_t tasks_atomic = 0, tasks_segment = 0, tasks_sort = 0;
 };
 
 namespace {
@@ -483,7 +547,7 @@ void rule_choice(const BItem &I, int *kind, int *chunk_log2)
 // Tasks of item idx with the given kind and tuple chunk (2^chunk_log2, or for -1 the
 // balanced chunks of at most 2^18).
 void add_tasks(int idx, const ItemInfo &info, int kind, int chunk_log2, std::vector<BTask> &bt,
-               std::vector<double> &cost, uint64_t &n_atomic, uint64_t &n_segment)
+               std::vector<double> &cost, uint64_t &n_atomic, uint64_t &n_segment, uint64_t &n_sort)
 {
     const BItem &I = info.I;
     const uint64_t n = I.n;
@@ -496,12 +560,15 @@ void add_tasks(int idx, const ItemInfo &info, int kind, int chunk_log2, std::vec
         const uint64_t C = (n + (1ull << chunk_log2) - 1) >> chunk_log2;
         chunk = (n + C - 1) / C;
     }
-    if (kind == 0) {
+    if (kind == 0 || kind == 2) {
+        // sort-reduce: the exchange network (21 steps of a key and a 64-bit value) per
+        // tuple and repetition in place of most of the atomics
+        const double per = kind == 0 ? info.steps + 40 : info.steps + 160;
         for (uint64_t b = 0; b < n; b += chunk) {
-            BTask T{idx, 0, 0, 0, b, std::min<uint64_t>(n, b + chunk)};
+            BTask T{idx, kind, 0, 0, b, std::min<uint64_t>(n, b + chunk)};
             bt.push_back(T);
-            cost.push_back((double)(T.end - T.begin) * I.d * (info.steps + 40));
-            ++n_atomic;
+            cost.push_back((double)(T.end - T.begin) * I.d * per);
+            ++(kind == 0 ? n_atomic : n_sort);
         }
     } else {
         const uint32_t R = I.R;
@@ -558,7 +625,7 @@ cs_status plan_batch(BatchState &B, const cs_update_item *items, int32_t n_items
     std::vector<BItem> bi;
     std::vector<BTask> bt;
     std::vector<double> cost;
-    B.tasks_atomic = B.tasks_segment = 0;
+    B.tasks_atomic = B.tasks_segment = B.tasks_sort = 0;
     for (int32_t i = 0; i < n_items; ++i) {
         const cs_update_item &it = items[i];
         if (!it.sketch) return fail(CS_EINVAL, "batch item without handle");
@@ -577,7 +644,7 @@ cs_status plan_batch(BatchState &B, const cs_update_item *items, int32_t n_items
             rule_choice(I, &kind, &chunk_log2);
         const int idx = (int)bi.size();
         bi.push_back(I);
-        add_tasks(idx, info, kind, chunk_log2, bt, cost, B.tasks_atomic, B.tasks_segment);
+        add_tasks(idx, info, kind, chunk_log2, bt, cost, B.tasks_atomic, B.tasks_segment, B.tasks_sort);
     }
     return upload_tables(B, bi, bt, cost, s);
 }
@@ -703,6 +770,16 @@ cs_status cs_batch_stats(const cs_batch *b, uint64_t *tasks_atomic, uint64_t *ta
     return CS_OK;
 }
 
+cs_status cs_batch_task_counts(const cs_batch *b, uint64_t *tasks_atomic, uint64_t *tasks_segment,
+                               uint64_t *tasks_sort_reduce)
+{
+    if (!b) return fail(CS_EINVAL, "null batch");
+    if (tasks_atomic) *tasks_atomic = b->b.tasks_atomic;
+    if (tasks_segment) *tasks_segment = b->b.tasks_segment;
+    if (tasks_sort_reduce) *tasks_sort_reduce = b->b.tasks_sort;
+    return CS_OK;
+}
+
 cs_status cs_tune_batch_update(cs_batch *b, const cs_update_item *items, int32_t n_items, void *stream,
                                cs_tune_batch_report *out)
 {
@@ -765,8 +842,9 @@ cs_status cs_tune_batch_update(cs_batch *b, const cs_update_item *items, int32_t
         return fail(CS_EDEVICE, "batch tuning events");
     }
     // candidates: (kind, log2 tuples per task); index 0, global atomics, is the reference;
-    // index 1 is the fixed rule (measured for the report, never stored)
-    const int cands[][2] = {{0, 16}, {-1, -1}, {1, 14}, {1, 16}, {1, 18}, {1, 20}};
+    // index 1 is the fixed rule (measured for the report, never stored); kind 2 is
+    // sort-reduce, kind 1 LDS segments
+    const int cands[][2] = {{0, 16}, {-1, -1}, {2, 16}, {1, 14}, {1, 16}, {1, 18}, {1, 20}};
     const int n_cand = (int)(sizeof(cands) / sizeof(cands[0]));
     cs_status st = CS_OK;
     for (auto &kv : classes) {
@@ -787,7 +865,7 @@ cs_status cs_tune_batch_update(cs_batch *b, const cs_update_item *items, int32_t
                 std::vector<BItem> bi;
                 std::vector<BTask> bt;
                 std::vector<double> cost;
-                uint64_t na = 0, ns = 0;
+                uint64_t na = 0, ns = 0, nr = 0;
                 for (int c = 0; c < copies; ++c)
                     for (size_t j = 0; j < members.size(); ++j) {
                         ItemInfo ii = info[members[j]];
@@ -796,7 +874,7 @@ cs_status cs_tune_batch_update(cs_batch *b, const cs_update_item *items, int32_t
                         if (kind < 0) rule_choice(ii.I, &kind, &chunk);
                         const int idx = (int)bi.size();
                         bi.push_back(ii.I);
-                        add_tasks(idx, ii, kind, chunk, bt, cost, na, ns);
+                        add_tasks(idx, ii, kind, chunk, bt, cost, na, ns, nr);
                     }
                 return upload_tables(T, bi, bt, cost, s);
             };

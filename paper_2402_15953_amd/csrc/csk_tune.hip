@@ -71,7 +71,8 @@ int n_class_of(uint64_t n)
 
 int scope_of_strategy(int32_t strategy)
 {
-    if (strategy == CS_TUNE_BATCH_ATOMIC || strategy == CS_TUNE_BATCH_SEGMENT) return 1;
+    if (strategy == CS_TUNE_BATCH_ATOMIC || strategy == CS_TUNE_BATCH_SEGMENT || strategy == CS_TUNE_BATCH_SORT)
+        return 1;
     if (strategy == CS_TUNE_TRANSFORM_SPLIT) return 2;
     return 0;
 }
@@ -152,7 +153,8 @@ bool tune_lookup_batch(int device, uint32_t m, int d, int n_cols, int e1, int un
     if (g_tune.empty()) return false;
     auto it = g_tune.find(batch_key(device, m, d, n_cols, e1, unit, n));
     if (it == g_tune.end()) return false;
-    *kind = it->second.strategy == CS_TUNE_BATCH_ATOMIC ? 0 : 1;
+    const int32_t code = it->second.strategy;
+    *kind = code == CS_TUNE_BATCH_ATOMIC ? 0 : code == CS_TUNE_BATCH_SORT ? 2 : 1;
     *chunk_log2 = it->second.grid;
     return true;
 }
@@ -162,7 +164,8 @@ void tune_store_batch(int device, uint32_t m, int d, int n_cols, int e1, int uni
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[batch_key(device, m, d, n_cols, e1, unit, n)] =
-        TuneChoice{kind == 0 ? CS_TUNE_BATCH_ATOMIC : CS_TUNE_BATCH_SEGMENT, chunk_log2, 0, ms};
+        TuneChoice{kind == 0 ? CS_TUNE_BATCH_ATOMIC : kind == 2 ? CS_TUNE_BATCH_SORT : CS_TUNE_BATCH_SEGMENT,
+                   chunk_log2, 0, ms};
 }
 
 int tune_split(int device, int log2m)

@@ -111,9 +111,10 @@ def test_checkpoint_blob_validation_before_any_device_work():
 
 
 def test_tune_table_batch_and_split_entries(tmp_path):
-    """Batched-task and transform-split entries share the table file with plain-update
-    entries (their own scope: same class fields, different entries) and are validated
-    on load: chunk exponents 12..22, splits 2^S with S = 10..12 and S < log2 m <= 2S."""
+    """Batched-task (atomic 16, LDS segment 17, sort-reduce 18) and transform-split entries
+    share the table file with plain-update entries (their own scope: same class fields,
+    different entries) and are validated on load: chunk exponents 12..22, splits 2^S with
+    S = 10..12 and S < log2 m <= 2S."""
     import paper_2402_15953_amd as csk
     csk.tune_clear()
     good = tmp_path / "tune.txt"
@@ -121,9 +122,10 @@ def test_tune_table_batch_and_split_entries(tmp_path):
                     "gfx950-256cu 65536 9 2 1 1 17 17 18 0 0.500000\n"
                     "gfx950-256cu 1024 5 1 1 1 12 16 16 0 0.010000\n"
                     "gfx950-256cu 262144 0 0 0 0 0 32 11 0 0.200000\n"
-                    "gfx950-256cu 65536 9 2 1 1 17 2 28 0 0.290000\n")
+                    "gfx950-256cu 65536 9 2 1 1 17 2 28 0 0.290000\n"
+                    "gfx950-256cu 4096 5 1 1 1 14 18 16 0 0.020000\n")
     csk.tune_load(str(good))
-    assert csk.tune_count() == 4
+    assert csk.tune_count() == 5
     out = tmp_path / "again.txt"
     csk.tune_save(str(out))
     assert sorted(out.read_text().splitlines()[1:]) == sorted(good.read_text().splitlines()[1:])
@@ -137,7 +139,7 @@ def test_tune_table_batch_and_split_entries(tmp_path):
         bad.write_text("csketch-tune 1\n" + bad_line + "\n")
         with pytest.raises(csk.CsError):
             csk.tune_load(str(bad))
-    assert csk.tune_count() == 4
+    assert csk.tune_count() == 5
     csk.tune_clear()
 
 

@@ -96,7 +96,7 @@ def test_batch_tuner_keeps_counters_and_plans_with_its_choice(tmp_path):
     path = tmp_path / "tuned.txt"
     csk.tune_save(str(path))
     codes = {int(l.split()[7]) for l in path.read_text().splitlines()[1:]}
-    assert codes <= {csk.TUNE_BATCH_ATOMIC, csk.TUNE_BATCH_SEGMENT}
+    assert codes <= {csk.TUNE_BATCH_ATOMIC, csk.TUNE_BATCH_SEGMENT, csk.TUNE_BATCH_SORT}
     # the handles' counters were not touched by tuning
     for sk in sks:
         for k in range(sk.graph.n_rel):
@@ -109,6 +109,45 @@ def test_batch_tuner_keeps_counters_and_plans_with_its_choice(tmp_path):
     ests = b.estimate(sks)
     for e, p in zip(ests, plain):
         assert e["value"] == p.estimate()["value"]
+    b.close()
+    csk.tune_clear()
+
+
+@pytest.mark.parametrize("weights", ["unit", "general"])
+def test_sort_reduce_tasks_give_the_per_query_sketches(weights, tmp_path):
+    """Every class of a batch forced to sort-reduce tasks through the tuning table: the
+    batch plans only sort-reduce tasks, and the sketches (Zipf-skewed keys, so runs of
+    equal counters in every wavefront) equal the per-query path's counter for counter,
+    for unit and for general int64 weights (up to +-2^40)."""
+    from tests.test_gpu_batch import _batched_items, _make_inputs, _plain
+    csk.tune_clear()
+    specs = W.batched_queries(24, seed=23, m_log2=(10, 16), n_range=(50, 150_000))
+    _say("sort-reduce", weights, len(specs), "queries")
+    data = _make_inputs(specs, weights_kind="big" if weights == "general" else None)
+    plain = _plain(specs, data)
+    sks, items, keep = _batched_items(specs, data)
+    b = csk.Batch()
+    rep = b.tune(items)
+    assert rep["rejected"] == 0
+    path = tmp_path / "tuned.txt"
+    csk.tune_save(str(path))
+    lines = path.read_text().splitlines()
+    forced = [lines[0]]
+    for line in lines[1:]:
+        f = line.split()
+        f[7], f[8] = str(csk.TUNE_BATCH_SORT), "16"
+        forced.append(" ".join(f))
+    fpath = tmp_path / "forced.txt"
+    fpath.write_text("\n".join(forced) + "\n")
+    csk.tune_clear()
+    csk.tune_load(str(fpath))
+    b.update(items)
+    torch.cuda.synchronize()
+    st = b.stats()
+    assert st["tasks_sort_reduce"] > 0 and st["tasks_atomic"] == 0 and st["tasks_segment"] == 0, st
+    for qi, (sp, a, p) in enumerate(zip(specs, sks, plain)):
+        for k in range(sp.graph.n_rel):
+            assert np.array_equal(a.read_sketch(k), p.read_sketch(k)), (qi, k)
     b.close()
     csk.tune_clear()
 
