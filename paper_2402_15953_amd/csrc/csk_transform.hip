@@ -228,9 +228,19 @@ __global__ __launch_bounds__(NT) void k_ntt(ModSrc src, uint32_t *buf, PassGeom 
         const int64_t pos = base + (int64_t)c * g.col_stride + (int64_t)n * g.elem_stride;
         uint32_t val = s[lp((n << g.log2C) + c)];
         if (g.twiddle) {
-            const int64_t colid = (int64_t)blk * C + c;
-            const int64_t e = ((int64_t)n * colid) & (m - 1);
-            val = R.mul(val, tw[(size_t)e << (log2T - g.log2m)]);
+            const int sh = log2T - g.log2m;
+            if (g.log2C > 0) {
+                // w^(n (blk C + c)) = w^(n blk C) w^(n c): the first factor is one entry
+                // for the C lanes of one n, the second lies in the table's first L C
+                // entries (n c < L C), so neither is a scattered read of a table of m
+                // entries (exact arithmetic: the same residue as one lookup)
+                const uint32_t a = tw[(size_t)(((int64_t)n * blk * C) & (m - 1)) << sh];
+                const uint32_t b = tw[(size_t)((int64_t)n * c) << sh];
+                val = R.mul(R.mul(val, a), b);
+            } else {
+                const int64_t e = ((int64_t)n * blk) & (m - 1);
+                val = R.mul(val, tw[(size_t)e << sh]);
+            }
         }
         if (g.scale) val = R.mul(val, P.minv[g.log2m]);
         vec[pos] = val;
