@@ -193,6 +193,7 @@ __global__ __launch_bounds__(NT) void k_ntt(ModSrc src, uint32_t *buf, PassGeom 
 {
     __shared__ uint32_t s[lds_len<TILE>()];
     __shared__ uint32_t stw[TILE / 2];
+    __shared__ uint32_t s_row[64];  // row passes with twiddles: w^(j blk), j < 64
     const int v = blockIdx.x;
     const int pi = v / vec_per_prime;
     if (kp && pi >= kp[rep_of[v % vec_per_prime]]) return;  // prime not needed
@@ -221,6 +222,8 @@ __global__ __launch_bounds__(NT) void k_ntt(ModSrc src, uint32_t *buf, PassGeom 
         }
     }
     load_stage_twiddles<NT>(stw, g.log2L, tw, log2T);
+    if (g.twiddle && g.log2C == 0 && threadIdx.x < 64)
+        s_row[threadIdx.x] = tw[(size_t)(((int64_t)threadIdx.x * blk) & (m - 1)) << (log2T - g.log2m)];
     __syncthreads();
     lds_stages<NT, RingM>(s, g.log2L, g.log2C, R, stw);
     for (int idx = threadIdx.x; idx < total; idx += NT) {
@@ -238,8 +241,10 @@ __global__ __launch_bounds__(NT) void k_ntt(ModSrc src, uint32_t *buf, PassGeom 
                 const uint32_t b = tw[(size_t)((int64_t)n * c) << sh];
                 val = R.mul(R.mul(val, a), b);
             } else {
-                const int64_t e = ((int64_t)n * blk) & (m - 1);
-                val = R.mul(val, tw[(size_t)e << sh]);
+                // a row (C = 1): w^(n blk) = w^(64 (n >> 6) blk) w^((n & 63) blk), the
+                // first factor one entry for a wavefront's 64 lanes, the second from LDS
+                const uint32_t a = tw[(size_t)(((int64_t)(n >> 6) * 64 * blk) & (m - 1)) << sh];
+                val = R.mul(R.mul(val, a), s_row[n & 63]);
             }
         }
         if (g.scale) val = R.mul(val, P.minv[g.log2m]);
