@@ -1235,6 +1235,11 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
     uint32_t *hist = s_hist[wave];
     const uint32_t sub = lane & (kPartHS - 1);
     if (lane < kPartHS) hist[kPartSinkRange * kPartHS + lane] = (uint32_t)kPartBlkCap + lane;  // never cleared
+    // a bucket b = j & (m - 1) (one-join hash) or j: range b >> 14 as one bit-field
+    // extract of j, position within the range j & min(m - 1, 2^14 - 1)
+    const uint32_t log2m = 31u - (uint32_t)__builtin_clz(m);  // m a power of two when FAST
+    const uint32_t rbits = FAST ? (log2m > kPartLog2R ? log2m - kPartLog2R : 0u) : 32u - kPartLog2R;
+    const uint32_t pmask = FAST ? min(m - 1, kPartR - 1) : kPartR - 1;
     for (int t = t0; t < t1; ++t) {
         hs.load(coef + (size_t)t * cpr);
         reinterpret_cast<uint4 *>(hist)[lane] = make_uint4(0u, 0u, 0u, 0u);
@@ -1270,11 +1275,11 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
                 const int s = G * q + g;
                 P[s] = kPartSink;
                 if ((live >> s) & 1u) {
-                    const uint32_t b = hs.bucket(j[g]);
-                    const uint32_t r = b >> kPartLog2R;
-                    const uint32_t rc = (b & (kPartR - 1)) | (((ng[g] ^ (wneg >> s)) & 1u) << kPartLog2R);
-                    const uint32_t pos = atomicAdd(&hist[r * kPartHS + sub], 1u);  // < 256
-                    P[s] = rc | (r << 16) | (pos << 23);
+                    const uint32_t r = __builtin_amdgcn_ubfe(j[g], kPartLog2R, rbits);
+                    const uint32_t rc = (j[g] & pmask) | (((ng[g] ^ (wneg >> s)) & 1u) << kPartLog2R);
+                    // the counts are kept times 2^23, so the rank (< 256) comes back in place
+                    const uint32_t pos23 = atomicAdd(&hist[r * kPartHS + sub], 1u << 23);
+                    P[s] = rc | (r << 16) | pos23;
                 }
             }
         }
@@ -1282,7 +1287,7 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
         // run of range L: this wavefront's four sub-counts, their prefix, the totals of
         // every wavefront; the block's runs padded to multiples of four records
         const uint4 h4 = reinterpret_cast<const uint4 *>(hist)[lane];
-        const uint32_t e1 = h4.x, e2 = e1 + h4.y, e3 = e2 + h4.z, tot = e3 + h4.w;
+        const uint32_t e1 = h4.x >> 23, e2 = e1 + (h4.y >> 23), e3 = e2 + (h4.z >> 23), tot = e3 + (h4.w >> 23);
         s_tot[wave][lane] = tot;
         __syncthreads();
         uint32_t before = 0, rtot = 0;
@@ -1673,12 +1678,29 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
                 const uint32_t *kb = a.keys + base * NC;
                 const int64_t *wb = a.weights ? a.weights + base : nullptr;
                 const bool a16 = (reinterpret_cast<uintptr_t>(kb) & 15) == 0 && (reinterpret_cast<uintptr_t>(wb) & 15) == 0;
-                // repetition groups: the fewest rounds of four workgroups per CU that
-                // leave every workgroup at least one repetition
-                const uint64_t slots = (uint64_t)n_cu * 4;  // resident pass-1 workgroups (128 VGPRs)
-                int groups = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)a.d, slots / std::max<uint64_t>(1, nblk)));
-                const int per = (a.d + groups - 1) / groups;
-                groups = (a.d + per - 1) / per;
+                // repetition groups: within one round (at most four resident workgroups
+                // per CU at 128 VGPRs), preferring at least three per CU to hide latency,
+                // the split with the fewest repetitions per SIMD (workgroups per CU x
+                // repetitions per workgroup); measured at 2^20 tuples, d = 15: three of
+                // five repetitions beat four of four, four, four and three by 4%
+                int groups = 1, per = a.d;
+                {
+                    uint64_t best = ~0ull;
+                    for (int g = 1; g <= a.d; ++g) {
+                        const int pg_ = (a.d + g - 1) / g, gg = (a.d + pg_ - 1) / pg_;
+                        if (gg != g) continue;
+                        const uint64_t k = (nblk * (uint64_t)gg + n_cu - 1) / n_cu;
+                        if (g > 1 && k > 4) break;
+                        // ties: fewer workgroups once three share a CU, else more
+                        const uint64_t key = ((k >= 3 ? 0ull : 1ull) << 62) | ((k * (uint64_t)pg_) << 8) |
+                                             (k >= 3 ? k : 255 - k);
+                        if (key < best) {
+                            best = key;
+                            groups = gg;
+                            per = pg_;
+                        }
+                    }
+                }
                 using T_ = std::true_type;
                 using F_ = std::false_type;
                 const bool filt = a.filter != nullptr;
