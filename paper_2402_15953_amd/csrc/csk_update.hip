@@ -964,6 +964,20 @@ __device__ __forceinline__ int32_t wave_sum_i32(int32_t v)
     return v;
 }
 
+// Inclusive prefix sum over the 64 lanes of a wavefront: in-row steps by DPP row shifts
+// of 1, 2, 4 and 8 lanes, then the row broadcasts of lane 15 (into rows 1 and 3) and of
+// lane 31 (into rows 2 and 3); a lane without a source adds 0.  All lanes must be active.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
+{
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);  // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return v;
+}
+
 // Entry of a tuple in the direct-mapped table of a block's hot tuples (multiplicative
 // hashing of the key words).
 constexpr int kPartHotTab = 256;
@@ -1298,16 +1312,11 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
             rtot += v;
         }
         const uint32_t padded = (rtot + 3u) & ~3u;
-        uint32_t incl = padded;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += y;
-        }
+        const uint32_t incl = wave_incl_scan(padded);
         const uint32_t start = incl - padded;
         const uint32_t wb = start + before;
         reinterpret_cast<uint4 *>(hist)[lane] = make_uint4(wb, wb + e1, wb + e2, wb + e3);
-        const uint32_t total = __shfl(incl, 63, 64);
+        const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
         if (wave == 0) {
             uint16_t *tb = tab + ((uint64_t)t * nblk + blk) * (uint64_t)(ranges + 1);
             if (lane < ranges) tb[lane] = (uint16_t)start;
