@@ -92,6 +92,16 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
+def launch_ms(pairs):
+    """Duration of a kernel from its (start, stop) event pairs: the median launch (a
+    sampled pair caught in a rare stall, once seen at 15x the others, would move a mean
+    by tens of percent), with the mean and the extremes kept beside it."""
+    v = sorted(a_.elapsed_ms(b_) for a_, b_ in pairs)
+    n = len(v)
+    med = v[n // 2] if n % 2 else 0.5 * (v[n // 2 - 1] + v[n // 2])
+    return med, {"launches": n, "median_ms": med, "mean_ms": sum(v) / n, "min_ms": v[0], "max_ms": v[-1]}
+
+
 def measured_traffic(which: str, strategy: int):
     """HBM bytes per launch of the dominant kernel from the committed FETCH_SIZE and
     WRITE_SIZE counter summary (scaled by a copy kernel of known size), or None when the
@@ -222,7 +232,8 @@ def bench_chain5(args, dev, stream):
 
     tuples_per_step = n * r * len(exps)
     value = tuples_per_step * args.steps / elapsed
-    kern_ms = {k: sum(a_.elapsed_ms(b_) for a_, b_ in kev[k]) / len(kev[k]) for k in range(r)}
+    kern_stat = {k: launch_ms(kev[k]) for k in range(r)}
+    kern_ms = {k: v[0] for k, v in kern_stat.items()}
     upd_ms = {}   # per exponent and relation: the 96 calls, both passes
     est_ms = {}
     for sx in exps:
@@ -253,7 +264,8 @@ def bench_chain5(args, dev, stream):
                      "traffic": measured_traffic("chain5", args.strategy),
                      "kernel": f"hashing pass (k_part_hash) of relation {kdom}'s update ({a_dom} key columns), "
                                f"one launch per 2^20-tuple call",
-                     "kernel_ms": kern_ms[kdom], "algorithmic_steps": steps_dom, "algorithmic_bytes": bytes_dom,
+                     "kernel_ms": kern_ms[kdom], "kernel_launches": kern_stat[kdom][1],
+                     "algorithmic_steps": steps_dom, "algorithmic_bytes": bytes_dom,
                      "hbm_GBps": hbm_achieved, "hbm_frac": hbm_achieved / HBM_PEAK_GBS},
         "hash_kernel_ms_per_call": {str(k): v for k, v in kern_ms.items()},
         "update_ms_per_relation": upd_ms,
@@ -348,7 +360,8 @@ def bench_chain3(args, dev, stream):
         torch.cuda.synchronize()
         elapsed_p = time.perf_counter() - t_p
     pub = [csk.read_estimate(b) for b in pinned]
-    kern_ms = {k: sum(a_.elapsed_ms(b_) for a_, b_ in kev[k]) / len(kev[k]) for k in range(n_rel)}
+    kern_stat = {k: launch_ms(kev[k]) for k in range(n_rel)}
+    kern_ms = {k: v[0] for k, v in kern_stat.items()}
     upd_ms = {k: sum(a_.elapsed_ms(b_) for a_, b_ in ev[k]) / len(ev[k]) for k in range(n_rel)}
     est_ms = sum(a_.elapsed_ms(b_) for a_, b_ in est_ev) / len(est_ev)
     kdom = max(kern_ms, key=kern_ms.get)
@@ -366,7 +379,8 @@ def bench_chain3(args, dev, stream):
                      "unit": "T Horner-steps/s", "frac": steps_dom / dur_s / ALU_STEP_PEAK,
                      "traffic": measured_traffic("chain3", args.strategy),
                      "kernel": f"hashing kernel of relation {kdom}'s update ({a_dom} key columns)",
-                     "kernel_ms": kern_ms[kdom], "algorithmic_bytes": n * 4 * a_dom,
+                     "kernel_ms": kern_ms[kdom], "kernel_launches": kern_stat[kdom][1],
+                     "algorithmic_bytes": n * 4 * a_dom,
                      "hbm_frac": n * 4 * a_dom / dur_s / 1e9 / HBM_PEAK_GBS},
         "hash_kernel_ms_per_relation": {str(k): v for k, v in kern_ms.items()},
         "update_ms_per_relation": {str(k): v for k, v in upd_ms.items()},

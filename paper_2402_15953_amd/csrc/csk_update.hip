@@ -1248,6 +1248,8 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
     hs.mmask = m - 1;
     uint32_t *hist = s_hist[wave];
     const uint32_t sub = lane & (kPartHS - 1);
+    // byte offset of this lane's sub-histogram column of range 0 within s_hist
+    const uint32_t hsub = (uint32_t)(((uintptr_t)(hist + sub)) - (uintptr_t)&s_hist[0][0]);
     if (lane < kPartHS) hist[kPartSinkRange * kPartHS + lane] = (uint32_t)kPartBlkCap + lane;  // never cleared
     // a bucket b = j & (m - 1) (one-join hash) or j: range b >> 14 as one bit-field
     // extract of j, position within the range j & min(m - 1, 2^14 - 1)
@@ -1331,9 +1333,20 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
         for (int s0 = 0; s0 < kPartSlots; s0 += 8) {
             uint32_t at[8];
 #pragma unroll
-            for (int s = 0; s < 8; ++s) at[s] = hist[((P[s0 + s] >> 16) & 127u) * kPartHS + sub];
+            for (int s = 0; s < 8; ++s) {
+                // LDS byte address of the slot's sub-histogram entry: range * 16 + hsub in
+                // two instructions
+                uint32_t a;
+                asm("v_bfe_u32 %0, %1, 16, 7\n\tv_lshl_add_u32 %0, %0, 4, %2" : "=&v"(a) : "v"(P[s0 + s]), "v"(hsub));
+                at[s] = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(s_hist) + a);
+            }
 #pragma unroll
-            for (int s = 0; s < 8; ++s) s_stage[at[s] + (P[s0 + s] >> 23)] = (uint16_t)P[s0 + s];
+            for (int s = 0; s < 8; ++s) {
+                // byte offset (at + rank) * 2 in one add-and-shift (bit 31 of a slot word is 0)
+                uint32_t off;
+                asm("v_add_lshl_u32 %0, %1, %2, 1" : "=v"(off) : "v"(at[s]), "v"(P[s0 + s] >> 23));
+                *reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(s_stage) + off) = (uint16_t)P[s0 + s];
+            }
         }
         __syncthreads();
         uint4 *dst = reinterpret_cast<uint4 *>(rec_out + ((uint64_t)t * nblk + blk) * kPartBlkCap);
