@@ -322,12 +322,16 @@ cs_status create_handle(const cs_graph *graph, uint32_t m, uint32_t d, uint64_t 
     h.own_scratch = with_scratch;
     if (hipMalloc(&h.kept_dev, 2 * sizeof(unsigned long long)) != hipSuccess ||
         hipMemset(h.kept_dev, 0, 2 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&h.hints_dev, (size_t)h.g.n_rel * sizeof(PartHints)) != hipSuccess ||
+        hipMemset(h.hints_dev, 0, (size_t)h.g.n_rel * sizeof(PartHints)) != hipSuccess ||
         hipMemcpy(h.coef_dev, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(h.counters, 0, n_ctr * sizeof(int64_t)) != hipSuccess ||
         hipStreamSynchronize(nullptr) != hipSuccess) {  // the null stream only: other streams' work is not waited for
         hipFree(h.counters);
         hipFree(h.coef_dev);
         hipFree(h.scratch);
+        hipFree(h.kept_dev);
+        hipFree(h.hints_dev);
         delete hs;
         return fail(CS_EDEVICE, "initialisation failed");
     }
@@ -353,6 +357,7 @@ cs_status cs_destroy(cs_sketch *hs)
     if (h.scratch) hipFree(h.scratch);
     if (h.filter_scratch) hipFree(h.filter_scratch);
     if (h.kept_dev) hipFree(h.kept_dev);
+    if (h.hints_dev) hipFree(h.hints_dev);
     hipSetDevice(cur);
     delete hs;
     return CS_OK;
@@ -428,6 +433,7 @@ cs_status update_args(cs_sketch *hs, int32_t rel, const uint32_t *keys, const in
     a.scratch = h.scratch;
     a.scratch_bytes = h.scratch_bytes;
     a.filter_count = h.kept_dev ? h.kept_dev + 1 : nullptr;
+    a.hints = h.hints_dev ? h.hints_dev + rel : nullptr;
     a.unit_weights = (flags & CS_UPDATE_UNIT_WEIGHTS) != 0;
     a.compact = (flags & CS_UPDATE_NO_COMPACT) == 0;
     a.counters16 = (flags & CS_UPDATE_NO_COUNTERS16) == 0;

@@ -75,6 +75,7 @@ struct Handle {
     // two device words: [0] the kept tuples of a filtered update that asked for the
     // count, [1] the per-round count of the filtered 16-bit path (zero between updates)
     unsigned long long *kept_dev = nullptr;
+    PartHints *hints_dev = nullptr;    // [r]: hot-tuple hints of the partition strategy
 };
 
 // Relation k's counters [d][m].

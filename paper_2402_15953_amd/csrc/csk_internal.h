@@ -121,6 +121,7 @@ struct FilterSpec {
     uint32_t lo[CS_MAX_PREDICATES], hi[CS_MAX_PREDICATES];
 };
 
+struct PartHints;
 struct UpdateArgs {
     const uint32_t *keys;
     const int64_t *weights;
@@ -150,6 +151,8 @@ struct UpdateArgs {
     // a device word that is zero between filtered updates (the handle's), used by the
     // filtered 16-bit path for its per-round count of kept tuples
     unsigned long long *filter_count = nullptr;
+    // the relation's hot-tuple hints (partition strategy; may be null)
+    PartHints *hints = nullptr;
 };
 struct SegGeom {
     uint32_t R;        // counter cells per segment
@@ -167,6 +170,14 @@ constexpr int kPartHot = 8;
 struct PartHot {
     uint32_t key[kPartHot][2];
     int32_t sum[kPartHot];
+};
+// A relation's most frequent hot tuples over the blocks of its last partition update
+// (n of them, hottest first), offered to the next update of that relation as election
+// candidates before its own sampled tuples.  Any content gives the same counters: a
+// candidate is elected only on its count in the block's sample.
+struct PartHints {
+    uint32_t n;
+    uint32_t key[kPartHot][2];
 };
 struct PartGeom {
     int32_t ranges;          // bucket ranges of 2^14 per repetition (the last may be partial)

@@ -904,12 +904,15 @@ __global__ void k_seg_reduce(const CT *__restrict__ partial, int32_t C, uint64_t
 // Zipf-skewed keys put a large share of a stream on a few tuples; left alone, pass 2's
 // LDS adds on their buckets would serialise (same-address atomics) and the workgroup of
 // their range would carry most records.  Each block therefore elects up to kPartHot hot
-// tuples (sixteen candidates, the first tuples of four lanes of every wavefront, counted
-// over the first four quads of the block's lanes; kept when they hold at least 1/64 of
-// that sample), sums their Deltas instead of emitting records for them, and leaves
-// (tuple, Delta sum) in a list that pass 2 hashes once per repetition.  The sketch is
-// linear (Sec. 2.2): n equal tuples with Deltas Delta_i add sum_i Delta_i at their one
-// counter, so the counters are unchanged.
+// tuples (sixteen candidates: the relation's hints, the hottest tuples of its previous
+// update, then the first tuples of lanes of every wavefront; counted over the first four
+// quads of the block's lanes and kept when they hold at least 8 of those 1024 tuples),
+// sums their Deltas instead of emitting records for them, and leaves (tuple, Delta sum)
+// in a list that pass 2 hashes once per repetition.  The sketch is linear (Sec. 2.2): n
+// equal tuples with Deltas Delta_i add sum_i Delta_i at their one counter, so the
+// counters are unchanged whichever tuples are elected.  Sixteen sampled tuples alone
+// miss a key of 6% of the stream in a third of the blocks; the hints carry the stream's
+// heavy keys from one update call to the next.
 //
 // Pass 2 (k_part_accum): workgroup (range r, repetition t) zeroes two copies of 2^14
 // int32 LDS counters (even and odd lanes add to different copies, which halves the
@@ -917,7 +920,9 @@ __global__ void k_seg_reduce(const CT *__restrict__ partial, int32_t C, uint64_t
 // its group from every block (8-byte loads of four records, four runs in flight per
 // wavefront), adds the hot tuples whose bucket falls in its range, and adds the non-zero
 // sums of the two copies into the sketch (it owns those counters: plain
-// read-modify-write, no atomics).
+// read-modify-write, no atomics).  One extra workgroup writes the relation's hints: the
+// distinct hot tuples of the first eight blocks, ranked by their |Delta sum| over all
+// blocks.
 
 constexpr int kPartLog2R = 14;                   // buckets per range (pass-2 LDS: two copies of 2^14 int32, 128 KB)
 constexpr uint32_t kPartR = 1u << kPartLog2R;
@@ -930,6 +935,7 @@ constexpr int kPartBlkCap = kPartBlk + 4 * 64;   // records of a block and repet
 constexpr int kPartHS = 4;                       // sub-histograms per range
 constexpr int kPAB = 1024;                       // pass-2 workgroup
 constexpr uint32_t kPartNone = 0xFFFFFFFFu;      // an empty hot-table entry
+constexpr uint32_t kPartHotMin = 8;              // sample hits (of 1024) for a hot tuple
 // Word of a slot in pass 1: record (15 bits: offset in its range, sign) | 0 (bit 15) |
 // range (bits 16-22) | rank in its sub-histogram (bits 23-30, < 256).  A slot without a
 // record carries range kPartSinkRange, whose sub-histogram entries permanently point at
@@ -1032,7 +1038,8 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
                                                          int32_t reps_per_group, uint64_t nblk, uint16_t *rec_out,
                                                          uint16_t *tab, PartHot *hot, uint32_t canon_thresh,
                                                          const uint32_t *__restrict__ attrs, int32_t n_attrs,
-                                                         FilterSpec f, unsigned long long *kept)
+                                                         FilterSpec f, unsigned long long *kept,
+                                                         const PartHints *__restrict__ hints)
 {
     static_assert(NC == 1 || NC == 2, "one- and two-column relations");
     __shared__ __align__(16) uint32_t s_hist[kPB / 64][(kPartSinkRange + 1) * kPartHS];
@@ -1143,9 +1150,16 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
     __shared__ int32_t s_hsum[kPB / 64][kPartHot];
     __shared__ int32_t s_nh;
     __shared__ uint4 s_htab[kPartHotTab];  // key(s), index into s_hot (kPartNone: empty)
-    if (lane < 4) {
+    // candidates: the relation's hints from its previous update, then sampled tuples
+    // (the first of lanes 0-3 of every wavefront, lane-major, while room is left)
+    const int nhint = hints ? (int)min(hints->n, (uint32_t)kPartHot) : 0;
+    if (threadIdx.x < nhint) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) s_cand[wave * 4 + lane][c] = x[0][c];
+        for (int c = 0; c < NC; ++c) s_cand[threadIdx.x][c] = hints->key[threadIdx.x][c];
+    }
+    if (lane < 4 && nhint + lane * 4 + wave < kCand) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) s_cand[nhint + lane * 4 + wave][c] = x[0][c];
     }
     for (int e = threadIdx.x; e < kPartHotTab; e += kPB) s_htab[e] = make_uint4(0u, 0u, kPartNone, 0u);
     __syncthreads();
@@ -1161,7 +1175,7 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
     __syncthreads();
     if (wave == 0) {
         // candidates by total count over the 1024 sampled tuples, distinct keys, at
-        // least 16 hits (1/64), the kPartHot hottest (ties: lower candidate index); lane
+        // least kPartHotMin hits, the kPartHot hottest (ties: lower candidate index); lane
         // ci < kCand holds candidate ci.  A candidate enters the direct-mapped table
         // unless a hotter elected one has the same entry (it stays an ordinary tuple);
         // entries are numbered in hotness order.
@@ -1184,7 +1198,7 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
             const uint32_t vj = __shfl(v, cj, 64);
             rank += (vj > v || (vj == v && cj < ci)) ? 1 : 0;
         }
-        const bool elig = lane < kCand && rank < kPartHot && v >= 16u;
+        const bool elig = lane < kCand && rank < kPartHot && v >= kPartHotMin;
         const uint32_t slot = part_hot_slot<NC>(kc);
         bool blocked = false;
         int idx = 0;
@@ -1356,6 +1370,71 @@ __global__ __launch_bounds__(kPB, 4) void k_part_hash(const uint32_t *__restrict
     }
 }
 
+// The relation's hints for its next update: candidates are the distinct hot tuples of
+// the first eight blocks, each credited with the |Delta sum| of every block entry equal
+// to it; the kPartHot largest non-zero totals, largest first (ties: lower candidate).
+__device__ void part_hints(const PartHot *__restrict__ hot, uint64_t nblk, PartHints *out)
+{
+    constexpr int kHC = 8 * kPartHot;
+    __shared__ uint32_t h_key[kHC][2];
+    __shared__ uint32_t h_tot[kHC];
+    __shared__ uint32_t h_ok[kHC];
+    const int nc = (int)(nblk < 8 ? nblk : 8) * kPartHot;
+    const int tid = threadIdx.x;
+    if (tid < kHC) {
+        uint32_t k0 = 0, k1 = 0, ok = 0;
+        if (tid < nc) {
+            const PartHot &h = hot[tid / kPartHot];
+            k0 = h.key[tid % kPartHot][0];
+            k1 = h.key[tid % kPartHot][1];
+            ok = h.sum[tid % kPartHot] != 0 ? 1u : 0u;
+        }
+        h_key[tid][0] = k0;
+        h_key[tid][1] = k1;
+        h_ok[tid] = ok;
+        h_tot[tid] = 0;
+    }
+    __syncthreads();
+    bool live = false;
+    if (tid < kHC) {
+        live = h_ok[tid] != 0;
+        for (int c = 0; c < tid && live; ++c)
+            live = !(h_ok[c] && h_key[c][0] == h_key[tid][0] && h_key[c][1] == h_key[tid][1]);
+    }
+    __syncthreads();
+    if (tid < kHC) h_ok[tid] = live ? 1u : 0u;
+    __syncthreads();
+    for (uint64_t e = tid; e < nblk * kPartHot; e += blockDim.x) {
+        const PartHot &h = hot[e / kPartHot];
+        const int k = (int)(e % kPartHot);
+        const int32_t sm = h.sum[k];
+        if (sm == 0) continue;
+        const uint32_t k0 = h.key[k][0], k1 = h.key[k][1];
+        for (int c = 0; c < nc; ++c)
+            if (h_ok[c] && h_key[c][0] == k0 && h_key[c][1] == k1) {
+                atomicAdd(&h_tot[c], (uint32_t)(sm < 0 ? -sm : sm));
+                break;
+            }
+    }
+    __syncthreads();
+    if (tid < 64) {  // one wavefront ranks the kHC = 64 candidates
+        const uint32_t v = h_ok[tid] ? h_tot[tid] : 0u;
+        int rank = 0;
+        for (int c = 0; c < kHC; ++c) {
+            const uint32_t vc = __shfl(v, c, 64);
+            rank += (vc > v || (vc == v && c < tid)) ? 1 : 0;
+        }
+        const bool take = v > 0 && rank < kPartHot;
+        if (take) {
+            out->key[rank][0] = h_key[tid][0];
+            out->key[rank][1] = h_key[tid][1];
+        }
+        const uint64_t bal = __ballot(take);
+        if (tid == 0) out->n = (uint32_t)__popcll(bal);
+    }
+}
+static_assert(8 * kPartHot == 64, "one wavefront ranks the hint candidates");
+
 // Pass 2.  Block (range r, repetition t).
 template <int NC, bool FAST>
 __global__ __launch_bounds__(kPAB) void k_part_accum(const uint16_t *__restrict__ rec,
@@ -1363,9 +1442,13 @@ __global__ __launch_bounds__(kPAB) void k_part_accum(const uint16_t *__restrict_
                                                      const PartHot *__restrict__ hot, uint64_t nblk,
                                                      int32_t ranges, uint32_t m, const uint64_t *__restrict__ coef,
                                                      int32_t cpr, DevPlan plan, uint64_t *sketch,
-                                                     uint32_t canon_thresh)
+                                                     uint32_t canon_thresh, int32_t d, PartHints *hints_out)
 {
     extern __shared__ __align__(16) uint32_t s_dyn[];
+    if ((int)blockIdx.y == d) {  // the hints workgroup (row d of the grid: column 0 only)
+        if (blockIdx.x == 0 && hints_out) part_hints(hot, nblk, hints_out);
+        return;
+    }
     // two copies of the counters, taken by even and odd lanes: the lanes of one add that
     // hit a skewed bucket's word are split over two words
     int32_t *s_cnt = reinterpret_cast<int32_t *>(s_dyn);   // [2][kPartR]
@@ -1743,16 +1826,17 @@ cs_status launch_nc(const UpdateArgs &a, int strategy, int grid_blocks, hipStrea
                 const FilterSpec fs = filt ? *a.filter : FilterSpec{};
                 hipLaunchKernelGGL(hk, dim3((unsigned)nblk, (unsigned)groups), dim3(kPB), lds_f, s, kb, wb, cn, a.coef,
                                    a.plan.coef_per_rep, plan, a.m, a.d, pg.ranges, per, nblk, rec, tab, hot,
-                                   a.canon_thresh, ab, a.n_attrs, fs, a.kept);
+                                   a.canon_thresh, ab, a.n_attrs, fs, a.kept, a.hints);
                 CSK_HIP(hipGetLastError());
                 if (one_chunk) CSK_MARK(a.ev_stop, s);
                 auto ak = fast ? &k_part_accum<NC, true> : &k_part_accum<NC, false>;
                 const size_t lds = (size_t)kPartR * 8 + (size_t)nblk * 4;
                 CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(ak),
                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-                hipLaunchKernelGGL(ak, dim3((unsigned)pg.ranges, (unsigned)a.d), dim3(kPAB), lds, s, rec, tab, hot,
-                                   nblk, pg.ranges, a.m, a.coef, a.plan.coef_per_rep, plan, a.sketch,
-                                   a.canon_thresh);
+                // grid row d: the workgroup that writes the relation's hints
+                hipLaunchKernelGGL(ak, dim3((unsigned)pg.ranges, (unsigned)a.d + (a.hints ? 1u : 0u)), dim3(kPAB), lds,
+                                   s, rec, tab, hot, nblk, pg.ranges, a.m, a.coef, a.plan.coef_per_rep, plan,
+                                   a.sketch, a.canon_thresh, a.d, a.hints);
                 CSK_HIP(hipGetLastError());
             }
             if (!one_chunk) CSK_MARK(a.ev_stop, s);
