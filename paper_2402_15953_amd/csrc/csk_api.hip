@@ -320,10 +320,9 @@ cs_status create_handle(const cs_graph *graph, uint32_t m, uint32_t d, uint64_t 
     // orders itself against no other handle's updates; it is allocated by the first
     // update that needs it, sized for that update (and grown by a larger one)
     h.own_scratch = with_scratch;
-    if (hipMalloc(&h.kept_dev, 2 * sizeof(unsigned long long)) != hipSuccess ||
-        hipMemset(h.kept_dev, 0, 2 * sizeof(unsigned long long)) != hipSuccess ||
-        hipMalloc(&h.hints_dev, (size_t)h.g.n_rel * sizeof(PartHints)) != hipSuccess ||
-        hipMemset(h.hints_dev, 0, (size_t)h.g.n_rel * sizeof(PartHints)) != hipSuccess ||
+    // one small allocation: the filter's two counters, then the relations' hot-key hints
+    const size_t small_bytes = 2 * sizeof(unsigned long long) + (size_t)h.g.n_rel * sizeof(PartHints);
+    if (hipMalloc(&h.kept_dev, small_bytes) != hipSuccess || hipMemset(h.kept_dev, 0, small_bytes) != hipSuccess ||
         hipMemcpy(h.coef_dev, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(h.counters, 0, n_ctr * sizeof(int64_t)) != hipSuccess ||
         hipStreamSynchronize(nullptr) != hipSuccess) {  // the null stream only: other streams' work is not waited for
@@ -331,7 +330,6 @@ cs_status create_handle(const cs_graph *graph, uint32_t m, uint32_t d, uint64_t 
         hipFree(h.coef_dev);
         hipFree(h.scratch);
         hipFree(h.kept_dev);
-        hipFree(h.hints_dev);
         delete hs;
         return fail(CS_EDEVICE, "initialisation failed");
     }
@@ -356,8 +354,7 @@ cs_status cs_destroy(cs_sketch *hs)
     release_work(h.work);
     if (h.scratch) hipFree(h.scratch);
     if (h.filter_scratch) hipFree(h.filter_scratch);
-    if (h.kept_dev) hipFree(h.kept_dev);
-    if (h.hints_dev) hipFree(h.hints_dev);
+    if (h.kept_dev) hipFree(h.kept_dev);  // the hints share this allocation
     hipSetDevice(cur);
     delete hs;
     return CS_OK;
@@ -433,7 +430,7 @@ cs_status update_args(cs_sketch *hs, int32_t rel, const uint32_t *keys, const in
     a.scratch = h.scratch;
     a.scratch_bytes = h.scratch_bytes;
     a.filter_count = h.kept_dev ? h.kept_dev + 1 : nullptr;
-    a.hints = h.hints_dev ? h.hints_dev + rel : nullptr;
+    a.hints = h.kept_dev ? reinterpret_cast<PartHints *>(h.kept_dev + 2) + rel : nullptr;
     a.unit_weights = (flags & CS_UPDATE_UNIT_WEIGHTS) != 0;
     a.compact = (flags & CS_UPDATE_NO_COMPACT) == 0;
     a.counters16 = (flags & CS_UPDATE_NO_COUNTERS16) == 0;

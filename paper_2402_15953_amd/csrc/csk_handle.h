@@ -74,8 +74,9 @@ struct Handle {
     void *result_host = nullptr;       // pinned host staging for results
     // two device words: [0] the kept tuples of a filtered update that asked for the
     // count, [1] the per-round count of the filtered 16-bit path (zero between updates)
+    // two words of the filtered update (kept count, per-round count), followed by the
+    // partition strategy's hot-key hints PartHints[r] (one allocation)
     unsigned long long *kept_dev = nullptr;
-    PartHints *hints_dev = nullptr;    // [r]: hot-tuple hints of the partition strategy
 };
 
 // Relation k's counters [d][m].
