@@ -109,11 +109,13 @@ typedef enum cs_update_strategy {
     CS_UPDATE_WAVE_AGGREGATE = 3, /* equal buckets of one wavefront merged before the atomic */
     CS_UPDATE_PARTITION = 4       /* sort by bucket range: every tuple hashed once per
                                      repetition into a 16-bit record, grouped by
-                                     (repetition, range of 2^14 buckets) per wavefront
-                                     (up to two hot tuples per 1024-tuple segment summed
-                                     instead), then one workgroup per group sums its
-                                     records in LDS and owns those counters; needs
-                                     weights NULL or CS_UPDATE_UNIT_WEIGHTS, <= 2 columns */
+                                     (repetition, range of 2^14 buckets) per block of
+                                     4096 tuples (up to eight hot tuples per block,
+                                     candidates seeded by the relation's hottest tuples
+                                     of its previous call, summed instead), then one
+                                     workgroup per group sums its records in LDS and owns
+                                     those counters; needs weights NULL or
+                                     CS_UPDATE_UNIT_WEIGHTS, <= 2 columns */
 } cs_update_strategy;
 
 /* cs_update_ex flags */
