@@ -2,7 +2,7 @@
 // library runs on: the rate of the Horner step (v <- v * x + a mod 2^61 - 1 with a
 // 32-bit x, the update's unit of work, Alg. 2's hashes) when nothing else limits it,
 // and the rate at which a kernel streams a large buffer from HBM (the key stream's
-// bound).  The update and estimate kernels are judged against these two figures.
+// bound).  The update and estimate kernels are measured against these two figures.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
