@@ -236,7 +236,7 @@ size_t cs_update_noalloc_scratch_bytes(void);
 
 /* ------------------------------------------------------------------ machine-balance probes */
 
-/* The two rates the update is measured against, measured on the current device (the
+/* The two rates the update is compared with, measured on the current device (the
  * update's hashes are Horner steps v <- v * x + a mod 2^61 - 1, Sec. 4; Alg. 2):
  * cs_k0_horner runs a kernel of nothing but independent Horner steps (the library's own
  * step, 16 wavefronts per CU, 8 chains per lane, `iters` steps per chain) and returns
