@@ -3,7 +3,9 @@ the oracle, bit for bit, in the cases its structure singles out: heavy Zipf skew
 tuples taken out of the record stream and summed), hot tuples whose Deltas cancel or
 mix signs, a stream of one repeated tuple, segments cut short (n not a multiple of the
 1024-tuple segment), several chunks, keys not 16-byte aligned, m not a power of two and
-columns in several joins (the general hash), and the counters after many calls."""
+columns in several joins (the general hash), repetition groups of several shapes, the
+counters after many calls, and hot-key hints carried across calls whose heavy keys
+change."""
 import sys
 
 import numpy as np
@@ -57,6 +59,9 @@ CASES = [
     (W.multiway_star(3), 100_000, 1 << 18, 3, 1.3, 1000, None, 0),
     (W.star(3), 100_000, 1 << 16, 5, 1.1, 10 ** 5, None, 0),
     (W.single_join(), 100_000, 1000, 5, 1.1, 10 ** 5, "pm1", 0),
+    # repetition groups of other shapes: 129 blocks at d = 20, 300 blocks at d = 7
+    (W.chain(3), 128 * 4096 + 5, 1 << 18, 20, 1.3, 10 ** 6, None, 0),
+    (W.chain(3), 300 * 4096, 1 << 17, 7, 1.1, 10 ** 6, None, 0),
 ]
 
 
@@ -102,6 +107,33 @@ def test_partition_many_calls_equal_one():
     for c in range(calls):
         for k in range(g.n_rel):
             sk.update(k, dev[k][c * n_call:(c + 1) * n_call], strategy=csk.UPDATE_PARTITION)
+    torch.cuda.synchronize()
+    for k in range(g.n_rel):
+        assert np.array_equal(sk.read_sketch(k), ref[k]), k
+    sk.close()
+
+
+def test_partition_hints_follow_the_stream():
+    """Hot-key hints carried from call to call: a skewed stream, then one whose heavy
+    keys are different tuples (stale hints), then spread keys (no hot tuple), then the
+    first again; every relation's counters equal the oracle's on the whole stream."""
+    g, m, d, seed = W.chain(3), 1 << 18, 7, 21
+    n_call = 1 << 16
+    parts = []
+    for i, (s, shift) in enumerate(((1.5, 0), (1.5, 1000003), (0.5, 0), (1.5, 0))):
+        keys = []
+        for k in range(g.n_rel):
+            x = keys_u32(W.relation_keys(g, k, 3 * n_call, "zipf", config=2400 + i, s=s, D=10 ** 6))
+            keys.append((x.astype(np.uint64) + shift).astype(np.uint32))
+        parts.append(keys)
+    rels = [np.concatenate([p[k] for p in parts]) for k in range(g.n_rel)]
+    info, co, ref = oracle_sketches(g, rels, None, m, d, seed)
+    sk = csk.Sketch(g, m, d, seed)
+    for p in parts:
+        dev = [to_device_keys(x) for x in p]
+        for c in range(3):
+            for k in range(g.n_rel):
+                sk.update(k, dev[k][c * n_call:(c + 1) * n_call], strategy=csk.UPDATE_PARTITION)
     torch.cuda.synchronize()
     for k in range(g.n_rel):
         assert np.array_equal(sk.read_sketch(k), ref[k]), k
